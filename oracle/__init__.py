@@ -1,0 +1,223 @@
+"""Python access to the FP64 CPU oracle (oracle/liberf_oracle.so).
+
+TEST INFRASTRUCTURE ONLY.  Imported by tests, ``__graft_entry__.smoke`` and the
+``cpu_baseline`` leg of ``bench.py``; the product path never imports it.  It
+shares no code with the HIP library.
+
+State dictionaries hold numpy float64 arrays:
+    rho, rt : (nz, ny, nx)       density and rho*theta at cell centres
+    ru, rv  : (nz, ny, nx)       x-/y-face momenta (face i between cells i-1, i)
+    rw      : (nz+1, ny, nx)     z-face momentum (face k below cell k)
+    rq      : (nq, nz, ny, nx)   rho*q of the passive scalars
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liberf_oracle.so")
+_lib = None
+_lock = threading.Lock()
+
+FIELDS = ("rho", "rt", "ru", "rv", "rw", "rq")
+
+
+class _Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.POINTER(C.c_double))]
+
+
+class _Params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("n_substeps", C.c_int32), ("beta_s", C.c_double),
+                ("beta_d", C.c_double), ("adv_order_h", C.c_int32), ("adv_order_v", C.c_int32),
+                ("scalar_scheme", C.c_int32), ("n_scalars", C.c_int32), ("sgs", C.c_int32),
+                ("Cs", C.c_double), ("Pr_t", C.c_double), ("nu_m", C.c_double),
+                ("alpha_m", C.c_double), ("f_cor", C.c_double), ("Ug", C.c_double),
+                ("Vg", C.c_double), ("surf_heat_flux", C.c_double), ("grav", C.c_double)]
+
+
+class _Base(C.Structure):
+    _fields_ = [("rho0", C.POINTER(C.c_double)), ("theta0", C.POINTER(C.c_double)),
+                ("p0", C.POINTER(C.c_double)), ("pi0", C.POINTER(C.c_double))]
+
+
+class _State(C.Structure):
+    _fields_ = [(f, C.POINTER(C.c_double)) for f in FIELDS]
+
+
+_DP = C.POINTER(C.c_double)
+
+
+def lib():
+    """Load (building first if absent) the oracle shared library."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_SO):
+                from . import build as _b
+                _b.build()
+            L = C.CDLL(_SO)
+            L.orc_const.restype = C.c_double
+            L.orc_const.argtypes = [C.c_int]
+            L.orc_eos_p.restype = C.c_double
+            L.orc_eos_p.argtypes = [C.c_double]
+            L.orc_eos_pprime.restype = C.c_double
+            L.orc_eos_pprime.argtypes = [C.c_double, C.c_double, C.c_double]
+            L.orc_interp.restype = C.c_double
+            L.orc_interp.argtypes = [C.c_int32, _DP, C.c_double]
+            L.orc_weno5.restype = C.c_double
+            L.orc_weno5.argtypes = [_DP, C.c_double, C.c_double]
+            L.orc_thomas.argtypes = [C.c_int32, _DP, _DP, _DP, _DP, _DP]
+            L.orc_base_state.argtypes = [C.c_int32, _DP, _DP, C.c_double, C.c_double, _DP, _DP, _DP]
+            L.orc_slow_rhs.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Base),
+                                       C.POINTER(_State), C.POINTER(_State)]
+            L.orc_acoustic_substeps.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Base),
+                                                C.POINTER(_State), C.POINTER(_State), C.POINTER(_State),
+                                                C.c_int32, C.c_double, C.POINTER(_State), _DP, _DP, _DP]
+            L.orc_scalar_advance.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_State),
+                                             C.POINTER(_State), _DP, _DP, _DP, C.c_double, _DP]
+            L.orc_rk3_step.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Base),
+                                       C.POINTER(_State)]
+            L.orc_diagnostics.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Base),
+                                          C.POINTER(_State), _DP]
+            _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_DP)
+
+
+def const(name: str) -> float:
+    return lib().orc_const({"R_d": 0, "c_p": 1, "c_v": 2, "gamma": 3, "P00": 4}[name])
+
+
+class Oracle:
+    """Oracle bound to one grid and one parameter set (a workloads.Config)."""
+
+    def __init__(self, cfg):
+        self.cfg = cfg
+        self.nx, self.ny, self.nz = cfg.nx, cfg.ny, cfg.nz
+        self.dz = np.ascontiguousarray(cfg.dz, dtype=np.float64)
+        self._grid = _Grid(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, _p(self.dz))
+        self._params = _Params(cfg.dt, cfg.n_substeps, cfg.beta_s, cfg.beta_d, cfg.adv_order_h,
+                               cfg.adv_order_v, cfg.scalar_scheme, cfg.n_scalars, cfg.sgs, cfg.Cs,
+                               cfg.Pr_t, cfg.nu_m, cfg.alpha_m, cfg.f_cor, cfg.Ug, cfg.Vg,
+                               cfg.surf_heat_flux, cfg.grav)
+        self.base = None
+
+    # -- base state -------------------------------------------------------
+    def init_base_state(self, theta0: np.ndarray, p_surface: float):
+        nz = self.nz
+        th = np.ascontiguousarray(theta0, dtype=np.float64)
+        rho0, p0, pi0 = np.zeros(nz), np.zeros(nz), np.zeros(nz)
+        rc = lib().orc_base_state(nz, _p(self.dz), _p(th), p_surface, self.cfg.grav, _p(rho0), _p(p0), _p(pi0))
+        if rc != 0:
+            raise RuntimeError(f"orc_base_state failed ({rc})")
+        self.base = {"rho0": rho0, "theta0": th, "p0": p0, "pi0": pi0}
+        self._base = _Base(_p(rho0), _p(th), _p(p0), _p(pi0))
+        return self.base
+
+    # -- helpers ----------------------------------------------------------
+    def zeros_state(self):
+        nx, ny, nz, nq = self.nx, self.ny, self.nz, self.cfg.n_scalars
+        return {"rho": np.zeros((nz, ny, nx)), "rt": np.zeros((nz, ny, nx)),
+                "ru": np.zeros((nz, ny, nx)), "rv": np.zeros((nz, ny, nx)),
+                "rw": np.zeros((nz + 1, ny, nx)), "rq": np.zeros((max(nq, 0), nz, ny, nx))}
+
+    def _st(self, S):
+        arrs = {}
+        for f in FIELDS:
+            a = S[f]
+            if not (a.dtype == np.float64 and a.flags.c_contiguous):
+                raise TypeError(f"field {f} must be C-contiguous float64")
+            arrs[f] = _p(a) if a.size else C.cast(C.c_void_p(0), _DP)
+        return _State(**arrs)
+
+    def _check(self, rc, what):
+        if rc != 0:
+            raise RuntimeError(f"{what} failed with status {rc}")
+
+    # -- the calls ---------------------------------------------------------
+    def slow_rhs(self, S):
+        R = self.zeros_state()
+        self._check(lib().orc_slow_rhs(C.byref(self._grid), C.byref(self._params), C.byref(self._base),
+                                       C.byref(self._st(S)), C.byref(self._st(R))), "orc_slow_rhs")
+        return R
+
+    def acoustic_substeps(self, Sn, St, Rt, n_sub: int, dtau: float):
+        out = self.zeros_state()
+        nx, ny, nz = self.nx, self.ny, self.nz
+        Fu, Fv, Fw = np.zeros((nz, ny, nx)), np.zeros((nz, ny, nx)), np.zeros((nz + 1, ny, nx))
+        self._check(lib().orc_acoustic_substeps(C.byref(self._grid), C.byref(self._params), C.byref(self._base),
+                                                C.byref(self._st(Sn)), C.byref(self._st(St)),
+                                                C.byref(self._st(Rt)), n_sub, dtau, C.byref(self._st(out)),
+                                                _p(Fu), _p(Fv), _p(Fw)), "orc_acoustic_substeps")
+        return out, (Fu, Fv, Fw)
+
+    def scalar_advance(self, Sn, St, F, dts: float):
+        rq = np.zeros_like(Sn["rq"])
+        Fu, Fv, Fw = (np.ascontiguousarray(f, dtype=np.float64) for f in F)
+        self._check(lib().orc_scalar_advance(C.byref(self._grid), C.byref(self._params), C.byref(self._st(Sn)),
+                                             C.byref(self._st(St)), _p(Fu), _p(Fv), _p(Fw), dts,
+                                             _p(rq) if rq.size else C.cast(C.c_void_p(0), _DP)),
+                    "orc_scalar_advance")
+        return rq
+
+    def rk3_step(self, S):
+        """Advance S (modified in place) by one RK3 step."""
+        self._check(lib().orc_rk3_step(C.byref(self._grid), C.byref(self._params), C.byref(self._base),
+                                       C.byref(self._st(S))), "orc_rk3_step")
+        return S
+
+    def diagnostics(self, S):
+        out = np.zeros(5 + max(self.cfg.n_scalars, 0))
+        self._check(lib().orc_diagnostics(C.byref(self._grid), C.byref(self._params), C.byref(self._base),
+                                          C.byref(self._st(S)), _p(out)), "orc_diagnostics")
+        d = {"mass": out[0], "theta_mass": out[1], "energy": out[2], "max_w": out[3],
+             "nonfinite": int(out[4])}
+        d["scalar_mass"] = out[5:].copy()
+        return d
+
+
+# -- pointwise helpers used by the pin tests ---------------------------------
+def interp(order: int, q6, sgn: float) -> float:
+    q = np.ascontiguousarray(q6, dtype=np.float64)
+    return lib().orc_interp(order, _p(q), sgn)
+
+
+def weno5(q6, sgn: float, eps: float = 1e-6) -> float:
+    q = np.ascontiguousarray(q6, dtype=np.float64)
+    return lib().orc_weno5(_p(q), sgn, eps)
+
+
+def thomas(a, b, c, r):
+    n = len(b)
+    a, b, c, r = (np.ascontiguousarray(v, dtype=np.float64) for v in (a, b, c, r))
+    x = np.zeros(n)
+    lib().orc_thomas(n, _p(a), _p(b), _p(c), _p(r), _p(x))
+    return x
+
+
+def eos_p(Theta: float) -> float:
+    return lib().orc_eos_p(Theta)
+
+
+def eos_pprime(Theta: float, Theta0: float, p0: float) -> float:
+    return lib().orc_eos_pprime(Theta, Theta0, p0)
+
+
+def base_state(dz, theta0, p_surface: float, grav: float = 9.81):
+    dz = np.ascontiguousarray(dz, dtype=np.float64)
+    th = np.ascontiguousarray(theta0, dtype=np.float64)
+    nz = len(dz)
+    rho0, p0, pi0 = np.zeros(nz), np.zeros(nz), np.zeros(nz)
+    rc = lib().orc_base_state(nz, _p(dz), _p(th), p_surface, grav, _p(rho0), _p(p0), _p(pi0))
+    if rc != 0:
+        raise RuntimeError("orc_base_state failed")
+    return rho0, p0, pi0

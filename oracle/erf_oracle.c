@@ -1,0 +1,869 @@
+/*
+ * erf_oracle.c -- plain FP64 CPU oracle of one RK3 step of ERF's compressible
+ * dynamical core (Lattanzi et al., arXiv 2412.04395).
+ *
+ * TEST INFRASTRUCTURE ONLY: called by the tests, the smoke check and the CPU
+ * baseline of the benchmark, never by the product path.  It shares no code
+ * with the HIP library.  Written for obviousness, not speed: every operator is
+ * a loop over the points it defines, neighbours are fetched through wrap /
+ * reflection helpers, and temporaries are allocated per call.  Compiled with
+ * -ffp-contract=off so that every product and sum is rounded as written.
+ *
+ * Readings of points the paper leaves open are marked "reading:".
+ */
+#include "erf_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- constants.  Only P00 and gamma = c_p/(c_p - R_d) are printed in the
+ * paper (Sec. 2.1); R_d and c_p take the usual dry-air values (reading). ---- */
+static const double R_D = 287.0;
+static const double C_P = 1004.5;
+static const double P_00 = 1.0e5;
+#define C_V (C_P - R_D)
+#define GAM (C_P / (C_P - R_D))
+
+double orc_const(int which)
+{
+    switch (which) {
+    case 0: return R_D;
+    case 1: return C_P;
+    case 2: return C_V;
+    case 3: return GAM;
+    case 4: return P_00;
+    default: return NAN;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* indexing helpers                                                          */
+/* ------------------------------------------------------------------------ */
+static int wrap(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+/* even reflection of a cell index about the bottom and top lids:
+ * k = -1 -> 0, -2 -> 1, nz -> nz-1, ... (reading: ghost cells by reflection) */
+static int refl_c(int k, int nz)
+{
+    int p = 2 * nz;
+    int r = ((k % p) + p) % p;
+    return r >= nz ? p - 1 - r : r;
+}
+
+#define CIDX(g, i, j, k) (((size_t)(k) * (size_t)(g)->ny + (size_t)(j)) * (size_t)(g)->nx + (size_t)(i))
+
+/* centre (or horizontal-face) quantity: periodic in x and y, even in z */
+static double cget(const orc_grid *g, const double *f, int i, int j, int k)
+{
+    return f[CIDX(g, wrap(i, g->nx), wrap(j, g->ny), refl_c(k, g->nz))];
+}
+
+/* z-face quantity: periodic in x and y, odd reflection about the lids */
+static double wget(const orc_grid *g, const double *w, int i, int j, int k)
+{
+    int nz = g->nz, p = 2 * nz;
+    int r = ((k % p) + p) % p;
+    i = wrap(i, g->nx);
+    j = wrap(j, g->ny);
+    if (r <= nz) return w[CIDX(g, i, j, r)];
+    return -w[CIDX(g, i, j, p - r)];
+}
+
+static double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+
+static double *dalloc(size_t n) { return (double *)calloc(n ? n : 1, sizeof(double)); }
+
+/* ------------------------------------------------------------------------ */
+/* equation of state, Sec. 2.1                                               */
+/* ------------------------------------------------------------------------ */
+double orc_eos_p(double Theta) { return P_00 * pow(R_D * Theta / P_00, GAM); }
+
+/* p' = p(Theta) - p0 with p0 = p(Theta0).  Since p/p0 = (Theta/Theta0)^gamma,
+ * p' = p0 ((1 + Theta'/Theta0)^gamma - 1), evaluated with log1p/expm1 so that a
+ * small perturbation is not lost to cancellation against 1e5 Pa. */
+double orc_eos_pprime(double Theta, double Theta0, double p0)
+{
+    return p0 * expm1(GAM * log1p((Theta - Theta0) / Theta0));
+}
+
+/* Exner function pi = (p/P00)^(R_d/c_p) = (R_d Theta / P00)^(gamma - 1). */
+static double exner(double Theta) { return pow(R_D * Theta / P_00, GAM - 1.0); }
+
+/* ------------------------------------------------------------------------ */
+/* base state: dp0/dz = -rho0 g and p0 = EOS(rho0 theta0) (Sec. 2, Sec. 3.8) */
+/* ------------------------------------------------------------------------ */
+/* reading: between level centres the hydrostatic relation is discretised with
+ * the trapezoidal density, p_k - p_{k-1} = -g dzf_k (rho_k + rho_{k-1})/2, and
+ * the lowest centre sits dz_0/2 above the surface where p = p_surface.  Each
+ * level is one scalar Newton-Raphson root find for rho_k. */
+int orc_base_state(int32_t nz, const double *dz, const double *theta0, double p_surface,
+                   double grav, double *rho0, double *p0, double *pi0)
+{
+    if (nz < 1 || !dz || !theta0 || !rho0 || !p0) return -1;
+    double p_below = p_surface, rho_below = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        double h = (k == 0) ? 0.5 * dz[0] : 0.5 * (dz[k - 1] + dz[k]);
+        double rho = (k == 0) ? p_surface / (R_D * theta0[0]) : rho_below;
+        for (int it = 0; it < 30; ++it) {
+            double p = orc_eos_p(rho * theta0[k]);
+            double f, df;
+            if (k == 0) {
+                f = p - p_below + grav * h * rho;
+                df = GAM * p / rho + grav * h;
+            } else {
+                f = p - p_below + grav * h * 0.5 * (rho + rho_below);
+                df = GAM * p / rho + grav * h * 0.5;
+            }
+            double d = f / df;
+            rho = rho - d;
+            if (fabs(d) <= 1e-15 * rho) break;
+        }
+        rho0[k] = rho;
+        p0[k] = orc_eos_p(rho * theta0[k]);
+        if (pi0) pi0[k] = pow(p0[k] / P_00, R_D / C_P);
+        p_below = p0[k];
+        rho_below = rho;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* interpolants of Sec. 3.6                                                  */
+/* ------------------------------------------------------------------------ */
+/* q6 = {q_{m-3}, q_{m-2}, q_{m-1}, q_m, q_{m+1}, q_{m+2}}; returns q_{m-1/2}.
+ * sgn is the sign of the normal momentum at the face (reading of sign(u_m)). */
+double orc_interp(int32_t order, const double *q6, double s)
+{
+    double qm3 = q6[0], qm2 = q6[1], qm1 = q6[2], q0 = q6[3], qp1 = q6[4], qp2 = q6[5];
+    double c4 = 7.0 / 12.0 * (q0 + qm1) - 1.0 / 12.0 * (qp1 + qm2);
+    double c6 = 37.0 / 60.0 * (q0 + qm1) - 2.0 / 15.0 * (qp1 + qm2) + 1.0 / 60.0 * (qp2 + qm3);
+    switch (order) {
+    case 2: return 0.5 * (q0 + qm1);
+    case 3: return c4 + s / 12.0 * ((qp1 - qm2) - 3.0 * (q0 - qm1));
+    case 4: return c4;
+    case 5: return c6 - s / 60.0 * ((qp2 - qm3) - 5.0 * (qp1 - qm2) + 10.0 * (q0 - qm1));
+    case 6: return c6;
+    default: return NAN;
+    }
+}
+
+/* WENO5-JS (Jiang & Shu 1996, cited in Sec. 3.6): linear weights 0.1/0.6/0.3,
+ * smoothness indicators of the three 3-point candidate stencils, power 2.
+ * For positive flow the stencil is q_{m-3}..q_{m+1} (upwind cell m-1); for
+ * negative flow it is mirrored. */
+double orc_weno5(const double *q6, double s, double eps)
+{
+    double v0, v1, v2, v3, v4; /* v2 is the upwind cell */
+    if (s >= 0.0) {
+        v0 = q6[0]; v1 = q6[1]; v2 = q6[2]; v3 = q6[3]; v4 = q6[4];
+    } else {
+        v0 = q6[5]; v1 = q6[4]; v2 = q6[3]; v3 = q6[2]; v4 = q6[1];
+    }
+    double p0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) / 6.0;
+    double p1 = (-v1 + 5.0 * v2 + 2.0 * v3) / 6.0;
+    double p2 = (2.0 * v2 + 5.0 * v3 - v4) / 6.0;
+    double b0 = 13.0 / 12.0 * (v0 - 2.0 * v1 + v2) * (v0 - 2.0 * v1 + v2)
+              + 0.25 * (v0 - 4.0 * v1 + 3.0 * v2) * (v0 - 4.0 * v1 + 3.0 * v2);
+    double b1 = 13.0 / 12.0 * (v1 - 2.0 * v2 + v3) * (v1 - 2.0 * v2 + v3)
+              + 0.25 * (v1 - v3) * (v1 - v3);
+    double b2 = 13.0 / 12.0 * (v2 - 2.0 * v3 + v4) * (v2 - 2.0 * v3 + v4)
+              + 0.25 * (3.0 * v2 - 4.0 * v3 + v4) * (3.0 * v2 - 4.0 * v3 + v4);
+    double a0 = 0.1 / ((eps + b0) * (eps + b0));
+    double a1 = 0.6 / ((eps + b1) * (eps + b1));
+    double a2 = 0.3 / ((eps + b2) * (eps + b2));
+    return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+}
+
+static const double WENO_EPS = 1.0e-6; /* reading: the usual JS regulariser */
+
+/* ------------------------------------------------------------------------ */
+/* Thomas algorithm (no pivoting)                                            */
+/* ------------------------------------------------------------------------ */
+int orc_thomas(int32_t n, const double *a, const double *b, const double *c,
+               const double *r, double *x)
+{
+    if (n < 1) return 0;
+    double cp[n], dp[n];
+    cp[0] = c[0] / b[0];
+    dp[0] = r[0] / b[0];
+    for (int i = 1; i < n; ++i) {
+        double den = b[i] - a[i] * cp[i - 1];
+        cp[i] = c[i] / den;
+        dp[i] = (r[i] - a[i] * dp[i - 1]) / den;
+    }
+    x[n - 1] = dp[n - 1];
+    for (int i = n - 2; i >= 0; --i) x[i] = dp[i] - cp[i] * x[i + 1];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* primitive variables                                                       */
+/* ------------------------------------------------------------------------ */
+/* reading: velocities are momenta divided by the arithmetic mean of the two
+ * densities on either side of the face (index space). */
+static void primitives(const orc_grid *g, const orc_state *S, double *th, double *u, double *v,
+                       double *w)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                th[c] = S->rt[c] / S->rho[c];
+                u[c] = S->ru[c] / (0.5 * (cget(g, S->rho, i - 1, j, k) + S->rho[c]));
+                v[c] = S->rv[c] / (0.5 * (cget(g, S->rho, i, j - 1, k) + S->rho[c]));
+            }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k <= nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                if (k == 0 || k == nz)
+                    w[c] = 0.0;
+                else
+                    w[c] = S->rw[c] / (0.5 * (S->rho[CIDX(g, i, j, k - 1)] + S->rho[CIDX(g, i, j, k)]));
+            }
+}
+
+/* face value q_{m-1/2} along x of a centre-located (or y-face / z-face-in-x)
+ * field f, m = i, evaluated with the given order and upwind sign */
+static double ix(const orc_grid *g, const double *f, int i, int j, int k, int order, double s)
+{
+    double q[6];
+    for (int o = 0; o < 6; ++o) q[o] = cget(g, f, i - 3 + o, j, k);
+    return orc_interp(order, q, s);
+}
+static double iy(const orc_grid *g, const double *f, int i, int j, int k, int order, double s)
+{
+    double q[6];
+    for (int o = 0; o < 6; ++o) q[o] = cget(g, f, i, j - 3 + o, k);
+    return orc_interp(order, q, s);
+}
+/* along z for centre-located / horizontal-face fields (even ghosts) */
+static double izc(const orc_grid *g, const double *f, int i, int j, int k, int order, double s)
+{
+    double q[6];
+    for (int o = 0; o < 6; ++o) q[o] = cget(g, f, i, j, k - 3 + o);
+    return orc_interp(order, q, s);
+}
+/* along z for z-face fields (odd ghosts) */
+static double izw(const orc_grid *g, const double *f, int i, int j, int k, int order, double s)
+{
+    double q[6];
+    for (int o = 0; o < 6; ++o) q[o] = wget(g, f, i, j, k - 3 + o);
+    return orc_interp(order, q, s);
+}
+/* a z-face field read at a given face along x (periodic, no vertical ghost) */
+static double ixw(const orc_grid *g, const double *f, int i, int j, int k, int order, double s)
+{
+    double q[6];
+    for (int o = 0; o < 6; ++o) q[o] = wget(g, f, i - 3 + o, j, k);
+    return orc_interp(order, q, s);
+}
+static double iyw(const orc_grid *g, const double *f, int i, int j, int k, int order, double s)
+{
+    double q[6];
+    for (int o = 0; o < 6; ++o) q[o] = wget(g, f, i, j - 3 + o, k);
+    return orc_interp(order, q, s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* stress tensor and heat flux, eq. (stresstensor), Sec. 2.3                 */
+/* ------------------------------------------------------------------------ */
+/* reading: tau = -2 mu (S - D), mu = rho nu_m + rho (Cs Delta)^2 |S| with
+ * Delta = (dx dy dz)^(1/3) and |S| = sqrt(2 S:S).  Diagonal strain at cell
+ * centres, off-diagonal strain on cell edges, mu averaged from the four cells
+ * around an edge.  Heat diffusivity rho alpha_m + mu_t / Pr_t.  Free-slip lids:
+ * S13 = S23 = 0 on the bottom and top faces. */
+static void add_diffusion(const orc_grid *g, const orc_params *P, const orc_state *S,
+                          const double *th, const double *u, const double *v, const double *w,
+                          orc_state *R)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    size_t n = (size_t)nx * ny * nz, nw = (size_t)nx * ny * (nz + 1);
+    double dx = g->dx, dy = g->dy;
+    const double *dz = g->dz;
+    double *s11 = dalloc(n), *s22 = dalloc(n), *s33 = dalloc(n);
+    double *s12 = dalloc(n), *s13 = dalloc(nw), *s23 = dalloc(nw);
+    double *mu = dalloc(n), *kh = dalloc(n);
+
+    /* strain rates */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                s11[c] = (cget(g, u, i + 1, j, k) - u[c]) / dx;
+                s22[c] = (cget(g, v, i, j + 1, k) - v[c]) / dy;
+                s33[c] = (w[CIDX(g, i, j, k + 1)] - w[c]) / dz[k];
+                /* S12 on the edge of x-face i and y-face j */
+                s12[c] = 0.5 * ((u[c] - cget(g, u, i, j - 1, k)) / dy + (v[c] - cget(g, v, i - 1, j, k)) / dx);
+            }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k <= nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                if (k == 0 || k == nz) {
+                    s13[c] = 0.0;
+                    s23[c] = 0.0;
+                } else {
+                    double dzf = 0.5 * (dz[k - 1] + dz[k]);
+                    s13[c] = 0.5 * ((u[c] - u[CIDX(g, i, j, k - 1)]) / dzf + (w[c] - wget(g, w, i - 1, j, k)) / dx);
+                    s23[c] = 0.5 * ((v[c] - v[CIDX(g, i, j, k - 1)]) / dzf + (w[c] - wget(g, w, i, j - 1, k)) / dy);
+                }
+            }
+    /* viscosity and diffusivity at centres */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                double mut = 0.0;
+                if (P->sgs == 1) {
+                    double a12 = 0.25 * (s12[c] + cget(g, s12, i + 1, j, k) + cget(g, s12, i, j + 1, k) + cget(g, s12, i + 1, j + 1, k));
+                    double a13 = 0.25 * (s13[c] + wget(g, s13, i + 1, j, k) + s13[CIDX(g, i, j, k + 1)] + wget(g, s13, i + 1, j, k + 1));
+                    double a23 = 0.25 * (s23[c] + wget(g, s23, i, j + 1, k) + s23[CIDX(g, i, j, k + 1)] + wget(g, s23, i, j + 1, k + 1));
+                    double ss = 2.0 * (s11[c] * s11[c] + s22[c] * s22[c] + s33[c] * s33[c])
+                              + 4.0 * (a12 * a12 + a13 * a13 + a23 * a23);
+                    double delta = cbrt(dx * dy * dz[k]);
+                    double cd = P->Cs * delta;
+                    mut = S->rho[c] * cd * cd * sqrt(ss);
+                }
+                mu[c] = S->rho[c] * P->nu_m + mut;
+                kh[c] = S->rho[c] * P->alpha_m + (P->sgs == 1 ? mut / P->Pr_t : 0.0);
+            }
+
+    /* stress components: tau_ii at centres, tau_12 at xy-edges, tau_13/23 at z-face edges */
+    double *t11 = dalloc(n), *t22 = dalloc(n), *t33 = dalloc(n), *t12 = dalloc(n);
+    double *t13 = dalloc(nw), *t23 = dalloc(nw);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                double d = (s11[c] + s22[c] + s33[c]) / 3.0;
+                t11[c] = -2.0 * mu[c] * (s11[c] - d);
+                t22[c] = -2.0 * mu[c] * (s22[c] - d);
+                t33[c] = -2.0 * mu[c] * (s33[c] - d);
+                double me = 0.25 * (cget(g, mu, i - 1, j - 1, k) + cget(g, mu, i, j - 1, k) + cget(g, mu, i - 1, j, k) + mu[c]);
+                t12[c] = -2.0 * me * s12[c];
+            }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 1; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                double mxz = 0.25 * (cget(g, mu, i - 1, j, k - 1) + cget(g, mu, i, j, k - 1) + cget(g, mu, i - 1, j, k) + cget(g, mu, i, j, k));
+                double myz = 0.25 * (cget(g, mu, i, j - 1, k - 1) + cget(g, mu, i, j, k - 1) + cget(g, mu, i, j - 1, k) + cget(g, mu, i, j, k));
+                t13[c] = -2.0 * mxz * s13[c];
+                t23[c] = -2.0 * myz * s23[c];
+            }
+
+    /* R += -div(tau) on each momentum face; R_Theta += div(K grad theta) */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                R->ru[c] -= (t11[c] - cget(g, t11, i - 1, j, k)) / dx
+                          + (cget(g, t12, i, j + 1, k) - t12[c]) / dy
+                          + (t13[CIDX(g, i, j, k + 1)] - t13[c]) / dz[k];
+                R->rv[c] -= (cget(g, t12, i + 1, j, k) - t12[c]) / dx
+                          + (t22[c] - cget(g, t22, i, j - 1, k)) / dy
+                          + (t23[CIDX(g, i, j, k + 1)] - t23[c]) / dz[k];
+                /* heat: upward/rightward diffusive flux H = -K dtheta/dn */
+                double hx0 = -0.5 * (cget(g, kh, i - 1, j, k) + kh[c]) * (th[c] - cget(g, th, i - 1, j, k)) / dx;
+                double hx1 = -0.5 * (kh[c] + cget(g, kh, i + 1, j, k)) * (cget(g, th, i + 1, j, k) - th[c]) / dx;
+                double hy0 = -0.5 * (cget(g, kh, i, j - 1, k) + kh[c]) * (th[c] - cget(g, th, i, j - 1, k)) / dy;
+                double hy1 = -0.5 * (kh[c] + cget(g, kh, i, j + 1, k)) * (cget(g, th, i, j + 1, k) - th[c]) / dy;
+                double hz0 = 0.0, hz1 = 0.0;
+                if (k > 0)
+                    hz0 = -0.5 * (kh[CIDX(g, i, j, k - 1)] + kh[c]) * (th[c] - th[CIDX(g, i, j, k - 1)]) / (0.5 * (dz[k - 1] + dz[k]));
+                if (k < nz - 1)
+                    hz1 = -0.5 * (kh[c] + kh[CIDX(g, i, j, k + 1)]) * (th[CIDX(g, i, j, k + 1)] - th[c]) / (0.5 * (dz[k] + dz[k + 1]));
+                R->rt[c] -= (hx1 - hx0) / dx + (hy1 - hy0) / dy + (hz1 - hz0) / dz[k];
+            }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 1; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                double dzf = 0.5 * (dz[k - 1] + dz[k]);
+                R->rw[c] -= (wget(g, t13, i + 1, j, k) - t13[c]) / dx
+                          + (wget(g, t23, i, j + 1, k) - t23[c]) / dy
+                          + (t33[c] - t33[CIDX(g, i, j, k - 1)]) / dzf;
+            }
+    free(s11); free(s22); free(s33); free(s12); free(s13); free(s23);
+    free(mu); free(kh); free(t11); free(t22); free(t33); free(t12); free(t13); free(t23);
+}
+
+/* ------------------------------------------------------------------------ */
+/* slow right-hand side                                                      */
+/* ------------------------------------------------------------------------ */
+int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
+                 const orc_state *S, orc_state *R)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    if (nx < 1 || ny < 1 || nz < 1) return -2;
+    int oh = P->adv_order_h, ov = P->adv_order_v;
+    if (oh < 2 || oh > 6 || ov < 2 || ov > 6) return -1;
+    size_t n = (size_t)nx * ny * nz, nw = (size_t)nx * ny * (nz + 1);
+    double dx = g->dx, dy = g->dy, gr = P->grav;
+    const double *dz = g->dz;
+    double *th = dalloc(n), *u = dalloc(n), *v = dalloc(n), *w = dalloc(nw), *pp = dalloc(n);
+    primitives(g, S, th, u, v, w);
+    for (int k = 0; k < nz; ++k) {
+        double T0 = B->rho0[k] * B->theta0[k];
+        for (size_t c = (size_t)k * nx * ny; c < (size_t)(k + 1) * nx * ny; ++c)
+            pp[c] = orc_eos_pprime(S->rt[c], T0, B->p0[k]);
+    }
+
+    /* --- continuity and potential temperature, eqs. (con), (theta) --- */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                double U0 = S->ru[c], U1 = cget(g, S->ru, i + 1, j, k);
+                double V0 = S->rv[c], V1 = cget(g, S->rv, i, j + 1, k);
+                double W0 = S->rw[c], W1 = S->rw[CIDX(g, i, j, k + 1)];
+                R->rho[c] = -((U1 - U0) / dx + (V1 - V0) / dy + (W1 - W0) / dz[k]);
+                double fx0 = U0 * ix(g, th, i, j, k, oh, sgn(U0));
+                double fx1 = U1 * ix(g, th, i + 1, j, k, oh, sgn(U1));
+                double fy0 = V0 * iy(g, th, i, j, k, oh, sgn(V0));
+                double fy1 = V1 * iy(g, th, i, j + 1, k, oh, sgn(V1));
+                double fz0 = (k == 0) ? 0.0 : W0 * izc(g, th, i, j, k, ov, sgn(W0));
+                double fz1 = (k == nz - 1) ? 0.0 : W1 * izc(g, th, i, j, k + 1, ov, sgn(W1));
+                R->rt[c] = -((fx1 - fx0) / dx + (fy1 - fy0) / dy + (fz1 - fz0) / dz[k]);
+            }
+
+    /* --- x-momentum on x-faces, eq. (mom) --- */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                /* xx-flux at the centres right (i) and left (i-1) of the face */
+                double a_r = 0.5 * (S->ru[c] + cget(g, S->ru, i + 1, j, k));
+                double a_l = 0.5 * (cget(g, S->ru, i - 1, j, k) + S->ru[c]);
+                double fxx_r = a_r * ix(g, u, i + 1, j, k, oh, sgn(a_r));
+                double fxx_l = a_l * ix(g, u, i, j, k, oh, sgn(a_l));
+                /* xy-flux on the edges at y-faces j and j+1 */
+                double b_0 = 0.5 * (cget(g, S->rv, i - 1, j, k) + S->rv[c]);
+                double b_1 = 0.5 * (cget(g, S->rv, i - 1, j + 1, k) + cget(g, S->rv, i, j + 1, k));
+                double fxy0 = b_0 * iy(g, u, i, j, k, oh, sgn(b_0));
+                double fxy1 = b_1 * iy(g, u, i, j + 1, k, oh, sgn(b_1));
+                /* xz-flux on the edges at z-faces k and k+1 */
+                double e_0 = (k == 0) ? 0.0 : 0.5 * (wget(g, S->rw, i - 1, j, k) + S->rw[c]);
+                double e_1 = (k == nz - 1) ? 0.0 : 0.5 * (wget(g, S->rw, i - 1, j, k + 1) + S->rw[CIDX(g, i, j, k + 1)]);
+                double fxz0 = (k == 0) ? 0.0 : e_0 * izc(g, u, i, j, k, ov, sgn(e_0));
+                double fxz1 = (k == nz - 1) ? 0.0 : e_1 * izc(g, u, i, j, k + 1, ov, sgn(e_1));
+                double adv = (fxx_r - fxx_l) / dx + (fxy1 - fxy0) / dy + (fxz1 - fxz0) / dz[k];
+                double pgf = (pp[c] - cget(g, pp, i - 1, j, k)) / dx;
+                double rho_f = 0.5 * (cget(g, S->rho, i - 1, j, k) + S->rho[c]);
+                /* reading: f-plane Coriolis with geostrophic forcing, the
+                 * v-momentum averaged from the four surrounding y-faces */
+                double vbar = 0.25 * (cget(g, S->rv, i - 1, j, k) + S->rv[c] + cget(g, S->rv, i - 1, j + 1, k) + cget(g, S->rv, i, j + 1, k));
+                double cor = P->f_cor * (vbar - rho_f * P->Vg);
+                R->ru[c] = -adv - pgf + cor;
+            }
+
+    /* --- y-momentum on y-faces --- */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                double b_r = 0.5 * (S->rv[c] + cget(g, S->rv, i, j + 1, k));
+                double b_l = 0.5 * (cget(g, S->rv, i, j - 1, k) + S->rv[c]);
+                double fyy_r = b_r * iy(g, v, i, j + 1, k, oh, sgn(b_r));
+                double fyy_l = b_l * iy(g, v, i, j, k, oh, sgn(b_l));
+                double a_0 = 0.5 * (cget(g, S->ru, i, j - 1, k) + S->ru[c]);
+                double a_1 = 0.5 * (cget(g, S->ru, i + 1, j - 1, k) + cget(g, S->ru, i + 1, j, k));
+                double fyx0 = a_0 * ix(g, v, i, j, k, oh, sgn(a_0));
+                double fyx1 = a_1 * ix(g, v, i + 1, j, k, oh, sgn(a_1));
+                double e_0 = (k == 0) ? 0.0 : 0.5 * (wget(g, S->rw, i, j - 1, k) + S->rw[c]);
+                double e_1 = (k == nz - 1) ? 0.0 : 0.5 * (wget(g, S->rw, i, j - 1, k + 1) + S->rw[CIDX(g, i, j, k + 1)]);
+                double fyz0 = (k == 0) ? 0.0 : e_0 * izc(g, v, i, j, k, ov, sgn(e_0));
+                double fyz1 = (k == nz - 1) ? 0.0 : e_1 * izc(g, v, i, j, k + 1, ov, sgn(e_1));
+                double adv = (fyx1 - fyx0) / dx + (fyy_r - fyy_l) / dy + (fyz1 - fyz0) / dz[k];
+                double pgf = (pp[c] - cget(g, pp, i, j - 1, k)) / dy;
+                double rho_f = 0.5 * (cget(g, S->rho, i, j - 1, k) + S->rho[c]);
+                double ubar = 0.25 * (cget(g, S->ru, i, j - 1, k) + cget(g, S->ru, i + 1, j - 1, k) + S->ru[c] + cget(g, S->ru, i + 1, j, k));
+                double cor = -P->f_cor * (ubar - rho_f * P->Ug);
+                R->rv[c] = -adv - pgf + cor;
+            }
+
+    /* --- z-momentum on interior z-faces; buoyancy B = -(rho - rho0) g --- */
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            R->rw[CIDX(g, i, j, 0)] = 0.0;
+            R->rw[CIDX(g, i, j, nz)] = 0.0;
+        }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 1; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k), cm = CIDX(g, i, j, k - 1);
+                double dzf = 0.5 * (dz[k - 1] + dz[k]);
+                /* zx-flux on the edges at x-faces i and i+1 */
+                double a_0 = 0.5 * (S->ru[cm] + S->ru[c]);
+                double a_1 = 0.5 * (cget(g, S->ru, i + 1, j, k - 1) + cget(g, S->ru, i + 1, j, k));
+                double fzx0 = a_0 * ixw(g, w, i, j, k, oh, sgn(a_0));
+                double fzx1 = a_1 * ixw(g, w, i + 1, j, k, oh, sgn(a_1));
+                double b_0 = 0.5 * (S->rv[cm] + S->rv[c]);
+                double b_1 = 0.5 * (cget(g, S->rv, i, j + 1, k - 1) + cget(g, S->rv, i, j + 1, k));
+                double fzy0 = b_0 * iyw(g, w, i, j, k, oh, sgn(b_0));
+                double fzy1 = b_1 * iyw(g, w, i, j + 1, k, oh, sgn(b_1));
+                /* zz-flux at the centres above (k) and below (k-1) the face */
+                double e_u = 0.5 * (S->rw[c] + S->rw[CIDX(g, i, j, k + 1)]);
+                double e_d = 0.5 * (S->rw[cm] + S->rw[c]);
+                double fzz_u = e_u * izw(g, w, i, j, k + 1, ov, sgn(e_u));
+                double fzz_d = e_d * izw(g, w, i, j, k, ov, sgn(e_d));
+                double adv = (fzx1 - fzx0) / dx + (fzy1 - fzy0) / dy + (fzz_u - fzz_d) / dzf;
+                double pgf = (pp[c] - pp[cm]) / dzf;
+                /* reading of the garbled sign: heavier-than-base air sinks */
+                double buoy = -gr * 0.5 * ((S->rho[c] - B->rho0[k]) + (S->rho[cm] - B->rho0[k - 1]));
+                R->rw[c] = -adv - pgf + buoy;
+            }
+
+    if (P->sgs != 0 || P->nu_m != 0.0 || P->alpha_m != 0.0) add_diffusion(g, P, S, th, u, v, w, R);
+
+    /* prescribed kinematic surface heat flux enters the lowest cell (Sec. 3.8) */
+    if (P->surf_heat_flux != 0.0)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, 0);
+                R->rt[c] += S->rho[c] * P->surf_heat_flux / dz[0];
+            }
+
+    free(th); free(u); free(v); free(w); free(pp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* acoustic substepping, App. C                                              */
+/* ------------------------------------------------------------------------ */
+/* Readings: coefficients are frozen at the stage state S^t (Sec. 3.1); face
+ * values of theta^t and pi^t are two-point means; in the buoyancy correction
+ * of the W'' equation rho-bar and pi-bar are the base state on the face; the
+ * horizontal pressure gradient uses Theta'' predicted forward by
+ * beta_d (Theta'' - Theta''_previous substep) (divergence damping, Sec. 3.1),
+ * with no prediction on a stage's first substep. */
+int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base *B,
+                          const orc_state *Sn, const orc_state *St, const orc_state *Rt,
+                          int32_t n_sub, double dtau, orc_state *Sout,
+                          double *Fu, double *Fv, double *Fw)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    if (n_sub < 1) return -1;
+    size_t n = (size_t)nx * ny * nz, nw = (size_t)nx * ny * (nz + 1);
+    double dx = g->dx, dy = g->dy, gr = P->grav;
+    const double *dz = g->dz;
+    double b1 = 0.5 * (1.0 - P->beta_s), b2 = 0.5 * (1.0 + P->beta_s), bd = P->beta_d;
+
+    double *tht = dalloc(n), *pit = dalloc(n);
+    double *U2 = dalloc(n), *V2 = dalloc(n), *W2 = dalloc(nw), *T2 = dalloc(n), *R2 = dalloc(n);
+    double *T2p = dalloc(n), *Un = dalloc(n), *Vn = dalloc(n), *Wn = dalloc(nw), *Tn = dalloc(n), *Rn = dalloc(n);
+    double *sU = dalloc(n), *sV = dalloc(n), *sW = dalloc(nw);
+
+    for (size_t c = 0; c < n; ++c) {
+        tht[c] = St->rt[c] / St->rho[c];
+        pit[c] = exner(St->rt[c]);
+        U2[c] = Sn->ru[c] - St->ru[c];
+        V2[c] = Sn->rv[c] - St->rv[c];
+        T2[c] = Sn->rt[c] - St->rt[c];
+        R2[c] = Sn->rho[c] - St->rho[c];
+        T2p[c] = T2[c];
+    }
+    for (size_t c = 0; c < nw; ++c) W2[c] = Sn->rw[c] - St->rw[c];
+
+    for (int s = 0; s < n_sub; ++s) {
+        /* 1. horizontal momenta, explicit forward step with the predicted Theta'' */
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    size_t c = CIDX(g, i, j, k);
+                    double tt_c = T2[c] + bd * (T2[c] - T2p[c]);
+                    double tt_w = cget(g, T2, i - 1, j, k) + bd * (cget(g, T2, i - 1, j, k) - cget(g, T2p, i - 1, j, k));
+                    double tt_s = cget(g, T2, i, j - 1, k) + bd * (cget(g, T2, i, j - 1, k) - cget(g, T2p, i, j - 1, k));
+                    double pfx = 0.5 * (cget(g, pit, i - 1, j, k) + pit[c]);
+                    double pfy = 0.5 * (cget(g, pit, i, j - 1, k) + pit[c]);
+                    Un[c] = U2[c] + dtau * (-GAM * R_D * pfx * (tt_c - tt_w) / dx + Rt->ru[c]);
+                    Vn[c] = V2[c] + dtau * (-GAM * R_D * pfy * (tt_c - tt_s) / dy + Rt->rv[c]);
+                }
+        /* 2. per column: explicit parts of Theta'', rho''; implicit W'' */
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double th_hat[nz], rh_hat[nz], ta[nz + 1], tb[nz + 1], tc[nz + 1], tr[nz + 1], tx[nz + 1];
+                /* face theta^t in this column (lids carry W = 0, value unused) */
+#define THZ(kk) (((kk) <= 0 || (kk) >= nz) ? 0.0 : 0.5 * (tht[CIDX(g, i, j, (kk) - 1)] + tht[CIDX(g, i, j, (kk))]))
+                for (int k = 0; k < nz; ++k) {
+                    size_t c = CIDX(g, i, j, k);
+                    double thx0 = 0.5 * (cget(g, tht, i - 1, j, k) + tht[c]);
+                    double thx1 = 0.5 * (tht[c] + cget(g, tht, i + 1, j, k));
+                    double thy0 = 0.5 * (cget(g, tht, i, j - 1, k) + tht[c]);
+                    double thy1 = 0.5 * (tht[c] + cget(g, tht, i, j + 1, k));
+                    double Ue = cget(g, Un, i + 1, j, k), Uw = Un[c];
+                    double Vn_ = cget(g, Vn, i, j + 1, k), Vs = Vn[c];
+                    double Wt = W2[CIDX(g, i, j, k + 1)], Wb = W2[c];
+                    double hdiv_t = (Ue * thx1 - Uw * thx0) / dx + (Vn_ * thy1 - Vs * thy0) / dy;
+                    double hdiv_r = (Ue - Uw) / dx + (Vn_ - Vs) / dy;
+                    th_hat[k] = T2[c] + dtau * (-hdiv_t - b1 * (Wt * THZ(k + 1) - Wb * THZ(k)) / dz[k] + Rt->rt[c]);
+                    rh_hat[k] = R2[c] + dtau * (-hdiv_r - b1 * (Wt - Wb) / dz[k] + Rt->rho[c]);
+                }
+                /* Tridiagonal system for W at faces 1..nz-1, obtained by
+                 * substituting Theta''_new = th_hat - dtau b2 dz(W theta_f)/dz and
+                 * rho''_new = rh_hat - dtau b2 dz(W)/dz into the W'' equation.  Its
+                 * rows are (k - 1) in ta/tb/tc/tr. */
+                int m = nz - 1;
+                double D = dtau * dtau * b2 * b2;
+                for (int k = 1; k < nz; ++k) {
+                    size_t c = CIDX(g, i, j, k), cm = CIDX(g, i, j, k - 1);
+                    double dzf = 0.5 * (dz[k - 1] + dz[k]);
+                    double pif = 0.5 * (pit[cm] + pit[c]);
+                    double A = GAM * R_D * pif;
+                    double Cc = gr * 0.5 * (B->rho0[k - 1] + B->rho0[k]) * (R_D / C_V)
+                              * (pif / (0.5 * (B->pi0[k - 1] + B->pi0[k])))
+                              / (0.5 * (St->rt[cm] + St->rt[c]));
+                    double idzm = 1.0 / dz[k - 1], idz = 1.0 / dz[k];
+                    double tfm = THZ(k - 1), tf = THZ(k), tfp = THZ(k + 1);
+                    ta[k - 1] = -D * (A * tfm * idzm / dzf + 0.5 * Cc * tfm * idzm - 0.5 * gr * idzm);
+                    tc[k - 1] = -D * (A * tfp * idz / dzf - 0.5 * Cc * tfp * idz + 0.5 * gr * idz);
+                    tb[k - 1] = 1.0 + D * (A * tf * (idz + idzm) / dzf + 0.5 * Cc * tf * (idzm - idz) - 0.5 * gr * (idzm - idz));
+                    double tbk = b1 * T2[c] + b2 * th_hat[k], tbm = b1 * T2[cm] + b2 * th_hat[k - 1];
+                    double rbk = b1 * R2[c] + b2 * rh_hat[k], rbm = b1 * R2[cm] + b2 * rh_hat[k - 1];
+                    tr[k - 1] = W2[c] + dtau * (-A * (tbk - tbm) / dzf + 0.5 * Cc * (tbk + tbm) - 0.5 * gr * (rbk + rbm) + Rt->rw[c]);
+                }
+                if (m > 0) {
+                    ta[0] = 0.0;
+                    tc[m - 1] = 0.0;
+                    orc_thomas(m, ta, tb, tc, tr, tx);
+                }
+                Wn[CIDX(g, i, j, 0)] = 0.0;
+                Wn[CIDX(g, i, j, nz)] = 0.0;
+                for (int k = 1; k < nz; ++k) Wn[CIDX(g, i, j, k)] = tx[k - 1];
+                for (int k = 0; k < nz; ++k) {
+                    size_t c = CIDX(g, i, j, k);
+                    double Wt = Wn[CIDX(g, i, j, k + 1)], Wb = Wn[c];
+                    Tn[c] = th_hat[k] - dtau * b2 * (Wt * THZ(k + 1) - Wb * THZ(k)) / dz[k];
+                    Rn[c] = rh_hat[k] - dtau * b2 * (Wt - Wb) / dz[k];
+                }
+                for (int k = 0; k <= nz; ++k) {
+                    size_t c = CIDX(g, i, j, k);
+                    sW[c] += b1 * W2[c] + b2 * Wn[c];
+                }
+#undef THZ
+            }
+        /* 3. time sums of the horizontal momenta; advance the substep state */
+        for (size_t c = 0; c < n; ++c) {
+            sU[c] += Un[c];
+            sV[c] += Vn[c];
+            T2p[c] = T2[c];
+            T2[c] = Tn[c];
+            R2[c] = Rn[c];
+            U2[c] = Un[c];
+            V2[c] = Vn[c];
+        }
+        for (size_t c = 0; c < nw; ++c) W2[c] = Wn[c];
+    }
+
+    /* stage end: S = S^t + S'' (App. C); stage-averaged momenta (Sec. 3.1) */
+    for (size_t c = 0; c < n; ++c) {
+        Sout->rho[c] = St->rho[c] + R2[c];
+        Sout->rt[c] = St->rt[c] + T2[c];
+        Sout->ru[c] = St->ru[c] + U2[c];
+        Sout->rv[c] = St->rv[c] + V2[c];
+        if (Fu) Fu[c] = St->ru[c] + sU[c] / n_sub;
+        if (Fv) Fv[c] = St->rv[c] + sV[c] / n_sub;
+    }
+    for (size_t c = 0; c < nw; ++c) {
+        Sout->rw[c] = St->rw[c] + W2[c];
+        if (Fw) Fw[c] = St->rw[c] + sW[c] / n_sub;
+    }
+
+    free(tht); free(pit); free(U2); free(V2); free(W2); free(T2); free(R2); free(T2p);
+    free(Un); free(Vn); free(Wn); free(Tn); free(Rn); free(sU); free(sV); free(sW);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* scalar advance with stage-averaged fluxes (Sec. 3.1)                     */
+/* ------------------------------------------------------------------------ */
+int orc_scalar_advance(const orc_grid *g, const orc_params *P, const orc_state *Sn,
+                       const orc_state *St, const double *Fu, const double *Fv,
+                       const double *Fw, double dts, double *rq_out)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz, nq = P->n_scalars;
+    if (nq <= 0) return 0;
+    if (P->sgs != 0 || P->alpha_m != 0.0) return -5; /* scalar diffusion not provided */
+    size_t n = (size_t)nx * ny * nz;
+    int oh = P->adv_order_h, ov = P->adv_order_v;
+    double *q = dalloc(n);
+    for (int s = 0; s < nq; ++s) {
+        const double *rqn = Sn->rq + (size_t)s * n, *rqt = St->rq + (size_t)s * n;
+        double *out = rq_out + (size_t)s * n;
+        for (size_t c = 0; c < n; ++c) q[c] = rqt[c] / St->rho[c];
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    size_t c = CIDX(g, i, j, k);
+                    double f[6]; /* x0, x1, y0, y1, z0, z1 */
+                    double adv[6] = {Fu[c], cget(g, Fu, i + 1, j, k), Fv[c], cget(g, Fv, i, j + 1, k),
+                                     Fw[c], Fw[CIDX(g, i, j, k + 1)]};
+                    double qq[6];
+                    for (int side = 0; side < 2; ++side) {
+                        for (int o = 0; o < 6; ++o) qq[o] = cget(g, q, i + side - 3 + o, j, k);
+                        double fa = adv[side];
+                        f[side] = fa * (P->scalar_scheme == 1 ? orc_weno5(qq, sgn(fa), WENO_EPS) : orc_interp(oh, qq, sgn(fa)));
+                        for (int o = 0; o < 6; ++o) qq[o] = cget(g, q, i, j + side - 3 + o, k);
+                        fa = adv[2 + side];
+                        f[2 + side] = fa * (P->scalar_scheme == 1 ? orc_weno5(qq, sgn(fa), WENO_EPS) : orc_interp(oh, qq, sgn(fa)));
+                        int kf = k + side;
+                        if (kf == 0 || kf == nz) {
+                            f[4 + side] = 0.0;
+                        } else {
+                            for (int o = 0; o < 6; ++o) qq[o] = cget(g, q, i, j, kf - 3 + o);
+                            fa = adv[4 + side];
+                            f[4 + side] = fa * (P->scalar_scheme == 1 ? orc_weno5(qq, sgn(fa), WENO_EPS) : orc_interp(ov, qq, sgn(fa)));
+                        }
+                    }
+                    double div = (f[1] - f[0]) / g->dx + (f[3] - f[2]) / g->dy + (f[5] - f[4]) / g->dz[k];
+                    out[c] = rqn[c] - dts * div;
+                }
+    }
+    free(q);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* RK3 step with acoustic substeps (Sec. 3.1, Sec. 3.3)                      */
+/* ------------------------------------------------------------------------ */
+/* Stage s advances from S^n with the right-hand side at the latest stage
+ * state: dt/3 with one substep, dt/2 with n_s/2 substeps, dt with n_s
+ * substeps, the substep length being dt/n_s in the last two stages. */
+int orc_rk3_step(const orc_grid *g, const orc_params *P, const orc_base *B, orc_state *S)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz, nq = P->n_scalars;
+    int ns = P->n_substeps;
+    if (ns < 2 || ns % 2 != 0) return -1;
+    size_t n = (size_t)nx * ny * nz, nw = (size_t)nx * ny * (nz + 1), nqn = (size_t)(nq > 0 ? nq : 0) * n;
+    orc_state Sn, St, Rt, Snew;
+    double *bufs[4][6];
+    size_t sz[6] = {n, n, n, n, nw, nqn};
+    for (int b = 0; b < 4; ++b)
+        for (int f = 0; f < 6; ++f) bufs[b][f] = dalloc(sz[f]);
+#define BIND(st, b) st.rho = bufs[b][0], st.rt = bufs[b][1], st.ru = bufs[b][2], st.rv = bufs[b][3], st.rw = bufs[b][4], st.rq = bufs[b][5]
+    BIND(Sn, 0);
+    BIND(St, 1);
+    BIND(Rt, 2);
+    BIND(Snew, 3);
+#undef BIND
+    double *Fu = dalloc(n), *Fv = dalloc(n), *Fw = dalloc(nw);
+    memcpy(Sn.rho, S->rho, n * 8); memcpy(Sn.rt, S->rt, n * 8); memcpy(Sn.ru, S->ru, n * 8);
+    memcpy(Sn.rv, S->rv, n * 8); memcpy(Sn.rw, S->rw, nw * 8);
+    if (nqn) memcpy(Sn.rq, S->rq, nqn * 8);
+    memcpy(St.rho, S->rho, n * 8); memcpy(St.rt, S->rt, n * 8); memcpy(St.ru, S->ru, n * 8);
+    memcpy(St.rv, S->rv, n * 8); memcpy(St.rw, S->rw, nw * 8);
+    if (nqn) memcpy(St.rq, S->rq, nqn * 8);
+
+    int rc = 0;
+    for (int stage = 0; stage < 3 && rc == 0; ++stage) {
+        double dts = stage == 0 ? P->dt / 3.0 : (stage == 1 ? P->dt / 2.0 : P->dt);
+        int nsub = stage == 0 ? 1 : (stage == 1 ? ns / 2 : ns);
+        double dtau = stage == 0 ? P->dt / 3.0 : P->dt / ns;
+        rc = orc_slow_rhs(g, P, B, &St, &Rt);
+        if (rc) break;
+        rc = orc_acoustic_substeps(g, P, B, &Sn, &St, &Rt, nsub, dtau, &Snew, Fu, Fv, Fw);
+        if (rc) break;
+        if (nq > 0) rc = orc_scalar_advance(g, P, &Sn, &St, Fu, Fv, Fw, dts, Snew.rq);
+        /* the new stage state */
+        orc_state tmp = St;
+        St = Snew;
+        Snew = tmp;
+    }
+    if (rc == 0) {
+        memcpy(S->rho, St.rho, n * 8); memcpy(S->rt, St.rt, n * 8); memcpy(S->ru, St.ru, n * 8);
+        memcpy(S->rv, St.rv, n * 8); memcpy(S->rw, St.rw, nw * 8);
+        if (nqn) memcpy(S->rq, St.rq, nqn * 8);
+    }
+    for (int b = 0; b < 4; ++b)
+        for (int f = 0; f < 6; ++f) free(bufs[b][f]);
+    free(Fu); free(Fv); free(Fw);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* diagnostics (mass and energy budgets, Sec. 4.1.2)                          */
+/* ------------------------------------------------------------------------ */
+/* Kahan-compensated sums in the plain cell order. */
+typedef struct { double s, c; } ksum;
+static void kadd(ksum *k, double x)
+{
+    double y = x - k->c;
+    double t = k->s + y;
+    k->c = (t - k->s) - y;
+    k->s = t;
+}
+
+int orc_diagnostics(const orc_grid *g, const orc_params *P, const orc_base *B,
+                    const orc_state *S, double *out)
+{
+    (void)B;
+    int nx = g->nx, ny = g->ny, nz = g->nz, nq = P->n_scalars;
+    size_t n = (size_t)nx * ny * nz, nw = (size_t)nx * ny * (nz + 1);
+    ksum mass = {0, 0}, theta = {0, 0}, energy = {0, 0};
+    ksum *qm = (ksum *)calloc((size_t)(nq > 0 ? nq : 1), sizeof(ksum));
+    double wmax = 0.0, nonfinite = 0.0;
+    double z = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        double zc = z + 0.5 * g->dz[k];
+        double vol = g->dx * g->dy * g->dz[k];
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                double r = S->rho[c], T = S->rt[c];
+                kadd(&mass, r * vol);
+                kadd(&theta, T * vol);
+                double uc = 0.5 * (S->ru[c] / (0.5 * (cget(g, S->rho, i - 1, j, k) + r))
+                                 + cget(g, S->ru, i + 1, j, k) / (0.5 * (r + cget(g, S->rho, i + 1, j, k))));
+                double vc = 0.5 * (S->rv[c] / (0.5 * (cget(g, S->rho, i, j - 1, k) + r))
+                                 + cget(g, S->rv, i, j + 1, k) / (0.5 * (r + cget(g, S->rho, i, j + 1, k))));
+                double wb = (k == 0) ? 0.0 : S->rw[c] / (0.5 * (S->rho[CIDX(g, i, j, k - 1)] + r));
+                double wt = (k == nz - 1) ? 0.0 : S->rw[CIDX(g, i, j, k + 1)] / (0.5 * (r + S->rho[CIDX(g, i, j, k + 1)]));
+                double wc = 0.5 * (wb + wt);
+                double temp = (T / r) * exner(T);
+                kadd(&energy, (0.5 * r * (uc * uc + vc * vc + wc * wc) + r * C_V * temp + r * P->grav * zc) * vol);
+                for (int s = 0; s < nq; ++s) kadd(&qm[s], S->rq[(size_t)s * n + c] * vol);
+                if (!isfinite(r) || !isfinite(T) || !isfinite(S->ru[c]) || !isfinite(S->rv[c])) nonfinite += 1.0;
+            }
+        z += g->dz[k];
+    }
+    for (size_t c = 0; c < nw; ++c) {
+        if (!isfinite(S->rw[c])) nonfinite += 1.0;
+    }
+    for (int k = 1; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double wv = fabs(S->rw[CIDX(g, i, j, k)] / (0.5 * (S->rho[CIDX(g, i, j, k - 1)] + S->rho[CIDX(g, i, j, k)])));
+                if (wv > wmax) wmax = wv;
+            }
+    out[0] = mass.s;
+    out[1] = theta.s;
+    out[2] = energy.s;
+    out[3] = wmax;
+    out[4] = nonfinite;
+    for (int s = 0; s < nq; ++s) out[5 + s] = qm[s].s;
+    free(qm);
+    return 0;
+}

@@ -1,0 +1,113 @@
+/*
+ * erf_oracle.h -- plain FP64 CPU oracle of ERF's compressible RK3 step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links or calls this
+ * library; only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  It shares no code, header, table or constant with the HIP
+ * library.  Every routine is a direct, slow transcription of the equations of
+ * Lattanzi et al., "ERF: Energy Research and Forecasting Model" (arXiv
+ * 2412.04395); each function names the passage it follows.
+ *
+ * Layout (all arrays host, double, x fastest):
+ *   cell-centred  f[(k*ny + j)*nx + i],            k < nz
+ *   x-faces       U[(k*ny + j)*nx + i]  face i sits between cells i-1 and i
+ *   y-faces       V[(k*ny + j)*nx + i]  face j sits between cells j-1 and j
+ *   z-faces       W[(k*ny + j)*nx + i],            k <= nz, face k below cell k
+ * Lateral boundaries are periodic; bottom and top are free-slip rigid lids
+ * (W = 0 on faces 0 and nz).
+ */
+#ifndef ERF_ORACLE_H
+#define ERF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t nx, ny, nz;
+    double dx, dy;
+    const double *dz; /* nz cell thicknesses */
+} orc_grid;
+
+typedef struct {
+    double dt;
+    int32_t n_substeps;     /* per full step; even                            */
+    double beta_s;          /* off-centring (App. C), 0.1 in the paper          */
+    double beta_d;          /* forward-prediction weight of divergence damping */
+    int32_t adv_order_h;    /* 2..6, Sec. 3.6                                   */
+    int32_t adv_order_v;    /* 2..6                                            */
+    int32_t scalar_scheme;  /* 0: same interpolants as momentum; 1: WENO5-JS   */
+    int32_t n_scalars;
+    int32_t sgs;            /* 0 none, 1 Smagorinsky                            */
+    double Cs, Pr_t;
+    double nu_m, alpha_m;   /* constant kinematic viscosity / diffusivity       */
+    double f_cor, Ug, Vg;   /* f-plane Coriolis and geostrophic wind           */
+    double surf_heat_flux;  /* kinematic, K m/s                                 */
+    double grav;            /* magnitude of gravity                             */
+} orc_params;
+
+typedef struct {
+    const double *rho0, *theta0, *p0, *pi0; /* nz each */
+} orc_base;
+
+typedef struct {
+    double *rho, *rt, *ru, *rv, *rw, *rq; /* rq: n_scalars consecutive fields */
+} orc_state;
+
+/* physical constants used by the oracle (gas constant, heat capacity, P00) */
+double orc_const(int which); /* 0 R_d, 1 c_p, 2 c_v, 3 gamma, 4 P00 */
+
+/* Hydrostatic base state by Newton iteration, Sec. 2 and Sec. 3.8. */
+int orc_base_state(int32_t nz, const double *dz, const double *theta0, double p_surface,
+                   double grav, double *rho0, double *p0, double *pi0);
+
+/* Equation of state, Sec. 2.1: p = P00 (R_d Theta / P00)^gamma. */
+double orc_eos_p(double Theta);
+/* p' = p(Theta) - p(Theta0) evaluated without cancellation. */
+double orc_eos_pprime(double Theta, double Theta0, double p0);
+
+/* Face interpolant q_{m-1/2} of Sec. 3.6; q = {q_{m-3},...,q_{m+2}}. */
+double orc_interp(int32_t order, const double *q6, double sgn);
+/* WENO5-JS face value q_{m-1/2}; q = {q_{m-3},...,q_{m+2}}, eps is the
+ * regulariser of the smoothness weights. */
+double orc_weno5(const double *q6, double sgn, double eps);
+
+/* Thomas algorithm for a[i] x[i-1] + b[i] x[i] + c[i] x[i+1] = r[i], n >= 1. */
+int orc_thomas(int32_t n, const double *a, const double *b, const double *c,
+               const double *r, double *x);
+
+/* Slow right-hand side f(S) of eqs. (con), (mom), (theta) (Sec. 2.1, 2.3,
+ * 3.6, 3.7, 3.8).  R->rq is not touched. */
+int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
+                 const orc_state *S, orc_state *R);
+
+/* One RK stage of semi-implicit acoustic substepping, App. C and Sec. 3.1.
+ * Starts from S'' = S_n - S_t, takes n_sub substeps of size dtau, writes the
+ * stage-end state S_t + S'' into Sout (rho, rt, ru, rv, rw) and the
+ * stage-averaged normal momenta into Fu, Fv, Fw. */
+int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base *B,
+                          const orc_state *Sn, const orc_state *St, const orc_state *Rt,
+                          int32_t n_sub, double dtau, orc_state *Sout,
+                          double *Fu, double *Fv, double *Fw);
+
+/* Scalar update with time-averaged fluxes (Sec. 3.1):
+ * (rho q)^new = (rho q)^n - dts div(F q^t). */
+int orc_scalar_advance(const orc_grid *g, const orc_params *P, const orc_state *Sn,
+                       const orc_state *St, const double *Fu, const double *Fv,
+                       const double *Fw, double dts, double *rq_out);
+
+/* One full RK3 step with substeps (Sec. 3.1, 3.3), in place. */
+int orc_rk3_step(const orc_grid *g, const orc_params *P, const orc_base *B, orc_state *S);
+
+/* FP64 diagnostics: out[0] mass, out[1] sum Theta dV, out[2] total energy,
+ * out[3] max |w|, out[4] number of non-finite values, out[5..5+nq) scalar
+ * masses. */
+int orc_diagnostics(const orc_grid *g, const orc_params *P, const orc_base *B,
+                    const orc_state *S, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,307 @@
+"""Seeded synthetic workloads: grids, run parameters and initial conditions.
+
+This module is the only code shared by the oracle side and the HIP side.  It
+holds input descriptions and input generators and none of the method's
+arithmetic: the hydrostatic base state is computed by each side and passed in.
+
+Noise is counter-based: SplitMix64 (Steele, Lea & Flood 2014) applied to
+``(seed << 32) | linear_cell_index`` gives 64 random bits; the top 53 bits make
+a uniform u in [0, 1) and the perturbation is ``a * (2u - 1)``.  The same cell
+therefore gets the same value whatever the order of generation.
+
+The workloads stand in for the paper's: a dry warm bubble (Sec. 4.1.2), a
+convective boundary layer LES like the scaling case of Sec. 5.2 (5th-order
+upwind, Smagorinsky), an 80-level deep-atmosphere case with three advected
+moisture tracers like the squall-line timing case of Sec. 5.2, and a density
+current (Sec. 4.1.1) used for validation.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+# gas constant and heat capacity used only to write soundings (inputs)
+_RD, _CP, _P00 = 287.0, 1004.5, 1.0e5
+
+
+@dataclasses.dataclass
+class Config:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: np.ndarray
+    dt: float
+    n_substeps: int
+    steps: int = 1
+    beta_s: float = 0.1
+    beta_d: float = 0.1
+    adv_order_h: int = 2
+    adv_order_v: int = 2
+    scalar_scheme: int = 0  # 0: momentum interpolants, 1: WENO5-JS
+    n_scalars: int = 0
+    sgs: int = 0  # 0 none, 1 Smagorinsky
+    Cs: float = 0.1
+    Pr_t: float = 1.0 / 3.0
+    nu_m: float = 0.0
+    alpha_m: float = 0.0
+    f_cor: float = 0.0
+    Ug: float = 0.0
+    Vg: float = 0.0
+    surf_heat_flux: float = 0.0
+    grav: float = 9.81
+    prec: str = "fp64"  # "fp64" or "fp32" (FP32 bulk, FP64 column solve and sums)
+    p_surface: float = 1.0e5
+    seed: int = 1
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def replace(self, **kw) -> "Config":
+        return dataclasses.replace(self, **kw)
+
+    def z_centres(self) -> np.ndarray:
+        dz = np.asarray(self.dz, dtype=np.float64)
+        return np.cumsum(dz) - 0.5 * dz
+
+    def z_faces(self) -> np.ndarray:
+        dz = np.asarray(self.dz, dtype=np.float64)
+        return np.concatenate([[0.0], np.cumsum(dz)])
+
+
+# ---------------------------------------------------------------------------
+# counter-based noise
+# ---------------------------------------------------------------------------
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def splitmix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function of the 64-bit counter x (numpy uint64)."""
+    x = np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform_noise(seed: int, shape, amplitude: float) -> np.ndarray:
+    """a*(2u-1) for every cell of ``shape`` (x fastest), counter = seed<<32 | index."""
+    n = int(np.prod(shape))
+    ctr = (np.uint64(seed) << np.uint64(32)) | np.arange(n, dtype=np.uint64)
+    u = (splitmix64(ctr) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return (amplitude * (2.0 * u - 1.0)).reshape(shape)
+
+
+# ---------------------------------------------------------------------------
+# vertical grids and soundings
+# ---------------------------------------------------------------------------
+def uniform_dz(nz: int, dz: float) -> np.ndarray:
+    return np.full(nz, float(dz))
+
+
+def stretched_dz(nz: int, dz0: float, dzmax: float, ztop: float) -> np.ndarray:
+    """dz_k = min(dz0 r^k, dzmax) with r chosen by bisection so that sum = ztop."""
+    def total(r):
+        return float(np.minimum(dz0 * r ** np.arange(nz), dzmax).sum())
+    lo, hi = 1.0, 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if total(mid) < ztop:
+            lo = mid
+        else:
+            hi = mid
+    dz = np.minimum(dz0 * (0.5 * (lo + hi)) ** np.arange(nz), dzmax)
+    return dz * (ztop / dz.sum())
+
+
+def theta_sounding(cfg: Config) -> np.ndarray:
+    """Base-state potential temperature at cell centres for each workload."""
+    z = cfg.z_centres()
+    kind = cfg.name.split("@")[0]
+    if kind.startswith("cbl") or kind.startswith("mlp") or kind.startswith("ens"):
+        return np.where(z < 1000.0, 300.0, 300.0 + 3.0e-3 * (z - 1000.0))
+    if kind.startswith("deep"):
+        th_tr, z_tr, T_tr = 343.0, 12000.0, 213.0
+        below = 300.0 + (th_tr - 300.0) * (z / z_tr) ** 1.25
+        above = th_tr * np.exp(cfg.grav * (z - z_tr) / (_CP * T_tr))
+        return np.where(z <= z_tr, below, above)
+    if kind.startswith("isothermal"):
+        # theta of an isothermal atmosphere at T = 300 K: theta = T (P00/p)^kappa,
+        # p = p_s exp(-g z / (R_d T)) (an input profile, not a base state)
+        T = 300.0
+        return T * np.exp(cfg.grav * z / (_CP * T))
+    return np.full(cfg.nz, 300.0)
+
+
+# ---------------------------------------------------------------------------
+# initial states.  Perturbations of theta are applied at constant pressure:
+# rho*theta keeps its base value and rho = Theta0 / (theta0 + dtheta).
+# ---------------------------------------------------------------------------
+def _centres_xy(cfg: Config):
+    x = (np.arange(cfg.nx) + 0.5) * cfg.dx
+    y = (np.arange(cfg.ny) + 0.5) * cfg.dy
+    return x, y
+
+
+def _face_mean_x(f: np.ndarray) -> np.ndarray:
+    return 0.5 * (np.roll(f, 1, axis=-1) + f)
+
+
+def _face_mean_y(f: np.ndarray) -> np.ndarray:
+    return 0.5 * (np.roll(f, 1, axis=-2) + f)
+
+
+def state_from_theta(cfg: Config, rho0: np.ndarray, theta0: np.ndarray, dtheta: np.ndarray,
+                     u0: float = 0.0, v0: float = 0.0) -> dict:
+    nz, ny, nx = cfg.nz, cfg.ny, cfg.nx
+    Theta0 = (rho0 * theta0)[:, None, None] * np.ones((nz, ny, nx))
+    th = theta0[:, None, None] + dtheta
+    rho = Theta0 / th
+    S = {
+        "rho": np.ascontiguousarray(rho),
+        "rt": np.ascontiguousarray(Theta0),
+        "ru": np.ascontiguousarray(_face_mean_x(rho) * u0),
+        "rv": np.ascontiguousarray(_face_mean_y(rho) * v0),
+        "rw": np.zeros((nz + 1, ny, nx)),
+        "rq": np.zeros((cfg.n_scalars, nz, ny, nx)),
+    }
+    return S
+
+
+def initial_state(cfg: Config, rho0: np.ndarray, theta0: np.ndarray, p0: Optional[np.ndarray] = None,
+                  pi0: Optional[np.ndarray] = None) -> dict:
+    """Seeded initial state of workload ``cfg`` around the given base state."""
+    nz, ny, nx = cfg.nz, cfg.ny, cfg.nx
+    x, y = _centres_xy(cfg)
+    z = cfg.z_centres()
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    kind = cfg.name.split("@")[0]
+    dth = np.zeros((nz, ny, nx))
+    u0 = v0 = 0.0
+    if kind.startswith("bubble"):
+        # warm bubble: 2 cos^2(pi r / 2), r < 1 (Sec. 4.1.2), centred mid-domain
+        xc, zc, rr = 0.5 * nx * cfg.dx, 2000.0, 2000.0
+        r = np.sqrt(((X - xc) / rr) ** 2 + ((Z - zc) / rr) ** 2)
+        dth = np.where(r < 1.0, 2.0 * np.cos(0.5 * np.pi * r) ** 2, 0.0)
+        dth = dth + uniform_noise(cfg.seed, (nz, ny, nx), 0.01)
+    elif kind.startswith("density_current"):
+        # cold bubble of Sec. 4.1.1 (temperature decrement -15 K), mirrored
+        # about x = 0 in a periodic domain of twice the paper's half width
+        xc, zc, xr, zr = 0.5 * nx * cfg.dx, 3000.0, 4000.0, 2000.0
+        L = np.sqrt(((X - xc) / xr) ** 2 + ((Z - zc) / zr) ** 2)
+        dT = np.where(L < 1.0, -15.0 * (np.cos(np.pi * L) + 1.0) / 2.0, 0.0)
+        if pi0 is None:
+            raise ValueError("density current needs the base-state Exner function")
+        dth = dT / pi0[:, None, None]
+    elif kind.startswith("cbl") or kind.startswith("mlp") or kind.startswith("ens"):
+        dth = np.where(Z < 400.0, uniform_noise(cfg.seed, (nz, ny, nx), 0.1), 0.0)
+        u0, v0 = cfg.Ug, cfg.Vg
+    elif kind.startswith("deep"):
+        xc = 0.5 * nx * cfg.dx
+        dxl = np.abs(X - xc)
+        taper = np.where(dxl <= 10000.0, 1.0,
+                         np.where(dxl <= 12000.0, np.cos(0.5 * np.pi * (dxl - 10000.0) / 2000.0) ** 2, 0.0))
+        dth = np.where(Z < 2000.0, -5.0 * (1.0 - Z / 2000.0), 0.0) * taper
+        dth = dth + uniform_noise(cfg.seed, (nz, ny, nx), 0.1)
+    elif kind.startswith("isothermal"):
+        pass
+    elif kind.startswith("rest"):
+        pass
+    else:
+        raise ValueError(f"unknown workload {cfg.name}")
+    S = state_from_theta(cfg, rho0, theta0, dth, u0, v0)
+    if cfg.n_scalars > 0:
+        S["rq"] = scalar_layers(cfg, S["rho"], rho0, theta0, p0, pi0)
+    return S
+
+
+def scalar_layers(cfg: Config, rho: np.ndarray, rho0, theta0, p0, pi0) -> np.ndarray:
+    """rho*q for the advected tracers: q_v from a relative-humidity profile
+    (Bolton 1980 saturation pressure), q_c and q_r smooth layers."""
+    nz, ny, nx = cfg.nz, cfg.ny, cfg.nx
+    z = cfg.z_centres()
+    q = np.zeros((cfg.n_scalars, nz, ny, nx))
+    if p0 is not None and pi0 is not None:
+        T = theta0 * pi0
+        es = 611.2 * np.exp(17.67 * (T - 273.15) / (T - 29.65))
+        qvs = 0.622 * es / (p0 - es)
+        rh = np.where(z < 1500.0, 0.9,
+                      np.where(z < 12000.0, 0.9 - 0.65 * ((z - 1500.0) / 10500.0) ** 1.25, 0.25))
+        qv = rh * qvs
+    else:
+        qv = 0.01 * np.exp(-z / 3000.0)
+    qc = 1e-4 * np.exp(-((z - 3000.0) / 1000.0) ** 2)
+    qr = 1e-5 * np.exp(-((z - 1500.0) / 500.0) ** 2)
+    prof = [qv, qc, qr]
+    noise = uniform_noise(cfg.seed + 1000, (nz, ny, nx), 1.0)
+    for s in range(cfg.n_scalars):
+        base = prof[s % 3][:, None, None]
+        q[s] = rho * base * (1.0 + 0.05 * noise)
+    return np.ascontiguousarray(q)
+
+
+# ---------------------------------------------------------------------------
+# the workloads
+# ---------------------------------------------------------------------------
+def bubble2d(**kw) -> Config:
+    """Dry 2-D x-z warm bubble, FP64: 64x1x64 at 125 m, 2nd order, no SGS,
+    dt = 1 s, 6 substeps, 100 steps."""
+    c = Config(name="bubble2d", nx=64, ny=1, nz=64, dx=125.0, dy=125.0, dz=uniform_dz(64, 125.0),
+               dt=1.0, n_substeps=6, steps=100, adv_order_h=2, adv_order_v=2, seed=1)
+    return c.replace(**kw)
+
+
+def cbl(n_substeps: int = 6, **kw) -> Config:
+    """3-D dry convective boundary layer LES: 256x256x128, 20 m x 20 m x 10 m,
+    5th-order upwind, Smagorinsky Cs = 0.1, geostrophic wind 10 m/s,
+    surface heat flux 0.2 K m/s, dt = 0.5 s."""
+    c = Config(name="cbl", nx=256, ny=256, nz=128, dx=20.0, dy=20.0, dz=uniform_dz(128, 10.0),
+               dt=0.5, n_substeps=n_substeps, steps=20, adv_order_h=5, adv_order_v=5, sgs=1,
+               Cs=0.1, Pr_t=1.0 / 3.0, f_cor=1.0e-4, Ug=10.0, Vg=0.0, surf_heat_flux=0.2, seed=2)
+    return c.replace(**kw)
+
+
+def deep(**kw) -> Config:
+    """80-level deep atmosphere, stretched dz 50-500 m to 20 km, 250 m horizontal,
+    3 tracers by WENO5, 3rd-order momentum, dt = 2 s, 8 substeps."""
+    nz = kw.pop("nz", 80)
+    c = Config(name="deep", nx=512, ny=512, nz=nz, dx=250.0, dy=250.0,
+               dz=stretched_dz(nz, 50.0, 500.0, 20000.0), dt=2.0, n_substeps=8, steps=20,
+               adv_order_h=3, adv_order_v=3, scalar_scheme=1, n_scalars=3, prec="fp32", seed=3)
+    return c.replace(**kw)
+
+
+def density_current(dx: float = 100.0, **kw) -> Config:
+    """Straka density current (Sec. 4.1.1) at 100 m, mirrored to a periodic
+    51.2 km x 6.4 km domain; nu = alpha = 75 m^2/s, 3rd-order advection."""
+    nx, nz = int(round(51200.0 / dx)), int(round(6400.0 / dx))
+    c = Config(name="density_current", nx=nx, ny=1, nz=nz, dx=dx, dy=dx, dz=uniform_dz(nz, dx),
+               dt=dx / 100.0, n_substeps=6, steps=int(round(900.0 / (dx / 100.0))), adv_order_h=3,
+               adv_order_v=3, nu_m=75.0, alpha_m=75.0)
+    return c.replace(**kw)
+
+
+def small(name: str = "bubble_small", **kw) -> Config:
+    """A small case for parity tests: several tiles and a ragged tail."""
+    base = dict(name=name, nx=37, ny=21, nz=19, dx=125.0, dy=100.0, dz=uniform_dz(19, 100.0),
+                dt=1.0, n_substeps=6, steps=3, adv_order_h=5, adv_order_v=3, seed=7)
+    if "nz" in kw and "dz" not in kw:
+        kw["dz"] = uniform_dz(kw["nz"], 100.0)
+    base.update(kw)
+    return Config(**base)
+
+
+CONFIGS = {
+    "bubble2d": bubble2d,
+    "cbl": cbl,
+    "deep": deep,
+    "density_current": density_current,
+}
