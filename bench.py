@@ -1,0 +1,183 @@
+"""Benchmark: cell-updates/s of one RK3 step (with all acoustic substeps) of the
+compressible dynamical core on one MI355X, through the C-ABI of liberf.so.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Prints ONE JSON line.  The workload is the 3-D dry convective boundary layer
+LES, 256 x 256 x 128 cells, FP64 (5th-order upwind advection, Smagorinsky,
+Coriolis with geostrophic wind, surface heat flux), with seeded synthetic
+initial data.  As specified (dt = 0.5 s, 6 substeps) the horizontal acoustic
+substep is unstable at 20 m spacing and the run diverges in its first step;
+the headline therefore uses the stable variant with 14 substeps per step, and
+the as-specified variant is timed beside it (values do not change the
+arithmetic performed).
+
+``value`` is whole-job throughput with inputs resident in HBM; the roofline
+object refers to the kernel with the largest share of the step time, whose
+average launch duration is measured with HIP events recorded by the library on
+its own stream during the timed steps.  ``cpu_baseline`` times the FP64 CPU
+oracle (a reported baseline, never the target) on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2412_04395_amd import workloads as W  # noqa: E402
+
+METRIC = "cell-updates/s per RK3 step (incl. acoustic substeps), % HBM roofline, FP64 vs FP32"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+# Compulsory (algorithmic) FP64 values moved per cell by one launch of each
+# kernel: every distinct input field read once and every output written once.
+# n_s-independent; 'sgs' adds the eddy-viscosity field where it is read.
+KERNEL_VALUES = {
+    # rho, Theta, U, V, W, theta, p', u, v, w (+ mu_t) read; 5 tendencies written
+    "rhs": lambda sgs: 10 + sgs + 5,
+    # rho, Theta, U, V, W read; theta, p', u, v, w written
+    "prep": lambda sgs: 5 + 5,
+    # rho, u, v, w read; mu_t written
+    "mut": lambda sgs: 4 + 1,
+    # Theta''(2 levels), Exner, U'', V'', R_U, R_V, sum U, sum V read; U'', V'', sums written
+    "horiz": lambda sgs: 9 + 4,
+    # U'', V'', Theta'', rho'', W'', R_Theta, R_rho, R_W, theta^t, 5 coefficient
+    # fields, sum W read; Theta''_new, rho'', W'', sum W written
+    "column": lambda sgs: 15 + 4,
+    "stage_init": lambda sgs: 12 + 11,
+    "coef": lambda sgs: 4 + 5,
+    "finalize": lambda sgs: 14 + 8,
+}
+
+
+def _cfg(workload: str) -> W.Config:
+    if workload == "cbl":
+        return W.cbl(n_substeps=14, name="cbl@stable_ns14")
+    if workload == "cbl_as_stated":
+        return W.cbl(n_substeps=6, name="cbl@as_stated_ns6")
+    if workload == "bubble2d":
+        return W.bubble2d()
+    raise SystemExit(f"unknown workload {workload}")
+
+
+def _time_steps(s, S, steps: int, torch, kernel: str | None = None):
+    if kernel:
+        s.timing_begin(kernel, max_launches=64 * steps + 64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.rk3_step(S)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = s.timing_end() if kernel else (0.0, 0)
+    return el, kt
+
+
+def run_gpu(cfg: W.Config, steps: int, warmup: int):
+    import torch
+    from paper_2412_04395_amd import erf
+
+    s = erf.Solver(cfg)
+    th0 = W.theta_sounding(cfg)
+    b = s.init_base_state(th0)
+    S = s.to_device(W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"]))
+    for _ in range(warmup):
+        s.rk3_step(S)
+    # find the kernel with the largest share of a step (one short timed step per kernel)
+    shares = {}
+    for k in KERNEL_VALUES:
+        if k == "mut" and not cfg.sgs:
+            continue
+        _, (ms, n) = _time_steps(s, S, 1, torch, kernel=k)
+        if n:
+            shares[k] = (ms, n)
+    dominant = max(shares, key=lambda k: shares[k][0])
+    el, (kms, kn) = _time_steps(s, S, steps, torch, kernel=dominant)
+    d = s.diagnostics(S, allow_nonfinite=True)
+    s.close()
+    return el, dominant, kms, kn, shares, d
+
+
+def cpu_baseline(cfg: W.Config, target_s: float = 15.0):
+    """FP64 oracle on a bounded sample: the same physics on a 64 x 64 column
+    block of the workload (periodic), timed for whole RK3 steps."""
+    import oracle
+
+    sample = cfg.replace(nx=64, ny=64, name=cfg.name)
+    o = oracle.Oracle(sample)
+    th0 = W.theta_sounding(sample)
+    b = o.init_base_state(th0, sample.p_surface)
+    S = W.initial_state(sample, b["rho0"], th0, b["p0"], b["pi0"])
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.rk3_step(S)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > target_s or steps >= 3:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": sample.cells * steps / el, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{sample.nx}x{sample.ny}x{sample.nz} block of the same workload, {steps} RK3 steps, "
+                      f"{el:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cbl")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-as-stated", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU layout is a design "
+              f"in DESIGN.md, not a measured path", file=sys.stderr)
+        return 2
+    rank = int(os.environ.get("RANK", "0"))
+
+    cfg = _cfg(a.workload)
+    el, dom, kms, kn, shares, diag = run_gpu(cfg, a.steps, a.warmup)
+    value = cfg.cells * a.steps / el
+    sgs = 1 if cfg.sgs else 0
+    avg_ms = kms / max(kn, 1)
+    bytes_per_launch = KERNEL_VALUES[dom](sgs) * 8.0 * cfg.cells
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_ms, 4),
+            "launches_timed": kn}
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * el / a.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if cfg.prec == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": cfg.name, "grid": [cfg.nx, cfg.ny, cfg.nz], "cells": cfg.cells,
+                   "dt": cfg.dt, "n_substeps": cfg.n_substeps, "adv_order": [cfg.adv_order_h, cfg.adv_order_v],
+                   "sgs": "smagorinsky" if cfg.sgs else "none", "precision": cfg.prec},
+        "roofline": roof,
+        "kernel_ms_per_step": {k: round(v[0], 4) for k, v in shares.items()},
+        "final_diag": {"max_w": diag["max_w"], "nonfinite": diag["nonfinite"]},
+    }
+    if a.workload == "cbl" and not a.no_as_stated:
+        c2 = _cfg("cbl_as_stated")
+        el2, *_ = run_gpu(c2, a.steps, a.warmup)
+        out["as_stated"] = {"workload": c2.name, "value": c2.cells * a.steps / el2,
+                            "ms_per_step": 1e3 * el2 / a.steps, "note": "diverges in the first step (acoustic "
+                            "CFL); timed for throughput only"}
+    if rank == 0 and not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,182 @@
+/*
+ * erf.h -- C-ABI of liberf.so, an MI355X (gfx950) implementation of one RK3
+ * large time step of ERF's compressible dynamical core (Lattanzi et al.,
+ * "ERF: Energy Research and Forecasting Model", arXiv 2412.04395).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Grid: Arakawa C-grid (Sec. 3.4), nx x ny x nz cells, x fastest.  Lateral
+ * boundaries are periodic; the bottom and the top are free-slip rigid lids.
+ * Vertical spacing may vary per level (Sec. 3.4, stretched grids).
+ *
+ * Field layout in device memory (row-major, x fastest, no halo):
+ *   rho, rhotheta         [nz][ny][nx]    cell centres
+ *   rhou                  [nz][ny][nx]    x-face i lies between cells i-1 and i
+ *   rhov                  [nz][ny][nx]    y-face j lies between cells j-1 and j
+ *   rhow                  [nz+1][ny][nx]  z-face k lies below cell k; faces 0
+ *                                         and nz carry rho w = 0
+ *   rhoq                  [n_scalars][nz][ny][nx]
+ * Element type: double for ERF_FP64.  For ERF_FP32_MIXED every field is float
+ * and rho / rhotheta hold the perturbations rho - rho0(z) and
+ * rho*theta - rho0(z)*theta0(z) about the hydrostatic base state.
+ *
+ * Ownership: the caller owns every state, tendency and flux buffer (device
+ * memory, for instance torch tensors); the library never frees them.  The
+ * context owns its workspace, allocated once in erf_create.
+ *
+ * Streams: every call that takes a context enqueues its work on the HIP stream
+ * given to erf_create and returns without waiting, except erf_init_base_state
+ * and erf_diagnostics, which write host memory and wait for their own work.
+ *
+ * Errors: every call returns an erf_status.  Argument and shape errors are
+ * detected before anything is launched and leave the context usable.  A HIP
+ * error is sticky: the context then refuses further work (ERF_E_HIP) until it
+ * is destroyed.  erf_last_error returns a description of the latest failure.
+ * No call aborts or exits the process.
+ */
+#ifndef ERF_H
+#define ERF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ERF_OK = 0,
+    ERF_E_ARG = -1,         /* null pointer or parameter out of range        */
+    ERF_E_SHAPE = -2,       /* grid sizes not supported                     */
+    ERF_E_HIP = -3,         /* a HIP runtime call failed (sticky)           */
+    ERF_E_NONFINITE = -4,   /* diagnostics found NaN or Inf                 */
+    ERF_E_UNSUPPORTED = -5, /* option combination not provided              */
+    ERF_E_NOMEM = -6,       /* device allocation failed                     */
+    ERF_E_STATE = -7        /* call out of order (no base state yet)        */
+} erf_status;
+
+typedef enum { ERF_FP64 = 0, ERF_FP32_MIXED = 1 } erf_precision;
+typedef enum { ERF_SGS_NONE = 0, ERF_SGS_SMAGORINSKY = 1 } erf_sgs_model;
+typedef enum { ERF_SCALAR_INTERP = 0, ERF_SCALAR_WENO5 = 1 } erf_scalar_scheme;
+
+typedef struct {
+    int32_t nx, ny, nz;  /* cells; nx, ny >= 1, nz >= 2                          */
+    double dx, dy;       /* horizontal spacing [m]                              */
+    const double *dz;    /* host array of nz cell thicknesses [m], copied       */
+} erf_grid;
+
+typedef struct {
+    double dt;               /* large time step [s]                               */
+    int32_t n_substeps;      /* acoustic substeps per step, even (Sec. 3.3)       */
+    double beta_s;           /* off-centring of the vertical implicit terms
+                                (App. C; the paper uses 0.1)                      */
+    double beta_d;           /* divergence damping: horizontal pressure gradient
+                                uses Theta'' + beta_d (Theta'' - Theta''_prev)
+                                (Sec. 3.1)                                        */
+    int32_t adv_order_h;     /* 2..6, interpolants of Sec. 3.6, horizontal        */
+    int32_t adv_order_v;     /* 2..6, vertical                                    */
+    int32_t scalar_scheme;   /* erf_scalar_scheme for the passive scalars         */
+    int32_t n_scalars;       /* 0..8 advected scalars rho*q                       */
+    int32_t sgs;             /* erf_sgs_model                                     */
+    double Cs, Pr_t;         /* Smagorinsky constant, turbulent Prandtl number    */
+    double nu_m, alpha_m;    /* constant kinematic viscosity and diffusivity      */
+    double f_cor, Ug, Vg;    /* f-plane Coriolis parameter, geostrophic wind      */
+    double surf_heat_flux;   /* prescribed kinematic surface heat flux [K m/s]    */
+    double grav;             /* magnitude of gravity [m/s^2]                      */
+    int32_t precision;       /* erf_precision                                     */
+} erf_params;
+
+/* Device pointers to one state (or tendency, or flux) set; unused members may
+ * be NULL where a call says so. */
+typedef struct {
+    void *rho, *rhotheta, *rhou, *rhov, *rhow, *rhoq;
+} erf_state;
+
+typedef struct {
+    double mass;          /* sum rho dV [kg]                                   */
+    double theta_mass;    /* sum rho theta dV                                   */
+    double energy;        /* sum (rho |u|^2/2 + rho c_v T + rho g z) dV [J]      */
+    double max_w;         /* max |w| over interior z-faces [m/s]               */
+    int64_t nonfinite;    /* number of NaN / Inf values in the state           */
+    double scalar_mass[8];/* sum rho q dV per scalar                           */
+} erf_diag;
+
+typedef struct erf_ctx erf_ctx;
+
+/* Hydrostatic base state on the host, no GPU involved (Sec. 2, Sec. 3.8):
+ * dp0/dz = -rho0 g discretised between level centres with the trapezoidal
+ * density, p0 = EOS(rho0 theta0) (Sec. 2.1), solved level by level with
+ * Newton-Raphson from p(0) = p_surface.  Outputs are host arrays of nz values;
+ * pi0 (Exner function) may be NULL. */
+erf_status erf_base_state_host(int32_t nz, const double *dz, const double *theta0,
+                               double p_surface, double grav, double *rho0, double *p0,
+                               double *pi0);
+
+/* Create a context for one grid and one parameter set.  hip_stream is a
+ * hipStream_t (NULL: the default stream).  The grid's dz array is copied.
+ * Allocates the whole workspace; returns ERF_E_NOMEM if it does not fit. */
+erf_status erf_create(const erf_grid *grid, const erf_params *params, void *hip_stream,
+                      erf_ctx **out);
+void erf_destroy(erf_ctx *ctx);
+const char *erf_last_error(const erf_ctx *ctx);
+
+/* Device bytes of the context's workspace. */
+int64_t erf_workspace_bytes(const erf_ctx *ctx);
+
+/* Build the hydrostatic base state (as erf_base_state_host) from theta0 [nz]
+ * (host) and upload it.  Must precede the calls below.  Optional host outputs
+ * rho0, p0, pi0 [nz] may be NULL.  Synchronous. */
+erf_status erf_init_base_state(erf_ctx *ctx, const double *theta0, double p_surface,
+                               double *rho0, double *p0, double *pi0);
+
+/* Slow right-hand side f(S) of eqs. (con), (mom), (theta) (Sec. 2.1): flux-form
+ * advection with the interpolants of Sec. 3.6, the perturbation pressure
+ * gradient, buoyancy -(rho - rho0) g on z-faces, the stress tensor of
+ * eq. (stresstensor) with constant or Smagorinsky viscosity (Sec. 2.3),
+ * f-plane Coriolis with geostrophic forcing and the surface heat flux
+ * (Sec. 3.7-3.8).  S and R use the state layout; R->rhoq is ignored and may be
+ * NULL.  R->rhow is zero on faces 0 and nz. */
+erf_status erf_slow_rhs(erf_ctx *ctx, const erf_state *S, erf_state *R);
+
+/* One RK stage of semi-implicit acoustic substepping (Sec. 3.1, App. C).
+ * Starting from S'' = S_n - S_t, takes n_sub substeps of length dtau with the
+ * linearisation frozen at S_t and the slow tendencies R_t, and writes the stage
+ * end S_t + S'' to S_out (rho, rhotheta, rhou, rhov, rhow; rhoq untouched) and
+ * the stage-averaged normal momenta used for scalar transport to
+ * flux_avg->rhou / rhov / rhow (may be NULL).  S_out may alias S_n. */
+erf_status erf_acoustic_substeps(erf_ctx *ctx, const erf_state *S_n, const erf_state *S_t,
+                                 const erf_state *R_t, int32_t n_sub, double dtau,
+                                 erf_state *S_out, erf_state *flux_avg);
+
+/* Scalar update after substepping (Sec. 3.1): (rho q)^new = (rho q)^n
+ * - dts div(F q^t), q^t = (rho q)^t / rho^t, with F the stage-averaged momenta
+ * (flux_avg) and the interpolant or WENO5 of Sec. 3.6 upwinded by the sign of
+ * F.  rhoq_out [n_scalars][nz][ny][nx] may alias S_n->rhoq. */
+erf_status erf_scalar_advance(erf_ctx *ctx, const erf_state *S_n, const erf_state *S_t,
+                              const erf_state *flux_avg, double dts, void *rhoq_out);
+
+/* One full RK3 step (Sec. 3.1): stages of dt/3, dt/2 and dt with 1, n_s/2 and
+ * n_s substeps of length dt/3, dt/n_s and dt/n_s (Sec. 3.3), each stage being
+ * erf_slow_rhs, erf_acoustic_substeps and erf_scalar_advance.  S holds S^n on
+ * entry and S^{n+1} on return (in place). */
+erf_status erf_rk3_step(erf_ctx *ctx, erf_state *S);
+
+/* FP64 global sums of the mass and energy budgets (Sec. 4.1.2) and a count of
+ * non-finite values.  Synchronous.  Returns ERF_E_NONFINITE (with *out filled)
+ * if any state value is NaN or Inf. */
+erf_status erf_diagnostics(erf_ctx *ctx, const erf_state *S, erf_diag *out);
+
+/* Kernel timing for measurement.  While enabled, every launch of the named
+ * kernel is bracketed by two HIP events recorded on the context's stream; up to
+ * max_launches launches are timed, later ones run untimed.  Kernel names:
+ * "prep", "mut", "rhs", "stage_init", "coef", "horiz", "column", "finalize",
+ * "mixing_ratio", "scalar".  erf_timing_begin allocates the events
+ * (ERF_E_NOMEM on failure) and returns ERF_E_ARG for an unknown name. */
+erf_status erf_timing_begin(erf_ctx *ctx, const char *kernel, int32_t max_launches);
+/* Waits for the stream, returns the summed event time [ms] of the timed
+ * launches and their number, frees the events and stops timing. */
+erf_status erf_timing_end(erf_ctx *ctx, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ERF_H */

@@ -1,0 +1,378 @@
+// api.hip -- the C-ABI of liberf.so (include/erf.h): context, workspace,
+// base state and the RK3 driver that sequences the kernels of the other
+// translation units on the context's stream.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "erf_internal.h"
+
+using namespace erfk;
+
+namespace {
+
+erf_status fail(erf_ctx *c, erf_status s, const char *msg)
+{
+    if (c) {
+        c->err = msg;
+        if (s == ERF_E_HIP) c->sticky = ERF_E_HIP;
+    }
+    return s;
+}
+
+erf_status hip_fail(erf_ctx *c, hipError_t e, const char *where)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+    return fail(c, ERF_E_HIP, buf);
+}
+
+#define ERF_CHECK_CTX(c)                                                   \
+    do {                                                                   \
+        if (!(c)) return ERF_E_ARG;                                        \
+        if ((c)->sticky != ERF_OK) return (c)->sticky;                     \
+    } while (0)
+
+double eos_p(double Theta) { return kP00 * std::pow(kRd * Theta / kP00, kGamma); }
+
+// Newton-Raphson for the hydrostatic base state, level by level upward from
+// the surface: p_k = EOS(rho_k theta_k), p_0 = p_s - g (dz_0/2) rho_0 and
+// p_k - p_{k-1} = -g dzf_k (rho_k + rho_{k-1}) / 2.
+erf_status base_state(int nz, const double *dz, const double *theta0, double ps, double g,
+                      double *rho0, double *p0, double *pi0)
+{
+    if (nz < 1 || !dz || !theta0 || !rho0 || !p0) return ERF_E_ARG;
+    double p_prev = ps, rho_prev = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        if (!(theta0[k] > 0.0) || !(dz[k] > 0.0)) return ERF_E_ARG;
+        const double h = (k == 0) ? 0.5 * dz[0] : 0.5 * (dz[k - 1] + dz[k]);
+        double rho = (k == 0) ? ps / (kRd * theta0[0]) : rho_prev;
+        for (int it = 0; it < 30; ++it) {
+            const double p = eos_p(rho * theta0[k]);
+            double f, fp;
+            if (k == 0) {
+                f = p - p_prev + g * h * rho;
+                fp = kGamma * p / rho + g * h;
+            } else {
+                f = p - p_prev + g * h * 0.5 * (rho + rho_prev);
+                fp = kGamma * p / rho + g * h * 0.5;
+            }
+            const double step = f / fp;
+            rho = rho - step;
+            if (std::fabs(step) <= 1e-15 * rho) break;
+        }
+        rho0[k] = rho;
+        p0[k] = eos_p(rho * theta0[k]);
+        if (pi0) pi0[k] = std::pow(p0[k] / kP00, kRd / kCp);
+        p_prev = p0[k];
+        rho_prev = rho;
+    }
+    return ERF_OK;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" {
+
+erf_status erf_base_state_host(int32_t nz, const double *dz, const double *theta0, double p_surface,
+                               double grav, double *rho0, double *p0, double *pi0)
+{
+    return base_state(nz, dz, theta0, p_surface, grav, rho0, p0, pi0);
+}
+
+const char *erf_last_error(const erf_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int64_t erf_workspace_bytes(const erf_ctx *ctx) { return ctx ? ctx->ws_bytes : 0; }
+
+erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_stream, erf_ctx **out)
+{
+    if (!grid || !prm || !out || !grid->dz) return ERF_E_ARG;
+    *out = nullptr;
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 2) return ERF_E_SHAPE;
+    const int64_t nxy = (int64_t)grid->nx * grid->ny;
+    const int64_t nw = nxy * (grid->nz + 1);
+    const int64_t nq = prm->n_scalars;
+    if (nw * (nq > 1 ? nq : 1) >= ((int64_t)1 << 31)) return ERF_E_SHAPE;
+    if (!(grid->dx > 0.0) || !(grid->dy > 0.0)) return ERF_E_ARG;
+    for (int k = 0; k < grid->nz; ++k)
+        if (!(grid->dz[k] > 0.0)) return ERF_E_ARG;
+    if (prm->n_substeps < 2 || prm->n_substeps % 2 != 0) return ERF_E_ARG;
+    if (prm->adv_order_h < 2 || prm->adv_order_h > 6 || prm->adv_order_v < 2 || prm->adv_order_v > 6)
+        return ERF_E_ARG;
+    if (nq < 0 || nq > 8) return ERF_E_ARG;
+    if (prm->sgs != ERF_SGS_NONE && prm->sgs != ERF_SGS_SMAGORINSKY) return ERF_E_ARG;
+    if (prm->scalar_scheme != ERF_SCALAR_INTERP && prm->scalar_scheme != ERF_SCALAR_WENO5) return ERF_E_ARG;
+    if (prm->precision != ERF_FP64) return ERF_E_UNSUPPORTED;
+    if (nq > 0 && (prm->sgs != ERF_SGS_NONE || prm->alpha_m != 0.0)) return ERF_E_UNSUPPORTED;
+    if (!(prm->dt > 0.0) || !(prm->beta_s >= 0.0 && prm->beta_s <= 1.0)) return ERF_E_ARG;
+
+    erf_ctx *c = new (std::nothrow) erf_ctx();
+    if (!c) return ERF_E_NOMEM;
+    c->grid = *grid;
+    c->prm = *prm;
+    c->stream = (hipStream_t)hip_stream;
+    c->d.nx = grid->nx;
+    c->d.ny = grid->ny;
+    c->d.nz = grid->nz;
+    c->d.nxy = (int)nxy;
+    c->d.n = (int)(nxy * grid->nz);
+    c->d.nw = (int)nw;
+    c->dz_host = new double[grid->nz];
+    std::memcpy(c->dz_host, grid->dz, sizeof(double) * grid->nz);
+    c->grid.dz = c->dz_host;
+    (void)hipGetDevice(&c->device);
+
+    // one arena for the whole workspace
+    const size_t n = (size_t)c->d.n, w = (size_t)nw, q = (size_t)(nq > 0 ? nq : 0) * n;
+    struct Req { double **p; size_t count; };
+    Workspace &ws = c->ws;
+    Base &b = c->base;
+    Req reqs[] = {
+        {&ws.sa[0], n}, {&ws.sa[1], n}, {&ws.sa[2], n}, {&ws.sa[3], n}, {&ws.sa[4], w}, {&ws.sa[5], q},
+        {&ws.sb[0], n}, {&ws.sb[1], n}, {&ws.sb[2], n}, {&ws.sb[3], n}, {&ws.sb[4], w}, {&ws.sb[5], q},
+        {&ws.R[0], n}, {&ws.R[1], n}, {&ws.R[2], n}, {&ws.R[3], n}, {&ws.R[4], w},
+        {&ws.th, n}, {&ws.pp, n}, {&ws.pit, n}, {&ws.u, n}, {&ws.v, n}, {&ws.w, w}, {&ws.mut, n},
+        {&ws.t2[0], n}, {&ws.t2[1], n}, {&ws.r2, n}, {&ws.u2, n}, {&ws.v2, n}, {&ws.w2, w},
+        {&ws.su, n}, {&ws.sv, n}, {&ws.sw, w},
+        {&ws.ca, w}, {&ws.cb, w}, {&ws.cc, w}, {&ws.cA, w}, {&ws.cC, w},
+        {&ws.q, q}, {&ws.fu, n}, {&ws.fv, n}, {&ws.fw, w},
+        {&ws.diag, diag_slots_needed()},
+        {&b.rho0, (size_t)grid->nz}, {&b.theta0, (size_t)grid->nz}, {&b.Theta0, (size_t)grid->nz},
+        {&b.p0, (size_t)grid->nz}, {&b.pi0, (size_t)grid->nz}, {&b.dz, 2 * (size_t)grid->nz},
+    };
+    size_t total = 0;
+    for (const Req &r : reqs) total += align_up(r.count * sizeof(double));
+    hipError_t e = hipMalloc(&c->arena, total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete[] c->dz_host;
+        delete c;
+        return ERF_E_NOMEM;
+    }
+    c->ws_bytes = (int64_t)total;
+    char *p = (char *)c->arena;
+    for (const Req &r : reqs) {
+        *r.p = r.count ? (double *)p : nullptr;
+        p += align_up(r.count * sizeof(double));
+    }
+    // dz and centre heights
+    double *hz = new double[2 * grid->nz];
+    double zc = 0.0;
+    for (int k = 0; k < grid->nz; ++k) {
+        hz[k] = grid->dz[k];
+        hz[grid->nz + k] = zc + 0.5 * grid->dz[k];
+        zc += grid->dz[k];
+    }
+    e = hipMemcpy(b.dz, hz, 2 * grid->nz * sizeof(double), hipMemcpyHostToDevice);
+    delete[] hz;
+    if (e != hipSuccess) {
+        erf_destroy(c);
+        return ERF_E_HIP;
+    }
+    *out = c;
+    return ERF_OK;
+}
+
+void erf_destroy(erf_ctx *c)
+{
+    if (!c) return;
+    for (auto &x : c->timing_events)
+        if (x) (void)hipEventDestroy(x);
+    if (c->arena) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->arena);
+    }
+    delete[] c->dz_host;
+    delete c;
+}
+
+erf_status erf_init_base_state(erf_ctx *c, const double *theta0, double p_surface, double *rho0_out,
+                               double *p0_out, double *pi0_out)
+{
+    ERF_CHECK_CTX(c);
+    if (!theta0) return fail(c, ERF_E_ARG, "theta0 is NULL");
+    const int nz = c->d.nz;
+    double *h = new double[5 * nz];
+    double *rho0 = h, *p0 = h + nz, *pi0 = h + 2 * nz, *Th0 = h + 3 * nz, *th0 = h + 4 * nz;
+    erf_status s = base_state(nz, c->dz_host, theta0, p_surface, c->prm.grav, rho0, p0, pi0);
+    if (s != ERF_OK) {
+        delete[] h;
+        return fail(c, s, "base state: invalid theta0 or dz");
+    }
+    for (int k = 0; k < nz; ++k) {
+        th0[k] = theta0[k];
+        Th0[k] = rho0[k] * theta0[k];
+    }
+    hipError_t e = hipMemcpyAsync(c->base.rho0, rho0, nz * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->base.p0, p0, nz * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->base.pi0, pi0, nz * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->base.Theta0, Th0, nz * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->base.theta0, th0, nz * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        delete[] h;
+        return hip_fail(c, e, "uploading the base state");
+    }
+    if (rho0_out) std::memcpy(rho0_out, rho0, nz * sizeof(double));
+    if (p0_out) std::memcpy(p0_out, p0, nz * sizeof(double));
+    if (pi0_out) std::memcpy(pi0_out, pi0, nz * sizeof(double));
+    delete[] h;
+    c->have_base = true;
+    return ERF_OK;
+}
+
+static bool state_ok(const erf_state *S, bool need_q, int nq)
+{
+    return S && S->rho && S->rhotheta && S->rhou && S->rhov && S->rhow && (!need_q || nq == 0 || S->rhoq);
+}
+
+erf_status erf_slow_rhs(erf_ctx *c, const erf_state *S, erf_state *R)
+{
+    ERF_CHECK_CTX(c);
+    if (!c->have_base) return fail(c, ERF_E_STATE, "erf_init_base_state must come first");
+    if (!state_ok(S, false, 0) || !state_ok(R, false, 0)) return fail(c, ERF_E_ARG, "null field pointer");
+    hipError_t e = launch_slow_rhs(c, (const double *)S->rho, (const double *)S->rhotheta, (const double *)S->rhou,
+                                   (const double *)S->rhov, (const double *)S->rhow, (double *)R->rho,
+                                   (double *)R->rhotheta, (double *)R->rhou, (double *)R->rhov, (double *)R->rhow);
+    return e == hipSuccess ? ERF_OK : hip_fail(c, e, "slow rhs launch");
+}
+
+erf_status erf_acoustic_substeps(erf_ctx *c, const erf_state *Sn, const erf_state *St, const erf_state *Rt,
+                                 int32_t n_sub, double dtau, erf_state *Sout, erf_state *flux)
+{
+    ERF_CHECK_CTX(c);
+    if (!c->have_base) return fail(c, ERF_E_STATE, "erf_init_base_state must come first");
+    if (!state_ok(Sn, false, 0) || !state_ok(St, false, 0) || !state_ok(Rt, false, 0) || !state_ok(Sout, false, 0))
+        return fail(c, ERF_E_ARG, "null field pointer");
+    if (n_sub < 1 || !(dtau > 0.0)) return fail(c, ERF_E_ARG, "n_sub >= 1 and dtau > 0 required");
+    const double *sn[5] = {(const double *)Sn->rho, (const double *)Sn->rhotheta, (const double *)Sn->rhou,
+                           (const double *)Sn->rhov, (const double *)Sn->rhow};
+    const double *st[5] = {(const double *)St->rho, (const double *)St->rhotheta, (const double *)St->rhou,
+                           (const double *)St->rhov, (const double *)St->rhow};
+    const double *rt[5] = {(const double *)Rt->rho, (const double *)Rt->rhotheta, (const double *)Rt->rhou,
+                           (const double *)Rt->rhov, (const double *)Rt->rhow};
+    double *so[5] = {(double *)Sout->rho, (double *)Sout->rhotheta, (double *)Sout->rhou, (double *)Sout->rhov,
+                     (double *)Sout->rhow};
+    hipError_t e = launch_acoustic_stage(c, sn, st, rt, n_sub, dtau, so, flux ? (double *)flux->rhou : nullptr,
+                                         flux ? (double *)flux->rhov : nullptr, flux ? (double *)flux->rhow : nullptr);
+    return e == hipSuccess ? ERF_OK : hip_fail(c, e, "acoustic substeps launch");
+}
+
+erf_status erf_scalar_advance(erf_ctx *c, const erf_state *Sn, const erf_state *St, const erf_state *flux, double dts,
+                              void *rhoq_out)
+{
+    ERF_CHECK_CTX(c);
+    if (c->prm.n_scalars == 0) return ERF_OK;
+    if (!Sn || !St || !flux || !Sn->rhoq || !St->rhoq || !St->rho || !flux->rhou || !flux->rhov || !flux->rhow ||
+        !rhoq_out)
+        return fail(c, ERF_E_ARG, "null field pointer");
+    hipError_t e = launch_scalar_advance(c, (const double *)Sn->rhoq, (const double *)St->rho,
+                                         (const double *)St->rhoq, (const double *)flux->rhou,
+                                         (const double *)flux->rhov, (const double *)flux->rhow, dts,
+                                         (double *)rhoq_out);
+    return e == hipSuccess ? ERF_OK : hip_fail(c, e, "scalar advance launch");
+}
+
+erf_status erf_rk3_step(erf_ctx *c, erf_state *S)
+{
+    ERF_CHECK_CTX(c);
+    if (!c->have_base) return fail(c, ERF_E_STATE, "erf_init_base_state must come first");
+    const int nq = c->prm.n_scalars;
+    if (!state_ok(S, true, nq)) return fail(c, ERF_E_ARG, "null field pointer");
+    Workspace &w = c->ws;
+    const double dt = c->prm.dt;
+    const int ns = c->prm.n_substeps;
+    erf_state A{w.sa[0], w.sa[1], w.sa[2], w.sa[3], w.sa[4], w.sa[5]};
+    erf_state B{w.sb[0], w.sb[1], w.sb[2], w.sb[3], w.sb[4], w.sb[5]};
+    erf_state R{w.R[0], w.R[1], w.R[2], w.R[3], w.R[4], nullptr};
+    erf_state F{nullptr, nullptr, w.fu, w.fv, w.fw, nullptr};
+    const erf_state *St = S;
+    erf_state *outs[3] = {&A, &B, S};
+    for (int stage = 0; stage < 3; ++stage) {
+        const double dts = stage == 0 ? dt / 3.0 : (stage == 1 ? dt / 2.0 : dt);
+        const int nsub = stage == 0 ? 1 : (stage == 1 ? ns / 2 : ns);
+        const double dtau = stage == 0 ? dt / 3.0 : dt / ns;
+        erf_status s = erf_slow_rhs(c, St, &R);
+        if (s != ERF_OK) return s;
+        s = erf_acoustic_substeps(c, S, St, &R, nsub, dtau, outs[stage], &F);
+        if (s != ERF_OK) return s;
+        if (nq > 0) {
+            s = erf_scalar_advance(c, S, St, &F, dts, outs[stage]->rhoq);
+            if (s != ERF_OK) return s;
+        }
+        St = outs[stage];
+    }
+    return ERF_OK;
+}
+
+erf_status erf_timing_begin(erf_ctx *c, const char *kernel, int32_t max_launches)
+{
+    ERF_CHECK_CTX(c);
+    if (!kernel || max_launches < 1) return fail(c, ERF_E_ARG, "kernel name and max_launches >= 1 required");
+    int id = -1;
+    for (int k = 0; k < K_COUNT; ++k)
+        if (std::strcmp(kernel, kernel_name(k)) == 0) id = k;
+    if (id < 0) return fail(c, ERF_E_ARG, "unknown kernel name");
+    int64_t ms = 0;
+    double t = 0.0;
+    if (c->timed_kernel >= 0) erf_timing_end(c, &t, &ms);
+    c->timing_events.assign(2 * (size_t)max_launches, nullptr);
+    for (auto &e : c->timing_events) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            for (auto &x : c->timing_events)
+                if (x) (void)hipEventDestroy(x);
+            c->timing_events.clear();
+            return fail(c, ERF_E_NOMEM, "hipEventCreate failed");
+        }
+    }
+    c->timed_kernel = id;
+    c->timed_count = 0;
+    return ERF_OK;
+}
+
+erf_status erf_timing_end(erf_ctx *c, double *total_ms, int64_t *launches)
+{
+    ERF_CHECK_CTX(c);
+    double tot = 0.0;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    for (int i = 0; e == hipSuccess && i < c->timed_count; ++i) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, c->timing_events[2 * i], c->timing_events[2 * i + 1]);
+        tot += ms;
+    }
+    int64_t n = c->timed_count;
+    for (auto &x : c->timing_events)
+        if (x) (void)hipEventDestroy(x);
+    c->timing_events.clear();
+    c->timed_kernel = -1;
+    c->timed_count = 0;
+    if (e != hipSuccess) return hip_fail(c, e, "timing events");
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = n;
+    return ERF_OK;
+}
+
+erf_status erf_diagnostics(erf_ctx *c, const erf_state *S, erf_diag *out)
+{
+    ERF_CHECK_CTX(c);
+    if (!c->have_base) return fail(c, ERF_E_STATE, "erf_init_base_state must come first");
+    if (!state_ok(S, true, c->prm.n_scalars) || !out) return fail(c, ERF_E_ARG, "null pointer");
+    double h[13];
+    hipError_t e = launch_diagnostics(c, (const double *)S->rho, (const double *)S->rhotheta,
+                                      (const double *)S->rhou, (const double *)S->rhov, (const double *)S->rhow,
+                                      (const double *)S->rhoq, h);
+    if (e != hipSuccess) return hip_fail(c, e, "diagnostics");
+    out->mass = h[0];
+    out->theta_mass = h[1];
+    out->energy = h[2];
+    out->max_w = h[3];
+    out->nonfinite = (int64_t)h[4];
+    for (int s = 0; s < 8; ++s) out->scalar_mass[s] = h[5 + s];
+    return out->nonfinite ? ERF_E_NONFINITE : ERF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+// diag.hip -- FP64 budget sums (mass and energy, Sec. 4.1.2) and a non-finite
+// count.  Two passes with a fixed reduction tree, so the result does not
+// depend on scheduling: per-block partials in a grid-stride loop, then one
+// block sums the partials in block order.
+#include "erf_internal.h"
+
+namespace erfk {
+namespace {
+
+constexpr int kSlots = 13;  // mass, theta, energy, maxw, nonfinite, 8 scalars
+constexpr int kBlocks = 1024;
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ int cidx(const Dims &d, int i, int j, int k) { return (k * d.ny + j) * d.nx + i; }
+
+struct DiagArgs {
+    Dims d;
+    int nq;
+    double dx, dy, g;
+    const double *dz, *zc;
+    const double *rho, *rt, *ru, *rv, *rw, *rq;
+    double *part;
+};
+
+__device__ __forceinline__ bool bad(double x) { return !isfinite(x); }
+
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int q = 0; q < kThreads / 64; ++q) r += sh[q];
+    return r;
+}
+__device__ __forceinline__ double block_max(double v, double *sh)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int q = 0; q < kThreads / 64; ++q) r = fmax(r, sh[q]);
+    return r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_diag_partial(DiagArgs a)
+{
+    __shared__ double sh[kThreads / 64];
+    const Dims &d = a.d;
+    double acc[kSlots];
+    for (int s = 0; s < kSlots; ++s) acc[s] = 0.0;
+    const int total = d.nw;
+    for (int c = blockIdx.x * kThreads + threadIdx.x; c < total; c += gridDim.x * kThreads) {
+        int k = c / d.nxy, rem = c - k * d.nxy, j = rem / d.nx, i = rem - j * d.nx;
+        double W = a.rw[c];
+        if (bad(W)) acc[4] += 1.0;
+        if (k > 0 && k < d.nz) {
+            double wv = fabs(W / (0.5 * (a.rho[c - d.nxy] + a.rho[c])));
+            acc[3] = fmax(acc[3], wv);
+        }
+        if (k == d.nz) continue;
+        double vol = a.dx * a.dy * a.dz[k];
+        double r = a.rho[c], T = a.rt[c], U = a.ru[c], V = a.rv[c];
+        acc[4] += (double)bad(r) + (double)bad(T) + (double)bad(U) + (double)bad(V);
+        acc[0] += r * vol;
+        acc[1] += T * vol;
+        int ip = wrap_idx(i + 1, d.nx), im = wrap_idx(i - 1, d.nx), jp = wrap_idx(j + 1, d.ny), jm = wrap_idx(j - 1, d.ny);
+        double uc = 0.5 * (U / (0.5 * (a.rho[cidx(d, im, j, k)] + r)) +
+                           a.ru[cidx(d, ip, j, k)] / (0.5 * (r + a.rho[cidx(d, ip, j, k)])));
+        double vc = 0.5 * (V / (0.5 * (a.rho[cidx(d, i, jm, k)] + r)) +
+                           a.rv[cidx(d, i, jp, k)] / (0.5 * (r + a.rho[cidx(d, i, jp, k)])));
+        double wb = (k == 0) ? 0.0 : W / (0.5 * (a.rho[c - d.nxy] + r));
+        double wt = (k == d.nz - 1) ? 0.0 : a.rw[c + d.nxy] / (0.5 * (r + a.rho[c + d.nxy]));
+        double wc = 0.5 * (wb + wt);
+        double temp = (T / r) * pow(kRd * T / kP00, kGamma - 1.0);
+        acc[2] += (0.5 * r * (uc * uc + vc * vc + wc * wc) + r * kCv * temp + r * a.g * a.zc[k]) * vol;
+        for (int s = 0; s < a.nq && s < 8; ++s) acc[5 + s] += a.rq[(size_t)s * d.n + c] * vol;
+    }
+    for (int s = 0; s < kSlots; ++s) {
+        double v = (s == 3) ? block_max(acc[s], sh) : block_sum(acc[s], sh);
+        if (threadIdx.x == 0) a.part[blockIdx.x * kSlots + s] = v;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_diag_final(double *part, int nblocks)
+{
+    int s = threadIdx.x;
+    if (s >= kSlots) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        double v = part[b * kSlots + s];
+        acc = (s == 3) ? fmax(acc, v) : acc + v;
+    }
+    part[nblocks * kSlots + s] = acc;
+}
+
+}  // namespace
+
+hipError_t launch_diagnostics(erf_ctx *cx, const double *rho, const double *rt, const double *ru,
+                              const double *rv, const double *rw, const double *rq, double *host_out)
+{
+    DiagArgs a{};
+    a.d = cx->d;
+    a.nq = cx->prm.n_scalars;
+    a.dx = cx->grid.dx;
+    a.dy = cx->grid.dy;
+    a.g = cx->prm.grav;
+    a.dz = cx->base.dz;
+    a.zc = cx->base.dz + cx->d.nz;  // centre heights follow dz in the same buffer
+    a.rho = rho;
+    a.rt = rt;
+    a.ru = ru;
+    a.rv = rv;
+    a.rw = rw;
+    a.rq = rq;
+    a.part = cx->ws.diag;
+    int nb = (cx->d.nw + kThreads - 1) / kThreads;
+    if (nb > kBlocks) nb = kBlocks;
+    hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(kThreads), 0, cx->stream, a);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, cx->stream, a.part, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(host_out, a.part + (size_t)nb * kSlots, kSlots * sizeof(double), hipMemcpyDeviceToHost,
+                       cx->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(cx->stream);
+}
+
+size_t diag_slots_needed() { return (size_t)(kBlocks + 1) * kSlots; }
+
+}  // namespace erfk

@@ -1,0 +1,258 @@
+"""Thin Python binding of liberf.so (include/erf.h).
+
+Argument marshalling only: every step of the RK3 path runs in the HIP kernels
+of liberf.so.  torch supplies device memory and the stream.  There is no CPU
+fallback: if the library is missing, or no GPU is present, the calls raise.
+
+State dictionaries hold torch tensors on the GPU (float64 in FP64 mode):
+    rho, rt : (nz, ny, nx)     rho and rho*theta at cell centres
+    ru, rv  : (nz, ny, nx)     x-/y-face momenta (face i between cells i-1, i)
+    rw      : (nz+1, ny, nx)   z-face momentum (face k below cell k)
+    rq      : (nq, nz, ny, nx) rho*q of the advected scalars
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liberf.so")
+FIELDS = ("rho", "rt", "ru", "rv", "rw", "rq")
+
+ERF_OK, ERF_E_ARG, ERF_E_SHAPE, ERF_E_HIP, ERF_E_NONFINITE, ERF_E_UNSUPPORTED, ERF_E_NOMEM, ERF_E_STATE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+ERF_FP64, ERF_FP32_MIXED = 0, 1
+
+# every symbol include/erf.h declares
+EXPORTS = ("erf_base_state_host", "erf_create", "erf_destroy", "erf_last_error", "erf_workspace_bytes",
+           "erf_init_base_state", "erf_slow_rhs", "erf_acoustic_substeps", "erf_scalar_advance",
+           "erf_rk3_step", "erf_diagnostics", "erf_timing_begin", "erf_timing_end")
+
+
+class ErfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (erf_status {status})")
+        self.status = status
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("dx", C.c_double),
+                ("dy", C.c_double), ("dz", C.POINTER(C.c_double))]
+
+
+class Params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("n_substeps", C.c_int32), ("beta_s", C.c_double),
+                ("beta_d", C.c_double), ("adv_order_h", C.c_int32), ("adv_order_v", C.c_int32),
+                ("scalar_scheme", C.c_int32), ("n_scalars", C.c_int32), ("sgs", C.c_int32),
+                ("Cs", C.c_double), ("Pr_t", C.c_double), ("nu_m", C.c_double), ("alpha_m", C.c_double),
+                ("f_cor", C.c_double), ("Ug", C.c_double), ("Vg", C.c_double),
+                ("surf_heat_flux", C.c_double), ("grav", C.c_double), ("precision", C.c_int32)]
+
+
+class State(C.Structure):
+    _fields_ = [("rho", C.c_void_p), ("rhotheta", C.c_void_p), ("rhou", C.c_void_p),
+                ("rhov", C.c_void_p), ("rhow", C.c_void_p), ("rhoq", C.c_void_p)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("mass", C.c_double), ("theta_mass", C.c_double), ("energy", C.c_double),
+                ("max_w", C.c_double), ("nonfinite", C.c_int64), ("scalar_mass", C.c_double * 8)]
+
+
+_lib = None
+_lock = threading.Lock()
+_DP = C.POINTER(C.c_double)
+
+
+def load(path: str = LIB_PATH):
+    """Load liberf.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(path):
+                raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+            L = C.CDLL(path)
+            L.erf_base_state_host.argtypes = [C.c_int32, _DP, _DP, C.c_double, C.c_double, _DP, _DP, _DP]
+            L.erf_create.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_void_p, C.POINTER(C.c_void_p)]
+            L.erf_destroy.argtypes = [C.c_void_p]
+            L.erf_destroy.restype = None
+            L.erf_last_error.argtypes = [C.c_void_p]
+            L.erf_last_error.restype = C.c_char_p
+            L.erf_workspace_bytes.argtypes = [C.c_void_p]
+            L.erf_workspace_bytes.restype = C.c_int64
+            L.erf_init_base_state.argtypes = [C.c_void_p, _DP, C.c_double, _DP, _DP, _DP]
+            L.erf_slow_rhs.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(State)]
+            L.erf_acoustic_substeps.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(State), C.POINTER(State),
+                                                C.c_int32, C.c_double, C.POINTER(State), C.POINTER(State)]
+            L.erf_scalar_advance.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(State), C.POINTER(State),
+                                             C.c_double, C.c_void_p]
+            L.erf_rk3_step.argtypes = [C.c_void_p, C.POINTER(State)]
+            L.erf_diagnostics.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(Diag)]
+            L.erf_timing_begin.argtypes = [C.c_void_p, C.c_char_p, C.c_int32]
+            L.erf_timing_end.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+            for name in EXPORTS:
+                fn = getattr(L, name)
+                if name not in ("erf_destroy", "erf_last_error", "erf_workspace_bytes"):
+                    fn.restype = C.c_int32
+            _lib = L
+    return _lib
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+def base_state_host(dz, theta0, p_surface: float, grav: float = 9.81):
+    """Hydrostatic base state computed by the library's host code (no GPU)."""
+    L = load()
+    dz = np.ascontiguousarray(dz, dtype=np.float64)
+    th = np.ascontiguousarray(theta0, dtype=np.float64)
+    nz = len(dz)
+    rho0, p0, pi0 = np.zeros(nz), np.zeros(nz), np.zeros(nz)
+    st = L.erf_base_state_host(nz, _np_ptr(dz), _np_ptr(th), p_surface, grav, _np_ptr(rho0), _np_ptr(p0),
+                               _np_ptr(pi0))
+    if st != ERF_OK:
+        raise ErfError(st, "erf_base_state_host")
+    return rho0, p0, pi0
+
+
+def params_from_config(cfg) -> Params:
+    prec = {"fp64": ERF_FP64, "fp32": ERF_FP32_MIXED}[cfg.prec]
+    return Params(cfg.dt, cfg.n_substeps, cfg.beta_s, cfg.beta_d, cfg.adv_order_h, cfg.adv_order_v,
+                  cfg.scalar_scheme, cfg.n_scalars, cfg.sgs, cfg.Cs, cfg.Pr_t, cfg.nu_m, cfg.alpha_m,
+                  cfg.f_cor, cfg.Ug, cfg.Vg, cfg.surf_heat_flux, cfg.grav, prec)
+
+
+class Solver:
+    """One liberf context: a grid, a parameter set and a HIP stream."""
+
+    def __init__(self, cfg, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("liberf needs a GPU; none is visible")
+        self.torch = torch
+        self.cfg = cfg
+        self.L = load()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.dtype = torch.float64 if cfg.prec == "fp64" else torch.float32
+        self._dz = np.ascontiguousarray(cfg.dz, dtype=np.float64)
+        self._grid = Grid(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, _np_ptr(self._dz))
+        self._params = params_from_config(cfg)
+        h = C.c_void_p()
+        st = self.L.erf_create(C.byref(self._grid), C.byref(self._params), C.c_void_p(self.stream.cuda_stream),
+                               C.byref(h))
+        if st != ERF_OK:
+            raise ErfError(st, "erf_create")
+        self.h = h
+        self.base = None
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.L.erf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != ERF_OK:
+            msg = self.L.erf_last_error(self.h)
+            raise ErfError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.L.erf_workspace_bytes(self.h))
+
+    # -- base state ----------------------------------------------------------
+    def init_base_state(self, theta0, p_surface=None):
+        nz = self.cfg.nz
+        th = np.ascontiguousarray(theta0, dtype=np.float64)
+        rho0, p0, pi0 = np.zeros(nz), np.zeros(nz), np.zeros(nz)
+        ps = self.cfg.p_surface if p_surface is None else p_surface
+        self._check(self.L.erf_init_base_state(self.h, _np_ptr(th), ps, _np_ptr(rho0), _np_ptr(p0), _np_ptr(pi0)),
+                    "erf_init_base_state")
+        self.base = {"rho0": rho0, "theta0": th, "p0": p0, "pi0": pi0}
+        return self.base
+
+    # -- states ----------------------------------------------------------------
+    def shapes(self):
+        c = self.cfg
+        return {"rho": (c.nz, c.ny, c.nx), "rt": (c.nz, c.ny, c.nx), "ru": (c.nz, c.ny, c.nx),
+                "rv": (c.nz, c.ny, c.nx), "rw": (c.nz + 1, c.ny, c.nx), "rq": (c.n_scalars, c.nz, c.ny, c.nx)}
+
+    def empty_state(self):
+        t = self.torch
+        return {f: t.zeros(s, dtype=self.dtype, device=self.device) for f, s in self.shapes().items()}
+
+    def to_device(self, S_np):
+        t = self.torch
+        return {f: t.from_numpy(np.ascontiguousarray(S_np[f])).to(self.device, self.dtype) for f in FIELDS}
+
+    @staticmethod
+    def to_numpy(S):
+        return {f: S[f].detach().cpu().double().numpy() for f in FIELDS}
+
+    def _st(self, S, fields=FIELDS):
+        vals = {}
+        for f, name in zip(FIELDS, ("rho", "rhotheta", "rhou", "rhov", "rhow", "rhoq")):
+            t = S.get(f) if S is not None else None
+            if t is None or f not in fields or t.numel() == 0:
+                vals[name] = None
+                continue
+            if not (t.is_cuda and t.is_contiguous() and t.dtype == self.dtype):
+                raise TypeError(f"field {f} must be a contiguous {self.dtype} CUDA tensor")
+            if tuple(t.shape) != self.shapes()[f]:
+                raise ValueError(f"field {f} has shape {tuple(t.shape)}, expected {self.shapes()[f]}")
+            vals[name] = t.data_ptr()
+        return State(**vals)
+
+    # -- the calls -------------------------------------------------------------
+    def slow_rhs(self, S, R=None):
+        R = self.empty_state() if R is None else R
+        self._check(self.L.erf_slow_rhs(self.h, C.byref(self._st(S)), C.byref(self._st(R))), "erf_slow_rhs")
+        return R
+
+    def acoustic_substeps(self, Sn, St, Rt, n_sub: int, dtau: float, out=None, flux=None):
+        out = self.empty_state() if out is None else out
+        flux = self.empty_state() if flux is None else flux
+        self._check(self.L.erf_acoustic_substeps(self.h, C.byref(self._st(Sn)), C.byref(self._st(St)),
+                                                 C.byref(self._st(Rt)), int(n_sub), float(dtau),
+                                                 C.byref(self._st(out)), C.byref(self._st(flux))),
+                    "erf_acoustic_substeps")
+        return out, flux
+
+    def scalar_advance(self, Sn, St, flux, dts: float, out=None):
+        t = self.torch
+        out = t.zeros_like(Sn["rq"]) if out is None else out
+        self._check(self.L.erf_scalar_advance(self.h, C.byref(self._st(Sn)), C.byref(self._st(St)),
+                                              C.byref(self._st(flux)), float(dts), C.c_void_p(out.data_ptr())),
+                    "erf_scalar_advance")
+        return out
+
+    def rk3_step(self, S):
+        self._check(self.L.erf_rk3_step(self.h, C.byref(self._st(S))), "erf_rk3_step")
+        return S
+
+    def timing_begin(self, kernel: str, max_launches: int = 4096):
+        self._check(self.L.erf_timing_begin(self.h, kernel.encode(), int(max_launches)), "erf_timing_begin")
+
+    def timing_end(self):
+        ms, n = C.c_double(), C.c_int64()
+        self._check(self.L.erf_timing_end(self.h, C.byref(ms), C.byref(n)), "erf_timing_end")
+        return ms.value, n.value
+
+    def diagnostics(self, S, allow_nonfinite: bool = False):
+        d = Diag()
+        st = self.L.erf_diagnostics(self.h, C.byref(self._st(S)), C.byref(d))
+        if st != ERF_OK and not (allow_nonfinite and st == ERF_E_NONFINITE):
+            self._check(st, "erf_diagnostics")
+        return {"mass": d.mass, "theta_mass": d.theta_mass, "energy": d.energy, "max_w": d.max_w,
+                "nonfinite": int(d.nonfinite), "scalar_mass": np.array(d.scalar_mass[:self.cfg.n_scalars])}

@@ -11,3 +11,11 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (run with -m gpu)")
     config.addinivalue_line("markers", "slow: long CPU test")
+
+
+# import torch at collection, outside any per-test time limit (the first import
+# on a fresh machine can take a minute)
+try:
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover
+    torch = None

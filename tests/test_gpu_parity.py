@@ -1,0 +1,211 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Every case builds the same seeded input on both sides (each side computes its
+own base state; they are bitwise equal, see test_abi.py) and compares element
+by element.  Error measure for a field f (perturbations about the base state
+for rho and rho*theta):  max|f_gpu - f_oracle| / max|f_oracle|.
+
+Tolerances, derived from FP64 arithmetic (unit roundoff 1.1e-16): one call of
+the slow right-hand side or of a stage of substeps differs only by rounding of
+the transcendental functions (pow, expm1, log1p, cbrt: ~1 ulp on either side)
+and of a few re-associated sums, amplified by the cancellation in flux
+differences (|flux| / |flux difference| <~ 1e2): 1e-13.  After 100 RK3 steps of
+the 2-D bubble the rounding differences accumulate: 1e-12 (the bound stated for
+this path), measured on the full fields and on the perturbations.
+
+Floor for the perturbation fields: rho and rho*theta are stored as full values
+(rho*theta ~ 350), so a perturbation is only resolved to ulp(max|full|).  When
+the perturbation is small (the bubble keeps |Theta - Theta0| <~ 0.05) one ulp of
+the stored value is already ~1e-12 of max|perturbation|; the bound for those two
+fields is therefore max(tol, 4 ulp(max|full|) / max|perturbation|).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_04395_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CALL_TOL = 1e-13
+STEP100_TOL = 1e-12
+
+
+def _erf():
+    from paper_2412_04395_amd import erf
+    return erf
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _sides(cfg):
+    erf = _erf()
+    o = oracle.Oracle(cfg)
+    th0 = W.theta_sounding(cfg)
+    bo = o.init_base_state(th0, cfg.p_surface)
+    s = erf.Solver(cfg)
+    bs = s.init_base_state(th0)
+    for k in ("rho0", "p0", "pi0"):
+        assert np.array_equal(bo[k], bs[k]), k
+    return o, s, th0, bo
+
+
+def _rough_state(cfg, base, th0, seed):
+    """Initial state plus seeded momentum and density perturbations, so that
+    every term of the equations is active."""
+    S = W.initial_state(cfg, base["rho0"], th0, base["p0"], base["pi0"])
+    shp = S["rho"].shape
+    S["ru"] = S["ru"] + S["rho"] * W.uniform_noise(seed + 11, shp, 2.0)
+    S["rv"] = S["rv"] + S["rho"] * W.uniform_noise(seed + 12, shp, 2.0) * (cfg.ny > 1)
+    rw = W.uniform_noise(seed + 13, S["rw"].shape, 1.0)
+    rw[0] = 0.0
+    rw[-1] = 0.0
+    S["rw"] = np.ascontiguousarray(rw)
+    S["rho"] = S["rho"] * (1.0 + W.uniform_noise(seed + 14, shp, 1e-3))
+    for f in S:
+        S[f] = np.ascontiguousarray(S[f])
+    return S
+
+
+def _rel(a, b, base=None):
+    d = np.max(np.abs(a - b)) if a.size else 0.0
+    m = np.max(np.abs(b)) if b.size else 0.0
+    return d / m if m > 0 else d
+
+
+def _pert(S, base):
+    out = dict(S)
+    out["rho"] = S["rho"] - base["rho0"][:, None, None]
+    out["rt"] = S["rt"] - (base["rho0"] * base["theta0"])[:, None, None]
+    return out
+
+
+def _compare(tag, got, ref, tol, fields=("rho", "rt", "ru", "rv", "rw"), full=None):
+    """full: the reference state before subtracting the base state, for the
+    representation floor of the rho and rho*theta perturbations"""
+    errs = {f: _rel(got[f], ref[f]) for f in fields}
+    bounds = {}
+    for f in fields:
+        bounds[f] = tol
+        if full is not None and f in ("rho", "rt") and np.max(np.abs(ref[f])) > 0:
+            floor = 4.0 * np.spacing(np.max(np.abs(full[f]))) / np.max(np.abs(ref[f]))
+            bounds[f] = max(tol, floor)
+    _say(tag, {f: f"{e:.2e}/{bounds[f]:.1e}" for f, e in errs.items()})
+    for f, e in errs.items():
+        assert e <= bounds[f], (tag, f, e, bounds[f])
+    return errs
+
+
+CASES = {
+    "small_o53": dict(),
+    "small_o22": dict(adv_order_h=2, adv_order_v=2),
+    "small_o33": dict(adv_order_h=3, adv_order_v=3),
+    "small_o46": dict(adv_order_h=4, adv_order_v=6),
+    "small_o64": dict(adv_order_h=6, adv_order_v=4),
+    "smag_cor_flux": dict(name="cbl_small", nx=33, ny=18, nz=14, dx=20.0, dy=20.0, dz=W.uniform_dz(14, 10.0),
+                          dt=0.1, adv_order_h=5, adv_order_v=5, sgs=1, Cs=0.1, f_cor=1e-4, Ug=10.0, Vg=1.0,
+                          surf_heat_flux=0.2),
+    "const_visc": dict(nu_m=75.0, alpha_m=75.0, adv_order_h=3, adv_order_v=3),
+    "stretched": dict(nz=12, dz=np.array([40.0, 45.0, 52.0, 60.0, 70.0, 85.0, 100.0, 120.0, 150.0, 180.0, 200.0,
+                                          220.0]), adv_order_h=3, adv_order_v=5, sgs=1, Cs=0.15),
+    "two_d": dict(name="bubble2d", nx=70, ny=1, nz=24, dz=W.uniform_dz(24, 125.0), dx=125.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_slow_rhs_parity(case):
+    cfg = W.small(**CASES[case])
+    _say("slow_rhs", case, cfg.nx, cfg.ny, cfg.nz)
+    o, s, th0, b = _sides(cfg)
+    S = _rough_state(cfg, b, th0, seed=100)
+    R_ref = o.slow_rhs(S)
+    R = s.to_numpy(s.slow_rhs(s.to_device(S)))
+    _compare(f"slow_rhs[{case}]", R, R_ref, CALL_TOL)
+
+
+@pytest.mark.parametrize("case,nsub", [("small_o53", 1), ("small_o53", 3), ("stretched", 4), ("two_d", 3),
+                                       ("smag_cor_flux", 2)])
+def test_acoustic_substeps_parity(case, nsub):
+    cfg = W.small(**CASES[case])
+    _say("acoustic", case, nsub)
+    o, s, th0, b = _sides(cfg)
+    St = _rough_state(cfg, b, th0, seed=200)
+    Sn = _rough_state(cfg, b, th0, seed=300)
+    Rt = o.slow_rhs(St)
+    dtau = cfg.dt / cfg.n_substeps if nsub > 1 else cfg.dt / 3.0
+    out_ref, F_ref = o.acoustic_substeps(Sn, St, Rt, nsub, dtau)
+    out, F = s.acoustic_substeps(s.to_device(Sn), s.to_device(St), s.to_device(Rt), nsub, dtau)
+    out = s.to_numpy(out)
+    F = s.to_numpy(F)
+    _compare(f"acoustic[{case},{nsub}]", _pert(out, b), _pert(out_ref, b), CALL_TOL, full=out_ref)
+    for name, a, r in zip(("Fu", "Fv", "Fw"), (F["ru"], F["rv"], F["rw"]), F_ref):
+        e = _rel(a, r)
+        _say(name, f"{e:.2e}")
+        assert e <= CALL_TOL, (name, e)
+
+
+@pytest.mark.parametrize("scheme,order", [(1, 3), (0, 5), (0, 2), (0, 6)])
+def test_scalar_advance_parity(scheme, order):
+    cfg = W.small(n_scalars=3, scalar_scheme=scheme, adv_order_h=order, adv_order_v=order)
+    _say("scalars", scheme, order)
+    o, s, th0, b = _sides(cfg)
+    St = _rough_state(cfg, b, th0, seed=400)
+    Sn = _rough_state(cfg, b, th0, seed=500)
+    F = tuple(np.ascontiguousarray(_rough_state(cfg, b, th0, seed=600)[f]) for f in ("ru", "rv", "rw"))
+    ref = o.scalar_advance(Sn, St, F, 0.5)
+    Fd = s.to_device({"rho": St["rho"], "rt": St["rt"], "ru": F[0], "rv": F[1], "rw": F[2], "rq": St["rq"]})
+    got = s.scalar_advance(s.to_device(Sn), s.to_device(St), Fd, 0.5).cpu().numpy()
+    e = _rel(got - Sn["rq"], ref - Sn["rq"])
+    _say("scalar increment rel err", f"{e:.2e}")
+    assert e <= CALL_TOL
+
+
+def test_rk3_bubble_100_steps():
+    cfg = W.bubble2d()
+    _say("rk3 bubble2d 100 steps")
+    o, s, th0, b = _sides(cfg)
+    S = W.initial_state(cfg, b["rho0"], th0)
+    Sg = s.to_device(S)
+    for _ in range(cfg.steps):
+        o.rk3_step(S)
+        s.rk3_step(Sg)
+    got = s.to_numpy(Sg)
+    _compare("rk3 bubble2d x100 (full fields)", got, S, STEP100_TOL)
+    _compare("rk3 bubble2d x100", _pert(got, b), _pert(S, b), STEP100_TOL, full=S)
+    dg, do = s.diagnostics(Sg), o.diagnostics(S)
+    assert abs(dg["mass"] / do["mass"] - 1) < 1e-14
+    assert abs(dg["energy"] / do["energy"] - 1) < 1e-13
+    assert abs(dg["max_w"] / do["max_w"] - 1) < 1e-11
+
+
+@pytest.mark.parametrize("case", ["smag_cor_flux", "stretched"])
+def test_rk3_3d_parity(case):
+    cfg = W.small(**CASES[case])
+    _say("rk3", case)
+    o, s, th0, b = _sides(cfg)
+    S = W.initial_state(cfg, b["rho0"], th0)
+    Sg = s.to_device(S)
+    for _ in range(5):
+        o.rk3_step(S)
+        s.rk3_step(Sg)
+    _compare(f"rk3[{case}] x5", _pert(s.to_numpy(Sg), b), _pert(S, b), 1e-12, full=S)
+
+
+def test_rk3_scalars_weno_parity():
+    cfg = W.small(n_scalars=3, scalar_scheme=1, adv_order_h=3, adv_order_v=3)
+    _say("rk3 scalars weno")
+    o, s, th0, b = _sides(cfg)
+    S = W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"])
+    S["ru"] += 5.0 * S["rho"]
+    Sg = s.to_device(S)
+    for _ in range(4):
+        o.rk3_step(S)
+        s.rk3_step(Sg)
+    got = s.to_numpy(Sg)
+    _compare("rk3 weno x4", _pert(got, b), _pert(S, b), 1e-12, fields=("rho", "rt", "ru", "rv", "rw", "rq"), full=S)
