@@ -47,11 +47,10 @@ KERNEL_VALUES = {
     "prep": lambda sgs: 5 + 5,
     # rho, u, v, w read; mu_t written
     "mut": lambda sgs: 4 + 1,
-    # Theta''(2 levels), Exner, U'', V'', R_U, R_V, sum U, sum V read; U'', V'', sums written
-    "horiz": lambda sgs: 9 + 4,
-    # U'', V'', Theta'', rho'', W'', R_Theta, R_rho, R_W, theta^t, 5 coefficient
-    # fields, sum W read; Theta''_new, rho'', W'', sum W written
-    "column": lambda sgs: 15 + 4,
+    # one fused substep: Theta'' (two levels), U'', V'', rho'', W'' and the five
+    # tendencies read, theta^t and Exner (frozen) and four tridiagonal
+    # coefficient fields read; Theta''_new, U'', V'', rho'', W'' written
+    "substep": lambda sgs: 7 + 5 + 2 + 4 + 5,
     "stage_init": lambda sgs: 12 + 11,
     "coef": lambda sgs: 4 + 5,
     "finalize": lambda sgs: 14 + 8,

@@ -59,7 +59,7 @@ typedef enum { ERF_SGS_NONE = 0, ERF_SGS_SMAGORINSKY = 1 } erf_sgs_model;
 typedef enum { ERF_SCALAR_INTERP = 0, ERF_SCALAR_WENO5 = 1 } erf_scalar_scheme;
 
 typedef struct {
-    int32_t nx, ny, nz;  /* cells; nx, ny >= 1, nz >= 2                          */
+    int32_t nx, ny, nz;  /* cells; nx, ny >= 1, 2 <= nz <= 256                   */
     double dx, dy;       /* horizontal spacing [m]                              */
     const double *dz;    /* host array of nz cell thicknesses [m], copied       */
 } erf_grid;
@@ -168,7 +168,7 @@ erf_status erf_diagnostics(erf_ctx *ctx, const erf_state *S, erf_diag *out);
 /* Kernel timing for measurement.  While enabled, every launch of the named
  * kernel is bracketed by two HIP events recorded on the context's stream; up to
  * max_launches launches are timed, later ones run untimed.  Kernel names:
- * "prep", "mut", "rhs", "stage_init", "coef", "horiz", "column", "finalize",
+ * "prep", "mut", "rhs", "stage_init", "coef", "substep", "finalize",
  * "mixing_ratio", "scalar".  erf_timing_begin allocates the events
  * (ERF_E_NOMEM on failure) and returns ERF_E_ARG for an unknown name. */
 erf_status erf_timing_begin(erf_ctx *ctx, const char *kernel, int32_t max_launches);

@@ -4,23 +4,43 @@
 // Kernels of one stage:
 //   k_stage_init  S'' = S^n - S^t, frozen theta^t and Exner pi^t, zero sums
 //   k_coef        per column: the tridiagonal rows of the implicit W'' equation
-//                 (they depend only on S^t and dtau) and their Thomas factors
-//   per substep:
-//     k_horiz     U'', V'' forward step with the forward-predicted Theta''
-//                 (divergence damping), running sums of U'', V''
-//     k_column    per column: explicit parts of Theta'', rho''; forward
-//                 elimination with the frozen factors; back substitution for
-//                 W''; then Theta'', rho'' from the new W''
+//                 (they depend only on S^t and dtau) factorised once per stage
+//   k_substep     one launch per substep, everything of the substep fused:
+//                 U'', V'' forward step with the forward-predicted Theta''
+//                 (divergence damping); explicit parts of Theta'', rho'';
+//                 right-hand sides of the W'' rows; Thomas solve; update.
 //   k_finalize    S_out = S^t + S'', stage-averaged momenta
 //
-// Column kernels map one thread to one (i, j) column with i fastest, so every
-// level of the vertical sweep is a coalesced row access across the wavefront.
+// k_substep layout.  A block owns a tile of 64 columns (TX x TY, TX*TY = 64,
+// one lane per column) and all nz levels.  Its KG wavefronts split the levels
+// into chunks of L consecutive levels; the explicit work is parallel over
+// levels and keeps the per-level results (That, Rhat, theta^t on faces) in
+// registers.  The W'' right-hand sides go to LDS; the two Thomas sweeps (LU
+// factors frozen per stage) run as chunked linear recurrences, each wavefront
+// on its own rows with one short carry chain between chunks; every wavefront
+// then finishes its levels.  Neighbour columns'
+// U'', V'' on the tile's far faces are recomputed by the lane that needs them
+// (U'', V'' are double-buffered so no lane reads a value another block has
+// already overwritten).  Blocks are remapped so that the tiles one XCD
+// processes form a contiguous band of the domain and tile halos hit its L2.
 #include "erf_internal.h"
 
 namespace erfk {
 namespace {
 
+constexpr int kLanes = 64;  // columns per tile (one wavefront)
+
 __device__ __forceinline__ int cidx(const Dims &d, int i, int j, int k) { return (k * d.ny + j) * d.nx + i; }
+
+// Tiles handled by one XCD form a contiguous range of the tile order (the
+// hardware hands consecutive workgroups to the 8 XCDs in turn).
+__device__ __forceinline__ int xcd_tile(int b, int nblocks)
+{
+    const int nx = 8;
+    int x = b % nx, m = b / nx;
+    int q = nblocks / nx, r = nblocks % nx;
+    return x * q + (x < r ? x : r) + m;
+}
 
 struct StageArgs {
     Dims d;
@@ -34,10 +54,13 @@ struct StageArgs {
     const double *R_r, *R_t, *R_u, *R_v, *R_w;
     // frozen fields
     double *tht, *pit;
-    // perturbations and sums
-    double *T2cur, *T2prv, *T2nxt, *r2, *u2, *v2, *w2, *su, *sv, *sw;
-    // coefficients on z-faces
-    double *ca, *cden, *cc, *cA, *cC;
+    // perturbations (Theta'' three levels, U'' and V'' double-buffered) and sums
+    double *T2cur, *T2prv, *T2nxt, *r2, *u2in, *u2out, *v2in, *v2out, *w2, *su, *sv, *sw;
+    int sums;
+    // coefficients on z-faces: alpha_k = a_k / den_k, m_k = 1 / den_k, c'_k, C_k
+    double *calpha, *cm, *cc, *cC;
+    // tiles
+    int TX, TY, ntx, nty;
 };
 
 __global__ __launch_bounds__(256) void k_stage_init(StageArgs a)
@@ -49,17 +72,19 @@ __global__ __launch_bounds__(256) void k_stage_init(StageArgs a)
     if (i >= d.nx || j >= d.ny) return;
     int c = cidx(d, i, j, k);
     a.w2[c] = a.n_w[c] - a.t_w[c];
-    a.sw[c] = 0.0;
+    if (a.sums) a.sw[c] = 0.0;
     if (k == d.nz) return;
     double Tt = a.t_t[c];
     a.tht[c] = Tt / a.t_r[c];
     a.pit[c] = pow(kRd * Tt / kP00, kGamma - 1.0);
     a.T2cur[c] = a.n_t[c] - Tt;
     a.r2[c] = a.n_r[c] - a.t_r[c];
-    a.u2[c] = a.n_u[c] - a.t_u[c];
-    a.v2[c] = a.n_v[c] - a.t_v[c];
-    a.su[c] = 0.0;
-    a.sv[c] = 0.0;
+    a.u2in[c] = a.n_u[c] - a.t_u[c];
+    a.v2in[c] = a.n_v[c] - a.t_v[c];
+    if (a.sums) {
+        a.su[c] = 0.0;
+        a.sv[c] = 0.0;
+    }
 }
 
 // theta^t on z-face k of a column (lid faces carry W = 0; value unused)
@@ -69,11 +94,11 @@ __device__ __forceinline__ double thz(const StageArgs &a, int col, int k)
     return 0.5 * (a.tht[col + (k - 1) * a.d.nxy] + a.tht[col + k * a.d.nxy]);
 }
 
-// Tridiagonal rows for W'' at interior faces k = 1..nz-1.  With
+// Tridiagonal rows for W'' at interior faces k = 1..nz-1.  Substituting
 // Theta''_new = That - dtau b2 delta_z(W theta_f)/dz and rho''_new = Rhat -
-// dtau b2 delta_z(W)/dz substituted into the W'' equation of App. C, face k
-// couples W_{k-1}, W_k, W_{k+1} with coefficients that only involve the frozen
-// state.  Stores a_k, the Thomas pivot den_k and c'_k.
+// dtau b2 delta_z(W)/dz into the W'' equation of App. C couples W_{k-1}, W_k,
+// W_{k+1} with coefficients of the frozen state only.  Factorised here (Thomas,
+// no pivoting; the rows are diagonally dominant).
 __global__ __launch_bounds__(256) void k_coef(StageArgs a)
 {
     const Dims &d = a.d;
@@ -96,103 +121,228 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs a)
         double up = (k == nz - 1) ? 0.0 : -D * (A * tfp * idz / dzf - 0.5 * C * tfp * idz + 0.5 * g * idz);
         double di = 1.0 + D * (A * tf * (idz + idzm) / dzf + 0.5 * C * tf * (idzm - idz) - 0.5 * g * (idzm - idz));
         double den = (k == 1) ? di : di - lo * cprev;
-        double cp = up / den;
-        a.ca[c] = lo;
-        a.cden[c] = den;
+        double m = 1.0 / den;
+        double cp = up * m;
+        a.calpha[c] = lo * m;
+        a.cm[c] = m;
         a.cc[c] = cp;
-        a.cA[c] = A;
         a.cC[c] = C;
         cprev = cp;
     }
 }
 
-// U'', V'' forward step.  bd = 0 on the first substep of a stage.
-__global__ __launch_bounds__(256) void k_horiz(StageArgs a)
+// One fused acoustic substep.  blockDim = (64, KG), kLevels levels per
+// wavefront; dynamic LDS holds the (nz + 1) x 64 solve buffer and the
+// chunk-boundary values.
+template <int kLevels>
+__global__ __launch_bounds__(1024) void k_substep(StageArgs a)
 {
+    extern __shared__ double lds[];
     const Dims &d = a.d;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y * blockDim.y + threadIdx.y;
-    int k = blockIdx.z;
-    if (i >= d.nx || j >= d.ny) return;
-    int c = cidx(d, i, j, k);
-    int cw = cidx(d, wrap_idx(i - 1, d.nx), j, k), cs = cidx(d, i, wrap_idx(j - 1, d.ny), k);
-    const double bd = a.bd;
-    double Tc = a.T2cur[c], Tw = a.T2cur[cw], Ts = a.T2cur[cs];
-    double ttc = Tc + bd * (Tc - a.T2prv[c]);
-    double ttw = Tw + bd * (Tw - a.T2prv[cw]);
-    double tts = Ts + bd * (Ts - a.T2prv[cs]);
-    double pfx = 0.5 * (a.pit[cw] + a.pit[c]);
-    double pfy = 0.5 * (a.pit[cs] + a.pit[c]);
-    double un = a.u2[c] + a.dtau * (-kGamma * kRd * pfx * (ttc - ttw) / a.dx + a.R_u[c]);
-    double vn = a.v2[c] + a.dtau * (-kGamma * kRd * pfy * (ttc - tts) / a.dy + a.R_v[c]);
-    a.u2[c] = un;
-    a.v2[c] = vn;
-    a.su[c] += un;
-    a.sv[c] += vn;
-}
+    const int nz = d.nz, nxy = d.nxy;
+    const int lane = threadIdx.x, g = threadIdx.y;
+    double *rbuf = lds;                     // [(nz + 1) * 64]
+    double *bnd = lds + (nz + 1) * kLanes;  // [KG][2][64]
 
-// Explicit parts of Theta'' and rho'', the implicit W'' solve, and the update.
-// In the forward sweep That and Rhat are stored in T2nxt and r2 (in place) and
-// the eliminated right-hand side d'_k in w2 (in place, after W''_k is read).
-__global__ __launch_bounds__(256) void k_column(StageArgs a)
-{
-    const Dims &d = a.d;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= d.nx || j >= d.ny) return;
-    const int nxy = d.nxy, nz = d.nz, col = j * d.nx + i;
-    const int ip = wrap_idx(i + 1, d.nx), im = wrap_idx(i - 1, d.nx);
-    const int jp = wrap_idx(j + 1, d.ny), jm = wrap_idx(j - 1, d.ny);
-    const int o_e = ip - i, o_w = im - i, o_n = (jp - j) * d.nx, o_s = (jm - j) * d.nx;
-    const double dt = a.dtau, b1 = a.b1, b2 = a.b2, g = a.g;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % a.ntx, ty = tile / a.ntx;
+    const int i = tx * a.TX + lane % a.TX, j = ty * a.TY + lane / a.TX;
+    const bool act = (i < d.nx) && (j < d.ny);
+    const int ic = act ? i : 0, jc = act ? j : 0;
+    const int col = jc * d.nx + ic;
+    const int o_e = wrap_idx(ic + 1, d.nx) - ic, o_w = wrap_idx(ic - 1, d.nx) - ic;
+    const int o_n = (wrap_idx(jc + 1, d.ny) - jc) * d.nx, o_s = (wrap_idx(jc - 1, d.ny) - jc) * d.nx;
+    const double dt = a.dtau, b1 = a.b1, b2 = a.b2, gr = a.g, bd = a.bd;
+    const double gRd = kGamma * kRd;
 
-    double th_prev = 0.0, rh_prev = 0.0, t2_prev = 0.0, r2_prev = 0.0, dprev = 0.0;
-    double w_lo = a.w2[col];  // W''_k (old), carried upward
-    for (int k = 0; k < nz; ++k) {
-        const int c = col + k * nxy;
-        const double tc = a.tht[c];
-        const double thx0 = 0.5 * (a.tht[c + o_w] + tc), thx1 = 0.5 * (tc + a.tht[c + o_e]);
-        const double thy0 = 0.5 * (a.tht[c + o_s] + tc), thy1 = 0.5 * (tc + a.tht[c + o_n]);
-        const double Ue = a.u2[c + o_e], Uw = a.u2[c], Vn = a.v2[c + o_n], Vs = a.v2[c];
-        const double w_hi = a.w2[c + nxy];
-        const double hdiv_t = (Ue * thx1 - Uw * thx0) / a.dx + (Vn * thy1 - Vs * thy0) / a.dy;
-        const double hdiv_r = (Ue - Uw) / a.dx + (Vn - Vs) / a.dy;
-        const double t2 = a.T2cur[c], r2 = a.r2[c];
-        const double tfk = thz(a, col, k), tfk1 = thz(a, col, k + 1);
-        const double th_hat = t2 + dt * (-hdiv_t - b1 * (w_hi * tfk1 - w_lo * tfk) / a.dz[k] + a.R_t[c]);
-        const double rh_hat = r2 + dt * (-hdiv_r - b1 * (w_hi - w_lo) / a.dz[k] + a.R_r[c]);
-        if (k >= 1) {
-            const double dzf = 0.5 * (a.dz[k - 1] + a.dz[k]);
-            const double A = a.cA[c], C = a.cC[c];
-            const double tbk = b1 * t2 + b2 * th_hat, tbm = b1 * t2_prev + b2 * th_prev;
-            const double rbk = b1 * r2 + b2 * rh_hat, rbm = b1 * r2_prev + b2 * rh_prev;
-            const double rk = w_lo + dt * (-A * (tbk - tbm) / dzf + 0.5 * C * (tbk + tbm) - 0.5 * g * (rbk + rbm) + a.R_w[c]);
-            const double dk = (k == 1) ? rk / a.cden[c] : (rk - a.ca[c] * dprev) / a.cden[c];
-            a.w2[c] = dk;
-            dprev = dk;
+    const int k0 = g * kLevels;
+    double th[kLevels], rh[kLevels], tf[kLevels];
+    double tf_top = 0.0;
+    double e_first = 0.0, f_first = 0.0;
+
+    // ---------------- phase 1: explicit work, W'' right-hand sides ----------
+    if (act && k0 < nz) {
+        double e_prev = 0.0, f_prev = 0.0;
+        double pi_below = (k0 > 0) ? a.pit[col + (k0 - 1) * nxy] : 0.0;
+        double th_below = (k0 > 0) ? a.tht[col + (k0 - 1) * nxy] : 0.0;
+        double w_lo = a.w2[col + k0 * nxy];
+#pragma unroll
+        for (int l = 0; l < kLevels; ++l) {
+            const int k = k0 + l;
+            if (k < nz) {
+                const int c = col + k * nxy;
+                // forward-predicted Theta'' at the centre and its four neighbours
+                const double Tc = a.T2cur[c];
+                const double ttc = Tc + bd * (Tc - a.T2prv[c]);
+                const double Tw = a.T2cur[c + o_w], Te = a.T2cur[c + o_e], Ts = a.T2cur[c + o_s], Tn = a.T2cur[c + o_n];
+                const double ttw = Tw + bd * (Tw - a.T2prv[c + o_w]);
+                const double tte = Te + bd * (Te - a.T2prv[c + o_e]);
+                const double tts = Ts + bd * (Ts - a.T2prv[c + o_s]);
+                const double ttn = Tn + bd * (Tn - a.T2prv[c + o_n]);
+                const double pc = a.pit[c], pw = a.pit[c + o_w], pe = a.pit[c + o_e], ps = a.pit[c + o_s],
+                             pn = a.pit[c + o_n];
+                // U'' on this column's x-face and on the next one, V'' likewise
+                const double Uw = a.u2in[c] + dt * (-gRd * (0.5 * (pw + pc)) * (ttc - ttw) / a.dx + a.R_u[c]);
+                const double Ue =
+                    a.u2in[c + o_e] + dt * (-gRd * (0.5 * (pc + pe)) * (tte - ttc) / a.dx + a.R_u[c + o_e]);
+                const double Vs = a.v2in[c] + dt * (-gRd * (0.5 * (ps + pc)) * (ttc - tts) / a.dy + a.R_v[c]);
+                const double Vn =
+                    a.v2in[c + o_n] + dt * (-gRd * (0.5 * (pc + pn)) * (ttn - ttc) / a.dy + a.R_v[c + o_n]);
+                a.u2out[c] = Uw;
+                a.v2out[c] = Vs;
+                if (a.sums) {
+                    a.su[c] += Uw;
+                    a.sv[c] += Vs;
+                }
+                // explicit parts of Theta'' and rho''
+                const double thc = a.tht[c];
+                const double thx0 = 0.5 * (a.tht[c + o_w] + thc), thx1 = 0.5 * (thc + a.tht[c + o_e]);
+                const double thy0 = 0.5 * (a.tht[c + o_s] + thc), thy1 = 0.5 * (thc + a.tht[c + o_n]);
+                const double hdiv_t = (Ue * thx1 - Uw * thx0) / a.dx + (Vn * thy1 - Vs * thy0) / a.dy;
+                const double hdiv_r = (Ue - Uw) / a.dx + (Vn - Vs) / a.dy;
+                const double th_above = (k < nz - 1) ? a.tht[c + nxy] : 0.0;
+                const double tfk = (k == 0) ? 0.0 : 0.5 * (th_below + thc);
+                const double tfk1 = (k == nz - 1) ? 0.0 : 0.5 * (thc + th_above);
+                const double w_hi = a.w2[c + nxy];
+                const double dzk = a.dz[k];
+                const double r2c = a.r2[c];
+                const double that = Tc + dt * (-hdiv_t - b1 * (w_hi * tfk1 - w_lo * tfk) / dzk + a.R_t[c]);
+                const double rhat = r2c + dt * (-hdiv_r - b1 * (w_hi - w_lo) / dzk + a.R_r[c]);
+                const double e = b1 * Tc + b2 * that, f = b1 * r2c + b2 * rhat;
+                if (l == 0) {
+                    e_first = e;
+                    f_first = f;
+                } else {
+                    // right-hand side of the W'' row on face k
+                    const double dzf = 0.5 * (a.dz[k - 1] + dzk);
+                    const double A = gRd * (0.5 * (pi_below + pc));
+                    const double C = a.cC[c];
+                    rbuf[k * kLanes + lane] = w_lo + dt * (-A * (e - e_prev) / dzf + 0.5 * C * (e + e_prev) -
+                                                           0.5 * gr * (f + f_prev) + a.R_w[c]);
+                }
+                th[l] = that;
+                rh[l] = rhat;
+                tf[l] = tfk;
+                tf_top = tfk1;
+                e_prev = e;
+                f_prev = f;
+                pi_below = pc;
+                th_below = thc;
+                w_lo = w_hi;
+                if (l == kLevels - 1 || k == nz - 1) {
+                    bnd[(g * 2 + 0) * kLanes + lane] = e;
+                    bnd[(g * 2 + 1) * kLanes + lane] = f;
+                }
+            }
         }
-        a.T2nxt[c] = th_hat;
-        a.r2[c] = rh_hat;
-        th_prev = th_hat;
-        rh_prev = rh_hat;
-        t2_prev = t2;
-        r2_prev = r2;
-        w_lo = w_hi;
     }
-    // back substitution and the implicit parts of Theta'', rho''
-    double w_up = 0.0;  // W at face k+1 (face nz is the lid)
-    for (int k = nz - 1; k >= 0; --k) {
-        const int c = col + k * nxy;
-        double wk = 0.0;
-        if (k >= 1) {
-            wk = a.w2[c] - a.cc[c] * w_up;
-            a.w2[c] = wk;
-            a.sw[c] += wk;
+    __syncthreads();
+    // row k0 of every chunk but the first needs the last level of the chunk below
+    if (act && k0 < nz && g > 0) {
+        const int k = k0, c = col + k * nxy;
+        const double e_prev = bnd[((g - 1) * 2 + 0) * kLanes + lane];
+        const double f_prev = bnd[((g - 1) * 2 + 1) * kLanes + lane];
+        const double dzf = 0.5 * (a.dz[k - 1] + a.dz[k]);
+        const double A = gRd * (0.5 * (a.pit[c - nxy] + a.pit[c]));
+        const double C = a.cC[c];
+        rbuf[k * kLanes + lane] = a.w2[c] + dt * (-A * (e_first - e_prev) / dzf + 0.5 * C * (e_first + e_prev) -
+                                                  0.5 * gr * (f_first + f_prev) + a.R_w[c]);
+    }
+    __syncthreads();
+
+    // ---------------- phase 2: the Thomas sweeps as chunked recurrences -----
+    // Forward: d_k = r_k m_k - alpha_k d_{k-1}; backward: x_k = d_k - c'_k x_{k+1}.
+    // Both are first-order linear recurrences with frozen coefficients, so each
+    // wavefront runs them over its own rows from a zero carry, keeping the
+    // carry multipliers (products of -alpha, resp. -c'); one wavefront then
+    // chains the chunk ends, and every wavefront adds carry x multiplier.
+    // Rows of chunk g: faces k0..k0+L-1 (face 0, the lid, is not a row).
+    double *carry = bnd;  // reuses the boundary area: [KG][2][64]
+    double mult[kLevels];
+    const int rlo = k0 > 0 ? k0 : 1;
+    const int rhi = (k0 + kLevels < nz ? k0 + kLevels : nz) - 1;  // last row of the chunk
+    if (act && rlo <= rhi) {
+        double dl = 0.0, pm = 1.0;
+#pragma unroll
+        for (int l = 0; l < kLevels; ++l) {
+            const int k = k0 + l;
+            if (k >= rlo && k <= rhi) {
+                const int c = col + k * nxy;
+                const double al = a.calpha[c];
+                dl = rbuf[k * kLanes + lane] * a.cm[c] - al * dl;
+                pm = -al * pm;
+                rbuf[k * kLanes + lane] = dl;
+                mult[l] = pm;
+            }
         }
-        const double tfk = thz(a, col, k), tfk1 = thz(a, col, k + 1);
-        a.T2nxt[c] = a.T2nxt[c] - dt * b2 * (w_up * tfk1 - wk * tfk) / a.dz[k];
-        a.r2[c] = a.r2[c] - dt * b2 * (w_up - wk) / a.dz[k];
-        w_up = wk;
+        carry[(g * 2 + 0) * kLanes + lane] = dl;  // local d at the chunk's last row
+        carry[(g * 2 + 1) * kLanes + lane] = pm;  // its carry multiplier
+    }
+    __syncthreads();
+    const int KG = blockDim.y;
+    if (g == 0 && act) {
+        double D = 0.0;
+        for (int q = 0; q < KG; ++q) {
+            if (q * kLevels >= nz) break;
+            D = carry[(q * 2 + 0) * kLanes + lane] + carry[(q * 2 + 1) * kLanes + lane] * D;
+            carry[(q * 2 + 0) * kLanes + lane] = D;  // true d at the end of chunk q
+        }
+    }
+    __syncthreads();
+    if (act && rlo <= rhi) {
+        const double Dprev = g > 0 ? carry[((g - 1) * 2 + 0) * kLanes + lane] : 0.0;
+        double xl = 0.0, qm = 1.0;
+#pragma unroll
+        for (int l = kLevels - 1; l >= 0; --l) {
+            const int k = k0 + l;
+            if (k >= rlo && k <= rhi) {
+                const int c = col + k * nxy;
+                const double dk = rbuf[k * kLanes + lane] + mult[l] * Dprev;
+                const double cp = a.cc[c];
+                xl = dk - cp * xl;
+                qm = -cp * qm;
+                rbuf[k * kLanes + lane] = xl;
+                mult[l] = qm;
+            }
+        }
+    }
+    __syncthreads();
+    if (act && rlo <= rhi) {
+        carry[(g * 2 + 0) * kLanes + lane] = rbuf[rlo * kLanes + lane];  // local x at the first row
+        carry[(g * 2 + 1) * kLanes + lane] = (g == 0) ? mult[1] : mult[0];  // rlo - k0 is 1 or 0
+    }
+    __syncthreads();
+    if (g == 0 && act) {
+        double X = 0.0;  // x above the last chunk: the lid
+        for (int q = KG - 1; q >= 0; --q) {
+            if (q * kLevels >= nz) continue;
+            X = carry[(q * 2 + 0) * kLanes + lane] + carry[(q * 2 + 1) * kLanes + lane] * X;
+            carry[(q * 2 + 0) * kLanes + lane] = X;  // true x at the first row of chunk q
+        }
+    }
+    __syncthreads();
+
+    // ---------------- phase 3: implicit parts of Theta'', rho''; W'' -------
+    if (act && k0 < nz) {
+        const double Xnext = (k0 + kLevels < nz) ? carry[((g + 1) * 2 + 0) * kLanes + lane] : 0.0;
+        double wk1 = Xnext;  // W on the face above the current level
+#pragma unroll
+        for (int l = kLevels - 1; l >= 0; --l) {
+            const int k = k0 + l;
+            if (k < nz) {
+                const int c = col + k * nxy;
+                const double wk = (k >= rlo && k <= rhi) ? rbuf[k * kLanes + lane] + mult[l] * Xnext : 0.0;
+                const double tf1 = (l == kLevels - 1 || k == nz - 1) ? tf_top : tf[l + 1 < kLevels ? l + 1 : l];
+                const double dzk = a.dz[k];
+                a.T2nxt[c] = th[l] - dt * b2 * (wk1 * tf1 - wk * tf[l]) / dzk;
+                a.r2[c] = rh[l] - dt * b2 * (wk1 - wk) / dzk;
+                if (k >= 1) {
+                    a.w2[c] = wk;
+                    if (a.sums) a.sw[c] += wk;
+                }
+                wk1 = wk;
+            }
+        }
     }
 }
 
@@ -217,8 +367,11 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs a)
     if (i >= d.nx || j >= d.ny) return;
     int c = cidx(d, i, j, k);
     double inv = 1.0 / a.n_sub;
-    double wt = a.t_w[c], w0 = a.n_w[c] - wt, wN = a.w2[c];
-    if (a.Fw) a.Fw[c] = wt + (a.sw[c] + a.b1 * (w0 - wN)) * inv;
+    double wt = a.t_w[c], wN = a.w2[c];
+    if (a.Fw) {
+        double w0 = a.n_w[c] - wt;
+        a.Fw[c] = wt + (a.sw[c] + a.b1 * (w0 - wN)) * inv;
+    }
     a.o_w[c] = wt + wN;
     if (k == d.nz) return;
     a.o_r[c] = a.t_r[c] + a.r2[c];
@@ -254,34 +407,68 @@ hipError_t launch_acoustic_stage(erf_ctx *cx, const double *const Sn[5], const d
     a.R_r = Rt[0]; a.R_t = Rt[1]; a.R_u = Rt[2]; a.R_v = Rt[3]; a.R_w = Rt[4];
     a.tht = w.th;
     a.pit = w.pit;
-    a.r2 = w.r2; a.u2 = w.u2; a.v2 = w.v2; a.w2 = w.w2;
-    a.su = w.su; a.sv = w.sv; a.sw = w.sw;
-    a.ca = w.ca; a.cden = w.cb; a.cc = w.cc; a.cA = w.cA; a.cC = w.cC;
-    int cur = 0;
-    a.T2cur = w.t2[0];
-    a.T2prv = w.t2[0];
-    a.T2nxt = w.t2[1];
+    a.r2 = w.r2;
+    a.w2 = w.w2;
+    a.su = w.su;
+    a.sv = w.sv;
+    a.sw = w.sw;
+    a.sums = (Fu || Fv || Fw) ? 1 : 0;
+    a.calpha = w.ca;
+    a.cm = w.cb;
+    a.cc = w.cc;
+    a.cC = w.cC;
+    // tile shape: 64 columns, four rows when the domain has them
+    a.TY = d.ny >= 4 ? 4 : (d.ny >= 2 ? 2 : 1);
+    a.TX = kLanes / a.TY;
+    a.ntx = (d.nx + a.TX - 1) / a.TX;
+    a.nty = (d.ny + a.TY - 1) / a.TY;
+    // 8 levels per wavefront up to nz = 128 (registers without spills), 16 above
+    const int L = d.nz <= 128 ? 8 : 16;
+    const int KG = (d.nz + L - 1) / L;
+    if (KG > 16) return hipErrorInvalidValue;  // nz <= 256
+    const size_t lds = sizeof(double) * ((size_t)(d.nz + 1) * kLanes + 2 * (size_t)KG * kLanes);
+    const void *kfn = L == 8 ? (const void *)k_substep<8> : (const void *)k_substep<16>;
 
+    int t_cur = 0, t_prv = 2, u_in = 0;  // Theta'' rotates over 3 buffers, U'' and V'' over 2
+    a.T2cur = w.t2[0];
+    a.u2in = w.u2[0];
+    a.v2in = w.v2[0];
+
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     dim3 blk(64, 4, 1);
-    dim3 g3((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz), g3w((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz + 1);
+    dim3 g3w((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz + 1);
     dim3 g2((d.nx + 63) / 64, (d.ny + 3) / 4, 1);
     timing_start(cx, K_STAGE_INIT); hipLaunchKernelGGL(k_stage_init, g3w, blk, 0, cx->stream, a); timing_stop(cx, K_STAGE_INIT);
     timing_start(cx, K_COEF); hipLaunchKernelGGL(k_coef, g2, blk, 0, cx->stream, a); timing_stop(cx, K_COEF);
     for (int s = 0; s < n_sub; ++s) {
-        a.T2cur = w.t2[cur];
-        a.T2prv = (s == 0) ? w.t2[cur] : w.t2[cur ^ 1];
-        a.T2nxt = w.t2[cur ^ 1];
+        const int t_nxt = 3 - t_cur - t_prv;
+        a.T2cur = w.t2[t_cur];
+        a.T2prv = (s == 0) ? w.t2[t_cur] : w.t2[t_prv];
+        a.T2nxt = w.t2[t_nxt];
+        a.u2in = w.u2[u_in];
+        a.u2out = w.u2[u_in ^ 1];
+        a.v2in = w.v2[u_in];
+        a.v2out = w.v2[u_in ^ 1];
         a.bd = (s == 0) ? 0.0 : cx->prm.beta_d;
-        timing_start(cx, K_HORIZ); hipLaunchKernelGGL(k_horiz, g3, blk, 0, cx->stream, a); timing_stop(cx, K_HORIZ);
-        timing_start(cx, K_COLUMN); hipLaunchKernelGGL(k_column, g2, blk, 0, cx->stream, a); timing_stop(cx, K_COLUMN);
-        cur ^= 1;
+        timing_start(cx, K_SUBSTEP);
+        if (L == 8)
+            hipLaunchKernelGGL(k_substep<8>, dim3(a.ntx * a.nty), dim3(kLanes, KG), lds, cx->stream, a);
+        else
+            hipLaunchKernelGGL(k_substep<16>, dim3(a.ntx * a.nty), dim3(kLanes, KG), lds, cx->stream, a);
+        timing_stop(cx, K_SUBSTEP);
+        t_prv = t_cur;
+        t_cur = t_nxt;
+        u_in ^= 1;
     }
     FinArgs f{};
     f.d = d;
     f.n_sub = n_sub;
     f.b1 = a.b1;
     f.t_r = St[0]; f.t_t = St[1]; f.t_u = St[2]; f.t_v = St[3]; f.t_w = St[4]; f.n_w = Sn[4];
-    f.T2 = w.t2[cur]; f.r2 = w.r2; f.u2 = w.u2; f.v2 = w.v2; f.w2 = w.w2;
+    f.T2 = w.t2[t_cur]; f.r2 = w.r2; f.u2 = w.u2[u_in]; f.v2 = w.v2[u_in]; f.w2 = w.w2;
     f.su = w.su; f.sv = w.sv; f.sw = w.sw;
     f.o_r = Sout[0]; f.o_t = Sout[1]; f.o_u = Sout[2]; f.o_v = Sout[3]; f.o_w = Sout[4];
     f.Fu = Fu; f.Fv = Fv; f.Fw = Fw;

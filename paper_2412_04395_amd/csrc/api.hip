@@ -96,6 +96,7 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     const int64_t nw = nxy * (grid->nz + 1);
     const int64_t nq = prm->n_scalars;
     if (nw * (nq > 1 ? nq : 1) >= ((int64_t)1 << 31)) return ERF_E_SHAPE;
+    if (grid->nz > 256) return ERF_E_SHAPE;  // a substep block holds whole columns
     if (!(grid->dx > 0.0) || !(grid->dy > 0.0)) return ERF_E_ARG;
     for (int k = 0; k < grid->nz; ++k)
         if (!(grid->dz[k] > 0.0)) return ERF_E_ARG;
@@ -135,9 +136,10 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
         {&ws.sb[0], n}, {&ws.sb[1], n}, {&ws.sb[2], n}, {&ws.sb[3], n}, {&ws.sb[4], w}, {&ws.sb[5], q},
         {&ws.R[0], n}, {&ws.R[1], n}, {&ws.R[2], n}, {&ws.R[3], n}, {&ws.R[4], w},
         {&ws.th, n}, {&ws.pp, n}, {&ws.pit, n}, {&ws.u, n}, {&ws.v, n}, {&ws.w, w}, {&ws.mut, n},
-        {&ws.t2[0], n}, {&ws.t2[1], n}, {&ws.r2, n}, {&ws.u2, n}, {&ws.v2, n}, {&ws.w2, w},
+        {&ws.t2[0], n}, {&ws.t2[1], n}, {&ws.t2[2], n}, {&ws.r2, n}, {&ws.w2, w},
+        {&ws.u2[0], n}, {&ws.u2[1], n}, {&ws.v2[0], n}, {&ws.v2[1], n},
         {&ws.su, n}, {&ws.sv, n}, {&ws.sw, w},
-        {&ws.ca, w}, {&ws.cb, w}, {&ws.cc, w}, {&ws.cA, w}, {&ws.cC, w},
+        {&ws.ca, w}, {&ws.cb, w}, {&ws.cc, w}, {&ws.cC, w},
         {&ws.q, q}, {&ws.fu, n}, {&ws.fv, n}, {&ws.fw, w},
         {&ws.diag, diag_slots_needed()},
         {&b.rho0, (size_t)grid->nz}, {&b.theta0, (size_t)grid->nz}, {&b.Theta0, (size_t)grid->nz},
@@ -297,7 +299,8 @@ erf_status erf_rk3_step(erf_ctx *c, erf_state *S)
         const double dtau = stage == 0 ? dt / 3.0 : dt / ns;
         erf_status s = erf_slow_rhs(c, St, &R);
         if (s != ERF_OK) return s;
-        s = erf_acoustic_substeps(c, S, St, &R, nsub, dtau, outs[stage], &F);
+        // the stage-averaged momenta are only needed to transport scalars
+        s = erf_acoustic_substeps(c, S, St, &R, nsub, dtau, outs[stage], nq > 0 ? &F : nullptr);
         if (s != ERF_OK) return s;
         if (nq > 0) {
             s = erf_scalar_advance(c, S, St, &F, dts, outs[stage]->rhoq);

@@ -99,14 +99,16 @@ struct Workspace {
     // stage-frozen fields at centres: theta, p', pi, velocities, mu_t
     double *th = nullptr, *pp = nullptr, *pit = nullptr;
     double *u = nullptr, *v = nullptr, *w = nullptr, *mut = nullptr;
-    // substep perturbations: Theta'' (two time levels), rho'', U'', V'', W''
-    double *t2[2] = {};
-    double *r2 = nullptr, *u2 = nullptr, *v2 = nullptr, *w2 = nullptr;
+    // substep perturbations: Theta'' (three time levels), rho'', U'' and V''
+    // (double-buffered), W''
+    double *t2[3] = {};
+    double *u2[2] = {}, *v2[2] = {};
+    double *r2 = nullptr, *w2 = nullptr;
     // running sums of the substep momenta (stage-averaged fluxes at the end)
     double *su = nullptr, *sv = nullptr, *sw = nullptr;
     // per-stage tridiagonal coefficients on z-faces
-    double *ca = nullptr, *cb = nullptr, *cc = nullptr;  // a_k, Thomas pivot den_k, c'_k
-    double *cA = nullptr, *cC = nullptr;                 // acoustic and buoyancy coefficients
+    double *ca = nullptr, *cb = nullptr, *cc = nullptr;  // a_k / den_k, 1 / den_k, c'_k (Thomas)
+    double *cC = nullptr;                                // buoyancy coefficient of the W'' rows
     // mixing ratios q^t of the scalars, stage-averaged momenta of rk3_step
     double *q = nullptr;
     double *fu = nullptr, *fv = nullptr, *fw = nullptr;
@@ -144,10 +146,10 @@ struct erf_ctx {
 namespace erfk {
 
 // kernel ids for the timing instrumentation
-enum KernelId { K_PREP, K_MUT, K_RHS, K_STAGE_INIT, K_COEF, K_HORIZ, K_COLUMN, K_FINALIZE, K_MIXRATIO, K_SCALAR, K_COUNT };
+enum KernelId { K_PREP, K_MUT, K_RHS, K_STAGE_INIT, K_COEF, K_SUBSTEP, K_FINALIZE, K_MIXRATIO, K_SCALAR, K_COUNT };
 inline const char *kernel_name(int id)
 {
-    static const char *names[K_COUNT] = {"prep", "mut", "rhs", "stage_init", "coef", "horiz", "column", "finalize",
+    static const char *names[K_COUNT] = {"prep", "mut", "rhs", "stage_init", "coef", "substep", "finalize",
                                          "mixing_ratio", "scalar"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
