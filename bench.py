@@ -41,8 +41,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 # kernel: every distinct input field read once and every output written once.
 # n_s-independent; 'sgs' adds the eddy-viscosity field where it is read.
 KERNEL_VALUES = {
-    # rho, Theta, U, V, W, theta, p', u, v, w (+ mu_t) read; 5 tendencies written
-    "rhs": lambda sgs: 10 + sgs + 5,
+    # rho, U, V, W, theta, p', u, v, w read (+ 6 stresses and the diffusivity
+    # in viscous runs); 5 tendencies written
+    "rhs": lambda sgs: 9 + 7 * sgs + 5,
+    # u, v, w, rho, mu_t read; 6 stresses and the diffusivity written
+    "stress": lambda sgs: 5 + 7,
     # rho, Theta, U, V, W read; theta, p', u, v, w written
     "prep": lambda sgs: 5 + 5,
     # rho, u, v, w read; mu_t written
@@ -55,6 +58,23 @@ KERNEL_VALUES = {
     "coef": lambda sgs: 4 + 5,
     "finalize": lambda sgs: 14 + 8,
 }
+
+
+def _profiled_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary under profiles/, if the kernel's source is unchanged since."""
+    import glob
+    import hashlib
+    import re
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        text = open(path).read()
+        fields = dict(re.findall(r"^\s+(kernel|source|source_sha256|traffic_bytes_per_launch): (\S+)$", text, re.M))
+        if fields.get("kernel") != kernel or "source" not in fields:
+            continue
+        src = os.path.join(ROOT, fields["source"])
+        if os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == fields.get("source_sha256"):
+            return float(fields["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
 
 
 def _cfg(workload: str) -> W.Config:
@@ -136,6 +156,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="cbl")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-as-stated", action="store_true")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="first run one plain device copy of this many GiB (reference for HBM counters)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU layout is a design "
@@ -144,14 +166,24 @@ def main(argv=None):
     rank = int(os.environ.get("RANK", "0"))
 
     cfg = _cfg(a.workload)
+    if a.copy_gib > 0:
+        import torch
+        n = int(a.copy_gib * (1 << 30)) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     el, dom, kms, kn, shares, diag = run_gpu(cfg, a.steps, a.warmup)
     value = cfg.cells * a.steps / el
     sgs = 1 if cfg.sgs else 0
     avg_ms = kms / max(kn, 1)
     bytes_per_launch = KERNEL_VALUES[dom](sgs) * 8.0 * cfg.cells
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic, tsrc = _profiled_traffic(dom) if cfg.prec == "fp64" and "stable" in cfg.name else (None, None)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": tsrc,
             "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_ms, 4),
             "launches_timed": kn}
     out = {

@@ -168,7 +168,7 @@ erf_status erf_diagnostics(erf_ctx *ctx, const erf_state *S, erf_diag *out);
 /* Kernel timing for measurement.  While enabled, every launch of the named
  * kernel is bracketed by two HIP events recorded on the context's stream; up to
  * max_launches launches are timed, later ones run untimed.  Kernel names:
- * "prep", "mut", "rhs", "stage_init", "coef", "substep", "finalize",
+ * "prep", "mut", "stress", "rhs", "stage_init", "coef", "substep", "finalize",
  * "mixing_ratio", "scalar".  erf_timing_begin allocates the events
  * (ERF_E_NOMEM on failure) and returns ERF_E_ARG for an unknown name. */
 erf_status erf_timing_begin(erf_ctx *ctx, const char *kernel, int32_t max_launches);

@@ -845,7 +845,8 @@ int orc_diagnostics(const orc_grid *g, const orc_params *P, const orc_base *B,
                 double temp = (T / r) * exner(T);
                 kadd(&energy, (0.5 * r * (uc * uc + vc * vc + wc * wc) + r * C_V * temp + r * P->grav * zc) * vol);
                 for (int s = 0; s < nq; ++s) kadd(&qm[s], S->rq[(size_t)s * n + c] * vol);
-                if (!isfinite(r) || !isfinite(T) || !isfinite(S->ru[c]) || !isfinite(S->rv[c])) nonfinite += 1.0;
+                nonfinite += (double)!isfinite(r) + (double)!isfinite(T) + (double)!isfinite(S->ru[c]) +
+                             (double)!isfinite(S->rv[c]);
             }
         z += g->dz[k];
     }

@@ -45,7 +45,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks)
 struct StageArgs {
     Dims d;
     double dx, dy;
-    const double *dz;
+    const double *dz, *idz, *idzf;
     double g, b1, b2, bd, dtau;
     const double *rho0, *pi0;
     // S^n, S^t, R^t
@@ -154,6 +154,7 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs a)
     const int o_n = (wrap_idx(jc + 1, d.ny) - jc) * d.nx, o_s = (wrap_idx(jc - 1, d.ny) - jc) * d.nx;
     const double dt = a.dtau, b1 = a.b1, b2 = a.b2, gr = a.g, bd = a.bd;
     const double gRd = kGamma * kRd;
+    const double idx = 1.0 / a.dx, idy = 1.0 / a.dy;
 
     const int k0 = g * kLevels;
     double th[kLevels], rh[kLevels], tf[kLevels];
@@ -182,12 +183,12 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs a)
                 const double pc = a.pit[c], pw = a.pit[c + o_w], pe = a.pit[c + o_e], ps = a.pit[c + o_s],
                              pn = a.pit[c + o_n];
                 // U'' on this column's x-face and on the next one, V'' likewise
-                const double Uw = a.u2in[c] + dt * (-gRd * (0.5 * (pw + pc)) * (ttc - ttw) / a.dx + a.R_u[c]);
+                const double Uw = a.u2in[c] + dt * (-gRd * (0.5 * (pw + pc)) * (ttc - ttw) * idx + a.R_u[c]);
                 const double Ue =
-                    a.u2in[c + o_e] + dt * (-gRd * (0.5 * (pc + pe)) * (tte - ttc) / a.dx + a.R_u[c + o_e]);
-                const double Vs = a.v2in[c] + dt * (-gRd * (0.5 * (ps + pc)) * (ttc - tts) / a.dy + a.R_v[c]);
+                    a.u2in[c + o_e] + dt * (-gRd * (0.5 * (pc + pe)) * (tte - ttc) * idx + a.R_u[c + o_e]);
+                const double Vs = a.v2in[c] + dt * (-gRd * (0.5 * (ps + pc)) * (ttc - tts) * idy + a.R_v[c]);
                 const double Vn =
-                    a.v2in[c + o_n] + dt * (-gRd * (0.5 * (pc + pn)) * (ttn - ttc) / a.dy + a.R_v[c + o_n]);
+                    a.v2in[c + o_n] + dt * (-gRd * (0.5 * (pc + pn)) * (ttn - ttc) * idy + a.R_v[c + o_n]);
                 a.u2out[c] = Uw;
                 a.v2out[c] = Vs;
                 if (a.sums) {
@@ -198,26 +199,26 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs a)
                 const double thc = a.tht[c];
                 const double thx0 = 0.5 * (a.tht[c + o_w] + thc), thx1 = 0.5 * (thc + a.tht[c + o_e]);
                 const double thy0 = 0.5 * (a.tht[c + o_s] + thc), thy1 = 0.5 * (thc + a.tht[c + o_n]);
-                const double hdiv_t = (Ue * thx1 - Uw * thx0) / a.dx + (Vn * thy1 - Vs * thy0) / a.dy;
-                const double hdiv_r = (Ue - Uw) / a.dx + (Vn - Vs) / a.dy;
+                const double hdiv_t = (Ue * thx1 - Uw * thx0) * idx + (Vn * thy1 - Vs * thy0) * idy;
+                const double hdiv_r = (Ue - Uw) * idx + (Vn - Vs) * idy;
                 const double th_above = (k < nz - 1) ? a.tht[c + nxy] : 0.0;
                 const double tfk = (k == 0) ? 0.0 : 0.5 * (th_below + thc);
                 const double tfk1 = (k == nz - 1) ? 0.0 : 0.5 * (thc + th_above);
                 const double w_hi = a.w2[c + nxy];
-                const double dzk = a.dz[k];
+                const double idzk = a.idz[k];
                 const double r2c = a.r2[c];
-                const double that = Tc + dt * (-hdiv_t - b1 * (w_hi * tfk1 - w_lo * tfk) / dzk + a.R_t[c]);
-                const double rhat = r2c + dt * (-hdiv_r - b1 * (w_hi - w_lo) / dzk + a.R_r[c]);
+                const double that = Tc + dt * (-hdiv_t - b1 * (w_hi * tfk1 - w_lo * tfk) * idzk + a.R_t[c]);
+                const double rhat = r2c + dt * (-hdiv_r - b1 * (w_hi - w_lo) * idzk + a.R_r[c]);
                 const double e = b1 * Tc + b2 * that, f = b1 * r2c + b2 * rhat;
                 if (l == 0) {
                     e_first = e;
                     f_first = f;
                 } else {
                     // right-hand side of the W'' row on face k
-                    const double dzf = 0.5 * (a.dz[k - 1] + dzk);
+                    const double idzf = a.idzf[k];
                     const double A = gRd * (0.5 * (pi_below + pc));
                     const double C = a.cC[c];
-                    rbuf[k * kLanes + lane] = w_lo + dt * (-A * (e - e_prev) / dzf + 0.5 * C * (e + e_prev) -
+                    rbuf[k * kLanes + lane] = w_lo + dt * (-A * (e - e_prev) * idzf + 0.5 * C * (e + e_prev) -
                                                            0.5 * gr * (f + f_prev) + a.R_w[c]);
                 }
                 th[l] = that;
@@ -242,10 +243,10 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs a)
         const int k = k0, c = col + k * nxy;
         const double e_prev = bnd[((g - 1) * 2 + 0) * kLanes + lane];
         const double f_prev = bnd[((g - 1) * 2 + 1) * kLanes + lane];
-        const double dzf = 0.5 * (a.dz[k - 1] + a.dz[k]);
+        const double idzf = a.idzf[k];
         const double A = gRd * (0.5 * (a.pit[c - nxy] + a.pit[c]));
         const double C = a.cC[c];
-        rbuf[k * kLanes + lane] = a.w2[c] + dt * (-A * (e_first - e_prev) / dzf + 0.5 * C * (e_first + e_prev) -
+        rbuf[k * kLanes + lane] = a.w2[c] + dt * (-A * (e_first - e_prev) * idzf + 0.5 * C * (e_first + e_prev) -
                                                   0.5 * gr * (f_first + f_prev) + a.R_w[c]);
     }
     __syncthreads();
@@ -333,9 +334,9 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs a)
                 const int c = col + k * nxy;
                 const double wk = (k >= rlo && k <= rhi) ? rbuf[k * kLanes + lane] + mult[l] * Xnext : 0.0;
                 const double tf1 = (l == kLevels - 1 || k == nz - 1) ? tf_top : tf[l + 1 < kLevels ? l + 1 : l];
-                const double dzk = a.dz[k];
-                a.T2nxt[c] = th[l] - dt * b2 * (wk1 * tf1 - wk * tf[l]) / dzk;
-                a.r2[c] = rh[l] - dt * b2 * (wk1 - wk) / dzk;
+                const double idzk = a.idz[k];
+                a.T2nxt[c] = th[l] - dt * b2 * (wk1 * tf1 - wk * tf[l]) * idzk;
+                a.r2[c] = rh[l] - dt * b2 * (wk1 - wk) * idzk;
                 if (k >= 1) {
                     a.w2[c] = wk;
                     if (a.sums) a.sw[c] += wk;
@@ -396,6 +397,8 @@ hipError_t launch_acoustic_stage(erf_ctx *cx, const double *const Sn[5], const d
     a.dx = cx->grid.dx;
     a.dy = cx->grid.dy;
     a.dz = cx->base.dz;
+    a.idz = cx->base.idz();
+    a.idzf = cx->base.idzf();
     a.g = cx->prm.grav;
     a.b1 = 0.5 * (1.0 - cx->prm.beta_s);
     a.b2 = 0.5 * (1.0 + cx->prm.beta_s);

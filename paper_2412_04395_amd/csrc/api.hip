@@ -136,6 +136,8 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
         {&ws.sb[0], n}, {&ws.sb[1], n}, {&ws.sb[2], n}, {&ws.sb[3], n}, {&ws.sb[4], w}, {&ws.sb[5], q},
         {&ws.R[0], n}, {&ws.R[1], n}, {&ws.R[2], n}, {&ws.R[3], n}, {&ws.R[4], w},
         {&ws.th, n}, {&ws.pp, n}, {&ws.pit, n}, {&ws.u, n}, {&ws.v, n}, {&ws.w, w}, {&ws.mut, n},
+        {&ws.tau[0], n}, {&ws.tau[1], n}, {&ws.tau[2], n}, {&ws.tau[3], n}, {&ws.tau[4], w}, {&ws.tau[5], w},
+        {&ws.kap, n},
         {&ws.t2[0], n}, {&ws.t2[1], n}, {&ws.t2[2], n}, {&ws.r2, n}, {&ws.w2, w},
         {&ws.u2[0], n}, {&ws.u2[1], n}, {&ws.v2[0], n}, {&ws.v2[1], n},
         {&ws.su, n}, {&ws.sv, n}, {&ws.sw, w},
@@ -143,7 +145,7 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
         {&ws.q, q}, {&ws.fu, n}, {&ws.fv, n}, {&ws.fw, w},
         {&ws.diag, diag_slots_needed()},
         {&b.rho0, (size_t)grid->nz}, {&b.theta0, (size_t)grid->nz}, {&b.Theta0, (size_t)grid->nz},
-        {&b.p0, (size_t)grid->nz}, {&b.pi0, (size_t)grid->nz}, {&b.dz, 2 * (size_t)grid->nz},
+        {&b.p0, (size_t)grid->nz}, {&b.pi0, (size_t)grid->nz}, {&b.dz, 4 * (size_t)grid->nz + 1},
     };
     size_t total = 0;
     for (const Req &r : reqs) total += align_up(r.count * sizeof(double));
@@ -160,15 +162,20 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
         *r.p = r.count ? (double *)p : nullptr;
         p += align_up(r.count * sizeof(double));
     }
-    // dz and centre heights
-    double *hz = new double[2 * grid->nz];
+    // dz, centre heights, 1/dz and 2/(dz_{k-1} + dz_k) on the z-faces
+    const int nz = grid->nz;
+    b.nz = nz;
+    double *hz = new double[4 * nz + 1];
     double zc = 0.0;
-    for (int k = 0; k < grid->nz; ++k) {
+    for (int k = 0; k < nz; ++k) {
         hz[k] = grid->dz[k];
-        hz[grid->nz + k] = zc + 0.5 * grid->dz[k];
+        hz[nz + k] = zc + 0.5 * grid->dz[k];
+        hz[2 * nz + k] = 1.0 / grid->dz[k];
+        hz[3 * nz + k] = k == 0 ? 0.0 : 2.0 / (grid->dz[k - 1] + grid->dz[k]);
         zc += grid->dz[k];
     }
-    e = hipMemcpy(b.dz, hz, 2 * grid->nz * sizeof(double), hipMemcpyHostToDevice);
+    hz[4 * nz] = 0.0;
+    e = hipMemcpy(b.dz, hz, (4 * nz + 1) * sizeof(double), hipMemcpyHostToDevice);
     delete[] hz;
     if (e != hipSuccess) {
         erf_destroy(c);

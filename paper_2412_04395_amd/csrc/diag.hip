@@ -112,7 +112,7 @@ hipError_t launch_diagnostics(erf_ctx *cx, const double *rho, const double *rt, 
     a.dy = cx->grid.dy;
     a.g = cx->prm.grav;
     a.dz = cx->base.dz;
-    a.zc = cx->base.dz + cx->d.nz;  // centre heights follow dz in the same buffer
+    a.zc = cx->base.zc();
     a.rho = rho;
     a.rt = rt;
     a.ru = ru;

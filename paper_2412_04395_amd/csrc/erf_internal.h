@@ -99,6 +99,10 @@ struct Workspace {
     // stage-frozen fields at centres: theta, p', pi, velocities, mu_t
     double *th = nullptr, *pp = nullptr, *pit = nullptr;
     double *u = nullptr, *v = nullptr, *w = nullptr, *mut = nullptr;
+    // stresses tau_11, tau_22, tau_33 (centres), tau_12 (xy-edges), tau_13,
+    // tau_23 (z-face edges) and the heat diffusivity (centres)
+    double *tau[6] = {};
+    double *kap = nullptr;
     // substep perturbations: Theta'' (three time levels), rho'', U'' and V''
     // (double-buffered), W''
     double *t2[3] = {};
@@ -118,7 +122,14 @@ struct Workspace {
 
 struct Base {
     double *rho0 = nullptr, *theta0 = nullptr, *Theta0 = nullptr, *p0 = nullptr, *pi0 = nullptr;
-    double *dz = nullptr;  // device: dz [nz] followed by the centre heights [nz]
+    // device: dz [nz], centre heights [nz], 1/dz [nz] and the reciprocal
+    // centre-to-centre distances across the z-faces, 2/(dz_{k-1} + dz_k) [nz + 1]
+    // (zero on the lids), in one buffer
+    double *dz = nullptr;
+    const double *zc() const { return dz + nz; }
+    const double *idz() const { return dz + 2 * nz; }
+    const double *idzf() const { return dz + 3 * nz; }
+    int nz = 0;
 };
 
 }  // namespace erfk
@@ -146,11 +157,11 @@ struct erf_ctx {
 namespace erfk {
 
 // kernel ids for the timing instrumentation
-enum KernelId { K_PREP, K_MUT, K_RHS, K_STAGE_INIT, K_COEF, K_SUBSTEP, K_FINALIZE, K_MIXRATIO, K_SCALAR, K_COUNT };
+enum KernelId { K_PREP, K_MUT, K_STRESS, K_RHS, K_STAGE_INIT, K_COEF, K_SUBSTEP, K_FINALIZE, K_MIXRATIO, K_SCALAR, K_COUNT };
 inline const char *kernel_name(int id)
 {
-    static const char *names[K_COUNT] = {"prep", "mut", "rhs", "stage_init", "coef", "substep", "finalize",
-                                         "mixing_ratio", "scalar"};
+    static const char *names[K_COUNT] = {"prep", "mut", "stress", "rhs", "stage_init", "coef", "substep",
+                                         "finalize", "mixing_ratio", "scalar"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 // bracket a launch with events when its kernel is being timed

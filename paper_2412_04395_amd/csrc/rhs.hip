@@ -1,13 +1,19 @@
 // rhs.hip -- slow right-hand side f(S) of the compressible equations
 // (eqs. con, mom, theta of Sec. 2.1) on the C-grid, FP64.
 //
-// Three passes per call:
-//   k_prep    primitive fields at centres / faces: theta, p', Exner, u, v, w
-//   k_mut     Smagorinsky eddy viscosity at centres (only with the SGS model)
-//   k_rhs     one thread per (i,j,k): R_rho, R_Theta at the cell, R_U, R_V at
-//             its x- and y-face, R_W at its z-face
-// Neighbours are read through the cache hierarchy; the x-fastest thread layout
-// keeps every stencil load of a wavefront on consecutive addresses.
+// Passes per call:
+//   k_prep    primitive fields: theta, p' at centres, u, v, w on faces
+//   k_mut     Smagorinsky eddy viscosity at centres (SGS model only)
+//   k_stress  stress tensor of eq. (stresstensor) at its staggered points
+//             (normal stresses at centres, shear stresses on edges) and the
+//             heat diffusivity (any viscous run)
+//   k_rhs     one thread per (i, j, k): R_rho, R_Theta of the cell, R_U, R_V
+//             of its x- and y-face, R_W of its z-face: flux-form advection
+//             with the interpolants of Sec. 3.6, pressure gradient, buoyancy,
+//             Coriolis, surface heat flux and the divergence of the stresses.
+// Every thread resolves the periodic wrap in x and y and the lid reflections in
+// z once, into offset tables, so the stencil loads are base + offset.  The
+// interpolation order is a template parameter for the orders the workloads use.
 #include "erf_internal.h"
 
 namespace erfk {
@@ -16,66 +22,22 @@ namespace {
 struct RhsArgs {
     Dims d;
     double dx, dy, idx, idy;
-    const double *dz;
+    const double *dz, *idz, *idzf;
     int oh, ov;
-    int sgs;
+    int sgs, visc;
     double Cs, Pr_t, nu, alpha, f, Ug, Vg, Qs, g;
     // state
     const double *rho, *rt, *ru, *rv, *rw;
     // base state
     const double *rho0, *Theta0, *p0;
-    // primitives
-    const double *th, *pp, *u, *v, *w, *mut;
+    // primitives and stresses (workspace)
+    double *th, *pp, *u, *v, *w, *mut;
+    double *t11, *t22, *t33, *t12, *t13, *t23, *kap;
     // outputs
     double *Rr, *Rt, *Ru, *Rv, *Rw;
 };
 
 __device__ __forceinline__ int cidx(const Dims &d, int i, int j, int k) { return (k * d.ny + j) * d.nx + i; }
-
-// centre-located or horizontal-face quantity: periodic in x, y; even ghosts in z
-__device__ __forceinline__ double ldc(const double *f, const Dims &d, int i, int j, int k)
-{
-    return f[cidx(d, wrap_idx(i, d.nx), wrap_idx(j, d.ny), refl_centre(k, d.nz))];
-}
-
-// z-face quantity: periodic in x, y; odd ghosts about the lids
-__device__ __forceinline__ double ldw(const double *f, const Dims &d, int i, int j, int k)
-{
-    double s;
-    int kk = refl_face(k, d.nz, s);
-    return s * f[cidx(d, wrap_idx(i, d.nx), wrap_idx(j, d.ny), kk)];
-}
-
-__device__ __forceinline__ double interp_x(const double *f, const Dims &d, int i, int j, int k, int o, double s)
-{
-    return face_interp(o, ldc(f, d, i - 3, j, k), ldc(f, d, i - 2, j, k), ldc(f, d, i - 1, j, k),
-                       ldc(f, d, i, j, k), ldc(f, d, i + 1, j, k), ldc(f, d, i + 2, j, k), s);
-}
-__device__ __forceinline__ double interp_y(const double *f, const Dims &d, int i, int j, int k, int o, double s)
-{
-    return face_interp(o, ldc(f, d, i, j - 3, k), ldc(f, d, i, j - 2, k), ldc(f, d, i, j - 1, k),
-                       ldc(f, d, i, j, k), ldc(f, d, i, j + 1, k), ldc(f, d, i, j + 2, k), s);
-}
-__device__ __forceinline__ double interp_zc(const double *f, const Dims &d, int i, int j, int k, int o, double s)
-{
-    return face_interp(o, ldc(f, d, i, j, k - 3), ldc(f, d, i, j, k - 2), ldc(f, d, i, j, k - 1),
-                       ldc(f, d, i, j, k), ldc(f, d, i, j, k + 1), ldc(f, d, i, j, k + 2), s);
-}
-__device__ __forceinline__ double interp_zw(const double *f, const Dims &d, int i, int j, int k, int o, double s)
-{
-    return face_interp(o, ldw(f, d, i, j, k - 3), ldw(f, d, i, j, k - 2), ldw(f, d, i, j, k - 1),
-                       ldw(f, d, i, j, k), ldw(f, d, i, j, k + 1), ldw(f, d, i, j, k + 2), s);
-}
-__device__ __forceinline__ double interp_xw(const double *f, const Dims &d, int i, int j, int k, int o, double s)
-{
-    return face_interp(o, ldw(f, d, i - 3, j, k), ldw(f, d, i - 2, j, k), ldw(f, d, i - 1, j, k),
-                       ldw(f, d, i, j, k), ldw(f, d, i + 1, j, k), ldw(f, d, i + 2, j, k), s);
-}
-__device__ __forceinline__ double interp_yw(const double *f, const Dims &d, int i, int j, int k, int o, double s)
-{
-    return face_interp(o, ldw(f, d, i, j - 3, k), ldw(f, d, i, j - 2, k), ldw(f, d, i, j - 1, k),
-                       ldw(f, d, i, j, k), ldw(f, d, i, j + 1, k), ldw(f, d, i, j + 2, k), s);
-}
 
 // ---------------------------------------------------------------------------
 // primitives
@@ -90,57 +52,36 @@ __global__ __launch_bounds__(256) void k_prep(RhsArgs a)
     int c = cidx(d, i, j, k);
     double r = a.rho[c], T = a.rt[c];
     double T0 = a.Theta0[k];
-    double *th = const_cast<double *>(a.th), *pp = const_cast<double *>(a.pp);
-    double *u = const_cast<double *>(a.u), *v = const_cast<double *>(a.v), *w = const_cast<double *>(a.w);
-    th[c] = T / r;
+    a.th[c] = T / r;
     // p' = p0 ((Theta/Theta0)^gamma - 1) without cancellation (EOS, Sec. 2.1)
-    pp[c] = a.p0[k] * expm1(kGamma * log1p((T - T0) / T0));
-    u[c] = a.ru[c] / (0.5 * (a.rho[cidx(d, wrap_idx(i - 1, d.nx), j, k)] + r));
-    v[c] = a.rv[c] / (0.5 * (a.rho[cidx(d, i, wrap_idx(j - 1, d.ny), k)] + r));
-    w[c] = (k == 0) ? 0.0 : a.rw[c] / (0.5 * (a.rho[c - d.nxy] + r));
-    if (k == d.nz - 1) w[c + d.nxy] = 0.0;
+    a.pp[c] = a.p0[k] * expm1(kGamma * log1p((T - T0) / T0));
+    a.u[c] = a.ru[c] / (0.5 * (a.rho[cidx(d, wrap_idx(i - 1, d.nx), j, k)] + r));
+    a.v[c] = a.rv[c] / (0.5 * (a.rho[cidx(d, i, wrap_idx(j - 1, d.ny), k)] + r));
+    a.w[c] = (k == 0) ? 0.0 : a.rw[c] / (0.5 * (a.rho[c - d.nxy] + r));
+    if (k == d.nz - 1) a.w[c + d.nxy] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
-// strain rates (Sec. 2.3): diagonal at centres, off-diagonal on edges
+// strain rates and stresses (Sec. 2.3)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double s11(const RhsArgs &a, int i, int j, int k)
+// Neighbour offsets of one thread: x and y wrap periodically.
+struct Nbr {
+    int c, im, ip, jm, jp;  // c and the signed offsets of i-1, i+1, j-1, j+1
+};
+
+__device__ __forceinline__ Nbr nbr(const Dims &d, int i, int j, int k)
 {
-    return (ldc(a.u, a.d, i + 1, j, k) - ldc(a.u, a.d, i, j, k)) / a.dx;
-}
-__device__ __forceinline__ double s22(const RhsArgs &a, int i, int j, int k)
-{
-    return (ldc(a.v, a.d, i, j + 1, k) - ldc(a.v, a.d, i, j, k)) / a.dy;
-}
-__device__ __forceinline__ double s33(const RhsArgs &a, int i, int j, int k)
-{
-    // k is an interior centre index here
-    return (a.w[cidx(a.d, wrap_idx(i, a.d.nx), wrap_idx(j, a.d.ny), k + 1)] -
-            a.w[cidx(a.d, wrap_idx(i, a.d.nx), wrap_idx(j, a.d.ny), k)]) / a.dz[k];
-}
-// edge of x-face i and y-face j at level k
-__device__ __forceinline__ double s12(const RhsArgs &a, int i, int j, int k)
-{
-    return 0.5 * ((ldc(a.u, a.d, i, j, k) - ldc(a.u, a.d, i, j - 1, k)) / a.dy +
-                  (ldc(a.v, a.d, i, j, k) - ldc(a.v, a.d, i - 1, j, k)) / a.dx);
-}
-// edge of x-face i and z-face k (zero on the free-slip lids)
-__device__ __forceinline__ double s13(const RhsArgs &a, int i, int j, int k)
-{
-    if (k <= 0 || k >= a.d.nz) return 0.0;
-    double dzf = 0.5 * (a.dz[k - 1] + a.dz[k]);
-    return 0.5 * ((ldc(a.u, a.d, i, j, k) - ldc(a.u, a.d, i, j, k - 1)) / dzf +
-                  (ldw(a.w, a.d, i, j, k) - ldw(a.w, a.d, i - 1, j, k)) / a.dx);
-}
-__device__ __forceinline__ double s23(const RhsArgs &a, int i, int j, int k)
-{
-    if (k <= 0 || k >= a.d.nz) return 0.0;
-    double dzf = 0.5 * (a.dz[k - 1] + a.dz[k]);
-    return 0.5 * ((ldc(a.v, a.d, i, j, k) - ldc(a.v, a.d, i, j, k - 1)) / dzf +
-                  (ldw(a.w, a.d, i, j, k) - ldw(a.w, a.d, i, j - 1, k)) / a.dy);
+    Nbr n;
+    n.c = cidx(d, i, j, k);
+    n.im = wrap_idx(i - 1, d.nx) - i;
+    n.ip = wrap_idx(i + 1, d.nx) - i;
+    n.jm = (wrap_idx(j - 1, d.ny) - j) * d.nx;
+    n.jp = (wrap_idx(j + 1, d.ny) - j) * d.nx;
+    return n;
 }
 
-// Smagorinsky eddy viscosity mu_t = rho (Cs Delta)^2 sqrt(2 S:S), Delta = (dx dy dz)^(1/3)
+// Smagorinsky eddy viscosity mu_t = rho (Cs Delta)^2 sqrt(2 S:S), Delta = (dx dy dz)^(1/3);
+// off-diagonal strains are averaged from the four edges around the centre.
 __global__ __launch_bounds__(256) void k_mut(RhsArgs a)
 {
     const Dims &d = a.d;
@@ -148,202 +89,265 @@ __global__ __launch_bounds__(256) void k_mut(RhsArgs a)
     int j = blockIdx.y * blockDim.y + threadIdx.y;
     int k = blockIdx.z;
     if (i >= d.nx || j >= d.ny) return;
-    int c = cidx(d, i, j, k);
-    double e11 = s11(a, i, j, k), e22 = s22(a, i, j, k), e33 = s33(a, i, j, k);
-    double a12 = 0.25 * (s12(a, i, j, k) + s12(a, i + 1, j, k) + s12(a, i, j + 1, k) + s12(a, i + 1, j + 1, k));
-    double a13 = 0.25 * (s13(a, i, j, k) + s13(a, i + 1, j, k) + s13(a, i, j, k + 1) + s13(a, i + 1, j, k + 1));
-    double a23 = 0.25 * (s23(a, i, j, k) + s23(a, i, j + 1, k) + s23(a, i, j, k + 1) + s23(a, i, j + 1, k + 1));
-    double ss = 2.0 * (e11 * e11 + e22 * e22 + e33 * e33) + 4.0 * (a12 * a12 + a13 * a13 + a23 * a23);
-    double cd = a.Cs * cbrt(a.dx * a.dy * a.dz[k]);
-    const_cast<double *>(a.mut)[c] = a.rho[c] * cd * cd * sqrt(ss);
+    const Nbr n = nbr(d, i, j, k);
+    const int c = n.c, P = d.nxy;
+    const double *u = a.u, *v = a.v, *w = a.w;
+    const double idz = a.idz[k];
+    const double e11 = (u[c + n.ip] - u[c]) * a.idx;
+    const double e22 = (v[c + n.jp] - v[c]) * a.idy;
+    const double e33 = (w[c + P] - w[c]) * idz;
+    // offsets of i-1 and j-1 seen from the neighbours i+1 and j+1
+    const int ip1 = wrap_idx(i + 1, d.nx), jp1 = wrap_idx(j + 1, d.ny);
+    const int nip_im = wrap_idx(ip1 - 1, d.nx) - ip1;
+    const int njp_jm = (wrap_idx(jp1 - 1, d.ny) - jp1) * d.nx;
+    // S12 on the edge (x-face, y-face) at offset o, with its i-1 / j-1 offsets
+    auto s12 = [&](int o, int oim, int ojm) {
+        return 0.5 * ((u[c + o] - u[c + o + ojm]) * a.idy + (v[c + o] - v[c + o + oim]) * a.idx);
+    };
+    const double a12 = 0.25 * (s12(0, n.im, n.jm) + s12(n.ip, nip_im, n.jm) + s12(n.jp, n.im, njp_jm) +
+                               s12(n.ip + n.jp, nip_im, njp_jm));
+    // S13 / S23 on z-face edges; zero on the lids
+    auto s13 = [&](int o, int oim, int kf) {
+        if (kf <= 0 || kf >= d.nz) return 0.0;
+        const double idzf = a.idzf[kf];
+        return 0.5 * ((u[c + o] - u[c + o - P]) * idzf + (w[c + o] - w[c + o + oim]) * a.idx);
+    };
+    auto s23 = [&](int o, int ojm, int kf) {
+        if (kf <= 0 || kf >= d.nz) return 0.0;
+        const double idzf = a.idzf[kf];
+        return 0.5 * ((v[c + o] - v[c + o - P]) * idzf + (w[c + o] - w[c + o + ojm]) * a.idy);
+    };
+    const double a13 =
+        0.25 * (s13(0, n.im, k) + s13(n.ip, nip_im, k) + s13(P, n.im, k + 1) + s13(P + n.ip, nip_im, k + 1));
+    const double a23 =
+        0.25 * (s23(0, n.jm, k) + s23(n.jp, njp_jm, k) + s23(P, n.jm, k + 1) + s23(P + n.jp, njp_jm, k + 1));
+    const double ss = 2.0 * (e11 * e11 + e22 * e22 + e33 * e33) + 4.0 * (a12 * a12 + a13 * a13 + a23 * a23);
+    const double cd = a.Cs * cbrt(a.dx * a.dy * a.dz[k]);
+    a.mut[c] = a.rho[c] * cd * cd * sqrt(ss);
 }
 
-__device__ __forceinline__ double mu_tot(const RhsArgs &a, int i, int j, int k)
-{
-    int c = cidx(a.d, wrap_idx(i, a.d.nx), wrap_idx(j, a.d.ny), k);
-    return a.rho[c] * a.nu + (a.sgs ? a.mut[c] : 0.0);
-}
-__device__ __forceinline__ double kappa(const RhsArgs &a, int c)
-{
-    return a.rho[c] * a.alpha + (a.sgs ? a.mut[c] / a.Pr_t : 0.0);
-}
-// deviatoric normal stresses at a centre
-__device__ __forceinline__ void tau_diag(const RhsArgs &a, int i, int j, int k, double &t11, double &t22, double &t33)
-{
-    double e11 = s11(a, i, j, k), e22 = s22(a, i, j, k), e33 = s33(a, i, j, k);
-    double dd = (e11 + e22 + e33) / 3.0;
-    double m = mu_tot(a, i, j, k);
-    t11 = -2.0 * m * (e11 - dd);
-    t22 = -2.0 * m * (e22 - dd);
-    t33 = -2.0 * m * (e33 - dd);
-}
-__device__ __forceinline__ double tau12(const RhsArgs &a, int i, int j, int k)
-{
-    double me = 0.25 * (mu_tot(a, i - 1, j - 1, k) + mu_tot(a, i, j - 1, k) + mu_tot(a, i - 1, j, k) + mu_tot(a, i, j, k));
-    return -2.0 * me * s12(a, i, j, k);
-}
-__device__ __forceinline__ double tau13(const RhsArgs &a, int i, int j, int k)
-{
-    if (k <= 0 || k >= a.d.nz) return 0.0;
-    double me = 0.25 * (mu_tot(a, i - 1, j, k - 1) + mu_tot(a, i, j, k - 1) + mu_tot(a, i - 1, j, k) + mu_tot(a, i, j, k));
-    return -2.0 * me * s13(a, i, j, k);
-}
-__device__ __forceinline__ double tau23(const RhsArgs &a, int i, int j, int k)
-{
-    if (k <= 0 || k >= a.d.nz) return 0.0;
-    double me = 0.25 * (mu_tot(a, i, j - 1, k - 1) + mu_tot(a, i, j, k - 1) + mu_tot(a, i, j - 1, k) + mu_tot(a, i, j, k));
-    return -2.0 * me * s23(a, i, j, k);
-}
-
-// ---------------------------------------------------------------------------
-// tendencies
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_rhs(RhsArgs a)
+// Stresses tau = -2 mu (S - D) at their points, mu = rho nu_m + mu_t averaged
+// from the four cells around an edge; heat diffusivity rho alpha_m + mu_t/Pr_t.
+// z runs to nz for the shear stresses on the top faces (zero: free slip).
+__global__ __launch_bounds__(256) void k_stress(RhsArgs a)
 {
     const Dims &d = a.d;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int j = blockIdx.y * blockDim.y + threadIdx.y;
     int k = blockIdx.z;
     if (i >= d.nx || j >= d.ny) return;
-    const int nz = d.nz, oh = a.oh, ov = a.ov;
+    const Nbr n = nbr(d, i, j, k);
+    const int P = d.nxy, c = n.c;
+    const double *u = a.u, *v = a.v, *w = a.w, *rho = a.rho, *mut = a.mut;
+    auto mu = [&](int cc) { return rho[cc] * a.nu + (a.sgs ? mut[cc] : 0.0); };
+    // shear stresses on the z-face edges of face k
+    if (k == 0 || k == d.nz) {
+        a.t13[c] = 0.0;
+        a.t23[c] = 0.0;
+    } else {
+        const double idzf = a.idzf[k];
+        const double s13 = 0.5 * ((u[c] - u[c - P]) * idzf + (w[c] - w[c + n.im]) * a.idx);
+        const double s23 = 0.5 * ((v[c] - v[c - P]) * idzf + (w[c] - w[c + n.jm]) * a.idy);
+        const double mxz = 0.25 * (mu(c - P + n.im) + mu(c - P) + mu(c + n.im) + mu(c));
+        const double myz = 0.25 * (mu(c - P + n.jm) + mu(c - P) + mu(c + n.jm) + mu(c));
+        a.t13[c] = -2.0 * mxz * s13;
+        a.t23[c] = -2.0 * myz * s23;
+    }
+    if (k == d.nz) return;
+    const double idz = a.idz[k];
+    const double e11 = (u[c + n.ip] - u[c]) * a.idx;
+    const double e22 = (v[c + n.jp] - v[c]) * a.idy;
+    const double e33 = (w[c + P] - w[c]) * idz;
+    const double dd = (e11 + e22 + e33) / 3.0;
+    const double m = mu(c);
+    a.t11[c] = -2.0 * m * (e11 - dd);
+    a.t22[c] = -2.0 * m * (e22 - dd);
+    a.t33[c] = -2.0 * m * (e33 - dd);
+    const double s12 = 0.5 * ((u[c] - u[c + n.jm]) * a.idy + (v[c] - v[c + n.im]) * a.idx);
+    const double me = 0.25 * (mu(c + n.im + n.jm) + mu(c + n.jm) + mu(c + n.im) + m);
+    a.t12[c] = -2.0 * me * s12;
+    a.kap[c] = rho[c] * a.alpha + (a.sgs ? mut[c] / a.Pr_t : 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// interpolants (Sec. 3.6), order fixed at compile time (O = 0: runtime order)
+// ---------------------------------------------------------------------------
+// q holds q_{-3..3} around the thread's point; the face value q_{m-1/2} uses
+// q_{m-3..m+2}: o = 0 for the face on the low side of the point, o = 1 for the
+// face on the high side.
+template <int O>
+__device__ __forceinline__ double interp(int order, const double (&q)[7], int o, double s)
+{
+    const double qm3 = q[o], qm2 = q[o + 1], qm1 = q[o + 2], q0 = q[o + 3], qp1 = q[o + 4], qp2 = q[o + 5];
+    const int ord = O ? O : order;
+    if (ord == 2) return 0.5 * (q0 + qm1);
+    if (ord == 3 || ord == 4) {
+        const double c4 = 7.0 / 12.0 * (q0 + qm1) - 1.0 / 12.0 * (qp1 + qm2);
+        return ord == 4 ? c4 : c4 + s / 12.0 * ((qp1 - qm2) - 3.0 * (q0 - qm1));
+    }
+    const double c6 = 37.0 / 60.0 * (q0 + qm1) - 2.0 / 15.0 * (qp1 + qm2) + 1.0 / 60.0 * (qp2 + qm3);
+    return ord == 6 ? c6 : c6 - s / 60.0 * ((qp2 - qm3) - 5.0 * (qp1 - qm2) + 10.0 * (q0 - qm1));
+}
+
+template <int OH, int OV>
+__global__ __launch_bounds__(256) void k_rhs(RhsArgs a)
+{
+    const Dims &d = a.d;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= d.nx || j >= d.ny) return;
+    const int nz = d.nz, P = d.nxy;
     const int c = cidx(d, i, j, k);
-    const int ip = wrap_idx(i + 1, d.nx), im = wrap_idx(i - 1, d.nx);
-    const int jp = wrap_idx(j + 1, d.ny), jm = wrap_idx(j - 1, d.ny);
-    const double dzk = a.dz[k];
-    const bool visc = a.sgs != 0 || a.nu != 0.0 || a.alpha != 0.0;
+    // neighbour offset tables: x and y periodic; z reflected (even for centre
+    // and horizontal-face fields, odd with a sign for z-face fields)
+    int ox[7], oy[7], ozc[7], ozw[7];
+    double szw[7];
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+        ox[t] = wrap_idx(i + t - 3, d.nx) - i;
+        oy[t] = (wrap_idx(j + t - 3, d.ny) - j) * d.nx;
+        ozc[t] = (refl_centre(k + t - 3, nz) - k) * P;
+        double sg;
+        ozw[t] = (refl_face(k + t - 3, nz, sg) - k) * P;
+        szw[t] = sg;
+    }
+    const double idz = a.idz[k];
+    const int oh = a.oh, ov = a.ov;
+    double q[7];
 
     // ---------------- cell: continuity and rho*theta ----------------
+    const double U0 = a.ru[c], U1 = a.ru[c + ox[4]];
+    const double V0 = a.rv[c], V1 = a.rv[c + oy[4]];
+    const double W0 = a.rw[c], W1 = a.rw[c + P];
     {
-        double U0 = a.ru[c], U1 = a.ru[cidx(d, ip, j, k)];
-        double V0 = a.rv[c], V1 = a.rv[cidx(d, i, jp, k)];
-        double W0 = a.rw[c], W1 = a.rw[c + d.nxy];
-        a.Rr[c] = -((U1 - U0) / a.dx + (V1 - V0) / a.dy + (W1 - W0) / dzk);
-        double fx0 = U0 * interp_x(a.th, d, i, j, k, oh, sign_of(U0));
-        double fx1 = U1 * interp_x(a.th, d, i + 1, j, k, oh, sign_of(U1));
-        double fy0 = V0 * interp_y(a.th, d, i, j, k, oh, sign_of(V0));
-        double fy1 = V1 * interp_y(a.th, d, i, j + 1, k, oh, sign_of(V1));
-        double fz0 = (k == 0) ? 0.0 : W0 * interp_zc(a.th, d, i, j, k, ov, sign_of(W0));
-        double fz1 = (k == nz - 1) ? 0.0 : W1 * interp_zc(a.th, d, i, j, k + 1, ov, sign_of(W1));
-        double r = -((fx1 - fx0) / a.dx + (fy1 - fy0) / a.dy + (fz1 - fz0) / dzk);
-        if (visc) {
-            const double *th = a.th;
-            double kc = kappa(a, c);
-            double hx0 = -0.5 * (kappa(a, cidx(d, im, j, k)) + kc) * (th[c] - th[cidx(d, im, j, k)]) / a.dx;
-            double hx1 = -0.5 * (kc + kappa(a, cidx(d, ip, j, k))) * (th[cidx(d, ip, j, k)] - th[c]) / a.dx;
-            double hy0 = -0.5 * (kappa(a, cidx(d, i, jm, k)) + kc) * (th[c] - th[cidx(d, i, jm, k)]) / a.dy;
-            double hy1 = -0.5 * (kc + kappa(a, cidx(d, i, jp, k))) * (th[cidx(d, i, jp, k)] - th[c]) / a.dy;
+        a.Rr[c] = -((U1 - U0) * a.idx + (V1 - V0) * a.idy + (W1 - W0) * idz);
+        const double *th = a.th;
+#pragma unroll
+        for (int t = 0; t < 7; ++t) q[t] = th[c + ox[t]];
+        const double fx0 = U0 * interp<OH>(oh, q, 0, sign_of(U0)), fx1 = U1 * interp<OH>(oh, q, 1, sign_of(U1));
+#pragma unroll
+        for (int t = 0; t < 7; ++t) q[t] = th[c + oy[t]];
+        const double fy0 = V0 * interp<OH>(oh, q, 0, sign_of(V0)), fy1 = V1 * interp<OH>(oh, q, 1, sign_of(V1));
+#pragma unroll
+        for (int t = 0; t < 7; ++t) q[t] = th[c + ozc[t]];
+        const double fz0 = (k == 0) ? 0.0 : W0 * interp<OV>(ov, q, 0, sign_of(W0));
+        const double fz1 = (k == nz - 1) ? 0.0 : W1 * interp<OV>(ov, q, 1, sign_of(W1));
+        double r = -((fx1 - fx0) * a.idx + (fy1 - fy0) * a.idy + (fz1 - fz0) * idz);
+        if (a.visc) {
+            const double *kp = a.kap;
+            const double kc = kp[c], thc = th[c];
+            const double hx0 = -0.5 * (kp[c + ox[2]] + kc) * (thc - th[c + ox[2]]) * a.idx;
+            const double hx1 = -0.5 * (kc + kp[c + ox[4]]) * (th[c + ox[4]] - thc) * a.idx;
+            const double hy0 = -0.5 * (kp[c + oy[2]] + kc) * (thc - th[c + oy[2]]) * a.idy;
+            const double hy1 = -0.5 * (kc + kp[c + oy[4]]) * (th[c + oy[4]] - thc) * a.idy;
             double hz0 = 0.0, hz1 = 0.0;
-            if (k > 0)
-                hz0 = -0.5 * (kappa(a, c - d.nxy) + kc) * (th[c] - th[c - d.nxy]) / (0.5 * (a.dz[k - 1] + dzk));
-            if (k < nz - 1)
-                hz1 = -0.5 * (kc + kappa(a, c + d.nxy)) * (th[c + d.nxy] - th[c]) / (0.5 * (dzk + a.dz[k + 1]));
-            r -= (hx1 - hx0) / a.dx + (hy1 - hy0) / a.dy + (hz1 - hz0) / dzk;
+            if (k > 0) hz0 = -0.5 * (kp[c - P] + kc) * (thc - th[c - P]) * a.idzf[k];
+            if (k < nz - 1) hz1 = -0.5 * (kc + kp[c + P]) * (th[c + P] - thc) * a.idzf[k + 1];
+            r -= (hx1 - hx0) * a.idx + (hy1 - hy0) * a.idy + (hz1 - hz0) * idz;
         }
-        if (k == 0 && a.Qs != 0.0) r += a.rho[c] * a.Qs / dzk;
+        if (k == 0 && a.Qs != 0.0) r += a.rho[c] * a.Qs * idz;
         a.Rt[c] = r;
     }
 
     // ---------------- x-momentum on x-face (i, j, k) ----------------
     {
-        double Uc = a.ru[c];
-        double ar = 0.5 * (Uc + a.ru[cidx(d, ip, j, k)]);
-        double al = 0.5 * (a.ru[cidx(d, im, j, k)] + Uc);
-        double fxx_r = ar * interp_x(a.u, d, i + 1, j, k, oh, sign_of(ar));
-        double fxx_l = al * interp_x(a.u, d, i, j, k, oh, sign_of(al));
-        double b0 = 0.5 * (a.rv[cidx(d, im, j, k)] + a.rv[c]);
-        double b1 = 0.5 * (a.rv[cidx(d, im, jp, k)] + a.rv[cidx(d, i, jp, k)]);
-        double fxy0 = b0 * interp_y(a.u, d, i, j, k, oh, sign_of(b0));
-        double fxy1 = b1 * interp_y(a.u, d, i, j + 1, k, oh, sign_of(b1));
+        const double Um = a.ru[c + ox[2]];
+        const double ar = 0.5 * (U0 + U1), al = 0.5 * (Um + U0);
+        const double *u = a.u;
+#pragma unroll
+        for (int t = 0; t < 7; ++t) q[t] = u[c + ox[t]];
+        const double fxx_r = ar * interp<OH>(oh, q, 1, sign_of(ar)), fxx_l = al * interp<OH>(oh, q, 0, sign_of(al));
+        const double Vw = a.rv[c + ox[2]], Vwn = a.rv[c + ox[2] + oy[4]];
+        const double b0 = 0.5 * (Vw + V0), b1 = 0.5 * (Vwn + V1);
+#pragma unroll
+        for (int t = 0; t < 7; ++t) q[t] = u[c + oy[t]];
+        const double fxy0 = b0 * interp<OH>(oh, q, 0, sign_of(b0)), fxy1 = b1 * interp<OH>(oh, q, 1, sign_of(b1));
+#pragma unroll
+        for (int t = 0; t < 7; ++t) q[t] = u[c + ozc[t]];
         double fxz0 = 0.0, fxz1 = 0.0;
         if (k > 0) {
-            double e0 = 0.5 * (a.rw[cidx(d, im, j, k)] + a.rw[c]);
-            fxz0 = e0 * interp_zc(a.u, d, i, j, k, ov, sign_of(e0));
+            const double e0 = 0.5 * (a.rw[c + ox[2]] + W0);
+            fxz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0));
         }
         if (k < nz - 1) {
-            double e1 = 0.5 * (a.rw[cidx(d, im, j, k + 1)] + a.rw[c + d.nxy]);
-            fxz1 = e1 * interp_zc(a.u, d, i, j, k + 1, ov, sign_of(e1));
+            const double e1 = 0.5 * (a.rw[c + ox[2] + P] + W1);
+            fxz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1));
         }
-        double adv = (fxx_r - fxx_l) / a.dx + (fxy1 - fxy0) / a.dy + (fxz1 - fxz0) / dzk;
-        double pgf = (a.pp[c] - a.pp[cidx(d, im, j, k)]) / a.dx;
-        double rho_f = 0.5 * (a.rho[cidx(d, im, j, k)] + a.rho[c]);
-        double vbar = 0.25 * (a.rv[cidx(d, im, j, k)] + a.rv[c] + a.rv[cidx(d, im, jp, k)] + a.rv[cidx(d, i, jp, k)]);
+        const double adv = (fxx_r - fxx_l) * a.idx + (fxy1 - fxy0) * a.idy + (fxz1 - fxz0) * idz;
+        const double pgf = (a.pp[c] - a.pp[c + ox[2]]) * a.idx;
+        const double rho_f = 0.5 * (a.rho[c + ox[2]] + a.rho[c]);
+        const double vbar = 0.25 * (Vw + V0 + Vwn + V1);
         double r = -adv - pgf + a.f * (vbar - rho_f * a.Vg);
-        if (visc) {
-            double t11c, t22c, t33c, t11w, t22w, t33w;
-            tau_diag(a, i, j, k, t11c, t22c, t33c);
-            tau_diag(a, i - 1, j, k, t11w, t22w, t33w);
-            r -= (t11c - t11w) / a.dx + (tau12(a, i, j + 1, k) - tau12(a, i, j, k)) / a.dy +
-                 (tau13(a, i, j, k + 1) - tau13(a, i, j, k)) / dzk;
-        }
+        if (a.visc)
+            r -= (a.t11[c] - a.t11[c + ox[2]]) * a.idx + (a.t12[c + oy[4]] - a.t12[c]) * a.idy +
+                 (a.t13[c + P] - a.t13[c]) * idz;
         a.Ru[c] = r;
     }
 
     // ---------------- y-momentum on y-face (i, j, k) ----------------
     {
-        double Vc = a.rv[c];
-        double br = 0.5 * (Vc + a.rv[cidx(d, i, jp, k)]);
-        double bl = 0.5 * (a.rv[cidx(d, i, jm, k)] + Vc);
-        double fyy_r = br * interp_y(a.v, d, i, j + 1, k, oh, sign_of(br));
-        double fyy_l = bl * interp_y(a.v, d, i, j, k, oh, sign_of(bl));
-        double a0 = 0.5 * (a.ru[cidx(d, i, jm, k)] + a.ru[c]);
-        double a1 = 0.5 * (a.ru[cidx(d, ip, jm, k)] + a.ru[cidx(d, ip, j, k)]);
-        double fyx0 = a0 * interp_x(a.v, d, i, j, k, oh, sign_of(a0));
-        double fyx1 = a1 * interp_x(a.v, d, i + 1, j, k, oh, sign_of(a1));
+        const double Vs = a.rv[c + oy[2]];
+        const double br = 0.5 * (V0 + V1), bl = 0.5 * (Vs + V0);
+        const double *v = a.v;
+#pragma unroll
+        for (int t = 0; t < 7; ++t) q[t] = v[c + oy[t]];
+        const double fyy_r = br * interp<OH>(oh, q, 1, sign_of(br)), fyy_l = bl * interp<OH>(oh, q, 0, sign_of(bl));
+        const double Us = a.ru[c + oy[2]], Use = a.ru[c + oy[2] + ox[4]];
+        const double a0 = 0.5 * (Us + U0), a1 = 0.5 * (Use + U1);
+#pragma unroll
+        for (int t = 0; t < 7; ++t) q[t] = v[c + ox[t]];
+        const double fyx0 = a0 * interp<OH>(oh, q, 0, sign_of(a0)), fyx1 = a1 * interp<OH>(oh, q, 1, sign_of(a1));
+#pragma unroll
+        for (int t = 0; t < 7; ++t) q[t] = v[c + ozc[t]];
         double fyz0 = 0.0, fyz1 = 0.0;
         if (k > 0) {
-            double e0 = 0.5 * (a.rw[cidx(d, i, jm, k)] + a.rw[c]);
-            fyz0 = e0 * interp_zc(a.v, d, i, j, k, ov, sign_of(e0));
+            const double e0 = 0.5 * (a.rw[c + oy[2]] + W0);
+            fyz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0));
         }
         if (k < nz - 1) {
-            double e1 = 0.5 * (a.rw[cidx(d, i, jm, k + 1)] + a.rw[c + d.nxy]);
-            fyz1 = e1 * interp_zc(a.v, d, i, j, k + 1, ov, sign_of(e1));
+            const double e1 = 0.5 * (a.rw[c + oy[2] + P] + W1);
+            fyz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1));
         }
-        double adv = (fyx1 - fyx0) / a.dx + (fyy_r - fyy_l) / a.dy + (fyz1 - fyz0) / dzk;
-        double pgf = (a.pp[c] - a.pp[cidx(d, i, jm, k)]) / a.dy;
-        double rho_f = 0.5 * (a.rho[cidx(d, i, jm, k)] + a.rho[c]);
-        double ubar = 0.25 * (a.ru[cidx(d, i, jm, k)] + a.ru[cidx(d, ip, jm, k)] + a.ru[c] + a.ru[cidx(d, ip, j, k)]);
+        const double adv = (fyx1 - fyx0) * a.idx + (fyy_r - fyy_l) * a.idy + (fyz1 - fyz0) * idz;
+        const double pgf = (a.pp[c] - a.pp[c + oy[2]]) * a.idy;
+        const double rho_f = 0.5 * (a.rho[c + oy[2]] + a.rho[c]);
+        const double ubar = 0.25 * (Us + Use + U0 + U1);
         double r = -adv - pgf - a.f * (ubar - rho_f * a.Ug);
-        if (visc) {
-            double t11c, t22c, t33c, t11s, t22s, t33s;
-            tau_diag(a, i, j, k, t11c, t22c, t33c);
-            tau_diag(a, i, j - 1, k, t11s, t22s, t33s);
-            r -= (tau12(a, i + 1, j, k) - tau12(a, i, j, k)) / a.dx + (t22c - t22s) / a.dy +
-                 (tau23(a, i, j, k + 1) - tau23(a, i, j, k)) / dzk;
-        }
+        if (a.visc)
+            r -= (a.t12[c + ox[4]] - a.t12[c]) * a.idx + (a.t22[c] - a.t22[c + oy[2]]) * a.idy +
+                 (a.t23[c + P] - a.t23[c]) * idz;
         a.Rv[c] = r;
     }
 
     // ---------------- z-momentum on z-face (i, j, k) ----------------
     if (k == 0) {
         a.Rw[c] = 0.0;
-        a.Rw[c + nz * d.nxy] = 0.0;
+        a.Rw[c + nz * P] = 0.0;
     } else {
-        const int cm = c - d.nxy;
-        double dzf = 0.5 * (a.dz[k - 1] + dzk);
-        double a0 = 0.5 * (a.ru[cm] + a.ru[c]);
-        double a1 = 0.5 * (a.ru[cidx(d, ip, j, k - 1)] + a.ru[cidx(d, ip, j, k)]);
-        double fzx0 = a0 * interp_xw(a.w, d, i, j, k, oh, sign_of(a0));
-        double fzx1 = a1 * interp_xw(a.w, d, i + 1, j, k, oh, sign_of(a1));
-        double b0 = 0.5 * (a.rv[cm] + a.rv[c]);
-        double b1 = 0.5 * (a.rv[cidx(d, i, jp, k - 1)] + a.rv[cidx(d, i, jp, k)]);
-        double fzy0 = b0 * interp_yw(a.w, d, i, j, k, oh, sign_of(b0));
-        double fzy1 = b1 * interp_yw(a.w, d, i, j + 1, k, oh, sign_of(b1));
-        double eu = 0.5 * (a.rw[c] + a.rw[c + d.nxy]);
-        double ed = 0.5 * (a.rw[cm] + a.rw[c]);
-        double fzz_u = eu * interp_zw(a.w, d, i, j, k + 1, ov, sign_of(eu));
-        double fzz_d = ed * interp_zw(a.w, d, i, j, k, ov, sign_of(ed));
-        double adv = (fzx1 - fzx0) / a.dx + (fzy1 - fzy0) / a.dy + (fzz_u - fzz_d) / dzf;
-        double pgf = (a.pp[c] - a.pp[cm]) / dzf;
+        const int cm = c - P;
+        const double idzf = a.idzf[k];
+        const double a0 = 0.5 * (a.ru[cm] + U0), a1 = 0.5 * (a.ru[cm + ox[4]] + U1);
+        const double *w = a.w;
+#pragma unroll
+        for (int t = 0; t < 7; ++t) q[t] = w[c + ox[t]];
+        const double fzx0 = a0 * interp<OH>(oh, q, 0, sign_of(a0)), fzx1 = a1 * interp<OH>(oh, q, 1, sign_of(a1));
+        const double b0 = 0.5 * (a.rv[cm] + V0), b1 = 0.5 * (a.rv[cm + oy[4]] + V1);
+#pragma unroll
+        for (int t = 0; t < 7; ++t) q[t] = w[c + oy[t]];
+        const double fzy0 = b0 * interp<OH>(oh, q, 0, sign_of(b0)), fzy1 = b1 * interp<OH>(oh, q, 1, sign_of(b1));
+        const double eu = 0.5 * (W0 + W1), ed = 0.5 * (a.rw[cm] + W0);
+#pragma unroll
+        for (int t = 0; t < 7; ++t) q[t] = szw[t] * w[c + ozw[t]];
+        const double fzz_u = eu * interp<OV>(ov, q, 1, sign_of(eu)), fzz_d = ed * interp<OV>(ov, q, 0, sign_of(ed));
+        const double adv = (fzx1 - fzx0) * a.idx + (fzy1 - fzy0) * a.idy + (fzz_u - fzz_d) * idzf;
+        const double pgf = (a.pp[c] - a.pp[cm]) * idzf;
         // buoyancy B = -(rho - rho0) g on the face; heavier air sinks
-        double buoy = -a.g * 0.5 * ((a.rho[c] - a.rho0[k]) + (a.rho[cm] - a.rho0[k - 1]));
+        const double buoy = -a.g * 0.5 * ((a.rho[c] - a.rho0[k]) + (a.rho[cm] - a.rho0[k - 1]));
         double r = -adv - pgf + buoy;
-        if (visc) {
-            double t11c, t22c, t33c, t11b, t22b, t33b;
-            tau_diag(a, i, j, k, t11c, t22c, t33c);
-            tau_diag(a, i, j, k - 1, t11b, t22b, t33b);
-            r -= (tau13(a, i + 1, j, k) - tau13(a, i, j, k)) / a.dx + (tau23(a, i, j + 1, k) - tau23(a, i, j, k)) / a.dy +
-                 (t33c - t33b) / dzf;
-        }
+        if (a.visc)
+            r -= (a.t13[c + ox[4]] - a.t13[c]) * a.idx + (a.t23[c + oy[4]] - a.t23[c]) * a.idy +
+                 (a.t33[c] - a.t33[cm]) * idzf;
         a.Rw[c] = r;
     }
 }
@@ -355,6 +359,7 @@ hipError_t launch_slow_rhs(erf_ctx *cx, const double *rho, const double *rt, con
                            double *Rv, double *Rw)
 {
     const erf_params &p = cx->prm;
+    Workspace &ws = cx->ws;
     RhsArgs a{};
     a.d = cx->d;
     a.dx = cx->grid.dx;
@@ -362,9 +367,12 @@ hipError_t launch_slow_rhs(erf_ctx *cx, const double *rho, const double *rt, con
     a.idx = 1.0 / a.dx;
     a.idy = 1.0 / a.dy;
     a.dz = cx->base.dz;
+    a.idz = cx->base.idz();
+    a.idzf = cx->base.idzf();
     a.oh = p.adv_order_h;
     a.ov = p.adv_order_v;
     a.sgs = p.sgs;
+    a.visc = (p.sgs != 0 || p.nu_m != 0.0 || p.alpha_m != 0.0) ? 1 : 0;
     a.Cs = p.Cs;
     a.Pr_t = p.Pr_t;
     a.nu = p.nu_m;
@@ -382,12 +390,19 @@ hipError_t launch_slow_rhs(erf_ctx *cx, const double *rho, const double *rt, con
     a.rho0 = cx->base.rho0;
     a.Theta0 = cx->base.Theta0;
     a.p0 = cx->base.p0;
-    a.th = cx->ws.th;
-    a.pp = cx->ws.pp;
-    a.u = cx->ws.u;
-    a.v = cx->ws.v;
-    a.w = cx->ws.w;
-    a.mut = cx->ws.mut;
+    a.th = ws.th;
+    a.pp = ws.pp;
+    a.u = ws.u;
+    a.v = ws.v;
+    a.w = ws.w;
+    a.mut = ws.mut;
+    a.t11 = ws.tau[0];
+    a.t22 = ws.tau[1];
+    a.t33 = ws.tau[2];
+    a.t12 = ws.tau[3];
+    a.t13 = ws.tau[4];
+    a.t23 = ws.tau[5];
+    a.kap = ws.kap;
     a.Rr = Rr;
     a.Rt = Rt;
     a.Ru = Ru;
@@ -395,9 +410,20 @@ hipError_t launch_slow_rhs(erf_ctx *cx, const double *rho, const double *rt, con
     a.Rw = Rw;
     const Dims &d = cx->d;
     dim3 blk(64, 4, 1), grd((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz);
+    dim3 grdw((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz + 1);
     timing_start(cx, K_PREP); hipLaunchKernelGGL(k_prep, grd, blk, 0, cx->stream, a); timing_stop(cx, K_PREP);
     if (p.sgs) { timing_start(cx, K_MUT); hipLaunchKernelGGL(k_mut, grd, blk, 0, cx->stream, a); timing_stop(cx, K_MUT); }
-    timing_start(cx, K_RHS); hipLaunchKernelGGL(k_rhs, grd, blk, 0, cx->stream, a); timing_stop(cx, K_RHS);
+    if (a.visc) { timing_start(cx, K_STRESS); hipLaunchKernelGGL(k_stress, grdw, blk, 0, cx->stream, a); timing_stop(cx, K_STRESS); }
+    timing_start(cx, K_RHS);
+    if (a.oh == 5 && a.ov == 5)
+        hipLaunchKernelGGL((k_rhs<5, 5>), grd, blk, 0, cx->stream, a);
+    else if (a.oh == 3 && a.ov == 3)
+        hipLaunchKernelGGL((k_rhs<3, 3>), grd, blk, 0, cx->stream, a);
+    else if (a.oh == 2 && a.ov == 2)
+        hipLaunchKernelGGL((k_rhs<2, 2>), grd, blk, 0, cx->stream, a);
+    else
+        hipLaunchKernelGGL((k_rhs<0, 0>), grd, blk, 0, cx->stream, a);
+    timing_stop(cx, K_RHS);
     return hipGetLastError();
 }
 
