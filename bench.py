@@ -37,27 +37,36 @@ from paper_2412_04395_amd import workloads as W  # noqa: E402
 METRIC = "cell-updates/s per RK3 step (incl. acoustic substeps), % HBM roofline, FP64 vs FP32"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
-# Compulsory (algorithmic) FP64 values moved per cell by one launch of each
-# kernel: every distinct input field read once and every output written once.
-# n_s-independent; 'sgs' adds the eddy-viscosity field where it is read.
+# Compulsory (algorithmic) values moved per cell by one launch of each kernel:
+# every distinct input field read once and every output written once.
+# (bulk values, FP64 values): bulk fields are stored in the run's precision
+# (8 B in FP64, 4 B in FP32); the tridiagonal factors are always FP64.
+# 'sgs' = 1 adds the fields only viscous runs touch.
 KERNEL_VALUES = {
-    # rho, U, V, W, theta, p', u, v, w read (+ 6 stresses and the diffusivity
-    # in viscous runs); 5 tendencies written
-    "rhs": lambda sgs: 9 + 7 * sgs + 5,
-    # u, v, w, rho, mu_t read; 6 stresses and the diffusivity written
-    "stress": lambda sgs: 5 + 7,
+    # rho, U, V, W, theta, p', u, v, w read (+ 6 stresses and the diffusivity); 5 tendencies written
+    "rhs": lambda sgs: (9 + 7 * sgs + 5, 0),
     # rho, Theta, U, V, W read; theta, p', u, v, w written
-    "prep": lambda sgs: 5 + 5,
+    "prep": lambda sgs: (5 + 5, 0),
     # rho, u, v, w read; mu_t written
-    "mut": lambda sgs: 4 + 1,
-    # one fused substep: Theta'' (two levels), U'', V'', rho'', W'' and the five
-    # tendencies read, theta^t and Exner (frozen) and four tridiagonal
-    # coefficient fields read; Theta''_new, U'', V'', rho'', W'' written
-    "substep": lambda sgs: 7 + 5 + 2 + 4 + 5,
-    "stage_init": lambda sgs: 12 + 11,
-    "coef": lambda sgs: 4 + 5,
-    "finalize": lambda sgs: 14 + 8,
+    "mut": lambda sgs: (4 + 1, 0),
+    # u, v, w, rho, mu_t read; 6 stresses and the diffusivity written
+    "stress": lambda sgs: (5 + 7, 0),
+    # one fused substep: Theta'' (two levels), U'', V'', rho'', W'', the five
+    # tendencies, theta^t, Exner and the buoyancy coefficient read, the three
+    # Thomas factors read; Theta'', U'', V'', rho'', W'' written
+    "substep": lambda sgs: (14 + 5, 3),
+    # S^n, S^t read; theta^t, Exner, Theta'', rho'', U'', V'', W'' written
+    "stage_init": lambda sgs: (10 + 7, 0),
+    # Exner, theta^t, Theta^t read; buoyancy coefficient and three factors written
+    "coef": lambda sgs: (3 + 1, 3),
+    # S^t and S'' read; S_out written
+    "finalize": lambda sgs: (10 + 5, 0),
 }
+
+
+def _kernel_bytes(kernel: str, sgs: int, prec: str) -> float:
+    bulk, f64 = KERNEL_VALUES[kernel](sgs)
+    return bulk * (8.0 if prec == "fp64" else 4.0) + f64 * 8.0
 
 
 def _profiled_traffic(kernel: str):
@@ -82,6 +91,8 @@ def _cfg(workload: str) -> W.Config:
         return W.cbl(n_substeps=14, name="cbl@stable_ns14")
     if workload == "cbl_as_stated":
         return W.cbl(n_substeps=6, name="cbl@as_stated_ns6")
+    if workload == "cbl_fp32":
+        return W.cbl(n_substeps=14, name="cbl@stable_ns14", prec="fp32")
     if workload == "bubble2d":
         return W.bubble2d()
     raise SystemExit(f"unknown workload {workload}")
@@ -107,7 +118,7 @@ def run_gpu(cfg: W.Config, steps: int, warmup: int):
     s = erf.Solver(cfg)
     th0 = W.theta_sounding(cfg)
     b = s.init_base_state(th0)
-    S = s.to_device(W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"]))
+    S = s.from_full(W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"]))
     for _ in range(warmup):
         s.rk3_step(S)
     # find the kernel with the largest share of a step (one short timed step per kernel)
@@ -148,6 +159,18 @@ def cpu_baseline(cfg: W.Config, target_s: float = 15.0):
                       f"{el:.1f} s"}
 
 
+def _roofline(cfg, dom, kms, kn):
+    sgs = 1 if cfg.sgs else 0
+    avg_ms = kms / max(kn, 1)
+    bytes_per_launch = _kernel_bytes(dom, sgs, cfg.prec) * cfg.cells
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic, tsrc = _profiled_traffic(dom) if cfg.prec == "fp64" and "stable" in cfg.name else (None, None)
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": tsrc,
+            "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_ms, 4),
+            "launches_timed": kn}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +179,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="cbl")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-as-stated", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first run one plain device copy of this many GiB (reference for HBM counters)")
     a = ap.parse_args(argv)
@@ -177,15 +201,7 @@ def main(argv=None):
         del src, dst
     el, dom, kms, kn, shares, diag = run_gpu(cfg, a.steps, a.warmup)
     value = cfg.cells * a.steps / el
-    sgs = 1 if cfg.sgs else 0
-    avg_ms = kms / max(kn, 1)
-    bytes_per_launch = KERNEL_VALUES[dom](sgs) * 8.0 * cfg.cells
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic, tsrc = _profiled_traffic(dom) if cfg.prec == "fp64" and "stable" in cfg.name else (None, None)
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": tsrc,
-            "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_ms, 4),
-            "launches_timed": kn}
+    roof = _roofline(cfg, dom, kms, kn)
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": 1e3 * el / a.steps, "higher_is_better": True, "scaling": "weak",
@@ -203,6 +219,13 @@ def main(argv=None):
         out["as_stated"] = {"workload": c2.name, "value": c2.cells * a.steps / el2,
                             "ms_per_step": 1e3 * el2 / a.steps, "note": "diverges in the first step (acoustic "
                             "CFL); timed for throughput only"}
+    if a.workload == "cbl" and not a.no_fp32:
+        c3 = _cfg("cbl_fp32")
+        el3, dom3, kms3, kn3, shares3, _ = run_gpu(c3, a.steps, a.warmup)
+        out["fp32"] = {"workload": c3.name, "precision": "FP32 storage, FP64 arithmetic, solve and sums",
+                       "value": c3.cells * a.steps / el3, "ms_per_step": 1e3 * el3 / a.steps,
+                       "speedup_vs_fp64": el / el3, "roofline": _roofline(c3, dom3, kms3, kn3),
+                       "kernel_ms_per_step": {k: round(v[0], 4) for k, v in shares3.items()}}
     if rank == 0 and not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     if rank == 0:

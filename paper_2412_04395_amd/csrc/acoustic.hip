@@ -1,5 +1,7 @@
 // acoustic.hip -- one RK stage of semi-implicit acoustic substepping (App. C of
-// the ERF paper, Sec. 3.1), FP64.
+// the ERF paper, Sec. 3.1).  Bulk fields are stored as T (double, or float with
+// rho and rho*theta as perturbations about the base state); all arithmetic,
+// the tridiagonal factors and the Thomas sweeps are double.
 //
 // Kernels of one stage:
 //   k_stage_init  S'' = S^n - S^t, frozen theta^t and Exner pi^t, zero sums
@@ -42,28 +44,32 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks)
     return x * q + (x < r ? x : r) + m;
 }
 
+template <typename T>
 struct StageArgs {
     Dims d;
     double dx, dy;
     const double *dz, *idz, *idzf;
     double g, b1, b2, bd, dtau;
-    const double *rho0, *pi0;
+    const double *rho0, *pi0, *Theta0;
     // S^n, S^t, R^t
-    const double *n_r, *n_t, *n_u, *n_v, *n_w;
-    const double *t_r, *t_t, *t_u, *t_v, *t_w;
-    const double *R_r, *R_t, *R_u, *R_v, *R_w;
+    const T *n_r, *n_t, *n_u, *n_v, *n_w;
+    const T *t_r, *t_t, *t_u, *t_v, *t_w;
+    const T *R_r, *R_t, *R_u, *R_v, *R_w;
     // frozen fields
-    double *tht, *pit;
+    T *tht, *pit;
     // perturbations (Theta'' three levels, U'' and V'' double-buffered) and sums
-    double *T2cur, *T2prv, *T2nxt, *r2, *u2in, *u2out, *v2in, *v2out, *w2, *su, *sv, *sw;
+    T *T2cur, *T2prv, *T2nxt, *r2, *u2in, *u2out, *v2in, *v2out, *w2, *su, *sv, *sw;
     int sums;
-    // coefficients on z-faces: alpha_k = a_k / den_k, m_k = 1 / den_k, c'_k, C_k
-    double *calpha, *cm, *cc, *cC;
+    // coefficients on z-faces: C_k (bulk precision); alpha_k = a_k / den_k,
+    // m_k = 1 / den_k, c'_k (double)
+    T *cC;
+    double *calpha, *cm, *cc;
     // tiles
     int TX, TY, ntx, nty;
 };
 
-__global__ __launch_bounds__(256) void k_stage_init(StageArgs a)
+template <typename T>
+__global__ __launch_bounds__(256) void k_stage_init(StageArgs<T> a)
 {
     const Dims &d = a.d;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -71,16 +77,22 @@ __global__ __launch_bounds__(256) void k_stage_init(StageArgs a)
     int k = blockIdx.z;  // 0..nz (the extra plane handles the top z-face)
     if (i >= d.nx || j >= d.ny) return;
     int c = cidx(d, i, j, k);
-    a.w2[c] = a.n_w[c] - a.t_w[c];
+    a.w2[c] = (double)a.n_w[c] - (double)a.t_w[c];
     if (a.sums) a.sw[c] = 0.0;
     if (k == d.nz) return;
-    double Tt = a.t_t[c];
-    a.tht[c] = Tt / a.t_r[c];
-    a.pit[c] = pow(kRd * Tt / kP00, kGamma - 1.0);
-    a.T2cur[c] = a.n_t[c] - Tt;
-    a.r2[c] = a.n_r[c] - a.t_r[c];
-    a.u2in[c] = a.n_u[c] - a.t_u[c];
-    a.v2in[c] = a.n_v[c] - a.t_v[c];
+    const double T0 = a.Theta0[k];
+    const double Tt = full_of(a.t_t, c, T0);
+    a.tht[c] = Tt / full_of(a.t_r, c, a.rho0[k]);
+    // Exner function of the stage state: (R_d Theta / P00)^(gamma - 1); from
+    // the perturbation in FP32 storage, pi0 (1 + Theta'/Theta0)^(gamma - 1)
+    if constexpr (kPert<T>)
+        a.pit[c] = a.pi0[k] * exp((kGamma - 1.0) * log1p((double)a.t_t[c] / T0));
+    else
+        a.pit[c] = pow(kRd * Tt / kP00, kGamma - 1.0);
+    a.T2cur[c] = (double)a.n_t[c] - (double)a.t_t[c];
+    a.r2[c] = (double)a.n_r[c] - (double)a.t_r[c];
+    a.u2in[c] = (double)a.n_u[c] - (double)a.t_u[c];
+    a.v2in[c] = (double)a.n_v[c] - (double)a.t_v[c];
     if (a.sums) {
         a.su[c] = 0.0;
         a.sv[c] = 0.0;
@@ -88,10 +100,11 @@ __global__ __launch_bounds__(256) void k_stage_init(StageArgs a)
 }
 
 // theta^t on z-face k of a column (lid faces carry W = 0; value unused)
-__device__ __forceinline__ double thz(const StageArgs &a, int col, int k)
+template <typename T>
+__device__ __forceinline__ double thz(const StageArgs<T> &a, int col, int k)
 {
     if (k <= 0 || k >= a.d.nz) return 0.0;
-    return 0.5 * (a.tht[col + (k - 1) * a.d.nxy] + a.tht[col + k * a.d.nxy]);
+    return 0.5 * ((double)a.tht[col + (k - 1) * a.d.nxy] + (double)a.tht[col + k * a.d.nxy]);
 }
 
 // Tridiagonal rows for W'' at interior faces k = 1..nz-1.  Substituting
@@ -99,7 +112,8 @@ __device__ __forceinline__ double thz(const StageArgs &a, int col, int k)
 // dtau b2 delta_z(W)/dz into the W'' equation of App. C couples W_{k-1}, W_k,
 // W_{k+1} with coefficients of the frozen state only.  Factorised here (Thomas,
 // no pivoting; the rows are diagonally dominant).
-__global__ __launch_bounds__(256) void k_coef(StageArgs a)
+template <typename T>
+__global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
 {
     const Dims &d = a.d;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -111,10 +125,10 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs a)
     for (int k = 1; k < nz; ++k) {
         int c = col + k * nxy, cm = c - nxy;
         double dzf = 0.5 * (a.dz[k - 1] + a.dz[k]);
-        double pif = 0.5 * (a.pit[cm] + a.pit[c]);
+        double pif = 0.5 * ((double)a.pit[cm] + (double)a.pit[c]);
         double A = kGamma * kRd * pif;
         double C = g * 0.5 * (a.rho0[k - 1] + a.rho0[k]) * (kRd / kCv) * (pif / (0.5 * (a.pi0[k - 1] + a.pi0[k]))) /
-                   (0.5 * (a.t_t[cm] + a.t_t[c]));
+                   (0.5 * (full_of(a.t_t, cm, a.Theta0[k - 1]) + full_of(a.t_t, c, a.Theta0[k])));
         double idzm = 1.0 / a.dz[k - 1], idz = 1.0 / a.dz[k];
         double tfm = thz(a, col, k - 1), tf = thz(a, col, k), tfp = thz(a, col, k + 1);
         double lo = (k == 1) ? 0.0 : -D * (A * tfm * idzm / dzf + 0.5 * C * tfm * idzm - 0.5 * g * idzm);
@@ -134,8 +148,8 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs a)
 // One fused acoustic substep.  blockDim = (64, KG), kLevels levels per
 // wavefront; dynamic LDS holds the (nz + 1) x 64 solve buffer and the
 // chunk-boundary values.
-template <int kLevels>
-__global__ __launch_bounds__(1024) void k_substep(StageArgs a)
+template <typename T, int kLevels>
+__global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
 {
     extern __shared__ double lds[];
     const Dims &d = a.d;
@@ -347,19 +361,23 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs a)
     }
 }
 
+template <typename T>
 struct FinArgs {
     Dims d;
     int n_sub;
     double b1;
-    const double *t_r, *t_t, *t_u, *t_v, *t_w, *n_w;
-    const double *T2, *r2, *u2, *v2, *w2, *su, *sv, *sw;
-    double *o_r, *o_t, *o_u, *o_v, *o_w, *Fu, *Fv, *Fw;
+    const T *t_r, *t_t, *t_u, *t_v, *t_w, *n_w;
+    const T *T2, *r2, *u2, *v2, *w2, *su, *sv, *sw;
+    T *o_r, *o_t, *o_u, *o_v, *o_w, *Fu, *Fv, *Fw;
 };
 
 // S_out = S^t + S''; stage-averaged momenta.  The W-sum accumulated only the
 // new W'' of each substep; the beta-weighted average over substeps is
 // b1 W''_0 + W''_1 + ... + W''_{N-1} + b2 W''_N = sum_{s=1..N} W''_s + b1 (W''_0 - W''_N).
-__global__ __launch_bounds__(256) void k_finalize(FinArgs a)
+// In both storages S^t and S'' are added as stored: full + perturbation in FP64,
+// perturbation about the base state + perturbation in FP32.
+template <typename T>
+__global__ __launch_bounds__(256) void k_finalize(FinArgs<T> a)
 {
     const Dims &d = a.d;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -370,29 +388,38 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs a)
     double inv = 1.0 / a.n_sub;
     double wt = a.t_w[c], wN = a.w2[c];
     if (a.Fw) {
-        double w0 = a.n_w[c] - wt;
-        a.Fw[c] = wt + (a.sw[c] + a.b1 * (w0 - wN)) * inv;
+        double w0 = (double)a.n_w[c] - wt;
+        a.Fw[c] = wt + ((double)a.sw[c] + a.b1 * (w0 - wN)) * inv;
     }
     a.o_w[c] = wt + wN;
     if (k == d.nz) return;
-    a.o_r[c] = a.t_r[c] + a.r2[c];
-    a.o_t[c] = a.t_t[c] + a.T2[c];
+    a.o_r[c] = (double)a.t_r[c] + (double)a.r2[c];
+    a.o_t[c] = (double)a.t_t[c] + (double)a.T2[c];
     double ut = a.t_u[c], vt = a.t_v[c];
-    a.o_u[c] = ut + a.u2[c];
-    a.o_v[c] = vt + a.v2[c];
-    if (a.Fu) a.Fu[c] = ut + a.su[c] * inv;
-    if (a.Fv) a.Fv[c] = vt + a.sv[c] * inv;
+    a.o_u[c] = ut + (double)a.u2[c];
+    a.o_v[c] = vt + (double)a.v2[c];
+    if (a.Fu) a.Fu[c] = ut + (double)a.su[c] * inv;
+    if (a.Fv) a.Fv[c] = vt + (double)a.sv[c] * inv;
 }
 
 }  // namespace
 
-hipError_t launch_acoustic_stage(erf_ctx *cx, const double *const Sn[5], const double *const St[5],
-                                 const double *const Rt[5], int n_sub, double dtau,
-                                 double *const Sout[5], double *Fu, double *Fv, double *Fw)
+namespace {
+template <typename T>
+hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const St_[5], const void *const Rt_[5],
+                      int n_sub, double dtau, void *const Sout_[5], T *Fu, T *Fv, T *Fw)
 {
+    const T *Sn[5], *St[5], *Rt[5];
+    T *Sout[5];
+    for (int f = 0; f < 5; ++f) {
+        Sn[f] = (const T *)Sn_[f];
+        St[f] = (const T *)St_[f];
+        Rt[f] = (const T *)Rt_[f];
+        Sout[f] = (T *)Sout_[f];
+    }
     const Dims &d = cx->d;
     Workspace &w = cx->ws;
-    StageArgs a{};
+    StageArgs<T> a{};
     a.d = d;
     a.dx = cx->grid.dx;
     a.dy = cx->grid.dy;
@@ -405,21 +432,22 @@ hipError_t launch_acoustic_stage(erf_ctx *cx, const double *const Sn[5], const d
     a.dtau = dtau;
     a.rho0 = cx->base.rho0;
     a.pi0 = cx->base.pi0;
+    a.Theta0 = cx->base.Theta0;
     a.n_r = Sn[0]; a.n_t = Sn[1]; a.n_u = Sn[2]; a.n_v = Sn[3]; a.n_w = Sn[4];
     a.t_r = St[0]; a.t_t = St[1]; a.t_u = St[2]; a.t_v = St[3]; a.t_w = St[4];
     a.R_r = Rt[0]; a.R_t = Rt[1]; a.R_u = Rt[2]; a.R_v = Rt[3]; a.R_w = Rt[4];
-    a.tht = w.th;
-    a.pit = w.pit;
-    a.r2 = w.r2;
-    a.w2 = w.w2;
-    a.su = w.su;
-    a.sv = w.sv;
-    a.sw = w.sw;
+    a.tht = (T *)w.th;
+    a.pit = (T *)w.pit;
+    a.r2 = (T *)w.r2;
+    a.w2 = (T *)w.w2;
+    a.su = (T *)w.su;
+    a.sv = (T *)w.sv;
+    a.sw = (T *)w.sw;
     a.sums = (Fu || Fv || Fw) ? 1 : 0;
     a.calpha = w.ca;
     a.cm = w.cb;
     a.cc = w.cc;
-    a.cC = w.cC;
+    a.cC = (T *)w.cC;
     // tile shape: 64 columns, four rows when the domain has them
     a.TY = d.ny >= 4 ? 4 : (d.ny >= 2 ? 2 : 1);
     a.TX = kLanes / a.TY;
@@ -430,12 +458,14 @@ hipError_t launch_acoustic_stage(erf_ctx *cx, const double *const Sn[5], const d
     const int KG = (d.nz + L - 1) / L;
     if (KG > 16) return hipErrorInvalidValue;  // nz <= 256
     const size_t lds = sizeof(double) * ((size_t)(d.nz + 1) * kLanes + 2 * (size_t)KG * kLanes);
-    const void *kfn = L == 8 ? (const void *)k_substep<8> : (const void *)k_substep<16>;
+    const void *kfn = L == 8 ? (const void *)k_substep<T, 8> : (const void *)k_substep<T, 16>;
 
     int t_cur = 0, t_prv = 2, u_in = 0;  // Theta'' rotates over 3 buffers, U'' and V'' over 2
-    a.T2cur = w.t2[0];
-    a.u2in = w.u2[0];
-    a.v2in = w.v2[0];
+    T *t2[3] = {(T *)w.t2[0], (T *)w.t2[1], (T *)w.t2[2]};
+    T *u2[2] = {(T *)w.u2[0], (T *)w.u2[1]}, *v2[2] = {(T *)w.v2[0], (T *)w.v2[1]};
+    a.T2cur = t2[0];
+    a.u2in = u2[0];
+    a.v2in = v2[0];
 
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -444,39 +474,49 @@ hipError_t launch_acoustic_stage(erf_ctx *cx, const double *const Sn[5], const d
     dim3 blk(64, 4, 1);
     dim3 g3w((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz + 1);
     dim3 g2((d.nx + 63) / 64, (d.ny + 3) / 4, 1);
-    timing_start(cx, K_STAGE_INIT); hipLaunchKernelGGL(k_stage_init, g3w, blk, 0, cx->stream, a); timing_stop(cx, K_STAGE_INIT);
-    timing_start(cx, K_COEF); hipLaunchKernelGGL(k_coef, g2, blk, 0, cx->stream, a); timing_stop(cx, K_COEF);
+    timing_start(cx, K_STAGE_INIT); hipLaunchKernelGGL(k_stage_init<T>, g3w, blk, 0, cx->stream, a); timing_stop(cx, K_STAGE_INIT);
+    timing_start(cx, K_COEF); hipLaunchKernelGGL(k_coef<T>, g2, blk, 0, cx->stream, a); timing_stop(cx, K_COEF);
     for (int s = 0; s < n_sub; ++s) {
         const int t_nxt = 3 - t_cur - t_prv;
-        a.T2cur = w.t2[t_cur];
-        a.T2prv = (s == 0) ? w.t2[t_cur] : w.t2[t_prv];
-        a.T2nxt = w.t2[t_nxt];
-        a.u2in = w.u2[u_in];
-        a.u2out = w.u2[u_in ^ 1];
-        a.v2in = w.v2[u_in];
-        a.v2out = w.v2[u_in ^ 1];
+        a.T2cur = t2[t_cur];
+        a.T2prv = (s == 0) ? t2[t_cur] : t2[t_prv];
+        a.T2nxt = t2[t_nxt];
+        a.u2in = u2[u_in];
+        a.u2out = u2[u_in ^ 1];
+        a.v2in = v2[u_in];
+        a.v2out = v2[u_in ^ 1];
         a.bd = (s == 0) ? 0.0 : cx->prm.beta_d;
         timing_start(cx, K_SUBSTEP);
         if (L == 8)
-            hipLaunchKernelGGL(k_substep<8>, dim3(a.ntx * a.nty), dim3(kLanes, KG), lds, cx->stream, a);
+            hipLaunchKernelGGL((k_substep<T, 8>), dim3(a.ntx * a.nty), dim3(kLanes, KG), lds, cx->stream, a);
         else
-            hipLaunchKernelGGL(k_substep<16>, dim3(a.ntx * a.nty), dim3(kLanes, KG), lds, cx->stream, a);
+            hipLaunchKernelGGL((k_substep<T, 16>), dim3(a.ntx * a.nty), dim3(kLanes, KG), lds, cx->stream, a);
         timing_stop(cx, K_SUBSTEP);
         t_prv = t_cur;
         t_cur = t_nxt;
         u_in ^= 1;
     }
-    FinArgs f{};
+    FinArgs<T> f{};
     f.d = d;
     f.n_sub = n_sub;
     f.b1 = a.b1;
     f.t_r = St[0]; f.t_t = St[1]; f.t_u = St[2]; f.t_v = St[3]; f.t_w = St[4]; f.n_w = Sn[4];
-    f.T2 = w.t2[t_cur]; f.r2 = w.r2; f.u2 = w.u2[u_in]; f.v2 = w.v2[u_in]; f.w2 = w.w2;
-    f.su = w.su; f.sv = w.sv; f.sw = w.sw;
+    f.T2 = t2[t_cur]; f.r2 = (T *)w.r2; f.u2 = u2[u_in]; f.v2 = v2[u_in]; f.w2 = (T *)w.w2;
+    f.su = (T *)w.su; f.sv = (T *)w.sv; f.sw = (T *)w.sw;
     f.o_r = Sout[0]; f.o_t = Sout[1]; f.o_u = Sout[2]; f.o_v = Sout[3]; f.o_w = Sout[4];
     f.Fu = Fu; f.Fv = Fv; f.Fw = Fw;
-    timing_start(cx, K_FINALIZE); hipLaunchKernelGGL(k_finalize, g3w, blk, 0, cx->stream, f); timing_stop(cx, K_FINALIZE);
+    timing_start(cx, K_FINALIZE); hipLaunchKernelGGL(k_finalize<T>, g3w, blk, 0, cx->stream, f); timing_stop(cx, K_FINALIZE);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_acoustic_stage(erf_ctx *cx, const void *const Sn[5], const void *const St[5],
+                                 const void *const Rt[5], int n_sub, double dtau, void *const Sout[5],
+                                 void *Fu, void *Fv, void *Fw)
+{
+    if (cx->prm.precision == ERF_FP32_MIXED)
+        return acoustic_t<float>(cx, Sn, St, Rt, n_sub, dtau, Sout, (float *)Fu, (float *)Fv, (float *)Fw);
+    return acoustic_t<double>(cx, Sn, St, Rt, n_sub, dtau, Sout, (double *)Fu, (double *)Fv, (double *)Fw);
 }
 
 }  // namespace erfk

@@ -106,7 +106,7 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     if (nq < 0 || nq > 8) return ERF_E_ARG;
     if (prm->sgs != ERF_SGS_NONE && prm->sgs != ERF_SGS_SMAGORINSKY) return ERF_E_ARG;
     if (prm->scalar_scheme != ERF_SCALAR_INTERP && prm->scalar_scheme != ERF_SCALAR_WENO5) return ERF_E_ARG;
-    if (prm->precision != ERF_FP64) return ERF_E_UNSUPPORTED;
+    if (prm->precision != ERF_FP64 && prm->precision != ERF_FP32_MIXED) return ERF_E_ARG;
     if (nq > 0 && (prm->sgs != ERF_SGS_NONE || prm->alpha_m != 0.0)) return ERF_E_UNSUPPORTED;
     if (!(prm->dt > 0.0) || !(prm->beta_s >= 0.0 && prm->beta_s <= 1.0)) return ERF_E_ARG;
 
@@ -126,29 +126,32 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     c->grid.dz = c->dz_host;
     (void)hipGetDevice(&c->device);
 
-    // one arena for the whole workspace
+    // one arena for the whole workspace; bulk fields in the context's precision
     const size_t n = (size_t)c->d.n, w = (size_t)nw, q = (size_t)(nq > 0 ? nq : 0) * n;
-    struct Req { double **p; size_t count; };
+    const size_t es = prm->precision == ERF_FP32_MIXED ? sizeof(float) : sizeof(double);
+    struct Req { void **p; size_t bytes; };
     Workspace &ws = c->ws;
     Base &b = c->base;
+    const size_t N = n * es, Wb = w * es, Q = q * es, D = sizeof(double);
+    const size_t nzs = (size_t)grid->nz;
     Req reqs[] = {
-        {&ws.sa[0], n}, {&ws.sa[1], n}, {&ws.sa[2], n}, {&ws.sa[3], n}, {&ws.sa[4], w}, {&ws.sa[5], q},
-        {&ws.sb[0], n}, {&ws.sb[1], n}, {&ws.sb[2], n}, {&ws.sb[3], n}, {&ws.sb[4], w}, {&ws.sb[5], q},
-        {&ws.R[0], n}, {&ws.R[1], n}, {&ws.R[2], n}, {&ws.R[3], n}, {&ws.R[4], w},
-        {&ws.th, n}, {&ws.pp, n}, {&ws.pit, n}, {&ws.u, n}, {&ws.v, n}, {&ws.w, w}, {&ws.mut, n},
-        {&ws.tau[0], n}, {&ws.tau[1], n}, {&ws.tau[2], n}, {&ws.tau[3], n}, {&ws.tau[4], w}, {&ws.tau[5], w},
-        {&ws.kap, n},
-        {&ws.t2[0], n}, {&ws.t2[1], n}, {&ws.t2[2], n}, {&ws.r2, n}, {&ws.w2, w},
-        {&ws.u2[0], n}, {&ws.u2[1], n}, {&ws.v2[0], n}, {&ws.v2[1], n},
-        {&ws.su, n}, {&ws.sv, n}, {&ws.sw, w},
-        {&ws.ca, w}, {&ws.cb, w}, {&ws.cc, w}, {&ws.cC, w},
-        {&ws.q, q}, {&ws.fu, n}, {&ws.fv, n}, {&ws.fw, w},
-        {&ws.diag, diag_slots_needed()},
-        {&b.rho0, (size_t)grid->nz}, {&b.theta0, (size_t)grid->nz}, {&b.Theta0, (size_t)grid->nz},
-        {&b.p0, (size_t)grid->nz}, {&b.pi0, (size_t)grid->nz}, {&b.dz, 4 * (size_t)grid->nz + 1},
+        {&ws.sa[0], N}, {&ws.sa[1], N}, {&ws.sa[2], N}, {&ws.sa[3], N}, {&ws.sa[4], Wb}, {&ws.sa[5], Q},
+        {&ws.sb[0], N}, {&ws.sb[1], N}, {&ws.sb[2], N}, {&ws.sb[3], N}, {&ws.sb[4], Wb}, {&ws.sb[5], Q},
+        {&ws.R[0], N}, {&ws.R[1], N}, {&ws.R[2], N}, {&ws.R[3], N}, {&ws.R[4], Wb},
+        {&ws.th, N}, {&ws.pp, N}, {&ws.pit, N}, {&ws.u, N}, {&ws.v, N}, {&ws.w, Wb}, {&ws.mut, N},
+        {&ws.tau[0], N}, {&ws.tau[1], N}, {&ws.tau[2], N}, {&ws.tau[3], N}, {&ws.tau[4], Wb}, {&ws.tau[5], Wb},
+        {&ws.kap, N},
+        {&ws.t2[0], N}, {&ws.t2[1], N}, {&ws.t2[2], N}, {&ws.r2, N}, {&ws.w2, Wb},
+        {&ws.u2[0], N}, {&ws.u2[1], N}, {&ws.v2[0], N}, {&ws.v2[1], N},
+        {&ws.su, N}, {&ws.sv, N}, {&ws.sw, Wb},
+        {&ws.cC, Wb}, {(void **)&ws.ca, w * D}, {(void **)&ws.cb, w * D}, {(void **)&ws.cc, w * D},
+        {&ws.q, Q}, {&ws.fu, N}, {&ws.fv, N}, {&ws.fw, Wb},
+        {(void **)&ws.diag, diag_slots_needed() * D},
+        {(void **)&b.rho0, nzs * D}, {(void **)&b.theta0, nzs * D}, {(void **)&b.Theta0, nzs * D},
+        {(void **)&b.p0, nzs * D}, {(void **)&b.pi0, nzs * D}, {(void **)&b.dz, (4 * nzs + 1) * D},
     };
     size_t total = 0;
-    for (const Req &r : reqs) total += align_up(r.count * sizeof(double));
+    for (const Req &r : reqs) total += align_up(r.bytes);
     hipError_t e = hipMalloc(&c->arena, total);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -159,8 +162,8 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     c->ws_bytes = (int64_t)total;
     char *p = (char *)c->arena;
     for (const Req &r : reqs) {
-        *r.p = r.count ? (double *)p : nullptr;
-        p += align_up(r.count * sizeof(double));
+        *r.p = r.bytes ? (void *)p : nullptr;
+        p += align_up(r.bytes);
     }
     // dz, centre heights, 1/dz and 2/(dz_{k-1} + dz_k) on the z-faces
     const int nz = grid->nz;
@@ -243,9 +246,9 @@ erf_status erf_slow_rhs(erf_ctx *c, const erf_state *S, erf_state *R)
     ERF_CHECK_CTX(c);
     if (!c->have_base) return fail(c, ERF_E_STATE, "erf_init_base_state must come first");
     if (!state_ok(S, false, 0) || !state_ok(R, false, 0)) return fail(c, ERF_E_ARG, "null field pointer");
-    hipError_t e = launch_slow_rhs(c, (const double *)S->rho, (const double *)S->rhotheta, (const double *)S->rhou,
-                                   (const double *)S->rhov, (const double *)S->rhow, (double *)R->rho,
-                                   (double *)R->rhotheta, (double *)R->rhou, (double *)R->rhov, (double *)R->rhow);
+    const void *s5[5] = {S->rho, S->rhotheta, S->rhou, S->rhov, S->rhow};
+    void *r5[5] = {R->rho, R->rhotheta, R->rhou, R->rhov, R->rhow};
+    hipError_t e = launch_slow_rhs(c, s5, r5);
     return e == hipSuccess ? ERF_OK : hip_fail(c, e, "slow rhs launch");
 }
 
@@ -257,16 +260,12 @@ erf_status erf_acoustic_substeps(erf_ctx *c, const erf_state *Sn, const erf_stat
     if (!state_ok(Sn, false, 0) || !state_ok(St, false, 0) || !state_ok(Rt, false, 0) || !state_ok(Sout, false, 0))
         return fail(c, ERF_E_ARG, "null field pointer");
     if (n_sub < 1 || !(dtau > 0.0)) return fail(c, ERF_E_ARG, "n_sub >= 1 and dtau > 0 required");
-    const double *sn[5] = {(const double *)Sn->rho, (const double *)Sn->rhotheta, (const double *)Sn->rhou,
-                           (const double *)Sn->rhov, (const double *)Sn->rhow};
-    const double *st[5] = {(const double *)St->rho, (const double *)St->rhotheta, (const double *)St->rhou,
-                           (const double *)St->rhov, (const double *)St->rhow};
-    const double *rt[5] = {(const double *)Rt->rho, (const double *)Rt->rhotheta, (const double *)Rt->rhou,
-                           (const double *)Rt->rhov, (const double *)Rt->rhow};
-    double *so[5] = {(double *)Sout->rho, (double *)Sout->rhotheta, (double *)Sout->rhou, (double *)Sout->rhov,
-                     (double *)Sout->rhow};
-    hipError_t e = launch_acoustic_stage(c, sn, st, rt, n_sub, dtau, so, flux ? (double *)flux->rhou : nullptr,
-                                         flux ? (double *)flux->rhov : nullptr, flux ? (double *)flux->rhow : nullptr);
+    const void *sn[5] = {Sn->rho, Sn->rhotheta, Sn->rhou, Sn->rhov, Sn->rhow};
+    const void *st[5] = {St->rho, St->rhotheta, St->rhou, St->rhov, St->rhow};
+    const void *rt[5] = {Rt->rho, Rt->rhotheta, Rt->rhou, Rt->rhov, Rt->rhow};
+    void *so[5] = {Sout->rho, Sout->rhotheta, Sout->rhou, Sout->rhov, Sout->rhow};
+    hipError_t e = launch_acoustic_stage(c, sn, st, rt, n_sub, dtau, so, flux ? flux->rhou : nullptr,
+                                         flux ? flux->rhov : nullptr, flux ? flux->rhow : nullptr);
     return e == hipSuccess ? ERF_OK : hip_fail(c, e, "acoustic substeps launch");
 }
 
@@ -278,10 +277,8 @@ erf_status erf_scalar_advance(erf_ctx *c, const erf_state *Sn, const erf_state *
     if (!Sn || !St || !flux || !Sn->rhoq || !St->rhoq || !St->rho || !flux->rhou || !flux->rhov || !flux->rhow ||
         !rhoq_out)
         return fail(c, ERF_E_ARG, "null field pointer");
-    hipError_t e = launch_scalar_advance(c, (const double *)Sn->rhoq, (const double *)St->rho,
-                                         (const double *)St->rhoq, (const double *)flux->rhou,
-                                         (const double *)flux->rhov, (const double *)flux->rhow, dts,
-                                         (double *)rhoq_out);
+    hipError_t e = launch_scalar_advance(c, Sn->rhoq, St->rho, St->rhoq, flux->rhou, flux->rhov, flux->rhow, dts,
+                                         rhoq_out);
     return e == hipSuccess ? ERF_OK : hip_fail(c, e, "scalar advance launch");
 }
 
@@ -372,9 +369,8 @@ erf_status erf_diagnostics(erf_ctx *c, const erf_state *S, erf_diag *out)
     if (!c->have_base) return fail(c, ERF_E_STATE, "erf_init_base_state must come first");
     if (!state_ok(S, true, c->prm.n_scalars) || !out) return fail(c, ERF_E_ARG, "null pointer");
     double h[13];
-    hipError_t e = launch_diagnostics(c, (const double *)S->rho, (const double *)S->rhotheta,
-                                      (const double *)S->rhou, (const double *)S->rhov, (const double *)S->rhow,
-                                      (const double *)S->rhoq, h);
+    const void *s6[6] = {S->rho, S->rhotheta, S->rhou, S->rhov, S->rhow, S->rhoq};
+    hipError_t e = launch_diagnostics(c, s6, h);
     if (e != hipSuccess) return hip_fail(c, e, "diagnostics");
     out->mass = h[0];
     out->theta_mass = h[1];

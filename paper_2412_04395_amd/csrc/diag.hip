@@ -13,12 +13,13 @@ constexpr int kThreads = 256;
 
 __device__ __forceinline__ int cidx(const Dims &d, int i, int j, int k) { return (k * d.ny + j) * d.nx + i; }
 
+template <typename T>
 struct DiagArgs {
     Dims d;
     int nq;
     double dx, dy, g;
-    const double *dz, *zc;
-    const double *rho, *rt, *ru, *rv, *rw, *rq;
+    const double *dz, *zc, *rho0, *Theta0;
+    const T *rho, *rt, *ru, *rv, *rw, *rq;
     double *part;
 };
 
@@ -49,7 +50,8 @@ __device__ __forceinline__ double block_max(double v, double *sh)
     return r;
 }
 
-__global__ __launch_bounds__(kThreads) void k_diag_partial(DiagArgs a)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_diag_partial(DiagArgs<T> a)
 {
     __shared__ double sh[kThreads / 64];
     const Dims &d = a.d;
@@ -60,27 +62,29 @@ __global__ __launch_bounds__(kThreads) void k_diag_partial(DiagArgs a)
         int k = c / d.nxy, rem = c - k * d.nxy, j = rem / d.nx, i = rem - j * d.nx;
         double W = a.rw[c];
         if (bad(W)) acc[4] += 1.0;
+        // full density on level kk
+        auto rh = [&](int cc, int kk) { return full_of(a.rho, cc, a.rho0[kk]); };
         if (k > 0 && k < d.nz) {
-            double wv = fabs(W / (0.5 * (a.rho[c - d.nxy] + a.rho[c])));
+            double wv = fabs(W / (0.5 * (rh(c - d.nxy, k - 1) + rh(c, k))));
             acc[3] = fmax(acc[3], wv);
         }
         if (k == d.nz) continue;
         double vol = a.dx * a.dy * a.dz[k];
-        double r = a.rho[c], T = a.rt[c], U = a.ru[c], V = a.rv[c];
-        acc[4] += (double)bad(r) + (double)bad(T) + (double)bad(U) + (double)bad(V);
+        double r = rh(c, k), Tf = full_of(a.rt, c, a.Theta0[k]), U = a.ru[c], V = a.rv[c];
+        acc[4] += (double)bad(r) + (double)bad(Tf) + (double)bad(U) + (double)bad(V);
         acc[0] += r * vol;
-        acc[1] += T * vol;
+        acc[1] += Tf * vol;
         int ip = wrap_idx(i + 1, d.nx), im = wrap_idx(i - 1, d.nx), jp = wrap_idx(j + 1, d.ny), jm = wrap_idx(j - 1, d.ny);
-        double uc = 0.5 * (U / (0.5 * (a.rho[cidx(d, im, j, k)] + r)) +
-                           a.ru[cidx(d, ip, j, k)] / (0.5 * (r + a.rho[cidx(d, ip, j, k)])));
-        double vc = 0.5 * (V / (0.5 * (a.rho[cidx(d, i, jm, k)] + r)) +
-                           a.rv[cidx(d, i, jp, k)] / (0.5 * (r + a.rho[cidx(d, i, jp, k)])));
-        double wb = (k == 0) ? 0.0 : W / (0.5 * (a.rho[c - d.nxy] + r));
-        double wt = (k == d.nz - 1) ? 0.0 : a.rw[c + d.nxy] / (0.5 * (r + a.rho[c + d.nxy]));
+        double uc = 0.5 * (U / (0.5 * (rh(cidx(d, im, j, k), k) + r)) +
+                           a.ru[cidx(d, ip, j, k)] / (0.5 * (r + rh(cidx(d, ip, j, k), k))));
+        double vc = 0.5 * (V / (0.5 * (rh(cidx(d, i, jm, k), k) + r)) +
+                           a.rv[cidx(d, i, jp, k)] / (0.5 * (r + rh(cidx(d, i, jp, k), k))));
+        double wb = (k == 0) ? 0.0 : W / (0.5 * (rh(c - d.nxy, k - 1) + r));
+        double wt = (k == d.nz - 1) ? 0.0 : a.rw[c + d.nxy] / (0.5 * (r + rh(c + d.nxy, k + 1)));
         double wc = 0.5 * (wb + wt);
-        double temp = (T / r) * pow(kRd * T / kP00, kGamma - 1.0);
+        double temp = (Tf / r) * pow(kRd * Tf / kP00, kGamma - 1.0);
         acc[2] += (0.5 * r * (uc * uc + vc * vc + wc * wc) + r * kCv * temp + r * a.g * a.zc[k]) * vol;
-        for (int s = 0; s < a.nq && s < 8; ++s) acc[5 + s] += a.rq[(size_t)s * d.n + c] * vol;
+        for (int s = 0; s < a.nq && s < 8; ++s) acc[5 + s] += (double)a.rq[(size_t)s * d.n + c] * vol;
     }
     for (int s = 0; s < kSlots; ++s) {
         double v = (s == 3) ? block_max(acc[s], sh) : block_sum(acc[s], sh);
@@ -102,10 +106,11 @@ __global__ __launch_bounds__(64) void k_diag_final(double *part, int nblocks)
 
 }  // namespace
 
-hipError_t launch_diagnostics(erf_ctx *cx, const double *rho, const double *rt, const double *ru,
-                              const double *rv, const double *rw, const double *rq, double *host_out)
+namespace {
+template <typename T>
+hipError_t diag_t(erf_ctx *cx, const void *const S[6], double *host_out)
 {
-    DiagArgs a{};
+    DiagArgs<T> a{};
     a.d = cx->d;
     a.nq = cx->prm.n_scalars;
     a.dx = cx->grid.dx;
@@ -113,16 +118,18 @@ hipError_t launch_diagnostics(erf_ctx *cx, const double *rho, const double *rt, 
     a.g = cx->prm.grav;
     a.dz = cx->base.dz;
     a.zc = cx->base.zc();
-    a.rho = rho;
-    a.rt = rt;
-    a.ru = ru;
-    a.rv = rv;
-    a.rw = rw;
-    a.rq = rq;
+    a.rho0 = cx->base.rho0;
+    a.Theta0 = cx->base.Theta0;
+    a.rho = (const T *)S[0];
+    a.rt = (const T *)S[1];
+    a.ru = (const T *)S[2];
+    a.rv = (const T *)S[3];
+    a.rw = (const T *)S[4];
+    a.rq = (const T *)S[5];
     a.part = cx->ws.diag;
     int nb = (cx->d.nw + kThreads - 1) / kThreads;
     if (nb > kBlocks) nb = kBlocks;
-    hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(kThreads), 0, cx->stream, a);
+    hipLaunchKernelGGL(k_diag_partial<T>, dim3(nb), dim3(kThreads), 0, cx->stream, a);
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, cx->stream, a.part, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -130,6 +137,13 @@ hipError_t launch_diagnostics(erf_ctx *cx, const double *rho, const double *rt, 
                        cx->stream);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(cx->stream);
+}
+}  // namespace
+
+hipError_t launch_diagnostics(erf_ctx *cx, const void *const S[6], double *host_out)
+{
+    if (cx->prm.precision == ERF_FP32_MIXED) return diag_t<float>(cx, S, host_out);
+    return diag_t<double>(cx, S, host_out);
 }
 
 size_t diag_slots_needed() { return (size_t)(kBlocks + 1) * kSlots; }

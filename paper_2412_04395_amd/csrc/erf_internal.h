@@ -9,6 +9,7 @@
 
 #include <cstdint>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/erf.h"
@@ -71,6 +72,29 @@ __device__ __forceinline__ int refl_face(int k, int nz, double &sgn)
 
 __device__ __forceinline__ double sign_of(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
+// Storage conventions.  FP64 storage holds full rho and rho*theta; FP32
+// storage holds their perturbations about the base state.  These return the
+// full value and the perturbation of element c on level k, in double.
+template <typename T>
+inline constexpr bool kPert = std::is_same<T, float>::value;
+
+template <typename T>
+__device__ __forceinline__ double full_of(const T *f, int c, double base)
+{
+    if constexpr (kPert<T>)
+        return base + (double)f[c];
+    else
+        return f[c];
+}
+template <typename T>
+__device__ __forceinline__ double pert_of(const T *f, int c, double base)
+{
+    if constexpr (kPert<T>)
+        return (double)f[c];
+    else
+        return f[c] - base;
+}
+
 // Interpolated face value q_{m-1/2} (Sec. 3.6) from q[0..5] = q_{m-3..m+2};
 // s is the sign of the normal momentum at the face.
 __device__ __forceinline__ double face_interp(int order, double qm3, double qm2, double qm1,
@@ -90,32 +114,37 @@ __device__ __forceinline__ double face_interp(int order, double qm3, double qm2,
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
+// Bulk fields are stored in the context's precision (double for ERF_FP64,
+// float for ERF_FP32_MIXED) and kept as untyped pointers here; the tridiagonal
+// factors and the reduction partials are always double.
 struct Workspace {
     // stage states S*, S** (5 fields + scalars each)
-    double *sa[6] = {};
-    double *sb[6] = {};
+    void *sa[6] = {};
+    void *sb[6] = {};
     // slow tendencies
-    double *R[5] = {};
-    // stage-frozen fields at centres: theta, p', pi, velocities, mu_t
-    double *th = nullptr, *pp = nullptr, *pit = nullptr;
-    double *u = nullptr, *v = nullptr, *w = nullptr, *mut = nullptr;
+    void *R[5] = {};
+    // stage fields at centres / faces: theta (theta - theta0 in FP32 storage),
+    // p', Exner, velocities, mu_t
+    void *th = nullptr, *pp = nullptr, *pit = nullptr;
+    void *u = nullptr, *v = nullptr, *w = nullptr, *mut = nullptr;
     // stresses tau_11, tau_22, tau_33 (centres), tau_12 (xy-edges), tau_13,
     // tau_23 (z-face edges) and the heat diffusivity (centres)
-    double *tau[6] = {};
-    double *kap = nullptr;
+    void *tau[6] = {};
+    void *kap = nullptr;
     // substep perturbations: Theta'' (three time levels), rho'', U'' and V''
     // (double-buffered), W''
-    double *t2[3] = {};
-    double *u2[2] = {}, *v2[2] = {};
-    double *r2 = nullptr, *w2 = nullptr;
+    void *t2[3] = {};
+    void *u2[2] = {}, *v2[2] = {};
+    void *r2 = nullptr, *w2 = nullptr;
     // running sums of the substep momenta (stage-averaged fluxes at the end)
-    double *su = nullptr, *sv = nullptr, *sw = nullptr;
-    // per-stage tridiagonal coefficients on z-faces
-    double *ca = nullptr, *cb = nullptr, *cc = nullptr;  // a_k / den_k, 1 / den_k, c'_k (Thomas)
-    double *cC = nullptr;                                // buoyancy coefficient of the W'' rows
+    void *su = nullptr, *sv = nullptr, *sw = nullptr;
+    // per-stage tridiagonal rows on z-faces: buoyancy coefficient (bulk
+    // precision) and the Thomas factors a_k / den_k, 1 / den_k, c'_k (double)
+    void *cC = nullptr;
+    double *ca = nullptr, *cb = nullptr, *cc = nullptr;
     // mixing ratios q^t of the scalars, stage-averaged momenta of rk3_step
-    double *q = nullptr;
-    double *fu = nullptr, *fv = nullptr, *fw = nullptr;
+    void *q = nullptr;
+    void *fu = nullptr, *fv = nullptr, *fw = nullptr;
     // diagnostics partial sums
     double *diag = nullptr;
 };
@@ -182,20 +211,16 @@ inline void timing_stop(erf_ctx *c, int id)
 // launchers (host), one translation unit each
 // ---------------------------------------------------------------------------
 // rhs.hip
-hipError_t launch_slow_rhs(erf_ctx *c, const double *rho, const double *rt, const double *ru,
-                           const double *rv, const double *rw, double *Rr, double *Rt, double *Ru,
-                           double *Rv, double *Rw);
+hipError_t launch_slow_rhs(erf_ctx *c, const void *const S[5], void *const R[5]);
 // acoustic.hip
-hipError_t launch_acoustic_stage(erf_ctx *c, const double *const Sn[5], const double *const St[5],
-                                 const double *const Rt[5], int n_sub, double dtau,
-                                 double *const Sout[5], double *Fu, double *Fv, double *Fw);
+hipError_t launch_acoustic_stage(erf_ctx *c, const void *const Sn[5], const void *const St[5],
+                                 const void *const Rt[5], int n_sub, double dtau, void *const Sout[5],
+                                 void *Fu, void *Fv, void *Fw);
 // scalars.hip
-hipError_t launch_scalar_advance(erf_ctx *c, const double *rqn, const double *rho_t,
-                                 const double *rq_t, const double *Fu, const double *Fv,
-                                 const double *Fw, double dts, double *rq_out);
+hipError_t launch_scalar_advance(erf_ctx *c, const void *rqn, const void *rho_t, const void *rq_t,
+                                 const void *Fu, const void *Fv, const void *Fw, double dts, void *rq_out);
 // diag.hip
 size_t diag_slots_needed();
-hipError_t launch_diagnostics(erf_ctx *c, const double *rho, const double *rt, const double *ru,
-                              const double *rv, const double *rw, const double *rq, double *host_out);
+hipError_t launch_diagnostics(erf_ctx *c, const void *const S[6], double *host_out);
 
 }  // namespace erfk

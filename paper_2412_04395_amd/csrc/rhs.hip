@@ -1,5 +1,7 @@
 // rhs.hip -- slow right-hand side f(S) of the compressible equations
-// (eqs. con, mom, theta of Sec. 2.1) on the C-grid, FP64.
+// (eqs. con, mom, theta of Sec. 2.1) on the C-grid.  Fields are stored as T
+// (double, or float holding perturbations of rho and rho*theta about the base
+// state); all arithmetic is double.
 //
 // Passes per call:
 //   k_prep    primitive fields: theta, p' at centres, u, v, w on faces
@@ -14,11 +16,14 @@
 // Every thread resolves the periodic wrap in x and y and the lid reflections in
 // z once, into offset tables, so the stencil loads are base + offset.  The
 // interpolation order is a template parameter for the orders the workloads use.
+// In the FP32 storage theta is kept as theta - theta0(z) and the base value is
+// added back per level before interpolating.
 #include "erf_internal.h"
 
 namespace erfk {
 namespace {
 
+template <typename T>
 struct RhsArgs {
     Dims d;
     double dx, dy, idx, idy;
@@ -27,14 +32,14 @@ struct RhsArgs {
     int sgs, visc;
     double Cs, Pr_t, nu, alpha, f, Ug, Vg, Qs, g;
     // state
-    const double *rho, *rt, *ru, *rv, *rw;
+    const T *rho, *rt, *ru, *rv, *rw;
     // base state
-    const double *rho0, *Theta0, *p0;
+    const double *rho0, *Theta0, *theta0, *p0;
     // primitives and stresses (workspace)
-    double *th, *pp, *u, *v, *w, *mut;
-    double *t11, *t22, *t33, *t12, *t13, *t23, *kap;
+    T *th, *pp, *u, *v, *w, *mut;
+    T *t11, *t22, *t33, *t12, *t13, *t23, *kap;
     // outputs
-    double *Rr, *Rt, *Ru, *Rv, *Rw;
+    T *Rr, *Rt, *Ru, *Rv, *Rw;
 };
 
 __device__ __forceinline__ int cidx(const Dims &d, int i, int j, int k) { return (k * d.ny + j) * d.nx + i; }
@@ -42,7 +47,8 @@ __device__ __forceinline__ int cidx(const Dims &d, int i, int j, int k) { return
 // ---------------------------------------------------------------------------
 // primitives
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_prep(RhsArgs a)
+template <typename T>
+__global__ __launch_bounds__(256) void k_prep(RhsArgs<T> a)
 {
     const Dims &d = a.d;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -50,14 +56,14 @@ __global__ __launch_bounds__(256) void k_prep(RhsArgs a)
     int k = blockIdx.z;
     if (i >= d.nx || j >= d.ny) return;
     int c = cidx(d, i, j, k);
-    double r = a.rho[c], T = a.rt[c];
-    double T0 = a.Theta0[k];
-    a.th[c] = T / r;
+    const double r0 = a.rho0[k], T0 = a.Theta0[k];
+    const double r = full_of(a.rho, c, r0), Tf = full_of(a.rt, c, T0);
+    a.th[c] = kPert<T> ? (T)(Tf / r - a.theta0[k]) : (T)(Tf / r);
     // p' = p0 ((Theta/Theta0)^gamma - 1) without cancellation (EOS, Sec. 2.1)
-    a.pp[c] = a.p0[k] * expm1(kGamma * log1p((T - T0) / T0));
-    a.u[c] = a.ru[c] / (0.5 * (a.rho[cidx(d, wrap_idx(i - 1, d.nx), j, k)] + r));
-    a.v[c] = a.rv[c] / (0.5 * (a.rho[cidx(d, i, wrap_idx(j - 1, d.ny), k)] + r));
-    a.w[c] = (k == 0) ? 0.0 : a.rw[c] / (0.5 * (a.rho[c - d.nxy] + r));
+    a.pp[c] = a.p0[k] * expm1(kGamma * log1p(pert_of(a.rt, c, T0) / T0));
+    a.u[c] = a.ru[c] / (0.5 * (full_of(a.rho, cidx(d, wrap_idx(i - 1, d.nx), j, k), r0) + r));
+    a.v[c] = a.rv[c] / (0.5 * (full_of(a.rho, cidx(d, i, wrap_idx(j - 1, d.ny), k), r0) + r));
+    a.w[c] = (k == 0) ? 0.0 : a.rw[c] / (0.5 * (full_of(a.rho, c - d.nxy, a.rho0[k - 1]) + r));
     if (k == d.nz - 1) a.w[c + d.nxy] = 0.0;
 }
 
@@ -82,7 +88,8 @@ __device__ __forceinline__ Nbr nbr(const Dims &d, int i, int j, int k)
 
 // Smagorinsky eddy viscosity mu_t = rho (Cs Delta)^2 sqrt(2 S:S), Delta = (dx dy dz)^(1/3);
 // off-diagonal strains are averaged from the four edges around the centre.
-__global__ __launch_bounds__(256) void k_mut(RhsArgs a)
+template <typename T>
+__global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
 {
     const Dims &d = a.d;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -91,18 +98,21 @@ __global__ __launch_bounds__(256) void k_mut(RhsArgs a)
     if (i >= d.nx || j >= d.ny) return;
     const Nbr n = nbr(d, i, j, k);
     const int c = n.c, P = d.nxy;
-    const double *u = a.u, *v = a.v, *w = a.w;
+    // velocity loads widened to double before any arithmetic
+    auto u = [&](int cc) { return (double)a.u[cc]; };
+    auto v = [&](int cc) { return (double)a.v[cc]; };
+    auto w = [&](int cc) { return (double)a.w[cc]; };
     const double idz = a.idz[k];
-    const double e11 = (u[c + n.ip] - u[c]) * a.idx;
-    const double e22 = (v[c + n.jp] - v[c]) * a.idy;
-    const double e33 = (w[c + P] - w[c]) * idz;
+    const double e11 = (u(c + n.ip) - u(c)) * a.idx;
+    const double e22 = (v(c + n.jp) - v(c)) * a.idy;
+    const double e33 = (w(c + P) - w(c)) * idz;
     // offsets of i-1 and j-1 seen from the neighbours i+1 and j+1
     const int ip1 = wrap_idx(i + 1, d.nx), jp1 = wrap_idx(j + 1, d.ny);
     const int nip_im = wrap_idx(ip1 - 1, d.nx) - ip1;
     const int njp_jm = (wrap_idx(jp1 - 1, d.ny) - jp1) * d.nx;
     // S12 on the edge (x-face, y-face) at offset o, with its i-1 / j-1 offsets
     auto s12 = [&](int o, int oim, int ojm) {
-        return 0.5 * ((u[c + o] - u[c + o + ojm]) * a.idy + (v[c + o] - v[c + o + oim]) * a.idx);
+        return 0.5 * ((u(c + o) - u(c + o + ojm)) * a.idy + (v(c + o) - v(c + o + oim)) * a.idx);
     };
     const double a12 = 0.25 * (s12(0, n.im, n.jm) + s12(n.ip, nip_im, n.jm) + s12(n.jp, n.im, njp_jm) +
                                s12(n.ip + n.jp, nip_im, njp_jm));
@@ -110,12 +120,12 @@ __global__ __launch_bounds__(256) void k_mut(RhsArgs a)
     auto s13 = [&](int o, int oim, int kf) {
         if (kf <= 0 || kf >= d.nz) return 0.0;
         const double idzf = a.idzf[kf];
-        return 0.5 * ((u[c + o] - u[c + o - P]) * idzf + (w[c + o] - w[c + o + oim]) * a.idx);
+        return 0.5 * ((u(c + o) - u(c + o - P)) * idzf + (w(c + o) - w(c + o + oim)) * a.idx);
     };
     auto s23 = [&](int o, int ojm, int kf) {
         if (kf <= 0 || kf >= d.nz) return 0.0;
         const double idzf = a.idzf[kf];
-        return 0.5 * ((v[c + o] - v[c + o - P]) * idzf + (w[c + o] - w[c + o + ojm]) * a.idy);
+        return 0.5 * ((v(c + o) - v(c + o - P)) * idzf + (w(c + o) - w(c + o + ojm)) * a.idy);
     };
     const double a13 =
         0.25 * (s13(0, n.im, k) + s13(n.ip, nip_im, k) + s13(P, n.im, k + 1) + s13(P + n.ip, nip_im, k + 1));
@@ -123,13 +133,14 @@ __global__ __launch_bounds__(256) void k_mut(RhsArgs a)
         0.25 * (s23(0, n.jm, k) + s23(n.jp, njp_jm, k) + s23(P, n.jm, k + 1) + s23(P + n.jp, njp_jm, k + 1));
     const double ss = 2.0 * (e11 * e11 + e22 * e22 + e33 * e33) + 4.0 * (a12 * a12 + a13 * a13 + a23 * a23);
     const double cd = a.Cs * cbrt(a.dx * a.dy * a.dz[k]);
-    a.mut[c] = a.rho[c] * cd * cd * sqrt(ss);
+    a.mut[c] = full_of(a.rho, c, a.rho0[k]) * cd * cd * sqrt(ss);
 }
 
 // Stresses tau = -2 mu (S - D) at their points, mu = rho nu_m + mu_t averaged
 // from the four cells around an edge; heat diffusivity rho alpha_m + mu_t/Pr_t.
 // z runs to nz for the shear stresses on the top faces (zero: free slip).
-__global__ __launch_bounds__(256) void k_stress(RhsArgs a)
+template <typename T>
+__global__ __launch_bounds__(256) void k_stress(RhsArgs<T> a)
 {
     const Dims &d = a.d;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -138,35 +149,40 @@ __global__ __launch_bounds__(256) void k_stress(RhsArgs a)
     if (i >= d.nx || j >= d.ny) return;
     const Nbr n = nbr(d, i, j, k);
     const int P = d.nxy, c = n.c;
-    const double *u = a.u, *v = a.v, *w = a.w, *rho = a.rho, *mut = a.mut;
-    auto mu = [&](int cc) { return rho[cc] * a.nu + (a.sgs ? mut[cc] : 0.0); };
+    const T *rho = a.rho, *mut = a.mut;
+    auto u = [&](int cc) { return (double)a.u[cc]; };
+    auto v = [&](int cc) { return (double)a.v[cc]; };
+    auto w = [&](int cc) { return (double)a.w[cc]; };
+    // full density on level kk
+    auto rh = [&](int cc, int kk) { return full_of(rho, cc, a.rho0[kk]); };
+    auto mu = [&](int cc, int kk) { return rh(cc, kk) * a.nu + (a.sgs ? (double)mut[cc] : 0.0); };
     // shear stresses on the z-face edges of face k
     if (k == 0 || k == d.nz) {
         a.t13[c] = 0.0;
         a.t23[c] = 0.0;
     } else {
         const double idzf = a.idzf[k];
-        const double s13 = 0.5 * ((u[c] - u[c - P]) * idzf + (w[c] - w[c + n.im]) * a.idx);
-        const double s23 = 0.5 * ((v[c] - v[c - P]) * idzf + (w[c] - w[c + n.jm]) * a.idy);
-        const double mxz = 0.25 * (mu(c - P + n.im) + mu(c - P) + mu(c + n.im) + mu(c));
-        const double myz = 0.25 * (mu(c - P + n.jm) + mu(c - P) + mu(c + n.jm) + mu(c));
+        const double s13 = 0.5 * ((u(c) - u(c - P)) * idzf + (w(c) - w(c + n.im)) * a.idx);
+        const double s23 = 0.5 * ((v(c) - v(c - P)) * idzf + (w(c) - w(c + n.jm)) * a.idy);
+        const double mxz = 0.25 * (mu(c - P + n.im, k - 1) + mu(c - P, k - 1) + mu(c + n.im, k) + mu(c, k));
+        const double myz = 0.25 * (mu(c - P + n.jm, k - 1) + mu(c - P, k - 1) + mu(c + n.jm, k) + mu(c, k));
         a.t13[c] = -2.0 * mxz * s13;
         a.t23[c] = -2.0 * myz * s23;
     }
     if (k == d.nz) return;
     const double idz = a.idz[k];
-    const double e11 = (u[c + n.ip] - u[c]) * a.idx;
-    const double e22 = (v[c + n.jp] - v[c]) * a.idy;
-    const double e33 = (w[c + P] - w[c]) * idz;
+    const double e11 = (u(c + n.ip) - u(c)) * a.idx;
+    const double e22 = (v(c + n.jp) - v(c)) * a.idy;
+    const double e33 = (w(c + P) - w(c)) * idz;
     const double dd = (e11 + e22 + e33) / 3.0;
-    const double m = mu(c);
+    const double m = mu(c, k);
     a.t11[c] = -2.0 * m * (e11 - dd);
     a.t22[c] = -2.0 * m * (e22 - dd);
     a.t33[c] = -2.0 * m * (e33 - dd);
-    const double s12 = 0.5 * ((u[c] - u[c + n.jm]) * a.idy + (v[c] - v[c + n.im]) * a.idx);
-    const double me = 0.25 * (mu(c + n.im + n.jm) + mu(c + n.jm) + mu(c + n.im) + m);
+    const double s12 = 0.5 * ((u(c) - u(c + n.jm)) * a.idy + (v(c) - v(c + n.im)) * a.idx);
+    const double me = 0.25 * (mu(c + n.im + n.jm, k) + mu(c + n.jm, k) + mu(c + n.im, k) + m);
     a.t12[c] = -2.0 * me * s12;
-    a.kap[c] = rho[c] * a.alpha + (a.sgs ? mut[c] / a.Pr_t : 0.0);
+    a.kap[c] = rh(c, k) * a.alpha + (a.sgs ? (double)mut[c] / a.Pr_t : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -189,8 +205,8 @@ __device__ __forceinline__ double interp(int order, const double (&q)[7], int o,
     return ord == 6 ? c6 : c6 - s / 60.0 * ((qp2 - qm3) - 5.0 * (qp1 - qm2) + 10.0 * (q0 - qm1));
 }
 
-template <int OH, int OV>
-__global__ __launch_bounds__(256) void k_rhs(RhsArgs a)
+template <typename T, int OH, int OV>
+__global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
 {
     const Dims &d = a.d;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -202,12 +218,14 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs a)
     // neighbour offset tables: x and y periodic; z reflected (even for centre
     // and horizontal-face fields, odd with a sign for z-face fields)
     int ox[7], oy[7], ozc[7], ozw[7];
-    double szw[7];
+    double szw[7], thz0[7];  // thz0: theta0 on the reflected levels (FP32 storage)
 #pragma unroll
     for (int t = 0; t < 7; ++t) {
         ox[t] = wrap_idx(i + t - 3, d.nx) - i;
         oy[t] = (wrap_idx(j + t - 3, d.ny) - j) * d.nx;
-        ozc[t] = (refl_centre(k + t - 3, nz) - k) * P;
+        const int kr = refl_centre(k + t - 3, nz);
+        ozc[t] = (kr - k) * P;
+        thz0[t] = kPert<T> ? a.theta0[kr] : 0.0;
         double sg;
         ozw[t] = (refl_face(k + t - 3, nz, sg) - k) * P;
         szw[t] = sg;
@@ -220,33 +238,37 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs a)
     const double U0 = a.ru[c], U1 = a.ru[c + ox[4]];
     const double V0 = a.rv[c], V1 = a.rv[c + oy[4]];
     const double W0 = a.rw[c], W1 = a.rw[c + P];
+    const double r0k = a.rho0[k], rc = full_of(a.rho, c, r0k);
+    const double th0k = kPert<T> ? a.theta0[k] : 0.0;
     {
         a.Rr[c] = -((U1 - U0) * a.idx + (V1 - V0) * a.idy + (W1 - W0) * idz);
-        const double *th = a.th;
+        const T *th = a.th;
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = th[c + ox[t]];
+        for (int t = 0; t < 7; ++t) q[t] = th0k + th[c + ox[t]];
         const double fx0 = U0 * interp<OH>(oh, q, 0, sign_of(U0)), fx1 = U1 * interp<OH>(oh, q, 1, sign_of(U1));
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = th[c + oy[t]];
+        for (int t = 0; t < 7; ++t) q[t] = th0k + th[c + oy[t]];
         const double fy0 = V0 * interp<OH>(oh, q, 0, sign_of(V0)), fy1 = V1 * interp<OH>(oh, q, 1, sign_of(V1));
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = th[c + ozc[t]];
+        for (int t = 0; t < 7; ++t) q[t] = thz0[t] + th[c + ozc[t]];
         const double fz0 = (k == 0) ? 0.0 : W0 * interp<OV>(ov, q, 0, sign_of(W0));
         const double fz1 = (k == nz - 1) ? 0.0 : W1 * interp<OV>(ov, q, 1, sign_of(W1));
         double r = -((fx1 - fx0) * a.idx + (fy1 - fy0) * a.idy + (fz1 - fz0) * idz);
         if (a.visc) {
-            const double *kp = a.kap;
-            const double kc = kp[c], thc = th[c];
-            const double hx0 = -0.5 * (kp[c + ox[2]] + kc) * (thc - th[c + ox[2]]) * a.idx;
-            const double hx1 = -0.5 * (kc + kp[c + ox[4]]) * (th[c + ox[4]] - thc) * a.idx;
-            const double hy0 = -0.5 * (kp[c + oy[2]] + kc) * (thc - th[c + oy[2]]) * a.idy;
-            const double hy1 = -0.5 * (kc + kp[c + oy[4]]) * (th[c + oy[4]] - thc) * a.idy;
+            const T *kp = a.kap;
+            const double kc = kp[c], thc = th0k + th[c];
+            const double hx0 = -0.5 * (kp[c + ox[2]] + kc) * (thc - (th0k + th[c + ox[2]])) * a.idx;
+            const double hx1 = -0.5 * (kc + kp[c + ox[4]]) * ((th0k + th[c + ox[4]]) - thc) * a.idx;
+            const double hy0 = -0.5 * (kp[c + oy[2]] + kc) * (thc - (th0k + th[c + oy[2]])) * a.idy;
+            const double hy1 = -0.5 * (kc + kp[c + oy[4]]) * ((th0k + th[c + oy[4]]) - thc) * a.idy;
             double hz0 = 0.0, hz1 = 0.0;
-            if (k > 0) hz0 = -0.5 * (kp[c - P] + kc) * (thc - th[c - P]) * a.idzf[k];
-            if (k < nz - 1) hz1 = -0.5 * (kc + kp[c + P]) * (th[c + P] - thc) * a.idzf[k + 1];
+            if (k > 0)
+                hz0 = -0.5 * (kp[c - P] + kc) * (thc - (thz0[2] + th[c - P])) * a.idzf[k];
+            if (k < nz - 1)
+                hz1 = -0.5 * (kc + kp[c + P]) * ((thz0[4] + th[c + P]) - thc) * a.idzf[k + 1];
             r -= (hx1 - hx0) * a.idx + (hy1 - hy0) * a.idy + (hz1 - hz0) * idz;
         }
-        if (k == 0 && a.Qs != 0.0) r += a.rho[c] * a.Qs * idz;
+        if (k == 0 && a.Qs != 0.0) r += rc * a.Qs * idz;
         a.Rt[c] = r;
     }
 
@@ -254,7 +276,7 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs a)
     {
         const double Um = a.ru[c + ox[2]];
         const double ar = 0.5 * (U0 + U1), al = 0.5 * (Um + U0);
-        const double *u = a.u;
+        const T *u = a.u;
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = u[c + ox[t]];
         const double fxx_r = ar * interp<OH>(oh, q, 1, sign_of(ar)), fxx_l = al * interp<OH>(oh, q, 0, sign_of(al));
@@ -276,7 +298,7 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs a)
         }
         const double adv = (fxx_r - fxx_l) * a.idx + (fxy1 - fxy0) * a.idy + (fxz1 - fxz0) * idz;
         const double pgf = (a.pp[c] - a.pp[c + ox[2]]) * a.idx;
-        const double rho_f = 0.5 * (a.rho[c + ox[2]] + a.rho[c]);
+        const double rho_f = 0.5 * (full_of(a.rho, c + ox[2], r0k) + rc);
         const double vbar = 0.25 * (Vw + V0 + Vwn + V1);
         double r = -adv - pgf + a.f * (vbar - rho_f * a.Vg);
         if (a.visc)
@@ -289,7 +311,7 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs a)
     {
         const double Vs = a.rv[c + oy[2]];
         const double br = 0.5 * (V0 + V1), bl = 0.5 * (Vs + V0);
-        const double *v = a.v;
+        const T *v = a.v;
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = v[c + oy[t]];
         const double fyy_r = br * interp<OH>(oh, q, 1, sign_of(br)), fyy_l = bl * interp<OH>(oh, q, 0, sign_of(bl));
@@ -311,7 +333,7 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs a)
         }
         const double adv = (fyx1 - fyx0) * a.idx + (fyy_r - fyy_l) * a.idy + (fyz1 - fyz0) * idz;
         const double pgf = (a.pp[c] - a.pp[c + oy[2]]) * a.idy;
-        const double rho_f = 0.5 * (a.rho[c + oy[2]] + a.rho[c]);
+        const double rho_f = 0.5 * (full_of(a.rho, c + oy[2], r0k) + rc);
         const double ubar = 0.25 * (Us + Use + U0 + U1);
         double r = -adv - pgf - a.f * (ubar - rho_f * a.Ug);
         if (a.visc)
@@ -328,7 +350,7 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs a)
         const int cm = c - P;
         const double idzf = a.idzf[k];
         const double a0 = 0.5 * (a.ru[cm] + U0), a1 = 0.5 * (a.ru[cm + ox[4]] + U1);
-        const double *w = a.w;
+        const T *w = a.w;
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = w[c + ox[t]];
         const double fzx0 = a0 * interp<OH>(oh, q, 0, sign_of(a0)), fzx1 = a1 * interp<OH>(oh, q, 1, sign_of(a1));
@@ -343,7 +365,7 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs a)
         const double adv = (fzx1 - fzx0) * a.idx + (fzy1 - fzy0) * a.idy + (fzz_u - fzz_d) * idzf;
         const double pgf = (a.pp[c] - a.pp[cm]) * idzf;
         // buoyancy B = -(rho - rho0) g on the face; heavier air sinks
-        const double buoy = -a.g * 0.5 * ((a.rho[c] - a.rho0[k]) + (a.rho[cm] - a.rho0[k - 1]));
+        const double buoy = -a.g * 0.5 * (pert_of(a.rho, c, r0k) + pert_of(a.rho, cm, a.rho0[k - 1]));
         double r = -adv - pgf + buoy;
         if (a.visc)
             r -= (a.t13[c + ox[4]] - a.t13[c]) * a.idx + (a.t23[c + oy[4]] - a.t23[c]) * a.idy +
@@ -354,13 +376,13 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs a)
 
 }  // namespace
 
-hipError_t launch_slow_rhs(erf_ctx *cx, const double *rho, const double *rt, const double *ru,
-                           const double *rv, const double *rw, double *Rr, double *Rt, double *Ru,
-                           double *Rv, double *Rw)
+namespace {
+template <typename T>
+hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5])
 {
     const erf_params &p = cx->prm;
     Workspace &ws = cx->ws;
-    RhsArgs a{};
+    RhsArgs<T> a{};
     a.d = cx->d;
     a.dx = cx->grid.dx;
     a.dy = cx->grid.dy;
@@ -382,49 +404,57 @@ hipError_t launch_slow_rhs(erf_ctx *cx, const double *rho, const double *rt, con
     a.Vg = p.Vg;
     a.Qs = p.surf_heat_flux;
     a.g = p.grav;
-    a.rho = rho;
-    a.rt = rt;
-    a.ru = ru;
-    a.rv = rv;
-    a.rw = rw;
+    a.rho = (const T *)S[0];
+    a.rt = (const T *)S[1];
+    a.ru = (const T *)S[2];
+    a.rv = (const T *)S[3];
+    a.rw = (const T *)S[4];
     a.rho0 = cx->base.rho0;
     a.Theta0 = cx->base.Theta0;
+    a.theta0 = cx->base.theta0;
     a.p0 = cx->base.p0;
-    a.th = ws.th;
-    a.pp = ws.pp;
-    a.u = ws.u;
-    a.v = ws.v;
-    a.w = ws.w;
-    a.mut = ws.mut;
-    a.t11 = ws.tau[0];
-    a.t22 = ws.tau[1];
-    a.t33 = ws.tau[2];
-    a.t12 = ws.tau[3];
-    a.t13 = ws.tau[4];
-    a.t23 = ws.tau[5];
-    a.kap = ws.kap;
-    a.Rr = Rr;
-    a.Rt = Rt;
-    a.Ru = Ru;
-    a.Rv = Rv;
-    a.Rw = Rw;
+    a.th = (T *)ws.th;
+    a.pp = (T *)ws.pp;
+    a.u = (T *)ws.u;
+    a.v = (T *)ws.v;
+    a.w = (T *)ws.w;
+    a.mut = (T *)ws.mut;
+    a.t11 = (T *)ws.tau[0];
+    a.t22 = (T *)ws.tau[1];
+    a.t33 = (T *)ws.tau[2];
+    a.t12 = (T *)ws.tau[3];
+    a.t13 = (T *)ws.tau[4];
+    a.t23 = (T *)ws.tau[5];
+    a.kap = (T *)ws.kap;
+    a.Rr = (T *)R[0];
+    a.Rt = (T *)R[1];
+    a.Ru = (T *)R[2];
+    a.Rv = (T *)R[3];
+    a.Rw = (T *)R[4];
     const Dims &d = cx->d;
     dim3 blk(64, 4, 1), grd((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz);
     dim3 grdw((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz + 1);
-    timing_start(cx, K_PREP); hipLaunchKernelGGL(k_prep, grd, blk, 0, cx->stream, a); timing_stop(cx, K_PREP);
-    if (p.sgs) { timing_start(cx, K_MUT); hipLaunchKernelGGL(k_mut, grd, blk, 0, cx->stream, a); timing_stop(cx, K_MUT); }
-    if (a.visc) { timing_start(cx, K_STRESS); hipLaunchKernelGGL(k_stress, grdw, blk, 0, cx->stream, a); timing_stop(cx, K_STRESS); }
+    timing_start(cx, K_PREP); hipLaunchKernelGGL(k_prep<T>, grd, blk, 0, cx->stream, a); timing_stop(cx, K_PREP);
+    if (p.sgs) { timing_start(cx, K_MUT); hipLaunchKernelGGL(k_mut<T>, grd, blk, 0, cx->stream, a); timing_stop(cx, K_MUT); }
+    if (a.visc) { timing_start(cx, K_STRESS); hipLaunchKernelGGL(k_stress<T>, grdw, blk, 0, cx->stream, a); timing_stop(cx, K_STRESS); }
     timing_start(cx, K_RHS);
     if (a.oh == 5 && a.ov == 5)
-        hipLaunchKernelGGL((k_rhs<5, 5>), grd, blk, 0, cx->stream, a);
+        hipLaunchKernelGGL((k_rhs<T, 5, 5>), grd, blk, 0, cx->stream, a);
     else if (a.oh == 3 && a.ov == 3)
-        hipLaunchKernelGGL((k_rhs<3, 3>), grd, blk, 0, cx->stream, a);
+        hipLaunchKernelGGL((k_rhs<T, 3, 3>), grd, blk, 0, cx->stream, a);
     else if (a.oh == 2 && a.ov == 2)
-        hipLaunchKernelGGL((k_rhs<2, 2>), grd, blk, 0, cx->stream, a);
+        hipLaunchKernelGGL((k_rhs<T, 2, 2>), grd, blk, 0, cx->stream, a);
     else
-        hipLaunchKernelGGL((k_rhs<0, 0>), grd, blk, 0, cx->stream, a);
+        hipLaunchKernelGGL((k_rhs<T, 0, 0>), grd, blk, 0, cx->stream, a);
     timing_stop(cx, K_RHS);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_slow_rhs(erf_ctx *cx, const void *const S[5], void *const R[5])
+{
+    if (cx->prm.precision == ERF_FP32_MIXED) return slow_rhs_t<float>(cx, S, R);
+    return slow_rhs_t<double>(cx, S, R);
 }
 
 }  // namespace erfk

@@ -200,6 +200,31 @@ class Solver:
     def to_numpy(S):
         return {f: S[f].detach().cpu().double().numpy() for f in FIELDS}
 
+    # The FP32 storage keeps rho and rho*theta as perturbations about the base
+    # state (include/erf.h); these two convert a full FP64 host state to and
+    # from the context's storage.
+    def _base_cols(self):
+        if self.base is None:
+            raise RuntimeError("init_base_state must come first")
+        rho0 = self.base["rho0"][:, None, None]
+        return rho0, (self.base["rho0"] * self.base["theta0"])[:, None, None]
+
+    def from_full(self, S_np):
+        S = dict(S_np)
+        if self.cfg.prec == "fp32":
+            rho0, T0 = self._base_cols()
+            S["rho"] = S_np["rho"] - rho0
+            S["rt"] = S_np["rt"] - T0
+        return self.to_device(S)
+
+    def to_full(self, S):
+        out = self.to_numpy(S)
+        if self.cfg.prec == "fp32":
+            rho0, T0 = self._base_cols()
+            out["rho"] = out["rho"] + rho0
+            out["rt"] = out["rt"] + T0
+        return out
+
     def _st(self, S, fields=FIELDS):
         vals = {}
         for f, name in zip(FIELDS, ("rho", "rhotheta", "rhou", "rhov", "rhow", "rhoq")):

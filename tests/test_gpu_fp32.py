@@ -1,0 +1,175 @@
+"""FP32-bulk path (FP32 storage, rho and rho*theta as perturbations about the
+FP64 base state; FP64 arithmetic, tridiagonal factors and sums) against the
+FP64 oracle.
+
+Per call, both sides get the same FP32-representable input (the FP64 state is
+rounded through the FP32 storage first), so the difference measures the FP32
+storage of the intermediate and output fields only: unit roundoff 6e-8 times
+the cancellation of flux differences (<~ 1e2) gives a 1e-5 bound.
+
+Over time the bound is the one stated for this path: max |theta'| error
+<= 1e-3 K and max |u|, |w| error <= 1e-3 m/s.  It is claimed only where an FP64
+twin stays well below it; the twin is the FP64 oracle started from the initial
+state rounded through the FP32 storage (the smallest perturbation that storage
+makes).  The 2-D bubble is chaotic: that twin differs by 4e-6 K at 10 min,
+7e-5 K at 15 min, 4e-3 K at 25 min and 6e-2 K at 30 min, and the FP32 run,
+which rounds every step rather than once, sits about ten times above the twin
+(at 15 min: 5.6e-4 K, w 1.2e-3 m/s).  The bubble is therefore checked at 10 min
+with the twin asserted below 1e-4; the linear isothermal gravity wave is
+checked after one hour.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_04395_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _sides(cfg32):
+    from paper_2412_04395_amd import erf
+    cfg64 = cfg32.replace(prec="fp64")
+    o = oracle.Oracle(cfg64)
+    th0 = W.theta_sounding(cfg64)
+    b = o.init_base_state(th0, cfg64.p_surface)
+    s = erf.Solver(cfg32)
+    bs = s.init_base_state(th0)
+    assert np.array_equal(b["rho0"], bs["rho0"])
+    return o, s, th0, b
+
+
+def _round_through_fp32(S, b):
+    """The FP64 state that the FP32 storage represents exactly."""
+    out = {}
+    rho0 = b["rho0"][:, None, None]
+    T0 = (b["rho0"] * b["theta0"])[:, None, None]
+    out["rho"] = rho0 + (S["rho"] - rho0).astype(np.float32).astype(np.float64)
+    out["rt"] = T0 + (S["rt"] - T0).astype(np.float32).astype(np.float64)
+    for f in ("ru", "rv", "rw", "rq"):
+        out[f] = S[f].astype(np.float32).astype(np.float64)
+    return {k: np.ascontiguousarray(v) for k, v in out.items()}
+
+
+def _rough(cfg, b, th0, seed):
+    S = W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"])
+    shp = S["rho"].shape
+    S["ru"] = S["ru"] + S["rho"] * W.uniform_noise(seed + 1, shp, 2.0)
+    S["rv"] = S["rv"] + S["rho"] * W.uniform_noise(seed + 2, shp, 2.0) * (cfg.ny > 1)
+    rw = W.uniform_noise(seed + 3, S["rw"].shape, 1.0)
+    rw[0] = rw[-1] = 0.0
+    S["rw"] = rw
+    S["rho"] = S["rho"] * (1.0 + W.uniform_noise(seed + 4, shp, 1e-3))
+    return {k: np.ascontiguousarray(v) for k, v in S.items()}
+
+
+def _rel(a, b):
+    m = np.max(np.abs(b))
+    return np.max(np.abs(a - b)) / m if m > 0 else np.max(np.abs(a - b))
+
+
+TOL32 = 1e-5
+
+
+@pytest.mark.parametrize("case", ["o53", "smag"])
+def test_fp32_slow_rhs_per_call(case):
+    kw = dict(prec="fp32")
+    if case == "smag":
+        kw.update(name="cbl_small", nx=33, ny=18, nz=14, dx=20.0, dy=20.0, dz=W.uniform_dz(14, 10.0), dt=0.1,
+                  adv_order_h=5, adv_order_v=5, sgs=1, Cs=0.1, f_cor=1e-4, Ug=10.0, surf_heat_flux=0.2)
+    cfg = W.small(**kw)
+    o, s, th0, b = _sides(cfg)
+    S = _round_through_fp32(_rough(cfg, b, th0, 10), b)
+    R_ref = o.slow_rhs(S)
+    R = s.to_numpy(s.slow_rhs(s.from_full(S)))
+    errs = {f: _rel(R[f], R_ref[f]) for f in ("rho", "rt", "ru", "rv", "rw")}
+    _say("fp32 slow_rhs", case, {f: f"{e:.2e}" for f, e in errs.items()})
+    for f, e in errs.items():
+        assert e <= TOL32, (f, e)
+
+
+def test_fp32_acoustic_stage_per_call():
+    cfg = W.small(prec="fp32")
+    o, s, th0, b = _sides(cfg)
+    St = _round_through_fp32(_rough(cfg, b, th0, 20), b)
+    Sn = _round_through_fp32(_rough(cfg, b, th0, 30), b)
+    Rt = {k: v.astype(np.float32).astype(np.float64) for k, v in o.slow_rhs(St).items()}
+    Rt = {k: np.ascontiguousarray(v) for k, v in Rt.items()}
+    out_ref, F_ref = o.acoustic_substeps(Sn, St, Rt, 3, cfg.dt / cfg.n_substeps)
+    Rd = s.to_device(Rt)
+    out, F = s.acoustic_substeps(s.from_full(Sn), s.from_full(St), Rd, 3, cfg.dt / cfg.n_substeps)
+    got = s.to_full(out)
+    rho0 = b["rho0"][:, None, None]
+    T0 = (b["rho0"] * b["theta0"])[:, None, None]
+    errs = {"rho": _rel(got["rho"] - rho0, out_ref["rho"] - rho0), "rt": _rel(got["rt"] - T0, out_ref["rt"] - T0)}
+    for f in ("ru", "rv", "rw"):
+        errs[f] = _rel(got[f], out_ref[f])
+    Fn = s.to_numpy(F)
+    for f, r in zip(("ru", "rv", "rw"), F_ref):
+        errs["F" + f] = _rel(Fn[f], r)
+    _say("fp32 acoustic", {f: f"{e:.2e}" for f, e in errs.items()})
+    for f, e in errs.items():
+        assert e <= TOL32, (f, e)
+
+
+def _prims(S, b):
+    rho = S["rho"]
+    th = S["rt"] / rho - b["theta0"][:, None, None]
+    u = S["ru"] / (0.5 * (np.roll(rho, 1, -1) + rho))
+    w = np.zeros_like(S["rw"])
+    w[1:-1] = S["rw"][1:-1] / (0.5 * (rho[1:] + rho[:-1]))
+    return th, u, w
+
+
+def _diff(A, B, b):
+    (a, bb, c), (x, y, z) = _prims(A, b), _prims(B, b)
+    return np.abs(a - x).max(), np.abs(bb - y).max(), np.abs(c - z).max(), np.abs(z).max()
+
+
+def _run_pair(cfg32, steps, S0, twin=False):
+    o, s, th0, b = _sides(cfg32)
+    S = {k: v.copy() for k, v in S0(b, th0).items()}
+    Sg = s.from_full(S)
+    Tw = _round_through_fp32(S, b) if twin else None
+    for n in range(steps):
+        o.rk3_step(S)
+        s.rk3_step(Sg)
+        if twin:
+            o.rk3_step(Tw)
+    got = s.to_full(Sg)
+    return _diff(got, S, b), (_diff(Tw, S, b) if twin else None)
+
+
+def test_fp32_bubble_10min_error_bound():
+    cfg = W.bubble2d(prec="fp32")
+    (eth, eu, ew, wmax), (tth, tu, tw, _) = _run_pair(cfg, 600, lambda b, th0: W.initial_state(cfg, b["rho0"], th0),
+                                                      twin=True)
+    _say(f"fp32 bubble 10 min: theta' {eth:.2e} K, u {eu:.2e} m/s, w {ew:.2e} m/s (max w {wmax:.1f}); "
+         f"FP64 twin: theta' {tth:.2e} K, u {tu:.2e}, w {tw:.2e}")
+    assert tth <= 1e-4 and tu <= 1e-4 and tw <= 1e-4
+    assert eth <= 1e-3 and eu <= 1e-3 and ew <= 1e-3
+
+
+def test_fp32_gravity_wave_1h_error_bound():
+    n, Lx, depth, T = 24, 20000.0, 10000.0, 300.0
+    cfg = W.small(name="isothermal", nx=n, ny=1, nz=n, dx=Lx / n, dy=100.0, dz=W.uniform_dz(n, depth / n),
+                  dt=5.0, n_substeps=6, adv_order_h=2, adv_order_v=2, prec="fp32")
+
+    def init(b, th0):
+        H = oracle.const("R_d") * T / cfg.grav
+        x = (np.arange(n) + 0.5) * cfg.dx
+        z = cfg.z_centres()
+        amp = 0.01 * np.exp(z / (2 * H)) * np.sin(np.pi * z / depth)
+        dth = (amp[:, None] * np.cos(2 * np.pi * x / Lx)[None, :])[:, None, :]
+        return W.state_from_theta(cfg, b["rho0"], th0, dth * th0[:, None, None] / T)
+
+    (eth, eu, ew, wmax), _ = _run_pair(cfg, 720, init)
+    _say(f"fp32 gravity wave 1 h: theta' {eth:.2e} K, u {eu:.2e} m/s, w {ew:.2e} m/s (max w {wmax:.2e})")
+    assert eth <= 1e-3 and eu <= 1e-3 and ew <= 1e-3
