@@ -37,7 +37,9 @@ class _Params(C.Structure):
                 ("scalar_scheme", C.c_int32), ("n_scalars", C.c_int32), ("sgs", C.c_int32),
                 ("Cs", C.c_double), ("Pr_t", C.c_double), ("nu_m", C.c_double),
                 ("alpha_m", C.c_double), ("f_cor", C.c_double), ("Ug", C.c_double),
-                ("Vg", C.c_double), ("surf_heat_flux", C.c_double), ("grav", C.c_double)]
+                ("Vg", C.c_double), ("surf_heat_flux", C.c_double), ("grav", C.c_double),
+                ("mlp_params", C.POINTER(C.c_double)), ("mlp_norm", C.POINTER(C.c_double)),
+                ("mlp_bf16", C.c_int32)]
 
 
 class _Base(C.Structure):
@@ -84,6 +86,18 @@ def lib():
                                        C.POINTER(_State)]
             L.orc_diagnostics.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Base),
                                           C.POINTER(_State), _DP]
+            L.orc_bf16.restype = C.c_double
+            L.orc_bf16.argtypes = [C.c_double]
+            L.orc_mlp_forward.argtypes = [_DP, _DP, C.c_int64, _DP, C.c_int]
+            L.orc_mlp_loss_grad.argtypes = [_DP, _DP, _DP, C.c_int64, C.c_int, _DP, _DP]
+            L.orc_adam.argtypes = [_DP, _DP, _DP, _DP, C.c_int64, C.c_int64, C.c_double, C.c_double,
+                                   C.c_double, C.c_double]
+            L.orc_sgs_features.argtypes = [C.POINTER(_Grid), C.POINTER(_State), _DP]
+            L.orc_box_filter.argtypes = [C.POINTER(_Grid), C.POINTER(_State), C.c_int32, C.c_double, C.c_double,
+                                         C.POINTER(_State), _DP]
+            L.orc_slow_rhs_mlp.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Base),
+                                           C.POINTER(_State), _DP, _DP, C.c_int, C.POINTER(_State),
+                                           C.POINTER(C.c_int64)]
             _lib = L
     return _lib
 
@@ -108,8 +122,20 @@ class Oracle:
         self._params = _Params(cfg.dt, cfg.n_substeps, cfg.beta_s, cfg.beta_d, cfg.adv_order_h,
                                cfg.adv_order_v, cfg.scalar_scheme, cfg.n_scalars, cfg.sgs, cfg.Cs,
                                cfg.Pr_t, cfg.nu_m, cfg.alpha_m, cfg.f_cor, cfg.Ug, cfg.Vg,
-                               cfg.surf_heat_flux, cfg.grav)
+                               cfg.surf_heat_flux, cfg.grav, None, None, 0)
         self.base = None
+        self._mlp = None
+
+    def set_mlp(self, params, norm, bf16: bool = False):
+        """Closure weights for sgs == 2 (kept alive by this object)."""
+        pa = np.ascontiguousarray(params, dtype=np.float64)
+        no = np.ascontiguousarray(norm, dtype=np.float64)
+        if pa.size != mlp_nparams() or no.size != 38:
+            raise ValueError("MLP parameters must have mlp_nparams() values and norm 38")
+        self._mlp = (pa, no)
+        self._params.mlp_params = _p(pa)
+        self._params.mlp_norm = _p(no)
+        self._params.mlp_bf16 = int(bool(bf16))
 
     # -- base state -------------------------------------------------------
     def init_base_state(self, theta0: np.ndarray, p_surface: float):
@@ -183,6 +209,74 @@ class Oracle:
              "nonfinite": int(out[4])}
         d["scalar_mass"] = out[5:].copy()
         return d
+
+
+    # -- learned closure ---------------------------------------------------
+    def sgs_features(self, S):
+        n = self.nx * self.ny * self.nz
+        feat = np.zeros((n, 10))
+        self._check(lib().orc_sgs_features(C.byref(self._grid), C.byref(self._st(S)), _p(feat)),
+                    "orc_sgs_features")
+        return feat
+
+    def box_filter(self, S, r: int, Cs: float = 0.0, Pr_t: float = 1.0 / 3.0):
+        """Coarse state (rho, rt, ru, rv, rw; rq empty) and targets[nc][9];
+        Cs > 0 adds the block mean of the fine Smagorinsky stresses."""
+        nx, ny, nz = self.nx // r, self.ny // r, self.nz // r
+        Cst = {"rho": np.zeros((nz, ny, nx)), "rt": np.zeros((nz, ny, nx)), "ru": np.zeros((nz, ny, nx)),
+               "rv": np.zeros((nz, ny, nx)), "rw": np.zeros((nz + 1, ny, nx)), "rq": np.zeros((0, nz, ny, nx))}
+        tg = np.zeros((nx * ny * nz, 9))
+        Sx = dict(S)
+        Sx["rq"] = np.zeros((0,) + S["rho"].shape)
+        self._check(lib().orc_box_filter(C.byref(self._grid), C.byref(self._st(Sx)), r, Cs, Pr_t,
+                                         C.byref(self._st(Cst)), _p(tg)), "orc_box_filter")
+        return Cst, tg
+
+    def slow_rhs_mlp(self, S, params, norm, bf16: bool = False):
+        """Slow RHS with the learned closure; returns (R, number of fallback cells)."""
+        R = self.zeros_state()
+        pa = np.ascontiguousarray(params, dtype=np.float64)
+        no = np.ascontiguousarray(norm, dtype=np.float64)
+        nfb = C.c_int64(0)
+        self._check(lib().orc_slow_rhs_mlp(C.byref(self._grid), C.byref(self._params), C.byref(self._base),
+                                           C.byref(self._st(S)), _p(pa), _p(no), int(bool(bf16)),
+                                           C.byref(self._st(R)), C.byref(nfb)), "orc_slow_rhs_mlp")
+        return R, int(nfb.value)
+
+
+# -- learned closure: network helpers ----------------------------------------
+def mlp_nparams() -> int:
+    return int(lib().orc_mlp_nparams())
+
+
+def bf16(x: float) -> float:
+    return lib().orc_bf16(float(x))
+
+
+def mlp_forward(params, x, bf16: bool = False):
+    pa = np.ascontiguousarray(params, dtype=np.float64)
+    xa = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 10)
+    y = np.zeros((xa.shape[0], 9))
+    lib().orc_mlp_forward(_p(pa), _p(xa), xa.shape[0], _p(y), int(bool(bf16)))
+    return y
+
+
+def mlp_loss_grad(params, x, t, bf16: bool = False):
+    pa = np.ascontiguousarray(params, dtype=np.float64)
+    xa = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 10)
+    ta = np.ascontiguousarray(t, dtype=np.float64).reshape(-1, 9)
+    assert xa.shape[0] == ta.shape[0]
+    loss = C.c_double(0.0)
+    g = np.zeros(pa.size)
+    lib().orc_mlp_loss_grad(_p(pa), _p(xa), _p(ta), xa.shape[0], int(bool(bf16)), C.byref(loss), _p(g))
+    return loss.value, g
+
+
+def adam(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step on float64 arrays, in place."""
+    for a in (params, grad, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib().orc_adam(_p(params), _p(grad), _p(m), _p(v), params.size, step, lr, beta1, beta2, eps)
 
 
 # -- pointwise helpers used by the pin tests ---------------------------------

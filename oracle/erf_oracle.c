@@ -407,9 +407,16 @@ static void add_diffusion(const orc_grid *g, const orc_params *P, const orc_stat
 /* ------------------------------------------------------------------------ */
 /* slow right-hand side                                                      */
 /* ------------------------------------------------------------------------ */
+int orc_slow_rhs_mlp(const orc_grid *g, const orc_params *P, const orc_base *B, const orc_state *S,
+                     const double *params, const double *norm, int bf16, orc_state *R, int64_t *fallback_out);
+
 int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                  const orc_state *S, orc_state *R)
 {
+    if (P->sgs == 2) {
+        if (!P->mlp_params || !P->mlp_norm) return -1;
+        return orc_slow_rhs_mlp(g, P, B, S, P->mlp_params, P->mlp_norm, P->mlp_bf16, R, NULL);
+    }
     int nx = g->nx, ny = g->ny, nz = g->nz;
     if (nx < 1 || ny < 1 || nz < 1) return -2;
     int oh = P->adv_order_h, ov = P->adv_order_v;
@@ -534,7 +541,7 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                 R->rw[c] = -adv - pgf + buoy;
             }
 
-    if (P->sgs != 0 || P->nu_m != 0.0 || P->alpha_m != 0.0) add_diffusion(g, P, S, th, u, v, w, R);
+    if (P->sgs == 1 || P->nu_m != 0.0 || P->alpha_m != 0.0) add_diffusion(g, P, S, th, u, v, w, R);
 
     /* prescribed kinematic surface heat flux enters the lowest cell (Sec. 3.8) */
     if (P->surf_heat_flux != 0.0)
@@ -866,5 +873,392 @@ int orc_diagnostics(const orc_grid *g, const orc_params *P, const orc_base *B,
     out[4] = nonfinite;
     for (int s = 0; s < nq; ++s) out[5 + s] = qm[s].s;
     free(qm);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* learned SGS closure: MLP 10 -> 64 -> 64 -> 64 -> 9, ReLU hidden layers     */
+/* ------------------------------------------------------------------------ */
+/* Not part of the paper's method: the paper names surrogate models only as
+ * future work (Sec. 6).  This is the reference for the closure that replaces
+ * the Smagorinsky stresses. */
+enum { MI = 10, MH = 64, MO = 9 };
+#define OFF_W1 0
+#define OFF_B1 (OFF_W1 + MI * MH)
+#define OFF_W2 (OFF_B1 + MH)
+#define OFF_B2 (OFF_W2 + MH * MH)
+#define OFF_W3 (OFF_B2 + MH)
+#define OFF_B3 (OFF_W3 + MH * MH)
+#define OFF_W4 (OFF_B3 + MH)
+#define OFF_B4 (OFF_W4 + MH * MO)
+#define N_PARAMS (OFF_B4 + MO)
+
+int orc_mlp_nparams(void) { return N_PARAMS; }
+
+/* bfloat16 = the upper 16 bits of a float, rounded to nearest even */
+double orc_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (double)f; /* inf / nan */
+    uint32_t lsb = (u >> 16) & 1u;
+    u = (u + 0x7fffu + lsb) & 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+static double rb(double x, int bf16) { return bf16 ? orc_bf16(x) : x; }
+
+/* one dense layer: out[j] = b[j] + sum_i in[i] W[i][j] (operands rounded) */
+static void dense(const double *in, int nin, const double *W, const double *b, int nout, int bf16,
+                  double *out)
+{
+    for (int j = 0; j < nout; ++j) {
+        double acc = 0.0;
+        for (int i = 0; i < nin; ++i) acc += rb(in[i], bf16) * rb(W[i * nout + j], bf16);
+        out[j] = b[j] + acc;
+    }
+}
+
+static void relu(double *h, int n)
+{
+    for (int j = 0; j < n; ++j)
+        if (!(h[j] > 0.0)) h[j] = 0.0;
+}
+
+int orc_mlp_forward(const double *p, const double *x, int64_t n, double *y, int bf16)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < n; ++s) {
+        double h1[MH], h2[MH], h3[MH];
+        dense(x + s * MI, MI, p + OFF_W1, p + OFF_B1, MH, bf16, h1);
+        relu(h1, MH);
+        dense(h1, MH, p + OFF_W2, p + OFF_B2, MH, bf16, h2);
+        relu(h2, MH);
+        dense(h2, MH, p + OFF_W3, p + OFF_B3, MH, bf16, h3);
+        relu(h3, MH);
+        dense(h3, MH, p + OFF_W4, p + OFF_B4, MO, bf16, y + s * MO);
+    }
+    return 0;
+}
+
+/* Loss L = mean over samples and outputs of (y - t)^2; backpropagation through
+ * the four layers (ReLU derivative 0 at 0). */
+int orc_mlp_loss_grad(const double *p, const double *x, const double *t, int64_t n, int bf16,
+                      double *loss, double *grad)
+{
+    memset(grad, 0, sizeof(double) * N_PARAMS);
+    double L = 0.0;
+    const double scale = 2.0 / ((double)n * MO);
+    for (int64_t s = 0; s < n; ++s) {
+        const double *xs = x + s * MI;
+        double h1[MH], h2[MH], h3[MH], y[MO], dy[MO], d3[MH], d2[MH], d1[MH];
+        dense(xs, MI, p + OFF_W1, p + OFF_B1, MH, bf16, h1);
+        relu(h1, MH);
+        dense(h1, MH, p + OFF_W2, p + OFF_B2, MH, bf16, h2);
+        relu(h2, MH);
+        dense(h2, MH, p + OFF_W3, p + OFF_B3, MH, bf16, h3);
+        relu(h3, MH);
+        dense(h3, MH, p + OFF_W4, p + OFF_B4, MO, bf16, y);
+        for (int j = 0; j < MO; ++j) {
+            double e = y[j] - t[s * MO + j];
+            L += e * e;
+            dy[j] = scale * e;
+        }
+        /* layer 4 */
+        for (int i = 0; i < MH; ++i)
+            for (int j = 0; j < MO; ++j) grad[OFF_W4 + i * MO + j] += rb(h3[i], bf16) * rb(dy[j], bf16);
+        for (int j = 0; j < MO; ++j) grad[OFF_B4 + j] += dy[j];
+        for (int i = 0; i < MH; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < MO; ++j) acc += rb(dy[j], bf16) * rb(p[OFF_W4 + i * MO + j], bf16);
+            d3[i] = h3[i] > 0.0 ? acc : 0.0;
+        }
+        /* layer 3 */
+        for (int i = 0; i < MH; ++i)
+            for (int j = 0; j < MH; ++j) grad[OFF_W3 + i * MH + j] += rb(h2[i], bf16) * rb(d3[j], bf16);
+        for (int j = 0; j < MH; ++j) grad[OFF_B3 + j] += d3[j];
+        for (int i = 0; i < MH; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < MH; ++j) acc += rb(d3[j], bf16) * rb(p[OFF_W3 + i * MH + j], bf16);
+            d2[i] = h2[i] > 0.0 ? acc : 0.0;
+        }
+        /* layer 2 */
+        for (int i = 0; i < MH; ++i)
+            for (int j = 0; j < MH; ++j) grad[OFF_W2 + i * MH + j] += rb(h1[i], bf16) * rb(d2[j], bf16);
+        for (int j = 0; j < MH; ++j) grad[OFF_B2 + j] += d2[j];
+        for (int i = 0; i < MH; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < MH; ++j) acc += rb(d2[j], bf16) * rb(p[OFF_W2 + i * MH + j], bf16);
+            d1[i] = h1[i] > 0.0 ? acc : 0.0;
+        }
+        /* layer 1 */
+        for (int i = 0; i < MI; ++i)
+            for (int j = 0; j < MH; ++j) grad[OFF_W1 + i * MH + j] += rb(xs[i], bf16) * rb(d1[j], bf16);
+        for (int j = 0; j < MH; ++j) grad[OFF_B1 + j] += d1[j];
+    }
+    if (loss) *loss = L / ((double)n * MO);
+    return 0;
+}
+
+/* Adam (Kingma & Ba 2015) with bias correction */
+int orc_adam(double *p, const double *g, double *m, double *v, int64_t np, int64_t step, double lr,
+             double beta1, double beta2, double eps)
+{
+    double c1 = 1.0 - pow(beta1, (double)step), c2 = 1.0 - pow(beta2, (double)step);
+    for (int64_t i = 0; i < np; ++i) {
+        m[i] = beta1 * m[i] + (1.0 - beta1) * g[i];
+        v[i] = beta2 * v[i] + (1.0 - beta2) * g[i] * g[i];
+        p[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* closure inputs at cell centres                                            */
+/* ------------------------------------------------------------------------ */
+/* Diagonal gradients from the two faces of the cell; off-diagonal ones as the
+ * mean of the four edge differences around the centre (free-slip lids: du/dz,
+ * dv/dz, dw/dx, dw/dy vanish on the lid edges); dtheta/dz as the mean of the
+ * two face differences (zero through the lids). */
+int orc_sgs_features(const orc_grid *g, const orc_state *S, double *feat)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    size_t n = (size_t)nx * ny * nz, nw = (size_t)nx * ny * (nz + 1);
+    double *th = dalloc(n), *u = dalloc(n), *v = dalloc(n), *w = dalloc(nw);
+    primitives(g, S, th, u, v, w);
+    const double dx = g->dx, dy = g->dy;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                double *f = feat + c * MI;
+                /* edge differences */
+#define DUDY(ii, jj) ((cget(g, u, ii, jj, k) - cget(g, u, ii, (jj) - 1, k)) / dy)
+#define DVDX(ii, jj) ((cget(g, v, ii, jj, k) - cget(g, v, (ii) - 1, jj, k)) / dx)
+#define DUDZ(ii, kk) (((kk) <= 0 || (kk) >= nz) ? 0.0 : (cget(g, u, ii, j, kk) - cget(g, u, ii, j, (kk) - 1)) / (0.5 * (g->dz[(kk) - 1] + g->dz[kk])))
+#define DVDZ(jj, kk) (((kk) <= 0 || (kk) >= nz) ? 0.0 : (cget(g, v, i, jj, kk) - cget(g, v, i, jj, (kk) - 1)) / (0.5 * (g->dz[(kk) - 1] + g->dz[kk])))
+#define DWDX(ii, kk) (((kk) <= 0 || (kk) >= nz) ? 0.0 : (wget(g, w, ii, j, kk) - wget(g, w, (ii) - 1, j, kk)) / dx)
+#define DWDY(jj, kk) (((kk) <= 0 || (kk) >= nz) ? 0.0 : (wget(g, w, i, jj, kk) - wget(g, w, i, (jj) - 1, kk)) / dy)
+                f[0] = (cget(g, u, i + 1, j, k) - u[c]) / dx;
+                f[1] = 0.25 * (DUDY(i, j) + DUDY(i + 1, j) + DUDY(i, j + 1) + DUDY(i + 1, j + 1));
+                f[2] = 0.25 * (DUDZ(i, k) + DUDZ(i + 1, k) + DUDZ(i, k + 1) + DUDZ(i + 1, k + 1));
+                f[3] = 0.25 * (DVDX(i, j) + DVDX(i + 1, j) + DVDX(i, j + 1) + DVDX(i + 1, j + 1));
+                f[4] = (cget(g, v, i, j + 1, k) - v[c]) / dy;
+                f[5] = 0.25 * (DVDZ(j, k) + DVDZ(j + 1, k) + DVDZ(j, k + 1) + DVDZ(j + 1, k + 1));
+                f[6] = 0.25 * (DWDX(i, k) + DWDX(i + 1, k) + DWDX(i, k + 1) + DWDX(i + 1, k + 1));
+                f[7] = 0.25 * (DWDY(j, k) + DWDY(j + 1, k) + DWDY(j, k + 1) + DWDY(j + 1, k + 1));
+                f[8] = (w[CIDX(g, i, j, k + 1)] - w[c]) / g->dz[k];
+                double gb = (k == 0) ? 0.0 : (th[c] - th[CIDX(g, i, j, k - 1)]) / (0.5 * (g->dz[k - 1] + g->dz[k]));
+                double gt = (k == nz - 1) ? 0.0 : (th[CIDX(g, i, j, k + 1)] - th[c]) / (0.5 * (g->dz[k] + g->dz[k + 1]));
+                f[9] = 0.5 * (gb + gt);
+#undef DUDY
+#undef DVDX
+#undef DUDZ
+#undef DVDZ
+#undef DWDX
+#undef DWDY
+            }
+    free(th); free(u); free(v); free(w);
+    return 0;
+}
+
+/* Smagorinsky stress and heat flux at a cell centre from its closure inputs
+ * f[10] and the centred horizontal theta gradients (Sec. 2.3): kinematic
+ * tau_ij = -2 nu_t (S_ij - delta_ij tr S / 3), q_j = -(nu_t / Pr_t) dtheta/dx_j;
+ * returns nu_t |S|^2, the dissipation -tau:S of the deviatoric part. */
+static double centre_smagorinsky(const double *f, double dthx, double dthy, double Cs, double Pr_t,
+                                 double delta, double *t)
+{
+    double s11 = f[0], s22 = f[4], s33 = f[8];
+    double s12 = 0.5 * (f[1] + f[3]), s13 = 0.5 * (f[2] + f[6]), s23 = 0.5 * (f[5] + f[7]);
+    double ss = 2.0 * (s11 * s11 + s22 * s22 + s33 * s33) + 4.0 * (s12 * s12 + s13 * s13 + s23 * s23);
+    double cd = Cs * delta;
+    double nut = cd * cd * sqrt(ss);
+    if (t) {
+        double dd = (s11 + s22 + s33) / 3.0;
+        t[0] = -2.0 * nut * (s11 - dd);
+        t[1] = -2.0 * nut * (s22 - dd);
+        t[2] = -2.0 * nut * (s33 - dd);
+        t[3] = -2.0 * nut * s12;
+        t[4] = -2.0 * nut * s13;
+        t[5] = -2.0 * nut * s23;
+        t[6] = -(nut / Pr_t) * dthx;
+        t[7] = -(nut / Pr_t) * dthy;
+        t[8] = -(nut / Pr_t) * f[9];
+    }
+    return nut * ss;
+}
+
+/* ------------------------------------------------------------------------ */
+/* box filter and SGS targets                                                */
+/* ------------------------------------------------------------------------ */
+int orc_box_filter(const orc_grid *g, const orc_state *S, int32_t r, double Cs, double Pr_t, orc_state *C,
+                   double *targets)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    if (r < 1 || nx % r || ny % r || nz % r) return -2;
+    int cx = nx / r, cy = ny / r, cz = nz / r;
+    size_t n = (size_t)nx * ny * nz, nw = (size_t)nx * ny * (nz + 1);
+    double *th = dalloc(n), *u = dalloc(n), *v = dalloc(n), *w = dalloc(nw);
+    primitives(g, S, th, u, v, w);
+    double *fsgs = NULL;
+    if (Cs > 0.0) {
+        double *feat = dalloc(n * MI);
+        fsgs = dalloc(n * MO);
+        orc_sgs_features(g, S, feat);
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    size_t c = CIDX(g, i, j, k);
+                    double dthx = 0.5 * (cget(g, th, i + 1, j, k) - cget(g, th, i - 1, j, k)) / g->dx;
+                    double dthy = 0.5 * (cget(g, th, i, j + 1, k) - cget(g, th, i, j - 1, k)) / g->dy;
+                    centre_smagorinsky(feat + c * MI, dthx, dthy, Cs, Pr_t, cbrt(g->dx * g->dy * g->dz[k]),
+                                       fsgs + c * MO);
+                }
+        free(feat);
+    }
+    orc_grid cg = {cx, cy, cz, g->dx * r, g->dy * r, NULL};
+    double r3 = (double)r * r * r, r2 = (double)r * r;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int K = 0; K < cz; ++K)
+        for (int J = 0; J < cy; ++J)
+            for (int I = 0; I < cx; ++I) {
+                size_t cc = CIDX(&cg, I, J, K);
+                double mr = 0, mt = 0, su[3] = {0, 0, 0}, sth = 0, suu[6] = {0, 0, 0, 0, 0, 0}, sut[3] = {0, 0, 0};
+                double ssg[MO] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                for (int kk = 0; kk < r; ++kk)
+                    for (int jj = 0; jj < r; ++jj)
+                        for (int ii = 0; ii < r; ++ii) {
+                            int i = I * r + ii, j = J * r + jj, k = K * r + kk;
+                            size_t c = CIDX(g, i, j, k);
+                            mr += S->rho[c];
+                            mt += S->rt[c];
+                            double uc = 0.5 * (u[c] + cget(g, u, i + 1, j, k));
+                            double vc = 0.5 * (v[c] + cget(g, v, i, j + 1, k));
+                            double wc = 0.5 * (w[c] + w[CIDX(g, i, j, k + 1)]);
+                            double t = th[c];
+                            su[0] += uc; su[1] += vc; su[2] += wc; sth += t;
+                            suu[0] += uc * uc; suu[1] += vc * vc; suu[2] += wc * wc;
+                            suu[3] += uc * vc; suu[4] += uc * wc; suu[5] += vc * wc;
+                            sut[0] += uc * t; sut[1] += vc * t; sut[2] += wc * t;
+                            if (fsgs)
+                                for (int o = 0; o < MO; ++o) ssg[o] += fsgs[c * MO + o];
+                        }
+                C->rho[cc] = mr / r3;
+                C->rt[cc] = mt / r3;
+                double mu_[3] = {su[0] / r3, su[1] / r3, su[2] / r3}, mth = sth / r3;
+                double *tg = targets + cc * 9;
+                tg[0] = suu[0] / r3 - mu_[0] * mu_[0];
+                tg[1] = suu[1] / r3 - mu_[1] * mu_[1];
+                tg[2] = suu[2] / r3 - mu_[2] * mu_[2];
+                tg[3] = suu[3] / r3 - mu_[0] * mu_[1];
+                tg[4] = suu[4] / r3 - mu_[0] * mu_[2];
+                tg[5] = suu[5] / r3 - mu_[1] * mu_[2];
+                tg[6] = sut[0] / r3 - mu_[0] * mth;
+                tg[7] = sut[1] / r3 - mu_[1] * mth;
+                tg[8] = sut[2] / r3 - mu_[2] * mth;
+                for (int o = 0; o < MO; ++o) tg[o] += ssg[o] / r3;
+                /* face momenta: mean over the fine faces on the coarse face */
+                double fu = 0, fv = 0, fw = 0;
+                for (int a = 0; a < r; ++a)
+                    for (int b = 0; b < r; ++b) {
+                        fu += S->ru[CIDX(g, I * r, J * r + a, K * r + b)];
+                        fv += S->rv[CIDX(g, I * r + a, J * r, K * r + b)];
+                        fw += S->rw[CIDX(g, I * r + a, J * r + b, K * r)];
+                    }
+                C->ru[cc] = fu / r2;
+                C->rv[cc] = fv / r2;
+                C->rw[cc] = (K == 0) ? 0.0 : fw / r2;
+            }
+    for (int J = 0; J < cy; ++J)
+        for (int I = 0; I < cx; ++I) C->rw[CIDX(&cg, I, J, cz)] = 0.0;
+    free(th); free(u); free(v); free(w); free(fsgs);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* slow right-hand side with the learned closure                            */
+/* ------------------------------------------------------------------------ */
+int orc_slow_rhs_mlp(const orc_grid *g, const orc_params *P, const orc_base *B, const orc_state *S,
+                     const double *params, const double *norm, int bf16, orc_state *R, int64_t *fallback_out)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    size_t n = (size_t)nx * ny * nz, nw = (size_t)nx * ny * (nz + 1);
+    if (P->nu_m != 0.0 || P->alpha_m != 0.0) return -5;
+    /* resolved terms: the same right-hand side without any stress */
+    orc_params Q = *P;
+    Q.sgs = 0;
+    int rc = orc_slow_rhs(g, &Q, B, S, R);
+    if (rc) return rc;
+    double *feat = dalloc(n * MI), *xs = dalloc(n * MI), *ys = dalloc(n * MO);
+    double *th = dalloc(n), *u = dalloc(n), *v = dalloc(n), *w = dalloc(nw);
+    primitives(g, S, th, u, v, w);
+    orc_sgs_features(g, S, feat);
+    const double *mx = norm, *sx = norm + MI, *my = norm + 2 * MI, *sy = norm + 2 * MI + MO;
+    for (size_t c = 0; c < n; ++c)
+        for (int f = 0; f < MI; ++f) xs[c * MI + f] = (feat[c * MI + f] - mx[f]) / sx[f];
+    orc_mlp_forward(params, xs, (int64_t)n, ys, bf16);
+    /* rho tau and rho q at centres, with the per-cell Smagorinsky fallback */
+    double *T = dalloc(n * MO);
+    int64_t nfb = 0;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                const double *f = feat + c * MI;
+                double t[MO];
+                int finite = 1;
+                for (int o = 0; o < MO; ++o) {
+                    t[o] = ys[c * MO + o] * sy[o] + my[o];
+                    if (!isfinite(t[o])) finite = 0;
+                }
+                double s11 = f[0], s22 = f[4], s33 = f[8];
+                double s12 = 0.5 * (f[1] + f[3]), s13 = 0.5 * (f[2] + f[6]), s23 = 0.5 * (f[5] + f[7]);
+                double dthx = 0.5 * (cget(g, th, i + 1, j, k) - cget(g, th, i - 1, j, k)) / g->dx;
+                double dthy = 0.5 * (cget(g, th, i, j + 1, k) - cget(g, th, i, j - 1, k)) / g->dy;
+                double ts[MO];
+                double diss_smag = centre_smagorinsky(f, dthx, dthy, P->Cs, P->Pr_t, cbrt(g->dx * g->dy * g->dz[k]), ts);
+                /* energy transfer to the subgrid scales, -tau:S */
+                double pi_mlp = -(t[0] * s11 + t[1] * s22 + t[2] * s33 + 2.0 * (t[3] * s12 + t[4] * s13 + t[5] * s23));
+                if (!finite || pi_mlp < -2.0 * diss_smag) {
+                    for (int o = 0; o < MO; ++o) t[o] = ts[o];
+                    ++nfb;
+                }
+                for (int o = 0; o < MO; ++o) T[c * MO + o] = S->rho[c] * t[o];
+            }
+    /* divergence on the staggered points (4-cell means on edges, 2-cell means on faces) */
+#define TT(ii, jj, kk, o) (T[CIDX(g, wrap(ii, nx), wrap(jj, ny), kk) * MO + (o)])
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                /* tau_12 on xy-edge (x-face ii, y-face jj) */
+#define E12(ii, jj) (0.25 * (TT((ii) - 1, (jj) - 1, k, 3) + TT(ii, (jj) - 1, k, 3) + TT((ii) - 1, jj, k, 3) + TT(ii, jj, k, 3)))
+#define E13(ii, kk) (((kk) <= 0 || (kk) >= nz) ? 0.0 : 0.25 * (TT((ii) - 1, j, (kk) - 1, 4) + TT(ii, j, (kk) - 1, 4) + TT((ii) - 1, j, kk, 4) + TT(ii, j, kk, 4)))
+#define E23(jj, kk) (((kk) <= 0 || (kk) >= nz) ? 0.0 : 0.25 * (TT(i, (jj) - 1, (kk) - 1, 5) + TT(i, jj, (kk) - 1, 5) + TT(i, (jj) - 1, kk, 5) + TT(i, jj, kk, 5)))
+                R->ru[c] -= (TT(i, j, k, 0) - TT(i - 1, j, k, 0)) / g->dx + (E12(i, j + 1) - E12(i, j)) / g->dy +
+                            (E13(i, k + 1) - E13(i, k)) / g->dz[k];
+                R->rv[c] -= (E12(i + 1, j) - E12(i, j)) / g->dx + (TT(i, j, k, 1) - TT(i, j - 1, k, 1)) / g->dy +
+                            (E23(j, k + 1) - E23(j, k)) / g->dz[k];
+                if (k > 0)
+                    R->rw[c] -= (E13(i + 1, k) - E13(i, k)) / g->dx + (E23(j + 1, k) - E23(j, k)) / g->dy +
+                                (TT(i, j, k, 2) - TT(i, j, k - 1, 2)) / (0.5 * (g->dz[k - 1] + g->dz[k]));
+                /* heat: face fluxes as 2-cell means, zero through the lids */
+                double hx0 = 0.5 * (TT(i - 1, j, k, 6) + TT(i, j, k, 6)), hx1 = 0.5 * (TT(i, j, k, 6) + TT(i + 1, j, k, 6));
+                double hy0 = 0.5 * (TT(i, j - 1, k, 7) + TT(i, j, k, 7)), hy1 = 0.5 * (TT(i, j, k, 7) + TT(i, j + 1, k, 7));
+                double hz0 = (k == 0) ? 0.0 : 0.5 * (TT(i, j, k - 1, 8) + TT(i, j, k, 8));
+                double hz1 = (k == nz - 1) ? 0.0 : 0.5 * (TT(i, j, k, 8) + TT(i, j, k + 1, 8));
+                R->rt[c] -= (hx1 - hx0) / g->dx + (hy1 - hy0) / g->dy + (hz1 - hz0) / g->dz[k];
+#undef E12
+#undef E13
+#undef E23
+            }
+#undef TT
+    if (fallback_out) *fallback_out = nfb;
+    free(feat); free(xs); free(ys); free(th); free(u); free(v); free(w); free(T);
     return 0;
 }

@@ -40,12 +40,15 @@ typedef struct {
     int32_t adv_order_v;    /* 2..6                                            */
     int32_t scalar_scheme;  /* 0: same interpolants as momentum; 1: WENO5-JS   */
     int32_t n_scalars;
-    int32_t sgs;            /* 0 none, 1 Smagorinsky                            */
+    int32_t sgs;            /* 0 none, 1 Smagorinsky, 2 learned closure (MLP)   */
     double Cs, Pr_t;
     double nu_m, alpha_m;   /* constant kinematic viscosity / diffusivity       */
     double f_cor, Ug, Vg;   /* f-plane Coriolis and geostrophic wind           */
     double surf_heat_flux;  /* kinematic, K m/s                                 */
     double grav;            /* magnitude of gravity                             */
+    /* learned closure (sgs == 2): parameters, norm stats, BF16 emulation */
+    const double *mlp_params, *mlp_norm;
+    int32_t mlp_bf16;
 } orc_params;
 
 typedef struct {
@@ -106,6 +109,48 @@ int orc_rk3_step(const orc_grid *g, const orc_params *P, const orc_base *B, orc_
  * masses. */
 int orc_diagnostics(const orc_grid *g, const orc_params *P, const orc_base *B,
                     const orc_state *S, double *out);
+
+/* ---------------- learned SGS closure (MLP 10 -> 64 -> 64 -> 64 -> 9) ---------------- */
+/* Parameters, flat: W1[10][64], b1[64], W2[64][64], b2[64], W3[64][64], b3[64],
+ * W4[64][9], b4[9] (row = input feature, column = output unit); 9609 values.
+ * Norm stats: mean_x[10], std_x[10], mean_y[9], std_y[9]. */
+int orc_mlp_nparams(void);
+/* Forward pass on standardised inputs x[n][10] -> standardised outputs y[n][9].
+ * bf16 = 1 rounds every matrix operand to bfloat16 (through float, round to
+ * nearest even) and accumulates in double, as the GPU's BF16 products do. */
+int orc_mlp_forward(const double *params, const double *x, int64_t n, double *y, int bf16);
+/* Mean-squared error over n samples x 9 outputs and its gradient (9609). */
+int orc_mlp_loss_grad(const double *params, const double *x, const double *t, int64_t n, int bf16,
+                      double *loss, double *grad);
+/* One Adam step (beta1, beta2, eps), step counts from 1. */
+int orc_adam(double *params, const double *grad, double *m, double *v, int64_t np, int64_t step,
+             double lr, double beta1, double beta2, double eps);
+/* Round to bfloat16 through float (round to nearest even). */
+double orc_bf16(double x);
+
+/* The 10 closure inputs at every cell centre: du/dx, du/dy, du/dz, dv/dx,
+ * dv/dy, dv/dz, dw/dx, dw/dy, dw/dz, dtheta/dz; feat[n][10] (cell order). */
+int orc_sgs_features(const orc_grid *g, const orc_state *S, double *feat);
+/* Box filter by an integer factor r (nx, ny, nz divisible by r) onto the
+ * coarse grid (dz summed over blocks): rho and rho*theta as block means, face
+ * momenta as means over the r x r fine faces on each coarse face (conservative
+ * restriction), and the SGS targets from cell-centre velocities and theta,
+ * tau_ij = <u_i u_j> - <u_i><u_j> (11,22,33,12,13,23) and
+ * q_j = <u_j theta> - <u_j><theta> (1,2,3), targets[nc][9].  With Cs > 0 the
+ * block mean of the fine grid's own Smagorinsky stress and heat flux (built at
+ * centres from the closure inputs, Prandtl number Pr_t) is added. */
+int orc_box_filter(const orc_grid *g, const orc_state *S, int32_t r, double Cs, double Pr_t,
+                   orc_state *coarse, double *targets);
+
+/* Slow right-hand side with the learned closure in place of the Smagorinsky
+ * stresses: the MLP gives kinematic tau_ij and q_j at cell centres; stresses
+ * rho tau act on the staggered points by 4-cell (2-cell) averages; a cell falls
+ * back to Smagorinsky when its output is not finite or its backscatter exceeds
+ * twice the Smagorinsky dissipation.  norm = mean_x, std_x, mean_y, std_y.
+ * P->sgs must be 2.  fallback_out (nullable) receives the number of fallback
+ * cells. */
+int orc_slow_rhs_mlp(const orc_grid *g, const orc_params *P, const orc_base *B, const orc_state *S,
+                     const double *params, const double *norm, int bf16, orc_state *R, int64_t *fallback_out);
 
 #ifdef __cplusplus
 }
