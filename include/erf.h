@@ -55,7 +55,10 @@ typedef enum {
 } erf_status;
 
 typedef enum { ERF_FP64 = 0, ERF_FP32_MIXED = 1 } erf_precision;
-typedef enum { ERF_SGS_NONE = 0, ERF_SGS_SMAGORINSKY = 1 } erf_sgs_model;
+/* ERF_SGS_MLP: the learned closure of erf_mlp.h in place of the Smagorinsky
+ * stresses; needs erf_mlp_set_weights before the first right-hand side, and
+ * nu_m = alpha_m = 0, n_scalars = 0. */
+typedef enum { ERF_SGS_NONE = 0, ERF_SGS_SMAGORINSKY = 1, ERF_SGS_MLP = 2 } erf_sgs_model;
 typedef enum { ERF_SCALAR_INTERP = 0, ERF_SCALAR_WENO5 = 1 } erf_scalar_scheme;
 
 typedef struct {
@@ -169,7 +172,8 @@ erf_status erf_diagnostics(erf_ctx *ctx, const erf_state *S, erf_diag *out);
  * kernel is bracketed by two HIP events recorded on the context's stream; up to
  * max_launches launches are timed, later ones run untimed.  Kernel names:
  * "prep", "mut", "stress", "rhs", "stage_init", "coef", "substep", "finalize",
- * "mixing_ratio", "scalar".  erf_timing_begin allocates the events
+ * "mixing_ratio", "scalar", "mlp" (closure network), "mlp_div" (its stress
+ * divergence).  erf_timing_begin allocates the events
  * (ERF_E_NOMEM on failure) and returns ERF_E_ARG for an unknown name. */
 erf_status erf_timing_begin(erf_ctx *ctx, const char *kernel, int32_t max_launches);
 /* Waits for the stream, returns the summed event time [ms] of the timed

@@ -104,7 +104,8 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     if (prm->adv_order_h < 2 || prm->adv_order_h > 6 || prm->adv_order_v < 2 || prm->adv_order_v > 6)
         return ERF_E_ARG;
     if (nq < 0 || nq > 8) return ERF_E_ARG;
-    if (prm->sgs != ERF_SGS_NONE && prm->sgs != ERF_SGS_SMAGORINSKY) return ERF_E_ARG;
+    if (prm->sgs != ERF_SGS_NONE && prm->sgs != ERF_SGS_SMAGORINSKY && prm->sgs != ERF_SGS_MLP) return ERF_E_ARG;
+    if (prm->sgs == ERF_SGS_MLP && (prm->nu_m != 0.0 || prm->alpha_m != 0.0)) return ERF_E_UNSUPPORTED;
     if (prm->scalar_scheme != ERF_SCALAR_INTERP && prm->scalar_scheme != ERF_SCALAR_WENO5) return ERF_E_ARG;
     if (prm->precision != ERF_FP64 && prm->precision != ERF_FP32_MIXED) return ERF_E_ARG;
     if (nq > 0 && (prm->sgs != ERF_SGS_NONE || prm->alpha_m != 0.0)) return ERF_E_UNSUPPORTED;
@@ -134,6 +135,7 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     Base &b = c->base;
     const size_t N = n * es, Wb = w * es, Q = q * es, D = sizeof(double);
     const size_t nzs = (size_t)grid->nz;
+    const size_t G = prm->sgs == ERF_SGS_MLP ? N : 0;
     Req reqs[] = {
         {&ws.sa[0], N}, {&ws.sa[1], N}, {&ws.sa[2], N}, {&ws.sa[3], N}, {&ws.sa[4], Wb}, {&ws.sa[5], Q},
         {&ws.sb[0], N}, {&ws.sb[1], N}, {&ws.sb[2], N}, {&ws.sb[3], N}, {&ws.sb[4], Wb}, {&ws.sb[5], Q},
@@ -147,6 +149,8 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
         {&ws.cC, Wb}, {(void **)&ws.ca, w * D}, {(void **)&ws.cb, w * D}, {(void **)&ws.cc, w * D},
         {&ws.q, Q}, {&ws.fu, N}, {&ws.fv, N}, {&ws.fw, Wb},
         {(void **)&ws.diag, diag_slots_needed() * D},
+        {&ws.sg[0], G}, {&ws.sg[1], G}, {&ws.sg[2], G}, {&ws.sg[3], G}, {&ws.sg[4], G}, {&ws.sg[5], G},
+        {&ws.sg[6], G}, {&ws.sg[7], G}, {&ws.sg[8], G},
         {(void **)&b.rho0, nzs * D}, {(void **)&b.theta0, nzs * D}, {(void **)&b.Theta0, nzs * D},
         {(void **)&b.p0, nzs * D}, {(void **)&b.pi0, nzs * D}, {(void **)&b.dz, (4 * nzs + 1) * D},
     };
@@ -193,10 +197,10 @@ void erf_destroy(erf_ctx *c)
     if (!c) return;
     for (auto &x : c->timing_events)
         if (x) (void)hipEventDestroy(x);
-    if (c->arena) {
-        (void)hipStreamSynchronize(c->stream);
-        (void)hipFree(c->arena);
-    }
+    if (c->arena || c->mlp.alloc || c->mlp.talloc) (void)hipStreamSynchronize(c->stream);
+    if (c->arena) (void)hipFree(c->arena);
+    if (c->mlp.alloc) (void)hipFree(c->mlp.alloc);
+    if (c->mlp.talloc) (void)hipFree(c->mlp.talloc);
     delete[] c->dz_host;
     delete c;
 }
@@ -246,6 +250,8 @@ erf_status erf_slow_rhs(erf_ctx *c, const erf_state *S, erf_state *R)
     ERF_CHECK_CTX(c);
     if (!c->have_base) return fail(c, ERF_E_STATE, "erf_init_base_state must come first");
     if (!state_ok(S, false, 0) || !state_ok(R, false, 0)) return fail(c, ERF_E_ARG, "null field pointer");
+    if (c->prm.sgs == ERF_SGS_MLP && !c->mlp.have_weights)
+        return fail(c, ERF_E_STATE, "erf_mlp_set_weights must precede the learned closure");
     const void *s5[5] = {S->rho, S->rhotheta, S->rhou, S->rhov, S->rhow};
     void *r5[5] = {R->rho, R->rhotheta, R->rhou, R->rhov, R->rhow};
     hipError_t e = launch_slow_rhs(c, s5, r5);

@@ -24,6 +24,15 @@ constexpr double kCv = kCp - kRd;
 constexpr double kGamma = kCp / (kCp - kRd);
 constexpr double kP00 = 1.0e5;
 
+// learned closure: 10 -> 64 -> 64 -> 64 -> 9, parameters W1[10][64], b1,
+// W2[64][64], b2, W3[64][64], b3, W4[64][9], b4 (row = input unit)
+constexpr int kMlpIn = 10, kMlpH = 64, kMlpOut = 9;
+constexpr int kMlpW1 = 0, kMlpB1 = kMlpW1 + kMlpIn * kMlpH, kMlpW2 = kMlpB1 + kMlpH;
+constexpr int kMlpB2 = kMlpW2 + kMlpH * kMlpH, kMlpW3 = kMlpB2 + kMlpH, kMlpB3 = kMlpW3 + kMlpH * kMlpH;
+constexpr int kMlpW4 = kMlpB3 + kMlpH, kMlpB4 = kMlpW4 + kMlpH * kMlpOut, kMlpParams = kMlpB4 + kMlpOut;
+constexpr int kMlpNorm = 2 * kMlpIn + 2 * kMlpOut;
+static_assert(kMlpParams == 9609, "parameter layout");
+
 struct Dims {
     int nx, ny, nz;
     int nxy;  // nx * ny, one horizontal plane
@@ -147,6 +156,29 @@ struct Workspace {
     void *fu = nullptr, *fv = nullptr, *fw = nullptr;
     // diagnostics partial sums
     double *diag = nullptr;
+    // learned closure: rho tau_11, 22, 33, 12, 13, 23 and rho q_1, 2, 3 at
+    // centres (allocated for the learned closure only)
+    void *sg[9] = {};
+};
+
+// Learned-closure state: FP32 master parameters with Adam moments, the BF16
+// operands packed for the matrix cores, biases, input/output statistics, the
+// running count of cells that fell back to Smagorinsky, and training buffers.
+struct MlpState {
+    void *alloc = nullptr;
+    float *master = nullptr, *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
+    void *wpk = nullptr;            // 22 operands x 64 lanes x 16 bytes
+    float *bias = nullptr;          // b1, b2, b3, b4 padded to 16: 208
+    double *norm = nullptr;         // mean_x[10], std_x[10], mean_y[9], std_y[9]
+    unsigned long long *fallbacks = nullptr;
+    double *loss = nullptr;
+    bool have_weights = false;
+    int64_t step = 0;
+    // training activations and partials, grown on demand
+    void *talloc = nullptr;
+    int64_t cap = 0;
+    float *tbuf = nullptr, *tpart = nullptr;
+    double *tdpart = nullptr;
 };
 
 struct Base {
@@ -171,6 +203,7 @@ struct erf_ctx {
     double *dz_host = nullptr;
     erfk::Base base;
     erfk::Workspace ws;
+    erfk::MlpState mlp;
     bool have_base = false;
     erf_status sticky = ERF_OK;
     std::string err;
@@ -186,11 +219,12 @@ struct erf_ctx {
 namespace erfk {
 
 // kernel ids for the timing instrumentation
-enum KernelId { K_PREP, K_MUT, K_STRESS, K_RHS, K_STAGE_INIT, K_COEF, K_SUBSTEP, K_FINALIZE, K_MIXRATIO, K_SCALAR, K_COUNT };
+enum KernelId { K_PREP, K_MUT, K_STRESS, K_RHS, K_STAGE_INIT, K_COEF, K_SUBSTEP, K_FINALIZE, K_MIXRATIO, K_SCALAR,
+                K_MLP, K_MLP_DIV, K_COUNT };
 inline const char *kernel_name(int id)
 {
     static const char *names[K_COUNT] = {"prep", "mut", "stress", "rhs", "stage_init", "coef", "substep",
-                                         "finalize", "mixing_ratio", "scalar"};
+                                         "finalize", "mixing_ratio", "scalar", "mlp", "mlp_div"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 // bracket a launch with events when its kernel is being timed
@@ -212,6 +246,8 @@ inline void timing_stop(erf_ctx *c, int id)
 // ---------------------------------------------------------------------------
 // rhs.hip
 hipError_t launch_slow_rhs(erf_ctx *c, const void *const S[5], void *const R[5]);
+// primitive fields of S (theta, p', u, v, w) into the workspace only
+hipError_t launch_prep(erf_ctx *c, const void *const S[5]);
 // acoustic.hip
 hipError_t launch_acoustic_stage(erf_ctx *c, const void *const Sn[5], const void *const St[5],
                                  const void *const Rt[5], int n_sub, double dtau, void *const Sout[5],
@@ -219,6 +255,23 @@ hipError_t launch_acoustic_stage(erf_ctx *c, const void *const Sn[5], const void
 // scalars.hip
 hipError_t launch_scalar_advance(erf_ctx *c, const void *rqn, const void *rho_t, const void *rq_t,
                                  const void *Fu, const void *Fv, const void *Fw, double dts, void *rq_out);
+// mlp.hip
+hipError_t mlp_pack(erf_ctx *c);
+hipError_t launch_mlp_closure(erf_ctx *c, const void *rho, void *const R[5]);
+hipError_t launch_mlp_forward(erf_ctx *c, const float *x, int64_t n, float *y);
+hipError_t launch_features(erf_ctx *c, double *feat);
+hipError_t launch_box_filter(erf_ctx *c, const void *const S[5], int r, double Cs, double Pr_t,
+                             double *const C[5], double *targets);
+size_t stat_partials(int64_t n);
+hipError_t launch_col_stats(erf_ctx *c, const double *X, int64_t n, int ncol, double *mean, double *sd,
+                            double *part);
+hipError_t launch_standardize(erf_ctx *c, const double *X, int64_t n, int ncol, const double *mean,
+                              const double *sd, float *out);
+size_t train_floats(int64_t cap);
+size_t train_partial_floats();
+size_t train_partial_doubles(int64_t cap);
+hipError_t launch_loss_grad(erf_ctx *c, const float *X, const float *T, int64_t n, float *G, double *loss_dev);
+hipError_t launch_adam(erf_ctx *c, double lr, int64_t step);
 // diag.hip
 size_t diag_slots_needed();
 hipError_t launch_diagnostics(erf_ctx *c, const void *const S[6], double *host_out);

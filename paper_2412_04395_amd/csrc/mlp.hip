@@ -1,0 +1,1040 @@
+// mlp.hip -- learned subgrid closure: a 10 -> 64 -> 64 -> 64 -> 9 ReLU network
+// that maps the resolved velocity-gradient tensor and dtheta/dz at a cell
+// centre to the kinematic subgrid stresses tau_ij and heat fluxes q_j, used in
+// place of the Smagorinsky stresses of Sec. 2.3 (the paper names learned
+// surrogates only as future work, Sec. 6).
+//
+// Matrix products run on the CDNA matrix cores: v_mfma_f32_16x16x32_bf16
+// (BF16 operands, FP32 accumulation).  The network is evaluated in the
+// transposed form H^T = W^T X^T: hidden units are the MFMA rows, cells the
+// columns, so a layer's FP32 result (lane l: cell l%16, units 4*(l/16)+r of
+// each 16-unit tile) is already in the place of the next layer's B operand,
+// with the K index permuted: K-step s, lane group g, slot i stands for input
+// unit 32s + 4g + i (i < 4) or 32s + 16 + 4g + i - 4 (i >= 4).  The weights are
+// packed once into A operands with the same permutation, so no value crosses
+// lanes between layers.
+//
+// Everything around the products (closure inputs, de-standardisation, the
+// Smagorinsky fallback, the stress divergence) is FP64, like the rest of the
+// slow right-hand side.
+#include <cmath>
+
+#include "erf_internal.h"
+
+namespace erfk {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int cidx(const Dims &d, int i, int j, int k) { return (k * d.ny + j) * d.nx + i; }
+
+// float -> bfloat16 bits, round to nearest even (infinities and overflow to
+// infinity follow from the carry into the exponent; NaN stays a quiet NaN)
+__device__ __forceinline__ unsigned int bf16_bits(float f)
+{
+    unsigned int u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ unsigned int pack2(float a, float b) { return bf16_bits(a) | (bf16_bits(b) << 16); }
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ __forceinline__ floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// K-step operand from two 16-unit tiles: ReLU, then BF16
+__device__ __forceinline__ bf16x8 relu_pack(floatx4 lo, floatx4 hi)
+{
+    u32x4 v;
+    v.x = pack2(fmaxf(lo[0], 0.f), fmaxf(lo[1], 0.f));
+    v.y = pack2(fmaxf(lo[2], 0.f), fmaxf(lo[3], 0.f));
+    v.z = pack2(fmaxf(hi[0], 0.f), fmaxf(hi[1], 0.f));
+    v.w = pack2(fmaxf(hi[2], 0.f), fmaxf(hi[3], 0.f));
+    return as_bf16x8(v);
+}
+
+// the input unit that K-step s, lane group g, slot i of a hidden layer stands for
+__device__ __forceinline__ int perm_unit(int s, int g, int i) { return 32 * s + (i < 4 ? 4 * g + i : 16 + 4 * g + i - 4); }
+
+// ---------------------------------------------------------------------------
+// weight packing: master FP32 parameters -> 22 A operands x 64 lanes (BF16)
+// ---------------------------------------------------------------------------
+// operands 0..3: layer 1 tiles; 4..11: layer 2 (tile t, K-step s at 4 + 2t + s);
+// 12..19: layer 3; 20..21: layer 4 (K-steps 0, 1).  Biases: float[208] =
+// b1, b2, b3, b4 padded to 16.
+__global__ __launch_bounds__(64) void k_mlp_pack(const float *__restrict__ P, u32x4 *__restrict__ wpk,
+                                                 float *__restrict__ bias)
+{
+    const int o = blockIdx.x, l = threadIdx.x, g = l >> 4, r = l & 15;
+    float v[8];
+    for (int i = 0; i < 8; ++i) {
+        float x = 0.f;
+        if (o < 4) {
+            const int f = 8 * g + i, unit = 16 * o + r;
+            x = f < kMlpIn ? P[kMlpW1 + f * kMlpH + unit] : 0.f;
+        } else if (o < 20) {
+            const int base = o < 12 ? kMlpW2 : kMlpW3, q = (o - 4) & 7, t = q >> 1, s = q & 1;
+            x = P[base + perm_unit(s, g, i) * kMlpH + 16 * t + r];
+        } else {
+            const int s = o - 20;
+            x = r < kMlpOut ? P[kMlpW4 + perm_unit(s, g, i) * kMlpOut + r] : 0.f;
+        }
+        v[i] = x;
+    }
+    u32x4 w;
+    w.x = pack2(v[0], v[1]);
+    w.y = pack2(v[2], v[3]);
+    w.z = pack2(v[4], v[5]);
+    w.w = pack2(v[6], v[7]);
+    wpk[o * 64 + l] = w;
+    if (o == 0) {
+        for (int u = l; u < 208; u += 64) {
+            float b;
+            if (u < 64) b = P[kMlpB1 + u];
+            else if (u < 128) b = P[kMlpB2 + u - 64];
+            else if (u < 192) b = P[kMlpB3 + u - 128];
+            else b = (u - 192) < kMlpOut ? P[kMlpB4 + u - 192] : 0.f;
+            bias[u] = b;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the network on 64 samples of one wave
+// ---------------------------------------------------------------------------
+// xs: 64 rows of 16 BF16 inputs (10 used) as two u32x4 each; ys: 64 rows of 12
+// floats (9 used).  W: the wave's 22 packed operands; bias in LDS.
+struct WaveWeights {
+    bf16x8 w[22];
+};
+
+__device__ __forceinline__ void load_weights(WaveWeights &W, const u32x4 *__restrict__ wpk, int lane)
+{
+#pragma unroll
+    for (int o = 0; o < 22; ++o) W.w[o] = as_bf16x8(wpk[o * 64 + lane]);
+}
+
+__device__ __forceinline__ floatx4 bias4(const float *b, int g)
+{
+    floatx4 c;
+    c[0] = b[4 * g];
+    c[1] = b[4 * g + 1];
+    c[2] = b[4 * g + 2];
+    c[3] = b[4 * g + 3];
+    return c;
+}
+
+__device__ __forceinline__ floatx4 mlp16(const WaveWeights &W, const float *bias, bf16x8 x, int g)
+{
+    floatx4 h[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) h[t] = mfma(W.w[t], x, bias4(bias + 16 * t, g));
+    bf16x8 b0 = relu_pack(h[0], h[1]), b1 = relu_pack(h[2], h[3]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) h[t] = mfma(W.w[5 + 2 * t], b1, mfma(W.w[4 + 2 * t], b0, bias4(bias + 64 + 16 * t, g)));
+    b0 = relu_pack(h[0], h[1]);
+    b1 = relu_pack(h[2], h[3]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        h[t] = mfma(W.w[13 + 2 * t], b1, mfma(W.w[12 + 2 * t], b0, bias4(bias + 128 + 16 * t, g)));
+    b0 = relu_pack(h[0], h[1]);
+    b1 = relu_pack(h[2], h[3]);
+    return mfma(W.w[21], b1, mfma(W.w[20], b0, bias4(bias + 192, g)));
+}
+
+// xs/ys are this wave's LDS rows; the caller synchronises around the call
+__device__ __forceinline__ void mlp64(const WaveWeights &W, const float *bias, const u32x4 *xs, float *ys, int lane)
+{
+    const int g = lane >> 4, col = lane & 15;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int row = 16 * q + col;
+        const u32x4 zero = {0u, 0u, 0u, 0u};
+        const bf16x8 x = as_bf16x8(g < 2 ? xs[2 * row + g] : zero);
+        const floatx4 y = mlp16(W, bias, x, g);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (4 * g + r < kMlpOut) ys[row * 12 + 4 * g + r] = y[r];
+    }
+}
+
+// standardised inputs x[10] -> LDS row (BF16, zero padded)
+__device__ __forceinline__ void store_inputs(u32x4 *xs, int lane, const float x[10])
+{
+    u32x4 a, b;
+    a.x = pack2(x[0], x[1]);
+    a.y = pack2(x[2], x[3]);
+    a.z = pack2(x[4], x[5]);
+    a.w = pack2(x[6], x[7]);
+    b.x = pack2(x[8], x[9]);
+    b.y = 0u;
+    b.z = 0u;
+    b.w = 0u;
+    xs[2 * lane] = a;
+    xs[2 * lane + 1] = b;
+}
+
+// ---------------------------------------------------------------------------
+// closure inputs at a cell centre (FP64)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct ClosureIn {
+    Dims d;
+    double idx, idy;
+    const double *idz, *idzf, *theta0;
+    const T *u, *v, *w, *th;
+};
+
+template <typename T>
+__device__ __forceinline__ double theta_full(const ClosureIn<T> &a, int c, int k)
+{
+    return kPert<T> ? (double)a.th[c] + a.theta0[k] : (double)a.th[c];
+}
+
+// du/dx, du/dy, du/dz, dv/dx, dv/dy, dv/dz, dw/dx, dw/dy, dw/dz, dtheta/dz:
+// diagonal terms across the cell, off-diagonal ones as the mean of the four
+// edge differences around the centre (zero on lid edges for du/dz, dv/dz,
+// dw/dx, dw/dy), dtheta/dz as the mean of the two face differences (zero
+// through the lids); also the centred horizontal theta gradients.
+template <typename T>
+__device__ void closure_inputs(const ClosureIn<T> &a, int i, int j, int k, double f[10], double &dthx, double &dthy)
+{
+    const Dims &d = a.d;
+    const int nz = d.nz, P = d.nxy;
+    const int im = wrap_idx(i - 1, d.nx), ip = wrap_idx(i + 1, d.nx);
+    const int jm = wrap_idx(j - 1, d.ny), jp = wrap_idx(j + 1, d.ny);
+    const int c = cidx(d, i, j, k);
+    auto U = [&](int ii, int jj, int kk) { return (double)a.u[cidx(d, ii, jj, kk)]; };
+    auto V = [&](int ii, int jj, int kk) { return (double)a.v[cidx(d, ii, jj, kk)]; };
+    auto Wf = [&](int ii, int jj, int kk) { return (double)a.w[cidx(d, ii, jj, kk)]; };
+    f[0] = (U(ip, j, k) - U(i, j, k)) * a.idx;
+    f[4] = (V(i, jp, k) - V(i, j, k)) * a.idy;
+    f[8] = (Wf(i, j, k + 1) - Wf(i, j, k)) * a.idz[k];
+    // du/dy on the edges (x-face ii, y-face jj)
+    auto dudy = [&](int ii, int jj) { return (U(ii, jj, k) - U(ii, wrap_idx(jj - 1, d.ny), k)) * a.idy; };
+    auto dvdx = [&](int ii, int jj) { return (V(ii, jj, k) - V(wrap_idx(ii - 1, d.nx), jj, k)) * a.idx; };
+    f[1] = 0.25 * (dudy(i, j) + dudy(ip, j) + dudy(i, jp) + dudy(ip, jp));
+    f[3] = 0.25 * (dvdx(i, j) + dvdx(ip, j) + dvdx(i, jp) + dvdx(ip, jp));
+    auto dudz = [&](int ii, int kk) {
+        return (kk <= 0 || kk >= nz) ? 0.0 : (U(ii, j, kk) - U(ii, j, kk - 1)) * a.idzf[kk];
+    };
+    auto dvdz = [&](int jj, int kk) {
+        return (kk <= 0 || kk >= nz) ? 0.0 : (V(i, jj, kk) - V(i, jj, kk - 1)) * a.idzf[kk];
+    };
+    auto dwdx = [&](int ii, int kk) {
+        return (kk <= 0 || kk >= nz) ? 0.0 : (Wf(ii, j, kk) - Wf(wrap_idx(ii - 1, d.nx), j, kk)) * a.idx;
+    };
+    auto dwdy = [&](int jj, int kk) {
+        return (kk <= 0 || kk >= nz) ? 0.0 : (Wf(i, jj, kk) - Wf(i, wrap_idx(jj - 1, d.ny), kk)) * a.idy;
+    };
+    f[2] = 0.25 * (dudz(i, k) + dudz(ip, k) + dudz(i, k + 1) + dudz(ip, k + 1));
+    f[5] = 0.25 * (dvdz(j, k) + dvdz(jp, k) + dvdz(j, k + 1) + dvdz(jp, k + 1));
+    f[6] = 0.25 * (dwdx(i, k) + dwdx(ip, k) + dwdx(i, k + 1) + dwdx(ip, k + 1));
+    f[7] = 0.25 * (dwdy(j, k) + dwdy(jp, k) + dwdy(j, k + 1) + dwdy(jp, k + 1));
+    const double tc = theta_full(a, c, k);
+    const double gb = k == 0 ? 0.0 : (tc - theta_full(a, c - P, k - 1)) * a.idzf[k];
+    const double gt = k == nz - 1 ? 0.0 : (theta_full(a, c + P, k + 1) - tc) * a.idzf[k + 1];
+    f[9] = 0.5 * (gb + gt);
+    dthx = 0.5 * (theta_full(a, cidx(d, ip, j, k), k) - theta_full(a, cidx(d, im, j, k), k)) * a.idx;
+    dthy = 0.5 * (theta_full(a, cidx(d, i, jp, k), k) - theta_full(a, cidx(d, i, jm, k), k)) * a.idy;
+}
+
+// Smagorinsky stresses and heat fluxes at a centre from the closure inputs:
+// tau = -2 nu_t (S - tr S / 3), q = -(nu_t / Pr_t) grad theta; returns the
+// dissipation nu_t |S|^2.
+__device__ __forceinline__ double centre_smag(const double f[10], double dthx, double dthy, double cd, double Pr_t,
+                                              double t[9])
+{
+    const double s11 = f[0], s22 = f[4], s33 = f[8];
+    const double s12 = 0.5 * (f[1] + f[3]), s13 = 0.5 * (f[2] + f[6]), s23 = 0.5 * (f[5] + f[7]);
+    const double ss = 2.0 * (s11 * s11 + s22 * s22 + s33 * s33) + 4.0 * (s12 * s12 + s13 * s13 + s23 * s23);
+    const double nut = cd * cd * sqrt(ss);
+    const double dd = (s11 + s22 + s33) / 3.0;
+    t[0] = -2.0 * nut * (s11 - dd);
+    t[1] = -2.0 * nut * (s22 - dd);
+    t[2] = -2.0 * nut * (s33 - dd);
+    t[3] = -2.0 * nut * s12;
+    t[4] = -2.0 * nut * s13;
+    t[5] = -2.0 * nut * s23;
+    t[6] = -(nut / Pr_t) * dthx;
+    t[7] = -(nut / Pr_t) * dthy;
+    t[8] = -(nut / Pr_t) * f[9];
+    return nut * ss;
+}
+
+// ---------------------------------------------------------------------------
+// closure: inputs -> network -> stresses rho tau, rho q at centres
+// ---------------------------------------------------------------------------
+template <typename T>
+struct ClosureArgs {
+    ClosureIn<T> in;
+    double dx, dy, Cs, Pr_t;
+    const double *dz, *rho0, *norm;  // norm: mean_x[10], std_x[10], mean_y[9], std_y[9]
+    const T *rho;
+    const u32x4 *wpk;
+    const float *bias;
+    T *out[9];
+    unsigned long long *fallbacks;
+};
+
+constexpr int kClosureBlock = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kClosureBlock) void k_mlp_closure(ClosureArgs<T> a)
+{
+    __shared__ u32x4 xs_all[4][128];
+    __shared__ float ys_all[4][64 * 12];
+    __shared__ float bias[208];
+    __shared__ double nrm[38];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int u = threadIdx.x; u < 208; u += kClosureBlock) bias[u] = a.bias[u];
+    for (int u = threadIdx.x; u < 38; u += kClosureBlock) nrm[u] = a.norm[u];
+    WaveWeights W;
+    load_weights(W, a.wpk, lane);
+    u32x4 *xs = xs_all[wave];
+    float *ys = ys_all[wave];
+    const Dims &d = a.in.d;
+    __syncthreads();
+    for (int base = blockIdx.x * kClosureBlock; base < d.n; base += gridDim.x * kClosureBlock) {
+        const int c = base + threadIdx.x;
+        const bool valid = c < d.n;
+        double f[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, dthx = 0.0, dthy = 0.0;
+        int k = 0;
+        if (valid) {
+            k = c / d.nxy;
+            const int rem = c - k * d.nxy, j = rem / d.nx, i = rem - j * d.nx;
+            closure_inputs(a.in, i, j, k, f, dthx, dthy);
+        }
+        float x[10];
+#pragma unroll
+        for (int o = 0; o < 10; ++o) x[o] = valid ? (float)((f[o] - nrm[o]) / nrm[10 + o]) : 0.f;
+        store_inputs(xs, lane, x);
+        __syncthreads();
+        mlp64(W, bias, xs, ys, lane);
+        __syncthreads();
+        bool fb = false;
+        if (valid) {
+            double t[9];
+            bool finite = true;
+#pragma unroll
+            for (int o = 0; o < 9; ++o) {
+                t[o] = (double)ys[lane * 12 + o] * nrm[29 + o] + nrm[20 + o];
+                finite = finite && isfinite(t[o]);
+            }
+            const double s11 = f[0], s22 = f[4], s33 = f[8];
+            const double s12 = 0.5 * (f[1] + f[3]), s13 = 0.5 * (f[2] + f[6]), s23 = 0.5 * (f[5] + f[7]);
+            double ts[9];
+            const double cd = a.Cs * cbrt(a.dx * a.dy * a.dz[k]);
+            const double diss = centre_smag(f, dthx, dthy, cd, a.Pr_t, ts);
+            // energy transfer to the subgrid scales, -tau:S
+            const double pi = -(t[0] * s11 + t[1] * s22 + t[2] * s33 + 2.0 * (t[3] * s12 + t[4] * s13 + t[5] * s23));
+            if (!finite || pi < -2.0 * diss) {
+                fb = true;
+#pragma unroll
+                for (int o = 0; o < 9; ++o) t[o] = ts[o];
+            }
+            const double r = full_of(a.rho, c, a.rho0[k]);
+#pragma unroll
+            for (int o = 0; o < 9; ++o) a.out[o][c] = (T)(r * t[o]);
+        }
+        const unsigned long long m = __ballot(fb);
+        if (lane == 0 && m) atomicAdd(a.fallbacks, (unsigned long long)__popcll(m));
+        // the next chunk rewrites xs / ys only after every wave read them
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// divergence of the closure stresses onto the slow tendencies
+// ---------------------------------------------------------------------------
+template <typename T>
+struct DivArgs {
+    Dims d;
+    double idx, idy;
+    const double *idz, *idzf;
+    const T *s[9];
+    T *Rt, *Ru, *Rv, *Rw;
+};
+
+// tau_12 on xy-edges, tau_13 / tau_23 on the z-face edges (zero on the lids)
+// and the heat fluxes on faces are 4-cell and 2-cell means of the centre values.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mlp_div(DivArgs<T> a)
+{
+    const Dims &d = a.d;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y, k = blockIdx.z;
+    if (i >= d.nx || j >= d.ny) return;
+    const int nz = d.nz;
+    auto S = [&](int o, int ii, int jj, int kk) {
+        return (double)a.s[o][cidx(d, wrap_idx(ii, d.nx), wrap_idx(jj, d.ny), kk)];
+    };
+    auto e12 = [&](int ii, int jj) {
+        return 0.25 * (S(3, ii - 1, jj - 1, k) + S(3, ii, jj - 1, k) + S(3, ii - 1, jj, k) + S(3, ii, jj, k));
+    };
+    auto e13 = [&](int ii, int kk) {
+        if (kk <= 0 || kk >= nz) return 0.0;
+        return 0.25 * (S(4, ii - 1, j, kk - 1) + S(4, ii, j, kk - 1) + S(4, ii - 1, j, kk) + S(4, ii, j, kk));
+    };
+    auto e23 = [&](int jj, int kk) {
+        if (kk <= 0 || kk >= nz) return 0.0;
+        return 0.25 * (S(5, i, jj - 1, kk - 1) + S(5, i, jj, kk - 1) + S(5, i, jj - 1, kk) + S(5, i, jj, kk));
+    };
+    const int c = cidx(d, i, j, k);
+    const double idz = a.idz[k];
+    const double du = (S(0, i, j, k) - S(0, i - 1, j, k)) * a.idx + (e12(i, j + 1) - e12(i, j)) * a.idy +
+                      (e13(i, k + 1) - e13(i, k)) * idz;
+    const double dv = (e12(i + 1, j) - e12(i, j)) * a.idx + (S(1, i, j, k) - S(1, i, j - 1, k)) * a.idy +
+                      (e23(j, k + 1) - e23(j, k)) * idz;
+    a.Ru[c] = (T)((double)a.Ru[c] - du);
+    a.Rv[c] = (T)((double)a.Rv[c] - dv);
+    if (k > 0) {
+        const double dw = (e13(i + 1, k) - e13(i, k)) * a.idx + (e23(j + 1, k) - e23(j, k)) * a.idy +
+                          (S(2, i, j, k) - S(2, i, j, k - 1)) * a.idzf[k];
+        a.Rw[c] = (T)((double)a.Rw[c] - dw);
+    }
+    const double hx0 = 0.5 * (S(6, i - 1, j, k) + S(6, i, j, k)), hx1 = 0.5 * (S(6, i, j, k) + S(6, i + 1, j, k));
+    const double hy0 = 0.5 * (S(7, i, j - 1, k) + S(7, i, j, k)), hy1 = 0.5 * (S(7, i, j, k) + S(7, i, j + 1, k));
+    const double hz0 = k == 0 ? 0.0 : 0.5 * (S(8, i, j, k - 1) + S(8, i, j, k));
+    const double hz1 = k == nz - 1 ? 0.0 : 0.5 * (S(8, i, j, k) + S(8, i, j, k + 1));
+    a.Rt[c] = (T)((double)a.Rt[c] - ((hx1 - hx0) * a.idx + (hy1 - hy0) * a.idy + (hz1 - hz0) * idz));
+}
+
+// ---------------------------------------------------------------------------
+// the network alone: standardised x[n][10] -> y[n][9]
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ X, int64_t n,
+                                                     const u32x4 *__restrict__ wpk, const float *__restrict__ biasg,
+                                                     float *__restrict__ Y)
+{
+    __shared__ u32x4 xs_all[4][128];
+    __shared__ float ys_all[4][64 * 12];
+    __shared__ float bias[208];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int u = threadIdx.x; u < 208; u += 256) bias[u] = biasg[u];
+    WaveWeights W;
+    load_weights(W, wpk, lane);
+    u32x4 *xs = xs_all[wave];
+    float *ys = ys_all[wave];
+    __syncthreads();
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+        const int64_t s = base + threadIdx.x;
+        const bool valid = s < n;
+        float x[10];
+#pragma unroll
+        for (int o = 0; o < 10; ++o) x[o] = valid ? X[s * 10 + o] : 0.f;
+        store_inputs(xs, lane, x);
+        __syncthreads();
+        mlp64(W, bias, xs, ys, lane);
+        __syncthreads();
+        if (valid)
+#pragma unroll
+            for (int o = 0; o < 9; ++o) Y[s * 9 + o] = ys[lane * 12 + o];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// closure inputs of every cell (training data), FP64
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_features(ClosureIn<T> a, double *__restrict__ feat)
+{
+    const Dims &d = a.d;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.n) return;
+    const int k = c / d.nxy, rem = c - k * d.nxy, j = rem / d.nx, i = rem - j * d.nx;
+    double f[10], dthx, dthy;
+    closure_inputs(a, i, j, k, f, dthx, dthy);
+    for (int o = 0; o < 10; ++o) feat[(int64_t)c * 10 + o] = f[o];
+}
+
+// ---------------------------------------------------------------------------
+// box filter of a fine state onto the r-coarsened grid, with SGS targets
+// ---------------------------------------------------------------------------
+template <typename T>
+struct BoxArgs {
+    ClosureIn<T> in;
+    int r;
+    Dims cd;  // coarse dims
+    double dx, dy, Cs, Pr_t;
+    const double *dz, *rho0, *Theta0;
+    const T *rho, *rt, *ru, *rv, *rw;
+    double *crho, *crt, *cru, *crv, *crw, *targets;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_box_filter(BoxArgs<T> a)
+{
+    const Dims &cd = a.cd, &d = a.in.d;
+    const int cc = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cc >= cd.n) return;
+    const int K = cc / cd.nxy, rem = cc - K * cd.nxy, J = rem / cd.nx, I = rem - J * cd.nx;
+    const int r = a.r;
+    double mr = 0, mt = 0, su[3] = {0, 0, 0}, sth = 0, suu[6] = {0, 0, 0, 0, 0, 0}, sut[3] = {0, 0, 0};
+    double ssg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int kk = 0; kk < r; ++kk)
+        for (int jj = 0; jj < r; ++jj)
+            for (int ii = 0; ii < r; ++ii) {
+                const int i = I * r + ii, j = J * r + jj, k = K * r + kk;
+                const int c = cidx(d, i, j, k);
+                mr += full_of(a.rho, c, a.rho0[k]);
+                mt += full_of(a.rt, c, a.Theta0[k]);
+                const double uc = 0.5 * ((double)a.in.u[c] + (double)a.in.u[cidx(d, wrap_idx(i + 1, d.nx), j, k)]);
+                const double vc = 0.5 * ((double)a.in.v[c] + (double)a.in.v[cidx(d, i, wrap_idx(j + 1, d.ny), k)]);
+                const double wc = 0.5 * ((double)a.in.w[c] + (double)a.in.w[c + d.nxy]);
+                const double t = theta_full(a.in, c, k);
+                su[0] += uc;
+                su[1] += vc;
+                su[2] += wc;
+                sth += t;
+                suu[0] += uc * uc;
+                suu[1] += vc * vc;
+                suu[2] += wc * wc;
+                suu[3] += uc * vc;
+                suu[4] += uc * wc;
+                suu[5] += vc * wc;
+                sut[0] += uc * t;
+                sut[1] += vc * t;
+                sut[2] += wc * t;
+                if (a.Cs > 0.0) {
+                    double f[10], dthx, dthy, ts[9];
+                    closure_inputs(a.in, i, j, k, f, dthx, dthy);
+                    centre_smag(f, dthx, dthy, a.Cs * cbrt(a.dx * a.dy * a.dz[k]), a.Pr_t, ts);
+                    for (int o = 0; o < 9; ++o) ssg[o] += ts[o];
+                }
+            }
+    const double r3 = (double)r * r * r, r2 = (double)r * r;
+    a.crho[cc] = mr / r3;
+    a.crt[cc] = mt / r3;
+    const double m0 = su[0] / r3, m1 = su[1] / r3, m2 = su[2] / r3, mth = sth / r3;
+    double *tg = a.targets + (int64_t)cc * 9;
+    tg[0] = suu[0] / r3 - m0 * m0 + ssg[0] / r3;
+    tg[1] = suu[1] / r3 - m1 * m1 + ssg[1] / r3;
+    tg[2] = suu[2] / r3 - m2 * m2 + ssg[2] / r3;
+    tg[3] = suu[3] / r3 - m0 * m1 + ssg[3] / r3;
+    tg[4] = suu[4] / r3 - m0 * m2 + ssg[4] / r3;
+    tg[5] = suu[5] / r3 - m1 * m2 + ssg[5] / r3;
+    tg[6] = sut[0] / r3 - m0 * mth + ssg[6] / r3;
+    tg[7] = sut[1] / r3 - m1 * mth + ssg[7] / r3;
+    tg[8] = sut[2] / r3 - m2 * mth + ssg[8] / r3;
+    double fu = 0, fv = 0, fw = 0;
+    for (int p = 0; p < r; ++p)
+        for (int q = 0; q < r; ++q) {
+            fu += (double)a.ru[cidx(d, I * r, J * r + p, K * r + q)];
+            fv += (double)a.rv[cidx(d, I * r + p, J * r, K * r + q)];
+            fw += (double)a.rw[cidx(d, I * r + p, J * r + q, K * r)];
+        }
+    a.cru[cc] = fu / r2;
+    a.crv[cc] = fv / r2;
+    a.crw[cc] = K == 0 ? 0.0 : fw / r2;
+    if (K == cd.nz - 1) a.crw[cc + cd.nxy] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// statistics and standardisation of training data
+// ---------------------------------------------------------------------------
+constexpr int kStatRows = 1024;  // rows per partial block
+
+// partial column sums of (x - shift)^p, p = 1 or 2, over kStatRows rows
+__global__ __launch_bounds__(64) void k_col_moments(const double *__restrict__ X, int64_t n, int ncol,
+                                                    const double *__restrict__ shift, int power,
+                                                    double *__restrict__ part)
+{
+    const int col = threadIdx.x;
+    if (col >= ncol) return;
+    const int64_t r0 = (int64_t)blockIdx.x * kStatRows, r1 = r0 + kStatRows < n ? r0 + kStatRows : n;
+    const double s0 = shift ? shift[col] : 0.0;
+    double acc = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const double v = X[r * ncol + col] - s0;
+        acc += power == 1 ? v : v * v;
+    }
+    part[(int64_t)blockIdx.x * ncol + col] = acc;
+}
+
+// out[col] = sum of the partials in block order / n (square root for p = 2)
+__global__ __launch_bounds__(64) void k_col_finish(const double *__restrict__ part, int nblk, int ncol, int64_t n,
+                                                   int take_sqrt, double *__restrict__ out)
+{
+    const int col = threadIdx.x;
+    if (col >= ncol) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += part[(int64_t)b * ncol + col];
+    double v = acc / (double)n;
+    if (take_sqrt) {
+        v = sqrt(v);
+        if (!(v > 0.0)) v = 1.0;  // a constant column keeps unit scale
+    }
+    out[col] = v;
+}
+
+__global__ __launch_bounds__(256) void k_standardize(const double *__restrict__ X, int64_t n, int ncol,
+                                                     const double *__restrict__ mean, const double *__restrict__ sd,
+                                                     float *__restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * ncol) return;
+    const int col = (int)(e % ncol);
+    out[e] = (float)((X[e] - mean[col]) / sd[col]);
+}
+
+// ---------------------------------------------------------------------------
+// training: BF16 MFMA products, FP32 buffers, FP64 loss and Adam arithmetic
+// ---------------------------------------------------------------------------
+// C(m, n) = sum_k A(m, k) B(k, n), A(m, k) = A[m sam + k sak],
+// B(k, n) = B[k sbk + n sbn]; operands rounded to BF16, FP32 accumulation.
+// blockIdx.y splits K into chunks of kchunk (multiple of 32); with one split
+// the epilogue is applied here, otherwise k_gemm_reduce applies it.
+struct GemmArgs {
+    const float *A;
+    int64_t sam, sak;
+    const float *B;
+    int64_t sbk, sbn;
+    float *C;          // one split: C[m ldc + n]; several: partials [split][M][N]
+    int64_t ldc;
+    int M, N, K, kchunk, splits;
+    const float *bias;  // epilogue: + bias[n]
+    int relu;           // epilogue: max(., 0)
+    const float *mask;  // epilogue: * (mask[m ldm + n] > 0)
+    int64_t ldm;
+};
+
+__device__ __forceinline__ float epilogue(const GemmArgs &a, int m, int n, float v)
+{
+    if (a.bias) v += a.bias[n];
+    if (a.relu) v = fmaxf(v, 0.f);
+    if (a.mask && !(a.mask[(int64_t)m * a.ldm + n] > 0.f)) v = 0.f;
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
+    const int tiles_n = (a.N + 15) / 16, tiles = ((a.M + 15) / 16) * tiles_n;
+    const int tile = blockIdx.x * 4 + wave;
+    if (tile >= tiles) return;
+    const int m0 = (tile / tiles_n) * 16, n0 = (tile % tiles_n) * 16;
+    const int split = blockIdx.y;
+    const int kb = split * a.kchunk, ke = kb + a.kchunk < a.K ? kb + a.kchunk : a.K;
+    const int am = m0 + col, bn = n0 + col;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = kb; k0 < ke; k0 += 32) {
+        float av[8], bv[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = k0 + 8 * g + i;
+            const bool kin = k < ke;
+            av[i] = (kin && am < a.M) ? a.A[(int64_t)am * a.sam + (int64_t)k * a.sak] : 0.f;
+            bv[i] = (kin && bn < a.N) ? a.B[(int64_t)k * a.sbk + (int64_t)bn * a.sbn] : 0.f;
+        }
+        u32x4 pa, pb;
+        pa.x = pack2(av[0], av[1]);
+        pa.y = pack2(av[2], av[3]);
+        pa.z = pack2(av[4], av[5]);
+        pa.w = pack2(av[6], av[7]);
+        pb.x = pack2(bv[0], bv[1]);
+        pb.y = pack2(bv[2], bv[3]);
+        pb.z = pack2(bv[4], bv[5]);
+        pb.w = pack2(bv[6], bv[7]);
+        acc = mfma(as_bf16x8(pa), as_bf16x8(pb), acc);
+    }
+    // acc[r]: row m0 + 4g + r, column n0 + col
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int m = m0 + 4 * g + r, n = n0 + col;
+        if (m >= a.M || n >= a.N) continue;
+        if (a.splits == 1)
+            a.C[(int64_t)m * a.ldc + n] = epilogue(a, m, n, acc[r]);
+        else
+            a.C[((int64_t)split * a.M + m) * a.N + n] = acc[r];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs a, const float *__restrict__ part, float *__restrict__ C)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.M * a.N) return;
+    const int m = e / a.N, n = e - m * a.N;
+    float s = 0.f;
+    for (int p = 0; p < a.splits; ++p) s += part[((int64_t)p * a.M + m) * a.N + n];
+    C[(int64_t)m * a.ldc + n] = epilogue(a, m, n, s);
+}
+
+// loss partials and dY = 2 (Y - T) / (n 9)
+__global__ __launch_bounds__(256) void k_loss_dy(const float *__restrict__ Y, const float *__restrict__ T, int64_t n,
+                                                 float *__restrict__ dY, double *__restrict__ part)
+{
+    __shared__ double red[256];
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double sq = 0.0;
+    if (e < n * 9) {
+        const double err = (double)Y[e] - (double)T[e];
+        sq = err * err;
+        dY[e] = (float)(2.0 / ((double)n * 9.0) * err);
+    }
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(64) void k_loss_finish(const double *__restrict__ part, int nblk, int64_t n,
+                                                    double *__restrict__ loss)
+{
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[b];
+    *loss = s / ((double)n * 9.0);
+}
+
+// bias gradients: column sums of D[n][ncol] (FP64, fixed order)
+__global__ __launch_bounds__(64) void k_colsum_part(const float *__restrict__ D, int64_t n, int ncol,
+                                                    double *__restrict__ part)
+{
+    const int col = threadIdx.x;
+    if (col >= ncol) return;
+    const int64_t r0 = (int64_t)blockIdx.x * kStatRows, r1 = r0 + kStatRows < n ? r0 + kStatRows : n;
+    double acc = 0.0;
+    for (int64_t r = r0; r < r1; ++r) acc += (double)D[r * ncol + col];
+    part[(int64_t)blockIdx.x * ncol + col] = acc;
+}
+
+__global__ __launch_bounds__(64) void k_colsum_finish(const double *__restrict__ part, int nblk, int ncol,
+                                                      float *__restrict__ out)
+{
+    const int col = threadIdx.x;
+    if (col >= ncol) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += part[(int64_t)b * ncol + col];
+    out[col] = (float)acc;
+}
+
+// Adam (Kingma & Ba) with bias correction; FP32 storage, FP64 arithmetic
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ P, const float *__restrict__ G,
+                                              float *__restrict__ Mo, float *__restrict__ Vo, int np, double lr,
+                                              double b1, double b2, double eps, double c1, double c2)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= np) return;
+    const double g = G[e];
+    const double m = b1 * (double)Mo[e] + (1.0 - b1) * g;
+    const double v = b2 * (double)Vo[e] + (1.0 - b2) * g * g;
+    Mo[e] = (float)m;
+    Vo[e] = (float)v;
+    P[e] = (float)((double)P[e] - lr * (m / c1) / (sqrt(v / c2) + eps));
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+ClosureIn<T> closure_in(erf_ctx *cx)
+{
+    ClosureIn<T> in{};
+    in.d = cx->d;
+    in.idx = 1.0 / cx->grid.dx;
+    in.idy = 1.0 / cx->grid.dy;
+    in.idz = cx->base.idz();
+    in.idzf = cx->base.idzf();
+    in.theta0 = cx->base.theta0;
+    in.u = (const T *)cx->ws.u;
+    in.v = (const T *)cx->ws.v;
+    in.w = (const T *)cx->ws.w;
+    in.th = (const T *)cx->ws.th;
+    return in;
+}
+
+int grid_for(int64_t items, int per_block, int cap)
+{
+    int64_t b = (items + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    return (int)(b < cap ? b : cap);
+}
+
+template <typename T>
+hipError_t closure_t(erf_ctx *cx, const void *rho, void *const R[5])
+{
+    MlpState &m = cx->mlp;
+    ClosureArgs<T> a{};
+    a.in = closure_in<T>(cx);
+    a.dx = cx->grid.dx;
+    a.dy = cx->grid.dy;
+    a.Cs = cx->prm.Cs;
+    a.Pr_t = cx->prm.Pr_t;
+    a.dz = cx->base.dz;
+    a.rho0 = cx->base.rho0;
+    a.norm = m.norm;
+    a.rho = (const T *)rho;
+    a.wpk = (const u32x4 *)m.wpk;
+    a.bias = m.bias;
+    for (int o = 0; o < 9; ++o) a.out[o] = (T *)cx->ws.sg[o];
+    a.fallbacks = m.fallbacks;
+    const Dims &d = cx->d;
+    timing_start(cx, K_MLP);
+    hipLaunchKernelGGL(k_mlp_closure<T>, dim3(grid_for(d.n, kClosureBlock, 2048)), dim3(kClosureBlock), 0,
+                       cx->stream, a);
+    timing_stop(cx, K_MLP);
+    DivArgs<T> v{};
+    v.d = d;
+    v.idx = 1.0 / cx->grid.dx;
+    v.idy = 1.0 / cx->grid.dy;
+    v.idz = cx->base.idz();
+    v.idzf = cx->base.idzf();
+    for (int o = 0; o < 9; ++o) v.s[o] = (const T *)cx->ws.sg[o];
+    v.Rt = (T *)R[1];
+    v.Ru = (T *)R[2];
+    v.Rv = (T *)R[3];
+    v.Rw = (T *)R[4];
+    timing_start(cx, K_MLP_DIV);
+    hipLaunchKernelGGL(k_mlp_div<T>, dim3((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz), dim3(64, 4, 1), 0, cx->stream, v);
+    timing_stop(cx, K_MLP_DIV);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t features_t(erf_ctx *cx, double *feat)
+{
+    hipLaunchKernelGGL(k_features<T>, dim3(grid_for(cx->d.n, 256, 1 << 30)), dim3(256), 0, cx->stream,
+                       closure_in<T>(cx), feat);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t box_filter_t(erf_ctx *cx, const void *const S[5], int r, double Cs, double Pr_t, double *const C[5],
+                        double *targets)
+{
+    BoxArgs<T> a{};
+    a.in = closure_in<T>(cx);
+    a.r = r;
+    a.cd.nx = cx->d.nx / r;
+    a.cd.ny = cx->d.ny / r;
+    a.cd.nz = cx->d.nz / r;
+    a.cd.nxy = a.cd.nx * a.cd.ny;
+    a.cd.n = a.cd.nxy * a.cd.nz;
+    a.cd.nw = a.cd.nxy * (a.cd.nz + 1);
+    a.dx = cx->grid.dx;
+    a.dy = cx->grid.dy;
+    a.Cs = Cs;
+    a.Pr_t = Pr_t;
+    a.dz = cx->base.dz;
+    a.rho0 = cx->base.rho0;
+    a.Theta0 = cx->base.Theta0;
+    a.rho = (const T *)S[0];
+    a.rt = (const T *)S[1];
+    a.ru = (const T *)S[2];
+    a.rv = (const T *)S[3];
+    a.rw = (const T *)S[4];
+    a.crho = C[0];
+    a.crt = C[1];
+    a.cru = C[2];
+    a.crv = C[3];
+    a.crw = C[4];
+    a.targets = targets;
+    hipLaunchKernelGGL(k_box_filter<T>, dim3(grid_for(a.cd.n, 256, 1 << 30)), dim3(256), 0, cx->stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t mlp_pack(erf_ctx *cx)
+{
+    MlpState &m = cx->mlp;
+    hipLaunchKernelGGL(k_mlp_pack, dim3(22), dim3(64), 0, cx->stream, m.master, (u32x4 *)m.wpk, m.bias);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_closure(erf_ctx *cx, const void *rho, void *const R[5])
+{
+    if (cx->prm.precision == ERF_FP32_MIXED) return closure_t<float>(cx, rho, R);
+    return closure_t<double>(cx, rho, R);
+}
+
+hipError_t launch_mlp_forward(erf_ctx *cx, const float *x, int64_t n, float *y)
+{
+    MlpState &m = cx->mlp;
+    hipLaunchKernelGGL(k_mlp_forward, dim3(grid_for(n, 256, 4096)), dim3(256), 0, cx->stream, x, n,
+                       (const u32x4 *)m.wpk, (const float *)m.bias, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_features(erf_ctx *cx, double *feat)
+{
+    if (cx->prm.precision == ERF_FP32_MIXED) return features_t<float>(cx, feat);
+    return features_t<double>(cx, feat);
+}
+
+hipError_t launch_box_filter(erf_ctx *cx, const void *const S[5], int r, double Cs, double Pr_t,
+                             double *const C[5], double *targets)
+{
+    if (cx->prm.precision == ERF_FP32_MIXED) return box_filter_t<float>(cx, S, r, Cs, Pr_t, C, targets);
+    return box_filter_t<double>(cx, S, r, Cs, Pr_t, C, targets);
+}
+
+size_t stat_partials(int64_t n) { return (size_t)((n + kStatRows - 1) / kStatRows) * 16; }
+
+hipError_t launch_col_stats(erf_ctx *cx, const double *X, int64_t n, int ncol, double *mean, double *sd,
+                            double *part)
+{
+    const int nblk = (int)((n + kStatRows - 1) / kStatRows);
+    hipLaunchKernelGGL(k_col_moments, dim3(nblk), dim3(64), 0, cx->stream, X, n, ncol, (const double *)nullptr, 1, part);
+    hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(64), 0, cx->stream, (const double *)part, nblk, ncol, n, 0, mean);
+    hipLaunchKernelGGL(k_col_moments, dim3(nblk), dim3(64), 0, cx->stream, X, n, ncol, (const double *)mean, 2, part);
+    hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(64), 0, cx->stream, (const double *)part, nblk, ncol, n, 1, sd);
+    return hipGetLastError();
+}
+
+hipError_t launch_standardize(erf_ctx *cx, const double *X, int64_t n, int ncol, const double *mean,
+                              const double *sd, float *out)
+{
+    hipLaunchKernelGGL(k_standardize, dim3(grid_for(n * ncol, 256, 1 << 30)), dim3(256), 0, cx->stream, X, n, ncol,
+                       mean, sd, out);
+    return hipGetLastError();
+}
+
+namespace {
+// one product with its epilogue; K split over blocks when long
+hipError_t gemm(erf_ctx *cx, GemmArgs a, float *C, float *part, size_t part_floats)
+{
+    int splits = 1;
+    if (a.K > 4096) {
+        splits = (a.K + 2047) / 2048;
+        const size_t per = (size_t)a.M * a.N;
+        const int cap = (int)(part_floats / (per ? per : 1));
+        if (splits > cap) splits = cap;
+        if (splits > 256) splits = 256;
+        if (splits < 1) splits = 1;
+    }
+    int kchunk = (a.K + splits - 1) / splits;
+    kchunk = (kchunk + 31) / 32 * 32;
+    splits = (a.K + kchunk - 1) / kchunk;
+    if (splits < 1) splits = 1;
+    a.kchunk = kchunk > 0 ? kchunk : 32;
+    a.splits = splits;
+    const int tiles = ((a.M + 15) / 16) * ((a.N + 15) / 16);
+    a.C = splits == 1 ? C : part;
+    hipLaunchKernelGGL(k_gemm, dim3((tiles + 3) / 4, splits), dim3(256), 0, cx->stream, a);
+    if (splits > 1)
+        hipLaunchKernelGGL(k_gemm_reduce, dim3((a.M * a.N + 255) / 256), dim3(256), 0, cx->stream, a,
+                           (const float *)part, C);
+    return hipGetLastError();
+}
+
+GemmArgs gargs(const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbk, int64_t sbn, int M, int N,
+               int K, int64_t ldc)
+{
+    GemmArgs a{};
+    a.A = A;
+    a.sam = sam;
+    a.sak = sak;
+    a.B = B;
+    a.sbk = sbk;
+    a.sbn = sbn;
+    a.M = M;
+    a.N = N;
+    a.K = K;
+    a.ldc = ldc;
+    return a;
+}
+}  // namespace
+
+size_t train_floats(int64_t cap)
+{
+    // H1, H2, H3, D (two), each cap x 64; Y, dY cap x 9
+    return (size_t)cap * (5 * 64 + 2 * 9);
+}
+size_t train_partial_floats() { return (size_t)256 * 64 * 64; }
+size_t train_partial_doubles(int64_t cap) { return (size_t)((cap + kStatRows - 1) / kStatRows + 1) * 64 + (size_t)((cap * 9 + 255) / 256 + 1); }
+
+hipError_t launch_loss_grad(erf_ctx *cx, const float *X, const float *Tt, int64_t n, float *G, double *loss_dev)
+{
+    MlpState &m = cx->mlp;
+    const float *P = m.master;
+    float *H1 = m.tbuf, *H2 = H1 + n * 64, *H3 = H2 + n * 64, *Da = H3 + n * 64, *Db = Da + n * 64;
+    float *Y = Db + n * 64, *dY = Y + n * 9;
+    float *part = m.tpart;
+    const size_t pf = train_partial_floats();
+    double *dpart = m.tdpart;
+    const int N = (int)n;
+    hipError_t e;
+    // forward
+    GemmArgs a = gargs(X, 10, 1, P + kMlpW1, 64, 1, N, 64, 10, 64);
+    a.bias = P + kMlpB1;
+    a.relu = 1;
+    if ((e = gemm(cx, a, H1, part, pf)) != hipSuccess) return e;
+    a = gargs(H1, 64, 1, P + kMlpW2, 64, 1, N, 64, 64, 64);
+    a.bias = P + kMlpB2;
+    a.relu = 1;
+    if ((e = gemm(cx, a, H2, part, pf)) != hipSuccess) return e;
+    a = gargs(H2, 64, 1, P + kMlpW3, 64, 1, N, 64, 64, 64);
+    a.bias = P + kMlpB3;
+    a.relu = 1;
+    if ((e = gemm(cx, a, H3, part, pf)) != hipSuccess) return e;
+    a = gargs(H3, 64, 1, P + kMlpW4, 9, 1, N, 9, 64, 9);
+    a.bias = P + kMlpB4;
+    if ((e = gemm(cx, a, Y, part, pf)) != hipSuccess) return e;
+    // loss and dY
+    const int lblk = (int)((n * 9 + 255) / 256);
+    double *lpart = dpart + ((n + kStatRows - 1) / kStatRows + 1) * 64;
+    hipLaunchKernelGGL(k_loss_dy, dim3(lblk), dim3(256), 0, cx->stream, (const float *)Y, Tt, n, dY, lpart);
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(64), 0, cx->stream, (const double *)lpart, lblk, n, loss_dev);
+    const int cblk = (int)((n + kStatRows - 1) / kStatRows);
+    auto colsum = [&](const float *D, int ncol, float *out) {
+        hipLaunchKernelGGL(k_colsum_part, dim3(cblk), dim3(64), 0, cx->stream, D, n, ncol, dpart);
+        hipLaunchKernelGGL(k_colsum_finish, dim3(1), dim3(64), 0, cx->stream, (const double *)dpart, cblk, ncol, out);
+    };
+    // layer 4
+    a = gargs(H3, 1, 64, dY, 9, 1, 64, 9, N, 9);
+    if ((e = gemm(cx, a, G + kMlpW4, part, pf)) != hipSuccess) return e;
+    colsum(dY, 9, G + kMlpB4);
+    a = gargs(dY, 9, 1, P + kMlpW4, 1, 9, N, 64, 9, 64);
+    a.mask = H3;
+    a.ldm = 64;
+    if ((e = gemm(cx, a, Da, part, pf)) != hipSuccess) return e;
+    // layer 3
+    a = gargs(H2, 1, 64, Da, 64, 1, 64, 64, N, 64);
+    if ((e = gemm(cx, a, G + kMlpW3, part, pf)) != hipSuccess) return e;
+    colsum(Da, 64, G + kMlpB3);
+    a = gargs(Da, 64, 1, P + kMlpW3, 1, 64, N, 64, 64, 64);
+    a.mask = H2;
+    a.ldm = 64;
+    if ((e = gemm(cx, a, Db, part, pf)) != hipSuccess) return e;
+    // layer 2
+    a = gargs(H1, 1, 64, Db, 64, 1, 64, 64, N, 64);
+    if ((e = gemm(cx, a, G + kMlpW2, part, pf)) != hipSuccess) return e;
+    colsum(Db, 64, G + kMlpB2);
+    a = gargs(Db, 64, 1, P + kMlpW2, 1, 64, N, 64, 64, 64);
+    a.mask = H1;
+    a.ldm = 64;
+    if ((e = gemm(cx, a, Da, part, pf)) != hipSuccess) return e;
+    // layer 1
+    a = gargs(X, 1, 10, Da, 64, 1, 10, 64, N, 64);
+    if ((e = gemm(cx, a, G + kMlpW1, part, pf)) != hipSuccess) return e;
+    colsum(Da, 64, G + kMlpB1);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(erf_ctx *cx, double lr, int64_t step)
+{
+    MlpState &m = cx->mlp;
+    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    const double c1 = 1.0 - std::pow(b1, (double)step), c2 = 1.0 - std::pow(b2, (double)step);
+    hipLaunchKernelGGL(k_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, cx->stream, m.master,
+                       (const float *)m.grad, m.adam_m, m.adam_v, kMlpParams, lr, b1, b2, eps, c1, c2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return mlp_pack(cx);
+}
+
+}  // namespace erfk

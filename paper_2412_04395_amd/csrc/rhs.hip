@@ -378,7 +378,7 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
 
 namespace {
 template <typename T>
-hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5])
+hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5], bool prep_only)
 {
     const erf_params &p = cx->prm;
     Workspace &ws = cx->ws;
@@ -393,8 +393,10 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5])
     a.idzf = cx->base.idzf();
     a.oh = p.adv_order_h;
     a.ov = p.adv_order_v;
-    a.sgs = p.sgs;
-    a.visc = (p.sgs != 0 || p.nu_m != 0.0 || p.alpha_m != 0.0) ? 1 : 0;
+    // the learned closure adds its own stress divergence after k_rhs
+    const bool mlp = p.sgs == ERF_SGS_MLP;
+    a.sgs = mlp ? 0 : p.sgs;
+    a.visc = (a.sgs != 0 || p.nu_m != 0.0 || p.alpha_m != 0.0) ? 1 : 0;
     a.Cs = p.Cs;
     a.Pr_t = p.Pr_t;
     a.nu = p.nu_m;
@@ -435,7 +437,8 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5])
     dim3 blk(64, 4, 1), grd((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz);
     dim3 grdw((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz + 1);
     timing_start(cx, K_PREP); hipLaunchKernelGGL(k_prep<T>, grd, blk, 0, cx->stream, a); timing_stop(cx, K_PREP);
-    if (p.sgs) { timing_start(cx, K_MUT); hipLaunchKernelGGL(k_mut<T>, grd, blk, 0, cx->stream, a); timing_stop(cx, K_MUT); }
+    if (prep_only) return hipGetLastError();
+    if (a.sgs) { timing_start(cx, K_MUT); hipLaunchKernelGGL(k_mut<T>, grd, blk, 0, cx->stream, a); timing_stop(cx, K_MUT); }
     if (a.visc) { timing_start(cx, K_STRESS); hipLaunchKernelGGL(k_stress<T>, grdw, blk, 0, cx->stream, a); timing_stop(cx, K_STRESS); }
     timing_start(cx, K_RHS);
     if (a.oh == 5 && a.ov == 5)
@@ -447,14 +450,26 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5])
     else
         hipLaunchKernelGGL((k_rhs<T, 0, 0>), grd, blk, 0, cx->stream, a);
     timing_stop(cx, K_RHS);
+    if (mlp) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_mlp_closure(cx, S[0], R);
+    }
     return hipGetLastError();
 }
 }  // namespace
 
 hipError_t launch_slow_rhs(erf_ctx *cx, const void *const S[5], void *const R[5])
 {
-    if (cx->prm.precision == ERF_FP32_MIXED) return slow_rhs_t<float>(cx, S, R);
-    return slow_rhs_t<double>(cx, S, R);
+    if (cx->prm.precision == ERF_FP32_MIXED) return slow_rhs_t<float>(cx, S, R, false);
+    return slow_rhs_t<double>(cx, S, R, false);
+}
+
+hipError_t launch_prep(erf_ctx *cx, const void *const S[5])
+{
+    void *const none[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (cx->prm.precision == ERF_FP32_MIXED) return slow_rhs_t<float>(cx, S, none, true);
+    return slow_rhs_t<double>(cx, S, none, true);
 }
 
 }  // namespace erfk

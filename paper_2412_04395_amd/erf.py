@@ -26,10 +26,16 @@ ERF_OK, ERF_E_ARG, ERF_E_SHAPE, ERF_E_HIP, ERF_E_NONFINITE, ERF_E_UNSUPPORTED, E
     0, -1, -2, -3, -4, -5, -6, -7
 ERF_FP64, ERF_FP32_MIXED = 0, 1
 
-# every symbol include/erf.h declares
+ERF_SGS_NONE, ERF_SGS_SMAGORINSKY, ERF_SGS_MLP = 0, 1, 2
+MLP_NPARAMS, MLP_NNORM = 9609, 38
+
+# every symbol include/erf.h and include/erf_mlp.h declare
 EXPORTS = ("erf_base_state_host", "erf_create", "erf_destroy", "erf_last_error", "erf_workspace_bytes",
            "erf_init_base_state", "erf_slow_rhs", "erf_acoustic_substeps", "erf_scalar_advance",
-           "erf_rk3_step", "erf_diagnostics", "erf_timing_begin", "erf_timing_end")
+           "erf_rk3_step", "erf_diagnostics", "erf_timing_begin", "erf_timing_end",
+           "erf_mlp_set_weights", "erf_mlp_get_weights", "erf_mlp_forward", "erf_mlp_features",
+           "erf_box_filter", "erf_mlp_fit_norm", "erf_mlp_standardize", "erf_mlp_loss_grad",
+           "erf_mlp_train_step", "erf_mlp_fallback_count")
 
 
 class ErfError(RuntimeError):
@@ -93,6 +99,19 @@ def load(path: str = LIB_PATH):
             L.erf_diagnostics.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(Diag)]
             L.erf_timing_begin.argtypes = [C.c_void_p, C.c_char_p, C.c_int32]
             L.erf_timing_end.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+            _FP = C.POINTER(C.c_float)
+            L.erf_mlp_set_weights.argtypes = [C.c_void_p, _FP, _DP]
+            L.erf_mlp_get_weights.argtypes = [C.c_void_p, _FP, _DP]
+            L.erf_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+            L.erf_mlp_features.argtypes = [C.c_void_p, C.POINTER(State), C.c_void_p]
+            L.erf_box_filter.argtypes = [C.c_void_p, C.POINTER(State), C.c_int32, C.c_double, C.c_double,
+                                         C.POINTER(State), C.c_void_p]
+            L.erf_mlp_fit_norm.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
+            L.erf_mlp_standardize.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                              C.c_void_p]
+            L.erf_mlp_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, _DP]
+            L.erf_mlp_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, _DP]
+            L.erf_mlp_fallback_count.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
             for name in EXPORTS:
                 fn = getattr(L, name)
                 if name not in ("erf_destroy", "erf_last_error", "erf_workspace_bytes"):
@@ -273,6 +292,103 @@ class Solver:
         ms, n = C.c_double(), C.c_int64()
         self._check(self.L.erf_timing_end(self.h, C.byref(ms), C.byref(n)), "erf_timing_end")
         return ms.value, n.value
+
+    # -- learned closure (include/erf_mlp.h) -----------------------------------
+    def _dev(self, t, dtype, shape=None, what="tensor"):
+        torch = self.torch
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == dtype):
+            raise TypeError(f"{what} must be a contiguous {dtype} CUDA tensor")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        return C.c_void_p(t.data_ptr())
+
+    def mlp_set_weights(self, params, norm=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != MLP_NPARAMS:
+            raise ValueError(f"params must hold {MLP_NPARAMS} values")
+        n = None if norm is None else np.ascontiguousarray(norm, dtype=np.float64)
+        if n is not None and n.size != MLP_NNORM:
+            raise ValueError(f"norm must hold {MLP_NNORM} values")
+        self._check(self.L.erf_mlp_set_weights(self.h, p.ctypes.data_as(C.POINTER(C.c_float)),
+                                               None if n is None else _np_ptr(n)), "erf_mlp_set_weights")
+
+    def mlp_get_weights(self):
+        p = np.zeros(MLP_NPARAMS, dtype=np.float32)
+        n = np.zeros(MLP_NNORM)
+        self._check(self.L.erf_mlp_get_weights(self.h, p.ctypes.data_as(C.POINTER(C.c_float)), _np_ptr(n)),
+                    "erf_mlp_get_weights")
+        return p, n
+
+    def mlp_forward(self, x):
+        n = x.shape[0]
+        y = self.torch.empty((n, 9), dtype=self.torch.float32, device=self.device)
+        self._check(self.L.erf_mlp_forward(self.h, self._dev(x, self.torch.float32, (n, 10), "x"), n,
+                                           C.c_void_p(y.data_ptr())), "erf_mlp_forward")
+        return y
+
+    def mlp_features(self, S):
+        c = self.cfg
+        f = self.torch.empty((c.nx * c.ny * c.nz, 10), dtype=self.torch.float64, device=self.device)
+        self._check(self.L.erf_mlp_features(self.h, C.byref(self._st(S)), C.c_void_p(f.data_ptr())),
+                    "erf_mlp_features")
+        return f
+
+    def box_filter(self, S, r: int, Cs: float = 0.0, Pr_t: float = 1.0 / 3.0):
+        """Coarse state (float64 full values, dict of tensors) and targets (nc, 9)."""
+        torch, c = self.torch, self.cfg
+        nx, ny, nz = c.nx // r, c.ny // r, c.nz // r
+        z = lambda *s: torch.zeros(s, dtype=torch.float64, device=self.device)
+        Cst = {"rho": z(nz, ny, nx), "rt": z(nz, ny, nx), "ru": z(nz, ny, nx), "rv": z(nz, ny, nx),
+               "rw": z(nz + 1, ny, nx), "rq": z(0, nz, ny, nx)}
+        tg = z(nx * ny * nz, 9)
+        cs = State(Cst["rho"].data_ptr(), Cst["rt"].data_ptr(), Cst["ru"].data_ptr(), Cst["rv"].data_ptr(),
+                   Cst["rw"].data_ptr(), None)
+        self._check(self.L.erf_box_filter(self.h, C.byref(self._st(S)), int(r), float(Cs), float(Pr_t),
+                                          C.byref(cs), C.c_void_p(tg.data_ptr())), "erf_box_filter")
+        return Cst, tg
+
+    def mlp_fit_norm(self, feat, targets):
+        n = feat.shape[0]
+        self._check(self.L.erf_mlp_fit_norm(self.h, self._dev(feat, self.torch.float64, (n, 10), "feat"),
+                                            self._dev(targets, self.torch.float64, (n, 9), "targets"), n),
+                    "erf_mlp_fit_norm")
+
+    def mlp_standardize(self, feat, targets=None):
+        torch = self.torch
+        n = feat.shape[0]
+        x = torch.empty((n, 10), dtype=torch.float32, device=self.device)
+        t = None if targets is None else torch.empty((n, 9), dtype=torch.float32, device=self.device)
+        self._check(self.L.erf_mlp_standardize(self.h, self._dev(feat, torch.float64, (n, 10), "feat"),
+                                               None if targets is None else
+                                               self._dev(targets, torch.float64, (n, 9), "targets"), n,
+                                               C.c_void_p(x.data_ptr()),
+                                               None if t is None else C.c_void_p(t.data_ptr())),
+                    "erf_mlp_standardize")
+        return x, t
+
+    def mlp_loss_grad(self, x, t):
+        torch = self.torch
+        n = x.shape[0]
+        g = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=self.device)
+        loss = C.c_double()
+        self._check(self.L.erf_mlp_loss_grad(self.h, self._dev(x, torch.float32, (n, 10), "x"),
+                                             self._dev(t, torch.float32, (n, 9), "t"), n,
+                                             C.c_void_p(g.data_ptr()), C.byref(loss)), "erf_mlp_loss_grad")
+        return loss.value, g
+
+    def mlp_train_step(self, x, t, lr: float, want_loss: bool = True):
+        torch = self.torch
+        n = x.shape[0]
+        loss = C.c_double()
+        self._check(self.L.erf_mlp_train_step(self.h, self._dev(x, torch.float32, (n, 10), "x"),
+                                              self._dev(t, torch.float32, (n, 9), "t"), n, float(lr),
+                                              C.byref(loss) if want_loss else None), "erf_mlp_train_step")
+        return loss.value if want_loss else None
+
+    def mlp_fallback_count(self) -> int:
+        v = C.c_int64()
+        self._check(self.L.erf_mlp_fallback_count(self.h, C.byref(v)), "erf_mlp_fallback_count")
+        return v.value
 
     def diagnostics(self, S, allow_nonfinite: bool = False):
         d = Diag()

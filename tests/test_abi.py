@@ -74,9 +74,16 @@ def test_create_rejects_bad_arguments_before_touching_the_gpu():
     assert _create(cfg.replace(n_scalars=9))[0] == erf.ERF_E_ARG
     assert _create(cfg.replace(n_scalars=1, sgs=1))[0] == erf.ERF_E_UNSUPPORTED
     assert _create(cfg.replace(dt=0.0))[0] == erf.ERF_E_ARG
+    assert _create(cfg.replace(sgs=3))[0] == erf.ERF_E_ARG
+    assert _create(cfg.replace(sgs=2, nu_m=1e-3))[0] == erf.ERF_E_UNSUPPORTED
+    assert _create(cfg.replace(sgs=2, n_scalars=1))[0] == erf.ERF_E_UNSUPPORTED
     L = erf.load()
     assert L.erf_create(None, None, None, None) == erf.ERF_E_ARG
     assert L.erf_rk3_step(None, None) == erf.ERF_E_ARG
+    assert L.erf_mlp_set_weights(None, None, None) == erf.ERF_E_ARG
+    assert L.erf_mlp_forward(None, None, 0, None) == erf.ERF_E_ARG
+    assert L.erf_mlp_train_step(None, None, None, 1, 1e-3, None) == erf.ERF_E_ARG
+    assert L.erf_box_filter(None, None, 2, 0.0, 1.0, None, None) == erf.ERF_E_ARG
 
 
 def test_product_path_has_no_oracle_dependency():
