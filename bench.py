@@ -36,6 +36,9 @@ from paper_2412_04395_amd import workloads as W  # noqa: E402
 
 METRIC = "cell-updates/s per RK3 step (incl. acoustic substeps), % HBM roofline, FP64 vs FP32"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, vendor figure
+# multiply-adds of one evaluation of the 10 -> 64 -> 64 -> 64 -> 9 closure network
+MLP_FLOP_PER_CELL = 2 * (10 * 64 + 64 * 64 + 64 * 64 + 64 * 9)
 
 # Compulsory (algorithmic) values moved per cell by one launch of each kernel:
 # every distinct input field read once and every output written once.
@@ -136,6 +139,58 @@ def run_gpu(cfg: W.Config, steps: int, warmup: int):
     return el, dominant, kms, kn, shares, d
 
 
+def run_closure(steps: int, warmup: int):
+    """RK3 steps of the coarse LES with the learned closure (128x128x64, FP32):
+    step throughput and the closure kernel's matrix-core roofline.  The network
+    has He-initialised weights (the values do not change the work) with output
+    scales small enough that the run stays on the network, not the fallback."""
+    import torch
+    from paper_2412_04395_amd import erf
+
+    cfg = W.les_mlp()
+    s = erf.Solver(cfg)
+    th0 = W.theta_sounding(cfg)
+    b = s.init_base_state(th0)
+    S = s.from_full(W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"]))
+    rng = np.random.default_rng(cfg.seed)
+    p = np.zeros(erf.MLP_NPARAMS)
+    for off, fan_in, fan_out in ((0, 10, 64), (704, 64, 64), (4864, 64, 64), (9024, 64, 9)):
+        p[off:off + fan_in * fan_out] = rng.normal(0, np.sqrt(2.0 / fan_in), fan_in * fan_out)
+    s.mlp_set_weights(p.astype(np.float32))
+    feat = s.mlp_features(S)
+    s.mlp_fit_norm(feat, torch.zeros((feat.shape[0], 9), dtype=torch.float64, device=feat.device))
+    del feat
+    p32, nrm = s.mlp_get_weights()
+    # the initial state is nearly free of velocity gradients: floor the input
+    # scales at physical values (1e-2 1/s, 1e-3 K/m) so inputs stay O(1)
+    nrm[10:19] = np.maximum(nrm[10:19], 1e-2)
+    nrm[19] = max(nrm[19], 1e-3)
+    nrm[29:] = 1e-4
+    s.mlp_set_weights(p32, nrm)
+    for _ in range(warmup):
+        s.rk3_step(S)
+    shares = {}
+    for k in ("mlp", "mlp_div", "rhs", "substep"):
+        _, (ms, n) = _time_steps(s, S, 1, torch, kernel=k)
+        shares[k] = round(ms, 4)
+    fb0 = s.mlp_fallback_count()
+    el, (kms, kn) = _time_steps(s, S, steps, torch, kernel="mlp")
+    fb = s.mlp_fallback_count() - fb0
+    d = s.diagnostics(S, allow_nonfinite=True)
+    s.close()
+    avg_ms = kms / max(kn, 1)
+    flops = MLP_FLOP_PER_CELL * cfg.cells
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    return {"workload": cfg.name, "grid": [cfg.nx, cfg.ny, cfg.nz], "precision": "FP32 storage, BF16 network",
+            "value": cfg.cells * steps / el, "unit": "cell-updates/s", "ms_per_step": 1e3 * el / steps,
+            "kernel_ms_per_step": shares, "fallback_fraction": fb / (3 * steps * cfg.cells),
+            "final_diag": {"max_w": d["max_w"], "nonfinite": d["nonfinite"]},
+            "roofline": {"bound": "mfma", "kernel": "mlp", "achieved": round(achieved, 2),
+                         "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
+                         "traffic": None, "flop_per_launch": flops, "avg_launch_ms": round(avg_ms, 4),
+                         "launches_timed": kn}}
+
+
 def cpu_baseline(cfg: W.Config, target_s: float = 15.0):
     """FP64 oracle on a bounded sample: the same physics on a 64 x 64 column
     block of the workload (periodic), timed for whole RK3 steps."""
@@ -180,6 +235,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-as-stated", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-closure", action="store_true")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first run one plain device copy of this many GiB (reference for HBM counters)")
     a = ap.parse_args(argv)
@@ -226,6 +282,8 @@ def main(argv=None):
                        "value": c3.cells * a.steps / el3, "ms_per_step": 1e3 * el3 / a.steps,
                        "speedup_vs_fp64": el / el3, "roofline": _roofline(c3, dom3, kms3, kn3),
                        "kernel_ms_per_step": {k: round(v[0], 4) for k, v in shares3.items()}}
+    if a.workload == "cbl" and not a.no_closure:
+        out["closure"] = run_closure(a.steps, a.warmup)
     if rank == 0 and not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     if rank == 0:

@@ -152,7 +152,7 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
         {&ws.sg[0], G}, {&ws.sg[1], G}, {&ws.sg[2], G}, {&ws.sg[3], G}, {&ws.sg[4], G}, {&ws.sg[5], G},
         {&ws.sg[6], G}, {&ws.sg[7], G}, {&ws.sg[8], G},
         {(void **)&b.rho0, nzs * D}, {(void **)&b.theta0, nzs * D}, {(void **)&b.Theta0, nzs * D},
-        {(void **)&b.p0, nzs * D}, {(void **)&b.pi0, nzs * D}, {(void **)&b.dz, (4 * nzs + 1) * D},
+        {(void **)&b.p0, nzs * D}, {(void **)&b.pi0, nzs * D}, {(void **)&b.dz, (5 * nzs + 1) * D},
     };
     size_t total = 0;
     for (const Req &r : reqs) total += align_up(r.bytes);
@@ -172,7 +172,7 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     // dz, centre heights, 1/dz and 2/(dz_{k-1} + dz_k) on the z-faces
     const int nz = grid->nz;
     b.nz = nz;
-    double *hz = new double[4 * nz + 1];
+    double *hz = new double[5 * nz + 1];
     double zc = 0.0;
     for (int k = 0; k < nz; ++k) {
         hz[k] = grid->dz[k];
@@ -182,7 +182,11 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
         zc += grid->dz[k];
     }
     hz[4 * nz] = 0.0;
-    e = hipMemcpy(b.dz, hz, (4 * nz + 1) * sizeof(double), hipMemcpyHostToDevice);
+    for (int k = 0; k < nz; ++k) {
+        const double cd = prm->Cs * std::cbrt(grid->dx * grid->dy * grid->dz[k]);
+        hz[4 * nz + 1 + k] = cd * cd;
+    }
+    e = hipMemcpy(b.dz, hz, (5 * nz + 1) * sizeof(double), hipMemcpyHostToDevice);
     delete[] hz;
     if (e != hipSuccess) {
         erf_destroy(c);

@@ -183,13 +183,15 @@ struct MlpState {
 
 struct Base {
     double *rho0 = nullptr, *theta0 = nullptr, *Theta0 = nullptr, *p0 = nullptr, *pi0 = nullptr;
-    // device: dz [nz], centre heights [nz], 1/dz [nz] and the reciprocal
+    // device: dz [nz], centre heights [nz], 1/dz [nz], the reciprocal
     // centre-to-centre distances across the z-faces, 2/(dz_{k-1} + dz_k) [nz + 1]
-    // (zero on the lids), in one buffer
+    // (zero on the lids), and the squared Smagorinsky length (Cs Delta_k)^2 with
+    // Delta_k = (dx dy dz_k)^(1/3) [nz], in one buffer
     double *dz = nullptr;
     const double *zc() const { return dz + nz; }
     const double *idz() const { return dz + 2 * nz; }
     const double *idzf() const { return dz + 3 * nz; }
+    const double *cs2() const { return dz + 4 * nz + 1; }
     int nz = 0;
 };
 

@@ -31,21 +31,30 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int cidx(const Dims &d, int i, int j, int k) { return (k * d.ny + j) * d.nx + i; }
 
-// float -> bfloat16 bits, round to nearest even (infinities and overflow to
-// infinity follow from the carry into the exponent; NaN stays a quiet NaN)
-__device__ __forceinline__ unsigned int bf16_bits(float f)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// two floats -> packed bfloat16, round to nearest even (one v_cvt_pk_bf16_f32)
+__device__ __forceinline__ unsigned int pack2(float a, float b)
 {
-    unsigned int u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
+    bf16x2 v;
+    v[0] = (__bf16)a;
+    v[1] = (__bf16)b;
+    return __builtin_bit_cast(unsigned int, v);
 }
-__device__ __forceinline__ unsigned int pack2(float a, float b) { return bf16_bits(a) | (bf16_bits(b) << 16); }
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
 __device__ __forceinline__ floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// order this wave's LDS writes before its later LDS reads (the rows a wave
+// exchanges through LDS belong to that wave alone)
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // K-step operand from two 16-unit tiles: ReLU, then BF16
@@ -274,8 +283,8 @@ __device__ __forceinline__ double centre_smag(const double f[10], double dthx, d
 template <typename T>
 struct ClosureArgs {
     ClosureIn<T> in;
-    double dx, dy, Cs, Pr_t;
-    const double *dz, *rho0, *norm;  // norm: mean_x[10], std_x[10], mean_y[9], std_y[9]
+    double iPr_t;
+    const double *cs2, *rho0, *norm;  // cs2: (Cs Delta_k)^2 per level; norm: mean_x, std_x, mean_y, std_y
     const T *rho;
     const u32x4 *wpk;
     const float *bias;
@@ -285,24 +294,29 @@ struct ClosureArgs {
 
 constexpr int kClosureBlock = 256;
 
+// One wave takes 64 consecutive cells at a time (a persistent loop over the
+// grid): inputs in FP64 into LDS as BF16, the network on four groups of 16,
+// then per cell the de-standardised stresses, the fallback test and rho tau.
 template <typename T>
 __global__ __launch_bounds__(kClosureBlock) void k_mlp_closure(ClosureArgs<T> a)
 {
     __shared__ u32x4 xs_all[4][128];
     __shared__ float ys_all[4][64 * 12];
     __shared__ float bias[208];
-    __shared__ double nrm[38];
+    __shared__ double nrm[38];  // mean_x, 1 / std_x, mean_y, std_y
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int u = threadIdx.x; u < 208; u += kClosureBlock) bias[u] = a.bias[u];
-    for (int u = threadIdx.x; u < 38; u += kClosureBlock) nrm[u] = a.norm[u];
+    for (int u = threadIdx.x; u < 38; u += kClosureBlock)
+        nrm[u] = (u >= 10 && u < 20) ? 1.0 / a.norm[u] : a.norm[u];
     WaveWeights W;
     load_weights(W, a.wpk, lane);
     u32x4 *xs = xs_all[wave];
     float *ys = ys_all[wave];
     const Dims &d = a.in.d;
     __syncthreads();
-    for (int base = blockIdx.x * kClosureBlock; base < d.n; base += gridDim.x * kClosureBlock) {
-        const int c = base + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kClosureBlock;
+    for (int64_t base = (int64_t)blockIdx.x * kClosureBlock + wave * 64; base < d.n; base += stride) {
+        const int c = (int)base + lane;
         const bool valid = c < d.n;
         double f[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, dthx = 0.0, dthy = 0.0;
         int k = 0;
@@ -313,11 +327,11 @@ __global__ __launch_bounds__(kClosureBlock) void k_mlp_closure(ClosureArgs<T> a)
         }
         float x[10];
 #pragma unroll
-        for (int o = 0; o < 10; ++o) x[o] = valid ? (float)((f[o] - nrm[o]) / nrm[10 + o]) : 0.f;
+        for (int o = 0; o < 10; ++o) x[o] = valid ? (float)((f[o] - nrm[o]) * nrm[10 + o]) : 0.f;
         store_inputs(xs, lane, x);
-        __syncthreads();
+        wave_sync();
         mlp64(W, bias, xs, ys, lane);
-        __syncthreads();
+        wave_sync();
         bool fb = false;
         if (valid) {
             double t[9];
@@ -329,15 +343,23 @@ __global__ __launch_bounds__(kClosureBlock) void k_mlp_closure(ClosureArgs<T> a)
             }
             const double s11 = f[0], s22 = f[4], s33 = f[8];
             const double s12 = 0.5 * (f[1] + f[3]), s13 = 0.5 * (f[2] + f[6]), s23 = 0.5 * (f[5] + f[7]);
-            double ts[9];
-            const double cd = a.Cs * cbrt(a.dx * a.dy * a.dz[k]);
-            const double diss = centre_smag(f, dthx, dthy, cd, a.Pr_t, ts);
-            // energy transfer to the subgrid scales, -tau:S
+            const double ss = 2.0 * (s11 * s11 + s22 * s22 + s33 * s33) + 4.0 * (s12 * s12 + s13 * s13 + s23 * s23);
+            const double nut = a.cs2[k] * sqrt(ss);
+            // energy transfer to the subgrid scales, -tau:S, against the
+            // Smagorinsky dissipation nu_t |S|^2
             const double pi = -(t[0] * s11 + t[1] * s22 + t[2] * s33 + 2.0 * (t[3] * s12 + t[4] * s13 + t[5] * s23));
-            if (!finite || pi < -2.0 * diss) {
+            if (!finite || pi < -2.0 * (nut * ss)) {
                 fb = true;
-#pragma unroll
-                for (int o = 0; o < 9; ++o) t[o] = ts[o];
+                const double dd = (s11 + s22 + s33) / 3.0;
+                t[0] = -2.0 * nut * (s11 - dd);
+                t[1] = -2.0 * nut * (s22 - dd);
+                t[2] = -2.0 * nut * (s33 - dd);
+                t[3] = -2.0 * nut * s12;
+                t[4] = -2.0 * nut * s13;
+                t[5] = -2.0 * nut * s23;
+                t[6] = -(nut * a.iPr_t) * dthx;
+                t[7] = -(nut * a.iPr_t) * dthy;
+                t[8] = -(nut * a.iPr_t) * f[9];
             }
             const double r = full_of(a.rho, c, a.rho0[k]);
 #pragma unroll
@@ -345,8 +367,8 @@ __global__ __launch_bounds__(kClosureBlock) void k_mlp_closure(ClosureArgs<T> a)
         }
         const unsigned long long m = __ballot(fb);
         if (lane == 0 && m) atomicAdd(a.fallbacks, (unsigned long long)__popcll(m));
-        // the next chunk rewrites xs / ys only after every wave read them
-        __syncthreads();
+        // the next chunk rewrites this wave's rows only after it read them
+        wave_sync();
     }
 }
 
@@ -422,20 +444,21 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ X
     u32x4 *xs = xs_all[wave];
     float *ys = ys_all[wave];
     __syncthreads();
-    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
-        const int64_t s = base + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t base = (int64_t)blockIdx.x * 256 + wave * 64; base < n; base += stride) {
+        const int64_t s = base + lane;
         const bool valid = s < n;
         float x[10];
 #pragma unroll
         for (int o = 0; o < 10; ++o) x[o] = valid ? X[s * 10 + o] : 0.f;
         store_inputs(xs, lane, x);
-        __syncthreads();
+        wave_sync();
         mlp64(W, bias, xs, ys, lane);
-        __syncthreads();
+        wave_sync();
         if (valid)
 #pragma unroll
             for (int o = 0; o < 9; ++o) Y[s * 9 + o] = ys[lane * 12 + o];
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -766,11 +789,8 @@ hipError_t closure_t(erf_ctx *cx, const void *rho, void *const R[5])
     MlpState &m = cx->mlp;
     ClosureArgs<T> a{};
     a.in = closure_in<T>(cx);
-    a.dx = cx->grid.dx;
-    a.dy = cx->grid.dy;
-    a.Cs = cx->prm.Cs;
-    a.Pr_t = cx->prm.Pr_t;
-    a.dz = cx->base.dz;
+    a.iPr_t = 1.0 / cx->prm.Pr_t;
+    a.cs2 = cx->base.cs2();
     a.rho0 = cx->base.rho0;
     a.norm = m.norm;
     a.rho = (const T *)rho;
@@ -780,7 +800,7 @@ hipError_t closure_t(erf_ctx *cx, const void *rho, void *const R[5])
     a.fallbacks = m.fallbacks;
     const Dims &d = cx->d;
     timing_start(cx, K_MLP);
-    hipLaunchKernelGGL(k_mlp_closure<T>, dim3(grid_for(d.n, kClosureBlock, 2048)), dim3(kClosureBlock), 0,
+    hipLaunchKernelGGL(k_mlp_closure<T>, dim3(grid_for(d.n, kClosureBlock, 1024)), dim3(kClosureBlock), 0,
                        cx->stream, a);
     timing_stop(cx, K_MLP);
     DivArgs<T> v{};
@@ -864,7 +884,7 @@ hipError_t launch_mlp_closure(erf_ctx *cx, const void *rho, void *const R[5])
 hipError_t launch_mlp_forward(erf_ctx *cx, const float *x, int64_t n, float *y)
 {
     MlpState &m = cx->mlp;
-    hipLaunchKernelGGL(k_mlp_forward, dim3(grid_for(n, 256, 4096)), dim3(256), 0, cx->stream, x, n,
+    hipLaunchKernelGGL(k_mlp_forward, dim3(grid_for(n, 256, 1024)), dim3(256), 0, cx->stream, x, n,
                        (const u32x4 *)m.wpk, (const float *)m.bias, y);
     return hipGetLastError();
 }

@@ -27,7 +27,7 @@ template <typename T>
 struct RhsArgs {
     Dims d;
     double dx, dy, idx, idy;
-    const double *dz, *idz, *idzf;
+    const double *dz, *idz, *idzf, *cs2;
     int oh, ov;
     int sgs, visc;
     double Cs, Pr_t, nu, alpha, f, Ug, Vg, Qs, g;
@@ -132,8 +132,7 @@ __global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
     const double a23 =
         0.25 * (s23(0, n.jm, k) + s23(n.jp, njp_jm, k) + s23(P, n.jm, k + 1) + s23(P + n.jp, njp_jm, k + 1));
     const double ss = 2.0 * (e11 * e11 + e22 * e22 + e33 * e33) + 4.0 * (a12 * a12 + a13 * a13 + a23 * a23);
-    const double cd = a.Cs * cbrt(a.dx * a.dy * a.dz[k]);
-    a.mut[c] = full_of(a.rho, c, a.rho0[k]) * cd * cd * sqrt(ss);
+    a.mut[c] = full_of(a.rho, c, a.rho0[k]) * a.cs2[k] * sqrt(ss);
 }
 
 // Stresses tau = -2 mu (S - D) at their points, mu = rho nu_m + mu_t averaged
@@ -391,6 +390,7 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5], boo
     a.dz = cx->base.dz;
     a.idz = cx->base.idz();
     a.idzf = cx->base.idzf();
+    a.cs2 = cx->base.cs2();
     a.oh = p.adv_order_h;
     a.ov = p.adv_order_v;
     // the learned closure adds its own stress divergence after k_rhs

@@ -35,7 +35,11 @@ EXPORTS = ("erf_base_state_host", "erf_create", "erf_destroy", "erf_last_error",
            "erf_rk3_step", "erf_diagnostics", "erf_timing_begin", "erf_timing_end",
            "erf_mlp_set_weights", "erf_mlp_get_weights", "erf_mlp_forward", "erf_mlp_features",
            "erf_box_filter", "erf_mlp_fit_norm", "erf_mlp_standardize", "erf_mlp_loss_grad",
-           "erf_mlp_train_step", "erf_mlp_fallback_count")
+           "erf_mlp_train_step", "erf_mlp_fallback_count",
+           "erf_ensemble_create", "erf_ensemble_destroy", "erf_ensemble_last_error", "erf_ensemble_member",
+           "erf_ensemble_set_branches", "erf_ensemble_branches", "erf_ensemble_rk3_step", "erf_ensemble_autotune")
+_NOT_STATUS = ("erf_destroy", "erf_last_error", "erf_workspace_bytes", "erf_ensemble_destroy",
+               "erf_ensemble_last_error", "erf_ensemble_member", "erf_ensemble_branches")
 
 
 class ErfError(RuntimeError):
@@ -112,9 +116,23 @@ def load(path: str = LIB_PATH):
             L.erf_mlp_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, _DP]
             L.erf_mlp_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, _DP]
             L.erf_mlp_fallback_count.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+            L.erf_ensemble_create.argtypes = [C.c_int32, C.POINTER(Grid), C.POINTER(Params), C.c_void_p,
+                                              C.POINTER(C.c_void_p)]
+            L.erf_ensemble_destroy.argtypes = [C.c_void_p]
+            L.erf_ensemble_destroy.restype = None
+            L.erf_ensemble_last_error.argtypes = [C.c_void_p]
+            L.erf_ensemble_last_error.restype = C.c_char_p
+            L.erf_ensemble_member.argtypes = [C.c_void_p, C.c_int32]
+            L.erf_ensemble_member.restype = C.c_void_p
+            L.erf_ensemble_set_branches.argtypes = [C.c_void_p, C.c_int32]
+            L.erf_ensemble_branches.argtypes = [C.c_void_p]
+            L.erf_ensemble_branches.restype = C.c_int32
+            L.erf_ensemble_rk3_step.argtypes = [C.c_void_p, C.POINTER(State)]
+            L.erf_ensemble_autotune.argtypes = [C.c_void_p, C.POINTER(State), C.c_int32, C.POINTER(C.c_int32),
+                                                C.POINTER(C.c_double)]
             for name in EXPORTS:
                 fn = getattr(L, name)
-                if name not in ("erf_destroy", "erf_last_error", "erf_workspace_bytes"):
+                if name not in _NOT_STATUS:
                     fn.restype = C.c_int32
             _lib = L
     return _lib
@@ -148,7 +166,7 @@ def params_from_config(cfg) -> Params:
 class Solver:
     """One liberf context: a grid, a parameter set and a HIP stream."""
 
-    def __init__(self, cfg, stream=None):
+    def __init__(self, cfg, stream=None, _handle=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("liberf needs a GPU; none is visible")
@@ -161,19 +179,23 @@ class Solver:
         self._dz = np.ascontiguousarray(cfg.dz, dtype=np.float64)
         self._grid = Grid(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, _np_ptr(self._dz))
         self._params = params_from_config(cfg)
-        h = C.c_void_p()
-        st = self.L.erf_create(C.byref(self._grid), C.byref(self._params), C.c_void_p(self.stream.cuda_stream),
-                               C.byref(h))
-        if st != ERF_OK:
-            raise ErfError(st, "erf_create")
-        self.h = h
+        self._owned = _handle is None
+        if _handle is not None:      # a member context owned by an Ensemble
+            self.h = C.c_void_p(_handle)
+        else:
+            h = C.c_void_p()
+            st = self.L.erf_create(C.byref(self._grid), C.byref(self._params),
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(h))
+            if st != ERF_OK:
+                raise ErfError(st, "erf_create")
+            self.h = h
         self.base = None
 
     # -- lifetime ----------------------------------------------------------
     def close(self):
-        if getattr(self, "h", None) is not None and self.h.value:
+        if getattr(self, "h", None) is not None and self.h.value and self._owned:
             self.L.erf_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -397,3 +419,69 @@ class Solver:
             self._check(st, "erf_diagnostics")
         return {"mass": d.mass, "theta_mass": d.theta_mass, "energy": d.energy, "max_w": d.max_w,
                 "nonfinite": int(d.nonfinite), "scalar_mass": np.array(d.scalar_mass[:self.cfg.n_scalars])}
+
+
+class Ensemble:
+    """Independent members stepped together (include/erf_ensemble.h): one HIP
+    graph launch per ensemble step."""
+
+    def __init__(self, cfgs, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("liberf needs a GPU; none is visible")
+        self.torch = torch
+        self.L = load()
+        self.cfgs = list(cfgs)
+        n = len(self.cfgs)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._dz = [np.ascontiguousarray(c.dz, dtype=np.float64) for c in self.cfgs]
+        grids = (Grid * n)(*[Grid(c.nx, c.ny, c.nz, c.dx, c.dy, _np_ptr(d)) for c, d in zip(self.cfgs, self._dz)])
+        params = (Params * n)(*[params_from_config(c) for c in self.cfgs])
+        h = C.c_void_p()
+        st = self.L.erf_ensemble_create(n, grids, params, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != ERF_OK:
+            raise ErfError(st, "erf_ensemble_create")
+        self.h = h
+        self.members = [Solver(c, stream=self.stream, _handle=self.L.erf_ensemble_member(h, m))
+                        for m, c in enumerate(self.cfgs)]
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            for s in self.members:
+                s.h = None
+            self.L.erf_ensemble_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != ERF_OK:
+            msg = self.L.erf_ensemble_last_error(self.h)
+            raise ErfError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def _states(self, states):
+        if len(states) != len(self.members):
+            raise ValueError("one state per member")
+        return (State * len(states))(*[m._st(S) for m, S in zip(self.members, states)])
+
+    @property
+    def branches(self) -> int:
+        return int(self.L.erf_ensemble_branches(self.h))
+
+    def set_branches(self, n: int):
+        self._check(self.L.erf_ensemble_set_branches(self.h, int(n)), "erf_ensemble_set_branches")
+
+    def rk3_step(self, states):
+        self._states_keep = self._states(states)
+        self._check(self.L.erf_ensemble_rk3_step(self.h, self._states_keep), "erf_ensemble_rk3_step")
+
+    def autotune(self, states, trials: int = 3):
+        nb, ms = C.c_int32(), C.c_double()
+        self._check(self.L.erf_ensemble_autotune(self.h, self._states(states), int(trials), C.byref(nb),
+                                                 C.byref(ms)), "erf_ensemble_autotune")
+        return nb.value, ms.value

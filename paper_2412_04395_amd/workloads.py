@@ -269,6 +269,47 @@ def cbl(n_substeps: int = 6, **kw) -> Config:
     return c.replace(**kw)
 
 
+def les_mlp(**kw) -> Config:
+    """Coarse LES with the learned subgrid closure: 128x128x64 cells at 40 m
+    (5.12 x 5.12 x 2.56 km), the boundary-layer physics of cbl() with the
+    closure in place of Smagorinsky (which stays as its fallback), FP32
+    storage, dt = 0.4 s with 8 substeps (horizontal acoustic Courant number
+    c dtau / dx = 0.43)."""
+    c = Config(name="mlp_les", nx=128, ny=128, nz=64, dx=40.0, dy=40.0, dz=uniform_dz(64, 40.0),
+               dt=0.4, n_substeps=8, steps=20, adv_order_h=5, adv_order_v=5, sgs=2,
+               Cs=0.1, Pr_t=1.0 / 3.0, f_cor=1.0e-4, Ug=10.0, Vg=0.0, surf_heat_flux=0.2, prec="fp32", seed=41)
+    return c.replace(**kw)
+
+
+def les_fine(**kw) -> Config:
+    """Fine LES that the learned closure is trained on: the boundary-layer
+    physics of cbl() at 10 m, 256x256x128 cells (2.56 x 2.56 x 1.28 km), FP64,
+    Smagorinsky, dt = 0.1 s with 8 substeps (c dtau / dx = 0.43).  Its 4x box
+    filter lives on the 40 m grid of les_mlp()."""
+    c = Config(name="mlp_fine", nx=256, ny=256, nz=128, dx=10.0, dy=10.0, dz=uniform_dz(128, 10.0),
+               dt=0.1, n_substeps=8, steps=20, adv_order_h=5, adv_order_v=5, sgs=1,
+               Cs=0.1, Pr_t=1.0 / 3.0, f_cor=1.0e-4, Ug=10.0, Vg=0.0, surf_heat_flux=0.2, seed=41)
+    return c.replace(**kw)
+
+
+def ensemble(sizes=((96, 96, 64), (128, 128, 64), (192, 192, 96)), per_size: int = 16, **kw) -> list:
+    """Ensemble of boundary-layer LES members at 40 m: per_size members of each
+    size (default 16 each of 96x96x64, 128x128x64 and 192x192x96, 82,837,504
+    cells), FP32 storage, 5th-order upwind, dt = 0.4 s with 8 substeps.  Member
+    m has seed 5000 + m and a surface heat flux drawn uniformly from
+    [0.05, 0.3] K m/s (seed 5999); odd members use the learned closure, even
+    members Smagorinsky."""
+    n = per_size * len(sizes)
+    qs = 0.175 + uniform_noise(5999, (n,), 0.125)
+    out = []
+    for m in range(n):
+        nx, ny, nz = sizes[m // per_size]
+        c = les_mlp(name=f"ens_{m}", nx=nx, ny=ny, nz=nz, dz=uniform_dz(nz, 40.0), seed=5000 + m,
+                    surf_heat_flux=float(qs[m]), sgs=2 if m % 2 else 1)
+        out.append(c.replace(**kw))
+    return out
+
+
 def deep(**kw) -> Config:
     """80-level deep atmosphere, stretched dz 50-500 m to 20 km, 250 m horizontal,
     3 tracers by WENO5, 3rd-order momentum, dt = 2 s, 8 substeps."""
@@ -303,5 +344,7 @@ CONFIGS = {
     "bubble2d": bubble2d,
     "cbl": cbl,
     "deep": deep,
+    "les_mlp": les_mlp,
+    "les_fine": les_fine,
     "density_current": density_current,
 }

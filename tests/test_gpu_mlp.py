@@ -94,6 +94,33 @@ def test_network_integer_case_is_bitwise():
     assert len(bad) == 0, bad[:10]
 
 
+def test_bf16_rounding_of_inputs_is_nearest_even():
+    """A network that passes x_0..x_8 through unchanged (relu(x) - relu(-x)):
+    its outputs are the BF16 roundings of the inputs, ties to even included,
+    bitwise equal to the oracle's BF16 mode."""
+    torch = pytest.importorskip("torch")
+    p = np.zeros(NP)
+    v = _view(p)
+    for i in range(10):
+        v["W1"][i, 2 * i], v["W1"][i, 2 * i + 1] = 1.0, -1.0
+    for h in range(20):
+        v["W2"][h, h] = v["W3"][h, h] = 1.0
+    for i in range(9):
+        v["W4"][2 * i, i], v["W4"][2 * i + 1, i] = 1.0, -1.0
+    ties = [257.0, 259.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20, 3 * 2 ** -9 + 2 ** -17,
+            -257.0, -(1 + 3 * 2 ** -8), 255.5, 0.1, -1e-3, 65535.0, 2 ** -130, 3.0e38]
+    rng = np.random.default_rng(25)
+    x = rng.choice(ties, size=(640, 10)).astype(np.float32).astype(np.float64)
+    ref = oracle.mlp_forward(p, x, bf16=True)
+    s, _ = _solver(_net_cfg())
+    s.mlp_set_weights(p.astype(np.float32))
+    y = s.mlp_forward(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().double().numpy()
+    assert np.array_equal(ref[:, 0][x[:, 0] == 257.0], np.full(np.sum(x[:, 0] == 257.0), 256.0))
+    bad = np.argwhere(y != ref)
+    _say(f"bf16 ties: {len(bad)} of {y.size} outputs differ")
+    assert len(bad) == 0, [(x[i, j], y[i, j], ref[i, j]) for i, j in bad[:5]]
+
+
 def test_network_real_parameters_match_bf16_oracle():
     torch = pytest.importorskip("torch")
     p = _he_params(22)
