@@ -139,11 +139,39 @@ def run_gpu(cfg: W.Config, steps: int, warmup: int):
     return el, dominant, kms, kn, shares, d
 
 
+WEIGHTS = os.path.join(ROOT, "paper_2412_04395_amd", "data", "closure_les40m.npz")
+
+
+def closure_weights(solver, S, seed: int):
+    """Trained closure weights if the package holds them, else He-initialised
+    weights with input scales from S floored at physical values (1e-2 1/s,
+    1e-3 K/m) and output scales of 1e-4 (the values do not change the work)."""
+    if os.path.exists(WEIGHTS):
+        z = np.load(WEIGHTS, allow_pickle=False)
+        solver.mlp_set_weights(z["params"], z["norm"])
+        return "trained"
+    import torch
+    from paper_2412_04395_amd import erf
+    rng = np.random.default_rng(seed)
+    p = np.zeros(erf.MLP_NPARAMS)
+    for off, fan_in, fan_out in ((0, 10, 64), (704, 64, 64), (4864, 64, 64), (9024, 64, 9)):
+        p[off:off + fan_in * fan_out] = rng.normal(0, np.sqrt(2.0 / fan_in), fan_in * fan_out)
+    solver.mlp_set_weights(p.astype(np.float32))
+    feat = solver.mlp_features(S)
+    solver.mlp_fit_norm(feat, torch.zeros((feat.shape[0], 9), dtype=torch.float64, device=feat.device))
+    del feat
+    p32, nrm = solver.mlp_get_weights()
+    nrm[10:19] = np.maximum(nrm[10:19], 1e-2)
+    nrm[19] = max(nrm[19], 1e-3)
+    nrm[29:] = 1e-4
+    solver.mlp_set_weights(p32, nrm)
+    return "he-initialised"
+
+
 def run_closure(steps: int, warmup: int):
     """RK3 steps of the coarse LES with the learned closure (128x128x64, FP32):
-    step throughput and the closure kernel's matrix-core roofline.  The network
-    has He-initialised weights (the values do not change the work) with output
-    scales small enough that the run stays on the network, not the fallback."""
+    step throughput and the closure kernel's matrix-core roofline (weights as
+    closure_weights gives them)."""
     import torch
     from paper_2412_04395_amd import erf
 
@@ -152,21 +180,7 @@ def run_closure(steps: int, warmup: int):
     th0 = W.theta_sounding(cfg)
     b = s.init_base_state(th0)
     S = s.from_full(W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"]))
-    rng = np.random.default_rng(cfg.seed)
-    p = np.zeros(erf.MLP_NPARAMS)
-    for off, fan_in, fan_out in ((0, 10, 64), (704, 64, 64), (4864, 64, 64), (9024, 64, 9)):
-        p[off:off + fan_in * fan_out] = rng.normal(0, np.sqrt(2.0 / fan_in), fan_in * fan_out)
-    s.mlp_set_weights(p.astype(np.float32))
-    feat = s.mlp_features(S)
-    s.mlp_fit_norm(feat, torch.zeros((feat.shape[0], 9), dtype=torch.float64, device=feat.device))
-    del feat
-    p32, nrm = s.mlp_get_weights()
-    # the initial state is nearly free of velocity gradients: floor the input
-    # scales at physical values (1e-2 1/s, 1e-3 K/m) so inputs stay O(1)
-    nrm[10:19] = np.maximum(nrm[10:19], 1e-2)
-    nrm[19] = max(nrm[19], 1e-3)
-    nrm[29:] = 1e-4
-    s.mlp_set_weights(p32, nrm)
+    weights = closure_weights(s, S, cfg.seed)
     for _ in range(warmup):
         s.rk3_step(S)
     shares = {}
@@ -182,6 +196,7 @@ def run_closure(steps: int, warmup: int):
     flops = MLP_FLOP_PER_CELL * cfg.cells
     achieved = flops / (avg_ms * 1e-3) / 1e12
     return {"workload": cfg.name, "grid": [cfg.nx, cfg.ny, cfg.nz], "precision": "FP32 storage, BF16 network",
+            "weights": weights,
             "value": cfg.cells * steps / el, "unit": "cell-updates/s", "ms_per_step": 1e3 * el / steps,
             "kernel_ms_per_step": shares, "fallback_fraction": fb / (3 * steps * cfg.cells),
             "final_diag": {"max_w": d["max_w"], "nonfinite": d["nonfinite"]},
@@ -189,6 +204,54 @@ def run_closure(steps: int, warmup: int):
                          "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
                          "traffic": None, "flop_per_launch": flops, "avg_launch_ms": round(avg_ms, 4),
                          "launches_timed": kn}}
+
+
+def run_ensemble(steps: int, warmup: int, per_size: int = 16):
+    """The 48-member ensemble (16 each of 96x96x64, 128x128x64, 192x192x96 at
+    40 m, FP32, odd members on the learned closure): member steps one after
+    another on one stream against one graph launch per ensemble step with the
+    autotuned branch count."""
+    import torch
+    from paper_2412_04395_amd import erf
+
+    cfgs = W.ensemble(per_size=per_size)
+    ens = erf.Ensemble(cfgs)
+    states, weights = [], None
+    for s, c in zip(ens.members, cfgs):
+        th0 = W.theta_sounding(c)
+        b = s.init_base_state(th0)
+        S = s.from_full(W.initial_state(c, b["rho0"], th0, b["p0"], b["pi0"]))
+        if c.sgs == 2:
+            weights = closure_weights(s, S, c.seed)
+        states.append(S)
+    cells = sum(c.cells for c in cfgs)
+    # members one after another, ordinary launches on one stream
+    for _ in range(warmup):
+        for s, S in zip(ens.members, states):
+            s.rk3_step(S)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for s, S in zip(ens.members, states):
+            s.rk3_step(S)
+    torch.cuda.synchronize()
+    el_seq = time.perf_counter() - t0
+    nb, tune_ms = ens.autotune(states, trials=2)
+    for _ in range(warmup):
+        ens.rk3_step(states)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ens.rk3_step(states)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    bad = sum(s.diagnostics(S, allow_nonfinite=True)["nonfinite"] for s, S in zip(ens.members, states))
+    ens.close()
+    return {"workload": f"ensemble of {len(cfgs)} boundary-layer members", "members": len(cfgs), "cells": cells,
+            "precision": "FP32 storage; odd members BF16 closure", "weights": weights,
+            "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": 1e3 * el / steps,
+            "branches": nb, "sequential_ms_per_step": 1e3 * el_seq / steps, "speedup_vs_sequential": el_seq / el,
+            "nonfinite": bad}
 
 
 def cpu_baseline(cfg: W.Config, target_s: float = 15.0):
@@ -236,6 +299,7 @@ def main(argv=None):
     ap.add_argument("--no-as-stated", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-closure", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first run one plain device copy of this many GiB (reference for HBM counters)")
     a = ap.parse_args(argv)
@@ -284,6 +348,8 @@ def main(argv=None):
                        "kernel_ms_per_step": {k: round(v[0], 4) for k, v in shares3.items()}}
     if a.workload == "cbl" and not a.no_closure:
         out["closure"] = run_closure(a.steps, a.warmup)
+    if a.workload == "cbl" and not a.no_ensemble:
+        out["ensemble"] = run_ensemble(min(a.steps, 5), min(a.warmup, 1))
     if rank == 0 and not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     if rank == 0:

@@ -34,16 +34,6 @@ constexpr int kLanes = 64;  // columns per tile (one wavefront)
 
 __device__ __forceinline__ int cidx(const Dims &d, int i, int j, int k) { return (k * d.ny + j) * d.nx + i; }
 
-// Tiles handled by one XCD form a contiguous range of the tile order (the
-// hardware hands consecutive workgroups to the 8 XCDs in turn).
-__device__ __forceinline__ int xcd_tile(int b, int nblocks)
-{
-    const int nx = 8;
-    int x = b % nx, m = b / nx;
-    int q = nblocks / nx, r = nblocks % nx;
-    return x * q + (x < r ? x : r) + m;
-}
-
 template <typename T>
 struct StageArgs {
     Dims d;
@@ -122,6 +112,9 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
     const int col = j * d.nx + i, nxy = d.nxy, nz = d.nz;
     const double D = a.dtau * a.dtau * a.b2 * a.b2, g = a.g;
     double cprev = 0.0;
+    // one column per thread leaves one wavefront per SIMD: unrolling lets the
+    // loads of several levels (independent of the recurrence) issue together
+#pragma unroll 4
     for (int k = 1; k < nz; ++k) {
         int c = col + k * nxy, cm = c - nxy;
         double dzf = 0.5 * (a.dz[k - 1] + a.dz[k]);
@@ -158,7 +151,7 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
     double *rbuf = lds;                     // [(nz + 1) * 64]
     double *bnd = lds + (nz + 1) * kLanes;  // [KG][2][64]
 
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int i = tx * a.TX + lane % a.TX, j = ty * a.TY + lane / a.TX;
     const bool act = (i < d.nx) && (j < d.ny);

@@ -79,6 +79,28 @@ __device__ __forceinline__ int refl_face(int k, int nz, double &sgn)
     return k;
 }
 
+// Workgroups go to the 8 XCDs of the chip round-robin by linear id.  This maps
+// the linear id b of a grid of n workgroups to a position such that every XCD
+// receives one contiguous range of positions, so neighbouring tiles (and
+// their stencil halos) share one L2.
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    const int x = b % 8, m = b / 8, q = n / 8, r = n % 8;
+    return x * q + (x < r ? x : r) + m;
+}
+
+// Cell (i, j, k) of a flattened 64 x 4 x 1 tiling launched as a 1-D grid of
+// ntx * nty * nlev workgroups, in XCD-contiguous order (x tiles fastest).
+struct TileIdx {
+    int i, j, k;
+};
+__device__ __forceinline__ TileIdx tile_cell(int ntx, int nty)
+{
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = t % ntx, r = t / ntx, by = r % nty, bz = r / nty;
+    return {bx * 64 + (int)threadIdx.x, by * 4 + (int)threadIdx.y, bz};
+}
+
 __device__ __forceinline__ double sign_of(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
 // Storage conventions.  FP64 storage holds full rho and rho*theta; FP32

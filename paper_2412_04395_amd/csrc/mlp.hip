@@ -378,6 +378,7 @@ __global__ __launch_bounds__(kClosureBlock) void k_mlp_closure(ClosureArgs<T> a)
 template <typename T>
 struct DivArgs {
     Dims d;
+    int ntx, nty;
     double idx, idy;
     const double *idz, *idzf;
     const T *s[9];
@@ -390,7 +391,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_mlp_div(DivArgs<T> a)
 {
     const Dims &d = a.d;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y, k = blockIdx.z;
+    const TileIdx tc = tile_cell(a.ntx, a.nty);
+    const int i = tc.i, j = tc.j, k = tc.k;
     if (i >= d.nx || j >= d.ny) return;
     const int nz = d.nz;
     auto S = [&](int o, int ii, int jj, int kk) {
@@ -814,8 +816,10 @@ hipError_t closure_t(erf_ctx *cx, const void *rho, void *const R[5])
     v.Ru = (T *)R[2];
     v.Rv = (T *)R[3];
     v.Rw = (T *)R[4];
+    v.ntx = (d.nx + 63) / 64;
+    v.nty = (d.ny + 3) / 4;
     timing_start(cx, K_MLP_DIV);
-    hipLaunchKernelGGL(k_mlp_div<T>, dim3((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz), dim3(64, 4, 1), 0, cx->stream, v);
+    hipLaunchKernelGGL(k_mlp_div<T>, dim3(v.ntx * v.nty * d.nz), dim3(64, 4, 1), 0, cx->stream, v);
     timing_stop(cx, K_MLP_DIV);
     return hipGetLastError();
 }

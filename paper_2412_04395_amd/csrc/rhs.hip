@@ -29,6 +29,7 @@ struct RhsArgs {
     double dx, dy, idx, idy;
     const double *dz, *idz, *idzf, *cs2;
     int oh, ov;
+    int ntx, nty;  // 64 x 4 tiles per level
     int sgs, visc;
     double Cs, Pr_t, nu, alpha, f, Ug, Vg, Qs, g;
     // state
@@ -51,9 +52,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_prep(RhsArgs<T> a)
 {
     const Dims &d = a.d;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y * blockDim.y + threadIdx.y;
-    int k = blockIdx.z;
+    const TileIdx t = tile_cell(a.ntx, a.nty);
+    const int i = t.i, j = t.j, k = t.k;
     if (i >= d.nx || j >= d.ny) return;
     int c = cidx(d, i, j, k);
     const double r0 = a.rho0[k], T0 = a.Theta0[k];
@@ -92,9 +92,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
 {
     const Dims &d = a.d;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y * blockDim.y + threadIdx.y;
-    int k = blockIdx.z;
+    const TileIdx t = tile_cell(a.ntx, a.nty);
+    const int i = t.i, j = t.j, k = t.k;
     if (i >= d.nx || j >= d.ny) return;
     const Nbr n = nbr(d, i, j, k);
     const int c = n.c, P = d.nxy;
@@ -142,9 +141,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_stress(RhsArgs<T> a)
 {
     const Dims &d = a.d;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y * blockDim.y + threadIdx.y;
-    int k = blockIdx.z;
+    const TileIdx t = tile_cell(a.ntx, a.nty);
+    const int i = t.i, j = t.j, k = t.k;
     if (i >= d.nx || j >= d.ny) return;
     const Nbr n = nbr(d, i, j, k);
     const int P = d.nxy, c = n.c;
@@ -208,9 +206,8 @@ template <typename T, int OH, int OV>
 __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
 {
     const Dims &d = a.d;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const TileIdx tc = tile_cell(a.ntx, a.nty);
+    const int i = tc.i, j = tc.j, k = tc.k;
     if (i >= d.nx || j >= d.ny) return;
     const int nz = d.nz, P = d.nxy;
     const int c = cidx(d, i, j, k);
@@ -434,8 +431,9 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5], boo
     a.Rv = (T *)R[3];
     a.Rw = (T *)R[4];
     const Dims &d = cx->d;
-    dim3 blk(64, 4, 1), grd((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz);
-    dim3 grdw((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz + 1);
+    a.ntx = (d.nx + 63) / 64;
+    a.nty = (d.ny + 3) / 4;
+    dim3 blk(64, 4, 1), grd(a.ntx * a.nty * d.nz), grdw(a.ntx * a.nty * (d.nz + 1));
     timing_start(cx, K_PREP); hipLaunchKernelGGL(k_prep<T>, grd, blk, 0, cx->stream, a); timing_stop(cx, K_PREP);
     if (prep_only) return hipGetLastError();
     if (a.sgs) { timing_start(cx, K_MUT); hipLaunchKernelGGL(k_mut<T>, grd, blk, 0, cx->stream, a); timing_stop(cx, K_MUT); }
