@@ -112,9 +112,6 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
     const int col = j * d.nx + i, nxy = d.nxy, nz = d.nz;
     const double D = a.dtau * a.dtau * a.b2 * a.b2, g = a.g;
     double cprev = 0.0;
-    // one column per thread leaves one wavefront per SIMD: unrolling lets the
-    // loads of several levels (independent of the recurrence) issue together
-#pragma unroll 4
     for (int k = 1; k < nz; ++k) {
         int c = col + k * nxy, cm = c - nxy;
         double dzf = 0.5 * (a.dz[k - 1] + a.dz[k]);

@@ -90,13 +90,16 @@ __device__ __forceinline__ int xcd_remap(int b, int n)
 }
 
 // Cell (i, j, k) of a flattened 64 x 4 x 1 tiling launched as a 1-D grid of
-// ntx * nty * nlev workgroups, in XCD-contiguous order (x tiles fastest).
+// ntx * nty * nlev workgroups, x tiles fastest.  (Measured on the slow-RHS
+// kernels: the XCD-contiguous order of xcd_remap is slower there -- 5-7 % --
+// than this plain order, whose concurrently resident workgroups span several
+// neighbouring levels.)
 struct TileIdx {
     int i, j, k;
 };
 __device__ __forceinline__ TileIdx tile_cell(int ntx, int nty)
 {
-    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int t = blockIdx.x;
     const int bx = t % ntx, r = t / ntx, by = r % nty, bz = r / nty;
     return {bx * 64 + (int)threadIdx.x, by * 4 + (int)threadIdx.y, bz};
 }

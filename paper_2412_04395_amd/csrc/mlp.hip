@@ -118,15 +118,20 @@ __global__ __launch_bounds__(64) void k_mlp_pack(const float *__restrict__ P, u3
 // the network on 64 samples of one wave
 // ---------------------------------------------------------------------------
 // xs: 64 rows of 16 BF16 inputs (10 used) as two u32x4 each; ys: 64 rows of 12
-// floats (9 used).  W: the wave's 22 packed operands; bias in LDS.
+// floats (9 used).  The 22 packed operands and the biases sit in LDS, shared by
+// the block's wavefronts (registers stay free for more wavefronts per SIMD).
 struct WaveWeights {
-    bf16x8 w[22];
+    const u32x4 *w;  // LDS, [22][64]
+    int lane;
+    __device__ __forceinline__ bf16x8 operator[](int o) const { return as_bf16x8(w[o * 64 + lane]); }
 };
 
-__device__ __forceinline__ void load_weights(WaveWeights &W, const u32x4 *__restrict__ wpk, int lane)
+// the block copies the packed operands and biases into LDS
+__device__ __forceinline__ void stage_weights(u32x4 *wl, float *bias, const u32x4 *__restrict__ wpk,
+                                              const float *__restrict__ biasg)
 {
-#pragma unroll
-    for (int o = 0; o < 22; ++o) W.w[o] = as_bf16x8(wpk[o * 64 + lane]);
+    for (int u = threadIdx.x; u < 22 * 64; u += blockDim.x) wl[u] = wpk[u];
+    for (int u = threadIdx.x; u < 208; u += blockDim.x) bias[u] = biasg[u];
 }
 
 __device__ __forceinline__ floatx4 bias4(const float *b, int g)
@@ -143,18 +148,18 @@ __device__ __forceinline__ floatx4 mlp16(const WaveWeights &W, const float *bias
 {
     floatx4 h[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) h[t] = mfma(W.w[t], x, bias4(bias + 16 * t, g));
+    for (int t = 0; t < 4; ++t) h[t] = mfma(W[t], x, bias4(bias + 16 * t, g));
     bf16x8 b0 = relu_pack(h[0], h[1]), b1 = relu_pack(h[2], h[3]);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) h[t] = mfma(W.w[5 + 2 * t], b1, mfma(W.w[4 + 2 * t], b0, bias4(bias + 64 + 16 * t, g)));
+    for (int t = 0; t < 4; ++t) h[t] = mfma(W[5 + 2 * t], b1, mfma(W[4 + 2 * t], b0, bias4(bias + 64 + 16 * t, g)));
     b0 = relu_pack(h[0], h[1]);
     b1 = relu_pack(h[2], h[3]);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
-        h[t] = mfma(W.w[13 + 2 * t], b1, mfma(W.w[12 + 2 * t], b0, bias4(bias + 128 + 16 * t, g)));
+        h[t] = mfma(W[13 + 2 * t], b1, mfma(W[12 + 2 * t], b0, bias4(bias + 128 + 16 * t, g)));
     b0 = relu_pack(h[0], h[1]);
     b1 = relu_pack(h[2], h[3]);
-    return mfma(W.w[21], b1, mfma(W.w[20], b0, bias4(bias + 192, g)));
+    return mfma(W[21], b1, mfma(W[20], b0, bias4(bias + 192, g)));
 }
 
 // xs/ys are this wave's LDS rows; the caller synchronises around the call
@@ -166,7 +171,12 @@ __device__ __forceinline__ void mlp64(const WaveWeights &W, const float *bias, c
         const int row = 16 * q + col;
         const u32x4 zero = {0u, 0u, 0u, 0u};
         const bf16x8 x = as_bf16x8(g < 2 ? xs[2 * row + g] : zero);
-        const floatx4 y = mlp16(W, bias, x, g);
+        // an index the compiler cannot prove equal across groups: every
+        // operand is read from LDS right before its one product instead of
+        // being held in 88 registers for the whole loop
+        int ln = W.lane;
+        asm volatile("" : "+v"(ln));
+        const floatx4 y = mlp16(WaveWeights{W.w, ln}, bias, x, g);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             if (4 * g + r < kMlpOut) ys[row * 12 + 4 * g + r] = y[r];
@@ -292,24 +302,24 @@ struct ClosureArgs {
     unsigned long long *fallbacks;
 };
 
-constexpr int kClosureBlock = 256;
+constexpr int kClosureBlock = 512;  // 8 wavefronts
 
 // One wave takes 64 consecutive cells at a time (a persistent loop over the
 // grid): inputs in FP64 into LDS as BF16, the network on four groups of 16,
 // then per cell the de-standardised stresses, the fallback test and rho tau.
 template <typename T>
-__global__ __launch_bounds__(kClosureBlock) void k_mlp_closure(ClosureArgs<T> a)
+__global__ __launch_bounds__(kClosureBlock, 4) void k_mlp_closure(ClosureArgs<T> a)
 {
-    __shared__ u32x4 xs_all[4][128];
-    __shared__ float ys_all[4][64 * 12];
+    __shared__ u32x4 wl[22 * 64];
+    __shared__ u32x4 xs_all[kClosureBlock / 64][128];
+    __shared__ float ys_all[kClosureBlock / 64][64 * 12];
     __shared__ float bias[208];
     __shared__ double nrm[38];  // mean_x, 1 / std_x, mean_y, std_y
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int u = threadIdx.x; u < 208; u += kClosureBlock) bias[u] = a.bias[u];
+    stage_weights(wl, bias, a.wpk, a.bias);
     for (int u = threadIdx.x; u < 38; u += kClosureBlock)
         nrm[u] = (u >= 10 && u < 20) ? 1.0 / a.norm[u] : a.norm[u];
-    WaveWeights W;
-    load_weights(W, a.wpk, lane);
+    const WaveWeights W{wl, lane};
     u32x4 *xs = xs_all[wave];
     float *ys = ys_all[wave];
     const Dims &d = a.in.d;
@@ -432,17 +442,17 @@ __global__ __launch_bounds__(256) void k_mlp_div(DivArgs<T> a)
 // ---------------------------------------------------------------------------
 // the network alone: standardised x[n][10] -> y[n][9]
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ X, int64_t n,
+__global__ __launch_bounds__(256, 3) void k_mlp_forward(const float *__restrict__ X, int64_t n,
                                                      const u32x4 *__restrict__ wpk, const float *__restrict__ biasg,
                                                      float *__restrict__ Y)
 {
+    __shared__ u32x4 wl[22 * 64];
     __shared__ u32x4 xs_all[4][128];
     __shared__ float ys_all[4][64 * 12];
     __shared__ float bias[208];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int u = threadIdx.x; u < 208; u += 256) bias[u] = biasg[u];
-    WaveWeights W;
-    load_weights(W, wpk, lane);
+    stage_weights(wl, bias, wpk, biasg);
+    const WaveWeights W{wl, lane};
     u32x4 *xs = xs_all[wave];
     float *ys = ys_all[wave];
     __syncthreads();
@@ -802,7 +812,7 @@ hipError_t closure_t(erf_ctx *cx, const void *rho, void *const R[5])
     a.fallbacks = m.fallbacks;
     const Dims &d = cx->d;
     timing_start(cx, K_MLP);
-    hipLaunchKernelGGL(k_mlp_closure<T>, dim3(grid_for(d.n, kClosureBlock, 1024)), dim3(kClosureBlock), 0,
+    hipLaunchKernelGGL(k_mlp_closure<T>, dim3(grid_for(d.n, kClosureBlock, 512)), dim3(kClosureBlock), 0,
                        cx->stream, a);
     timing_stop(cx, K_MLP);
     DivArgs<T> v{};

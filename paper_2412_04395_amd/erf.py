@@ -84,6 +84,9 @@ def load(path: str = LIB_PATH):
         if _lib is None:
             if not os.path.exists(path):
                 raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+            # torch first: the library must bind to the HIP runtime torch
+            # allocates with, not to a second copy of it
+            import torch  # noqa: F401
             L = C.CDLL(path)
             L.erf_base_state_host.argtypes = [C.c_int32, _DP, _DP, C.c_double, C.c_double, _DP, _DP, _DP]
             L.erf_create.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_void_p, C.POINTER(C.c_void_p)]
