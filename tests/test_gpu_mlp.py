@@ -362,3 +362,26 @@ def test_training_decreases_loss_like_oracle():
     assert abs(lg[0] - lo[0]) <= 1e-5 * lo[0]
     assert lg[-1] < 0.5 * lg[0]
     assert abs(lg[-1] - lo[-1]) <= 0.05 * lo[-1]
+
+
+def test_trained_weights_run_stable():
+    """The stored weights (paper_2412_04395_amd/data, trained by
+    closure_training.py) keep a 40 m boundary-layer run finite, with most cells
+    on the network rather than the fallback."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2412_04395_amd",
+                        "data", "closure_les40m.npz")
+    z = np.load(path, allow_pickle=False)
+    assert z["params"].shape == (NP,) and z["norm"].shape == (38,)
+    cfg = W.les_mlp(nx=64, ny=64, nz=32, dz=W.uniform_dz(32, 40.0))
+    s, th0 = _solver(cfg)
+    s.mlp_set_weights(z["params"], z["norm"])
+    b = s.base
+    S = s.from_full(W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"]))
+    steps = 60
+    for _ in range(steps):
+        s.rk3_step(S)
+    d = s.diagnostics(S)
+    frac = s.mlp_fallback_count() / (3 * steps * cfg.cells)
+    _say(f"trained closure, {steps} steps: max w {d['max_w']:.3f} m/s, fallback fraction {frac:.3f}")
+    assert d["nonfinite"] == 0 and frac < 0.5
