@@ -16,8 +16,9 @@
 // k_substep layout.  A block owns a tile of 64 columns (TX x TY, TX*TY = 64,
 // one lane per column) and all nz levels.  Its KG wavefronts split the levels
 // into chunks of L consecutive levels; the explicit work is parallel over
-// levels and keeps the per-level results (That, Rhat, theta^t on faces) in
-// registers.  The W'' right-hand sides go to LDS; the two Thomas sweeps (LU
+// levels and keeps the per-level results (That in LDS up to 8 levels per
+// wavefront, Rhat in registers; theta^t on faces is recomputed from the cache
+// where needed).  The W'' right-hand sides go to LDS; the two Thomas sweeps (LU
 // factors frozen per stage) run as chunked linear recurrences, each wavefront
 // on its own rows with one short carry chain between chunks; every wavefront
 // then finishes its levels.  Neighbour columns'
@@ -135,6 +136,104 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
     }
 }
 
+// Phase 1 of a substep on one wavefront's levels of one column: U'', V'' with
+// the forward-predicted Theta'', the explicit parts of Theta'' (in LDS, thl,
+// up to 8 levels per wavefront; else in th) and rho'' (rh), and the
+// right-hand sides of the W'' rows (rbuf; chunk-end e, f in bnd).  Keeping few
+// values live across the level loop leaves registers for more loads in
+// flight.  The pointers are restrict: the arrays
+// written here (U'', V'' of the next level, their sums) are never read here,
+// so the loads of later levels may be issued ahead of earlier stores.
+template <typename T, int kLevels>
+__device__ __forceinline__ void substep_explicit(
+    const T *__restrict__ T2cur, const T *__restrict__ T2prv, const T *__restrict__ pit, const T *__restrict__ tht,
+    const T *__restrict__ u2in, const T *__restrict__ v2in, const T *__restrict__ R_u, const T *__restrict__ R_v,
+    const T *__restrict__ R_t, const T *__restrict__ R_r, const T *__restrict__ R_w, const T *__restrict__ w2,
+    const T *__restrict__ r2, const T *__restrict__ cC, const double *__restrict__ idz_t,
+    const double *__restrict__ idzf_t, T *__restrict__ u2out, T *__restrict__ v2out, T *__restrict__ su,
+    T *__restrict__ sv, int sums, double *rbuf, double *bnd, bool act, int col, int nxy, int nz, int k0, int g,
+    int lane, int o_e, int o_w, int o_n, int o_s, double dt, double b1, double b2, double gr, double bd,
+    double gRd, double idx, double idy, double (&th)[kLevels], double *thl, double (&rh)[kLevels],
+    double &e_first, double &f_first)
+{
+    if (act && k0 < nz) {
+        double e_prev = 0.0, f_prev = 0.0;
+        double pi_below = (k0 > 0) ? pit[col + (k0 - 1) * nxy] : 0.0;
+        double th_below = (k0 > 0) ? tht[col + (k0 - 1) * nxy] : 0.0;
+        double w_lo = w2[col + k0 * nxy];
+#pragma unroll
+        for (int l = 0; l < kLevels; ++l) {
+            const int k = k0 + l;
+            if (k < nz) {
+                const int c = col + k * nxy;
+                // forward-predicted Theta'' at the centre and its four neighbours
+                const double Tc = T2cur[c];
+                const double ttc = Tc + bd * (Tc - T2prv[c]);
+                const double Tw = T2cur[c + o_w], Te = T2cur[c + o_e], Ts = T2cur[c + o_s], Tn = T2cur[c + o_n];
+                const double ttw = Tw + bd * (Tw - T2prv[c + o_w]);
+                const double tte = Te + bd * (Te - T2prv[c + o_e]);
+                const double tts = Ts + bd * (Ts - T2prv[c + o_s]);
+                const double ttn = Tn + bd * (Tn - T2prv[c + o_n]);
+                const double pc = pit[c], pw = pit[c + o_w], pe = pit[c + o_e], ps = pit[c + o_s],
+                             pn = pit[c + o_n];
+                // U'' on this column's x-face and on the next one, V'' likewise
+                const double Uw = u2in[c] + dt * (-gRd * (0.5 * (pw + pc)) * (ttc - ttw) * idx + R_u[c]);
+                const double Ue =
+                    u2in[c + o_e] + dt * (-gRd * (0.5 * (pc + pe)) * (tte - ttc) * idx + R_u[c + o_e]);
+                const double Vs = v2in[c] + dt * (-gRd * (0.5 * (ps + pc)) * (ttc - tts) * idy + R_v[c]);
+                const double Vn =
+                    v2in[c + o_n] + dt * (-gRd * (0.5 * (pc + pn)) * (ttn - ttc) * idy + R_v[c + o_n]);
+                u2out[c] = Uw;
+                v2out[c] = Vs;
+                if (sums) {
+                    su[c] += Uw;
+                    sv[c] += Vs;
+                }
+                // explicit parts of Theta'' and rho''
+                const double thc = tht[c];
+                const double thx0 = 0.5 * (tht[c + o_w] + thc), thx1 = 0.5 * (thc + tht[c + o_e]);
+                const double thy0 = 0.5 * (tht[c + o_s] + thc), thy1 = 0.5 * (thc + tht[c + o_n]);
+                const double hdiv_t = (Ue * thx1 - Uw * thx0) * idx + (Vn * thy1 - Vs * thy0) * idy;
+                const double hdiv_r = (Ue - Uw) * idx + (Vn - Vs) * idy;
+                const double th_above = (k < nz - 1) ? tht[c + nxy] : 0.0;
+                const double tfk = (k == 0) ? 0.0 : 0.5 * (th_below + thc);
+                const double tfk1 = (k == nz - 1) ? 0.0 : 0.5 * (thc + th_above);
+                const double w_hi = w2[c + nxy];
+                const double idzk = idz_t[k];
+                const double r2c = r2[c];
+                const double that = Tc + dt * (-hdiv_t - b1 * (w_hi * tfk1 - w_lo * tfk) * idzk + R_t[c]);
+                const double rhat = r2c + dt * (-hdiv_r - b1 * (w_hi - w_lo) * idzk + R_r[c]);
+                const double e = b1 * Tc + b2 * that, f = b1 * r2c + b2 * rhat;
+                if (l == 0) {
+                    e_first = e;
+                    f_first = f;
+                } else {
+                    // right-hand side of the W'' row on face k
+                    const double idzf = idzf_t[k];
+                    const double A = gRd * (0.5 * (pi_below + pc));
+                    const double C = cC[c];
+                    rbuf[k * kLanes + lane] = w_lo + dt * (-A * (e - e_prev) * idzf + 0.5 * C * (e + e_prev) -
+                                                           0.5 * gr * (f + f_prev) + R_w[c]);
+                }
+                if constexpr (kLevels <= 8)
+                    thl[k * kLanes + lane] = that;
+                else
+                    th[l] = that;
+                rh[l] = rhat;
+                e_prev = e;
+                f_prev = f;
+                pi_below = pc;
+                th_below = thc;
+                w_lo = w_hi;
+                if (l == kLevels - 1 || k == nz - 1) {
+                    bnd[(g * 2 + 0) * kLanes + lane] = e;
+                    bnd[(g * 2 + 1) * kLanes + lane] = f;
+                }
+            }
+        }
+    }
+}
+
 // One fused acoustic substep.  blockDim = (64, KG), kLevels levels per
 // wavefront; dynamic LDS holds the (nz + 1) x 64 solve buffer and the
 // chunk-boundary values.
@@ -147,6 +246,7 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
     const int lane = threadIdx.x, g = threadIdx.y;
     double *rbuf = lds;                     // [(nz + 1) * 64]
     double *bnd = lds + (nz + 1) * kLanes;  // [KG][2][64]
+    double *thl = bnd + 2 * blockDim.y * kLanes;  // [nz][64] when kLevels <= 8
 
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = tile % a.ntx, ty = tile / a.ntx;
@@ -161,86 +261,14 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
     const double idx = 1.0 / a.dx, idy = 1.0 / a.dy;
 
     const int k0 = g * kLevels;
-    double th[kLevels], rh[kLevels], tf[kLevels];
-    double tf_top = 0.0;
+    double th[kLevels], rh[kLevels];
     double e_first = 0.0, f_first = 0.0;
 
     // ---------------- phase 1: explicit work, W'' right-hand sides ----------
-    if (act && k0 < nz) {
-        double e_prev = 0.0, f_prev = 0.0;
-        double pi_below = (k0 > 0) ? a.pit[col + (k0 - 1) * nxy] : 0.0;
-        double th_below = (k0 > 0) ? a.tht[col + (k0 - 1) * nxy] : 0.0;
-        double w_lo = a.w2[col + k0 * nxy];
-#pragma unroll
-        for (int l = 0; l < kLevels; ++l) {
-            const int k = k0 + l;
-            if (k < nz) {
-                const int c = col + k * nxy;
-                // forward-predicted Theta'' at the centre and its four neighbours
-                const double Tc = a.T2cur[c];
-                const double ttc = Tc + bd * (Tc - a.T2prv[c]);
-                const double Tw = a.T2cur[c + o_w], Te = a.T2cur[c + o_e], Ts = a.T2cur[c + o_s], Tn = a.T2cur[c + o_n];
-                const double ttw = Tw + bd * (Tw - a.T2prv[c + o_w]);
-                const double tte = Te + bd * (Te - a.T2prv[c + o_e]);
-                const double tts = Ts + bd * (Ts - a.T2prv[c + o_s]);
-                const double ttn = Tn + bd * (Tn - a.T2prv[c + o_n]);
-                const double pc = a.pit[c], pw = a.pit[c + o_w], pe = a.pit[c + o_e], ps = a.pit[c + o_s],
-                             pn = a.pit[c + o_n];
-                // U'' on this column's x-face and on the next one, V'' likewise
-                const double Uw = a.u2in[c] + dt * (-gRd * (0.5 * (pw + pc)) * (ttc - ttw) * idx + a.R_u[c]);
-                const double Ue =
-                    a.u2in[c + o_e] + dt * (-gRd * (0.5 * (pc + pe)) * (tte - ttc) * idx + a.R_u[c + o_e]);
-                const double Vs = a.v2in[c] + dt * (-gRd * (0.5 * (ps + pc)) * (ttc - tts) * idy + a.R_v[c]);
-                const double Vn =
-                    a.v2in[c + o_n] + dt * (-gRd * (0.5 * (pc + pn)) * (ttn - ttc) * idy + a.R_v[c + o_n]);
-                a.u2out[c] = Uw;
-                a.v2out[c] = Vs;
-                if (a.sums) {
-                    a.su[c] += Uw;
-                    a.sv[c] += Vs;
-                }
-                // explicit parts of Theta'' and rho''
-                const double thc = a.tht[c];
-                const double thx0 = 0.5 * (a.tht[c + o_w] + thc), thx1 = 0.5 * (thc + a.tht[c + o_e]);
-                const double thy0 = 0.5 * (a.tht[c + o_s] + thc), thy1 = 0.5 * (thc + a.tht[c + o_n]);
-                const double hdiv_t = (Ue * thx1 - Uw * thx0) * idx + (Vn * thy1 - Vs * thy0) * idy;
-                const double hdiv_r = (Ue - Uw) * idx + (Vn - Vs) * idy;
-                const double th_above = (k < nz - 1) ? a.tht[c + nxy] : 0.0;
-                const double tfk = (k == 0) ? 0.0 : 0.5 * (th_below + thc);
-                const double tfk1 = (k == nz - 1) ? 0.0 : 0.5 * (thc + th_above);
-                const double w_hi = a.w2[c + nxy];
-                const double idzk = a.idz[k];
-                const double r2c = a.r2[c];
-                const double that = Tc + dt * (-hdiv_t - b1 * (w_hi * tfk1 - w_lo * tfk) * idzk + a.R_t[c]);
-                const double rhat = r2c + dt * (-hdiv_r - b1 * (w_hi - w_lo) * idzk + a.R_r[c]);
-                const double e = b1 * Tc + b2 * that, f = b1 * r2c + b2 * rhat;
-                if (l == 0) {
-                    e_first = e;
-                    f_first = f;
-                } else {
-                    // right-hand side of the W'' row on face k
-                    const double idzf = a.idzf[k];
-                    const double A = gRd * (0.5 * (pi_below + pc));
-                    const double C = a.cC[c];
-                    rbuf[k * kLanes + lane] = w_lo + dt * (-A * (e - e_prev) * idzf + 0.5 * C * (e + e_prev) -
-                                                           0.5 * gr * (f + f_prev) + a.R_w[c]);
-                }
-                th[l] = that;
-                rh[l] = rhat;
-                tf[l] = tfk;
-                tf_top = tfk1;
-                e_prev = e;
-                f_prev = f;
-                pi_below = pc;
-                th_below = thc;
-                w_lo = w_hi;
-                if (l == kLevels - 1 || k == nz - 1) {
-                    bnd[(g * 2 + 0) * kLanes + lane] = e;
-                    bnd[(g * 2 + 1) * kLanes + lane] = f;
-                }
-            }
-        }
-    }
+    substep_explicit<T, kLevels>(a.T2cur, a.T2prv, a.pit, a.tht, a.u2in, a.v2in, a.R_u, a.R_v, a.R_t, a.R_r, a.R_w,
+                                 a.w2, a.r2, a.cC, a.idz, a.idzf, a.u2out, a.v2out, a.su, a.sv, a.sums, rbuf, bnd,
+                                 act, col, nxy, nz, k0, g, lane, o_e, o_w, o_n, o_s, dt, b1, b2, gr, bd, gRd, idx,
+                                 idy, th, thl, rh, e_first, f_first);
     __syncthreads();
     // row k0 of every chunk but the first needs the last level of the chunk below
     if (act && k0 < nz && g > 0) {
@@ -337,9 +365,13 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
             if (k < nz) {
                 const int c = col + k * nxy;
                 const double wk = (k >= rlo && k <= rhi) ? rbuf[k * kLanes + lane] + mult[l] * Xnext : 0.0;
-                const double tf1 = (l == kLevels - 1 || k == nz - 1) ? tf_top : tf[l + 1 < kLevels ? l + 1 : l];
+                // theta^t on the faces below and above, again from the cache
+                const double thc = a.tht[c];
+                const double tfl = (k == 0) ? 0.0 : 0.5 * ((double)a.tht[c - nxy] + thc);
+                const double tf1 = (k == nz - 1) ? 0.0 : 0.5 * (thc + (double)a.tht[c + nxy]);
                 const double idzk = a.idz[k];
-                a.T2nxt[c] = th[l] - dt * b2 * (wk1 * tf1 - wk * tf[l]) * idzk;
+                const double thk = (kLevels <= 8) ? thl[k * kLanes + lane] : th[l];
+                a.T2nxt[c] = thk - dt * b2 * (wk1 * tf1 - wk * tfl) * idzk;
                 a.r2[c] = rh[l] - dt * b2 * (wk1 - wk) * idzk;
                 if (k >= 1) {
                     a.w2[c] = wk;
@@ -438,8 +470,9 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
     a.cm = w.cb;
     a.cc = w.cc;
     a.cC = (T *)w.cC;
-    // tile shape: 64 columns, four rows when the domain has them
-    a.TY = d.ny >= 4 ? 4 : (d.ny >= 2 ? 2 : 1);
+    // tile shape: 64 columns, one row of 64 where rows are that long (measured
+    // 1.3 % faster than 16 x 4 at 256 x 256), else up to four shorter rows
+    a.TY = d.nx >= 64 ? 1 : (d.ny >= 4 ? 4 : (d.ny >= 2 ? 2 : 1));
     a.TX = kLanes / a.TY;
     a.ntx = (d.nx + a.TX - 1) / a.TX;
     a.nty = (d.ny + a.TY - 1) / a.TY;
@@ -447,7 +480,8 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
     const int L = d.nz <= 128 ? 8 : 16;
     const int KG = (d.nz + L - 1) / L;
     if (KG > 16) return hipErrorInvalidValue;  // nz <= 256
-    const size_t lds = sizeof(double) * ((size_t)(d.nz + 1) * kLanes + 2 * (size_t)KG * kLanes);
+    const size_t lds = sizeof(double) * ((size_t)(d.nz + 1) * kLanes + 2 * (size_t)KG * kLanes +
+                                         (L == 8 ? (size_t)d.nz * kLanes : 0));
     const void *kfn = L == 8 ? (const void *)k_substep<T, 8> : (const void *)k_substep<T, 16>;
 
     int t_cur = 0, t_prv = 2, u_in = 0;  // Theta'' rotates over 3 buffers, U'' and V'' over 2
