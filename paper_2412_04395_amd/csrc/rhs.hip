@@ -213,26 +213,27 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
     const int c = cidx(d, i, j, k);
     // neighbour offset tables: x and y periodic; z reflected (even for centre
     // and horizontal-face fields, odd with a sign for z-face fields)
-    int ox[7], oy[7], ozc[7], ozw[7];
-    double szw[7], thz0[7];  // thz0: theta0 on the reflected levels (FP32 storage)
-#pragma unroll
-    for (int t = 0; t < 7; ++t) {
-        ox[t] = wrap_idx(i + t - 3, d.nx) - i;
-        oy[t] = (wrap_idx(j + t - 3, d.ny) - j) * d.nx;
-        const int kr = refl_centre(k + t - 3, nz);
-        ozc[t] = (kr - k) * P;
-        thz0[t] = kPert<T> ? a.theta0[kr] : 0.0;
+    // (computed where used: cheap integer work instead of 42 registers)
+    auto ox = [&](int t) { return wrap_idx(i + t - 3, d.nx) - i; };
+    auto oy = [&](int t) { return (wrap_idx(j + t - 3, d.ny) - j) * d.nx; };
+    auto ozc = [&](int t) { return (refl_centre(k + t - 3, nz) - k) * P; };
+    auto thz0 = [&](int t) { return kPert<T> ? a.theta0[refl_centre(k + t - 3, nz)] : 0.0; };
+    auto ozw = [&](int t) {
         double sg;
-        ozw[t] = (refl_face(k + t - 3, nz, sg) - k) * P;
-        szw[t] = sg;
-    }
+        return (refl_face(k + t - 3, nz, sg) - k) * P;
+    };
+    auto szw = [&](int t) {
+        double sg;
+        refl_face(k + t - 3, nz, sg);
+        return sg;
+    };
     const double idz = a.idz[k];
     const int oh = a.oh, ov = a.ov;
     double q[7];
 
     // ---------------- cell: continuity and rho*theta ----------------
-    const double U0 = a.ru[c], U1 = a.ru[c + ox[4]];
-    const double V0 = a.rv[c], V1 = a.rv[c + oy[4]];
+    const double U0 = a.ru[c], U1 = a.ru[c + ox(4)];
+    const double V0 = a.rv[c], V1 = a.rv[c + oy(4)];
     const double W0 = a.rw[c], W1 = a.rw[c + P];
     const double r0k = a.rho0[k], rc = full_of(a.rho, c, r0k);
     const double th0k = kPert<T> ? a.theta0[k] : 0.0;
@@ -240,28 +241,28 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
         a.Rr[c] = -((U1 - U0) * a.idx + (V1 - V0) * a.idy + (W1 - W0) * idz);
         const T *th = a.th;
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = th0k + th[c + ox[t]];
+        for (int t = 0; t < 7; ++t) q[t] = th0k + th[c + ox(t)];
         const double fx0 = U0 * interp<OH>(oh, q, 0, sign_of(U0)), fx1 = U1 * interp<OH>(oh, q, 1, sign_of(U1));
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = th0k + th[c + oy[t]];
+        for (int t = 0; t < 7; ++t) q[t] = th0k + th[c + oy(t)];
         const double fy0 = V0 * interp<OH>(oh, q, 0, sign_of(V0)), fy1 = V1 * interp<OH>(oh, q, 1, sign_of(V1));
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = thz0[t] + th[c + ozc[t]];
+        for (int t = 0; t < 7; ++t) q[t] = thz0(t) + th[c + ozc(t)];
         const double fz0 = (k == 0) ? 0.0 : W0 * interp<OV>(ov, q, 0, sign_of(W0));
         const double fz1 = (k == nz - 1) ? 0.0 : W1 * interp<OV>(ov, q, 1, sign_of(W1));
         double r = -((fx1 - fx0) * a.idx + (fy1 - fy0) * a.idy + (fz1 - fz0) * idz);
         if (a.visc) {
             const T *kp = a.kap;
             const double kc = kp[c], thc = th0k + th[c];
-            const double hx0 = -0.5 * (kp[c + ox[2]] + kc) * (thc - (th0k + th[c + ox[2]])) * a.idx;
-            const double hx1 = -0.5 * (kc + kp[c + ox[4]]) * ((th0k + th[c + ox[4]]) - thc) * a.idx;
-            const double hy0 = -0.5 * (kp[c + oy[2]] + kc) * (thc - (th0k + th[c + oy[2]])) * a.idy;
-            const double hy1 = -0.5 * (kc + kp[c + oy[4]]) * ((th0k + th[c + oy[4]]) - thc) * a.idy;
+            const double hx0 = -0.5 * (kp[c + ox(2)] + kc) * (thc - (th0k + th[c + ox(2)])) * a.idx;
+            const double hx1 = -0.5 * (kc + kp[c + ox(4)]) * ((th0k + th[c + ox(4)]) - thc) * a.idx;
+            const double hy0 = -0.5 * (kp[c + oy(2)] + kc) * (thc - (th0k + th[c + oy(2)])) * a.idy;
+            const double hy1 = -0.5 * (kc + kp[c + oy(4)]) * ((th0k + th[c + oy(4)]) - thc) * a.idy;
             double hz0 = 0.0, hz1 = 0.0;
             if (k > 0)
-                hz0 = -0.5 * (kp[c - P] + kc) * (thc - (thz0[2] + th[c - P])) * a.idzf[k];
+                hz0 = -0.5 * (kp[c - P] + kc) * (thc - (thz0(2) + th[c - P])) * a.idzf[k];
             if (k < nz - 1)
-                hz1 = -0.5 * (kc + kp[c + P]) * ((thz0[4] + th[c + P]) - thc) * a.idzf[k + 1];
+                hz1 = -0.5 * (kc + kp[c + P]) * ((thz0(4) + th[c + P]) - thc) * a.idzf[k + 1];
             r -= (hx1 - hx0) * a.idx + (hy1 - hy0) * a.idy + (hz1 - hz0) * idz;
         }
         if (k == 0 && a.Qs != 0.0) r += rc * a.Qs * idz;
@@ -270,70 +271,70 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
 
     // ---------------- x-momentum on x-face (i, j, k) ----------------
     {
-        const double Um = a.ru[c + ox[2]];
+        const double Um = a.ru[c + ox(2)];
         const double ar = 0.5 * (U0 + U1), al = 0.5 * (Um + U0);
         const T *u = a.u;
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = u[c + ox[t]];
+        for (int t = 0; t < 7; ++t) q[t] = u[c + ox(t)];
         const double fxx_r = ar * interp<OH>(oh, q, 1, sign_of(ar)), fxx_l = al * interp<OH>(oh, q, 0, sign_of(al));
-        const double Vw = a.rv[c + ox[2]], Vwn = a.rv[c + ox[2] + oy[4]];
+        const double Vw = a.rv[c + ox(2)], Vwn = a.rv[c + ox(2) + oy(4)];
         const double b0 = 0.5 * (Vw + V0), b1 = 0.5 * (Vwn + V1);
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = u[c + oy[t]];
+        for (int t = 0; t < 7; ++t) q[t] = u[c + oy(t)];
         const double fxy0 = b0 * interp<OH>(oh, q, 0, sign_of(b0)), fxy1 = b1 * interp<OH>(oh, q, 1, sign_of(b1));
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = u[c + ozc[t]];
+        for (int t = 0; t < 7; ++t) q[t] = u[c + ozc(t)];
         double fxz0 = 0.0, fxz1 = 0.0;
         if (k > 0) {
-            const double e0 = 0.5 * (a.rw[c + ox[2]] + W0);
+            const double e0 = 0.5 * (a.rw[c + ox(2)] + W0);
             fxz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0));
         }
         if (k < nz - 1) {
-            const double e1 = 0.5 * (a.rw[c + ox[2] + P] + W1);
+            const double e1 = 0.5 * (a.rw[c + ox(2) + P] + W1);
             fxz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1));
         }
         const double adv = (fxx_r - fxx_l) * a.idx + (fxy1 - fxy0) * a.idy + (fxz1 - fxz0) * idz;
-        const double pgf = (a.pp[c] - a.pp[c + ox[2]]) * a.idx;
-        const double rho_f = 0.5 * (full_of(a.rho, c + ox[2], r0k) + rc);
+        const double pgf = (a.pp[c] - a.pp[c + ox(2)]) * a.idx;
+        const double rho_f = 0.5 * (full_of(a.rho, c + ox(2), r0k) + rc);
         const double vbar = 0.25 * (Vw + V0 + Vwn + V1);
         double r = -adv - pgf + a.f * (vbar - rho_f * a.Vg);
         if (a.visc)
-            r -= (a.t11[c] - a.t11[c + ox[2]]) * a.idx + (a.t12[c + oy[4]] - a.t12[c]) * a.idy +
+            r -= (a.t11[c] - a.t11[c + ox(2)]) * a.idx + (a.t12[c + oy(4)] - a.t12[c]) * a.idy +
                  (a.t13[c + P] - a.t13[c]) * idz;
         a.Ru[c] = r;
     }
 
     // ---------------- y-momentum on y-face (i, j, k) ----------------
     {
-        const double Vs = a.rv[c + oy[2]];
+        const double Vs = a.rv[c + oy(2)];
         const double br = 0.5 * (V0 + V1), bl = 0.5 * (Vs + V0);
         const T *v = a.v;
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = v[c + oy[t]];
+        for (int t = 0; t < 7; ++t) q[t] = v[c + oy(t)];
         const double fyy_r = br * interp<OH>(oh, q, 1, sign_of(br)), fyy_l = bl * interp<OH>(oh, q, 0, sign_of(bl));
-        const double Us = a.ru[c + oy[2]], Use = a.ru[c + oy[2] + ox[4]];
+        const double Us = a.ru[c + oy(2)], Use = a.ru[c + oy(2) + ox(4)];
         const double a0 = 0.5 * (Us + U0), a1 = 0.5 * (Use + U1);
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = v[c + ox[t]];
+        for (int t = 0; t < 7; ++t) q[t] = v[c + ox(t)];
         const double fyx0 = a0 * interp<OH>(oh, q, 0, sign_of(a0)), fyx1 = a1 * interp<OH>(oh, q, 1, sign_of(a1));
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = v[c + ozc[t]];
+        for (int t = 0; t < 7; ++t) q[t] = v[c + ozc(t)];
         double fyz0 = 0.0, fyz1 = 0.0;
         if (k > 0) {
-            const double e0 = 0.5 * (a.rw[c + oy[2]] + W0);
+            const double e0 = 0.5 * (a.rw[c + oy(2)] + W0);
             fyz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0));
         }
         if (k < nz - 1) {
-            const double e1 = 0.5 * (a.rw[c + oy[2] + P] + W1);
+            const double e1 = 0.5 * (a.rw[c + oy(2) + P] + W1);
             fyz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1));
         }
         const double adv = (fyx1 - fyx0) * a.idx + (fyy_r - fyy_l) * a.idy + (fyz1 - fyz0) * idz;
-        const double pgf = (a.pp[c] - a.pp[c + oy[2]]) * a.idy;
-        const double rho_f = 0.5 * (full_of(a.rho, c + oy[2], r0k) + rc);
+        const double pgf = (a.pp[c] - a.pp[c + oy(2)]) * a.idy;
+        const double rho_f = 0.5 * (full_of(a.rho, c + oy(2), r0k) + rc);
         const double ubar = 0.25 * (Us + Use + U0 + U1);
         double r = -adv - pgf - a.f * (ubar - rho_f * a.Ug);
         if (a.visc)
-            r -= (a.t12[c + ox[4]] - a.t12[c]) * a.idx + (a.t22[c] - a.t22[c + oy[2]]) * a.idy +
+            r -= (a.t12[c + ox(4)] - a.t12[c]) * a.idx + (a.t22[c] - a.t22[c + oy(2)]) * a.idy +
                  (a.t23[c + P] - a.t23[c]) * idz;
         a.Rv[c] = r;
     }
@@ -345,18 +346,18 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
     } else {
         const int cm = c - P;
         const double idzf = a.idzf[k];
-        const double a0 = 0.5 * (a.ru[cm] + U0), a1 = 0.5 * (a.ru[cm + ox[4]] + U1);
+        const double a0 = 0.5 * (a.ru[cm] + U0), a1 = 0.5 * (a.ru[cm + ox(4)] + U1);
         const T *w = a.w;
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = w[c + ox[t]];
+        for (int t = 0; t < 7; ++t) q[t] = w[c + ox(t)];
         const double fzx0 = a0 * interp<OH>(oh, q, 0, sign_of(a0)), fzx1 = a1 * interp<OH>(oh, q, 1, sign_of(a1));
-        const double b0 = 0.5 * (a.rv[cm] + V0), b1 = 0.5 * (a.rv[cm + oy[4]] + V1);
+        const double b0 = 0.5 * (a.rv[cm] + V0), b1 = 0.5 * (a.rv[cm + oy(4)] + V1);
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = w[c + oy[t]];
+        for (int t = 0; t < 7; ++t) q[t] = w[c + oy(t)];
         const double fzy0 = b0 * interp<OH>(oh, q, 0, sign_of(b0)), fzy1 = b1 * interp<OH>(oh, q, 1, sign_of(b1));
         const double eu = 0.5 * (W0 + W1), ed = 0.5 * (a.rw[cm] + W0);
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = szw[t] * w[c + ozw[t]];
+        for (int t = 0; t < 7; ++t) q[t] = szw(t) * w[c + ozw(t)];
         const double fzz_u = eu * interp<OV>(ov, q, 1, sign_of(eu)), fzz_d = ed * interp<OV>(ov, q, 0, sign_of(ed));
         const double adv = (fzx1 - fzx0) * a.idx + (fzy1 - fzy0) * a.idy + (fzz_u - fzz_d) * idzf;
         const double pgf = (a.pp[c] - a.pp[cm]) * idzf;
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
         const double buoy = -a.g * 0.5 * (pert_of(a.rho, c, r0k) + pert_of(a.rho, cm, a.rho0[k - 1]));
         double r = -adv - pgf + buoy;
         if (a.visc)
-            r -= (a.t13[c + ox[4]] - a.t13[c]) * a.idx + (a.t23[c + oy[4]] - a.t23[c]) * a.idy +
+            r -= (a.t13[c + ox(4)] - a.t13[c]) * a.idx + (a.t23[c + oy(4)] - a.t23[c]) * a.idy +
                  (a.t33[c] - a.t33[cm]) * idzf;
         a.Rw[c] = r;
     }
