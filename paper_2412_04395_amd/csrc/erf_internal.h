@@ -202,7 +202,7 @@ struct MlpState {
     void *wpk = nullptr;            // 22 operands x 64 lanes x 16 bytes
     float *bias = nullptr;          // b1, b2, b3, b4 padded to 16: 208
     double *norm = nullptr;         // mean_x[10], std_x[10], mean_y[9], std_y[9]
-    unsigned long long *fallbacks = nullptr;
+    unsigned long long *fallbacks = nullptr;  // per-workgroup running counts
     double *loss = nullptr;
     bool have_weights = false;
     int64_t step = 0;
@@ -292,6 +292,7 @@ hipError_t launch_scalar_advance(erf_ctx *c, const void *rqn, const void *rho_t,
 // mlp.hip
 hipError_t mlp_pack(erf_ctx *c);
 hipError_t launch_mlp_closure(erf_ctx *c, const void *rho, void *const R[5]);
+int closure_count_slots();
 hipError_t launch_mlp_forward(erf_ctx *c, const float *x, int64_t n, float *y);
 hipError_t launch_features(erf_ctx *c, double *feat);
 hipError_t launch_box_filter(erf_ctx *c, const void *const S[5], int r, double Cs, double Pr_t,

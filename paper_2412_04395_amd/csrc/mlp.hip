@@ -221,47 +221,57 @@ __device__ __forceinline__ double theta_full(const ClosureIn<T> &a, int c, int k
 // edge differences around the centre (zero on lid edges for du/dz, dv/dz,
 // dw/dx, dw/dy), dtheta/dz as the mean of the two face differences (zero
 // through the lids); also the centred horizontal theta gradients.
+// Branch-free, so that all ~40 loads can be in flight together: periodic
+// neighbours by selects, vertical neighbours clamped to the column; the lid
+// terms vanish because 2/(dz_{k-1} + dz_k) is stored as zero on both lids and w
+// is zero on the lid faces.
 template <typename T>
 __device__ void closure_inputs(const ClosureIn<T> &a, int i, int j, int k, double f[10], double &dthx, double &dthy)
 {
     const Dims &d = a.d;
-    const int nz = d.nz, P = d.nxy;
-    const int im = wrap_idx(i - 1, d.nx), ip = wrap_idx(i + 1, d.nx);
-    const int jm = wrap_idx(j - 1, d.ny), jp = wrap_idx(j + 1, d.ny);
-    const int c = cidx(d, i, j, k);
-    auto U = [&](int ii, int jj, int kk) { return (double)a.u[cidx(d, ii, jj, kk)]; };
-    auto V = [&](int ii, int jj, int kk) { return (double)a.v[cidx(d, ii, jj, kk)]; };
-    auto Wf = [&](int ii, int jj, int kk) { return (double)a.w[cidx(d, ii, jj, kk)]; };
-    f[0] = (U(ip, j, k) - U(i, j, k)) * a.idx;
-    f[4] = (V(i, jp, k) - V(i, j, k)) * a.idy;
-    f[8] = (Wf(i, j, k + 1) - Wf(i, j, k)) * a.idz[k];
-    // du/dy on the edges (x-face ii, y-face jj)
-    auto dudy = [&](int ii, int jj) { return (U(ii, jj, k) - U(ii, wrap_idx(jj - 1, d.ny), k)) * a.idy; };
-    auto dvdx = [&](int ii, int jj) { return (V(ii, jj, k) - V(wrap_idx(ii - 1, d.nx), jj, k)) * a.idx; };
-    f[1] = 0.25 * (dudy(i, j) + dudy(ip, j) + dudy(i, jp) + dudy(ip, jp));
-    f[3] = 0.25 * (dvdx(i, j) + dvdx(ip, j) + dvdx(i, jp) + dvdx(ip, jp));
-    auto dudz = [&](int ii, int kk) {
-        return (kk <= 0 || kk >= nz) ? 0.0 : (U(ii, j, kk) - U(ii, j, kk - 1)) * a.idzf[kk];
-    };
-    auto dvdz = [&](int jj, int kk) {
-        return (kk <= 0 || kk >= nz) ? 0.0 : (V(i, jj, kk) - V(i, jj, kk - 1)) * a.idzf[kk];
-    };
-    auto dwdx = [&](int ii, int kk) {
-        return (kk <= 0 || kk >= nz) ? 0.0 : (Wf(ii, j, kk) - Wf(wrap_idx(ii - 1, d.nx), j, kk)) * a.idx;
-    };
-    auto dwdy = [&](int jj, int kk) {
-        return (kk <= 0 || kk >= nz) ? 0.0 : (Wf(i, jj, kk) - Wf(i, wrap_idx(jj - 1, d.ny), kk)) * a.idy;
-    };
-    f[2] = 0.25 * (dudz(i, k) + dudz(ip, k) + dudz(i, k + 1) + dudz(ip, k + 1));
-    f[5] = 0.25 * (dvdz(j, k) + dvdz(jp, k) + dvdz(j, k + 1) + dvdz(jp, k + 1));
-    f[6] = 0.25 * (dwdx(i, k) + dwdx(ip, k) + dwdx(i, k + 1) + dwdx(ip, k + 1));
-    f[7] = 0.25 * (dwdy(j, k) + dwdy(jp, k) + dwdy(j, k + 1) + dwdy(jp, k + 1));
-    const double tc = theta_full(a, c, k);
-    const double gb = k == 0 ? 0.0 : (tc - theta_full(a, c - P, k - 1)) * a.idzf[k];
-    const double gt = k == nz - 1 ? 0.0 : (theta_full(a, c + P, k + 1) - tc) * a.idzf[k + 1];
-    f[9] = 0.5 * (gb + gt);
-    dthx = 0.5 * (theta_full(a, cidx(d, ip, j, k), k) - theta_full(a, cidx(d, im, j, k), k)) * a.idx;
-    dthy = 0.5 * (theta_full(a, cidx(d, i, jp, k), k) - theta_full(a, cidx(d, i, jm, k), k)) * a.idy;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.nxy;
+    const int im = i == 0 ? nx - 1 : i - 1, ip = i == nx - 1 ? 0 : i + 1;
+    const int rj = j * nx, rjm = (j == 0 ? ny - 1 : j - 1) * nx, rjp = (j == ny - 1 ? 0 : j + 1) * nx;
+    const int lk = k * P, lkm = (k > 0 ? k - 1 : 0) * P, lkp = (k < nz - 1 ? k + 1 : nz - 1) * P;
+    const int kp1 = k + 1;  // the face above
+    auto U = [&](int ii, int r, int l) { return (double)a.u[l + r + ii]; };
+    auto V = [&](int ii, int r, int l) { return (double)a.v[l + r + ii]; };
+    auto Wf = [&](int ii, int r, int l) { return (double)a.w[l + r + ii]; };
+    const double gz0 = a.idzf[k], gz1 = a.idzf[kp1];  // zero on the lids
+    const double th0k = kPert<T> ? a.theta0[k] : 0.0;
+    const double th0m = kPert<T> ? a.theta0[k > 0 ? k - 1 : 0] : 0.0;
+    const double th0p = kPert<T> ? a.theta0[k < nz - 1 ? k + 1 : nz - 1] : 0.0;
+    auto TH = [&](int ii, int r, int l, double t0) { return (double)a.th[l + r + ii] + t0; };
+    // u on the x-faces i, i+1 of rows j-1, j, j+1 and levels k-1, k, k+1
+    const double u_c = U(i, rj, lk), u_e = U(ip, rj, lk);
+    const double u_s = U(i, rjm, lk), u_se = U(ip, rjm, lk), u_n = U(i, rjp, lk), u_ne = U(ip, rjp, lk);
+    const double u_b = U(i, rj, lkm), u_be = U(ip, rj, lkm), u_t = U(i, rj, lkp), u_te = U(ip, rj, lkp);
+    // v on the y-faces j, j+1 of columns i-1, i, i+1 and levels k-1, k, k+1
+    const double v_c = V(i, rj, lk), v_n = V(i, rjp, lk);
+    const double v_w = V(im, rj, lk), v_e = V(ip, rj, lk), v_nw = V(im, rjp, lk), v_ne = V(ip, rjp, lk);
+    const double v_b = V(i, rj, lkm), v_bn = V(i, rjp, lkm), v_t = V(i, rj, lkp), v_tn = V(i, rjp, lkp);
+    // w on the z-faces k, k+1 of the column and its four neighbours
+    const int lk1 = kp1 * P;
+    const double w_c = Wf(i, rj, lk), w_u = Wf(i, rj, lk1);
+    const double w_w = Wf(im, rj, lk), w_e = Wf(ip, rj, lk), w_wu = Wf(im, rj, lk1), w_eu = Wf(ip, rj, lk1);
+    const double w_s = Wf(i, rjm, lk), w_n = Wf(i, rjp, lk), w_su = Wf(i, rjm, lk1), w_nu = Wf(i, rjp, lk1);
+    // theta at the centre, below, above and at the four horizontal neighbours
+    const double t_c = TH(i, rj, lk, th0k), t_b = TH(i, rj, lkm, th0m), t_t = TH(i, rj, lkp, th0p);
+    const double t_w = TH(im, rj, lk, th0k), t_e = TH(ip, rj, lk, th0k), t_s = TH(i, rjm, lk, th0k),
+                 t_n = TH(i, rjp, lk, th0k);
+
+    f[0] = (u_e - u_c) * a.idx;
+    f[4] = (v_n - v_c) * a.idy;
+    f[8] = (w_u - w_c) * a.idz[k];
+    f[1] = 0.25 * (((u_c - u_s) + (u_e - u_se)) + ((u_n - u_c) + (u_ne - u_e))) * a.idy;
+    f[3] = 0.25 * (((v_c - v_w) + (v_e - v_c)) + ((v_n - v_nw) + (v_ne - v_n))) * a.idx;
+    f[2] = 0.25 * (((u_c - u_b) * gz0 + (u_e - u_be) * gz0) + ((u_t - u_c) * gz1 + (u_te - u_e) * gz1));
+    f[5] = 0.25 * (((v_c - v_b) * gz0 + (v_n - v_bn) * gz0) + ((v_t - v_c) * gz1 + (v_tn - v_n) * gz1));
+    f[6] = 0.25 * (((w_c - w_w) + (w_e - w_c)) + ((w_u - w_wu) + (w_eu - w_u))) * a.idx;
+    f[7] = 0.25 * (((w_c - w_s) + (w_n - w_c)) + ((w_u - w_su) + (w_nu - w_u))) * a.idy;
+    f[9] = 0.5 * ((t_c - t_b) * gz0 + (t_t - t_c) * gz1);
+    dthx = 0.5 * (t_e - t_w) * a.idx;
+    dthy = 0.5 * (t_n - t_s) * a.idy;
 }
 
 // Smagorinsky stresses and heat fluxes at a centre from the closure inputs:
@@ -299,10 +309,11 @@ struct ClosureArgs {
     const u32x4 *wpk;
     const float *bias;
     T *out[9];
-    unsigned long long *fallbacks;
+    unsigned long long *fallbacks;  // one running count per workgroup slot
 };
 
 constexpr int kClosureBlock = 512;  // 8 wavefronts
+constexpr int kClosureMaxBlocks = 512;
 
 // One wave takes 64 consecutive cells at a time (a persistent loop over the
 // grid): inputs in FP64 into LDS as BF16, the network on four groups of 16,
@@ -325,6 +336,7 @@ __global__ __launch_bounds__(kClosureBlock, 4) void k_mlp_closure(ClosureArgs<T>
     const Dims &d = a.in.d;
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * kClosureBlock;
+    unsigned int nfb = 0;  // fallback cells of this wavefront
     for (int64_t base = (int64_t)blockIdx.x * kClosureBlock + wave * 64; base < d.n; base += stride) {
         const int c = (int)base + lane;
         const bool valid = c < d.n;
@@ -375,10 +387,19 @@ __global__ __launch_bounds__(kClosureBlock, 4) void k_mlp_closure(ClosureArgs<T>
 #pragma unroll
             for (int o = 0; o < 9; ++o) a.out[o][c] = (T)(r * t[o]);
         }
-        const unsigned long long m = __ballot(fb);
-        if (lane == 0 && m) atomicAdd(a.fallbacks, (unsigned long long)__popcll(m));
+        nfb += (unsigned int)__popcll(__ballot(fb));
         // the next chunk rewrites this wave's rows only after it read them
         wave_sync();
+    }
+    // the block's count goes to its own slot: no atomics (a single counter
+    // updated by every wavefront costs more than the network itself)
+    __shared__ unsigned int wcount[kClosureBlock / 64];
+    if (lane == 0) wcount[wave] = nfb;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long sum = 0;
+        for (int w = 0; w < kClosureBlock / 64; ++w) sum += wcount[w];
+        a.fallbacks[blockIdx.x] += sum;
     }
 }
 
@@ -812,8 +833,8 @@ hipError_t closure_t(erf_ctx *cx, const void *rho, void *const R[5])
     a.fallbacks = m.fallbacks;
     const Dims &d = cx->d;
     timing_start(cx, K_MLP);
-    hipLaunchKernelGGL(k_mlp_closure<T>, dim3(grid_for(d.n, kClosureBlock, 512)), dim3(kClosureBlock), 0,
-                       cx->stream, a);
+    hipLaunchKernelGGL(k_mlp_closure<T>, dim3(grid_for(d.n, kClosureBlock, kClosureMaxBlocks)),
+                       dim3(kClosureBlock), 0, cx->stream, a);
     timing_stop(cx, K_MLP);
     DivArgs<T> v{};
     v.d = d;
@@ -915,6 +936,8 @@ hipError_t launch_box_filter(erf_ctx *cx, const void *const S[5], int r, double 
     if (cx->prm.precision == ERF_FP32_MIXED) return box_filter_t<float>(cx, S, r, Cs, Pr_t, C, targets);
     return box_filter_t<double>(cx, S, r, Cs, Pr_t, C, targets);
 }
+
+int closure_count_slots() { return kClosureMaxBlocks; }
 
 size_t stat_partials(int64_t n) { return (size_t)((n + kStatRows - 1) / kStatRows) * 16; }
 

@@ -2,6 +2,7 @@
 // closure state allocation, weights, training and data-preparation calls.
 #include <cstdio>
 #include <cstring>
+#include <vector>
 
 #include "../../include/erf_mlp.h"
 #include "erf_internal.h"
@@ -40,7 +41,7 @@ erf_status ensure_state(erf_ctx *c)
     if (m.alloc) return ERF_OK;
     const size_t P = kMlpParams * sizeof(float);
     const size_t sizes[] = {P, P, P, P, 22 * 64 * 16, 208 * sizeof(float), kMlpNorm * sizeof(double),
-                            sizeof(unsigned long long), sizeof(double)};
+                            closure_count_slots() * sizeof(unsigned long long), sizeof(double)};
     size_t total = 0;
     for (size_t s : sizes) total += al(s);
     hipError_t e = hipMalloc(&m.alloc, total);
@@ -243,11 +244,14 @@ erf_status erf_mlp_fallback_count(erf_ctx *c, int64_t *count)
         *count = 0;
         return ERF_OK;
     }
-    unsigned long long v = 0;
+    std::vector<unsigned long long> v(closure_count_slots());
     hipError_t e = hipStreamSynchronize(c->stream);
-    if (e == hipSuccess) e = hipMemcpy(&v, c->mlp.fallbacks, sizeof v, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(v.data(), c->mlp.fallbacks, v.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(c, e, "reading the fallback count");
-    *count = (int64_t)v;
+    unsigned long long sum = 0;
+    for (unsigned long long x : v) sum += x;
+    *count = (int64_t)sum;
     return ERF_OK;
 }
 

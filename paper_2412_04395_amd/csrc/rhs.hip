@@ -55,15 +55,24 @@ __global__ __launch_bounds__(256) void k_prep(RhsArgs<T> a)
     const TileIdx t = tile_cell(a.ntx, a.nty);
     const int i = t.i, j = t.j, k = t.k;
     if (i >= d.nx || j >= d.ny) return;
-    int c = cidx(d, i, j, k);
-    const double r0 = a.rho0[k], T0 = a.Theta0[k];
-    const double r = full_of(a.rho, c, r0), Tf = full_of(a.rt, c, T0);
-    a.th[c] = kPert<T> ? (T)(Tf / r - a.theta0[k]) : (T)(Tf / r);
+    const int c = cidx(d, i, j, k);
+    // every load first (neighbour indices clamped, so all are valid), then the stores
+    const int cw = cidx(d, i == 0 ? d.nx - 1 : i - 1, j, k), cs = cidx(d, i, j == 0 ? d.ny - 1 : j - 1, k);
+    const int kb = k > 0 ? k - 1 : 0, cb = c - (k - kb) * d.nxy;
+    const double r0 = a.rho0[k], T0 = a.Theta0[k], r0b = a.rho0[kb];
+    const double r = full_of(a.rho, c, r0), rw_ = full_of(a.rho, cw, r0), rs = full_of(a.rho, cs, r0);
+    const double rb = full_of(a.rho, cb, r0b);
+    const double Tf = full_of(a.rt, c, T0), Tp = pert_of(a.rt, c, T0);
+    const double U = a.ru[c], V = a.rv[c], Wc = a.rw[c];
+    const double th = Tf / r;
     // p' = p0 ((Theta/Theta0)^gamma - 1) without cancellation (EOS, Sec. 2.1)
-    a.pp[c] = a.p0[k] * expm1(kGamma * log1p(pert_of(a.rt, c, T0) / T0));
-    a.u[c] = a.ru[c] / (0.5 * (full_of(a.rho, cidx(d, wrap_idx(i - 1, d.nx), j, k), r0) + r));
-    a.v[c] = a.rv[c] / (0.5 * (full_of(a.rho, cidx(d, i, wrap_idx(j - 1, d.ny), k), r0) + r));
-    a.w[c] = (k == 0) ? 0.0 : a.rw[c] / (0.5 * (full_of(a.rho, c - d.nxy, a.rho0[k - 1]) + r));
+    const double pp = a.p0[k] * expm1(kGamma * log1p(Tp / T0));
+    const double w = (k == 0) ? 0.0 : Wc / (0.5 * (rb + r));
+    a.th[c] = kPert<T> ? (T)(th - a.theta0[k]) : (T)th;
+    a.pp[c] = pp;
+    a.u[c] = U / (0.5 * (rw_ + r));
+    a.v[c] = V / (0.5 * (rs + r));
+    a.w[c] = w;
     if (k == d.nz - 1) a.w[c + d.nxy] = 0.0;
 }
 
@@ -88,6 +97,9 @@ __device__ __forceinline__ Nbr nbr(const Dims &d, int i, int j, int k)
 
 // Smagorinsky eddy viscosity mu_t = rho (Cs Delta)^2 sqrt(2 S:S), Delta = (dx dy dz)^(1/3);
 // off-diagonal strains are averaged from the four edges around the centre.
+// Branch-free: neighbours by selects, vertical neighbours clamped; the lid
+// edges drop out because 2/(dz_{k-1} + dz_k) is zero on the lids and w is zero
+// on the lid faces.
 template <typename T>
 __global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
 {
@@ -95,43 +107,40 @@ __global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
     const TileIdx t = tile_cell(a.ntx, a.nty);
     const int i = t.i, j = t.j, k = t.k;
     if (i >= d.nx || j >= d.ny) return;
-    const Nbr n = nbr(d, i, j, k);
-    const int c = n.c, P = d.nxy;
-    // velocity loads widened to double before any arithmetic
-    auto u = [&](int cc) { return (double)a.u[cc]; };
-    auto v = [&](int cc) { return (double)a.v[cc]; };
-    auto w = [&](int cc) { return (double)a.w[cc]; };
-    const double idz = a.idz[k];
-    const double e11 = (u(c + n.ip) - u(c)) * a.idx;
-    const double e22 = (v(c + n.jp) - v(c)) * a.idy;
-    const double e33 = (w(c + P) - w(c)) * idz;
-    // offsets of i-1 and j-1 seen from the neighbours i+1 and j+1
-    const int ip1 = wrap_idx(i + 1, d.nx), jp1 = wrap_idx(j + 1, d.ny);
-    const int nip_im = wrap_idx(ip1 - 1, d.nx) - ip1;
-    const int njp_jm = (wrap_idx(jp1 - 1, d.ny) - jp1) * d.nx;
-    // S12 on the edge (x-face, y-face) at offset o, with its i-1 / j-1 offsets
-    auto s12 = [&](int o, int oim, int ojm) {
-        return 0.5 * ((u(c + o) - u(c + o + ojm)) * a.idy + (v(c + o) - v(c + o + oim)) * a.idx);
-    };
-    const double a12 = 0.25 * (s12(0, n.im, n.jm) + s12(n.ip, nip_im, n.jm) + s12(n.jp, n.im, njp_jm) +
-                               s12(n.ip + n.jp, nip_im, njp_jm));
-    // S13 / S23 on z-face edges; zero on the lids
-    auto s13 = [&](int o, int oim, int kf) {
-        if (kf <= 0 || kf >= d.nz) return 0.0;
-        const double idzf = a.idzf[kf];
-        return 0.5 * ((u(c + o) - u(c + o - P)) * idzf + (w(c + o) - w(c + o + oim)) * a.idx);
-    };
-    auto s23 = [&](int o, int ojm, int kf) {
-        if (kf <= 0 || kf >= d.nz) return 0.0;
-        const double idzf = a.idzf[kf];
-        return 0.5 * ((v(c + o) - v(c + o - P)) * idzf + (w(c + o) - w(c + o + ojm)) * a.idy);
-    };
-    const double a13 =
-        0.25 * (s13(0, n.im, k) + s13(n.ip, nip_im, k) + s13(P, n.im, k + 1) + s13(P + n.ip, nip_im, k + 1));
-    const double a23 =
-        0.25 * (s23(0, n.jm, k) + s23(n.jp, njp_jm, k) + s23(P, n.jm, k + 1) + s23(P + n.jp, njp_jm, k + 1));
+    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.nxy;
+    const int im = i == 0 ? nx - 1 : i - 1, ip = i == nx - 1 ? 0 : i + 1;
+    const int rj = j * nx, rjm = (j == 0 ? ny - 1 : j - 1) * nx, rjp = (j == ny - 1 ? 0 : j + 1) * nx;
+    const int lk = k * P, lkm = (k > 0 ? k - 1 : 0) * P, lkp = (k < nz - 1 ? k + 1 : nz - 1) * P, lk1 = (k + 1) * P;
+    auto U = [&](int ii, int r, int l) { return (double)a.u[l + r + ii]; };
+    auto V = [&](int ii, int r, int l) { return (double)a.v[l + r + ii]; };
+    auto Wf = [&](int ii, int r, int l) { return (double)a.w[l + r + ii]; };
+    const double gz0 = a.idzf[k], gz1 = a.idzf[k + 1];
+    const double u_c = U(i, rj, lk), u_e = U(ip, rj, lk), u_s = U(i, rjm, lk), u_se = U(ip, rjm, lk);
+    const double u_n = U(i, rjp, lk), u_ne = U(ip, rjp, lk);
+    const double u_b = U(i, rj, lkm), u_be = U(ip, rj, lkm), u_t = U(i, rj, lkp), u_te = U(ip, rj, lkp);
+    const double v_c = V(i, rj, lk), v_n = V(i, rjp, lk), v_w = V(im, rj, lk), v_e = V(ip, rj, lk);
+    const double v_nw = V(im, rjp, lk), v_ne = V(ip, rjp, lk);
+    const double v_b = V(i, rj, lkm), v_bn = V(i, rjp, lkm), v_t = V(i, rj, lkp), v_tn = V(i, rjp, lkp);
+    const double w_c = Wf(i, rj, lk), w_u = Wf(i, rj, lk1), w_w = Wf(im, rj, lk), w_e = Wf(ip, rj, lk);
+    const double w_wu = Wf(im, rj, lk1), w_eu = Wf(ip, rj, lk1), w_s = Wf(i, rjm, lk), w_n = Wf(i, rjp, lk);
+    const double w_su = Wf(i, rjm, lk1), w_nu = Wf(i, rjp, lk1);
+    const double rc = full_of(a.rho, lk + rj + i, a.rho0[k]);
+    const double e11 = (u_e - u_c) * a.idx, e22 = (v_n - v_c) * a.idy, e33 = (w_u - w_c) * a.idz[k];
+    // S12 on the four xy-edges; S13 on the x-face edges of faces k, k+1; S23 likewise
+    const double a12 = 0.25 * (0.5 * ((u_c - u_s) * a.idy + (v_c - v_w) * a.idx) +
+                               0.5 * ((u_e - u_se) * a.idy + (v_e - v_c) * a.idx) +
+                               0.5 * ((u_n - u_c) * a.idy + (v_n - v_nw) * a.idx) +
+                               0.5 * ((u_ne - u_e) * a.idy + (v_ne - v_n) * a.idx));
+    const double a13 = 0.25 * (0.5 * ((u_c - u_b) * gz0 + (w_c - w_w) * a.idx) +
+                               0.5 * ((u_e - u_be) * gz0 + (w_e - w_c) * a.idx) +
+                               0.5 * ((u_t - u_c) * gz1 + (w_u - w_wu) * a.idx) +
+                               0.5 * ((u_te - u_e) * gz1 + (w_eu - w_u) * a.idx));
+    const double a23 = 0.25 * (0.5 * ((v_c - v_b) * gz0 + (w_c - w_s) * a.idy) +
+                               0.5 * ((v_n - v_bn) * gz0 + (w_n - w_c) * a.idy) +
+                               0.5 * ((v_t - v_c) * gz1 + (w_u - w_su) * a.idy) +
+                               0.5 * ((v_tn - v_n) * gz1 + (w_nu - w_u) * a.idy));
     const double ss = 2.0 * (e11 * e11 + e22 * e22 + e33 * e33) + 4.0 * (a12 * a12 + a13 * a13 + a23 * a23);
-    a.mut[c] = full_of(a.rho, c, a.rho0[k]) * a.cs2[k] * sqrt(ss);
+    a.mut[lk + rj + i] = rc * a.cs2[k] * sqrt(ss);
 }
 
 // Stresses tau = -2 mu (S - D) at their points, mu = rho nu_m + mu_t averaged
@@ -142,44 +151,55 @@ __global__ __launch_bounds__(256) void k_stress(RhsArgs<T> a)
 {
     const Dims &d = a.d;
     const TileIdx t = tile_cell(a.ntx, a.nty);
-    const int i = t.i, j = t.j, k = t.k;
+    const int i = t.i, j = t.j, k = t.k;  // k = 0..nz: face k and, below the top, cell k
     if (i >= d.nx || j >= d.ny) return;
-    const Nbr n = nbr(d, i, j, k);
-    const int P = d.nxy, c = n.c;
-    const T *rho = a.rho, *mut = a.mut;
-    auto u = [&](int cc) { return (double)a.u[cc]; };
-    auto v = [&](int cc) { return (double)a.v[cc]; };
-    auto w = [&](int cc) { return (double)a.w[cc]; };
-    // full density on level kk
-    auto rh = [&](int cc, int kk) { return full_of(rho, cc, a.rho0[kk]); };
-    auto mu = [&](int cc, int kk) { return rh(cc, kk) * a.nu + (a.sgs ? (double)mut[cc] : 0.0); };
-    // shear stresses on the z-face edges of face k
-    if (k == 0 || k == d.nz) {
-        a.t13[c] = 0.0;
-        a.t23[c] = 0.0;
-    } else {
-        const double idzf = a.idzf[k];
-        const double s13 = 0.5 * ((u(c) - u(c - P)) * idzf + (w(c) - w(c + n.im)) * a.idx);
-        const double s23 = 0.5 * ((v(c) - v(c - P)) * idzf + (w(c) - w(c + n.jm)) * a.idy);
-        const double mxz = 0.25 * (mu(c - P + n.im, k - 1) + mu(c - P, k - 1) + mu(c + n.im, k) + mu(c, k));
-        const double myz = 0.25 * (mu(c - P + n.jm, k - 1) + mu(c - P, k - 1) + mu(c + n.jm, k) + mu(c, k));
-        a.t13[c] = -2.0 * mxz * s13;
-        a.t23[c] = -2.0 * myz * s23;
-    }
-    if (k == d.nz) return;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.nxy;
+    const int im = i == 0 ? nx - 1 : i - 1, ip = i == nx - 1 ? 0 : i + 1;
+    const int rj = j * nx, rjm = (j == 0 ? ny - 1 : j - 1) * nx, rjp = (j == ny - 1 ? 0 : j + 1) * nx;
+    // every load first, from indices clamped into the arrays: the cell level
+    // kc (k, or nz-1 for the top face) and the level below the face kb
+    const int kc = k < nz ? k : nz - 1, kb = k > 0 ? k - 1 : 0;
+    const int lc = kc * P, lb = kb * P, lf = k * P, lc1 = (kc + 1) * P;
+    const double rc0 = a.rho0[kc], rb0 = a.rho0[kb];
+    const bool sgs = a.sgs != 0;
+    // mu = rho nu_m + mu_t (mu_t read always and used only with the SGS model)
+    auto mu = [&](int cc, double r0) {
+        const double mt = (double)a.mut[cc];
+        return full_of(a.rho, cc, r0) * a.nu + (sgs ? mt : 0.0);
+    };
+    const double u_f = a.u[lc + rj + i], u_fb = a.u[lb + rj + i];
+    const double v_f = a.v[lc + rj + i], v_fb = a.v[lb + rj + i];
+    const double w_f = a.w[lf + rj + i], w_fw = a.w[lf + rj + im], w_fs = a.w[lf + rjm + i];
+    const double m_c = mu(lc + rj + i, rc0), m_w = mu(lc + rj + im, rc0), m_s = mu(lc + rjm + i, rc0);
+    const double m_ws = mu(lc + rjm + im, rc0);
+    const double m_b = mu(lb + rj + i, rb0), m_bw = mu(lb + rj + im, rb0), m_bs = mu(lb + rjm + i, rb0);
+    const double u_e = a.u[lc + rj + ip], u_s = a.u[lc + rjm + i];
+    const double v_n = a.v[lc + rjp + i], v_w = a.v[lc + rj + im];
+    const double w_u = a.w[lc1 + rj + i], w_c = a.w[lc + rj + i];
+    const double rc = full_of(a.rho, lc + rj + i, rc0), mtc = (double)a.mut[lc + rj + i];
+    // shear stresses on the z-face edges of face k (zero on the lids)
+    const bool inner = k > 0 && k < nz;
+    const double idzf = a.idzf[k];
+    const double s13 = 0.5 * ((u_f - u_fb) * idzf + (w_f - w_fw) * a.idx);
+    const double s23 = 0.5 * ((v_f - v_fb) * idzf + (w_f - w_fs) * a.idy);
+    const double mxz = 0.25 * (m_bw + m_b + m_w + m_c);
+    const double myz = 0.25 * (m_bs + m_b + m_s + m_c);
+    a.t13[lf + rj + i] = inner ? -2.0 * mxz * s13 : 0.0;
+    a.t23[lf + rj + i] = inner ? -2.0 * myz * s23 : 0.0;
+    if (k == nz) return;
     const double idz = a.idz[k];
-    const double e11 = (u(c + n.ip) - u(c)) * a.idx;
-    const double e22 = (v(c + n.jp) - v(c)) * a.idy;
-    const double e33 = (w(c + P) - w(c)) * idz;
+    const double e11 = (u_e - u_f) * a.idx;
+    const double e22 = (v_n - v_f) * a.idy;
+    const double e33 = (w_u - w_c) * idz;
     const double dd = (e11 + e22 + e33) / 3.0;
-    const double m = mu(c, k);
-    a.t11[c] = -2.0 * m * (e11 - dd);
-    a.t22[c] = -2.0 * m * (e22 - dd);
-    a.t33[c] = -2.0 * m * (e33 - dd);
-    const double s12 = 0.5 * ((u(c) - u(c + n.jm)) * a.idy + (v(c) - v(c + n.im)) * a.idx);
-    const double me = 0.25 * (mu(c + n.im + n.jm, k) + mu(c + n.jm, k) + mu(c + n.im, k) + m);
+    const int c = lc + rj + i;
+    a.t11[c] = -2.0 * m_c * (e11 - dd);
+    a.t22[c] = -2.0 * m_c * (e22 - dd);
+    a.t33[c] = -2.0 * m_c * (e33 - dd);
+    const double s12 = 0.5 * ((u_f - u_s) * a.idy + (v_f - v_w) * a.idx);
+    const double me = 0.25 * (m_ws + m_s + m_w + m_c);
     a.t12[c] = -2.0 * me * s12;
-    a.kap[c] = rh(c, k) * a.alpha + (a.sgs ? (double)mut[c] / a.Pr_t : 0.0);
+    a.kap[c] = rc * a.alpha + (sgs ? mtc / a.Pr_t : 0.0);
 }
 
 // ---------------------------------------------------------------------------
