@@ -254,7 +254,7 @@ def run_ensemble(steps: int, warmup: int, per_size: int = 16):
             "nonfinite": bad}
 
 
-def cpu_baseline(cfg: W.Config, target_s: float = 15.0):
+def cpu_baseline(cfg: W.Config, target_s: float = 12.0):
     """FP64 oracle on a bounded sample: the same physics on a 64 x 64 column
     block of the workload (periodic), timed for whole RK3 steps."""
     import oracle
@@ -269,7 +269,7 @@ def cpu_baseline(cfg: W.Config, target_s: float = 15.0):
         o.rk3_step(S)
         steps += 1
         el = time.perf_counter() - t0
-        if el > target_s or steps >= 3:
+        if el > target_s or steps >= 60:
             break
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": sample.cells * steps / el, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
