@@ -28,6 +28,7 @@
 // processes form a contiguous band of the domain and tile halos hit its L2.
 #include "erf_internal.h"
 
+
 namespace erfk {
 namespace {
 
@@ -68,25 +69,28 @@ __global__ __launch_bounds__(256) void k_stage_init(StageArgs<T> a)
     int k = blockIdx.z;  // 0..nz (the extra plane handles the top z-face)
     if (i >= d.nx || j >= d.ny) return;
     int c = cidx(d, i, j, k);
-    a.w2[c] = (double)a.n_w[c] - (double)a.t_w[c];
-    if (a.sums) a.sw[c] = 0.0;
+    // every value is read and written once: streaming accesses throughout
+    st_stream(a.w2 + c, (T)((double)ld_stream(a.n_w + c) - (double)ld_stream(a.t_w + c)));
+    if (a.sums) st_stream(a.sw + c, (T)0);
     if (k == d.nz) return;
     const double T0 = a.Theta0[k];
-    const double Tt = full_of(a.t_t, c, T0);
-    a.tht[c] = Tt / full_of(a.t_r, c, a.rho0[k]);
+    const T tt = ld_stream(a.t_t + c), tr = ld_stream(a.t_r + c);
+    const double Tt = kPert<T> ? T0 + (double)tt : (double)tt;
+    const double rt = kPert<T> ? a.rho0[k] + (double)tr : (double)tr;
+    st_stream(a.tht + c, (T)(Tt / rt));
     // Exner function of the stage state: (R_d Theta / P00)^(gamma - 1); from
     // the perturbation in FP32 storage, pi0 (1 + Theta'/Theta0)^(gamma - 1)
     if constexpr (kPert<T>)
-        a.pit[c] = a.pi0[k] * exp((kGamma - 1.0) * log1p((double)a.t_t[c] / T0));
+        st_stream(a.pit + c, (T)(a.pi0[k] * exp((kGamma - 1.0) * log1p((double)tt / T0))));
     else
-        a.pit[c] = pow(kRd * Tt / kP00, kGamma - 1.0);
-    a.T2cur[c] = (double)a.n_t[c] - (double)a.t_t[c];
-    a.r2[c] = (double)a.n_r[c] - (double)a.t_r[c];
-    a.u2in[c] = (double)a.n_u[c] - (double)a.t_u[c];
-    a.v2in[c] = (double)a.n_v[c] - (double)a.t_v[c];
+        st_stream(a.pit + c, (T)pow(kRd * Tt / kP00, kGamma - 1.0));
+    st_stream(a.T2cur + c, (T)((double)ld_stream(a.n_t + c) - (double)tt));
+    st_stream(a.r2 + c, (T)((double)ld_stream(a.n_r + c) - (double)tr));
+    st_stream(a.u2in + c, (T)((double)ld_stream(a.n_u + c) - (double)ld_stream(a.t_u + c)));
+    st_stream(a.v2in + c, (T)((double)ld_stream(a.n_v + c) - (double)ld_stream(a.t_v + c)));
     if (a.sums) {
-        a.su[c] = 0.0;
-        a.sv[c] = 0.0;
+        st_stream(a.su + c, (T)0);
+        st_stream(a.sv + c, (T)0);
     }
 }
 
@@ -128,10 +132,10 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
         double den = (k == 1) ? di : di - lo * cprev;
         double m = 1.0 / den;
         double cp = up * m;
-        a.calpha[c] = lo * m;
-        a.cm[c] = m;
-        a.cc[c] = cp;
-        a.cC[c] = C;
+        st_stream(a.calpha + c, lo * m);
+        st_stream(a.cm + c, m);
+        st_stream(a.cc + c, cp);
+        st_stream(a.cC + c, (T)C);
         cprev = cp;
     }
 }
@@ -183,26 +187,24 @@ __device__ __forceinline__ void substep_explicit(
                 const double Vs = v2in[c] + dt * (-gRd * (0.5 * (ps + pc)) * (ttc - tts) * idy + R_v[c]);
                 const double Vn =
                     v2in[c + o_n] + dt * (-gRd * (0.5 * (pc + pn)) * (ttn - ttc) * idy + R_v[c + o_n]);
-                u2out[c] = Uw;
-                v2out[c] = Vs;
-                if (sums) {
-                    su[c] += Uw;
-                    sv[c] += Vs;
-                }
+                st_stream(u2out + c, (T)Uw);
+                st_stream(v2out + c, (T)Vs);
                 // explicit parts of Theta'' and rho''
                 const double thc = tht[c];
                 const double thx0 = 0.5 * (tht[c + o_w] + thc), thx1 = 0.5 * (thc + tht[c + o_e]);
                 const double thy0 = 0.5 * (tht[c + o_s] + thc), thy1 = 0.5 * (thc + tht[c + o_n]);
                 const double hdiv_t = (Ue * thx1 - Uw * thx0) * idx + (Vn * thy1 - Vs * thy0) * idy;
                 const double hdiv_r = (Ue - Uw) * idx + (Vn - Vs) * idy;
-                const double th_above = (k < nz - 1) ? tht[c + nxy] : 0.0;
+                // the level above, clamped at the lid (its value unused there)
+                const double th_above = tht[c + (k < nz - 1 ? nxy : 0)];
                 const double tfk = (k == 0) ? 0.0 : 0.5 * (th_below + thc);
                 const double tfk1 = (k == nz - 1) ? 0.0 : 0.5 * (thc + th_above);
                 const double w_hi = w2[c + nxy];
                 const double idzk = idz_t[k];
-                const double r2c = r2[c];
-                const double that = Tc + dt * (-hdiv_t - b1 * (w_hi * tfk1 - w_lo * tfk) * idzk + R_t[c]);
-                const double rhat = r2c + dt * (-hdiv_r - b1 * (w_hi - w_lo) * idzk + R_r[c]);
+                // values read by this lane only: streaming loads
+                const double r2c = ld_stream(r2 + c), Rt = ld_stream(R_t + c), Rr = ld_stream(R_r + c);
+                const double that = Tc + dt * (-hdiv_t - b1 * (w_hi * tfk1 - w_lo * tfk) * idzk + Rt);
+                const double rhat = r2c + dt * (-hdiv_r - b1 * (w_hi - w_lo) * idzk + Rr);
                 const double e = b1 * Tc + b2 * that, f = b1 * r2c + b2 * rhat;
                 if (l == 0) {
                     e_first = e;
@@ -211,9 +213,9 @@ __device__ __forceinline__ void substep_explicit(
                     // right-hand side of the W'' row on face k
                     const double idzf = idzf_t[k];
                     const double A = gRd * (0.5 * (pi_below + pc));
-                    const double C = cC[c];
+                    const double C = ld_stream(cC + c);
                     rbuf[k * kLanes + lane] = w_lo + dt * (-A * (e - e_prev) * idzf + 0.5 * C * (e + e_prev) -
-                                                           0.5 * gr * (f + f_prev) + R_w[c]);
+                                                           0.5 * gr * (f + f_prev) + ld_stream(R_w + c));
                 }
                 if constexpr (kLevels <= 8)
                     thl[k * kLanes + lane] = that;
@@ -229,6 +231,11 @@ __device__ __forceinline__ void substep_explicit(
                     bnd[(g * 2 + 0) * kLanes + lane] = e;
                     bnd[(g * 2 + 1) * kLanes + lane] = f;
                 }
+                // running sums last, so that no branch separates this level's loads
+                if (sums) {
+                    su[c] += Uw;
+                    sv[c] += Vs;
+                }
             }
         }
     }
@@ -243,7 +250,10 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
     extern __shared__ double lds[];
     const Dims &d = a.d;
     const int nz = d.nz, nxy = d.nxy;
-    const int lane = threadIdx.x, g = threadIdx.y;
+    // blockDim.x is one wavefront, so the level chunk g is uniform per
+    // wavefront: said so to the compiler, level indices live in scalar
+    // registers and per-level tables (1/dz) are read with scalar loads
+    const int lane = threadIdx.x, g = __builtin_amdgcn_readfirstlane(threadIdx.y);
     double *rbuf = lds;                     // [(nz + 1) * 64]
     double *bnd = lds + (nz + 1) * kLanes;  // [KG][2][64]
     double *thl = bnd + 2 * blockDim.y * kLanes;  // [nz][64] when kLevels <= 8
@@ -269,6 +279,23 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
                                  a.w2, a.r2, a.cC, a.idz, a.idzf, a.u2out, a.v2out, a.su, a.sv, a.sums, rbuf, bnd,
                                  act, col, nxy, nz, k0, g, lane, o_e, o_w, o_n, o_s, dt, b1, b2, gr, bd, gRd, idx,
                                  idy, th, thl, rh, e_first, f_first);
+    // Up to 8 levels per wavefront, the chunk's tridiagonal factors (and, for
+    // phase 3, theta^t) are loaded together into registers, levels
+    // clamped into the column so that no branch separates the loads: the
+    // sweeps then wait on LDS only instead of one global round trip per level.
+    // With 16 levels they are loaded where used (registers).
+    constexpr bool kPre = kLevels <= 8;
+    constexpr int kP = kPre ? kLevels : 1;
+    double fal[kP], fcm[kP], fcc[kP];
+    if constexpr (kPre) {
+#pragma unroll
+        for (int l = 0; l < kLevels; ++l) {
+            const int c = col + min(k0 + l, nz - 1) * nxy;
+            fal[l] = ld_stream(a.calpha + c);
+            fcm[l] = ld_stream(a.cm + c);
+            fcc[l] = ld_stream(a.cc + c);
+        }
+    }
     __syncthreads();
     // row k0 of every chunk but the first needs the last level of the chunk below
     if (act && k0 < nz && g > 0) {
@@ -301,8 +328,8 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
             const int k = k0 + l;
             if (k >= rlo && k <= rhi) {
                 const int c = col + k * nxy;
-                const double al = a.calpha[c];
-                dl = rbuf[k * kLanes + lane] * a.cm[c] - al * dl;
+                const double al = kPre ? fal[kPre ? l : 0] : a.calpha[c];
+                dl = rbuf[k * kLanes + lane] * (kPre ? fcm[kPre ? l : 0] : a.cm[c]) - al * dl;
                 pm = -al * pm;
                 rbuf[k * kLanes + lane] = dl;
                 mult[l] = pm;
@@ -329,15 +356,21 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
         for (int l = kLevels - 1; l >= 0; --l) {
             const int k = k0 + l;
             if (k >= rlo && k <= rhi) {
-                const int c = col + k * nxy;
                 const double dk = rbuf[k * kLanes + lane] + mult[l] * Dprev;
-                const double cp = a.cc[c];
+                const double cp = kPre ? fcc[kPre ? l : 0] : a.cc[col + k * nxy];
                 xl = dk - cp * xl;
                 qm = -cp * qm;
                 rbuf[k * kLanes + lane] = xl;
                 mult[l] = qm;
             }
         }
+    }
+    // theta^t of the levels k0 - 1 .. k0 + kLevels (clamped) for phase 3, in
+    // flight while the chunk ends are chained
+    double thv[kP + 2];
+    if constexpr (kPre) {
+#pragma unroll
+        for (int l = 0; l < kLevels + 2; ++l) thv[l] = a.tht[col + min(max(k0 + l - 1, 0), nz - 1) * nxy];
     }
     __syncthreads();
     if (act && rlo <= rhi) {
@@ -365,16 +398,17 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
             if (k < nz) {
                 const int c = col + k * nxy;
                 const double wk = (k >= rlo && k <= rhi) ? rbuf[k * kLanes + lane] + mult[l] * Xnext : 0.0;
-                // theta^t on the faces below and above, again from the cache
-                const double thc = a.tht[c];
-                const double tfl = (k == 0) ? 0.0 : 0.5 * ((double)a.tht[c - nxy] + thc);
-                const double tf1 = (k == nz - 1) ? 0.0 : 0.5 * (thc + (double)a.tht[c + nxy]);
+                // theta^t on the faces below and above
+                const int p = kPre ? l : 0;
+                const double thc = kPre ? thv[p + 1] : (double)a.tht[c];
+                const double tfl = (k == 0) ? 0.0 : 0.5 * ((kPre ? thv[p] : (double)a.tht[c - nxy]) + thc);
+                const double tf1 = (k == nz - 1) ? 0.0 : 0.5 * (thc + (kPre ? thv[p + 2] : (double)a.tht[c + nxy]));
                 const double idzk = a.idz[k];
                 const double thk = (kLevels <= 8) ? thl[k * kLanes + lane] : th[l];
-                a.T2nxt[c] = thk - dt * b2 * (wk1 * tf1 - wk * tfl) * idzk;
-                a.r2[c] = rh[l] - dt * b2 * (wk1 - wk) * idzk;
+                st_stream(a.T2nxt + c, (T)(thk - dt * b2 * (wk1 * tf1 - wk * tfl) * idzk));
+                st_stream(a.r2 + c, (T)(rh[l] - dt * b2 * (wk1 - wk) * idzk));
                 if (k >= 1) {
-                    a.w2[c] = wk;
+                    st_stream(a.w2 + c, (T)wk);
                     if (a.sums) a.sw[c] += wk;
                 }
                 wk1 = wk;
@@ -407,21 +441,22 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs<T> a)
     int k = blockIdx.z;
     if (i >= d.nx || j >= d.ny) return;
     int c = cidx(d, i, j, k);
+    // every value is read and written once: streaming accesses throughout
     double inv = 1.0 / a.n_sub;
-    double wt = a.t_w[c], wN = a.w2[c];
+    double wt = ld_stream(a.t_w + c), wN = ld_stream(a.w2 + c);
     if (a.Fw) {
-        double w0 = (double)a.n_w[c] - wt;
-        a.Fw[c] = wt + ((double)a.sw[c] + a.b1 * (w0 - wN)) * inv;
+        double w0 = (double)ld_stream(a.n_w + c) - wt;
+        st_stream(a.Fw + c, (T)(wt + ((double)ld_stream(a.sw + c) + a.b1 * (w0 - wN)) * inv));
     }
-    a.o_w[c] = wt + wN;
+    st_stream(a.o_w + c, (T)(wt + wN));
     if (k == d.nz) return;
-    a.o_r[c] = (double)a.t_r[c] + (double)a.r2[c];
-    a.o_t[c] = (double)a.t_t[c] + (double)a.T2[c];
-    double ut = a.t_u[c], vt = a.t_v[c];
-    a.o_u[c] = ut + (double)a.u2[c];
-    a.o_v[c] = vt + (double)a.v2[c];
-    if (a.Fu) a.Fu[c] = ut + (double)a.su[c] * inv;
-    if (a.Fv) a.Fv[c] = vt + (double)a.sv[c] * inv;
+    st_stream(a.o_r + c, (T)((double)ld_stream(a.t_r + c) + (double)ld_stream(a.r2 + c)));
+    st_stream(a.o_t + c, (T)((double)ld_stream(a.t_t + c) + (double)ld_stream(a.T2 + c)));
+    double ut = ld_stream(a.t_u + c), vt = ld_stream(a.t_v + c);
+    st_stream(a.o_u + c, (T)(ut + (double)ld_stream(a.u2 + c)));
+    st_stream(a.o_v + c, (T)(vt + (double)ld_stream(a.v2 + c)));
+    if (a.Fu) st_stream(a.Fu + c, (T)(ut + (double)ld_stream(a.su + c) * inv));
+    if (a.Fv) st_stream(a.Fv + c, (T)(vt + (double)ld_stream(a.sv + c) * inv));
 }
 
 }  // namespace

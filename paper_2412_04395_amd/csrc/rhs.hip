@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
                                0.5 * ((v_t - v_c) * gz1 + (w_u - w_su) * a.idy) +
                                0.5 * ((v_tn - v_n) * gz1 + (w_nu - w_u) * a.idy));
     const double ss = 2.0 * (e11 * e11 + e22 * e22 + e33 * e33) + 4.0 * (a12 * a12 + a13 * a13 + a23 * a23);
-    a.mut[lk + rj + i] = rc * a.cs2[k] * sqrt(ss);
+    st_stream(a.mut + lk + rj + i, (T)(rc * a.cs2[k] * sqrt(ss)));  // read by a later launch only
 }
 
 // Stresses tau = -2 mu (S - D) at their points, mu = rho nu_m + mu_t averaged
@@ -258,7 +258,8 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
     const double r0k = a.rho0[k], rc = full_of(a.rho, c, r0k);
     const double th0k = kPert<T> ? a.theta0[k] : 0.0;
     {
-        a.Rr[c] = -((U1 - U0) * a.idx + (V1 - V0) * a.idy + (W1 - W0) * idz);
+        // tendencies are read by later launches only: streaming stores
+        st_stream(a.Rr + c, (T)(-((U1 - U0) * a.idx + (V1 - V0) * a.idy + (W1 - W0) * idz)));
         const T *th = a.th;
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = th0k + th[c + ox(t)];
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
             r -= (hx1 - hx0) * a.idx + (hy1 - hy0) * a.idy + (hz1 - hz0) * idz;
         }
         if (k == 0 && a.Qs != 0.0) r += rc * a.Qs * idz;
-        a.Rt[c] = r;
+        st_stream(a.Rt + c, (T)r);
     }
 
     // ---------------- x-momentum on x-face (i, j, k) ----------------
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
         if (a.visc)
             r -= (a.t11[c] - a.t11[c + ox(2)]) * a.idx + (a.t12[c + oy(4)] - a.t12[c]) * a.idy +
                  (a.t13[c + P] - a.t13[c]) * idz;
-        a.Ru[c] = r;
+        st_stream(a.Ru + c, (T)r);
     }
 
     // ---------------- y-momentum on y-face (i, j, k) ----------------
@@ -356,7 +357,7 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
         if (a.visc)
             r -= (a.t12[c + ox(4)] - a.t12[c]) * a.idx + (a.t22[c] - a.t22[c + oy(2)]) * a.idy +
                  (a.t23[c + P] - a.t23[c]) * idz;
-        a.Rv[c] = r;
+        st_stream(a.Rv + c, (T)r);
     }
 
     // ---------------- z-momentum on z-face (i, j, k) ----------------
@@ -387,7 +388,7 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
         if (a.visc)
             r -= (a.t13[c + ox(4)] - a.t13[c]) * a.idx + (a.t23[c + oy(4)] - a.t23[c]) * a.idy +
                  (a.t33[c] - a.t33[cm]) * idzf;
-        a.Rw[c] = r;
+        st_stream(a.Rw + c, (T)r);
     }
 }
 
