@@ -94,14 +94,6 @@ __global__ __launch_bounds__(256) void k_stage_init(StageArgs<T> a)
     }
 }
 
-// theta^t on z-face k of a column (lid faces carry W = 0; value unused)
-template <typename T>
-__device__ __forceinline__ double thz(const StageArgs<T> &a, int col, int k)
-{
-    if (k <= 0 || k >= a.d.nz) return 0.0;
-    return 0.5 * ((double)a.tht[col + (k - 1) * a.d.nxy] + (double)a.tht[col + k * a.d.nxy]);
-}
-
 // Tridiagonal rows for W'' at interior faces k = 1..nz-1.  Substituting
 // Theta''_new = That - dtau b2 delta_z(W theta_f)/dz and rho''_new = Rhat -
 // dtau b2 delta_z(W)/dz into the W'' equation of App. C couples W_{k-1}, W_k,
@@ -116,27 +108,50 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
     if (i >= d.nx || j >= d.ny) return;
     const int col = j * d.nx + i, nxy = d.nxy, nz = d.nz;
     const double D = a.dtau * a.dtau * a.b2 * a.b2, g = a.g;
+    // The elimination is serial in k, but its inputs are not: they are loaded
+    // for kChunk levels at a time (levels clamped into the column, unused
+    // values at the lids), so that a column waits for one memory round trip
+    // per chunk rather than one per level.
+    constexpr int kChunk = 8;
+    auto lev = [&](int k) { return col + min(max(k, 0), nz - 1) * nxy; };
     double cprev = 0.0;
-    for (int k = 1; k < nz; ++k) {
-        int c = col + k * nxy, cm = c - nxy;
-        double dzf = 0.5 * (a.dz[k - 1] + a.dz[k]);
-        double pif = 0.5 * ((double)a.pit[cm] + (double)a.pit[c]);
-        double A = kGamma * kRd * pif;
-        double C = g * 0.5 * (a.rho0[k - 1] + a.rho0[k]) * (kRd / kCv) * (pif / (0.5 * (a.pi0[k - 1] + a.pi0[k]))) /
-                   (0.5 * (full_of(a.t_t, cm, a.Theta0[k - 1]) + full_of(a.t_t, c, a.Theta0[k])));
-        double idzm = 1.0 / a.dz[k - 1], idz = 1.0 / a.dz[k];
-        double tfm = thz(a, col, k - 1), tf = thz(a, col, k), tfp = thz(a, col, k + 1);
-        double lo = (k == 1) ? 0.0 : -D * (A * tfm * idzm / dzf + 0.5 * C * tfm * idzm - 0.5 * g * idzm);
-        double up = (k == nz - 1) ? 0.0 : -D * (A * tfp * idz / dzf - 0.5 * C * tfp * idz + 0.5 * g * idz);
-        double di = 1.0 + D * (A * tf * (idz + idzm) / dzf + 0.5 * C * tf * (idzm - idz) - 0.5 * g * (idzm - idz));
-        double den = (k == 1) ? di : di - lo * cprev;
-        double m = 1.0 / den;
-        double cp = up * m;
-        st_stream(a.calpha + c, lo * m);
-        st_stream(a.cm + c, m);
-        st_stream(a.cc + c, cp);
-        st_stream(a.cC + c, (T)C);
-        cprev = cp;
+    for (int k0 = 1; k0 < nz; k0 += kChunk) {
+        double P[kChunk + 1], TT[kChunk + 1], H[kChunk + 3];
+#pragma unroll
+        for (int q = 0; q <= kChunk; ++q) {
+            P[q] = a.pit[lev(k0 - 1 + q)];      // Exner at level k0 - 1 + q
+            TT[q] = a.t_t[lev(k0 - 1 + q)];     // rho theta (stored form)
+        }
+#pragma unroll
+        for (int q = 0; q < kChunk + 3; ++q) H[q] = a.tht[lev(k0 - 2 + q)];  // theta at k0 - 2 + q
+        // theta on face m (between levels m - 1 and m); zero on the lids
+        auto tface = [&](int m, int q) { return (m <= 0 || m >= nz) ? 0.0 : 0.5 * (H[q] + H[q + 1]); };
+#pragma unroll
+        for (int l = 0; l < kChunk; ++l) {
+            const int k = k0 + l;
+            if (k >= nz) break;
+            const int c = col + k * nxy;
+            double dzf = 0.5 * (a.dz[k - 1] + a.dz[k]);
+            double pif = 0.5 * (P[l] + P[l + 1]);
+            double A = kGamma * kRd * pif;
+            const double Tm = kPert<T> ? a.Theta0[k - 1] + TT[l] : TT[l];
+            const double Tk = kPert<T> ? a.Theta0[k] + TT[l + 1] : TT[l + 1];
+            double C = g * 0.5 * (a.rho0[k - 1] + a.rho0[k]) * (kRd / kCv) * (pif / (0.5 * (a.pi0[k - 1] + a.pi0[k]))) /
+                       (0.5 * (Tm + Tk));
+            double idzm = 1.0 / a.dz[k - 1], idz = 1.0 / a.dz[k];
+            double tfm = tface(k - 1, l), tf = tface(k, l + 1), tfp = tface(k + 1, l + 2);
+            double lo = (k == 1) ? 0.0 : -D * (A * tfm * idzm / dzf + 0.5 * C * tfm * idzm - 0.5 * g * idzm);
+            double up = (k == nz - 1) ? 0.0 : -D * (A * tfp * idz / dzf - 0.5 * C * tfp * idz + 0.5 * g * idz);
+            double di = 1.0 + D * (A * tf * (idz + idzm) / dzf + 0.5 * C * tf * (idzm - idz) - 0.5 * g * (idzm - idz));
+            double den = (k == 1) ? di : di - lo * cprev;
+            double m = 1.0 / den;
+            double cp = up * m;
+            st_stream(a.calpha + c, lo * m);
+            st_stream(a.cm + c, m);
+            st_stream(a.cc + c, cp);
+            st_stream(a.cC + c, (T)C);
+            cprev = cp;
+        }
     }
 }
 

@@ -68,11 +68,13 @@ __global__ __launch_bounds__(256) void k_prep(RhsArgs<T> a)
     // p' = p0 ((Theta/Theta0)^gamma - 1) without cancellation (EOS, Sec. 2.1)
     const double pp = a.p0[k] * expm1(kGamma * log1p(Tp / T0));
     const double w = (k == 0) ? 0.0 : Wc / (0.5 * (rb + r));
-    a.th[c] = kPert<T> ? (T)(th - a.theta0[k]) : (T)th;
-    a.pp[c] = pp;
-    a.u[c] = U / (0.5 * (rw_ + r));
-    a.v[c] = V / (0.5 * (rs + r));
-    a.w[c] = w;
+    // outputs are read by later launches only: streaming stores, so that no
+    // dirty lines are left in the caches for the next kernel to write back
+    st_stream(a.th + c, kPert<T> ? (T)(th - a.theta0[k]) : (T)th);
+    st_stream(a.pp + c, (T)pp);
+    st_stream(a.u + c, (T)(U / (0.5 * (rw_ + r))));
+    st_stream(a.v + c, (T)(V / (0.5 * (rs + r))));
+    st_stream(a.w + c, (T)w);
     if (k == d.nz - 1) a.w[c + d.nxy] = 0.0;
 }
 
@@ -184,8 +186,8 @@ __global__ __launch_bounds__(256) void k_stress(RhsArgs<T> a)
     const double s23 = 0.5 * ((v_f - v_fb) * idzf + (w_f - w_fs) * a.idy);
     const double mxz = 0.25 * (m_bw + m_b + m_w + m_c);
     const double myz = 0.25 * (m_bs + m_b + m_s + m_c);
-    a.t13[lf + rj + i] = inner ? -2.0 * mxz * s13 : 0.0;
-    a.t23[lf + rj + i] = inner ? -2.0 * myz * s23 : 0.0;
+    st_stream(a.t13 + lf + rj + i, (T)(inner ? -2.0 * mxz * s13 : 0.0));
+    st_stream(a.t23 + lf + rj + i, (T)(inner ? -2.0 * myz * s23 : 0.0));
     if (k == nz) return;
     const double idz = a.idz[k];
     const double e11 = (u_e - u_f) * a.idx;
@@ -193,13 +195,13 @@ __global__ __launch_bounds__(256) void k_stress(RhsArgs<T> a)
     const double e33 = (w_u - w_c) * idz;
     const double dd = (e11 + e22 + e33) / 3.0;
     const int c = lc + rj + i;
-    a.t11[c] = -2.0 * m_c * (e11 - dd);
-    a.t22[c] = -2.0 * m_c * (e22 - dd);
-    a.t33[c] = -2.0 * m_c * (e33 - dd);
+    st_stream(a.t11 + c, (T)(-2.0 * m_c * (e11 - dd)));
+    st_stream(a.t22 + c, (T)(-2.0 * m_c * (e22 - dd)));
+    st_stream(a.t33 + c, (T)(-2.0 * m_c * (e33 - dd)));
     const double s12 = 0.5 * ((u_f - u_s) * a.idy + (v_f - v_w) * a.idx);
     const double me = 0.25 * (m_ws + m_s + m_w + m_c);
-    a.t12[c] = -2.0 * me * s12;
-    a.kap[c] = rc * a.alpha + (sgs ? mtc / a.Pr_t : 0.0);
+    st_stream(a.t12 + c, (T)(-2.0 * me * s12));
+    st_stream(a.kap + c, (T)(rc * a.alpha + (sgs ? mtc / a.Pr_t : 0.0)));
 }
 
 // ---------------------------------------------------------------------------
