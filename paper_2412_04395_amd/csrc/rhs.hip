@@ -224,7 +224,12 @@ __device__ __forceinline__ double interp(int order, const double (&q)[7], int o,
     return ord == 6 ? c6 : c6 - s / 60.0 * ((qp2 - qm3) - 5.0 * (qp1 - qm2) + 10.0 * (q0 - qm1));
 }
 
-template <typename T, int OH, int OV>
+// kNear: the domain is at least 3 cells wide and 3 levels high, so that one
+// conditional add or reflection brings any stencil offset (at most 3) back
+// into it; the periodic and reflected indices are then selects instead of
+// branches, and every load of a section can be issued before its arithmetic.
+// kVisc: the viscous and diffusive terms (stress and diffusivity arrays).
+template <typename T, int OH, int OV, bool kNear, bool kVisc>
 __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
 {
     const Dims &d = a.d;
@@ -233,22 +238,38 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
     if (i >= d.nx || j >= d.ny) return;
     const int nz = d.nz, P = d.nxy;
     const int c = cidx(d, i, j, k);
-    // neighbour offset tables: x and y periodic; z reflected (even for centre
-    // and horizontal-face fields, odd with a sign for z-face fields)
-    // (computed where used: cheap integer work instead of 42 registers)
-    auto ox = [&](int t) { return wrap_idx(i + t - 3, d.nx) - i; };
-    auto oy = [&](int t) { return (wrap_idx(j + t - 3, d.ny) - j) * d.nx; };
-    auto ozc = [&](int t) { return (refl_centre(k + t - 3, nz) - k) * P; };
-    auto thz0 = [&](int t) { return kPert<T> ? a.theta0[refl_centre(k + t - 3, nz)] : 0.0; };
+    // neighbour offsets: x and y periodic; z reflected (even for centre and
+    // horizontal-face fields, odd with a sign for z-face fields); computed
+    // where used: cheap integer work instead of 42 registers
+    auto wrap = [&](int v, int n) { return kNear ? v + (v < 0 ? n : 0) - (v >= n ? n : 0) : wrap_idx(v, n); };
+    // (two plain selects each rather than nested conditionals, which the
+    // compiler turns into branches)
+    auto reflc = [&](int kk) {
+        if constexpr (!kNear) return refl_centre(kk, nz);
+        const int r = kk < 0 ? -1 - kk : kk;
+        return r >= nz ? 2 * nz - 1 - r : r;
+    };
+    auto reflf = [&](int kk, double &sg) {
+        if constexpr (!kNear) return refl_face(kk, nz, sg);
+        sg = ((kk < 0) | (kk > nz)) ? -1.0 : 1.0;
+        const int r = kk < 0 ? -kk : kk;
+        return r > nz ? 2 * nz - r : r;
+    };
+    auto ox = [&](int t) { return wrap(i + t - 3, d.nx) - i; };
+    auto oy = [&](int t) { return (wrap(j + t - 3, d.ny) - j) * d.nx; };
+    auto ozc = [&](int t) { return (reflc(k + t - 3) - k) * P; };
+    auto thz0 = [&](int t) { return kPert<T> ? a.theta0[reflc(k + t - 3)] : 0.0; };
     auto ozw = [&](int t) {
         double sg;
-        return (refl_face(k + t - 3, nz, sg) - k) * P;
+        return (reflf(k + t - 3, sg) - k) * P;
     };
     auto szw = [&](int t) {
         double sg;
-        refl_face(k + t - 3, nz, sg);
+        reflf(k + t - 3, sg);
         return sg;
     };
+    // the cell below, clamped at the bottom (its values unused there)
+    const int dn = k > 0 ? P : 0;
     const double idz = a.idz[k];
     const int oh = a.oh, ov = a.ov;
     double q[7];
@@ -274,18 +295,17 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
         const double fz0 = (k == 0) ? 0.0 : W0 * interp<OV>(ov, q, 0, sign_of(W0));
         const double fz1 = (k == nz - 1) ? 0.0 : W1 * interp<OV>(ov, q, 1, sign_of(W1));
         double r = -((fx1 - fx0) * a.idx + (fy1 - fy0) * a.idy + (fz1 - fz0) * idz);
-        if (a.visc) {
+        if constexpr (kVisc) {
             const T *kp = a.kap;
+            const int up = k < nz - 1 ? P : 0;  // the cell above, clamped at the top
             const double kc = kp[c], thc = th0k + th[c];
             const double hx0 = -0.5 * (kp[c + ox(2)] + kc) * (thc - (th0k + th[c + ox(2)])) * a.idx;
             const double hx1 = -0.5 * (kc + kp[c + ox(4)]) * ((th0k + th[c + ox(4)]) - thc) * a.idx;
             const double hy0 = -0.5 * (kp[c + oy(2)] + kc) * (thc - (th0k + th[c + oy(2)])) * a.idy;
             const double hy1 = -0.5 * (kc + kp[c + oy(4)]) * ((th0k + th[c + oy(4)]) - thc) * a.idy;
-            double hz0 = 0.0, hz1 = 0.0;
-            if (k > 0)
-                hz0 = -0.5 * (kp[c - P] + kc) * (thc - (thz0(2) + th[c - P])) * a.idzf[k];
-            if (k < nz - 1)
-                hz1 = -0.5 * (kc + kp[c + P]) * ((thz0(4) + th[c + P]) - thc) * a.idzf[k + 1];
+            const double kb = kp[c - dn], tb = th[c - dn], ka = kp[c + up], ta = th[c + up];
+            const double hz0 = k > 0 ? -0.5 * (kb + kc) * (thc - (thz0(2) + tb)) * a.idzf[k] : 0.0;
+            const double hz1 = k < nz - 1 ? -0.5 * (kc + ka) * ((thz0(4) + ta) - thc) * a.idzf[k + 1] : 0.0;
             r -= (hx1 - hx0) * a.idx + (hy1 - hy0) * a.idy + (hz1 - hz0) * idz;
         }
         if (k == 0 && a.Qs != 0.0) r += rc * a.Qs * idz;
@@ -307,21 +327,16 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
         const double fxy0 = b0 * interp<OH>(oh, q, 0, sign_of(b0)), fxy1 = b1 * interp<OH>(oh, q, 1, sign_of(b1));
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = u[c + ozc(t)];
-        double fxz0 = 0.0, fxz1 = 0.0;
-        if (k > 0) {
-            const double e0 = 0.5 * (a.rw[c + ox(2)] + W0);
-            fxz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0));
-        }
-        if (k < nz - 1) {
-            const double e1 = 0.5 * (a.rw[c + ox(2) + P] + W1);
-            fxz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1));
-        }
+        // z-face momenta (faces 0..nz all exist; the lid fluxes are zero)
+        const double e0 = 0.5 * (a.rw[c + ox(2)] + W0), e1 = 0.5 * (a.rw[c + ox(2) + P] + W1);
+        const double fxz0 = k > 0 ? e0 * interp<OV>(ov, q, 0, sign_of(e0)) : 0.0;
+        const double fxz1 = k < nz - 1 ? e1 * interp<OV>(ov, q, 1, sign_of(e1)) : 0.0;
         const double adv = (fxx_r - fxx_l) * a.idx + (fxy1 - fxy0) * a.idy + (fxz1 - fxz0) * idz;
         const double pgf = (a.pp[c] - a.pp[c + ox(2)]) * a.idx;
         const double rho_f = 0.5 * (full_of(a.rho, c + ox(2), r0k) + rc);
         const double vbar = 0.25 * (Vw + V0 + Vwn + V1);
         double r = -adv - pgf + a.f * (vbar - rho_f * a.Vg);
-        if (a.visc)
+        if constexpr (kVisc)
             r -= (a.t11[c] - a.t11[c + ox(2)]) * a.idx + (a.t12[c + oy(4)] - a.t12[c]) * a.idy +
                  (a.t13[c + P] - a.t13[c]) * idz;
         st_stream(a.Ru + c, (T)r);
@@ -342,32 +357,25 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
         const double fyx0 = a0 * interp<OH>(oh, q, 0, sign_of(a0)), fyx1 = a1 * interp<OH>(oh, q, 1, sign_of(a1));
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = v[c + ozc(t)];
-        double fyz0 = 0.0, fyz1 = 0.0;
-        if (k > 0) {
-            const double e0 = 0.5 * (a.rw[c + oy(2)] + W0);
-            fyz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0));
-        }
-        if (k < nz - 1) {
-            const double e1 = 0.5 * (a.rw[c + oy(2) + P] + W1);
-            fyz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1));
-        }
+        const double e0 = 0.5 * (a.rw[c + oy(2)] + W0), e1 = 0.5 * (a.rw[c + oy(2) + P] + W1);
+        const double fyz0 = k > 0 ? e0 * interp<OV>(ov, q, 0, sign_of(e0)) : 0.0;
+        const double fyz1 = k < nz - 1 ? e1 * interp<OV>(ov, q, 1, sign_of(e1)) : 0.0;
         const double adv = (fyx1 - fyx0) * a.idx + (fyy_r - fyy_l) * a.idy + (fyz1 - fyz0) * idz;
         const double pgf = (a.pp[c] - a.pp[c + oy(2)]) * a.idy;
         const double rho_f = 0.5 * (full_of(a.rho, c + oy(2), r0k) + rc);
         const double ubar = 0.25 * (Us + Use + U0 + U1);
         double r = -adv - pgf - a.f * (ubar - rho_f * a.Ug);
-        if (a.visc)
+        if constexpr (kVisc)
             r -= (a.t12[c + ox(4)] - a.t12[c]) * a.idx + (a.t22[c] - a.t22[c + oy(2)]) * a.idy +
                  (a.t23[c + P] - a.t23[c]) * idz;
         st_stream(a.Rv + c, (T)r);
     }
 
     // ---------------- z-momentum on z-face (i, j, k) ----------------
-    if (k == 0) {
-        a.Rw[c] = 0.0;
-        a.Rw[c + nz * P] = 0.0;
-    } else {
-        const int cm = c - P;
+    // the lid faces carry W = 0: the bottom face's tendency is computed from
+    // clamped (in-range) indices and stored as zero
+    {
+        const int cm = c - dn;
         const double idzf = a.idzf[k];
         const double a0 = 0.5 * (a.ru[cm] + U0), a1 = 0.5 * (a.ru[cm + ox(4)] + U1);
         const T *w = a.w;
@@ -385,18 +393,37 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
         const double adv = (fzx1 - fzx0) * a.idx + (fzy1 - fzy0) * a.idy + (fzz_u - fzz_d) * idzf;
         const double pgf = (a.pp[c] - a.pp[cm]) * idzf;
         // buoyancy B = -(rho - rho0) g on the face; heavier air sinks
-        const double buoy = -a.g * 0.5 * (pert_of(a.rho, c, r0k) + pert_of(a.rho, cm, a.rho0[k - 1]));
+        const double buoy = -a.g * 0.5 * (pert_of(a.rho, c, r0k) + pert_of(a.rho, cm, a.rho0[k > 0 ? k - 1 : 0]));
         double r = -adv - pgf + buoy;
-        if (a.visc)
+        if constexpr (kVisc)
             r -= (a.t13[c + ox(4)] - a.t13[c]) * a.idx + (a.t23[c + oy(4)] - a.t23[c]) * a.idy +
                  (a.t33[c] - a.t33[cm]) * idzf;
-        st_stream(a.Rw + c, (T)r);
+        st_stream(a.Rw + c, (T)(k > 0 ? r : 0.0));
+        if (k == 0) a.Rw[c + nz * P] = 0.0;
     }
 }
 
 }  // namespace
 
 namespace {
+// orders 2, 3 and 5 in both directions have their own instances; any other
+// combination, and domains narrower than the stencil, take the general one
+template <typename T, bool kVisc>
+void launch_rhs(const RhsArgs<T> &a, dim3 grd, dim3 blk, hipStream_t st)
+{
+    const bool near = a.d.nx >= 3 && a.d.ny >= 3 && a.d.nz >= 3;
+    if (near && a.oh == 5 && a.ov == 5)
+        hipLaunchKernelGGL((k_rhs<T, 5, 5, true, kVisc>), grd, blk, 0, st, a);
+    else if (near && a.oh == 3 && a.ov == 3)
+        hipLaunchKernelGGL((k_rhs<T, 3, 3, true, kVisc>), grd, blk, 0, st, a);
+    else if (near && a.oh == 2 && a.ov == 2)
+        hipLaunchKernelGGL((k_rhs<T, 2, 2, true, kVisc>), grd, blk, 0, st, a);
+    else if (near)
+        hipLaunchKernelGGL((k_rhs<T, 0, 0, true, kVisc>), grd, blk, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_rhs<T, 0, 0, false, kVisc>), grd, blk, 0, st, a);
+}
+
 template <typename T>
 hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5], bool prep_only)
 {
@@ -463,14 +490,10 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5], boo
     if (a.sgs) { timing_start(cx, K_MUT); hipLaunchKernelGGL(k_mut<T>, grd, blk, 0, cx->stream, a); timing_stop(cx, K_MUT); }
     if (a.visc) { timing_start(cx, K_STRESS); hipLaunchKernelGGL(k_stress<T>, grdw, blk, 0, cx->stream, a); timing_stop(cx, K_STRESS); }
     timing_start(cx, K_RHS);
-    if (a.oh == 5 && a.ov == 5)
-        hipLaunchKernelGGL((k_rhs<T, 5, 5>), grd, blk, 0, cx->stream, a);
-    else if (a.oh == 3 && a.ov == 3)
-        hipLaunchKernelGGL((k_rhs<T, 3, 3>), grd, blk, 0, cx->stream, a);
-    else if (a.oh == 2 && a.ov == 2)
-        hipLaunchKernelGGL((k_rhs<T, 2, 2>), grd, blk, 0, cx->stream, a);
+    if (a.visc)
+        launch_rhs<T, true>(a, grd, blk, cx->stream);
     else
-        hipLaunchKernelGGL((k_rhs<T, 0, 0>), grd, blk, 0, cx->stream, a);
+        launch_rhs<T, false>(a, grd, blk, cx->stream);
     timing_stop(cx, K_RHS);
     if (mlp) {
         hipError_t e = hipGetLastError();
