@@ -162,24 +162,68 @@ __device__ __forceinline__ floatx4 mlp16(const WaveWeights &W, const float *bias
     return mfma(W[21], b1, mfma(W[20], b0, bias4(bias + 192, g)));
 }
 
+// Two 16-sample groups at once: every weight operand read from LDS serves
+// both groups' products (half the LDS weight traffic of one group at a time),
+// and the two groups' products are independent, so they fill each other's
+// pipeline gaps.  Each group's arithmetic is exactly mlp16's.
+__device__ __forceinline__ void mlp32(const WaveWeights &W, const float *bias, bf16x8 x0, bf16x8 x1, int g,
+                                      floatx4 &y0, floatx4 &y1)
+{
+    floatx4 h[4], k[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const bf16x8 w = W[t];
+        const floatx4 c = bias4(bias + 16 * t, g);
+        h[t] = mfma(w, x0, c);
+        k[t] = mfma(w, x1, c);
+    }
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+        const int ob = 4 + 8 * layer, bb = 64 + 64 * layer;
+        const bf16x8 a0 = relu_pack(h[0], h[1]), a1 = relu_pack(h[2], h[3]);
+        const bf16x8 c0 = relu_pack(k[0], k[1]), c1 = relu_pack(k[2], k[3]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const floatx4 c = bias4(bias + bb + 16 * t, g);
+            const bf16x8 w0 = W[ob + 2 * t];
+            h[t] = mfma(w0, a0, c);
+            k[t] = mfma(w0, c0, c);
+            const bf16x8 w1 = W[ob + 2 * t + 1];
+            h[t] = mfma(w1, a1, h[t]);
+            k[t] = mfma(w1, c1, k[t]);
+        }
+    }
+    const bf16x8 a0 = relu_pack(h[0], h[1]), a1 = relu_pack(h[2], h[3]);
+    const bf16x8 c0 = relu_pack(k[0], k[1]), c1 = relu_pack(k[2], k[3]);
+    const floatx4 c = bias4(bias + 192, g);
+    const bf16x8 w0 = W[20], w1 = W[21];
+    y0 = mfma(w1, a1, mfma(w0, a0, c));
+    y1 = mfma(w1, c1, mfma(w0, c0, c));
+}
+
 // xs/ys are this wave's LDS rows; the caller synchronises around the call
 __device__ __forceinline__ void mlp64(const WaveWeights &W, const float *bias, const u32x4 *xs, float *ys, int lane)
 {
     const int g = lane >> 4, col = lane & 15;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int row = 16 * q + col;
+    for (int q = 0; q < 4; q += 2) {
+        const int row0 = 16 * q + col, row1 = row0 + 16;
         const u32x4 zero = {0u, 0u, 0u, 0u};
-        const bf16x8 x = as_bf16x8(g < 2 ? xs[2 * row + g] : zero);
-        // an index the compiler cannot prove equal across groups: every
-        // operand is read from LDS right before its one product instead of
-        // being held in 88 registers for the whole loop
+        const bf16x8 x0 = as_bf16x8(g < 2 ? xs[2 * row0 + g] : zero);
+        const bf16x8 x1 = as_bf16x8(g < 2 ? xs[2 * row1 + g] : zero);
+        // an index the compiler cannot prove equal across pairs: every operand
+        // is read from LDS right before its two products instead of being held
+        // in 88 registers for the whole loop
         int ln = W.lane;
         asm volatile("" : "+v"(ln));
-        const floatx4 y = mlp16(WaveWeights{W.w, ln}, bias, x, g);
+        floatx4 y0, y1;
+        mlp32(WaveWeights{W.w, ln}, bias, x0, x1, g, y0, y1);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            if (4 * g + r < kMlpOut) ys[row * 12 + 4 * g + r] = y[r];
+            if (4 * g + r < kMlpOut) {
+                ys[row0 * 12 + 4 * g + r] = y0[r];
+                ys[row1 * 12 + 4 * g + r] = y1[r];
+            }
     }
 }
 
