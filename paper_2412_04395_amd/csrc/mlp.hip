@@ -384,12 +384,13 @@ __global__ __launch_bounds__(kClosureBlock, 4) void k_mlp_closure(ClosureArgs<T>
     for (int64_t base = (int64_t)blockIdx.x * kClosureBlock + wave * 64; base < d.n; base += stride) {
         const int c = (int)base + lane;
         const bool valid = c < d.n;
-        double f[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, dthx = 0.0, dthy = 0.0;
+        double f[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, dthx = 0.0, dthy = 0.0, r = 0.0;
         int k = 0;
         if (valid) {
             k = c / d.nxy;
             const int rem = c - k * d.nxy, j = rem / d.nx, i = rem - j * d.nx;
             closure_inputs(a.in, i, j, k, f, dthx, dthy);
+            r = full_of(a.rho, c, a.rho0[k]);  // with the gather: no second round trip after the network
         }
         float x[10];
 #pragma unroll
@@ -427,9 +428,9 @@ __global__ __launch_bounds__(kClosureBlock, 4) void k_mlp_closure(ClosureArgs<T>
                 t[7] = -(nut * a.iPr_t) * dthy;
                 t[8] = -(nut * a.iPr_t) * f[9];
             }
-            const double r = full_of(a.rho, c, a.rho0[k]);
+            // read by the divergence kernel only: streaming stores
 #pragma unroll
-            for (int o = 0; o < 9; ++o) a.out[o][c] = (T)(r * t[o]);
+            for (int o = 0; o < 9; ++o) st_stream(a.out[o] + c, (T)(r * t[o]));
         }
         nfb += (unsigned int)__popcll(__ballot(fb));
         // the next chunk rewrites this wave's rows only after it read them
