@@ -105,6 +105,37 @@ typedef struct {
 
 typedef struct erf_ctx erf_ctx;
 
+/* Fields of a state, for erf_layout. */
+typedef enum {
+    ERF_FIELD_RHO = 0,
+    ERF_FIELD_RHOTHETA = 1,
+    ERF_FIELD_RHOU = 2,
+    ERF_FIELD_RHOV = 3,
+    ERF_FIELD_RHOW = 4,
+    ERF_FIELD_RHOQ = 5
+} erf_field;
+
+/* Memory layout of one state field (the C-grid of Sec. 3.4 as stored). */
+typedef struct {
+    int32_t nx, ny, nz;      /* extent in x, y and levels (nz + 1 for rhow)        */
+    int32_t components;      /* n_scalars for rhoq (may be 0), else 1              */
+    int64_t stride_y;        /* elements between rows (x stride is 1)              */
+    int64_t stride_z;        /* elements between levels                            */
+    int64_t stride_c;        /* elements between rhoq components                   */
+    int64_t count;           /* elements in the field                              */
+    int64_t bytes;           /* count * elem_bytes                                 */
+    int32_t elem_bytes;      /* 8 (ERF_FP64) or 4 (ERF_FP32_MIXED)                 */
+    int32_t perturbation;    /* 1: stored as the departure from the base state     */
+} erf_field_layout;
+
+/* Result of erf_autotune. */
+typedef struct {
+    int32_t levels_per_wave; /* acoustic substep: levels per wavefront (8 or 16)   */
+    int32_t tile_rows;       /* acoustic substep: 64 columns as 1, 2 or 4 rows     */
+    double ms_per_step;      /* measured RK3 step time of the choice [ms]          */
+    int32_t from_cache;      /* 1: read from the cache file, nothing was timed     */
+} erf_tuning;
+
 /* Hydrostatic base state on the host, no GPU involved (Sec. 2, Sec. 3.8):
  * dp0/dz = -rho0 g discretised between level centres with the trapezoidal
  * density, p0 = EOS(rho0 theta0) (Sec. 2.1), solved level by level with
@@ -113,6 +144,13 @@ typedef struct erf_ctx erf_ctx;
 erf_status erf_base_state_host(int32_t nz, const double *dz, const double *theta0,
                                double p_surface, double grav, double *rho0, double *p0,
                                double *pi0);
+
+/* Layout of state field `field` (erf_field) for a grid and parameter set, as
+ * every call of this library reads and writes it (see the conventions above):
+ * the caller sizes its buffers from it.  Host only; ERF_E_ARG for an unknown
+ * field or NULL pointers, ERF_E_SHAPE / ERF_E_ARG for a grid or parameter set
+ * that erf_create would refuse on its sizes, precision or scalar count. */
+erf_status erf_layout(const erf_grid *grid, const erf_params *params, int32_t field, erf_field_layout *out);
 
 /* Create a context for one grid and one parameter set.  hip_stream is a
  * hipStream_t (NULL: the default stream).  The grid's dz array is copied.
@@ -167,6 +205,20 @@ erf_status erf_rk3_step(erf_ctx *ctx, erf_state *S);
  * non-finite values.  Synchronous.  Returns ERF_E_NONFINITE (with *out filled)
  * if any state value is NaN or Inf. */
 erf_status erf_diagnostics(erf_ctx *ctx, const erf_state *S, erf_diag *out);
+
+/* Choose the launch shape of the acoustic substep kernel (App. C: the
+ * vertically implicit solve over whole columns) for this context by timing:
+ * levels per wavefront 8 (nz <= 128) or 16, and the 64 columns of a workgroup
+ * as 1, 2 or 4 rows.  Every candidate runs one untimed and then `trials` timed
+ * erf_rk3_step calls on S, which therefore advances; the fastest is kept for
+ * the context's later calls.  Results do not depend on the row shape; the
+ * level count changes the rounding of the chunked tridiagonal sweeps only.
+ * cache_path (may be NULL): a text file of earlier choices, one line per grid
+ * size and precision; a matching line is applied without timing
+ * (out->from_cache = 1), otherwise the choice is appended to it (ERF_E_ARG if
+ * the file cannot be written; the choice is applied all the same).
+ * Synchronous.  out may be NULL. */
+erf_status erf_autotune(erf_ctx *ctx, erf_state *S, int32_t trials, const char *cache_path, erf_tuning *out);
 
 /* Kernel timing for measurement.  While enabled, every launch of the named
  * kernel is bracketed by two HIP events recorded on the context's stream; up to

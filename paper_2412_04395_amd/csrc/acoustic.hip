@@ -523,11 +523,12 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
     // tile shape: 64 columns, one row of 64 where rows are that long (measured
     // 1.3 % faster than 16 x 4 at 256 x 256), else up to four shorter rows
     a.TY = d.nx >= 64 ? 1 : (d.ny >= 4 ? 4 : (d.ny >= 2 ? 2 : 1));
+    if (cx->tune_rows > 0) a.TY = cx->tune_rows;  // erf_autotune's choice
     a.TX = kLanes / a.TY;
     a.ntx = (d.nx + a.TX - 1) / a.TX;
     a.nty = (d.ny + a.TY - 1) / a.TY;
     // 8 levels per wavefront up to nz = 128 (registers without spills), 16 above
-    const int L = d.nz <= 128 ? 8 : 16;
+    const int L = cx->tune_levels > 0 ? cx->tune_levels : (d.nz <= 128 ? 8 : 16);
     const int KG = (d.nz + L - 1) / L;
     if (KG > 16) return hipErrorInvalidValue;  // nz <= 256
     const size_t lds = sizeof(double) * ((size_t)(d.nz + 1) * kLanes + 2 * (size_t)KG * kLanes +

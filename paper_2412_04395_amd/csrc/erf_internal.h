@@ -260,6 +260,8 @@ struct erf_ctx {
     int64_t ws_bytes = 0;
     int device = 0;
     void *arena = nullptr;  // the single device allocation behind the workspace
+    // acoustic substep launch shape chosen by erf_autotune (0: the default rule)
+    int tune_levels = 0, tune_rows = 0;
     // kernel timing (erf_timing_begin / erf_timing_end)
     int timed_kernel = -1;
     int timed_count = 0;

@@ -29,10 +29,10 @@ ERF_FP64, ERF_FP32_MIXED = 0, 1
 ERF_SGS_NONE, ERF_SGS_SMAGORINSKY, ERF_SGS_MLP = 0, 1, 2
 MLP_NPARAMS, MLP_NNORM = 9609, 38
 
-# every symbol include/erf.h and include/erf_mlp.h declare
+# every symbol include/erf.h, include/erf_mlp.h and include/erf_ensemble.h declare
 EXPORTS = ("erf_base_state_host", "erf_create", "erf_destroy", "erf_last_error", "erf_workspace_bytes",
            "erf_init_base_state", "erf_slow_rhs", "erf_acoustic_substeps", "erf_scalar_advance",
-           "erf_rk3_step", "erf_diagnostics", "erf_timing_begin", "erf_timing_end",
+           "erf_rk3_step", "erf_diagnostics", "erf_timing_begin", "erf_timing_end", "erf_layout", "erf_autotune",
            "erf_mlp_set_weights", "erf_mlp_get_weights", "erf_mlp_forward", "erf_mlp_features",
            "erf_box_filter", "erf_mlp_fit_norm", "erf_mlp_standardize", "erf_mlp_loss_grad",
            "erf_mlp_train_step", "erf_mlp_fallback_count",
@@ -65,6 +65,21 @@ class Params(C.Structure):
 class State(C.Structure):
     _fields_ = [("rho", C.c_void_p), ("rhotheta", C.c_void_p), ("rhou", C.c_void_p),
                 ("rhov", C.c_void_p), ("rhow", C.c_void_p), ("rhoq", C.c_void_p)]
+
+
+class FieldLayout(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("components", C.c_int32),
+                ("stride_y", C.c_int64), ("stride_z", C.c_int64), ("stride_c", C.c_int64), ("count", C.c_int64),
+                ("bytes", C.c_int64), ("elem_bytes", C.c_int32), ("perturbation", C.c_int32)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("levels_per_wave", C.c_int32), ("tile_rows", C.c_int32), ("ms_per_step", C.c_double),
+                ("from_cache", C.c_int32)]
+
+
+# erf_field ids, in the order of the state dictionaries' keys
+FIELD_IDS = {"rho": 0, "rt": 1, "ru": 2, "rv": 3, "rw": 4, "rq": 5}
 
 
 class Diag(C.Structure):
@@ -106,6 +121,8 @@ def load(path: str = LIB_PATH):
             L.erf_diagnostics.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(Diag)]
             L.erf_timing_begin.argtypes = [C.c_void_p, C.c_char_p, C.c_int32]
             L.erf_timing_end.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+            L.erf_layout.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int32, C.POINTER(FieldLayout)]
+            L.erf_autotune.argtypes = [C.c_void_p, C.POINTER(State), C.c_int32, C.c_char_p, C.POINTER(Tuning)]
             _FP = C.POINTER(C.c_float)
             L.erf_mlp_set_weights.argtypes = [C.c_void_p, _FP, _DP]
             L.erf_mlp_get_weights.argtypes = [C.c_void_p, _FP, _DP]
@@ -164,6 +181,19 @@ def params_from_config(cfg) -> Params:
     return Params(cfg.dt, cfg.n_substeps, cfg.beta_s, cfg.beta_d, cfg.adv_order_h, cfg.adv_order_v,
                   cfg.scalar_scheme, cfg.n_scalars, cfg.sgs, cfg.Cs, cfg.Pr_t, cfg.nu_m, cfg.alpha_m,
                   cfg.f_cor, cfg.Ug, cfg.Vg, cfg.surf_heat_flux, cfg.grav, prec)
+
+
+def layout(cfg, field: str) -> dict:
+    """Layout of one state field ("rho", "rt", "ru", "rv", "rw" or "rq") as the
+    library stores it (erf_layout; host only, no GPU needed)."""
+    L = load()
+    dz = np.ascontiguousarray(cfg.dz, dtype=np.float64)
+    grid = Grid(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, _np_ptr(dz))
+    out = FieldLayout()
+    st = L.erf_layout(C.byref(grid), C.byref(params_from_config(cfg)), FIELD_IDS[field], C.byref(out))
+    if st != ERF_OK:
+        raise ErfError(st, f"erf_layout({field})")
+    return {name: getattr(out, name) for name, _ in FieldLayout._fields_}
 
 
 class Solver:
@@ -228,9 +258,13 @@ class Solver:
 
     # -- states ----------------------------------------------------------------
     def shapes(self):
-        c = self.cfg
-        return {"rho": (c.nz, c.ny, c.nx), "rt": (c.nz, c.ny, c.nx), "ru": (c.nz, c.ny, c.nx),
-                "rv": (c.nz, c.ny, c.nx), "rw": (c.nz + 1, c.ny, c.nx), "rq": (c.n_scalars, c.nz, c.ny, c.nx)}
+        """Tensor shapes of the state fields, from the library's erf_layout."""
+        out = {}
+        for f in FIELDS:
+            lay = layout(self.cfg, f)
+            shape = (lay["nz"], lay["ny"], lay["nx"])
+            out[f] = (lay["components"],) + shape if f == "rq" else shape
+        return out
 
     def empty_state(self):
         t = self.torch
@@ -309,6 +343,15 @@ class Solver:
     def rk3_step(self, S):
         self._check(self.L.erf_rk3_step(self.h, C.byref(self._st(S))), "erf_rk3_step")
         return S
+
+    def autotune(self, S, trials: int = 3, cache_path: str | None = None) -> dict:
+        """erf_autotune: time the acoustic substep's launch shapes on S (which
+        advances) or read the choice from cache_path; returns the choice."""
+        out = Tuning()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(self.L.erf_autotune(self.h, C.byref(self._st(S)), int(trials), path, C.byref(out)),
+                    "erf_autotune")
+        return {name: getattr(out, name) for name, _ in Tuning._fields_}
 
     def timing_begin(self, kernel: str, max_launches: int = 4096):
         self._check(self.L.erf_timing_begin(self.h, kernel.encode(), int(max_launches)), "erf_timing_begin")

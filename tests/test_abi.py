@@ -95,3 +95,50 @@ def test_product_path_has_no_oracle_dependency():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "erf_oracle" not in text, f
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_layout_matches_the_state_conventions(prec):
+    """erf_layout restates the conventions of include/erf.h: x fastest, nz + 1
+    z-faces for rho w, n_scalars components of rho q, 8- or 4-byte elements,
+    and in FP32 storage rho and rho*theta held as perturbations."""
+    cfg = W.small(nx=13, ny=7, nz=5, dz=W.uniform_dz(5, 100.0), n_scalars=3, prec=prec)
+    eb = 8 if prec == "fp64" else 4
+    for f in erf.FIELDS:
+        lay = erf.layout(cfg, f)
+        nz = cfg.nz + 1 if f == "rw" else cfg.nz
+        comps = 3 if f == "rq" else 1
+        assert (lay["nx"], lay["ny"], lay["nz"], lay["components"]) == (13, 7, nz, comps), f
+        assert (lay["stride_y"], lay["stride_z"], lay["stride_c"]) == (13, 13 * 7, 13 * 7 * nz), f
+        assert lay["count"] == 13 * 7 * nz * comps and lay["bytes"] == lay["count"] * eb, f
+        assert lay["elem_bytes"] == eb
+        assert lay["perturbation"] == (1 if prec == "fp32" and f in ("rho", "rt") else 0), f
+    # no scalars: an empty rho q
+    lay = erf.layout(W.small(prec=prec), "rq")
+    assert lay["components"] == 0 and lay["count"] == 0 and lay["bytes"] == 0
+
+
+def test_layout_rejects_what_create_rejects():
+    L = erf.load()
+    cfg = W.small()
+    out = erf.FieldLayout()
+
+    def call(nz=None, field=0, **prm):
+        c = W.small(**prm) if prm else cfg
+        dz = np.ascontiguousarray(c.dz if nz is None else np.full(nz, 100.0), dtype=np.float64)
+        g = erf.Grid(c.nx, c.ny, len(dz), c.dx, c.dy, dz.ctypes.data_as(C.POINTER(C.c_double)))
+        return L.erf_layout(C.byref(g), C.byref(erf.params_from_config(c)), field, C.byref(out))
+
+    assert call() == erf.ERF_OK
+    assert call(field=6) == erf.ERF_E_ARG
+    assert call(field=-1) == erf.ERF_E_ARG
+    assert call(nz=1) == erf.ERF_E_SHAPE
+    assert call(nz=257) == erf.ERF_E_SHAPE
+    assert call(n_scalars=9) == erf.ERF_E_ARG
+    p = erf.params_from_config(cfg)
+    p.precision = 7
+    dz = np.ascontiguousarray(cfg.dz, dtype=np.float64)
+    g = erf.Grid(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, dz.ctypes.data_as(C.POINTER(C.c_double)))
+    assert L.erf_layout(C.byref(g), C.byref(p), 0, C.byref(out)) == erf.ERF_E_ARG
+    assert L.erf_layout(None, C.byref(p), 0, C.byref(out)) == erf.ERF_E_ARG
+    assert L.erf_layout(C.byref(g), C.byref(erf.params_from_config(cfg)), 0, None) == erf.ERF_E_ARG
