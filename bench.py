@@ -124,6 +124,7 @@ def run_gpu(cfg: W.Config, steps: int, warmup: int):
     S = s.from_full(W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"]))
     for _ in range(warmup):
         s.rk3_step(S)
+    tune = s.autotune(S, trials=2, cache_path=TUNE_CACHE)
     # find the kernel with the largest share of a step (one short timed step per kernel)
     shares = {}
     for k in KERNEL_VALUES:
@@ -136,10 +137,15 @@ def run_gpu(cfg: W.Config, steps: int, warmup: int):
     el, (kms, kn) = _time_steps(s, S, steps, torch, kernel=dominant)
     d = s.diagnostics(S, allow_nonfinite=True)
     s.close()
+    d["substep_shape"] = {"levels_per_wave": tune["levels_per_wave"], "tile_rows": tune["tile_rows"],
+                          "from_cache": bool(tune["from_cache"])}
     return el, dominant, kms, kn, shares, d
 
 
 WEIGHTS = os.path.join(ROOT, "paper_2412_04395_amd", "data", "closure_les40m.npz")
+# launch shapes of the acoustic substep chosen by erf_autotune on MI355X, one
+# line per grid size and precision; a missing line is tuned and appended
+TUNE_CACHE = os.path.join(ROOT, "paper_2412_04395_amd", "data", "substep_shapes.txt")
 
 
 def closure_weights(solver, S, seed: int):
@@ -183,6 +189,7 @@ def run_closure(steps: int, warmup: int):
     weights = closure_weights(s, S, cfg.seed)
     for _ in range(warmup):
         s.rk3_step(S)
+    tune = s.autotune(S, trials=2, cache_path=TUNE_CACHE)
     shares = {}
     for k in ("mlp", "mlp_div", "rhs", "substep"):
         _, (ms, n) = _time_steps(s, S, 1, torch, kernel=k)
@@ -196,7 +203,9 @@ def run_closure(steps: int, warmup: int):
     flops = MLP_FLOP_PER_CELL * cfg.cells
     achieved = flops / (avg_ms * 1e-3) / 1e12
     return {"workload": cfg.name, "grid": [cfg.nx, cfg.ny, cfg.nz], "precision": "FP32 storage, BF16 network",
-            "weights": weights,
+            "weights": weights, "substep_shape": {"levels_per_wave": tune["levels_per_wave"],
+                                                  "tile_rows": tune["tile_rows"],
+                                                  "from_cache": bool(tune["from_cache"])},
             "value": cfg.cells * steps / el, "unit": "cell-updates/s", "ms_per_step": 1e3 * el / steps,
             "kernel_ms_per_step": shares, "fallback_fraction": fb / (3 * steps * cfg.cells),
             "final_diag": {"max_w": d["max_w"], "nonfinite": d["nonfinite"]},
@@ -328,7 +337,8 @@ def main(argv=None):
         "vs_baseline": None, "dtype": "f64" if cfg.prec == "fp64" else "f32", "data": "synthetic",
         "config": {"workload": cfg.name, "grid": [cfg.nx, cfg.ny, cfg.nz], "cells": cfg.cells,
                    "dt": cfg.dt, "n_substeps": cfg.n_substeps, "adv_order": [cfg.adv_order_h, cfg.adv_order_v],
-                   "sgs": "smagorinsky" if cfg.sgs else "none", "precision": cfg.prec},
+                   "sgs": "smagorinsky" if cfg.sgs else "none", "precision": cfg.prec,
+                   "substep_shape": diag["substep_shape"]},
         "roofline": roof,
         "kernel_ms_per_step": {k: round(v[0], 4) for k, v in shares.items()},
         "final_diag": {"max_w": diag["max_w"], "nonfinite": diag["nonfinite"]},
@@ -341,10 +351,11 @@ def main(argv=None):
                             "CFL); timed for throughput only"}
     if a.workload == "cbl" and not a.no_fp32:
         c3 = _cfg("cbl_fp32")
-        el3, dom3, kms3, kn3, shares3, _ = run_gpu(c3, a.steps, a.warmup)
+        el3, dom3, kms3, kn3, shares3, diag3 = run_gpu(c3, a.steps, a.warmup)
         out["fp32"] = {"workload": c3.name, "precision": "FP32 storage, FP64 arithmetic, solve and sums",
                        "value": c3.cells * a.steps / el3, "ms_per_step": 1e3 * el3 / a.steps,
                        "speedup_vs_fp64": el / el3, "roofline": _roofline(c3, dom3, kms3, kn3),
+                       "substep_shape": diag3["substep_shape"],
                        "kernel_ms_per_step": {k: round(v[0], 4) for k, v in shares3.items()}}
     if a.workload == "cbl" and not a.no_closure:
         out["closure"] = run_closure(a.steps, a.warmup)
