@@ -127,6 +127,11 @@ CASES = {
                                           220.0]), adv_order_h=3, adv_order_v=5, sgs=1, Cs=0.15),
     "two_d": dict(name="bubble2d", nx=70, ny=1, nz=24, dz=W.uniform_dz(24, 125.0), dx=125.0),
     "tall": dict(nx=9, ny=6, nz=140, dz=W.uniform_dz(140, 50.0), adv_order_h=3, adv_order_v=3),
+    # edge sizes: the fewest levels, the most levels a substep block holds, and
+    # a single column (every horizontal neighbour is the cell itself)
+    "min_nz": dict(nz=2, dz=W.uniform_dz(2, 100.0), sgs=1, Cs=0.15),
+    "max_nz": dict(nx=5, ny=4, nz=256, dz=W.uniform_dz(256, 20.0), adv_order_h=3, adv_order_v=3),
+    "one_column": dict(nx=1, ny=1, nz=16, dz=W.uniform_dz(16, 100.0), adv_order_h=5, adv_order_v=5),
 }
 
 
@@ -142,7 +147,8 @@ def test_slow_rhs_parity(case):
 
 
 @pytest.mark.parametrize("case,nsub", [("small_o53", 1), ("small_o53", 3), ("stretched", 4), ("two_d", 3),
-                                       ("smag_cor_flux", 2), ("tall", 3)])
+                                       ("smag_cor_flux", 2), ("tall", 3), ("min_nz", 3), ("max_nz", 3),
+                                       ("one_column", 3)])
 def test_acoustic_substeps_parity(case, nsub):
     cfg = W.small(**CASES[case])
     _say("acoustic", case, nsub)
