@@ -314,7 +314,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU layout is a design "
-              f"in DESIGN.md, not a measured path", file=sys.stderr)
+              f"of the library, not a measured path", file=sys.stderr)
         return 2
     rank = int(os.environ.get("RANK", "0"))
 
