@@ -58,6 +58,8 @@ KERNEL_VALUES = {
     # tendencies, theta^t, Exner and the buoyancy coefficient read, the three
     # Thomas factors read; Theta'', U'', V'', rho'', W'' written
     "substep": lambda sgs: (14 + 5, 3),
+    # (the last substep of a stage, without scalars, also reads S^t and writes
+    # S_out in place of S'': 5 more bulk values, see _substep_bytes)
     # S^n, S^t read; theta^t, Exner, Theta'', rho'', U'', V'', W'' written
     "stage_init": lambda sgs: (10 + 7, 0),
     # Exner, theta^t, Theta^t read; buoyancy coefficient and three factors written
@@ -286,10 +288,19 @@ def cpu_baseline(cfg: W.Config, target_s: float = 12.0):
                       f"{el:.1f} s"}
 
 
+def _substep_extra_share(cfg) -> float:
+    """Fraction of substep launches that also write the stage end (one per
+    stage; none with scalars, whose flux sums keep a separate finalize)."""
+    ns = cfg.n_substeps
+    return 0.0 if cfg.n_scalars else 3.0 / (1 + ns // 2 + ns)
+
+
 def _roofline(cfg, dom, kms, kn):
     sgs = 1 if cfg.sgs else 0
     avg_ms = kms / max(kn, 1)
     bytes_per_launch = _kernel_bytes(dom, sgs, cfg.prec) * cfg.cells
+    if dom == "substep":  # averaged over the timed launches
+        bytes_per_launch += _substep_extra_share(cfg) * 5 * (8.0 if cfg.prec == "fp64" else 4.0) * cfg.cells
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic, tsrc = _profiled_traffic(dom) if cfg.prec == "fp64" and "stable" in cfg.name else (None, None)
     return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

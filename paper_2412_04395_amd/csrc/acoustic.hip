@@ -58,6 +58,8 @@ struct StageArgs {
     double *calpha, *cm, *cc;
     // tiles
     int TX, TY, ntx, nty;
+    // stage end S^t + S'' (written by the last substep when no flux sums are kept)
+    T *o_r, *o_t, *o_u, *o_v, *o_w;
 };
 
 template <typename T>
@@ -163,9 +165,9 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
 // flight.  The pointers are restrict: the arrays
 // written here (U'', V'' of the next level, their sums) are never read here,
 // so the loads of later levels may be issued ahead of earlier stores.
-template <typename T, int kLevels>
+template <typename T, int kLevels, bool kLast>
 __device__ __forceinline__ void substep_explicit(
-    const T *__restrict__ T2cur, const T *__restrict__ T2prv, const T *__restrict__ pit, const T *__restrict__ tht,
+    const T *__restrict__ t_u, const T *__restrict__ t_v, const T *__restrict__ T2cur, const T *__restrict__ T2prv, const T *__restrict__ pit, const T *__restrict__ tht,
     const T *__restrict__ u2in, const T *__restrict__ v2in, const T *__restrict__ R_u, const T *__restrict__ R_v,
     const T *__restrict__ R_t, const T *__restrict__ R_r, const T *__restrict__ R_w, const T *__restrict__ w2,
     const T *__restrict__ r2, const T *__restrict__ cC, const double *__restrict__ idz_t,
@@ -202,8 +204,15 @@ __device__ __forceinline__ void substep_explicit(
                 const double Vs = v2in[c] + dt * (-gRd * (0.5 * (ps + pc)) * (ttc - tts) * idy + R_v[c]);
                 const double Vn =
                     v2in[c + o_n] + dt * (-gRd * (0.5 * (pc + pn)) * (ttn - ttc) * idy + R_v[c + o_n]);
-                st_stream(u2out + c, (T)Uw);
-                st_stream(v2out + c, (T)Vs);
+                if constexpr (kLast) {
+                    // the stage's last substep writes S^t + S'' (u2out, v2out
+                    // point to the stage-end momenta; S'' rounded as if stored)
+                    st_stream(u2out + c, (T)((double)ld_stream(t_u + c) + (double)(T)Uw));
+                    st_stream(v2out + c, (T)((double)ld_stream(t_v + c) + (double)(T)Vs));
+                } else {
+                    st_stream(u2out + c, (T)Uw);
+                    st_stream(v2out + c, (T)Vs);
+                }
                 // explicit parts of Theta'' and rho''
                 const double thc = tht[c];
                 const double thx0 = 0.5 * (tht[c + o_w] + thc), thx1 = 0.5 * (thc + tht[c + o_e]);
@@ -247,7 +256,7 @@ __device__ __forceinline__ void substep_explicit(
                     bnd[(g * 2 + 1) * kLanes + lane] = f;
                 }
                 // running sums last, so that no branch separates this level's loads
-                if (sums) {
+                if (!kLast && sums) {
                     su[c] += Uw;
                     sv[c] += Vs;
                 }
@@ -259,7 +268,7 @@ __device__ __forceinline__ void substep_explicit(
 // One fused acoustic substep.  blockDim = (64, KG), kLevels levels per
 // wavefront; dynamic LDS holds the (nz + 1) x 64 solve buffer and the
 // chunk-boundary values.
-template <typename T, int kLevels>
+template <typename T, int kLevels, bool kLast>
 __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
 {
     extern __shared__ double lds[];
@@ -290,7 +299,7 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
     double e_first = 0.0, f_first = 0.0;
 
     // ---------------- phase 1: explicit work, W'' right-hand sides ----------
-    substep_explicit<T, kLevels>(a.T2cur, a.T2prv, a.pit, a.tht, a.u2in, a.v2in, a.R_u, a.R_v, a.R_t, a.R_r, a.R_w,
+    substep_explicit<T, kLevels, kLast>(a.t_u, a.t_v, a.T2cur, a.T2prv, a.pit, a.tht, a.u2in, a.v2in, a.R_u, a.R_v, a.R_t, a.R_r, a.R_w,
                                  a.w2, a.r2, a.cC, a.idz, a.idzf, a.u2out, a.v2out, a.su, a.sv, a.sums, rbuf, bnd,
                                  act, col, nxy, nz, k0, g, lane, o_e, o_w, o_n, o_s, dt, b1, b2, gr, bd, gRd, idx,
                                  idy, th, thl, rh, e_first, f_first);
@@ -420,11 +429,27 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
                 const double tf1 = (k == nz - 1) ? 0.0 : 0.5 * (thc + (kPre ? thv[p + 2] : (double)a.tht[c + nxy]));
                 const double idzk = a.idz[k];
                 const double thk = (kLevels <= 8) ? thl[k * kLanes + lane] : th[l];
-                st_stream(a.T2nxt + c, (T)(thk - dt * b2 * (wk1 * tf1 - wk * tfl) * idzk));
-                st_stream(a.r2 + c, (T)(rh[l] - dt * b2 * (wk1 - wk) * idzk));
-                if (k >= 1) {
-                    st_stream(a.w2 + c, (T)wk);
-                    if (a.sums) a.sw[c] += wk;
+                const double Tn = thk - dt * b2 * (wk1 * tf1 - wk * tfl) * idzk;
+                const double rn = rh[l] - dt * b2 * (wk1 - wk) * idzk;
+                if constexpr (kLast) {
+                    // stage end S^t + S'' in place of S'' (S'' rounded to the
+                    // storage type first, as if it had been stored); the lid
+                    // faces keep W^t + W'' as they are
+                    st_stream(a.o_t + c, (T)((double)ld_stream(a.t_t + c) + (double)(T)Tn));
+                    st_stream(a.o_r + c, (T)((double)ld_stream(a.t_r + c) + (double)(T)rn));
+                    const int cw = k >= 1 ? c : col;  // face k, or the bottom lid
+                    st_stream(a.o_w + cw, (T)((double)ld_stream(a.t_w + cw) + (double)(k >= 1 ? (T)wk : a.w2[cw])));
+                    if (k == nz - 1) {
+                        const int ct = col + nz * nxy;
+                        st_stream(a.o_w + ct, (T)((double)ld_stream(a.t_w + ct) + (double)a.w2[ct]));
+                    }
+                } else {
+                    st_stream(a.T2nxt + c, (T)Tn);
+                    st_stream(a.r2 + c, (T)rn);
+                    if (k >= 1) {
+                        st_stream(a.w2 + c, (T)wk);
+                        if (a.sums) a.sw[c] += wk;
+                    }
                 }
                 wk1 = wk;
             }
@@ -533,7 +558,12 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
     if (KG > 16) return hipErrorInvalidValue;  // nz <= 256
     const size_t lds = sizeof(double) * ((size_t)(d.nz + 1) * kLanes + 2 * (size_t)KG * kLanes +
                                          (L == 8 ? (size_t)d.nz * kLanes : 0));
-    const void *kfn = L == 8 ? (const void *)k_substep<T, 8> : (const void *)k_substep<T, 16>;
+    // without flux sums the last substep also writes the stage end S^t + S''
+    // (no separate finalize pass over the five fields)
+    const bool fuse_end = !a.sums;
+    a.o_r = Sout[0]; a.o_t = Sout[1]; a.o_u = Sout[2]; a.o_v = Sout[3]; a.o_w = Sout[4];
+    const void *kfn[2] = {L == 8 ? (const void *)k_substep<T, 8, false> : (const void *)k_substep<T, 16, false>,
+                          L == 8 ? (const void *)k_substep<T, 8, true> : (const void *)k_substep<T, 16, true>};
 
     int t_cur = 0, t_prv = 2, u_in = 0;  // Theta'' rotates over 3 buffers, U'' and V'' over 2
     T *t2[3] = {(T *)w.t2[0], (T *)w.t2[1], (T *)w.t2[2]};
@@ -542,10 +572,11 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
     a.u2in = u2[0];
     a.v2in = v2[0];
 
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
+    if (lds > 64 * 1024)
+        for (const void *fn : kfn) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
     dim3 blk(64, 4, 1);
     dim3 g3w((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz + 1);
     dim3 g2((d.nx + 63) / 64, (d.ny + 3) / 4, 1);
@@ -561,16 +592,27 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
         a.v2in = v2[u_in];
         a.v2out = v2[u_in ^ 1];
         a.bd = (s == 0) ? 0.0 : cx->prm.beta_d;
+        const bool last = fuse_end && s == n_sub - 1;
+        if (last) {
+            a.u2out = Sout[2];
+            a.v2out = Sout[3];
+        }
+        const dim3 grid(a.ntx * a.nty), block(kLanes, KG);
         timing_start(cx, K_SUBSTEP);
-        if (L == 8)
-            hipLaunchKernelGGL((k_substep<T, 8>), dim3(a.ntx * a.nty), dim3(kLanes, KG), lds, cx->stream, a);
+        if (L == 8 && !last)
+            hipLaunchKernelGGL((k_substep<T, 8, false>), grid, block, lds, cx->stream, a);
+        else if (L == 8)
+            hipLaunchKernelGGL((k_substep<T, 8, true>), grid, block, lds, cx->stream, a);
+        else if (!last)
+            hipLaunchKernelGGL((k_substep<T, 16, false>), grid, block, lds, cx->stream, a);
         else
-            hipLaunchKernelGGL((k_substep<T, 16>), dim3(a.ntx * a.nty), dim3(kLanes, KG), lds, cx->stream, a);
+            hipLaunchKernelGGL((k_substep<T, 16, true>), grid, block, lds, cx->stream, a);
         timing_stop(cx, K_SUBSTEP);
         t_prv = t_cur;
         t_cur = t_nxt;
         u_in ^= 1;
     }
+    if (fuse_end) return hipGetLastError();
     FinArgs<T> f{};
     f.d = d;
     f.n_sub = n_sub;
