@@ -126,7 +126,7 @@ def run_gpu(cfg: W.Config, steps: int, warmup: int):
     S = s.from_full(W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"]))
     for _ in range(warmup):
         s.rk3_step(S)
-    tune = s.autotune(S, trials=2, cache_path=TUNE_CACHE)
+    tune = s.autotune(S, trials=2, cache_path=_tune_cache())
     # find the kernel with the largest share of a step (one short timed step per kernel)
     shares = {}
     for k in KERNEL_VALUES:
@@ -146,8 +146,25 @@ def run_gpu(cfg: W.Config, steps: int, warmup: int):
 
 WEIGHTS = os.path.join(ROOT, "paper_2412_04395_amd", "data", "closure_les40m.npz")
 # launch shapes of the acoustic substep chosen by erf_autotune on MI355X, one
-# line per grid size and precision; a missing line is tuned and appended
+# line per grid size and precision
 TUNE_CACHE = os.path.join(ROOT, "paper_2412_04395_amd", "data", "substep_shapes.txt")
+_tune_copy = None
+
+
+def _tune_cache() -> str:
+    """A private copy of the committed cache: its lines are read, and shapes
+    tuned for grids it lacks are appended to the copy, not to the package."""
+    global _tune_copy
+    if _tune_copy is None:
+        import shutil
+        import tempfile
+        import atexit
+        fd, _tune_copy = tempfile.mkstemp(prefix="substep_shapes_", suffix=".txt")
+        os.close(fd)
+        atexit.register(lambda p=_tune_copy: os.path.exists(p) and os.remove(p))
+        if os.path.exists(TUNE_CACHE):
+            shutil.copyfile(TUNE_CACHE, _tune_copy)
+    return _tune_copy
 
 
 def closure_weights(solver, S, seed: int):
@@ -191,7 +208,7 @@ def run_closure(steps: int, warmup: int):
     weights = closure_weights(s, S, cfg.seed)
     for _ in range(warmup):
         s.rk3_step(S)
-    tune = s.autotune(S, trials=2, cache_path=TUNE_CACHE)
+    tune = s.autotune(S, trials=2, cache_path=_tune_cache())
     shares = {}
     for k in ("mlp", "mlp_div", "rhs", "substep"):
         _, (ms, n) = _time_steps(s, S, 1, torch, kernel=k)
