@@ -234,6 +234,45 @@ def run_closure(steps: int, warmup: int):
                          "launches_timed": kn}}
 
 
+# one training sample: the forward products (MLP_FLOP_PER_CELL), the weight
+# gradients of all four layers (as many multiply-adds again) and the input
+# gradients of layers 2-4 (64*64 + 64*64 + 64*9 multiply-adds)
+TRAIN_FLOP_PER_SAMPLE = 2 * MLP_FLOP_PER_CELL + 2 * (64 * 64 + 64 * 64 + 64 * 9)
+
+
+def run_training(steps: int, batches=(16384, 262144)):
+    """Adam steps of the closure network (erf_mlp_train_step: BF16 MFMA forward
+    and backward products, FP64 loss and column sums, Adam) on synthetic
+    standardised samples; throughput against the BF16 matrix-core peak."""
+    import torch
+    from paper_2412_04395_amd import erf
+
+    cfg = W.les_mlp(nx=16, ny=16, nz=8, dz=W.uniform_dz(8, 40.0))  # the context only holds the network
+    s = erf.Solver(cfg)
+    gen = torch.Generator(device="cuda").manual_seed(cfg.seed)
+    p = np.random.default_rng(cfg.seed).normal(0.0, 0.1, erf.MLP_NPARAMS).astype(np.float32)
+    s.mlp_set_weights(p)
+    out = {}
+    for b in batches:
+        x = torch.randn((b, 10), generator=gen, device="cuda", dtype=torch.float32)
+        t = torch.randn((b, 9), generator=gen, device="cuda", dtype=torch.float32)
+        for _ in range(3):
+            s.mlp_train_step(x, t, 1e-4, want_loss=False)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        for _ in range(steps):
+            s.mlp_train_step(x, t, 1e-4, want_loss=False)
+        e1.record(s.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        tflops = TRAIN_FLOP_PER_SAMPLE * b / (ms * 1e-3) / 1e12
+        out[str(b)] = {"ms_per_step": round(ms, 4), "samples_per_s": b / (ms * 1e-3),
+                       "achieved_tflops": round(tflops, 2), "frac_bf16_peak": round(tflops / BF16_PEAK_TFLOPS, 4)}
+    s.close()
+    return {"workload": "closure network training, synthetic standardised samples",
+            "flop_per_sample": TRAIN_FLOP_PER_SAMPLE, "peak_tflops": BF16_PEAK_TFLOPS, "batches": out}
+
+
 def run_ensemble(steps: int, warmup: int, per_size: int = 16):
     """The 48-member ensemble (16 each of 96x96x64, 128x128x64, 192x192x96 at
     40 m, FP32, odd members on the learned closure): member steps one after
@@ -337,6 +376,7 @@ def main(argv=None):
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-closure", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-training", action="store_true")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first run one plain device copy of this many GiB (reference for HBM counters)")
     a = ap.parse_args(argv)
@@ -387,6 +427,8 @@ def main(argv=None):
                        "kernel_ms_per_step": {k: round(v[0], 4) for k, v in shares3.items()}}
     if a.workload == "cbl" and not a.no_closure:
         out["closure"] = run_closure(a.steps, a.warmup)
+    if a.workload == "cbl" and not a.no_training:
+        out["training"] = run_training(a.steps)
     if a.workload == "cbl" and not a.no_ensemble:
         out["ensemble"] = run_ensemble(min(a.steps, 5), min(a.warmup, 1))
     if rank == 0 and not a.no_cpu_baseline:

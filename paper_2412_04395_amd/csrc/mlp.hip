@@ -788,35 +788,58 @@ __global__ __launch_bounds__(256) void k_loss_dy(const float *__restrict__ Y, co
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(64) void k_loss_finish(const double *__restrict__ part, int nblk, int64_t n,
-                                                    double *__restrict__ loss)
+// one block of 256: strided partial sums, then a tree in LDS (fixed order)
+__global__ __launch_bounds__(256) void k_loss_finish(const double *__restrict__ part, int nblk, int64_t n,
+                                                     double *__restrict__ loss)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ double red[256];
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[b];
-    *loss = s / ((double)n * 9.0);
+    for (int b = threadIdx.x; b < nblk; b += 256) s += part[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0] / ((double)n * 9.0);
 }
 
-// bias gradients: column sums of D[n][ncol] (FP64, fixed order)
-__global__ __launch_bounds__(64) void k_colsum_part(const float *__restrict__ D, int64_t n, int ncol,
-                                                    double *__restrict__ part)
+// bias gradients: column sums of D[n][ncol] (FP64, fixed order).  A block of
+// 256 covers kStatRows rows: lane = column, each wavefront every fourth row
+// with four independent accumulators (loads in flight instead of one
+// dependent add per load), the wavefronts combined in LDS.
+__global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ D, int64_t n, int ncol,
+                                                     double *__restrict__ part)
 {
-    const int col = threadIdx.x;
-    if (col >= ncol) return;
+    __shared__ double red[4][64];
+    const int col = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t r0 = (int64_t)blockIdx.x * kStatRows, r1 = r0 + kStatRows < n ? r0 + kStatRows : n;
-    double acc = 0.0;
-    for (int64_t r = r0; r < r1; ++r) acc += (double)D[r * ncol + col];
-    part[(int64_t)blockIdx.x * ncol + col] = acc;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (col < ncol) {
+        int64_t r = r0 + w;
+        for (; r + 12 < r1; r += 16) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] += (double)D[(r + 4 * u) * ncol + col];
+        }
+        for (int u = 0; r < r1; r += 4, ++u) acc[u & 3] += (double)D[r * ncol + col];
+    }
+    red[w][col] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    __syncthreads();
+    if (w == 0 && col < ncol)
+        part[(int64_t)blockIdx.x * ncol + col] = (red[0][col] + red[1][col]) + (red[2][col] + red[3][col]);
 }
 
-__global__ __launch_bounds__(64) void k_colsum_finish(const double *__restrict__ part, int nblk, int ncol,
-                                                      float *__restrict__ out)
+__global__ __launch_bounds__(256) void k_colsum_finish(const double *__restrict__ part, int nblk, int ncol,
+                                                       float *__restrict__ out)
 {
-    const int col = threadIdx.x;
-    if (col >= ncol) return;
+    __shared__ double red[4][64];
+    const int col = threadIdx.x & 63, w = threadIdx.x >> 6;
     double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += part[(int64_t)b * ncol + col];
-    out[col] = (float)acc;
+    if (col < ncol)
+        for (int b = w; b < nblk; b += 4) acc += part[(int64_t)b * ncol + col];
+    red[w][col] = acc;
+    __syncthreads();
+    if (w == 0 && col < ncol) out[col] = (float)((red[0][col] + red[1][col]) + (red[2][col] + red[3][col]));
 }
 
 // Adam (Kingma & Ba) with bias correction; FP32 storage, FP64 arithmetic
@@ -1090,11 +1113,11 @@ hipError_t launch_loss_grad(erf_ctx *cx, const float *X, const float *Tt, int64_
     const int lblk = (int)((n * 9 + 255) / 256);
     double *lpart = dpart + ((n + kStatRows - 1) / kStatRows + 1) * 64;
     hipLaunchKernelGGL(k_loss_dy, dim3(lblk), dim3(256), 0, cx->stream, (const float *)Y, Tt, n, dY, lpart);
-    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(64), 0, cx->stream, (const double *)lpart, lblk, n, loss_dev);
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, cx->stream, (const double *)lpart, lblk, n, loss_dev);
     const int cblk = (int)((n + kStatRows - 1) / kStatRows);
     auto colsum = [&](const float *D, int ncol, float *out) {
-        hipLaunchKernelGGL(k_colsum_part, dim3(cblk), dim3(64), 0, cx->stream, D, n, ncol, dpart);
-        hipLaunchKernelGGL(k_colsum_finish, dim3(1), dim3(64), 0, cx->stream, (const double *)dpart, cblk, ncol, out);
+        hipLaunchKernelGGL(k_colsum_part, dim3(cblk), dim3(256), 0, cx->stream, D, n, ncol, dpart);
+        hipLaunchKernelGGL(k_colsum_finish, dim3(1), dim3(256), 0, cx->stream, (const double *)dpart, cblk, ncol, out);
     };
     // layer 4
     a = gargs(H3, 1, 64, dY, 9, 1, 64, 9, N, 9);
