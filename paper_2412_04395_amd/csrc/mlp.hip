@@ -704,6 +704,9 @@ struct GemmArgs {
     int relu;           // epilogue: max(., 0)
     const float *mask;  // epilogue: * (mask[m ldm + n] > 0)
     int64_t ldm;
+    // the 8 consecutive k of a lane are contiguous and 16-byte aligned (and
+    // every K-step is whole): two 16-byte loads instead of eight 4-byte ones
+    int vecA, vecB;
 };
 
 __device__ __forceinline__ float epilogue(const GemmArgs &a, int m, int n, float v)
@@ -727,12 +730,31 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int k0 = kb; k0 < ke; k0 += 32) {
         float av[8], bv[8];
+        if (a.vecA) {
+            const float4 *p = (const float4 *)(a.A + (int64_t)(am < a.M ? am : 0) * a.sam + k0 + 8 * g);
+            const float4 u = p[0], v = p[1];
+            const bool in = am < a.M;
+            av[0] = in ? u.x : 0.f; av[1] = in ? u.y : 0.f; av[2] = in ? u.z : 0.f; av[3] = in ? u.w : 0.f;
+            av[4] = in ? v.x : 0.f; av[5] = in ? v.y : 0.f; av[6] = in ? v.z : 0.f; av[7] = in ? v.w : 0.f;
+        } else {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int k = k0 + 8 * g + i;
-            const bool kin = k < ke;
-            av[i] = (kin && am < a.M) ? a.A[(int64_t)am * a.sam + (int64_t)k * a.sak] : 0.f;
-            bv[i] = (kin && bn < a.N) ? a.B[(int64_t)k * a.sbk + (int64_t)bn * a.sbn] : 0.f;
+            for (int i = 0; i < 8; ++i) {
+                const int k = k0 + 8 * g + i;
+                av[i] = (k < ke && am < a.M) ? a.A[(int64_t)am * a.sam + (int64_t)k * a.sak] : 0.f;
+            }
+        }
+        if (a.vecB) {
+            const float4 *p = (const float4 *)(a.B + (int64_t)(bn < a.N ? bn : 0) * a.sbn + k0 + 8 * g);
+            const float4 u = p[0], v = p[1];
+            const bool in = bn < a.N;
+            bv[0] = in ? u.x : 0.f; bv[1] = in ? u.y : 0.f; bv[2] = in ? u.z : 0.f; bv[3] = in ? u.w : 0.f;
+            bv[4] = in ? v.x : 0.f; bv[5] = in ? v.y : 0.f; bv[6] = in ? v.z : 0.f; bv[7] = in ? v.w : 0.f;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int k = k0 + 8 * g + i;
+                bv[i] = (k < ke && bn < a.N) ? a.B[(int64_t)k * a.sbk + (int64_t)bn * a.sbn] : 0.f;
+            }
         }
         u32x4 pa, pb;
         pa.x = pack2(av[0], av[1]);
@@ -757,14 +779,24 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
     }
 }
 
+// sum of the split-K partials: a block of 256 covers 64 outputs (lane =
+// output), each wavefront every fourth split, combined in LDS in a fixed
+// order; FP64 sums
 __global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs a, const float *__restrict__ part, float *__restrict__ C)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.M * a.N) return;
-    const int m = e / a.N, n = e - m * a.N;
-    float s = 0.f;
-    for (int p = 0; p < a.splits; ++p) s += part[((int64_t)p * a.M + m) * a.N + n];
-    C[(int64_t)m * a.ldc + n] = epilogue(a, m, n, s);
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t mn = (int64_t)a.M * a.N;
+    const int e = blockIdx.x * 64 + lane;
+    double acc = 0.0;
+    if (e < mn)
+        for (int p = w; p < a.splits; p += 4) acc += (double)part[(int64_t)p * mn + e];
+    red[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && e < mn) {
+        const int m = e / a.N, n = e - m * a.N;
+        C[(int64_t)m * a.ldc + n] = epilogue(a, m, n, (float)((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])));
+    }
 }
 
 // loss partials and dY = 2 (Y - T) / (n 9)
@@ -1030,15 +1062,19 @@ hipError_t launch_standardize(erf_ctx *cx, const double *X, int64_t n, int ncol,
 
 namespace {
 // one product with its epilogue; K split over blocks when long
+constexpr int kMaxSplits = 1024;  // split-K partials: at most this many of 64 x 64
+
 hipError_t gemm(erf_ctx *cx, GemmArgs a, float *C, float *part, size_t part_floats)
 {
+    // long reductions (the weight gradients, K = samples) are split into
+    // chunks of 256 so that every tile has hundreds of wavefronts behind it
     int splits = 1;
     if (a.K > 4096) {
-        splits = (a.K + 2047) / 2048;
+        splits = (a.K + 255) / 256;
         const size_t per = (size_t)a.M * a.N;
         const int cap = (int)(part_floats / (per ? per : 1));
         if (splits > cap) splits = cap;
-        if (splits > 256) splits = 256;
+        if (splits > kMaxSplits) splits = kMaxSplits;
         if (splits < 1) splits = 1;
     }
     int kchunk = (a.K + splits - 1) / splits;
@@ -1047,11 +1083,15 @@ hipError_t gemm(erf_ctx *cx, GemmArgs a, float *C, float *part, size_t part_floa
     if (splits < 1) splits = 1;
     a.kchunk = kchunk > 0 ? kchunk : 32;
     a.splits = splits;
+    // whole K-steps only (no partial chunk), rows 16-byte aligned
+    const bool whole = a.K % 32 == 0 && a.kchunk % 32 == 0;
+    a.vecA = whole && a.sak == 1 && a.sam % 4 == 0 && ((uintptr_t)a.A & 15) == 0;
+    a.vecB = whole && a.sbk == 1 && a.sbn % 4 == 0 && ((uintptr_t)a.B & 15) == 0;
     const int tiles = ((a.M + 15) / 16) * ((a.N + 15) / 16);
     a.C = splits == 1 ? C : part;
     hipLaunchKernelGGL(k_gemm, dim3((tiles + 3) / 4, splits), dim3(256), 0, cx->stream, a);
     if (splits > 1)
-        hipLaunchKernelGGL(k_gemm_reduce, dim3((a.M * a.N + 255) / 256), dim3(256), 0, cx->stream, a,
+        hipLaunchKernelGGL(k_gemm_reduce, dim3((a.M * a.N + 63) / 64), dim3(256), 0, cx->stream, a,
                            (const float *)part, C);
     return hipGetLastError();
 }
@@ -1079,7 +1119,7 @@ size_t train_floats(int64_t cap)
     // H1, H2, H3, D (two), each cap x 64; Y, dY cap x 9
     return (size_t)cap * (5 * 64 + 2 * 9);
 }
-size_t train_partial_floats() { return (size_t)256 * 64 * 64; }
+size_t train_partial_floats() { return (size_t)kMaxSplits * 64 * 64; }
 size_t train_partial_doubles(int64_t cap) { return (size_t)((cap + kStatRows - 1) / kStatRows + 1) * 64 + (size_t)((cap * 9 + 255) / 256 + 1); }
 
 hipError_t launch_loss_grad(erf_ctx *cx, const float *X, const float *Tt, int64_t n, float *G, double *loss_dev)
