@@ -22,6 +22,9 @@ pytestmark = pytest.mark.gpu
 # or 3 of 16, the last one partial
 CFG = dict(name="cbl_small", nx=70, ny=20, nz=40, dx=20.0, dy=20.0, dz=W.uniform_dz(40, 10.0), dt=0.1,
            adv_order_h=5, adv_order_v=5, sgs=1, Cs=0.1, f_cor=1e-4, Ug=10.0, Vg=1.0, surf_heat_flux=0.2)
+# 64 x 8 columns: every row shape fills its tiles exactly, so the substep
+# exchanges stencil neighbours across lanes instead of loading them
+CFG_FULL = dict(CFG, nx=64, ny=8, nz=24, dz=W.uniform_dz(24, 10.0))
 
 
 def _say(*a):
@@ -96,10 +99,11 @@ def test_autotune_rejects_bad_arguments(tmp_path):
     assert np.isfinite(s.to_numpy(S)["ru"]).all() and not np.array_equal(s.to_numpy(S)["ru"], S0["ru"])
 
 
+@pytest.mark.parametrize("grid", ["ragged", "full"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_every_shape_gives_the_same_step(tmp_path, prec):
-    cfg = W.small(**CFG, prec=prec)
-    _say("shapes", prec)
+def test_every_shape_gives_the_same_step(tmp_path, prec, grid):
+    cfg = W.small(**(CFG if grid == "ragged" else CFG_FULL), prec=prec)
+    _say("shapes", prec, grid, cfg.nx, cfg.ny, cfg.nz)
     s, th0, b = _solver(cfg)
     S0 = W.initial_state(cfg, b["rho0"], th0)
     out = {}
