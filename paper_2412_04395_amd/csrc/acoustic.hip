@@ -545,9 +545,9 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
     a.cm = w.cb;
     a.cc = w.cc;
     a.cC = (T *)w.cC;
-    // tile shape: 64 columns, one row of 64 where rows are that long (measured
-    // 1.3 % faster than 16 x 4 at 256 x 256), else up to four shorter rows
-    a.TY = d.nx >= 64 ? 1 : (d.ny >= 4 ? 4 : (d.ny >= 2 ? 2 : 1));
+    // tile shape: 64 columns as one row of 64 (measured 1.3 % faster than
+    // 16 x 4 at 256 x 256) unless rows of 32 or 16 pad the grid less
+    a.TY = kLanes / tile_width(d.nx, d.ny, kLanes);
     if (cx->tune_rows > 0) a.TY = cx->tune_rows;  // erf_autotune's choice
     a.TX = kLanes / a.TY;
     a.ntx = (d.nx + a.TX - 1) / a.TX;

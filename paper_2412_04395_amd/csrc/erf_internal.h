@@ -124,7 +124,26 @@ __device__ __forceinline__ TileIdx tile_cell(int ntx, int nty)
         t = (m / rows) * nrow + x * rows + m % rows;
     }
     const int bx = t % ntx, r = t / ntx, by = r % nty, bz = r / nty;
-    return {bx * 64 + (int)threadIdx.x, by * 4 + (int)threadIdx.y, bz};
+    return {bx * (int)blockDim.x + (int)threadIdx.x, by * (int)blockDim.y + (int)threadIdx.y, bz};
+}
+
+// Width of a workgroup's tile row for tiles of `lanes` cells in an nx x ny
+// plane: of 64, 32 and 16, the one that pads the plane least (a 96-wide grid
+// in rows of 64 would leave a third of its lanes idle); on a tie the widest,
+// whose rows are the longest contiguous segments.
+inline int tile_width(int nx, int ny, int lanes)
+{
+    int best = 64;
+    long best_cells = -1;
+    for (int tx = 64; tx >= 16; tx /= 2) {
+        const int ty = lanes / tx;
+        const long cells = (long)((nx + tx - 1) / tx) * tx * ((ny + ty - 1) / ty) * ty;
+        if (best_cells < 0 || cells < best_cells) {
+            best = tx;
+            best_cells = cells;
+        }
+    }
+    return best;
 }
 
 __device__ __forceinline__ double sign_of(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }

@@ -947,10 +947,11 @@ hipError_t closure_t(erf_ctx *cx, const void *rho, void *const R[5])
     v.Ru = (T *)R[2];
     v.Rv = (T *)R[3];
     v.Rw = (T *)R[4];
-    v.ntx = (d.nx + 63) / 64;
-    v.nty = (d.ny + 3) / 4;
+    const int tx = tile_width(d.nx, d.ny, 256), ty = 256 / tx;
+    v.ntx = (d.nx + tx - 1) / tx;
+    v.nty = (d.ny + ty - 1) / ty;
     timing_start(cx, K_MLP_DIV);
-    hipLaunchKernelGGL(k_mlp_div<T>, dim3(v.ntx * v.nty * d.nz), dim3(64, 4, 1), 0, cx->stream, v);
+    hipLaunchKernelGGL(k_mlp_div<T>, dim3(v.ntx * v.nty * d.nz), dim3(tx, ty, 1), 0, cx->stream, v);
     timing_stop(cx, K_MLP_DIV);
     return hipGetLastError();
 }

@@ -29,7 +29,7 @@ struct RhsArgs {
     double dx, dy, idx, idy;
     const double *dz, *idz, *idzf, *cs2;
     int oh, ov;
-    int ntx, nty;  // 64 x 4 tiles per level
+    int ntx, nty;  // tiles per level (blockDim.x x blockDim.y cells each)
     int sgs, visc;
     double Cs, Pr_t, nu, alpha, f, Ug, Vg, Qs, g;
     // state
@@ -482,9 +482,11 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5], boo
     a.Rv = (T *)R[3];
     a.Rw = (T *)R[4];
     const Dims &d = cx->d;
-    a.ntx = (d.nx + 63) / 64;
-    a.nty = (d.ny + 3) / 4;
-    dim3 blk(64, 4, 1), grd(a.ntx * a.nty * d.nz), grdw(a.ntx * a.nty * (d.nz + 1));
+    // 256-cell tiles per level, rows of 64, 32 or 16 cells (least padding)
+    const int tx = tile_width(d.nx, d.ny, 256), ty = 256 / tx;
+    a.ntx = (d.nx + tx - 1) / tx;
+    a.nty = (d.ny + ty - 1) / ty;
+    dim3 blk(tx, ty, 1), grd(a.ntx * a.nty * d.nz), grdw(a.ntx * a.nty * (d.nz + 1));
     timing_start(cx, K_PREP); hipLaunchKernelGGL(k_prep<T>, grd, blk, 0, cx->stream, a); timing_stop(cx, K_PREP);
     if (prep_only) return hipGetLastError();
     if (a.sgs) { timing_start(cx, K_MUT); hipLaunchKernelGGL(k_mut<T>, grd, blk, 0, cx->stream, a); timing_stop(cx, K_MUT); }
