@@ -2,6 +2,8 @@
 compressible dynamical core on one MI355X, through the C-ABI of liberf.so.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+    (NAME: cbl (default), cbl_as_stated, cbl_fp32, bubble2d; ensemble and
+    closure_training run that leg alone)
 
 Prints ONE JSON line.  The workload is the 3-D dry convective boundary layer
 LES, 256 x 256 x 128 cells, FP64 (5th-order upwind advection, Smagorinsky,
@@ -386,6 +388,13 @@ def main(argv=None):
         return 2
     rank = int(os.environ.get("RANK", "0"))
 
+    # single legs, each printed as its own JSON object (for profiling them alone)
+    if a.workload == "ensemble":
+        print(json.dumps(run_ensemble(min(a.steps, 5), min(a.warmup, 1))), flush=True)
+        return 0
+    if a.workload == "closure_training":
+        print(json.dumps(run_training(a.steps)), flush=True)
+        return 0
     cfg = _cfg(a.workload)
     if a.copy_gib > 0:
         import torch
