@@ -61,7 +61,7 @@ KERNEL_VALUES = {
     # Thomas factors read; Theta'', U'', V'', rho'', W'' written
     "substep": lambda sgs: (14 + 5, 3),
     # (the last substep of a stage, without scalars, also reads S^t and writes
-    # S_out in place of S'': 5 more bulk values, see _substep_bytes)
+    # S_out in place of S'': 5 more bulk values, see _substep_extra_share)
     # S^n, S^t read; theta^t, Exner, Theta'', rho'', U'', V'', W'' written
     "stage_init": lambda sgs: (10 + 7, 0),
     # Exner, theta^t, Theta^t read; buoyancy coefficient and three factors written
@@ -346,6 +346,62 @@ def cpu_baseline(cfg: W.Config, target_s: float = 12.0):
                       f"{el:.1f} s"}
 
 
+def _step_values(cfg):
+    """Algorithmic values per cell of one RK3 step, summed over the kernels that
+    run in it: (values in the storage precision, FP64 values)."""
+    sgs = 1 if cfg.sgs else 0
+    ns = cfg.n_substeps
+    counts = {"prep": 3, "rhs": 3, "mut": 3 * sgs, "stress": 3 * sgs, "stage_init": 3, "coef": 3,
+              "substep": 1 + ns // 2 + ns, "finalize": 3 if cfg.n_scalars else 0}
+    bulk = f64 = 0
+    for k, n in counts.items():
+        b, f = KERNEL_VALUES[k](sgs)
+        bulk += n * b
+        f64 += n * f
+    if not cfg.n_scalars:
+        bulk += 3 * 5  # the stage end written by the last substep of each stage
+    return bulk, f64
+
+
+def _one_pass_values(cfg) -> int:
+    """Lower bound on values per cell of a step for a design that makes one
+    grid pass per substep and per stage (3-D, F = 5 acoustic fields)."""
+    F, ns, nq = 5, cfg.n_substeps, cfg.n_scalars
+    chi = 1 if nq else 0
+    return 13 * F + 6 + (1 + ns // 2 + ns) * (3 * F + 3 + 6 * chi) + 9 * nq + 12 * chi
+
+
+def _copy_gbs() -> float:
+    """Measured device-to-device copy rate (1 GiB each way), GB/s."""
+    import torch
+    src = torch.ones((1 << 30) // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * 5 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def _step_roofline(cfg, ms_per_step: float, copy_gbs: float) -> dict:
+    eb = 8.0 if cfg.prec == "fp64" else 4.0
+    bulk, f64 = _step_values(cfg)
+    design = (bulk * eb + f64 * 8.0) * cfg.cells
+    bound = _one_pass_values(cfg) * eb * cfg.cells
+    ach = design / (ms_per_step * 1e-3) / 1e9
+    return {"design_values_per_cell": bulk + f64, "design_gb_per_step": round(design / 1e9, 3),
+            "achieved_gbs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+            "one_pass_bound_values_per_cell": _one_pass_values(cfg),
+            "one_pass_bound_frac": round(bound / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4)}
+
+
 def _substep_extra_share(cfg) -> float:
     """Fraction of substep launches that also write the stage end (one per
     stage; none with scalars, whose flux sums keep a separate finalize)."""
@@ -408,6 +464,7 @@ def main(argv=None):
     el, dom, kms, kn, shares, diag = run_gpu(cfg, a.steps, a.warmup)
     value = cfg.cells * a.steps / el
     roof = _roofline(cfg, dom, kms, kn)
+    copy_gbs = _copy_gbs()
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": 1e3 * el / a.steps, "higher_is_better": True, "scaling": "weak",
@@ -417,6 +474,9 @@ def main(argv=None):
                    "sgs": "smagorinsky" if cfg.sgs else "none", "precision": cfg.prec,
                    "substep_shape": diag["substep_shape"]},
         "roofline": roof,
+        # the whole step against HBM: the design's algorithmic bytes, the
+        # one-pass lower bound, and the measured copy rate
+        "step_roofline": _step_roofline(cfg, 1e3 * el / a.steps, copy_gbs),
         "kernel_ms_per_step": {k: round(v[0], 4) for k, v in shares.items()},
         "final_diag": {"max_w": diag["max_w"], "nonfinite": diag["nonfinite"]},
     }
@@ -432,6 +492,7 @@ def main(argv=None):
         out["fp32"] = {"workload": c3.name, "precision": "FP32 storage, FP64 arithmetic, solve and sums",
                        "value": c3.cells * a.steps / el3, "ms_per_step": 1e3 * el3 / a.steps,
                        "speedup_vs_fp64": el / el3, "roofline": _roofline(c3, dom3, kms3, kn3),
+                       "step_roofline": _step_roofline(c3, 1e3 * el3 / a.steps, copy_gbs),
                        "substep_shape": diag3["substep_shape"],
                        "kernel_ms_per_step": {k: round(v[0], 4) for k, v in shares3.items()}}
     if a.workload == "cbl" and not a.no_closure:
