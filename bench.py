@@ -45,7 +45,7 @@ MLP_FLOP_PER_CELL = 2 * (10 * 64 + 64 * 64 + 64 * 64 + 64 * 9)
 # Compulsory (algorithmic) values moved per cell by one launch of each kernel:
 # every distinct input field read once and every output written once.
 # (bulk values, FP64 values): bulk fields are stored in the run's precision
-# (8 B in FP64, 4 B in FP32); the tridiagonal factors are always FP64.
+# (8 B in FP64, 4 B in FP32); the tridiagonal pivots are always FP64.
 # 'sgs' = 1 adds the fields only viscous runs touch.
 KERNEL_VALUES = {
     # rho, U, V, W, theta, p', u, v, w read (+ 6 stresses and the diffusivity); 5 tendencies written
@@ -57,15 +57,15 @@ KERNEL_VALUES = {
     # u, v, w, rho, mu_t read; 6 stresses and the diffusivity written
     "stress": lambda sgs: (5 + 7, 0),
     # one fused substep: Theta'' (two levels), U'', V'', rho'', W'', the five
-    # tendencies, theta^t, Exner and the buoyancy coefficient read, the three
-    # Thomas factors read; Theta'', U'', V'', rho'', W'' written
-    "substep": lambda sgs: (14 + 5, 3),
+    # tendencies, theta^t, Exner and the buoyancy coefficient read, the Thomas
+    # pivots read; Theta'', U'', V'', rho'', W'' written
+    "substep": lambda sgs: (14 + 5, 1),
     # (the last substep of a stage, without scalars, also reads S^t and writes
     # S_out in place of S'': 5 more bulk values, see _substep_extra_share)
     # S^n, S^t read; theta^t, Exner, Theta'', rho'', U'', V'', W'' written
     "stage_init": lambda sgs: (10 + 7, 0),
-    # Exner, theta^t, Theta^t read; buoyancy coefficient and three factors written
-    "coef": lambda sgs: (3 + 1, 3),
+    # Exner, theta^t, Theta^t read; buoyancy coefficient and the pivots written
+    "coef": lambda sgs: (3 + 1, 1),
     # S^t and S'' read; S_out written
     "finalize": lambda sgs: (10 + 5, 0),
 }

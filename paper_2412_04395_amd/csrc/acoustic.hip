@@ -6,7 +6,9 @@
 // Kernels of one stage:
 //   k_stage_init  S'' = S^n - S^t, frozen theta^t and Exner pi^t, zero sums
 //   k_coef        per column: the tridiagonal rows of the implicit W'' equation
-//                 (they depend only on S^t and dtau) factorised once per stage
+//                 (they depend only on S^t and dtau) factorised once per stage;
+//                 only the pivots 1/den_k are kept, the off-diagonals are
+//                 recomputed by the substep from values it loads anyway
 //   k_substep     one launch per substep, everything of the substep fused:
 //                 U'', V'' forward step with the forward-predicted Theta''
 //                 (divergence damping); explicit parts of Theta'', rho'';
@@ -52,10 +54,10 @@ struct StageArgs {
     // perturbations (Theta'' three levels, U'' and V'' double-buffered) and sums
     T *T2cur, *T2prv, *T2nxt, *r2, *u2in, *u2out, *v2in, *v2out, *w2, *su, *sv, *sw;
     int sums;
-    // coefficients on z-faces: C_k (bulk precision); alpha_k = a_k / den_k,
-    // m_k = 1 / den_k, c'_k (double)
+    // coefficients on z-faces: C_k (bulk precision) and the Thomas pivots
+    // m_k = 1 / den_k (double)
     T *cC;
-    double *calpha, *cm, *cc;
+    double *cm;
     // tiles
     int TX, TY, ntx, nty;
     // stage end S^t + S'' (written by the last substep when no flux sums are kept)
@@ -96,11 +98,27 @@ __global__ __launch_bounds__(256) void k_stage_init(StageArgs<T> a)
     }
 }
 
+// Off-diagonal entries of the W'' row on face k (1 <= k <= nz - 1): lo
+// multiplies W''_{k-1}, up multiplies W''_{k+1}.  A = gamma R_d pi^t and C on
+// face k; tfm, tfp = theta^t on faces k - 1 and k + 1 (zero on the lids);
+// 1/dz of the levels below and above the face and 2/(dz_{k-1} + dz_k); D =
+// (dtau b2)^2.  k_coef and the substep evaluate the rows with this one
+// function on the same inputs, so the substep's alpha_k = lo_k m_k and c'_k =
+// up_k m_k are bitwise those of the factorisation.
+__device__ __forceinline__ void w_row_offdiag(double D, double g, double A, double C, double tfm, double tfp,
+                                              double idzm, double idzk, double idzf, int k, int nz, double &lo,
+                                              double &up)
+{
+    lo = (k == 1) ? 0.0 : -D * (A * tfm * idzm * idzf + 0.5 * C * tfm * idzm - 0.5 * g * idzm);
+    up = (k == nz - 1) ? 0.0 : -D * (A * tfp * idzk * idzf - 0.5 * C * tfp * idzk + 0.5 * g * idzk);
+}
+
 // Tridiagonal rows for W'' at interior faces k = 1..nz-1.  Substituting
 // Theta''_new = That - dtau b2 delta_z(W theta_f)/dz and rho''_new = Rhat -
 // dtau b2 delta_z(W)/dz into the W'' equation of App. C couples W_{k-1}, W_k,
 // W_{k+1} with coefficients of the frozen state only.  Factorised here (Thomas,
-// no pivoting; the rows are diagonally dominant).
+// no pivoting; the rows are diagonally dominant).  C enters the rows as
+// stored (rounded to the bulk type), as the substep reads it.
 template <typename T>
 __global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
 {
@@ -133,26 +151,23 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
             const int k = k0 + l;
             if (k >= nz) break;
             const int c = col + k * nxy;
-            double dzf = 0.5 * (a.dz[k - 1] + a.dz[k]);
             double pif = 0.5 * (P[l] + P[l + 1]);
             double A = kGamma * kRd * pif;
             const double Tm = kPert<T> ? a.Theta0[k - 1] + TT[l] : TT[l];
             const double Tk = kPert<T> ? a.Theta0[k] + TT[l + 1] : TT[l + 1];
-            double C = g * 0.5 * (a.rho0[k - 1] + a.rho0[k]) * (kRd / kCv) * (pif / (0.5 * (a.pi0[k - 1] + a.pi0[k]))) /
-                       (0.5 * (Tm + Tk));
-            double idzm = 1.0 / a.dz[k - 1], idz = 1.0 / a.dz[k];
-            double tfm = tface(k - 1, l), tf = tface(k, l + 1), tfp = tface(k + 1, l + 2);
-            double lo = (k == 1) ? 0.0 : -D * (A * tfm * idzm / dzf + 0.5 * C * tfm * idzm - 0.5 * g * idzm);
-            double up = (k == nz - 1) ? 0.0 : -D * (A * tfp * idz / dzf - 0.5 * C * tfp * idz + 0.5 * g * idz);
-            double di = 1.0 + D * (A * tf * (idz + idzm) / dzf + 0.5 * C * tf * (idzm - idz) - 0.5 * g * (idzm - idz));
+            const T Cst = (T)(g * 0.5 * (a.rho0[k - 1] + a.rho0[k]) * (kRd / kCv) *
+                              (pif / (0.5 * (a.pi0[k - 1] + a.pi0[k]))) / (0.5 * (Tm + Tk)));
+            const double C = Cst;
+            const double idzm = a.idz[k - 1], idz = a.idz[k], idzf = a.idzf[k];
+            const double tfm = tface(k - 1, l), tf = tface(k, l + 1), tfp = tface(k + 1, l + 2);
+            double lo, up;
+            w_row_offdiag(D, g, A, C, tfm, tfp, idzm, idz, idzf, k, nz, lo, up);
+            double di = 1.0 + D * (A * tf * (idz + idzm) * idzf + 0.5 * C * tf * (idzm - idz) - 0.5 * g * (idzm - idz));
             double den = (k == 1) ? di : di - lo * cprev;
             double m = 1.0 / den;
-            double cp = up * m;
-            st_stream(a.calpha + c, lo * m);
             st_stream(a.cm + c, m);
-            st_stream(a.cc + c, cp);
-            st_stream(a.cC + c, (T)C);
-            cprev = cp;
+            st_stream(a.cC + c, Cst);
+            cprev = up * m;
         }
     }
 }
@@ -174,11 +189,12 @@ __device__ __forceinline__ void substep_explicit(
     const double *__restrict__ idzf_t, T *__restrict__ u2out, T *__restrict__ v2out, T *__restrict__ su,
     T *__restrict__ sv, int sums, double *rbuf, double *bnd, bool act, int col, int nxy, int nz, int k0, int g,
     int lane, int o_e, int o_w, int o_n, int o_s, double dt, double b1, double b2, double gr, double bd,
-    double gRd, double idx, double idy, double (&th)[kLevels], double *thl, double (&rh)[kLevels],
-    double &e_first, double &f_first)
+    double gRd, double idx, double idy, double D, double (&th)[kLevels], double *thl, double (&rh)[kLevels],
+    double (&lo)[kLevels <= 8 ? kLevels : 1], double (&up)[kLevels <= 8 ? kLevels : 1], double &e_first,
+    double &f_first)
 {
     if (act && k0 < nz) {
-        double e_prev = 0.0, f_prev = 0.0;
+        double e_prev = 0.0, f_prev = 0.0, tf_prev = 0.0;
         double pi_below = (k0 > 0) ? pit[col + (k0 - 1) * nxy] : 0.0;
         double th_below = (k0 > 0) ? tht[col + (k0 - 1) * nxy] : 0.0;
         double w_lo = w2[col + k0 * nxy];
@@ -240,6 +256,9 @@ __device__ __forceinline__ void substep_explicit(
                     const double C = ld_stream(cC + c);
                     rbuf[k * kLanes + lane] = w_lo + dt * (-A * (e - e_prev) * idzf + 0.5 * C * (e + e_prev) -
                                                            0.5 * gr * (f + f_prev) + ld_stream(R_w + c));
+                    // the row's off-diagonals (up to 8 levels: kept for the sweeps)
+                    if constexpr (kLevels <= 8)
+                        w_row_offdiag(D, gr, A, C, tf_prev, tfk1, idz_t[k - 1], idzk, idzf, k, nz, lo[l], up[l]);
                 }
                 if constexpr (kLevels <= 8)
                     thl[k * kLanes + lane] = that;
@@ -250,6 +269,7 @@ __device__ __forceinline__ void substep_explicit(
                 f_prev = f;
                 pi_below = pc;
                 th_below = thc;
+                tf_prev = tfk;
                 w_lo = w_hi;
                 if (l == kLevels - 1 || k == nz - 1) {
                     bnd[(g * 2 + 0) * kLanes + lane] = e;
@@ -294,31 +314,40 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
     const double gRd = kGamma * kRd;
     const double idx = 1.0 / a.dx, idy = 1.0 / a.dy;
 
+    const double D = dt * dt * b2 * b2;  // as in k_coef
     const int k0 = g * kLevels;
     double th[kLevels], rh[kLevels];
     double e_first = 0.0, f_first = 0.0;
+    // Up to 8 levels per wavefront the rows' off-diagonals come out of phase 1
+    // in registers and the pivots are loaded together, levels clamped into
+    // the column so that no branch separates the loads: the sweeps then wait
+    // on LDS only instead of one global round trip per level.  With 16 levels
+    // the rows are evaluated where used, from loads of the frozen fields.
+    constexpr bool kPre = kLevels <= 8;
+    constexpr int kP = kPre ? kLevels : 1;
+    double flo[kP], fup[kP], fcm[kP];
+
+    // the off-diagonals of the row on face k (1 <= k <= nz - 1) from the
+    // frozen fields, as phase 1 and k_coef evaluate them
+    auto row_at = [&](int k, double &lo, double &up) {
+        const int c = col + k * nxy;
+        const double A = gRd * (0.5 * (a.pit[c - nxy] + a.pit[c]));
+        const double C = a.cC[c];
+        const double thm2 = a.tht[col + max(k - 2, 0) * nxy], thm = a.tht[c - nxy], thk = a.tht[c];
+        const double thp = a.tht[col + min(k + 1, nz - 1) * nxy];
+        const double tfm = (k - 1 <= 0) ? 0.0 : 0.5 * (thm2 + thm);
+        const double tfp = (k + 1 >= nz) ? 0.0 : 0.5 * (thk + thp);
+        w_row_offdiag(D, gr, A, C, tfm, tfp, a.idz[k - 1], a.idz[k], a.idzf[k], k, nz, lo, up);
+    };
 
     // ---------------- phase 1: explicit work, W'' right-hand sides ----------
     substep_explicit<T, kLevels, kLast>(a.t_u, a.t_v, a.T2cur, a.T2prv, a.pit, a.tht, a.u2in, a.v2in, a.R_u, a.R_v, a.R_t, a.R_r, a.R_w,
                                  a.w2, a.r2, a.cC, a.idz, a.idzf, a.u2out, a.v2out, a.su, a.sv, a.sums, rbuf, bnd,
                                  act, col, nxy, nz, k0, g, lane, o_e, o_w, o_n, o_s, dt, b1, b2, gr, bd, gRd, idx,
-                                 idy, th, thl, rh, e_first, f_first);
-    // Up to 8 levels per wavefront, the chunk's tridiagonal factors (and, for
-    // phase 3, theta^t) are loaded together into registers, levels
-    // clamped into the column so that no branch separates the loads: the
-    // sweeps then wait on LDS only instead of one global round trip per level.
-    // With 16 levels they are loaded where used (registers).
-    constexpr bool kPre = kLevels <= 8;
-    constexpr int kP = kPre ? kLevels : 1;
-    double fal[kP], fcm[kP], fcc[kP];
+                                 idy, D, th, thl, rh, flo, fup, e_first, f_first);
     if constexpr (kPre) {
 #pragma unroll
-        for (int l = 0; l < kLevels; ++l) {
-            const int c = col + min(k0 + l, nz - 1) * nxy;
-            fal[l] = ld_stream(a.calpha + c);
-            fcm[l] = ld_stream(a.cm + c);
-            fcc[l] = ld_stream(a.cc + c);
-        }
+        for (int l = 0; l < kLevels; ++l) fcm[l] = ld_stream(a.cm + col + min(k0 + l, nz - 1) * nxy);
     }
     __syncthreads();
     // row k0 of every chunk but the first needs the last level of the chunk below
@@ -331,6 +360,7 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
         const double C = a.cC[c];
         rbuf[k * kLanes + lane] = a.w2[c] + dt * (-A * (e_first - e_prev) * idzf + 0.5 * C * (e_first + e_prev) -
                                                   0.5 * gr * (f_first + f_prev) + a.R_w[c]);
+        if constexpr (kPre) row_at(k, flo[0], fup[0]);
     }
     __syncthreads();
 
@@ -352,8 +382,16 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
             const int k = k0 + l;
             if (k >= rlo && k <= rhi) {
                 const int c = col + k * nxy;
-                const double al = kPre ? fal[kPre ? l : 0] : a.calpha[c];
-                dl = rbuf[k * kLanes + lane] * (kPre ? fcm[kPre ? l : 0] : a.cm[c]) - al * dl;
+                double lo = 0.0, up = 0.0, m;
+                if constexpr (kPre) {
+                    lo = flo[l];
+                    m = fcm[l];
+                } else {
+                    row_at(k, lo, up);
+                    m = a.cm[c];
+                }
+                const double al = lo * m;  // alpha_k = a_k / den_k
+                dl = rbuf[k * kLanes + lane] * m - al * dl;
                 pm = -al * pm;
                 rbuf[k * kLanes + lane] = dl;
                 mult[l] = pm;
@@ -381,7 +419,14 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
             const int k = k0 + l;
             if (k >= rlo && k <= rhi) {
                 const double dk = rbuf[k * kLanes + lane] + mult[l] * Dprev;
-                const double cp = kPre ? fcc[kPre ? l : 0] : a.cc[col + k * nxy];
+                double cp;  // c'_k = c_k / den_k
+                if constexpr (kPre) {
+                    cp = fup[l] * fcm[l];
+                } else {
+                    double lo, up;
+                    row_at(k, lo, up);
+                    cp = up * a.cm[col + k * nxy];
+                }
                 xl = dk - cp * xl;
                 qm = -cp * qm;
                 rbuf[k * kLanes + lane] = xl;
@@ -541,9 +586,7 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
     a.sv = (T *)w.sv;
     a.sw = (T *)w.sw;
     a.sums = (Fu || Fv || Fw) ? 1 : 0;
-    a.calpha = w.ca;
     a.cm = w.cb;
-    a.cc = w.cc;
     a.cC = (T *)w.cC;
     // tile shape: 64 columns as one row of 64 (measured 1.3 % faster than
     // 16 x 4 at 256 x 256) unless rows of 32 or 16 pad the grid less

@@ -146,7 +146,7 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
         {&ws.t2[0], N}, {&ws.t2[1], N}, {&ws.t2[2], N}, {&ws.r2, N}, {&ws.w2, Wb},
         {&ws.u2[0], N}, {&ws.u2[1], N}, {&ws.v2[0], N}, {&ws.v2[1], N},
         {&ws.su, N}, {&ws.sv, N}, {&ws.sw, Wb},
-        {&ws.cC, Wb}, {(void **)&ws.ca, w * D}, {(void **)&ws.cb, w * D}, {(void **)&ws.cc, w * D},
+        {&ws.cC, Wb}, {(void **)&ws.cb, w * D},
         {&ws.q, Q}, {&ws.fu, N}, {&ws.fv, N}, {&ws.fw, Wb},
         {(void **)&ws.diag, diag_slots_needed() * D},
         {&ws.sg[0], G}, {&ws.sg[1], G}, {&ws.sg[2], G}, {&ws.sg[3], G}, {&ws.sg[4], G}, {&ws.sg[5], G},

@@ -215,9 +215,9 @@ struct Workspace {
     // running sums of the substep momenta (stage-averaged fluxes at the end)
     void *su = nullptr, *sv = nullptr, *sw = nullptr;
     // per-stage tridiagonal rows on z-faces: buoyancy coefficient (bulk
-    // precision) and the Thomas factors a_k / den_k, 1 / den_k, c'_k (double)
+    // precision) and the Thomas pivots 1 / den_k (double)
     void *cC = nullptr;
-    double *ca = nullptr, *cb = nullptr, *cc = nullptr;
+    double *cb = nullptr;
     // mixing ratios q^t of the scalars, stage-averaged momenta of rk3_step
     void *q = nullptr;
     void *fu = nullptr, *fv = nullptr, *fw = nullptr;
