@@ -25,9 +25,15 @@ def test_bench_constants():
     import bench
     # multiply-adds of 10 -> 64 -> 64 -> 64 -> 9, two flops each
     assert bench.MLP_FLOP_PER_CELL == 18816
-    # FP64 substep: 19 bulk values and 3 FP64 factors per cell
-    assert bench._kernel_bytes("substep", 1, "fp64") == 22 * 8
-    assert bench._kernel_bytes("substep", 1, "fp32") == 19 * 4 + 3 * 8
+    # substep: 19 bulk values and the FP64 Thomas pivots per cell
+    assert bench._kernel_bytes("substep", 1, "fp64") == 20 * 8
+    assert bench._kernel_bytes("substep", 1, "fp32") == 19 * 4 + 1 * 8
+    # whole step of the 14-substep boundary layer: 22 substeps of 20 values,
+    # 5 more in each stage's last, 48 + 17 + 5 per stage
+    cfg = bench._cfg("cbl")
+    bulk, f64 = bench._step_values(cfg)
+    assert bulk + f64 == 22 * 20 + 3 * 5 + 3 * (48 + 17 + 5)
+    assert bench._one_pass_values(cfg) == 13 * 5 + 6 + 22 * (3 * 5 + 3)
 
 
 def test_ensemble_recipe():
