@@ -61,7 +61,7 @@ KERNEL_VALUES = {
     # pivots read; Theta'', U'', V'', rho'', W'' written
     "substep": lambda sgs: (14 + 5, 1),
     # (the last substep of a stage, without scalars, also reads S^t and writes
-    # S_out in place of S'': 5 more bulk values, see _substep_extra_share)
+    # S_out in place of S'': 5 more bulk values; see _substep_value_adjust)
     # S^n, S^t read; theta^t, Exner, Theta'', rho'', U'', V'', W'' written
     "stage_init": lambda sgs: (10 + 7, 0),
     # Exner, theta^t, Theta^t read; buoyancy coefficient and the pivots written
@@ -69,6 +69,11 @@ KERNEL_VALUES = {
     # S^t and S'' read; S_out written
     "finalize": lambda sgs: (10 + 5, 0),
 }
+# The first RK3 stage starts from S^t = S^n with one substep, so S'' = 0 on
+# entry: its stage init moves only Theta^t, rho^t in and theta^t, Exner out
+# (13 bulk values fewer) and its substep reads none of the 6 S'' inputs
+# (Theta'' twice, U'', V'', rho'', W'').
+ZERO_START_SAVED = {"stage_init": 13, "substep": 6}
 
 
 def _kernel_bytes(kernel: str, sgs: int, prec: str) -> float:
@@ -356,7 +361,7 @@ def _step_values(cfg):
     bulk = f64 = 0
     for k, n in counts.items():
         b, f = KERNEL_VALUES[k](sgs)
-        bulk += n * b
+        bulk += n * b - (ZERO_START_SAVED.get(k, 0) if n else 0)
         f64 += n * f
     if not cfg.n_scalars:
         bulk += 3 * 5  # the stage end written by the last substep of each stage
@@ -402,11 +407,14 @@ def _step_roofline(cfg, ms_per_step: float, copy_gbs: float) -> dict:
             "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4)}
 
 
-def _substep_extra_share(cfg) -> float:
-    """Fraction of substep launches that also write the stage end (one per
-    stage; none with scalars, whose flux sums keep a separate finalize)."""
+def _substep_value_adjust(cfg) -> float:
+    """Bulk values per cell by which the average substep launch of a step
+    differs from KERNEL_VALUES: +5 for the one per stage that writes the stage
+    end (none with scalars, whose flux sums keep a separate finalize), -6 for
+    the first stage's, which reads no S''."""
     ns = cfg.n_substeps
-    return 0.0 if cfg.n_scalars else 3.0 / (1 + ns // 2 + ns)
+    n = 1 + ns // 2 + ns
+    return ((0.0 if cfg.n_scalars else 3.0 * 5) - ZERO_START_SAVED["substep"]) / n
 
 
 def _roofline(cfg, dom, kms, kn):
@@ -414,7 +422,7 @@ def _roofline(cfg, dom, kms, kn):
     avg_ms = kms / max(kn, 1)
     bytes_per_launch = _kernel_bytes(dom, sgs, cfg.prec) * cfg.cells
     if dom == "substep":  # averaged over the timed launches
-        bytes_per_launch += _substep_extra_share(cfg) * 5 * (8.0 if cfg.prec == "fp64" else 4.0) * cfg.cells
+        bytes_per_launch += _substep_value_adjust(cfg) * (8.0 if cfg.prec == "fp64" else 4.0) * cfg.cells
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic, tsrc = _profiled_traffic(dom) if cfg.prec == "fp64" and "stable" in cfg.name else (None, None)
     return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

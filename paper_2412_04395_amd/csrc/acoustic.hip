@@ -5,6 +5,9 @@
 //
 // Kernels of one stage:
 //   k_stage_init  S'' = S^n - S^t, frozen theta^t and Exner pi^t, zero sums
+//                 (a stage that starts from S^t = S^n with a single substep,
+//                 the first of RK3, has S'' = 0 exactly: its stage init and
+//                 substep are instances that neither write nor read the zeros)
 //   k_coef        per column: the tridiagonal rows of the implicit W'' equation
 //                 (they depend only on S^t and dtau) factorised once per stage;
 //                 only the pivots 1/den_k are kept, the off-diagonals are
@@ -64,7 +67,7 @@ struct StageArgs {
     T *o_r, *o_t, *o_u, *o_v, *o_w;
 };
 
-template <typename T>
+template <typename T, bool kZero>
 __global__ __launch_bounds__(256) void k_stage_init(StageArgs<T> a)
 {
     const Dims &d = a.d;
@@ -74,7 +77,12 @@ __global__ __launch_bounds__(256) void k_stage_init(StageArgs<T> a)
     if (i >= d.nx || j >= d.ny) return;
     int c = cidx(d, i, j, k);
     // every value is read and written once: streaming accesses throughout
-    st_stream(a.w2 + c, (T)((double)ld_stream(a.n_w + c) - (double)ld_stream(a.t_w + c)));
+    if constexpr (kZero) {
+        // S'' = 0: only the lid faces of W'' are stored (no substep writes them)
+        if (k == 0 || k == d.nz) st_stream(a.w2 + c, (T)0);
+    } else {
+        st_stream(a.w2 + c, (T)((double)ld_stream(a.n_w + c) - (double)ld_stream(a.t_w + c)));
+    }
     if (a.sums) st_stream(a.sw + c, (T)0);
     if (k == d.nz) return;
     const double T0 = a.Theta0[k];
@@ -88,10 +96,12 @@ __global__ __launch_bounds__(256) void k_stage_init(StageArgs<T> a)
         st_stream(a.pit + c, (T)(a.pi0[k] * exp((kGamma - 1.0) * log1p((double)tt / T0))));
     else
         st_stream(a.pit + c, (T)pow(kRd * Tt / kP00, kGamma - 1.0));
-    st_stream(a.T2cur + c, (T)((double)ld_stream(a.n_t + c) - (double)tt));
-    st_stream(a.r2 + c, (T)((double)ld_stream(a.n_r + c) - (double)tr));
-    st_stream(a.u2in + c, (T)((double)ld_stream(a.n_u + c) - (double)ld_stream(a.t_u + c)));
-    st_stream(a.v2in + c, (T)((double)ld_stream(a.n_v + c) - (double)ld_stream(a.t_v + c)));
+    if constexpr (!kZero) {
+        st_stream(a.T2cur + c, (T)((double)ld_stream(a.n_t + c) - (double)tt));
+        st_stream(a.r2 + c, (T)((double)ld_stream(a.n_r + c) - (double)tr));
+        st_stream(a.u2in + c, (T)((double)ld_stream(a.n_u + c) - (double)ld_stream(a.t_u + c)));
+        st_stream(a.v2in + c, (T)((double)ld_stream(a.n_v + c) - (double)ld_stream(a.t_v + c)));
+    }
     if (a.sums) {
         st_stream(a.su + c, (T)0);
         st_stream(a.sv + c, (T)0);
@@ -179,8 +189,10 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
 // values live across the level loop leaves registers for more loads in
 // flight.  The pointers are restrict: the arrays
 // written here (U'', V'' of the next level, their sums) are never read here,
-// so the loads of later levels may be issued ahead of earlier stores.
-template <typename T, int kLevels, bool kLast>
+// so the loads of later levels may be issued ahead of earlier stores.  kZero:
+// S'' is zero on entry (Theta'', U'', V'', rho'', W'' are not read; the same
+// arithmetic runs on zeros, so the results are those of reading them).
+template <typename T, int kLevels, bool kLast, bool kZero>
 __device__ __forceinline__ void substep_explicit(
     const T *__restrict__ t_u, const T *__restrict__ t_v, const T *__restrict__ T2cur, const T *__restrict__ T2prv, const T *__restrict__ pit, const T *__restrict__ tht,
     const T *__restrict__ u2in, const T *__restrict__ v2in, const T *__restrict__ R_u, const T *__restrict__ R_v,
@@ -193,33 +205,41 @@ __device__ __forceinline__ void substep_explicit(
     double (&lo)[kLevels <= 8 ? kLevels : 1], double (&up)[kLevels <= 8 ? kLevels : 1], double &e_first,
     double &f_first)
 {
+    // an S'' value on entry
+    auto in = [&](const T *__restrict__ p, int i) -> double {
+        if constexpr (kZero)
+            return 0.0;
+        else
+            return (double)p[i];
+    };
     if (act && k0 < nz) {
         double e_prev = 0.0, f_prev = 0.0, tf_prev = 0.0;
         double pi_below = (k0 > 0) ? pit[col + (k0 - 1) * nxy] : 0.0;
         double th_below = (k0 > 0) ? tht[col + (k0 - 1) * nxy] : 0.0;
-        double w_lo = w2[col + k0 * nxy];
+        double w_lo = in(w2, col + k0 * nxy);
 #pragma unroll
         for (int l = 0; l < kLevels; ++l) {
             const int k = k0 + l;
             if (k < nz) {
                 const int c = col + k * nxy;
                 // forward-predicted Theta'' at the centre and its four neighbours
-                const double Tc = T2cur[c];
-                const double ttc = Tc + bd * (Tc - T2prv[c]);
-                const double Tw = T2cur[c + o_w], Te = T2cur[c + o_e], Ts = T2cur[c + o_s], Tn = T2cur[c + o_n];
-                const double ttw = Tw + bd * (Tw - T2prv[c + o_w]);
-                const double tte = Te + bd * (Te - T2prv[c + o_e]);
-                const double tts = Ts + bd * (Ts - T2prv[c + o_s]);
-                const double ttn = Tn + bd * (Tn - T2prv[c + o_n]);
+                const double Tc = in(T2cur, c);
+                const double ttc = Tc + bd * (Tc - in(T2prv, c));
+                const double Tw = in(T2cur, c + o_w), Te = in(T2cur, c + o_e), Ts = in(T2cur, c + o_s),
+                             Tn = in(T2cur, c + o_n);
+                const double ttw = Tw + bd * (Tw - in(T2prv, c + o_w));
+                const double tte = Te + bd * (Te - in(T2prv, c + o_e));
+                const double tts = Ts + bd * (Ts - in(T2prv, c + o_s));
+                const double ttn = Tn + bd * (Tn - in(T2prv, c + o_n));
                 const double pc = pit[c], pw = pit[c + o_w], pe = pit[c + o_e], ps = pit[c + o_s],
                              pn = pit[c + o_n];
                 // U'' on this column's x-face and on the next one, V'' likewise
-                const double Uw = u2in[c] + dt * (-gRd * (0.5 * (pw + pc)) * (ttc - ttw) * idx + R_u[c]);
+                const double Uw = in(u2in, c) + dt * (-gRd * (0.5 * (pw + pc)) * (ttc - ttw) * idx + R_u[c]);
                 const double Ue =
-                    u2in[c + o_e] + dt * (-gRd * (0.5 * (pc + pe)) * (tte - ttc) * idx + R_u[c + o_e]);
-                const double Vs = v2in[c] + dt * (-gRd * (0.5 * (ps + pc)) * (ttc - tts) * idy + R_v[c]);
+                    in(u2in, c + o_e) + dt * (-gRd * (0.5 * (pc + pe)) * (tte - ttc) * idx + R_u[c + o_e]);
+                const double Vs = in(v2in, c) + dt * (-gRd * (0.5 * (ps + pc)) * (ttc - tts) * idy + R_v[c]);
                 const double Vn =
-                    v2in[c + o_n] + dt * (-gRd * (0.5 * (pc + pn)) * (ttn - ttc) * idy + R_v[c + o_n]);
+                    in(v2in, c + o_n) + dt * (-gRd * (0.5 * (pc + pn)) * (ttn - ttc) * idy + R_v[c + o_n]);
                 if constexpr (kLast) {
                     // the stage's last substep writes S^t + S'' (u2out, v2out
                     // point to the stage-end momenta; S'' rounded as if stored)
@@ -239,10 +259,11 @@ __device__ __forceinline__ void substep_explicit(
                 const double th_above = tht[c + (k < nz - 1 ? nxy : 0)];
                 const double tfk = (k == 0) ? 0.0 : 0.5 * (th_below + thc);
                 const double tfk1 = (k == nz - 1) ? 0.0 : 0.5 * (thc + th_above);
-                const double w_hi = w2[c + nxy];
+                const double w_hi = in(w2, c + nxy);
                 const double idzk = idz_t[k];
                 // values read by this lane only: streaming loads
-                const double r2c = ld_stream(r2 + c), Rt = ld_stream(R_t + c), Rr = ld_stream(R_r + c);
+                const double r2c = kZero ? 0.0 : (double)ld_stream(r2 + c);
+                const double Rt = ld_stream(R_t + c), Rr = ld_stream(R_r + c);
                 const double that = Tc + dt * (-hdiv_t - b1 * (w_hi * tfk1 - w_lo * tfk) * idzk + Rt);
                 const double rhat = r2c + dt * (-hdiv_r - b1 * (w_hi - w_lo) * idzk + Rr);
                 const double e = b1 * Tc + b2 * that, f = b1 * r2c + b2 * rhat;
@@ -288,7 +309,7 @@ __device__ __forceinline__ void substep_explicit(
 // One fused acoustic substep.  blockDim = (64, KG), kLevels levels per
 // wavefront; dynamic LDS holds the (nz + 1) x 64 solve buffer and the
 // chunk-boundary values.
-template <typename T, int kLevels, bool kLast>
+template <typename T, int kLevels, bool kLast, bool kZero>
 __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
 {
     extern __shared__ double lds[];
@@ -341,7 +362,7 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
     };
 
     // ---------------- phase 1: explicit work, W'' right-hand sides ----------
-    substep_explicit<T, kLevels, kLast>(a.t_u, a.t_v, a.T2cur, a.T2prv, a.pit, a.tht, a.u2in, a.v2in, a.R_u, a.R_v, a.R_t, a.R_r, a.R_w,
+    substep_explicit<T, kLevels, kLast, kZero>(a.t_u, a.t_v, a.T2cur, a.T2prv, a.pit, a.tht, a.u2in, a.v2in, a.R_u, a.R_v, a.R_t, a.R_r, a.R_w,
                                  a.w2, a.r2, a.cC, a.idz, a.idzf, a.u2out, a.v2out, a.su, a.sv, a.sums, rbuf, bnd,
                                  act, col, nxy, nz, k0, g, lane, o_e, o_w, o_n, o_s, dt, b1, b2, gr, bd, gRd, idx,
                                  idy, D, th, thl, rh, flo, fup, e_first, f_first);
@@ -358,7 +379,8 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
         const double idzf = a.idzf[k];
         const double A = gRd * (0.5 * (a.pit[c - nxy] + a.pit[c]));
         const double C = a.cC[c];
-        rbuf[k * kLanes + lane] = a.w2[c] + dt * (-A * (e_first - e_prev) * idzf + 0.5 * C * (e_first + e_prev) -
+        const double w0 = kZero ? 0.0 : (double)a.w2[c];
+        rbuf[k * kLanes + lane] = w0 + dt * (-A * (e_first - e_prev) * idzf + 0.5 * C * (e_first + e_prev) -
                                                   0.5 * gr * (f_first + f_prev) + a.R_w[c]);
         if constexpr (kPre) row_at(k, flo[0], fup[0]);
     }
@@ -483,10 +505,12 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
                     st_stream(a.o_t + c, (T)((double)ld_stream(a.t_t + c) + (double)(T)Tn));
                     st_stream(a.o_r + c, (T)((double)ld_stream(a.t_r + c) + (double)(T)rn));
                     const int cw = k >= 1 ? c : col;  // face k, or the bottom lid
-                    st_stream(a.o_w + cw, (T)((double)ld_stream(a.t_w + cw) + (double)(k >= 1 ? (T)wk : a.w2[cw])));
+                    const T wlid_lo = kZero ? (T)0 : a.w2[cw];
+                    st_stream(a.o_w + cw, (T)((double)ld_stream(a.t_w + cw) + (double)(k >= 1 ? (T)wk : wlid_lo)));
                     if (k == nz - 1) {
                         const int ct = col + nz * nxy;
-                        st_stream(a.o_w + ct, (T)((double)ld_stream(a.t_w + ct) + (double)a.w2[ct]));
+                        const T wlid_hi = kZero ? (T)0 : a.w2[ct];
+                        st_stream(a.o_w + ct, (T)((double)ld_stream(a.t_w + ct) + (double)wlid_hi));
                     }
                 } else {
                     st_stream(a.T2nxt + c, (T)Tn);
@@ -547,6 +571,33 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs<T> a)
 }  // namespace
 
 namespace {
+// one substep launch: the instance for the level count, the stage end and a
+// zero S'' on entry
+template <typename T, int L>
+void launch_substep(bool last, bool zero, dim3 grid, dim3 block, size_t lds, hipStream_t st, const StageArgs<T> &a)
+{
+    if (zero && last)
+        hipLaunchKernelGGL((k_substep<T, L, true, true>), grid, block, lds, st, a);
+    else if (zero)
+        hipLaunchKernelGGL((k_substep<T, L, false, true>), grid, block, lds, st, a);
+    else if (last)
+        hipLaunchKernelGGL((k_substep<T, L, true, false>), grid, block, lds, st, a);
+    else
+        hipLaunchKernelGGL((k_substep<T, L, false, false>), grid, block, lds, st, a);
+}
+
+template <typename T, int L>
+hipError_t allow_lds(size_t lds)
+{
+    const void *fn[4] = {(const void *)k_substep<T, L, false, false>, (const void *)k_substep<T, L, true, false>,
+                         (const void *)k_substep<T, L, false, true>, (const void *)k_substep<T, L, true, true>};
+    for (const void *f : fn) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template <typename T>
 hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const St_[5], const void *const Rt_[5],
                       int n_sub, double dtau, void *const Sout_[5], T *Fu, T *Fv, T *Fw)
@@ -605,8 +656,10 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
     // (no separate finalize pass over the five fields)
     const bool fuse_end = !a.sums;
     a.o_r = Sout[0]; a.o_t = Sout[1]; a.o_u = Sout[2]; a.o_v = Sout[3]; a.o_w = Sout[4];
-    const void *kfn[2] = {L == 8 ? (const void *)k_substep<T, 8, false> : (const void *)k_substep<T, 16, false>,
-                          L == 8 ? (const void *)k_substep<T, 8, true> : (const void *)k_substep<T, 16, true>};
+    // S^t = S^n and one substep (the first RK3 stage): S'' = 0 throughout the
+    // stage init and the substep's inputs, neither stored nor read
+    bool zero = n_sub == 1;
+    for (int f = 0; f < 5; ++f) zero = zero && Sn[f] == St[f];
 
     int t_cur = 0, t_prv = 2, u_in = 0;  // Theta'' rotates over 3 buffers, U'' and V'' over 2
     T *t2[3] = {(T *)w.t2[0], (T *)w.t2[1], (T *)w.t2[2]};
@@ -615,15 +668,19 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
     a.u2in = u2[0];
     a.v2in = v2[0];
 
-    if (lds > 64 * 1024)
-        for (const void *fn : kfn) {
-            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-        }
+    if (lds > 64 * 1024) {
+        const hipError_t e = L == 8 ? allow_lds<T, 8>(lds) : allow_lds<T, 16>(lds);
+        if (e != hipSuccess) return e;
+    }
     dim3 blk(64, 4, 1);
     dim3 g3w((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz + 1);
     dim3 g2((d.nx + 63) / 64, (d.ny + 3) / 4, 1);
-    timing_start(cx, K_STAGE_INIT); hipLaunchKernelGGL(k_stage_init<T>, g3w, blk, 0, cx->stream, a); timing_stop(cx, K_STAGE_INIT);
+    timing_start(cx, K_STAGE_INIT);
+    if (zero)
+        hipLaunchKernelGGL((k_stage_init<T, true>), g3w, blk, 0, cx->stream, a);
+    else
+        hipLaunchKernelGGL((k_stage_init<T, false>), g3w, blk, 0, cx->stream, a);
+    timing_stop(cx, K_STAGE_INIT);
     timing_start(cx, K_COEF); hipLaunchKernelGGL(k_coef<T>, g2, blk, 0, cx->stream, a); timing_stop(cx, K_COEF);
     for (int s = 0; s < n_sub; ++s) {
         const int t_nxt = 3 - t_cur - t_prv;
@@ -642,14 +699,10 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
         }
         const dim3 grid(a.ntx * a.nty), block(kLanes, KG);
         timing_start(cx, K_SUBSTEP);
-        if (L == 8 && !last)
-            hipLaunchKernelGGL((k_substep<T, 8, false>), grid, block, lds, cx->stream, a);
-        else if (L == 8)
-            hipLaunchKernelGGL((k_substep<T, 8, true>), grid, block, lds, cx->stream, a);
-        else if (!last)
-            hipLaunchKernelGGL((k_substep<T, 16, false>), grid, block, lds, cx->stream, a);
+        if (L == 8)
+            launch_substep<T, 8>(last, zero && s == 0, grid, block, lds, cx->stream, a);
         else
-            hipLaunchKernelGGL((k_substep<T, 16, true>), grid, block, lds, cx->stream, a);
+            launch_substep<T, 16>(last, zero && s == 0, grid, block, lds, cx->stream, a);
         timing_stop(cx, K_SUBSTEP);
         t_prv = t_cur;
         t_cur = t_nxt;

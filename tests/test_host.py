@@ -29,10 +29,11 @@ def test_bench_constants():
     assert bench._kernel_bytes("substep", 1, "fp64") == 20 * 8
     assert bench._kernel_bytes("substep", 1, "fp32") == 19 * 4 + 1 * 8
     # whole step of the 14-substep boundary layer: 22 substeps of 20 values,
-    # 5 more in each stage's last, 48 + 17 + 5 per stage
+    # 5 more in each stage's last, 48 + 17 + 5 per stage; the first stage,
+    # with S'' = 0 on entry, moves 13 + 6 values fewer
     cfg = bench._cfg("cbl")
     bulk, f64 = bench._step_values(cfg)
-    assert bulk + f64 == 22 * 20 + 3 * 5 + 3 * (48 + 17 + 5)
+    assert bulk + f64 == 22 * 20 + 3 * 5 + 3 * (48 + 17 + 5) - 19
     assert bench._one_pass_values(cfg) == 13 * 5 + 6 + 22 * (3 * 5 + 3)
 
 
