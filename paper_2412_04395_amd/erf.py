@@ -323,12 +323,18 @@ class Solver:
         self._check(self.L.erf_slow_rhs(self.h, C.byref(self._st(S)), C.byref(self._st(R))), "erf_slow_rhs")
         return R
 
-    def acoustic_substeps(self, Sn, St, Rt, n_sub: int, dtau: float, out=None, flux=None):
+    def acoustic_substeps(self, Sn, St, Rt, n_sub: int, dtau: float, out=None, flux=None, sums: bool = True):
+        """erf_acoustic_substeps; with sums=False no stage-averaged momenta are
+        kept (flux_avg = NULL) and the returned flux is None."""
         out = self.empty_state() if out is None else out
-        flux = self.empty_state() if flux is None else flux
+        if sums:
+            flux = self.empty_state() if flux is None else flux
+            fp = C.byref(self._st(flux))
+        else:
+            flux, fp = None, None
         self._check(self.L.erf_acoustic_substeps(self.h, C.byref(self._st(Sn)), C.byref(self._st(St)),
                                                  C.byref(self._st(Rt)), int(n_sub), float(dtau),
-                                                 C.byref(self._st(out)), C.byref(self._st(flux))),
+                                                 C.byref(self._st(out)), fp),
                     "erf_acoustic_substeps")
         return out, flux
 

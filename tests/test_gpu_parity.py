@@ -168,6 +168,34 @@ def test_acoustic_substeps_parity(case, nsub):
         assert e <= CALL_TOL, (name, e)
 
 
+@pytest.mark.parametrize("case,nsub,sums", [("small_o53", 1, True), ("small_o53", 1, False), ("one_column", 1, False),
+                                            ("max_nz", 1, False), ("small_o53", 2, False)])
+def test_acoustic_from_the_stage_state(case, nsub, sums):
+    """S^n and S^t the same arrays (the first RK3 stage): with one substep S''
+    starts at zero and is neither stored nor read.  The stage end must equal,
+    bit for bit, that of S^n passed as a separate copy of S^t (the general
+    path), and the oracle's."""
+    cfg = W.small(**CASES[case])
+    _say("acoustic from S^t", case, nsub, sums)
+    o, s, th0, b = _sides(cfg)
+    St = _rough_state(cfg, b, th0, seed=500)
+    Rt = o.slow_rhs(St)
+    dtau = cfg.dt / cfg.n_substeps if nsub > 1 else cfg.dt / 3.0
+    out_ref, F_ref = o.acoustic_substeps(St, St, Rt, nsub, dtau)
+    Sd, Rd = s.to_device(St), s.to_device(Rt)
+    out, F = s.acoustic_substeps(Sd, Sd, Rd, nsub, dtau, sums=sums)
+    out_copy, F_copy = s.acoustic_substeps(s.to_device(St), Sd, Rd, nsub, dtau, sums=sums)
+    out, out_copy = s.to_numpy(out), s.to_numpy(out_copy)
+    for f in ("rho", "rt", "ru", "rv", "rw"):
+        assert np.array_equal(out[f], out_copy[f]), f
+    _compare(f"acoustic_from_St[{case},{nsub}]", _pert(out, b), _pert(out_ref, b), CALL_TOL, full=out_ref)
+    if sums:
+        F, F_copy = s.to_numpy(F), s.to_numpy(F_copy)
+        for name, a, r in zip(("ru", "rv", "rw"), (F["ru"], F["rv"], F["rw"]), F_ref):
+            assert np.array_equal(a, F_copy[name]), name
+            assert _rel(a, r) <= CALL_TOL, name
+
+
 @pytest.mark.parametrize("scheme,order", [(1, 3), (0, 5), (0, 2), (0, 6)])
 def test_scalar_advance_parity(scheme, order):
     cfg = W.small(n_scalars=3, scalar_scheme=scheme, adv_order_h=order, adv_order_v=order)
