@@ -59,23 +59,24 @@ __global__ __launch_bounds__(256) void k_prep(RhsArgs<T> a)
     // every load first (neighbour indices clamped, so all are valid), then the stores
     const int cw = cidx(d, i == 0 ? d.nx - 1 : i - 1, j, k), cs = cidx(d, i, j == 0 ? d.ny - 1 : j - 1, k);
     const int kb = k > 0 ? k - 1 : 0, cb = c - (k - kb) * d.nxy;
-    const double r0 = a.rho0[k], T0 = a.Theta0[k], r0b = a.rho0[kb];
+    const double r0 = a.rho0[k], T0 = a.Theta0[k], r0b = a.rho0[kb], p0k = a.p0[k];
     const double r = full_of(a.rho, c, r0), rw_ = full_of(a.rho, cw, r0), rs = full_of(a.rho, cs, r0);
     const double rb = full_of(a.rho, cb, r0b);
     const double Tf = full_of(a.rt, c, T0), Tp = pert_of(a.rt, c, T0);
     const double U = a.ru[c], V = a.rv[c], Wc = a.rw[c];
     const double th = Tf / r;
-    // p' = p0 ((Theta/Theta0)^gamma - 1) without cancellation (EOS, Sec. 2.1)
-    const double pp = a.p0[k] * expm1(kGamma * log1p(Tp / T0));
     const double w = (k == 0) ? 0.0 : Wc / (0.5 * (rb + r));
     // outputs are read by later launches only: streaming stores, so that no
-    // dirty lines are left in the caches for the next kernel to write back
+    // dirty lines are left in the caches for the next kernel to write back.
+    // The divisions are stored before the EOS, whose library calls branch:
+    // a store keeps every load of the thread ahead of it.
     st_stream(a.th + c, kPert<T> ? (T)(th - a.theta0[k]) : (T)th);
-    st_stream(a.pp + c, (T)pp);
     st_stream(a.u + c, (T)(U / (0.5 * (rw_ + r))));
     st_stream(a.v + c, (T)(V / (0.5 * (rs + r))));
     st_stream(a.w + c, (T)w);
     if (k == d.nz - 1) a.w[c + d.nxy] = 0.0;
+    // p' = p0 ((Theta/Theta0)^gamma - 1) without cancellation (EOS, Sec. 2.1)
+    st_stream(a.pp + c, (T)(p0k * expm1(kGamma * log1p(Tp / T0))));
 }
 
 // ---------------------------------------------------------------------------
@@ -148,8 +149,10 @@ __global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
 // Stresses tau = -2 mu (S - D) at their points, mu = rho nu_m + mu_t averaged
 // from the four cells around an edge; heat diffusivity rho alpha_m + mu_t/Pr_t.
 // z runs to nz for the shear stresses on the top faces (zero: free slip).
+// (at most 4 wavefronts per SIMD: the register budget lets the scheduler issue
+// all 27 gathers at once instead of in two dependent groups)
 template <typename T>
-__global__ __launch_bounds__(256) void k_stress(RhsArgs<T> a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void k_stress(RhsArgs<T> a)
 {
     const Dims &d = a.d;
     const TileIdx t = tile_cell(a.ntx, a.nty);
@@ -186,22 +189,25 @@ __global__ __launch_bounds__(256) void k_stress(RhsArgs<T> a)
     const double s23 = 0.5 * ((v_f - v_fb) * idzf + (w_f - w_fs) * a.idy);
     const double mxz = 0.25 * (m_bw + m_b + m_w + m_c);
     const double myz = 0.25 * (m_bs + m_b + m_s + m_c);
-    st_stream(a.t13 + lf + rj + i, (T)(inner ? -2.0 * mxz * s13 : 0.0));
-    st_stream(a.t23 + lf + rj + i, (T)(inner ? -2.0 * myz * s23 : 0.0));
-    if (k == nz) return;
-    const double idz = a.idz[k];
+    // centre values of the level (the top face plane computes them for
+    // level nz - 1 again and does not store them)
+    const double idz = a.idz[kc];
     const double e11 = (u_e - u_f) * a.idx;
     const double e22 = (v_n - v_f) * a.idy;
     const double e33 = (w_u - w_c) * idz;
     const double dd = (e11 + e22 + e33) / 3.0;
-    const int c = lc + rj + i;
-    st_stream(a.t11 + c, (T)(-2.0 * m_c * (e11 - dd)));
-    st_stream(a.t22 + c, (T)(-2.0 * m_c * (e22 - dd)));
-    st_stream(a.t33 + c, (T)(-2.0 * m_c * (e33 - dd)));
     const double s12 = 0.5 * ((u_f - u_s) * a.idy + (v_f - v_w) * a.idx);
     const double me = 0.25 * (m_ws + m_s + m_w + m_c);
-    st_stream(a.t12 + c, (T)(-2.0 * me * s12));
-    st_stream(a.kap + c, (T)(rc * a.alpha + (sgs ? mtc / a.Pr_t : 0.0)));
+    st_stream(a.t13 + lf + rj + i, (T)(inner ? -2.0 * mxz * s13 : 0.0));
+    st_stream(a.t23 + lf + rj + i, (T)(inner ? -2.0 * myz * s23 : 0.0));
+    if (k < nz) {
+        const int c = lc + rj + i;
+        st_stream(a.t11 + c, (T)(-2.0 * m_c * (e11 - dd)));
+        st_stream(a.t22 + c, (T)(-2.0 * m_c * (e22 - dd)));
+        st_stream(a.t33 + c, (T)(-2.0 * m_c * (e33 - dd)));
+        st_stream(a.t12 + c, (T)(-2.0 * me * s12));
+        st_stream(a.kap + c, (T)(rc * a.alpha + (sgs ? mtc / a.Pr_t : 0.0)));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -229,8 +235,11 @@ __device__ __forceinline__ double interp(int order, const double (&q)[7], int o,
 // into it; the periodic and reflected indices are then selects instead of
 // branches, and every load of a section can be issued before its arithmetic.
 // kVisc: the viscous and diffusive terms (stress and diffusivity arrays).
+// Three wavefronts per SIMD (the occupancy its registers give anyway): told
+// so, the scheduler keeps each section's gathers in a few large groups
+// rather than trading round trips for registers.
 template <typename T, int OH, int OV, bool kNear, bool kVisc>
-__global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_rhs(RhsArgs<T> a)
 {
     const Dims &d = a.d;
     const TileIdx tc = tile_cell(a.ntx, a.nty);
@@ -270,6 +279,10 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
     };
     // the cell below, clamped at the bottom (its values unused there)
     const int dn = k > 0 ? P : 0;
+    // 1 away from the bottom (top) lid, 0 on it: the lid fluxes are masked by
+    // a product rather than a conditional, which the compiler would make a
+    // branch with part of the stencil loads behind it
+    const double not_bot = (double)(k > 0), not_top = (double)(k < nz - 1);
     const double idz = a.idz[k];
     const int oh = a.oh, ov = a.ov;
     double q[7];
@@ -292,8 +305,8 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
         const double fy0 = V0 * interp<OH>(oh, q, 0, sign_of(V0)), fy1 = V1 * interp<OH>(oh, q, 1, sign_of(V1));
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = thz0(t) + th[c + ozc(t)];
-        const double fz0 = (k == 0) ? 0.0 : W0 * interp<OV>(ov, q, 0, sign_of(W0));
-        const double fz1 = (k == nz - 1) ? 0.0 : W1 * interp<OV>(ov, q, 1, sign_of(W1));
+        const double fz0 = W0 * interp<OV>(ov, q, 0, sign_of(W0)) * not_bot;
+        const double fz1 = W1 * interp<OV>(ov, q, 1, sign_of(W1)) * not_top;
         double r = -((fx1 - fx0) * a.idx + (fy1 - fy0) * a.idy + (fz1 - fz0) * idz);
         if constexpr (kVisc) {
             const T *kp = a.kap;
@@ -304,8 +317,8 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
             const double hy0 = -0.5 * (kp[c + oy(2)] + kc) * (thc - (th0k + th[c + oy(2)])) * a.idy;
             const double hy1 = -0.5 * (kc + kp[c + oy(4)]) * ((th0k + th[c + oy(4)]) - thc) * a.idy;
             const double kb = kp[c - dn], tb = th[c - dn], ka = kp[c + up], ta = th[c + up];
-            const double hz0 = k > 0 ? -0.5 * (kb + kc) * (thc - (thz0(2) + tb)) * a.idzf[k] : 0.0;
-            const double hz1 = k < nz - 1 ? -0.5 * (kc + ka) * ((thz0(4) + ta) - thc) * a.idzf[k + 1] : 0.0;
+            const double hz0 = -0.5 * (kb + kc) * (thc - (thz0(2) + tb)) * a.idzf[k] * not_bot;
+            const double hz1 = -0.5 * (kc + ka) * ((thz0(4) + ta) - thc) * a.idzf[k + 1] * not_top;
             r -= (hx1 - hx0) * a.idx + (hy1 - hy0) * a.idy + (hz1 - hz0) * idz;
         }
         if (k == 0 && a.Qs != 0.0) r += rc * a.Qs * idz;
@@ -329,8 +342,8 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
         for (int t = 0; t < 7; ++t) q[t] = u[c + ozc(t)];
         // z-face momenta (faces 0..nz all exist; the lid fluxes are zero)
         const double e0 = 0.5 * (a.rw[c + ox(2)] + W0), e1 = 0.5 * (a.rw[c + ox(2) + P] + W1);
-        const double fxz0 = k > 0 ? e0 * interp<OV>(ov, q, 0, sign_of(e0)) : 0.0;
-        const double fxz1 = k < nz - 1 ? e1 * interp<OV>(ov, q, 1, sign_of(e1)) : 0.0;
+        const double fxz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0)) * not_bot;
+        const double fxz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1)) * not_top;
         const double adv = (fxx_r - fxx_l) * a.idx + (fxy1 - fxy0) * a.idy + (fxz1 - fxz0) * idz;
         const double pgf = (a.pp[c] - a.pp[c + ox(2)]) * a.idx;
         const double rho_f = 0.5 * (full_of(a.rho, c + ox(2), r0k) + rc);
@@ -358,8 +371,8 @@ __global__ __launch_bounds__(256) void k_rhs(RhsArgs<T> a)
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = v[c + ozc(t)];
         const double e0 = 0.5 * (a.rw[c + oy(2)] + W0), e1 = 0.5 * (a.rw[c + oy(2) + P] + W1);
-        const double fyz0 = k > 0 ? e0 * interp<OV>(ov, q, 0, sign_of(e0)) : 0.0;
-        const double fyz1 = k < nz - 1 ? e1 * interp<OV>(ov, q, 1, sign_of(e1)) : 0.0;
+        const double fyz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0)) * not_bot;
+        const double fyz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1)) * not_top;
         const double adv = (fyx1 - fyx0) * a.idx + (fyy_r - fyy_l) * a.idy + (fyz1 - fyz0) * idz;
         const double pgf = (a.pp[c] - a.pp[c + oy(2)]) * a.idy;
         const double rho_f = 0.5 * (full_of(a.rho, c + oy(2), r0k) + rc);
