@@ -463,6 +463,11 @@ struct DivArgs {
 
 // tau_12 on xy-edges, tau_13 / tau_23 on the z-face edges (zero on the lids)
 // and the heat fluxes on faces are 4-cell and 2-cell means of the centre values.
+// Every load first (periodic neighbours by selects, levels clamped into the
+// column, the lid terms masked by a 0/1 product rather than a conditional),
+// then the arithmetic, then the stores: with a store or a branch between them
+// the compiler splits the loads into dependent groups.  The tendencies are
+// read by later launches only: streaming stores.
 template <typename T>
 __global__ __launch_bounds__(256) void k_mlp_div(DivArgs<T> a)
 {
@@ -470,39 +475,51 @@ __global__ __launch_bounds__(256) void k_mlp_div(DivArgs<T> a)
     const TileIdx tc = tile_cell(a.ntx, a.nty);
     const int i = tc.i, j = tc.j, k = tc.k;
     if (i >= d.nx || j >= d.ny) return;
-    const int nz = d.nz;
-    auto S = [&](int o, int ii, int jj, int kk) {
-        return (double)a.s[o][cidx(d, wrap_idx(ii, d.nx), wrap_idx(jj, d.ny), kk)];
-    };
-    auto e12 = [&](int ii, int jj) {
-        return 0.25 * (S(3, ii - 1, jj - 1, k) + S(3, ii, jj - 1, k) + S(3, ii - 1, jj, k) + S(3, ii, jj, k));
-    };
-    auto e13 = [&](int ii, int kk) {
-        if (kk <= 0 || kk >= nz) return 0.0;
-        return 0.25 * (S(4, ii - 1, j, kk - 1) + S(4, ii, j, kk - 1) + S(4, ii - 1, j, kk) + S(4, ii, j, kk));
-    };
-    auto e23 = [&](int jj, int kk) {
-        if (kk <= 0 || kk >= nz) return 0.0;
-        return 0.25 * (S(5, i, jj - 1, kk - 1) + S(5, i, jj, kk - 1) + S(5, i, jj - 1, kk) + S(5, i, jj, kk));
-    };
+    const int nz = d.nz, nx = d.nx, P = d.nxy;
+    const int xm = (i == 0 ? nx - 1 : i - 1) - i, xp = (i == nx - 1 ? 0 : i + 1) - i;
+    const int ym = ((j == 0 ? d.ny - 1 : j - 1) - j) * nx, yp = ((j == d.ny - 1 ? 0 : j + 1) - j) * nx;
+    const int dn = k > 0 ? P : 0, up = k < nz - 1 ? P : 0;  // the levels below, above (clamped)
+    const double not_bot = (double)(k > 0), not_top = (double)(k < nz - 1);
     const int c = cidx(d, i, j, k);
+    auto L = [&](int o, int cc) { return (double)a.s[o][cc]; };
+    // tau_11, tau_22, tau_33 at the centres
+    const double s0c = L(0, c), s0w = L(0, c + xm), s1c = L(1, c), s1s = L(1, c + ym);
+    const double s2c = L(2, c), s2b = L(2, c - dn);
+    // S_12 at the four centres around an edge, for the edges (i, j), (i, j+1), (i+1, j)
+    const double a_ws = L(3, c + xm + ym), a_s = L(3, c + ym), a_w = L(3, c + xm), a_c = L(3, c);
+    const double a_wn = L(3, c + xm + yp), a_n = L(3, c + yp), a_es = L(3, c + xp + ym), a_e = L(3, c + xp);
+    // S_13 around the edges of face k (x: i, i+1) and face k+1 (x: i)
+    const double b_wb = L(4, c + xm - dn), b_b = L(4, c - dn), b_w = L(4, c + xm), b_c = L(4, c);
+    const double b_wu = L(4, c + xm + up), b_u = L(4, c + up), b_eb = L(4, c + xp - dn), b_e = L(4, c + xp);
+    // S_23 likewise with y
+    const double g_sb = L(5, c + ym - dn), g_b = L(5, c - dn), g_s = L(5, c + ym), g_c = L(5, c);
+    const double g_su = L(5, c + ym + up), g_u = L(5, c + up), g_nb = L(5, c + yp - dn), g_n = L(5, c + yp);
+    // heat fluxes at the centres
+    const double h6w = L(6, c + xm), h6c = L(6, c), h6e = L(6, c + xp);
+    const double h7s = L(7, c + ym), h7c = L(7, c), h7n = L(7, c + yp);
+    const double h8b = L(8, c - dn), h8c = L(8, c), h8u = L(8, c + up);
+    const double Ru = a.Ru[c], Rv = a.Rv[c], Rw = a.Rw[c], Rt = a.Rt[c];
+
     const double idz = a.idz[k];
-    const double du = (S(0, i, j, k) - S(0, i - 1, j, k)) * a.idx + (e12(i, j + 1) - e12(i, j)) * a.idy +
-                      (e13(i, k + 1) - e13(i, k)) * idz;
-    const double dv = (e12(i + 1, j) - e12(i, j)) * a.idx + (S(1, i, j, k) - S(1, i, j - 1, k)) * a.idy +
-                      (e23(j, k + 1) - e23(j, k)) * idz;
-    a.Ru[c] = (T)((double)a.Ru[c] - du);
-    a.Rv[c] = (T)((double)a.Rv[c] - dv);
-    if (k > 0) {
-        const double dw = (e13(i + 1, k) - e13(i, k)) * a.idx + (e23(j + 1, k) - e23(j, k)) * a.idy +
-                          (S(2, i, j, k) - S(2, i, j, k - 1)) * a.idzf[k];
-        a.Rw[c] = (T)((double)a.Rw[c] - dw);
-    }
-    const double hx0 = 0.5 * (S(6, i - 1, j, k) + S(6, i, j, k)), hx1 = 0.5 * (S(6, i, j, k) + S(6, i + 1, j, k));
-    const double hy0 = 0.5 * (S(7, i, j - 1, k) + S(7, i, j, k)), hy1 = 0.5 * (S(7, i, j, k) + S(7, i, j + 1, k));
-    const double hz0 = k == 0 ? 0.0 : 0.5 * (S(8, i, j, k - 1) + S(8, i, j, k));
-    const double hz1 = k == nz - 1 ? 0.0 : 0.5 * (S(8, i, j, k) + S(8, i, j, k + 1));
-    a.Rt[c] = (T)((double)a.Rt[c] - ((hx1 - hx0) * a.idx + (hy1 - hy0) * a.idy + (hz1 - hz0) * idz));
+    const double e12 = 0.25 * (a_ws + a_s + a_w + a_c);    // edge (i, j)
+    const double e12n = 0.25 * (a_w + a_c + a_wn + a_n);   // edge (i, j+1)
+    const double e12e = 0.25 * (a_s + a_es + a_c + a_e);   // edge (i+1, j)
+    const double e13 = 0.25 * (b_wb + b_b + b_w + b_c) * not_bot;   // face k
+    const double e13u = 0.25 * (b_w + b_c + b_wu + b_u) * not_top;  // face k+1
+    const double e13e = 0.25 * (b_b + b_eb + b_c + b_e) * not_bot;  // face k, i+1
+    const double e23 = 0.25 * (g_sb + g_b + g_s + g_c) * not_bot;
+    const double e23u = 0.25 * (g_s + g_c + g_su + g_u) * not_top;
+    const double e23n = 0.25 * (g_b + g_nb + g_c + g_n) * not_bot;
+    const double du = (s0c - s0w) * a.idx + (e12n - e12) * a.idy + (e13u - e13) * idz;
+    const double dv = (e12e - e12) * a.idx + (s1c - s1s) * a.idy + (e23u - e23) * idz;
+    const double dw = (e13e - e13) * a.idx + (e23n - e23) * a.idy + (s2c - s2b) * a.idzf[k];
+    const double hx0 = 0.5 * (h6w + h6c), hx1 = 0.5 * (h6c + h6e);
+    const double hy0 = 0.5 * (h7s + h7c), hy1 = 0.5 * (h7c + h7n);
+    const double hz0 = 0.5 * (h8b + h8c) * not_bot, hz1 = 0.5 * (h8c + h8u) * not_top;
+    st_stream(a.Ru + c, (T)(Ru - du));
+    st_stream(a.Rv + c, (T)(Rv - dv));
+    if (k > 0) st_stream(a.Rw + c, (T)(Rw - dw));  // the bottom lid face keeps its tendency
+    st_stream(a.Rt + c, (T)(Rt - ((hx1 - hx0) * a.idx + (hy1 - hy0) * a.idy + (hz1 - hz0) * idz)));
 }
 
 // ---------------------------------------------------------------------------
