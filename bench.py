@@ -69,6 +69,10 @@ KERNEL_VALUES = {
     # S^t and S'' read; S_out written
     "finalize": lambda sgs: (10 + 5, 0),
 }
+# Advected scalars (nq of them), per cell of one launch: the mixing ratios
+# q^t = (rho q)^t / rho^t (rho q and rho read, q written); the scalar update
+# (q, the three averaged momenta and (rho q)^n read, (rho q)^new written).
+SCALAR_VALUES = {"mixing_ratio": lambda nq: (2 * nq + 1, 0), "scalar": lambda nq: (3 * nq + 3, 0)}
 # The first RK3 stage starts from S^t = S^n with one substep, so S'' = 0 on
 # entry: its stage init moves only Theta^t, rho^t in and theta^t, Exner out
 # (13 bulk values fewer) and its substep reads none of the 6 S'' inputs
@@ -136,7 +140,7 @@ def run_gpu(cfg: W.Config, steps: int, warmup: int):
     tune = s.autotune(S, trials=2, cache_path=_tune_cache())
     # find the kernel with the largest share of a step (one short timed step per kernel)
     shares = {}
-    for k in KERNEL_VALUES:
+    for k in list(KERNEL_VALUES) + (list(SCALAR_VALUES) if cfg.n_scalars else []):
         if k == "mut" and not cfg.sgs:
             continue
         _, (ms, n) = _time_steps(s, S, 1, torch, kernel=k)
@@ -365,6 +369,13 @@ def _step_values(cfg):
         f64 += n * f
     if not cfg.n_scalars:
         bulk += 3 * 5  # the stage end written by the last substep of each stage
+    if cfg.n_scalars:
+        # flux sums for the scalar transport: read and written by every
+        # substep, zeroed by each stage init; the finalize then also reads
+        # them and W^n and writes the averaged momenta (22 values, not 15)
+        bulk += 6 * counts["substep"] + 3 * 3 + 3 * (22 - 15)
+        for f in SCALAR_VALUES.values():
+            bulk += 3 * f(cfg.n_scalars)[0]
     return bulk, f64
 
 
@@ -407,6 +418,28 @@ def _step_roofline(cfg, ms_per_step: float, copy_gbs: float) -> dict:
             "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4)}
 
 
+def run_scalars(steps: int, warmup: int) -> dict:
+    """The 80-level deep-atmosphere workload: 512 x 512 x 80, FP32 storage, three
+    tracers advected by WENO5 after every stage (the scalar-heavy case)."""
+    cfg = W.deep()
+    el, dom, kms, kn, shares, diag = run_gpu(cfg, steps, warmup)
+    out = {"workload": "deep atmosphere 512x512x80, stretched dz, 3 WENO5 tracers", "grid": [cfg.nx, cfg.ny, cfg.nz],
+           "precision": "FP32 storage, FP64 arithmetic, solve and sums", "n_scalars": cfg.n_scalars,
+           "n_substeps": cfg.n_substeps, "value": cfg.cells * steps / el, "unit": "cell-updates/s",
+           "ms_per_step": 1e3 * el / steps, "substep_shape": diag["substep_shape"],
+           "kernel_ms_per_step": {k: round(v[0], 4) for k, v in shares.items()},
+           "nonfinite": diag["nonfinite"]}
+    if "scalar" in shares:
+        ms, n = shares["scalar"]
+        us = 1e3 * ms / n
+        byts = SCALAR_VALUES["scalar"](cfg.n_scalars)[0] * 4.0 * cfg.cells
+        out["scalar_kernel"] = {"us_per_launch": round(us, 1), "algorithmic_bytes_per_launch": byts,
+                                "achieved_gbs": round(byts / (us * 1e-6) / 1e9, 1),
+                                "frac": round(byts / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    out["step_roofline"] = _step_roofline(cfg, 1e3 * el / steps, _copy_gbs())
+    return out
+
+
 def _substep_value_adjust(cfg) -> float:
     """Bulk values per cell by which the average substep launch of a step
     differs from KERNEL_VALUES: +5 for the one per stage that writes the stage
@@ -443,6 +476,7 @@ def main(argv=None):
     ap.add_argument("--no-closure", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-training", action="store_true")
+    ap.add_argument("--no-scalars", action="store_true")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first run one plain device copy of this many GiB (reference for HBM counters)")
     a = ap.parse_args(argv)
@@ -507,6 +541,8 @@ def main(argv=None):
         out["closure"] = run_closure(a.steps, a.warmup)
     if a.workload == "cbl" and not a.no_training:
         out["training"] = run_training(a.steps)
+    if a.workload == "cbl" and not a.no_scalars:
+        out["scalars"] = run_scalars(min(a.steps, 10), min(a.warmup, 2))
     if a.workload == "cbl" and not a.no_ensemble:
         out["ensemble"] = run_ensemble(min(a.steps, 5), min(a.warmup, 1))
     if rank == 0 and not a.no_cpu_baseline:

@@ -172,7 +172,8 @@ __device__ __forceinline__ double pert_of(const T *f, int c, double base)
 }
 
 // Interpolated face value q_{m-1/2} (Sec. 3.6) from q[0..5] = q_{m-3..m+2};
-// s is the sign of the normal momentum at the face.
+// s is the sign of the normal momentum at the face (-1, 0 or 1, so that
+// s * (1/12) and s * (1/60) equal s / 12 and s / 60 exactly).
 __device__ __forceinline__ double face_interp(int order, double qm3, double qm2, double qm1,
                                               double q0, double qp1, double qp2, double s)
 {
@@ -180,11 +181,11 @@ __device__ __forceinline__ double face_interp(int order, double qm3, double qm2,
     if (order == 3 || order == 4) {
         double c4 = 7.0 / 12.0 * (q0 + qm1) - 1.0 / 12.0 * (qp1 + qm2);
         if (order == 4) return c4;
-        return c4 + s / 12.0 * ((qp1 - qm2) - 3.0 * (q0 - qm1));
+        return c4 + s * (1.0 / 12.0) * ((qp1 - qm2) - 3.0 * (q0 - qm1));
     }
     double c6 = 37.0 / 60.0 * (q0 + qm1) - 2.0 / 15.0 * (qp1 + qm2) + 1.0 / 60.0 * (qp2 + qm3);
     if (order == 6) return c6;
-    return c6 - s / 60.0 * ((qp2 - qm3) - 5.0 * (qp1 - qm2) + 10.0 * (q0 - qm1));
+    return c6 - s * (1.0 / 60.0) * ((qp2 - qm3) - 5.0 * (qp1 - qm2) + 10.0 * (q0 - qm1));
 }
 
 // ---------------------------------------------------------------------------

@@ -215,7 +215,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
 // ---------------------------------------------------------------------------
 // q holds q_{-3..3} around the thread's point; the face value q_{m-1/2} uses
 // q_{m-3..m+2}: o = 0 for the face on the low side of the point, o = 1 for the
-// face on the high side.
+// face on the high side.  s is a sign (-1, 0 or 1), so s * (1/12) and
+// s * (1/60) are exactly s / 12 and s / 60, without a division.
 template <int O>
 __device__ __forceinline__ double interp(int order, const double (&q)[7], int o, double s)
 {
@@ -224,10 +225,10 @@ __device__ __forceinline__ double interp(int order, const double (&q)[7], int o,
     if (ord == 2) return 0.5 * (q0 + qm1);
     if (ord == 3 || ord == 4) {
         const double c4 = 7.0 / 12.0 * (q0 + qm1) - 1.0 / 12.0 * (qp1 + qm2);
-        return ord == 4 ? c4 : c4 + s / 12.0 * ((qp1 - qm2) - 3.0 * (q0 - qm1));
+        return ord == 4 ? c4 : c4 + s * (1.0 / 12.0) * ((qp1 - qm2) - 3.0 * (q0 - qm1));
     }
     const double c6 = 37.0 / 60.0 * (q0 + qm1) - 2.0 / 15.0 * (qp1 + qm2) + 1.0 / 60.0 * (qp2 + qm3);
-    return ord == 6 ? c6 : c6 - s / 60.0 * ((qp2 - qm3) - 5.0 * (qp1 - qm2) + 10.0 * (q0 - qm1));
+    return ord == 6 ? c6 : c6 - s * (1.0 / 60.0) * ((qp2 - qm3) - 5.0 * (qp1 - qm2) + 10.0 * (q0 - qm1));
 }
 
 // kNear: the domain is at least 3 cells wide and 3 levels high, so that one

@@ -31,62 +31,88 @@ __global__ __launch_bounds__(256) void k_mixing_ratio(ScalArgs<T> a)
 }
 
 // WENO5-JS face value; v2 is the upwind cell, candidate stencils of three cells
+// with values p_k, smoothness indicators beta_k and weights d_k / (eps +
+// beta_k)^2, d = (0.1, 0.6, 0.3), normalised.  Written over one common
+// denominator: the weights are multiplied by the product of the three (eps +
+// beta)^2 and the 1/6 of the p_k moves into the final quotient, so a face
+// takes one FP64 division instead of seven; equal to the three-weight form up
+// to rounding.
 __device__ __forceinline__ double weno5_face(double v0, double v1, double v2, double v3, double v4)
 {
     const double eps = 1.0e-6;
-    double p0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) / 6.0;
-    double p1 = (-v1 + 5.0 * v2 + 2.0 * v3) / 6.0;
-    double p2 = (2.0 * v2 + 5.0 * v3 - v4) / 6.0;
-    double s0 = v0 - 2.0 * v1 + v2, t0 = v0 - 4.0 * v1 + 3.0 * v2;
-    double s1 = v1 - 2.0 * v2 + v3, t1 = v1 - v3;
-    double s2 = v2 - 2.0 * v3 + v4, t2 = 3.0 * v2 - 4.0 * v3 + v4;
-    double be0 = 13.0 / 12.0 * s0 * s0 + 0.25 * t0 * t0;
-    double be1 = 13.0 / 12.0 * s1 * s1 + 0.25 * t1 * t1;
-    double be2 = 13.0 / 12.0 * s2 * s2 + 0.25 * t2 * t2;
-    double w0 = 0.1 / ((eps + be0) * (eps + be0));
-    double w1 = 0.6 / ((eps + be1) * (eps + be1));
-    double w2 = 0.3 / ((eps + be2) * (eps + be2));
-    return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
+    const double P0 = 2.0 * v0 - 7.0 * v1 + 11.0 * v2;  // 6 p0
+    const double P1 = -v1 + 5.0 * v2 + 2.0 * v3;        // 6 p1
+    const double P2 = 2.0 * v2 + 5.0 * v3 - v4;         // 6 p2
+    const double s0 = v0 - 2.0 * v1 + v2, t0 = v0 - 4.0 * v1 + 3.0 * v2;
+    const double s1 = v1 - 2.0 * v2 + v3, t1 = v1 - v3;
+    const double s2 = v2 - 2.0 * v3 + v4, t2 = 3.0 * v2 - 4.0 * v3 + v4;
+    const double be0 = 13.0 / 12.0 * s0 * s0 + 0.25 * t0 * t0;
+    const double be1 = 13.0 / 12.0 * s1 * s1 + 0.25 * t1 * t1;
+    const double be2 = 13.0 / 12.0 * s2 * s2 + 0.25 * t2 * t2;
+    const double a0 = (eps + be0) * (eps + be0), a1 = (eps + be1) * (eps + be1), a2 = (eps + be2) * (eps + be2);
+    const double w0 = 0.1 * (a1 * a2), w1 = 0.6 * (a0 * a2), w2 = 0.3 * (a0 * a1);
+    return (w0 * P0 + w1 * P1 + w2 * P2) / (6.0 * (w0 + w1 + w2));
 }
 
-template <typename T>
-__device__ __forceinline__ double face_value(const ScalArgs<T> &a, int order, double qm3, double qm2, double qm1,
-                                             double q0, double qp1, double qp2, double s)
-{
-    if (a.weno) {
-        return s >= 0.0 ? weno5_face(qm3, qm2, qm1, q0, qp1) : weno5_face(qp2, qp1, q0, qm1, qm2);
-    }
-    return face_interp(order, qm3, qm2, qm1, q0, qp1, qp2, s);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_scalar(ScalArgs<T> a)
+// One thread per (i, j, k, scalar).  kWeno: WENO5-JS faces, else the
+// interpolant of the run's order.  kNear: the domain is at least 3 cells wide
+// and 3 levels high, so that the periodic wrap and the lid reflection of any
+// stencil offset are selects.  Every load first, the lid fluxes masked by a 0/1
+// product, the upwind candidate stencil picked by selects and evaluated once:
+// with a branch between them (or one per sign, which diverges) the compiler
+// issues the loads in small dependent groups.
+// (At most 4 wavefronts per SIMD: the register budget lets the scheduler keep
+// the 25 loads together instead of trickling them.)
+template <typename T, bool kWeno, bool kNear>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void k_scalar(ScalArgs<T> a)
 {
     const Dims &d = a.d;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int j = blockIdx.y * blockDim.y + threadIdx.y;
     int kq = blockIdx.z;
     if (i >= d.nx || j >= d.ny) return;
-    const int k = kq % d.nz, s = kq / d.nz;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.nxy;
+    const int k = kq % nz, s = kq / nz;
     const int c = cidx(d, i, j, k);
     const T *q = a.q + (size_t)s * d.n;
-    auto qx = [&](int ii) { return (double)q[cidx(d, wrap_idx(ii, d.nx), j, k)]; };
-    auto qy = [&](int jj) { return (double)q[cidx(d, i, wrap_idx(jj, d.ny), k)]; };
-    auto qz = [&](int kk) { return (double)q[cidx(d, i, j, refl_centre(kk, d.nz))]; };
-    double Fx0 = a.Fu[c], Fx1 = a.Fu[cidx(d, wrap_idx(i + 1, d.nx), j, k)];
-    double Fy0 = a.Fv[c], Fy1 = a.Fv[cidx(d, i, wrap_idx(j + 1, d.ny), k)];
-    double Fz0 = a.Fw[c], Fz1 = a.Fw[c + d.nxy];
-    double fx0 = Fx0 * face_value(a, a.oh, qx(i - 3), qx(i - 2), qx(i - 1), qx(i), qx(i + 1), qx(i + 2), sign_of(Fx0));
-    double fx1 = Fx1 * face_value(a, a.oh, qx(i - 2), qx(i - 1), qx(i), qx(i + 1), qx(i + 2), qx(i + 3), sign_of(Fx1));
-    double fy0 = Fy0 * face_value(a, a.oh, qy(j - 3), qy(j - 2), qy(j - 1), qy(j), qy(j + 1), qy(j + 2), sign_of(Fy0));
-    double fy1 = Fy1 * face_value(a, a.oh, qy(j - 2), qy(j - 1), qy(j), qy(j + 1), qy(j + 2), qy(j + 3), sign_of(Fy1));
-    double fz0 = (k == 0) ? 0.0
-                          : Fz0 * face_value(a, a.ov, qz(k - 3), qz(k - 2), qz(k - 1), qz(k), qz(k + 1), qz(k + 2), sign_of(Fz0));
-    double fz1 = (k == d.nz - 1) ? 0.0
-                                 : Fz1 * face_value(a, a.ov, qz(k - 2), qz(k - 1), qz(k), qz(k + 1), qz(k + 2), qz(k + 3), sign_of(Fz1));
-    double div = (fx1 - fx0) / a.dx + (fy1 - fy0) / a.dy + (fz1 - fz0) / a.dz[k];
-    size_t o = (size_t)s * d.n + c;
-    a.out[o] = (double)a.rqn[o] - a.dts * div;
+    auto wrap = [&](int v, int n) { return kNear ? v + (v < 0 ? n : 0) - (v >= n ? n : 0) : wrap_idx(v, n); };
+    auto reflc = [&](int kk) {
+        if constexpr (!kNear) return refl_centre(kk, nz);
+        const int r = kk < 0 ? -1 - kk : kk;
+        return r >= nz ? 2 * nz - 1 - r : r;
+    };
+    // q at offsets -3..3 in x, y and z (z reflected at the lids)
+    double qx[7], qy[7], qz[7];
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+        qx[t] = q[c + (wrap(i + t - 3, nx) - i)];
+        qy[t] = q[c + (wrap(j + t - 3, ny) - j) * nx];
+        qz[t] = q[c + (reflc(k + t - 3) - k) * P];
+    }
+    const double Fx0 = a.Fu[c], Fx1 = a.Fu[c + (wrap(i + 1, nx) - i)];
+    const double Fy0 = a.Fv[c], Fy1 = a.Fv[c + (wrap(j + 1, ny) - j) * nx];
+    const double Fz0 = a.Fw[c], Fz1 = a.Fw[c + P];
+    const size_t o = (size_t)s * d.n + c;
+    const double rq = a.rqn[o];
+    const double not_bot = (double)(k > 0), not_top = (double)(k < nz - 1);
+    // face value on the low (oo = 0) or high (oo = 1) side of the cell,
+    // upwinded by the sign sg of the flux through it
+    auto face = [&](const double (&v)[7], int oo, double sg, int order) {
+        const double qm3 = v[oo], qm2 = v[oo + 1], qm1 = v[oo + 2], q0 = v[oo + 3], qp1 = v[oo + 4], qp2 = v[oo + 5];
+        if constexpr (kWeno) {
+            const bool pos = sg >= 0.0;
+            return weno5_face(pos ? qm3 : qp2, pos ? qm2 : qp1, pos ? qm1 : q0, pos ? q0 : qm1, pos ? qp1 : qm2);
+        } else {
+            return face_interp(order, qm3, qm2, qm1, q0, qp1, qp2, sg);
+        }
+    };
+    const double fx0 = Fx0 * face(qx, 0, sign_of(Fx0), a.oh), fx1 = Fx1 * face(qx, 1, sign_of(Fx1), a.oh);
+    const double fy0 = Fy0 * face(qy, 0, sign_of(Fy0), a.oh), fy1 = Fy1 * face(qy, 1, sign_of(Fy1), a.oh);
+    const double fz0 = Fz0 * face(qz, 0, sign_of(Fz0), a.ov) * not_bot;
+    const double fz1 = Fz1 * face(qz, 1, sign_of(Fz1), a.ov) * not_top;
+    const double div = (fx1 - fx0) / a.dx + (fy1 - fy0) / a.dy + (fz1 - fz0) / a.dz[k];
+    // read by later launches only (and rqn[o], its only other use, is read above)
+    st_stream(a.out + o, (T)(rq - a.dts * div));
 }
 
 }  // namespace
@@ -122,7 +148,17 @@ hipError_t scalar_t(erf_ctx *cx, const void *rqn, const void *rho_t, const void 
     hipLaunchKernelGGL(k_mixing_ratio<T>, dim3((total + 255) / 256), dim3(256), 0, cx->stream, a);
     timing_stop(cx, K_MIXRATIO);
     dim3 blk(64, 4, 1), grd((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz * a.nq);
-    timing_start(cx, K_SCALAR); hipLaunchKernelGGL(k_scalar<T>, grd, blk, 0, cx->stream, a); timing_stop(cx, K_SCALAR);
+    const bool near = d.nx >= 3 && d.ny >= 3 && d.nz >= 3;
+    timing_start(cx, K_SCALAR);
+    if (a.weno && near)
+        hipLaunchKernelGGL((k_scalar<T, true, true>), grd, blk, 0, cx->stream, a);
+    else if (a.weno)
+        hipLaunchKernelGGL((k_scalar<T, true, false>), grd, blk, 0, cx->stream, a);
+    else if (near)
+        hipLaunchKernelGGL((k_scalar<T, false, true>), grd, blk, 0, cx->stream, a);
+    else
+        hipLaunchKernelGGL((k_scalar<T, false, false>), grd, blk, 0, cx->stream, a);
+    timing_stop(cx, K_SCALAR);
     return hipGetLastError();
 }
 }  // namespace
