@@ -35,6 +35,12 @@ def test_bench_constants():
     bulk, f64 = bench._step_values(cfg)
     assert bulk + f64 == 22 * 20 + 3 * 5 + 3 * (48 + 17 + 5) - 19
     assert bench._one_pass_values(cfg) == 13 * 5 + 6 + 22 * (3 * 5 + 3)
+    # the deep workload (3 WENO5 tracers, 13 substeps, no SGS): prep 3 x 10,
+    # tendencies 3 x 14, stage init 3 x 17 - 13, coefficients 3 x 5, substeps
+    # 13 x 20 - 6, finalize 3 x 15, flux sums 13 x 6 + 3 x 3 + 3 x 7, mixing
+    # ratios 3 x 7 and the scalar update 3 x 12
+    deep = W.deep()
+    assert sum(bench._step_values(deep)) == 30 + 42 + 38 + 15 + 254 + 45 + 108 + 21 + 36
 
 
 def test_ensemble_recipe():
