@@ -85,16 +85,18 @@ def _kernel_bytes(kernel: str, sgs: int, prec: str) -> float:
     return bulk * (8.0 if prec == "fp64" else 4.0) + f64 * 8.0
 
 
-def _profiled_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary under profiles/, if the kernel's source is unchanged since."""
+def _profiled_traffic(kernel: str, prec: str = "fp64"):
+    """HBM bytes per launch of `kernel` in precision `prec` from the committed
+    rocprofv3 counter summary under profiles/, if the kernel's source is
+    unchanged since."""
     import glob
     import hashlib
     import re
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         text = open(path).read()
-        fields = dict(re.findall(r"^\s+(kernel|source|source_sha256|traffic_bytes_per_launch): (\S+)$", text, re.M))
-        if fields.get("kernel") != kernel or "source" not in fields:
+        fields = dict(re.findall(r"^\s+(kernel|precision|source|source_sha256|traffic_bytes_per_launch): (\S+)$",
+                                 text, re.M))
+        if fields.get("kernel") != kernel or fields.get("precision", "fp64") != prec or "source" not in fields:
             continue
         src = os.path.join(ROOT, fields["source"])
         if os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == fields.get("source_sha256"):
@@ -457,7 +459,7 @@ def _roofline(cfg, dom, kms, kn):
     if dom == "substep":  # averaged over the timed launches
         bytes_per_launch += _substep_value_adjust(cfg) * (8.0 if cfg.prec == "fp64" else 4.0) * cfg.cells
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic, tsrc = _profiled_traffic(dom) if cfg.prec == "fp64" and "stable" in cfg.name else (None, None)
+    traffic, tsrc = _profiled_traffic(dom, cfg.prec) if "stable" in cfg.name else (None, None)
     return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": tsrc,
             "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_ms, 4),
