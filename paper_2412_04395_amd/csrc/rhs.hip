@@ -287,6 +287,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     const double idz = a.idz[k];
     const int oh = a.oh, ov = a.ov;
     double q[7];
+    // the five tendencies, stored together at the end: a store between the
+    // sections would keep every later load behind it (the compiler cannot
+    // rule out that it aliases them)
+    double out_r, out_t, out_u, out_v, out_w;
 
     // ---------------- cell: continuity and rho*theta ----------------
     const double U0 = a.ru[c], U1 = a.ru[c + ox(4)];
@@ -296,7 +300,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     const double th0k = kPert<T> ? a.theta0[k] : 0.0;
     {
         // tendencies are read by later launches only: streaming stores
-        st_stream(a.Rr + c, (T)(-((U1 - U0) * a.idx + (V1 - V0) * a.idy + (W1 - W0) * idz)));
+        out_r = -((U1 - U0) * a.idx + (V1 - V0) * a.idy + (W1 - W0) * idz);
         const T *th = a.th;
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = th0k + th[c + ox(t)];
@@ -323,7 +327,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
             r -= (hx1 - hx0) * a.idx + (hy1 - hy0) * a.idy + (hz1 - hz0) * idz;
         }
         if (k == 0 && a.Qs != 0.0) r += rc * a.Qs * idz;
-        st_stream(a.Rt + c, (T)r);
+        out_t = r;
     }
 
     // ---------------- x-momentum on x-face (i, j, k) ----------------
@@ -353,7 +357,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         if constexpr (kVisc)
             r -= (a.t11[c] - a.t11[c + ox(2)]) * a.idx + (a.t12[c + oy(4)] - a.t12[c]) * a.idy +
                  (a.t13[c + P] - a.t13[c]) * idz;
-        st_stream(a.Ru + c, (T)r);
+        out_u = r;
     }
 
     // ---------------- y-momentum on y-face (i, j, k) ----------------
@@ -382,7 +386,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         if constexpr (kVisc)
             r -= (a.t12[c + ox(4)] - a.t12[c]) * a.idx + (a.t22[c] - a.t22[c + oy(2)]) * a.idy +
                  (a.t23[c + P] - a.t23[c]) * idz;
-        st_stream(a.Rv + c, (T)r);
+        out_v = r;
     }
 
     // ---------------- z-momentum on z-face (i, j, k) ----------------
@@ -412,9 +416,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         if constexpr (kVisc)
             r -= (a.t13[c + ox(4)] - a.t13[c]) * a.idx + (a.t23[c + oy(4)] - a.t23[c]) * a.idy +
                  (a.t33[c] - a.t33[cm]) * idzf;
-        st_stream(a.Rw + c, (T)(k > 0 ? r : 0.0));
-        if (k == 0) a.Rw[c + nz * P] = 0.0;
+        out_w = k > 0 ? r : 0.0;
     }
+    st_stream(a.Rr + c, (T)out_r);
+    st_stream(a.Rt + c, (T)out_t);
+    st_stream(a.Ru + c, (T)out_u);
+    st_stream(a.Rv + c, (T)out_v);
+    st_stream(a.Rw + c, (T)out_w);
+    if (k == 0) a.Rw[c + nz * P] = 0.0;
 }
 
 }  // namespace
