@@ -198,8 +198,20 @@ def test_acoustic_from_the_stage_state(case, nsub, sums):
 
 @pytest.mark.parametrize("scheme,order", [(1, 3), (0, 5), (0, 2), (0, 6)])
 def test_scalar_advance_parity(scheme, order):
-    cfg = W.small(n_scalars=3, scalar_scheme=scheme, adv_order_h=order, adv_order_v=order)
-    _say("scalars", scheme, order)
+    _scalar_advance_case(dict(), scheme, order)
+
+
+# domains narrower than the stencil in one direction take the kernel's
+# general wrap / reflection path
+@pytest.mark.parametrize("shape", [dict(nx=1), dict(ny=2), dict(nz=2, dz=W.uniform_dz(2, 100.0))])
+@pytest.mark.parametrize("scheme,order", [(1, 3), (0, 5)])
+def test_scalar_advance_parity_narrow(shape, scheme, order):
+    _scalar_advance_case(shape, scheme, order)
+
+
+def _scalar_advance_case(shape, scheme, order):
+    cfg = W.small(n_scalars=3, scalar_scheme=scheme, adv_order_h=order, adv_order_v=order, **shape)
+    _say("scalars", scheme, order, cfg.nx, cfg.ny, cfg.nz)
     o, s, th0, b = _sides(cfg)
     St = _rough_state(cfg, b, th0, seed=400)
     Sn = _rough_state(cfg, b, th0, seed=500)
