@@ -14,8 +14,10 @@
 //             with the interpolants of Sec. 3.6, pressure gradient, buoyancy,
 //             Coriolis, surface heat flux and the divergence of the stresses.
 // Every thread resolves the periodic wrap in x and y and the lid reflections in
-// z once, into offset tables, so the stencil loads are base + offset.  The
-// interpolation order is a template parameter for the orders the workloads use.
+// z as offsets from its cell (selects, not branches, on domains at least 3
+// cells wide), so the stencil loads are base + offset and can all be issued
+// ahead of the arithmetic.  The interpolation order is a template parameter for
+// the orders the workloads use.
 // In the FP32 storage theta is kept as theta - theta0(z) and the base value is
 // added back per level before interpolating.
 #include "erf_internal.h"
