@@ -14,20 +14,23 @@ template <typename T>
 struct ScalArgs {
     Dims d;
     int nq, oh, ov, weno;
-    double dx, dy, dts;
-    const double *dz, *rho0;
+    double idx, idy, dts;
+    const double *idz, *rho0;
     const T *rqn, *rho_t, *rq_t, *Fu, *Fv, *Fw;
     T *q, *out;
 };
 
+// q^t = (rho q)^t / rho^t; one thread per cell for every scalar (rho read once)
 template <typename T>
 __global__ __launch_bounds__(256) void k_mixing_ratio(ScalArgs<T> a)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    int total = a.nq * a.d.n;
-    if (c >= total) return;
-    const int cc = c % a.d.n;
-    a.q[c] = (double)a.rq_t[c] / full_of(a.rho_t, cc, a.rho0[cc / a.d.nxy]);
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.d.n) return;
+    const double r = full_of(a.rho_t, c, a.rho0[c / a.d.nxy]);
+    for (int s = 0; s < a.nq; ++s) {
+        const size_t o = (size_t)s * a.d.n + c;
+        a.q[o] = (double)a.rq_t[o] / r;
+    }
 }
 
 // WENO5-JS face value; v2 is the upwind cell, candidate stencils of three cells
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
     const double fy0 = Fy0 * face(qy, 0, sign_of(Fy0), a.oh), fy1 = Fy1 * face(qy, 1, sign_of(Fy1), a.oh);
     const double fz0 = Fz0 * face(qz, 0, sign_of(Fz0), a.ov) * not_bot;
     const double fz1 = Fz1 * face(qz, 1, sign_of(Fz1), a.ov) * not_top;
-    const double div = (fx1 - fx0) / a.dx + (fy1 - fy0) / a.dy + (fz1 - fz0) / a.dz[k];
+    const double div = (fx1 - fx0) * a.idx + (fy1 - fy0) * a.idy + (fz1 - fz0) * a.idz[k];
     // read by later launches only (and rqn[o], its only other use, is read above)
     st_stream(a.out + o, (T)(rq - a.dts * div));
 }
@@ -129,10 +132,10 @@ hipError_t scalar_t(erf_ctx *cx, const void *rqn, const void *rho_t, const void 
     a.oh = cx->prm.adv_order_h;
     a.ov = cx->prm.adv_order_v;
     a.weno = cx->prm.scalar_scheme == ERF_SCALAR_WENO5;
-    a.dx = cx->grid.dx;
-    a.dy = cx->grid.dy;
+    a.idx = 1.0 / cx->grid.dx;
+    a.idy = 1.0 / cx->grid.dy;
     a.dts = dts;
-    a.dz = cx->base.dz;
+    a.idz = cx->base.idz();
     a.rho0 = cx->base.rho0;
     a.rqn = (const T *)rqn;
     a.rho_t = (const T *)rho_t;
@@ -143,9 +146,8 @@ hipError_t scalar_t(erf_ctx *cx, const void *rqn, const void *rho_t, const void 
     a.q = (T *)cx->ws.q;
     a.out = (T *)rq_out;
     if (a.nq <= 0) return hipSuccess;
-    int total = a.nq * d.n;
     timing_start(cx, K_MIXRATIO);
-    hipLaunchKernelGGL(k_mixing_ratio<T>, dim3((total + 255) / 256), dim3(256), 0, cx->stream, a);
+    hipLaunchKernelGGL(k_mixing_ratio<T>, dim3((d.n + 255) / 256), dim3(256), 0, cx->stream, a);
     timing_stop(cx, K_MIXRATIO);
     dim3 blk(64, 4, 1), grd((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz * a.nq);
     const bool near = d.nx >= 3 && d.ny >= 3 && d.nz >= 3;
