@@ -57,25 +57,33 @@ __device__ __forceinline__ double weno5_face(double v0, double v1, double v2, do
     return (w0 * P0 + w1 * P1 + w2 * P2) / (6.0 * (w0 + w1 + w2));
 }
 
-// One thread per (i, j, k, scalar).  kWeno: WENO5-JS faces, else the
-// interpolant of the run's order.  kNear: the domain is at least 3 cells wide
-// and 3 levels high, so that the periodic wrap and the lid reflection of any
-// stencil offset are selects.  Every load first, the lid fluxes masked by a 0/1
-// product, the upwind candidate stencil picked by selects and evaluated once:
-// with a branch between them (or one per sign, which diverges) the compiler
-// issues the loads in small dependent groups.
-// (At most 4 wavefronts per SIMD: the register budget lets the scheduler keep
-// the 25 loads together instead of trickling them.)
+// Tiles of kSX x kSY cells per block of (kSX + 1) x (kSY + 1) threads, one
+// level of one scalar.  Every thread evaluates the x- and y-face on the low
+// side of its cell; the last lane and the last row of threads hold the cells
+// just past the tile and only lend those faces, through LDS, to their
+// neighbours, so each interior face is evaluated once instead of twice.  The
+// z-faces (both, per cell) are evaluated by the tile's own cells.  kWeno:
+// WENO5-JS faces, else the interpolant of the run's order.  kNear: the domain
+// is at least 3 cells wide and 3 levels high, so that the periodic wrap and
+// the lid reflection of any stencil offset are selects.  Every load first, the
+// lid fluxes masked by a 0/1 product, the upwind candidate stencil picked by
+// selects and evaluated once: with a branch between them (or one per sign,
+// which diverges) the compiler issues the loads in small dependent groups.
+constexpr int kSX = 63, kSY = 15;
 template <typename T, bool kWeno, bool kNear>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void k_scalar(ScalArgs<T> a)
+__global__ __launch_bounds__(1024) void k_scalar(ScalArgs<T> a)
 {
+    __shared__ double fxs[kSY + 1][kSX + 1], fys[kSY + 1][kSX + 1];
     const Dims &d = a.d;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y * blockDim.y + threadIdx.y;
-    int kq = blockIdx.z;
-    if (i >= d.nx || j >= d.ny) return;
+    const int lane = threadIdx.x, row = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.nxy;
-    const int k = kq % nz, s = kq / nz;
+    const int k = blockIdx.z % nz, s = blockIdx.z / nz;
+    // the thread's cell, wrapped periodically (the lending lane and row may lie
+    // past the domain's end); threads beyond them have nothing to do but the barrier
+    const int iu = blockIdx.x * kSX + lane, ju = blockIdx.y * kSY + row;
+    const bool lend = iu <= nx && ju <= ny;
+    const bool own = lane < kSX && row < kSY && iu < nx && ju < ny;
+    const int i = iu % nx, j = ju % ny;
     const int c = cidx(d, i, j, k);
     const T *q = a.q + (size_t)s * d.n;
     auto wrap = [&](int v, int n) { return kNear ? v + (v < 0 ? n : 0) - (v >= n ? n : 0) : wrap_idx(v, n); };
@@ -84,20 +92,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
         const int r = kk < 0 ? -1 - kk : kk;
         return r >= nz ? 2 * nz - 1 - r : r;
     };
-    // q at offsets -3..3 in x, y and z (z reflected at the lids)
-    double qx[7], qy[7], qz[7];
-#pragma unroll
-    for (int t = 0; t < 7; ++t) {
-        qx[t] = q[c + (wrap(i + t - 3, nx) - i)];
-        qy[t] = q[c + (wrap(j + t - 3, ny) - j) * nx];
-        qz[t] = q[c + (reflc(k + t - 3) - k) * P];
-    }
-    const double Fx0 = a.Fu[c], Fx1 = a.Fu[c + (wrap(i + 1, nx) - i)];
-    const double Fy0 = a.Fv[c], Fy1 = a.Fv[c + (wrap(j + 1, ny) - j) * nx];
-    const double Fz0 = a.Fw[c], Fz1 = a.Fw[c + P];
-    const size_t o = (size_t)s * d.n + c;
-    const double rq = a.rqn[o];
-    const double not_bot = (double)(k > 0), not_top = (double)(k < nz - 1);
     // face value on the low (oo = 0) or high (oo = 1) side of the cell,
     // upwinded by the sign sg of the flux through it
     auto face = [&](const double (&v)[7], int oo, double sg, int order) {
@@ -109,10 +103,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
             return face_interp(order, qm3, qm2, qm1, q0, qp1, qp2, sg);
         }
     };
-    const double fx0 = Fx0 * face(qx, 0, sign_of(Fx0), a.oh), fx1 = Fx1 * face(qx, 1, sign_of(Fx1), a.oh);
-    const double fy0 = Fy0 * face(qy, 0, sign_of(Fy0), a.oh), fy1 = Fy1 * face(qy, 1, sign_of(Fy1), a.oh);
-    const double fz0 = Fz0 * face(qz, 0, sign_of(Fz0), a.ov) * not_bot;
-    const double fz1 = Fz1 * face(qz, 1, sign_of(Fz1), a.ov) * not_top;
+    // q at offsets -3..3 in x and y (the low faces use -3..2)
+    double qx[7], qy[7];
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+        qx[t] = q[c + (wrap(i + t - 3, nx) - i)];
+        qy[t] = q[c + (wrap(j + t - 3, ny) - j) * nx];
+    }
+    const double Fx0 = a.Fu[c], Fy0 = a.Fv[c];
+    const double fx0 = Fx0 * face(qx, 0, sign_of(Fx0), a.oh), fy0 = Fy0 * face(qy, 0, sign_of(Fy0), a.oh);
+    fxs[row][lane] = fx0;
+    fys[row][lane] = fy0;
+    double fz0 = 0.0, fz1 = 0.0, rq = 0.0;
+    const size_t o = (size_t)s * d.n + c;
+    if (row < kSY) {  // the tile's rows: their z-faces (the lending row has none to give)
+        double qz[7];
+#pragma unroll
+        for (int t = 0; t < 7; ++t) qz[t] = q[c + (reflc(k + t - 3) - k) * P];
+        const double Fz0 = a.Fw[c], Fz1 = a.Fw[c + P];
+        const double not_bot = (double)(k > 0), not_top = (double)(k < nz - 1);
+        rq = a.rqn[o];
+        fz0 = Fz0 * face(qz, 0, sign_of(Fz0), a.ov) * not_bot;
+        fz1 = Fz1 * face(qz, 1, sign_of(Fz1), a.ov) * not_top;
+    }
+    __syncthreads();
+    if (!own || !lend) return;
+    const double fx1 = fxs[row][lane + 1], fy1 = fys[row + 1][lane];
     const double div = (fx1 - fx0) * a.idx + (fy1 - fy0) * a.idy + (fz1 - fz0) * a.idz[k];
     // read by later launches only (and rqn[o], its only other use, is read above)
     st_stream(a.out + o, (T)(rq - a.dts * div));
@@ -149,7 +165,7 @@ hipError_t scalar_t(erf_ctx *cx, const void *rqn, const void *rho_t, const void 
     timing_start(cx, K_MIXRATIO);
     hipLaunchKernelGGL(k_mixing_ratio<T>, dim3((d.n + 255) / 256), dim3(256), 0, cx->stream, a);
     timing_stop(cx, K_MIXRATIO);
-    dim3 blk(64, 4, 1), grd((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz * a.nq);
+    dim3 blk(kSX + 1, kSY + 1, 1), grd((d.nx + kSX - 1) / kSX, (d.ny + kSY - 1) / kSY, d.nz * a.nq);
     const bool near = d.nx >= 3 && d.ny >= 3 && d.nz >= 3;
     timing_start(cx, K_SCALAR);
     if (a.weno && near)
