@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
 // so the loads of later levels may be issued ahead of earlier stores.  kZero:
 // S'' is zero on entry (Theta'', U'', V'', rho'', W'' are not read; the same
 // arithmetic runs on zeros, so the results are those of reading them).
-template <typename T, int kLevels, bool kLast, bool kZero>
+template <typename T, int kLevels, bool kLast, bool kZero, bool kSums>
 __device__ __forceinline__ void substep_explicit(
     const T *__restrict__ t_u, const T *__restrict__ t_v, const T *__restrict__ T2cur, const T *__restrict__ T2prv, const T *__restrict__ pit, const T *__restrict__ tht,
     const T *__restrict__ u2in, const T *__restrict__ v2in, const T *__restrict__ R_u, const T *__restrict__ R_v,
@@ -222,6 +222,13 @@ __device__ __forceinline__ void substep_explicit(
             const int k = k0 + l;
             if (k < nz) {
                 const int c = col + k * nxy;
+                // the running flux sums (kSums: scalars are transported), read
+                // with this level's other loads and written at its end
+                double su0 = 0.0, sv0 = 0.0;
+                if constexpr (kSums) {
+                    su0 = su[c];
+                    sv0 = sv[c];
+                }
                 // forward-predicted Theta'' at the centre and its four neighbours
                 const double Tc = in(T2cur, c);
                 const double ttc = Tc + bd * (Tc - in(T2prv, c));
@@ -296,10 +303,9 @@ __device__ __forceinline__ void substep_explicit(
                     bnd[(g * 2 + 0) * kLanes + lane] = e;
                     bnd[(g * 2 + 1) * kLanes + lane] = f;
                 }
-                // running sums last, so that no branch separates this level's loads
-                if (!kLast && sums) {
-                    su[c] += Uw;
-                    sv[c] += Vs;
+                if constexpr (kSums) {
+                    su[c] = (T)(su0 + Uw);
+                    sv[c] = (T)(sv0 + Vs);
                 }
             }
         }
@@ -309,7 +315,7 @@ __device__ __forceinline__ void substep_explicit(
 // One fused acoustic substep.  blockDim = (64, KG), kLevels levels per
 // wavefront; dynamic LDS holds the (nz + 1) x 64 solve buffer and the
 // chunk-boundary values.
-template <typename T, int kLevels, bool kLast, bool kZero>
+template <typename T, int kLevels, bool kLast, bool kZero, bool kSums>
 __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
 {
     extern __shared__ double lds[];
@@ -362,7 +368,7 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
     };
 
     // ---------------- phase 1: explicit work, W'' right-hand sides ----------
-    substep_explicit<T, kLevels, kLast, kZero>(a.t_u, a.t_v, a.T2cur, a.T2prv, a.pit, a.tht, a.u2in, a.v2in, a.R_u, a.R_v, a.R_t, a.R_r, a.R_w,
+    substep_explicit<T, kLevels, kLast, kZero, kSums>(a.t_u, a.t_v, a.T2cur, a.T2prv, a.pit, a.tht, a.u2in, a.v2in, a.R_u, a.R_v, a.R_t, a.R_r, a.R_w,
                                  a.w2, a.r2, a.cC, a.idz, a.idzf, a.u2out, a.v2out, a.su, a.sv, a.sums, rbuf, bnd,
                                  act, col, nxy, nz, k0, g, lane, o_e, o_w, o_n, o_s, dt, b1, b2, gr, bd, gRd, idx,
                                  idy, D, th, thl, rh, flo, fup, e_first, f_first);
@@ -517,7 +523,7 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
                     st_stream(a.r2 + c, (T)rn);
                     if (k >= 1) {
                         st_stream(a.w2 + c, (T)wk);
-                        if (a.sums) a.sw[c] += wk;
+                        if constexpr (kSums) a.sw[c] += wk;
                     }
                 }
                 wk1 = wk;
@@ -571,26 +577,36 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs<T> a)
 }  // namespace
 
 namespace {
-// one substep launch: the instance for the level count, the stage end and a
-// zero S'' on entry
+// one substep launch: the instance for the level count, the stage end, a zero
+// S'' on entry and the flux sums (never together with the stage end: the sums
+// keep a separate finalize)
 template <typename T, int L>
-void launch_substep(bool last, bool zero, dim3 grid, dim3 block, size_t lds, hipStream_t st, const StageArgs<T> &a)
+void launch_substep(bool last, bool zero, bool sums, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                    const StageArgs<T> &a)
 {
-    if (zero && last)
-        hipLaunchKernelGGL((k_substep<T, L, true, true>), grid, block, lds, st, a);
-    else if (zero)
-        hipLaunchKernelGGL((k_substep<T, L, false, true>), grid, block, lds, st, a);
+    if (last && zero)
+        hipLaunchKernelGGL((k_substep<T, L, true, true, false>), grid, block, lds, st, a);
     else if (last)
-        hipLaunchKernelGGL((k_substep<T, L, true, false>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_substep<T, L, true, false, false>), grid, block, lds, st, a);
+    else if (sums && zero)
+        hipLaunchKernelGGL((k_substep<T, L, false, true, true>), grid, block, lds, st, a);
+    else if (sums)
+        hipLaunchKernelGGL((k_substep<T, L, false, false, true>), grid, block, lds, st, a);
+    else if (zero)
+        hipLaunchKernelGGL((k_substep<T, L, false, true, false>), grid, block, lds, st, a);
     else
-        hipLaunchKernelGGL((k_substep<T, L, false, false>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_substep<T, L, false, false, false>), grid, block, lds, st, a);
 }
 
 template <typename T, int L>
 hipError_t allow_lds(size_t lds)
 {
-    const void *fn[4] = {(const void *)k_substep<T, L, false, false>, (const void *)k_substep<T, L, true, false>,
-                         (const void *)k_substep<T, L, false, true>, (const void *)k_substep<T, L, true, true>};
+    const void *fn[6] = {(const void *)k_substep<T, L, false, false, false>,
+                         (const void *)k_substep<T, L, true, false, false>,
+                         (const void *)k_substep<T, L, false, true, false>,
+                         (const void *)k_substep<T, L, true, true, false>,
+                         (const void *)k_substep<T, L, false, false, true>,
+                         (const void *)k_substep<T, L, false, true, true>};
     for (const void *f : fn) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -700,9 +716,9 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
         const dim3 grid(a.ntx * a.nty), block(kLanes, KG);
         timing_start(cx, K_SUBSTEP);
         if (L == 8)
-            launch_substep<T, 8>(last, zero && s == 0, grid, block, lds, cx->stream, a);
+            launch_substep<T, 8>(last, zero && s == 0, a.sums != 0, grid, block, lds, cx->stream, a);
         else
-            launch_substep<T, 16>(last, zero && s == 0, grid, block, lds, cx->stream, a);
+            launch_substep<T, 16>(last, zero && s == 0, a.sums != 0, grid, block, lds, cx->stream, a);
         timing_stop(cx, K_SUBSTEP);
         t_prv = t_cur;
         t_cur = t_nxt;
