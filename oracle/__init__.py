@@ -90,6 +90,9 @@ def lib():
             L.orc_bf16.argtypes = [C.c_double]
             L.orc_mlp_forward.argtypes = [_DP, _DP, C.c_int64, _DP, C.c_int]
             L.orc_mlp_loss_grad.argtypes = [_DP, _DP, _DP, C.c_int64, C.c_int, _DP, _DP]
+            L.orc_mlp_grad_abs.argtypes = [_DP, _DP, _DP, C.c_int64, C.c_int, _DP]
+            L.orc_mlp_unit_margins.argtypes = [_DP, _DP, C.c_int64, _DP, C.POINTER(C.c_int32),
+                                               C.POINTER(C.c_int32), _DP]
             L.orc_adam.argtypes = [_DP, _DP, _DP, _DP, C.c_int64, C.c_int64, C.c_double, C.c_double,
                                    C.c_double, C.c_double]
             L.orc_sgs_features.argtypes = [C.POINTER(_Grid), C.POINTER(_State), _DP]
@@ -270,6 +273,51 @@ def mlp_loss_grad(params, x, t, bf16: bool = False):
     g = np.zeros(pa.size)
     lib().orc_mlp_loss_grad(_p(pa), _p(xa), _p(ta), xa.shape[0], int(bool(bf16)), C.byref(loss), _p(g))
     return loss.value, g
+
+
+def mlp_grad_abs(params, x, t, bf16: bool = False):
+    """Per parameter, the sum of the magnitudes of the terms of its gradient."""
+    pa = np.ascontiguousarray(params, dtype=np.float64)
+    xa = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 10)
+    ta = np.ascontiguousarray(t, dtype=np.float64).reshape(-1, 9)
+    assert xa.shape[0] == ta.shape[0]
+    g = np.zeros(pa.size)
+    lib().orc_mlp_grad_abs(_p(pa), _p(xa), _p(ta), xa.shape[0], int(bool(bf16)), _p(g))
+    return g
+
+
+def mlp_unit_margins(params, x):
+    """Per sample and hidden unit (n, 192; layers 1..3 of 64 units): the
+    relative distance of the unit's value to a bfloat16 rounding boundary (or
+    to zero) in the BF16-mode forward pass."""
+    pa = np.ascontiguousarray(params, dtype=np.float64)
+    xa = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 10)
+    m = np.zeros((xa.shape[0], 192))
+    lib().orc_mlp_unit_margins(_p(pa), _p(xa), xa.shape[0], _p(m), None, None, None)
+    return m
+
+
+def mlp_forward_margin(params, x):
+    """Per sample, the smallest relative distance of a hidden value to a
+    bfloat16 rounding boundary (or to zero) in the BF16-mode forward pass."""
+    return mlp_unit_margins(params, x).min(axis=1)
+
+
+def mlp_forward_flipped(params, x, units):
+    """BF16-mode outputs (n, 9) with, in sample s, hidden unit units[s] (0..191,
+    layer-major; -1: none) rounded to the bfloat16 neighbour on the other side
+    of its value instead of the nearest."""
+    pa = np.ascontiguousarray(params, dtype=np.float64)
+    xa = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 10)
+    u = np.asarray(units, dtype=np.int64).reshape(-1)
+    assert u.size == xa.shape[0]
+    layer = np.ascontiguousarray(np.where(u >= 0, u // 64, -1), dtype=np.int32)
+    unit = np.ascontiguousarray(np.where(u >= 0, u % 64, 0), dtype=np.int32)
+    y = np.zeros((xa.shape[0], 9))
+    P32 = C.POINTER(C.c_int32)
+    lib().orc_mlp_unit_margins(_p(pa), _p(xa), xa.shape[0], None, layer.ctypes.data_as(P32),
+                               unit.ctypes.data_as(P32), _p(y))
+    return y
 
 
 def adam(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):

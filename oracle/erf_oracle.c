@@ -1002,6 +1002,144 @@ int orc_mlp_loss_grad(const double *p, const double *x, const double *t, int64_t
     return 0;
 }
 
+/* Error scale of the gradient: the same backpropagation with every product
+ * replaced by the product of absolute values (and no ReLU sign cancellation
+ * in the deltas), i.e. for each parameter the sum of the magnitudes of all the
+ * terms whose sum is its gradient.  A sum of m terms computed in a precision
+ * with unit roundoff u differs from the exact sum by at most about m u times
+ * this scale, and a changed rounding of one operand (a BF16 boundary flip)
+ * changes it by at most 2^-8 of it. */
+int orc_mlp_grad_abs(const double *p, const double *x, const double *t, int64_t n, int bf16, double *gabs)
+{
+    memset(gabs, 0, sizeof(double) * N_PARAMS);
+    const double scale = 2.0 / ((double)n * MO);
+    for (int64_t s = 0; s < n; ++s) {
+        const double *xs = x + s * MI;
+        double h1[MH], h2[MH], h3[MH], y[MO], dy[MO], d3[MH], d2[MH], d1[MH];
+        dense(xs, MI, p + OFF_W1, p + OFF_B1, MH, bf16, h1);
+        relu(h1, MH);
+        dense(h1, MH, p + OFF_W2, p + OFF_B2, MH, bf16, h2);
+        relu(h2, MH);
+        dense(h2, MH, p + OFF_W3, p + OFF_B3, MH, bf16, h3);
+        relu(h3, MH);
+        dense(h3, MH, p + OFF_W4, p + OFF_B4, MO, bf16, y);
+        for (int j = 0; j < MO; ++j) dy[j] = fabs(scale * (y[j] - t[s * MO + j]));
+        for (int i = 0; i < MH; ++i)
+            for (int j = 0; j < MO; ++j) gabs[OFF_W4 + i * MO + j] += fabs(rb(h3[i], bf16)) * fabs(rb(dy[j], bf16));
+        for (int j = 0; j < MO; ++j) gabs[OFF_B4 + j] += dy[j];
+        for (int i = 0; i < MH; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < MO; ++j) acc += fabs(rb(dy[j], bf16)) * fabs(rb(p[OFF_W4 + i * MO + j], bf16));
+            d3[i] = h3[i] > 0.0 ? acc : 0.0;
+        }
+        for (int i = 0; i < MH; ++i)
+            for (int j = 0; j < MH; ++j) gabs[OFF_W3 + i * MH + j] += fabs(rb(h2[i], bf16)) * rb(d3[j], bf16);
+        for (int j = 0; j < MH; ++j) gabs[OFF_B3 + j] += d3[j];
+        for (int i = 0; i < MH; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < MH; ++j) acc += rb(d3[j], bf16) * fabs(rb(p[OFF_W3 + i * MH + j], bf16));
+            d2[i] = h2[i] > 0.0 ? acc : 0.0;
+        }
+        for (int i = 0; i < MH; ++i)
+            for (int j = 0; j < MH; ++j) gabs[OFF_W2 + i * MH + j] += fabs(rb(h1[i], bf16)) * rb(d2[j], bf16);
+        for (int j = 0; j < MH; ++j) gabs[OFF_B2 + j] += d2[j];
+        for (int i = 0; i < MH; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < MH; ++j) acc += rb(d2[j], bf16) * fabs(rb(p[OFF_W2 + i * MH + j], bf16));
+            d1[i] = h1[i] > 0.0 ? acc : 0.0;
+        }
+        for (int i = 0; i < MI; ++i)
+            for (int j = 0; j < MH; ++j) gabs[OFF_W1 + i * MH + j] += fabs(rb(xs[i], bf16)) * rb(d1[j], bf16);
+        for (int j = 0; j < MH; ++j) gabs[OFF_B1 + j] += d1[j];
+    }
+    return 0;
+}
+
+/* Distance of v > 0 to the nearest point where its bfloat16 rounding changes:
+ * v lies between the bfloat16 values lo <= v < hi; it rounds to lo or hi with
+ * the boundary at their midpoint, and to the value below lo past the midpoint
+ * of that value and lo. */
+static double bf16_boundary_distance(double v)
+{
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return INFINITY;
+    uint32_t lo = u & 0xffff0000u, hi = lo + 0x10000u;
+    float flo, fhi;
+    memcpy(&flo, &lo, 4);
+    memcpy(&fhi, &hi, 4);
+    double up = 0.5 * ((double)flo + (double)fhi) - v;
+    double down = INFINITY;
+    if (lo >= 0x10000u) {
+        uint32_t pv = lo - 0x10000u;
+        float fpv;
+        memcpy(&fpv, &pv, 4);
+        down = v - 0.5 * ((double)fpv + (double)flo);
+    }
+    return fabs(up) < fabs(down) ? fabs(up) : fabs(down);
+}
+
+/* For each sample of a BF16-mode forward pass and each hidden unit of the
+ * three hidden layers (margin[n][192], layer-major): the distance of the
+ * unit's exact pre-activation to the nearest point where its bfloat16 rounding
+ * changes (or, for a value at or below zero, to zero, where ReLU switches),
+ * divided by the sum of the magnitudes of its terms (|bias| + sum |x W|).
+ * Where this is below the relative accumulation error of another evaluation
+ * (at most about 64 * 2^-24 in FP32), that evaluation may round the unit to
+ * the neighbouring bfloat16 value; where it is above, both round it the same
+ * way.  A unit without terms reports infinity.  If flip_layer is not NULL,
+ * sample s rounds unit flip_unit[s] of hidden layer flip_layer[s] (0..2; -1:
+ * none) to the bfloat16 neighbour on the other side of its value instead of
+ * the nearest, and writes its outputs to y[n][9] (y may be NULL otherwise). */
+int orc_mlp_unit_margins(const double *p, const double *x, int64_t n, double *margin,
+                         const int32_t *flip_layer, const int32_t *flip_unit, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < n; ++s) {
+        double in[MH], out[MH];
+        int nin = MI;
+        for (int i = 0; i < MI; ++i) in[i] = x[s * MI + i];
+        const int offw[3] = {OFF_W1, OFF_W2, OFF_W3}, offb[3] = {OFF_B1, OFF_B2, OFF_B3};
+        for (int layer = 0; layer < 3; ++layer) {
+            for (int j = 0; j < MH; ++j) {
+                double acc = 0.0, mag = fabs(p[offb[layer] + j]);
+                for (int i = 0; i < nin; ++i) {
+                    double term = rb(in[i], 1) * rb(p[offw[layer] + i * MH + j], 1);
+                    acc += term;
+                    mag += fabs(term);
+                }
+                double v = p[offb[layer] + j] + acc;
+                if (margin) {
+                    /* positive: the nearest bfloat16 boundary (always closer
+                     * than zero); otherwise the distance to zero */
+                    double dist = v > 0.0 ? bf16_boundary_distance(v) : -v;
+                    margin[s * 3 * MH + layer * MH + j] = mag > 0.0 ? dist / mag : INFINITY;
+                }
+                out[j] = v > 0.0 ? v : 0.0;
+                if (flip_layer && flip_layer[s] == layer && flip_unit[s] == j && out[j] > 0.0) {
+                    /* the next layer rounds its inputs: hand it the neighbour
+                     * on the other side instead (exactly representable, so its
+                     * own rounding leaves it unchanged) */
+                    float f = (float)out[j];
+                    uint32_t u;
+                    memcpy(&u, &f, 4);
+                    uint32_t lo = u & 0xffff0000u, hi = lo + 0x10000u;
+                    double near = rb(out[j], 1);
+                    float fl, fh;
+                    memcpy(&fl, &lo, 4);
+                    memcpy(&fh, &hi, 4);
+                    out[j] = (near == (double)fl) ? (double)fh : (double)fl;
+                }
+            }
+            for (int j = 0; j < MH; ++j) in[j] = out[j];
+            nin = MH;
+        }
+        if (y) dense(in, MH, p + OFF_W4, p + OFF_B4, MO, 1, y + s * MO);
+    }
+    return 0;
+}
+
 /* Adam (Kingma & Ba 2015) with bias correction */
 int orc_adam(double *p, const double *g, double *m, double *v, int64_t np, int64_t step, double lr,
              double beta1, double beta2, double eps)

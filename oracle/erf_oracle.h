@@ -122,6 +122,19 @@ int orc_mlp_forward(const double *params, const double *x, int64_t n, double *y,
 /* Mean-squared error over n samples x 9 outputs and its gradient (9609). */
 int orc_mlp_loss_grad(const double *params, const double *x, const double *t, int64_t n, int bf16,
                       double *loss, double *grad);
+/* Error scale of the gradient: for every parameter, the sum of the magnitudes
+ * of the terms whose sum is its gradient (the backpropagation with absolute
+ * values), gabs[9609]. */
+int orc_mlp_grad_abs(const double *params, const double *x, const double *t, int64_t n, int bf16,
+                     double *gabs);
+/* Per sample of the BF16-mode forward pass on x[n][10] and per hidden unit of
+ * the three hidden layers (margin[n][192]): the distance of the unit's value
+ * to a bfloat16 rounding boundary (or to zero) relative to the sum of the
+ * magnitudes of its terms.  With flip_layer/flip_unit (nullable) each sample
+ * may round one hidden unit to the bfloat16 neighbour on the other side of its
+ * value; y[n][9] (nullable) receives the outputs of that pass. */
+int orc_mlp_unit_margins(const double *params, const double *x, int64_t n, double *margin,
+                         const int32_t *flip_layer, const int32_t *flip_unit, double *y);
 /* One Adam step (beta1, beta2, eps), step counts from 1. */
 int orc_adam(double *params, const double *grad, double *m, double *v, int64_t np, int64_t step,
              double lr, double beta1, double beta2, double eps);

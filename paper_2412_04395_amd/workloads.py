@@ -234,7 +234,7 @@ def scalar_layers(cfg: Config, rho: np.ndarray, rho0, theta0, p0, pi0) -> np.nda
         es = 611.2 * np.exp(17.67 * (T - 273.15) / (T - 29.65))
         qvs = 0.622 * es / (p0 - es)
         rh = np.where(z < 1500.0, 0.9,
-                      np.where(z < 12000.0, 0.9 - 0.65 * ((z - 1500.0) / 10500.0) ** 1.25, 0.25))
+                      np.where(z < 12000.0, 0.9 - 0.65 * (np.maximum(z - 1500.0, 0.0) / 10500.0) ** 1.25, 0.25))
         qv = rh * qvs
     else:
         qv = 0.01 * np.exp(-z / 3000.0)

@@ -8,13 +8,20 @@ even) and accumulates in FP64.
     agree bitwise, BF16 rounding of large activations included.  This pins
     the operand layouts, the K permutation and the packing.
   * With real-valued parameters the sums round differently (FP32 against
-    FP64: about 64 * 2^-24 of the sum of |terms|); a hidden value that lands
-    next to a BF16 rounding boundary can then round the other way, a change of
-    up to 2^-8 of that value.  Outputs are compared to 1e-2 of their scale at
-    worst and 1e-4 on 99.9% of the entries.  A tendency gathers up to 16 stress
-    values (2-cell and 4-cell means on both sides of a face), so up to 16 times
-    as many tendencies see such a rounding: they are compared to 1e-2 of the
-    stress part's scale at worst and 1e-5 on 97% of the entries.
+    FP64: at most about 64 * 2^-24 of the sum of |terms|).  That difference
+    matters only where a hidden value lies that close to a bfloat16 rounding
+    boundary: there one side may round it to the neighbouring bfloat16 value,
+    a change of up to 2^-8 of it.  Every output must agree to 1e-5 of the
+    output scale, unless the oracle, rerun with one of that sample's near-tie
+    hidden units (oracle margin below 1e-5) rounded the other way, reproduces
+    the GPU output to that bound: each difference must be explained by a
+    flip.  Closure tendencies must agree to 1e-5 of the stress part's scale
+    except within one cell (the reach of the 2-cell and 4-cell means) of a
+    cell whose network output flipped.
+  * Gradients are compared per parameter against the sum of the magnitudes of
+    the terms of that parameter's gradient (mlp_grad_abs): within 2^-7 of it
+    everywhere (a flip changes one term by 2^-8), and within the FP32
+    accumulation bound on all but the parameters that a flip can reach.
 Everything around the network (inputs, fallback, divergence, box filter,
 statistics) is FP64 on both sides and compared to 1e-12.
 """
@@ -34,6 +41,51 @@ NP = 9609
 def _say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+# a flip of a hidden value's bfloat16 rounding is possible where the oracle's
+# value lies within this fraction of its sum of |terms| of a boundary (FP32
+# accumulation of up to 64 terms: 64 * 2^-24 = 3.8e-6, with margin)
+FLIP_MARGIN = 1e-5
+# outputs that round every hidden value alike differ by the FP32 sums only
+OUT_TOL = 1e-5
+
+
+def _explain_flips(p, x, y, ref, scale, tol=OUT_TOL, max_try=16):
+    """Samples whose outputs y differ from the oracle's ref by more than tol
+    (relative to scale), and of those the ones that no single flipped hidden
+    unit explains: for each, the oracle is rerun with each of its near-tie
+    units (margin < FLIP_MARGIN, closest first) rounded the other way."""
+    err = np.abs(y - ref).max(axis=1) / scale
+    bad = np.flatnonzero(err > tol)
+    if bad.size == 0:
+        return err, bad, bad
+    marg = oracle.mlp_unit_margins(p, x[bad])
+    rows, units = [], []
+    for r, b in enumerate(bad):
+        order = np.argsort(marg[r])[:max_try]
+        for u in order[marg[r][order] < FLIP_MARGIN]:
+            rows.append(r)
+            units.append(u)
+    explained = np.zeros(bad.size, dtype=bool)
+    if rows:
+        rows = np.array(rows)
+        yf = oracle.mlp_forward_flipped(p, x[bad][rows], np.array(units))
+        ok = np.abs(yf - y[bad][rows]).max(axis=1) / scale <= tol
+        explained[np.unique(rows[ok])] = True
+    return err, bad, bad[~explained]
+
+
+def _bf16_input_ties(x):
+    """Inputs within one FP64 rounding (relative 1e-14) of a bfloat16 rounding
+    boundary: there the library's standardisation (multiplication by 1/std)
+    and the oracle's (division by std) may round to different inputs."""
+    f = np.abs(x).astype(np.float32)
+    u = f.view(np.uint32)
+    lo = (u & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)
+    hi = ((u & np.uint32(0xFFFF0000)) + np.uint32(0x10000)).view(np.float32).astype(np.float64)
+    mid = 0.5 * (lo + hi)
+    return np.any(np.abs(np.abs(x) - mid) <= 1e-14 * np.abs(x), axis=-1)
 
 
 def _view(p):
@@ -132,10 +184,14 @@ def test_network_real_parameters_match_bf16_oracle():
     s.mlp_set_weights(p.astype(np.float32))
     y = s.mlp_forward(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().double().numpy()
     scale = np.abs(ref).max()
-    err = np.abs(y - ref) / scale
-    q = np.quantile(err, 0.999)
-    _say(f"real network: max {err.max():.2e}, 99.9% {q:.2e}, median {np.median(err):.2e} (scale {scale:.2f})")
-    assert err.max() <= 1e-2 and q <= 1e-4
+    err, bad, unexplained = _explain_flips(p, x, y, ref, scale)
+    ok = np.ones(n, dtype=bool)
+    ok[bad] = False
+    _say(f"real network: {bad.size} of {n} samples beyond {OUT_TOL:g} (max {err.max():.2e}), "
+         f"{unexplained.size} not explained by one flipped hidden unit; others max {err[ok].max():.2e}")
+    assert unexplained.size == 0, unexplained[:10]
+    assert err.max() <= 1e-2
+    assert bad.size <= 0.01 * n
 
 
 def test_weights_round_trip_and_empty_batch():
@@ -286,10 +342,34 @@ def test_constant_and_nonfinite_outputs_match_oracle(prec):
     assert nfb_ref == cfg.nx * cfg.ny * cfg.nz
 
 
+def _stencil_reach(mask_cells, cfg):
+    """Cells within one cell (periodic in x and y, clipped at the lids) of a
+    flagged cell, as an (nz, ny, nx) mask."""
+    m = mask_cells.reshape(cfg.nz, cfg.ny, cfg.nx)
+    out = np.zeros_like(m)
+    for dk in (-1, 0, 1):
+        mk = np.zeros_like(m)
+        if dk < 0:
+            mk[:dk] = m[-dk:]
+        elif dk > 0:
+            mk[dk:] = m[:-dk]
+        else:
+            mk = m
+        for dj in (-1, 0, 1):
+            for di in (-1, 0, 1):
+                out |= np.roll(np.roll(mk, dj, axis=1), di, axis=2)
+    return out
+
+
 def test_network_closure_rhs_matches_bf16_oracle():
     """He-initialised network scaled so that no cell is near the fallback
-    threshold; the stress part of the tendency carries the network's rounding
-    (see the module docstring), the rest is FP64."""
+    threshold.  The network's per-cell outputs on the standardised inputs
+    (erf_mlp_forward, the same network code the closure kernel runs) must
+    match the oracle or differ by an explained flip; the stress part of each
+    tendency must then agree to 1e-5 of its scale everywhere except within one
+    cell of a flipped cell, and to 1e-2 there.  The rest of the right-hand side
+    is FP64 on both sides."""
+    torch = pytest.importorskip("torch")
     cfg = _closure_cfg()
     o, s, th0, b = _pair(cfg)
     S = _turbulent(cfg, b, th0, 80)
@@ -303,22 +383,43 @@ def test_network_closure_rhs_matches_bf16_oracle():
     s.mlp_set_weights(p.astype(np.float32), nrm)
     R = s.to_numpy(s.slow_rhs(s.to_device(S)))
     nfb = s.mlp_fallback_count()
+    # the network per cell
+    x = (o.sgs_features(S) - nrm[:10]) / nrm[10:20]
+    yref = oracle.mlp_forward(p, x, bf16=True)
+    y = s.mlp_forward(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().double().numpy()
+    err, flipped, unexplained = _explain_flips(p, x, y, yref, np.abs(yref).max())
+    cells = np.zeros(cfg.nx * cfg.ny * cfg.nz, dtype=bool)
+    cells[flipped] = True
+    cells |= _bf16_input_ties(x)
+    reach = _stencil_reach(cells, cfg)
     out = {}
     for f in ("rt", "ru", "rv", "rw"):
         sgs = ref[f] - base[f]
         m = np.abs(sgs).max()
         e = np.abs(R[f] - ref[f]) / m
-        out[f] = (m, e.max(), np.quantile(e, 0.97), np.median(e))
-    _say(f"network closure rhs: fallbacks {nfb} (oracle {nfb_ref});",
-         {f: f"|sgs| {m:.2e} max {a:.1e} 97% {q:.1e} median {md:.1e}" for f, (m, a, q, md) in out.items()})
+        # tendencies on z-faces: the faces below and above each flagged cell
+        r = reach if f != "rw" else np.concatenate([reach[:1], reach[:-1] | reach[1:], reach[-1:]])
+        out[f] = (m, e.max(), e[~r].max() if (~r).any() else 0.0, r.mean())
+    _say(f"network closure rhs: fallbacks {nfb} (oracle {nfb_ref}); {flipped.size} cells with a flipped hidden "
+         f"value ({unexplained.size} unexplained) of {cells.size};",
+         {f: f"|sgs| {m:.2e} max {a:.1e} elsewhere {q:.1e} (reach {fr:.3f})" for f, (m, a, q, fr) in out.items()})
+    assert unexplained.size == 0
     assert nfb == nfb_ref
-    for f, (m, a, q, md) in out.items():
+    for f, (m, a, q, fr) in out.items():
         assert m > 0 and a <= 1e-2 and q <= 1e-5, f
     assert _rel(R["rho"], ref["rho"]) <= 1e-12
 
 
 # -- training --------------------------------------------------------------------------
 def test_gradient_matches_bf16_oracle():
+    """Per parameter against the oracle's BF16-mode gradient, relative to the
+    sum of the magnitudes of that gradient's terms (mlp_grad_abs).  The
+    products of BF16 operands are exact in FP32; the sums are FP32 over chunks
+    of 256 samples and FP64 across chunks (about 256 * 2^-24 = 1.5e-5 of the
+    scale at worst).  Where a sample's hidden value or output difference sits at
+    a bfloat16 boundary, one term can change by 2^-8 of itself: every
+    parameter stays within 2^-7 of its scale, and the parameters beyond the
+    accumulation bound must be few."""
     torch = pytest.importorskip("torch")
     p = _he_params(90)
     rng = np.random.default_rng(91)
@@ -326,15 +427,23 @@ def test_gradient_matches_bf16_oracle():
     x = rng.normal(size=(n, 10)).astype(np.float32).astype(np.float64)
     t = rng.normal(size=(n, 9)).astype(np.float32).astype(np.float64)
     lref, gref = oracle.mlp_loss_grad(p, x, t, bf16=True)
+    gabs = oracle.mlp_grad_abs(p, x, t, bf16=True)
     s, _ = _solver(_net_cfg())
     s.mlp_set_weights(p.astype(np.float32))
     loss, g = s.mlp_loss_grad(torch.tensor(x, dtype=torch.float32, device="cuda"),
                               torch.tensor(t, dtype=torch.float32, device="cuda"))
     g = g.cpu().double().numpy()
-    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
-    _say(f"gradient: loss {loss:.6f} (oracle {lref:.6f}), relative L2 error {rel:.2e}")
+    live = gabs > 0
+    rel = np.zeros_like(g)
+    rel[live] = np.abs(g - gref)[live] / gabs[live]
+    over = np.count_nonzero(rel > 1.5e-5)
+    _say(f"gradient: loss {loss:.6f} (oracle {lref:.6f}); per parameter |diff| / sum|terms|: max {rel.max():.2e}, "
+         f"99.9% {np.quantile(rel, 0.999):.2e}, median {np.median(rel[live]):.2e}; {over} of {live.sum()} above the "
+         f"accumulation bound")
+    assert np.all(g[~live] == 0.0)
     assert abs(loss - lref) <= 1e-5 * lref
-    assert rel <= 1e-4
+    assert rel.max() <= 2.0 ** -7
+    assert over <= 0.01 * live.sum()
 
 
 def test_training_decreases_loss_like_oracle():

@@ -22,8 +22,8 @@ pytestmark = pytest.mark.gpu
 # or 3 of 16, the last one partial
 CFG = dict(name="cbl_small", nx=70, ny=20, nz=40, dx=20.0, dy=20.0, dz=W.uniform_dz(40, 10.0), dt=0.1,
            adv_order_h=5, adv_order_v=5, sgs=1, Cs=0.1, f_cor=1e-4, Ug=10.0, Vg=1.0, surf_heat_flux=0.2)
-# 64 x 8 columns: every row shape fills its tiles exactly, so the substep
-# exchanges stencil neighbours across lanes instead of loading them
+# 64 x 8 columns: every row shape fills its tiles exactly (no idle lanes, no
+# partial tile at the domain's end)
 CFG_FULL = dict(CFG, nx=64, ny=8, nz=24, dz=W.uniform_dz(24, 10.0))
 
 

@@ -163,6 +163,63 @@ def test_bf16_gradient_close_to_fp64():
     assert abs(l16 - l64) < 2e-2 * l64
 
 
+@pytest.mark.parametrize("bf16", [False, True])
+def test_gradient_magnitude_scale(bf16):
+    """The per-parameter scale sum |terms| bounds |gradient| (triangle
+    inequality), and equals it where no term can cancel: with non-negative
+    weights, biases and inputs every activation is positive, and with every
+    output above its target every backpropagated term is non-negative."""
+    p = np.abs(_rand_params(12))
+    rng = np.random.default_rng(13)
+    x = np.abs(rng.normal(size=(40, 10)))
+    y = oracle.mlp_forward(p, x, bf16=bf16)
+    t = y - 0.5 - rng.random(y.shape)               # every output above its target
+    _, g = oracle.mlp_loss_grad(p, x, t, bf16=bf16)
+    ga = oracle.mlp_grad_abs(p, x, t, bf16=bf16)
+    assert np.all(g >= 0.0)
+    assert np.allclose(ga, g, rtol=1e-12, atol=0.0)
+    # mixed signs: the scale bounds the gradient and exceeds it somewhere
+    p2, x2 = _rand_params(14), rng.normal(size=(40, 10))
+    t2 = rng.normal(size=(40, 9))
+    _, g2 = oracle.mlp_loss_grad(p2, x2, t2, bf16=bf16)
+    ga2 = oracle.mlp_grad_abs(p2, x2, t2, bf16=bf16)
+    assert np.all(np.abs(g2) <= ga2 * (1 + 1e-12))
+    assert np.any(np.abs(g2) < 0.5 * ga2)
+
+
+def test_forward_margin_closed_forms():
+    """One hidden unit per layer wired through (weight 1, every other weight
+    and bias zero, so the other units have no terms and report nothing), input
+    x0 = 1.  The bfloat16 values around 1 are 1 - 2^-8, 1 and 1 + 2^-7.
+      * bias 2^-8: the first unit's value 1 + 2^-8 is a rounding midpoint, margin 0;
+      * bias 2^-9: 2^-9 from the midpoint 1 + 2^-8, over |b| + |x W| = 1 + 2^-9
+        (the later units see 1, 2^-9 from the midpoint 1 - 2^-9 below, over 1);
+      * bias -1 - 2^-20: the value -2^-20 is 2^-20 from the ReLU switch at zero,
+        over 2 + 2^-20 (the later units see 0 and have no terms)."""
+    p = np.zeros(NP)
+    v = _view(p)
+    v["W1"][0, 0] = v["W2"][0, 0] = v["W3"][0, 0] = 1.0
+    x = np.zeros((1, 10))
+    x[0, 0] = 1.0
+    out = []
+    for b in (2.0 ** -8, 2.0 ** -9, -1.0 - 2.0 ** -20):
+        v["b1"][0] = b
+        out.append(oracle.mlp_forward_margin(p, x)[0])
+    assert out[0] == 0.0
+    assert out[1] == 2.0 ** -9 / (1 + 2.0 ** -9)
+    assert out[2] == 2.0 ** -20 / (2 + 2.0 ** -20)
+    # the counterfactual pass: 1 + 2^-9 rounds to 1 in the next layer; flipped,
+    # it is handed 1 + 2^-7, which the pass-through carries to output 0
+    v["b1"][0] = 2.0 ** -9
+    v["W4"][0, 0] = 1.0
+    y0 = oracle.mlp_forward_flipped(p, x, [-1])
+    assert np.array_equal(y0, oracle.mlp_forward(p, x, bf16=True))
+    assert y0[0, 0] == 1.0
+    assert oracle.mlp_forward_flipped(p, x, [0])[0, 0] == 1.0 + 2.0 ** -7
+    # a unit of the second layer (index 64 + 0) sees 1 and flips to 1 - 2^-8
+    assert oracle.mlp_forward_flipped(p, x, [64])[0, 0] in (1.0 - 2.0 ** -8, 1.0 + 2.0 ** -7)
+
+
 # -- Adam ---------------------------------------------------------------------------
 def test_adam_constant_gradient_step_is_lr():
     """With a constant gradient g the bias-corrected moments equal g and g^2,

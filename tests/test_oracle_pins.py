@@ -87,6 +87,171 @@ def test_weno5_limits():
     assert 0.99 < v <= 1.0 + 1e-12
 
 
+def _poly_mul(a, b):
+    out = [Fraction(0)] * (len(a) + len(b) - 1)
+    for i, x in enumerate(a):
+        for j, y in enumerate(b):
+            out[i + j] += x * y
+    return out
+
+
+def _poly_der(a):
+    return [i * a[i] for i in range(1, len(a))]
+
+
+def _poly_int(a, lo, hi):
+    return sum(c * (hi ** (n + 1) - lo ** (n + 1)) / (n + 1) for n, c in enumerate(a))
+
+
+def _poly_val(a, x):
+    return sum(c * x ** n for n, c in enumerate(a))
+
+
+def _fit_cell_averages(cells, vals):
+    """Polynomial (coefficients, ascending) whose averages over the unit cells
+    [j - 1/2, j + 1/2], j in cells, are vals: exact Gaussian elimination."""
+    h = Fraction(1, 2)
+    n = len(cells)
+    A = [[_poly_int([Fraction(0)] * m + [Fraction(1)], j - h, j + h) for m in range(n)] + [Fraction(v)]
+         for j, v in zip(cells, vals)]
+    for c in range(n):
+        piv = next(r for r in range(c, n) if A[r][c] != 0)
+        A[c], A[piv] = A[piv], A[c]
+        for r in range(n):
+            if r != c and A[r][c] != 0:
+                f = A[r][c] / A[c][c]
+                A[r] = [x - f * y for x, y in zip(A[r], A[c])]
+    return [A[r][n] / A[r][r] for r in range(n)]
+
+
+def _weno5_by_definition(v, eps, swap=False):
+    """WENO5-JS face value built from the scheme's definitions (Jiang & Shu
+    1996), in exact rational arithmetic: v[0..4] are the cell averages of cells
+    -2..2, cell 0 upwind of the face at x = 1/2.
+      * candidate k: the quadratic matching the averages of cells k-2..k, at x = 1/2;
+      * smoothness beta_k: sum over l = 1, 2 of the integral over cell 0 of
+        (d^l p_k / dx^l)^2 (unit spacing);
+      * linear weights d_k: the ones that make sum d_k p_k(1/2) equal the quartic
+        through all five averages, for any data;
+      * nonlinear weights alpha_k = d_k / (eps + beta_k)^2, normalised.
+    swap=True exchanges the weights of the two derivative integrals (a planted
+    mistake equivalent to swapping the 13/12 and 1/4 of the closed form)."""
+    h = Fraction(1, 2)
+    cands, betas = [], []
+    for k in range(3):
+        p = _fit_cell_averages([k - 2, k - 1, k], v[k:k + 3])
+        cands.append(_poly_val(p, h))
+        d1, d2 = _poly_der(p), _poly_der(_poly_der(p))
+        i1, i2 = _poly_int(_poly_mul(d1, d1), -h, h), _poly_int(_poly_mul(d2, d2), -h, h)
+        # p = a + b x + c x^2 about cell 0: the closed form's second difference
+        # of the averages is 2c and its first-difference term is +-2b, so the
+        # closed form 13/12 (2c)^2 + 1/4 (2b)^2 equals i1 + i2 = b^2 + 13 c^2 / 3;
+        # the swapped coefficients give 1/4 (2c)^2 + 13/12 (2b)^2
+        if swap:
+            betas.append(Fraction(1, 4) * (2 * p[2]) ** 2 + Fraction(13, 12) * (2 * p[1]) ** 2)
+        else:
+            betas.append(i1 + i2)
+    # linear weights from the quartic's coefficients of v[0] and v[4]
+    unit = lambda m: [Fraction(int(i == m)) for i in range(5)]
+    quart = [_poly_val(_fit_cell_averages([-2, -1, 0, 1, 2], unit(m)), h) for m in range(5)]
+    cand_coef = [[_poly_val(_fit_cell_averages([k - 2, k - 1, k], unit(m)[k:k + 3]), h) for m in range(5)]
+                 for k in range(3)]
+    d0 = quart[0] / cand_coef[0][0]
+    d2 = quart[4] / cand_coef[2][4]
+    d = [d0, 1 - d0 - d2, d2]
+    for m in range(5):   # the same weights reproduce every coefficient of the quartic
+        assert sum(d[k] * cand_coef[k][m] for k in range(3)) == quart[m]
+    alpha = [d[k] / (eps + betas[k]) ** 2 for k in range(3)]
+    return sum(a * c for a, c in zip(alpha, cands)) / sum(alpha), d, betas
+
+
+def test_weno5_equals_its_definition():
+    """The oracle's WENO5 (closed-form smoothness indicators) against the scheme
+    built from its definitions in exact arithmetic, on non-smooth stencils where
+    the nonlinear weights decide the value; both flow directions.  The closed
+    form with the 13/12 and 1/4 swapped would miss by far more than the
+    tolerance on these stencils (checked here too)."""
+    eps = Fraction(1, 10 ** 6)
+    stencils = [[0, 0, 1, 3, 7], [2, -1, 4, 4, -3], [1, 1, 1, 0, 0], [0, 1, 0, 1, 0], [5, 3, 2, 2, 9],
+                [Fraction(1, 1000), 0, Fraction(3, 1000), Fraction(-2, 1000), Fraction(7, 1000)]]
+    rng = np.random.default_rng(5)
+    stencils += [[Fraction(int(x), 1000) for x in rng.integers(-999, 1000, 5)] for _ in range(6)]
+    missed = 0
+    for v in stencils:
+        ref, d, betas = _weno5_by_definition(v, eps)
+        assert d == [Fraction(1, 10), Fraction(6, 10), Fraction(3, 10)]
+        fv = [float(x) for x in v]
+        scale = max(1.0, max(abs(x) for x in fv))
+        # positive flow: q6 = q_{m-3..m+2} with the upwind cell m-1 = v[2]
+        got = oracle.weno5([fv[0], fv[1], fv[2], fv[3], fv[4], 0.0], 1.0)
+        assert abs(got - float(ref)) <= 1e-14 * scale, (v, got, float(ref))
+        # negative flow: the mirrored stencil, upwind cell m = v[2]
+        got = oracle.weno5([0.0, fv[4], fv[3], fv[2], fv[1], fv[0]], -1.0)
+        assert abs(got - float(ref)) <= 1e-14 * scale, (v, got, float(ref))
+        bad, _, _ = _weno5_by_definition(v, eps, swap=True)
+        missed += abs(float(bad) - float(ref)) > 1e-6 * scale
+    assert missed >= 6
+
+
+def test_weno5_golden_worked_example():
+    """The worked example of tests/golden/weno5.txt (smoothness indicators and
+    face value derived by hand from the definitions) against the definition
+    code and the oracle."""
+    rows = {}
+    for line in open(os.path.join(GOLDEN, "weno5.txt")):
+        if line.strip() and not line.startswith("#"):
+            key, *vals = line.split()
+            rows[key] = [Fraction(x) for x in vals]
+    v, eps = rows["stencil"], rows["eps"][0]
+    ref, d, betas = _weno5_by_definition(v, eps)
+    assert betas == rows["beta"]
+    assert d == rows["d"]
+    assert ref == rows["face"][0]
+    got = oracle.weno5([float(x) for x in v] + [0.0], 1.0, float(eps))
+    assert abs(got - float(ref)) <= 1e-15 * 7
+
+
+# ---------------------------------------------------------------------------
+# diagnostics: mass and energy budgets (Sec. 4.1.2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("wind", [(0.0, 0.0, 0.0), (7.0, 0.0, 0.0), (0.0, -3.0, 0.0), (0.0, 0.0, 2.5),
+                                  (4.0, 1.5, -2.0)])
+def test_energy_diagnostic_closed_form(wind):
+    """Uniform density and temperature (any values: the sums are pointwise):
+    the ideal-gas relations p = rho R_d T and theta = T (P00/p)^(R_d/c_p) give
+    Theta = rho theta, and the energy is sum (rho c_v T + rho g z) dV plus
+    rho |u|^2/2 dV for a uniform wind.  w lives on the z-faces and is zero on
+    the lids, so the cell-centred w is w0 inside and w0/2 in the two cells
+    next to a lid.  Mass and Sum Theta dV follow from the same state."""
+    u0, v0, w0 = wind
+    nz = 12
+    dz = np.linspace(300.0, 600.0, nz)
+    cfg = W.small(name="rest", nx=6, ny=5, nz=nz, dx=150.0, dy=90.0, dz=dz)
+    o, b, th0 = _setup(cfg, np.full(nz, 300.0))
+    rho, T, g = 1.1, 281.5, cfg.grav
+    p = rho * RD * T
+    theta = T * (P00 / p) ** (RD / CP)
+    S = o.zeros_state()
+    S["rho"][:] = rho
+    S["rt"][:] = rho * theta
+    S["ru"][:] = rho * u0
+    S["rv"][:] = rho * v0
+    S["rw"][1:-1] = rho * w0
+    d = o.diagnostics(S)
+    z = cfg.z_centres()
+    area = cfg.nx * cfg.ny * cfg.dx * cfg.dy
+    wc = np.full(nz, w0)
+    wc[0] = wc[-1] = 0.5 * w0
+    e_ref = math.fsum(area * dz[k] * (rho * CV * T + rho * g * z[k] + 0.5 * rho * (u0 ** 2 + v0 ** 2 + wc[k] ** 2))
+                      for k in range(nz))
+    assert d["energy"] == pytest.approx(e_ref, rel=2e-14)
+    assert d["mass"] == pytest.approx(rho * area * dz.sum(), rel=1e-15)
+    assert d["theta_mass"] == pytest.approx(rho * theta * area * dz.sum(), rel=1e-15)
+    assert d["max_w"] == pytest.approx(abs(w0), rel=1e-15, abs=0.0)
+    # each part matters at this tolerance: internal, potential and kinetic energy
+    assert CP / CV - 1 > 1e-3 and g * z[0] / (CV * T) > 1e-3
+
+
 # ---------------------------------------------------------------------------
 # Thomas algorithm vs dense solve
 # ---------------------------------------------------------------------------
