@@ -39,12 +39,13 @@ class _Params(C.Structure):
                 ("alpha_m", C.c_double), ("f_cor", C.c_double), ("Ug", C.c_double),
                 ("Vg", C.c_double), ("surf_heat_flux", C.c_double), ("grav", C.c_double),
                 ("mlp_params", C.POINTER(C.c_double)), ("mlp_norm", C.POINTER(C.c_double)),
-                ("mlp_bf16", C.c_int32)]
+                ("mlp_bf16", C.c_int32), ("moist", C.c_int32)]
 
 
 class _Base(C.Structure):
     _fields_ = [("rho0", C.POINTER(C.c_double)), ("theta0", C.POINTER(C.c_double)),
-                ("p0", C.POINTER(C.c_double)), ("pi0", C.POINTER(C.c_double))]
+                ("p0", C.POINTER(C.c_double)), ("pi0", C.POINTER(C.c_double)),
+                ("qv0", C.POINTER(C.c_double))]
 
 
 class _State(C.Structure):
@@ -69,6 +70,11 @@ def lib():
             L.orc_eos_p.argtypes = [C.c_double]
             L.orc_eos_pprime.restype = C.c_double
             L.orc_eos_pprime.argtypes = [C.c_double, C.c_double, C.c_double]
+            L.orc_eos_p_moist.restype = C.c_double
+            L.orc_eos_p_moist.argtypes = [C.c_double, C.c_double]
+            L.orc_eos_pprime_moist.restype = C.c_double
+            L.orc_eos_pprime_moist.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]
+            L.orc_base_state_moist.argtypes = [C.c_int32, _DP, _DP, _DP, C.c_double, C.c_double, _DP, _DP, _DP]
             L.orc_interp.restype = C.c_double
             L.orc_interp.argtypes = [C.c_int32, _DP, C.c_double]
             L.orc_weno5.restype = C.c_double
@@ -111,7 +117,7 @@ def _p(a: np.ndarray):
 
 
 def const(name: str) -> float:
-    return lib().orc_const({"R_d": 0, "c_p": 1, "c_v": 2, "gamma": 3, "P00": 4}[name])
+    return lib().orc_const({"R_d": 0, "c_p": 1, "c_v": 2, "gamma": 3, "P00": 4, "R_v": 5}[name])
 
 
 class Oracle:
@@ -125,7 +131,7 @@ class Oracle:
         self._params = _Params(cfg.dt, cfg.n_substeps, cfg.beta_s, cfg.beta_d, cfg.adv_order_h,
                                cfg.adv_order_v, cfg.scalar_scheme, cfg.n_scalars, cfg.sgs, cfg.Cs,
                                cfg.Pr_t, cfg.nu_m, cfg.alpha_m, cfg.f_cor, cfg.Ug, cfg.Vg,
-                               cfg.surf_heat_flux, cfg.grav, None, None, 0)
+                               cfg.surf_heat_flux, cfg.grav, None, None, 0, int(cfg.moist))
         self.base = None
         self._mlp = None
 
@@ -141,15 +147,20 @@ class Oracle:
         self._params.mlp_bf16 = int(bool(bf16))
 
     # -- base state -------------------------------------------------------
-    def init_base_state(self, theta0: np.ndarray, p_surface: float):
+    def init_base_state(self, theta0: np.ndarray, p_surface: float, qv0=None):
+        """Hydrostatic base state; qv0[nz] (None: dry) is the base-state water
+        vapour mixing ratio of the moist EOS."""
         nz = self.nz
         th = np.ascontiguousarray(theta0, dtype=np.float64)
+        qv = None if qv0 is None else np.ascontiguousarray(qv0, dtype=np.float64)
         rho0, p0, pi0 = np.zeros(nz), np.zeros(nz), np.zeros(nz)
-        rc = lib().orc_base_state(nz, _p(self.dz), _p(th), p_surface, self.cfg.grav, _p(rho0), _p(p0), _p(pi0))
+        rc = lib().orc_base_state_moist(nz, _p(self.dz), _p(th), None if qv is None else _p(qv), p_surface,
+                                        self.cfg.grav, _p(rho0), _p(p0), _p(pi0))
         if rc != 0:
             raise RuntimeError(f"orc_base_state failed ({rc})")
-        self.base = {"rho0": rho0, "theta0": th, "p0": p0, "pi0": pi0}
-        self._base = _Base(_p(rho0), _p(th), _p(p0), _p(pi0))
+        self.base = {"rho0": rho0, "theta0": th, "p0": p0, "pi0": pi0,
+                     "qv0": np.zeros(nz) if qv is None else qv}
+        self._base = _Base(_p(rho0), _p(th), _p(p0), _p(pi0), None if qv is None else _p(qv))
         return self.base
 
     # -- helpers ----------------------------------------------------------
@@ -354,12 +365,22 @@ def eos_pprime(Theta: float, Theta0: float, p0: float) -> float:
     return lib().orc_eos_pprime(Theta, Theta0, p0)
 
 
-def base_state(dz, theta0, p_surface: float, grav: float = 9.81):
+def eos_p_moist(Theta: float, qv: float) -> float:
+    return lib().orc_eos_p_moist(Theta, qv)
+
+
+def eos_pprime_moist(Theta: float, qv: float, Theta0: float, qv0: float, p0: float) -> float:
+    return lib().orc_eos_pprime_moist(Theta, qv, Theta0, qv0, p0)
+
+
+def base_state(dz, theta0, p_surface: float, grav: float = 9.81, qv0=None):
     dz = np.ascontiguousarray(dz, dtype=np.float64)
     th = np.ascontiguousarray(theta0, dtype=np.float64)
+    qv = None if qv0 is None else np.ascontiguousarray(qv0, dtype=np.float64)
     nz = len(dz)
     rho0, p0, pi0 = np.zeros(nz), np.zeros(nz), np.zeros(nz)
-    rc = lib().orc_base_state(nz, _p(dz), _p(th), p_surface, grav, _p(rho0), _p(p0), _p(pi0))
+    rc = lib().orc_base_state_moist(nz, _p(dz), _p(th), None if qv is None else _p(qv), p_surface, grav,
+                                    _p(rho0), _p(p0), _p(pi0))
     if rc != 0:
         raise RuntimeError("orc_base_state failed")
     return rho0, p0, pi0

@@ -24,6 +24,9 @@ static const double C_P = 1004.5;
 static const double P_00 = 1.0e5;
 #define C_V (C_P - R_D)
 #define GAM (C_P / (C_P - R_D))
+/* gas constant of water vapour, the usual value (reading) */
+static const double R_V = 461.6;
+#define EPS_V (R_V / R_D)
 
 double orc_const(int which)
 {
@@ -33,6 +36,7 @@ double orc_const(int which)
     case 2: return C_V;
     case 3: return GAM;
     case 4: return P_00;
+    case 5: return R_V;
     default: return NAN;
     }
 }
@@ -94,6 +98,21 @@ double orc_eos_pprime(double Theta, double Theta0, double p0)
 /* Exner function pi = (p/P00)^(R_d/c_p) = (R_d Theta / P00)^(gamma - 1). */
 static double exner(double Theta) { return pow(R_D * Theta / P_00, GAM - 1.0); }
 
+/* Moist EOS of Sec. 2.1: water vapour enters through the factor
+ * 1 + (R_v/R_d) q_v on rho_d theta_d, so every dry formula applies to
+ * Theta (1 + R_v/R_d q_v).  With q_v = 0 the factor is exactly 1. */
+double orc_eos_p_moist(double Theta, double qv) { return orc_eos_p(Theta * (1.0 + EPS_V * qv)); }
+
+/* p' = p(Theta, q_v) - p(Theta0, q_v0).  With X = Theta (1 + eps q_v) and
+ * X0 = Theta0 (1 + eps q_v0), p/p0 = (X/X0)^gamma and
+ * X - X0 = (Theta - Theta0)(1 + eps q_v) + eps Theta0 (q_v - q_v0), an exact
+ * rewriting that keeps the small differences apart from the large values. */
+double orc_eos_pprime_moist(double Theta, double qv, double Theta0, double qv0, double p0)
+{
+    double x = ((Theta - Theta0) * (1.0 + EPS_V * qv) + EPS_V * Theta0 * (qv - qv0)) / (Theta0 * (1.0 + EPS_V * qv0));
+    return p0 * expm1(GAM * log1p(x));
+}
+
 /* ------------------------------------------------------------------------ */
 /* base state: dp0/dz = -rho0 g and p0 = EOS(rho0 theta0) (Sec. 2, Sec. 3.8) */
 /* ------------------------------------------------------------------------ */
@@ -104,30 +123,43 @@ static double exner(double Theta) { return pow(R_D * Theta / P_00, GAM - 1.0); }
 int orc_base_state(int32_t nz, const double *dz, const double *theta0, double p_surface,
                    double grav, double *rho0, double *p0, double *pi0)
 {
+    return orc_base_state_moist(nz, dz, theta0, NULL, p_surface, grav, rho0, p0, pi0);
+}
+
+/* reading (moist, Sec. 2 and Sec. 3.8): rho0 is the dry density; the column
+ * weighs rho0 (1 + q_v0) and the pressure is the moist EOS of rho0 theta0 and
+ * q_v0.  With q_v0 = 0 (or NULL) every factor is exactly 1 and the dry state
+ * is reproduced bit for bit. */
+int orc_base_state_moist(int32_t nz, const double *dz, const double *theta0, const double *qv0,
+                         double p_surface, double grav, double *rho0, double *p0, double *pi0)
+{
     if (nz < 1 || !dz || !theta0 || !rho0 || !p0) return -1;
-    double p_below = p_surface, rho_below = 0.0;
+    double p_below = p_surface, rho_below = 0.0, q_below = 0.0;
     for (int k = 0; k < nz; ++k) {
+        double q = qv0 ? qv0[k] : 0.0;
+        if (!(q >= 0.0)) return -1;
         double h = (k == 0) ? 0.5 * dz[0] : 0.5 * (dz[k - 1] + dz[k]);
-        double rho = (k == 0) ? p_surface / (R_D * theta0[0]) : rho_below;
+        double rho = (k == 0) ? p_surface / (R_D * theta0[0] * (1.0 + EPS_V * q)) : rho_below;
         for (int it = 0; it < 30; ++it) {
-            double p = orc_eos_p(rho * theta0[k]);
+            double p = orc_eos_p_moist(rho * theta0[k], q);
             double f, df;
             if (k == 0) {
-                f = p - p_below + grav * h * rho;
-                df = GAM * p / rho + grav * h;
+                f = p - p_below + grav * h * (rho * (1.0 + q));
+                df = GAM * p / rho + grav * h * (1.0 + q);
             } else {
-                f = p - p_below + grav * h * 0.5 * (rho + rho_below);
-                df = GAM * p / rho + grav * h * 0.5;
+                f = p - p_below + grav * h * 0.5 * (rho * (1.0 + q) + rho_below * (1.0 + q_below));
+                df = GAM * p / rho + grav * h * 0.5 * (1.0 + q);
             }
             double d = f / df;
             rho = rho - d;
             if (fabs(d) <= 1e-15 * rho) break;
         }
         rho0[k] = rho;
-        p0[k] = orc_eos_p(rho * theta0[k]);
+        p0[k] = orc_eos_p_moist(rho * theta0[k], q);
         if (pi0) pi0[k] = pow(p0[k] / P_00, R_D / C_P);
         p_below = p0[k];
         rho_below = rho;
+        q_below = q;
     }
     return 0;
 }
@@ -424,12 +456,28 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
     size_t n = (size_t)nx * ny * nz, nw = (size_t)nx * ny * (nz + 1);
     double dx = g->dx, dy = g->dy, gr = P->grav;
     const double *dz = g->dz;
+    int moist = P->moist != 0;
+    if (moist && (P->n_scalars < 3 || !S->rq)) return -1;
     double *th = dalloc(n), *u = dalloc(n), *v = dalloc(n), *w = dalloc(nw), *pp = dalloc(n);
+    /* moist: 1 + q_v + q_c (divides the pressure gradient and the buoyancy,
+     * eq. (mom)) and the departure of the total density rho_d (1 + q_v + q_c
+     * + q_r) from the base state's rho0 (1 + q_v0) (the buoyancy) */
+    double *qf = moist ? dalloc(n) : NULL, *bm = moist ? dalloc(n) : NULL;
     primitives(g, S, th, u, v, w);
     for (int k = 0; k < nz; ++k) {
         double T0 = B->rho0[k] * B->theta0[k];
-        for (size_t c = (size_t)k * nx * ny; c < (size_t)(k + 1) * nx * ny; ++c)
-            pp[c] = orc_eos_pprime(S->rt[c], T0, B->p0[k]);
+        double qv0 = B->qv0 ? B->qv0[k] : 0.0;
+        for (size_t c = (size_t)k * nx * ny; c < (size_t)(k + 1) * nx * ny; ++c) {
+            if (moist) {
+                double rqv = S->rq[c], rqc = S->rq[n + c], rqr = S->rq[2 * n + c];
+                double qv = rqv / S->rho[c], qc = rqc / S->rho[c];
+                pp[c] = orc_eos_pprime_moist(S->rt[c], qv, T0, qv0, B->p0[k]);
+                qf[c] = 1.0 + qv + qc;
+                bm[c] = (S->rho[c] - B->rho0[k]) + (rqv + rqc + rqr) - B->rho0[k] * qv0;
+            } else {
+                pp[c] = orc_eos_pprime(S->rt[c], T0, B->p0[k]);
+            }
+        }
     }
 
     /* --- continuity and potential temperature, eqs. (con), (theta) --- */
@@ -474,6 +522,8 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                 double fxz1 = (k == nz - 1) ? 0.0 : e_1 * izc(g, u, i, j, k + 1, ov, sgn(e_1));
                 double adv = (fxx_r - fxx_l) / dx + (fxy1 - fxy0) / dy + (fxz1 - fxz0) / dz[k];
                 double pgf = (pp[c] - cget(g, pp, i - 1, j, k)) / dx;
+                /* reading (moist): 1 + q_v + q_c on the face is the mean of its two cells */
+                if (moist) pgf = pgf / (0.5 * (cget(g, qf, i - 1, j, k) + qf[c]));
                 double rho_f = 0.5 * (cget(g, S->rho, i - 1, j, k) + S->rho[c]);
                 /* reading: f-plane Coriolis with geostrophic forcing, the
                  * v-momentum averaged from the four surrounding y-faces */
@@ -502,6 +552,7 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                 double fyz1 = (k == nz - 1) ? 0.0 : e_1 * izc(g, v, i, j, k + 1, ov, sgn(e_1));
                 double adv = (fyx1 - fyx0) / dx + (fyy_r - fyy_l) / dy + (fyz1 - fyz0) / dz[k];
                 double pgf = (pp[c] - cget(g, pp, i, j - 1, k)) / dy;
+                if (moist) pgf = pgf / (0.5 * (cget(g, qf, i, j - 1, k) + qf[c]));
                 double rho_f = 0.5 * (cget(g, S->rho, i, j - 1, k) + S->rho[c]);
                 double ubar = 0.25 * (cget(g, S->ru, i, j - 1, k) + cget(g, S->ru, i + 1, j - 1, k) + S->ru[c] + cget(g, S->ru, i + 1, j, k));
                 double cor = -P->f_cor * (ubar - rho_f * P->Ug);
@@ -537,8 +588,16 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                 double adv = (fzx1 - fzx0) / dx + (fzy1 - fzy0) / dy + (fzz_u - fzz_d) / dzf;
                 double pgf = (pp[c] - pp[cm]) / dzf;
                 /* reading of the garbled sign: heavier-than-base air sinks */
-                double buoy = -gr * 0.5 * ((S->rho[c] - B->rho0[k]) + (S->rho[cm] - B->rho0[k - 1]));
-                R->rw[c] = -adv - pgf + buoy;
+                if (moist) {
+                    /* reading (moist): B = -g (rho_m - rho_m0) with the total
+                     * densities, and -grad p' + B divided by 1 + q_v + q_c */
+                    double buoy = -gr * 0.5 * (bm[c] + bm[cm]);
+                    double qfm = 0.5 * (qf[cm] + qf[c]);
+                    R->rw[c] = -adv - pgf / qfm + buoy / qfm;
+                } else {
+                    double buoy = -gr * 0.5 * ((S->rho[c] - B->rho0[k]) + (S->rho[cm] - B->rho0[k - 1]));
+                    R->rw[c] = -adv - pgf + buoy;
+                }
             }
 
     if (P->sgs == 1 || P->nu_m != 0.0 || P->alpha_m != 0.0) add_diffusion(g, P, S, th, u, v, w, R);
@@ -551,7 +610,7 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                 R->rt[c] += S->rho[c] * P->surf_heat_flux / dz[0];
             }
 
-    free(th); free(u); free(v); free(w); free(pp);
+    free(th); free(u); free(v); free(w); free(pp); free(qf); free(bm);
     return 0;
 }
 
@@ -576,14 +635,32 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
     const double *dz = g->dz;
     double b1 = 0.5 * (1.0 - P->beta_s), b2 = 0.5 * (1.0 + P->beta_s), bd = P->beta_d;
 
-    double *tht = dalloc(n), *pit = dalloc(n);
+    int moist = P->moist != 0;
+    if (moist && (P->n_scalars < 3 || !St->rq)) return -1;
+    double *tht = dalloc(n), *pit = dalloc(n), *pim = dalloc(n), *rdm = dalloc(n);
     double *U2 = dalloc(n), *V2 = dalloc(n), *W2 = dalloc(nw), *T2 = dalloc(n), *R2 = dalloc(n);
     double *T2p = dalloc(n), *Un = dalloc(n), *Vn = dalloc(n), *Wn = dalloc(nw), *Tn = dalloc(n), *Rn = dalloc(n);
     double *sU = dalloc(n), *sV = dalloc(n), *sW = dalloc(nw);
 
+    /* reading (moist, App. C with the moist EOS of Sec. 2.1): pi^t is the
+     * Exner function of the moist stage state; the pressure-gradient
+     * coefficient gamma R_d pi^t becomes the exact dp/dTheta divided by
+     * 1 + q_v + q_c, i.e. gamma R_d pi^t (1 + R_v/R_d q_v^t)/(1 + q_v^t + q_c^t)
+     * (pim); rho_d/rho_m = 1/(1 + q_v + q_c + q_r) multiplies the buoyancy
+     * correction.  Dry: pim = pi^t and rho_d/rho_m = 1 exactly. */
     for (size_t c = 0; c < n; ++c) {
         tht[c] = St->rt[c] / St->rho[c];
-        pit[c] = exner(St->rt[c]);
+        if (moist) {
+            double qv = St->rq[c] / St->rho[c], qc = St->rq[n + c] / St->rho[c], qr = St->rq[2 * n + c] / St->rho[c];
+            double fv = 1.0 + EPS_V * qv;
+            pit[c] = exner(St->rt[c] * fv);
+            pim[c] = pit[c] * (fv / (1.0 + qv + qc));
+            rdm[c] = 1.0 / (1.0 + qv + qc + qr);
+        } else {
+            pit[c] = exner(St->rt[c]);
+            pim[c] = pit[c];
+            rdm[c] = 1.0;
+        }
         U2[c] = Sn->ru[c] - St->ru[c];
         V2[c] = Sn->rv[c] - St->rv[c];
         T2[c] = Sn->rt[c] - St->rt[c];
@@ -602,8 +679,8 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
                     double tt_c = T2[c] + bd * (T2[c] - T2p[c]);
                     double tt_w = cget(g, T2, i - 1, j, k) + bd * (cget(g, T2, i - 1, j, k) - cget(g, T2p, i - 1, j, k));
                     double tt_s = cget(g, T2, i, j - 1, k) + bd * (cget(g, T2, i, j - 1, k) - cget(g, T2p, i, j - 1, k));
-                    double pfx = 0.5 * (cget(g, pit, i - 1, j, k) + pit[c]);
-                    double pfy = 0.5 * (cget(g, pit, i, j - 1, k) + pit[c]);
+                    double pfx = 0.5 * (cget(g, pim, i - 1, j, k) + pim[c]);
+                    double pfy = 0.5 * (cget(g, pim, i, j - 1, k) + pim[c]);
                     Un[c] = U2[c] + dtau * (-GAM * R_D * pfx * (tt_c - tt_w) / dx + Rt->ru[c]);
                     Vn[c] = V2[c] + dtau * (-GAM * R_D * pfy * (tt_c - tt_s) / dy + Rt->rv[c]);
                 }
@@ -638,10 +715,13 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
                     size_t c = CIDX(g, i, j, k), cm = CIDX(g, i, j, k - 1);
                     double dzf = 0.5 * (dz[k - 1] + dz[k]);
                     double pif = 0.5 * (pit[cm] + pit[c]);
-                    double A = GAM * R_D * pif;
-                    double Cc = gr * 0.5 * (B->rho0[k - 1] + B->rho0[k]) * (R_D / C_V)
+                    double A = GAM * R_D * (0.5 * (pim[cm] + pim[c]));
+                    /* rho-bar: the base state's total density on the face */
+                    double qb0 = B->qv0 ? B->qv0[k - 1] : 0.0, qb1 = B->qv0 ? B->qv0[k] : 0.0;
+                    double Cc = gr * 0.5 * (B->rho0[k - 1] * (1.0 + qb0) + B->rho0[k] * (1.0 + qb1)) * (R_D / C_V)
                               * (pif / (0.5 * (B->pi0[k - 1] + B->pi0[k])))
-                              / (0.5 * (St->rt[cm] + St->rt[c]));
+                              / (0.5 * (St->rt[cm] + St->rt[c]))
+                              * (0.5 * (rdm[cm] + rdm[c]));
                     double idzm = 1.0 / dz[k - 1], idz = 1.0 / dz[k];
                     double tfm = THZ(k - 1), tf = THZ(k), tfp = THZ(k + 1);
                     ta[k - 1] = -D * (A * tfm * idzm / dzf + 0.5 * Cc * tfm * idzm - 0.5 * gr * idzm);
@@ -698,7 +778,7 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
         if (Fw) Fw[c] = St->rw[c] + sW[c] / n_sub;
     }
 
-    free(tht); free(pit); free(U2); free(V2); free(W2); free(T2); free(R2); free(T2p);
+    free(tht); free(pit); free(pim); free(rdm); free(U2); free(V2); free(W2); free(T2); free(R2); free(T2p);
     free(Un); free(Vn); free(Wn); free(Tn); free(Rn); free(sU); free(sV); free(sW);
     return 0;
 }

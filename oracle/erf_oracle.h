@@ -49,10 +49,15 @@ typedef struct {
     /* learned closure (sgs == 2): parameters, norm stats, BF16 emulation */
     const double *mlp_params, *mlp_norm;
     int32_t mlp_bf16;
+    /* moist dynamics: the first three scalars are rho q_v, rho q_c, rho q_r;
+     * they enter the EOS, the pressure-gradient and buoyancy terms and the
+     * acoustic coefficients (Sec. 2.1, App. C); needs n_scalars >= 3 */
+    int32_t moist;
 } orc_params;
 
 typedef struct {
     const double *rho0, *theta0, *p0, *pi0; /* nz each */
+    const double *qv0;                      /* nz, base-state vapour; NULL: dry */
 } orc_base;
 
 typedef struct {
@@ -60,16 +65,24 @@ typedef struct {
 } orc_state;
 
 /* physical constants used by the oracle (gas constant, heat capacity, P00) */
-double orc_const(int which); /* 0 R_d, 1 c_p, 2 c_v, 3 gamma, 4 P00 */
+double orc_const(int which); /* 0 R_d, 1 c_p, 2 c_v, 3 gamma, 4 P00, 5 R_v */
 
 /* Hydrostatic base state by Newton iteration, Sec. 2 and Sec. 3.8. */
 int orc_base_state(int32_t nz, const double *dz, const double *theta0, double p_surface,
                    double grav, double *rho0, double *p0, double *pi0);
+/* The same with a base-state water vapour mixing ratio qv0[nz] (NULL: dry):
+ * the moist EOS and the weight of the vapour, dp0/dz = -g rho0 (1 + qv0). */
+int orc_base_state_moist(int32_t nz, const double *dz, const double *theta0, const double *qv0,
+                         double p_surface, double grav, double *rho0, double *p0, double *pi0);
 
 /* Equation of state, Sec. 2.1: p = P00 (R_d Theta / P00)^gamma. */
 double orc_eos_p(double Theta);
 /* p' = p(Theta) - p(Theta0) evaluated without cancellation. */
 double orc_eos_pprime(double Theta, double Theta0, double p0);
+/* Moist EOS, Sec. 2.1: p = P00 (R_d Theta (1 + R_v/R_d q_v) / P00)^gamma. */
+double orc_eos_p_moist(double Theta, double qv);
+/* p' = p(Theta, q_v) - p0 with p0 = p(Theta0, q_v0), without cancellation. */
+double orc_eos_pprime_moist(double Theta, double qv, double Theta0, double qv0, double p0);
 
 /* Face interpolant q_{m-1/2} of Sec. 3.6; q = {q_{m-3},...,q_{m+2}}. */
 double orc_interp(int32_t order, const double *q6, double sgn);

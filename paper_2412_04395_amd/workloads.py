@@ -56,6 +56,7 @@ class Config:
     surf_heat_flux: float = 0.0
     grav: float = 9.81
     prec: str = "fp64"  # "fp64" or "fp32" (FP32 bulk, FP64 column solve and sums)
+    moist: int = 0  # 1: scalars 0, 1, 2 are rho q_v, rho q_c, rho q_r and enter the dynamics
     p_surface: float = 1.0e5
     seed: int = 1
 
@@ -141,6 +142,36 @@ def theta_sounding(cfg: Config) -> np.ndarray:
     return np.full(cfg.nz, 300.0)
 
 
+def relative_humidity(z: np.ndarray) -> np.ndarray:
+    """Relative humidity of the deep-atmosphere sounding: 0.9 up to 1.5 km,
+    decaying as a 5/4 power to 0.25 at 12 km, 0.25 above."""
+    frac = np.clip((z - 1500.0) / 10500.0, 0.0, 1.0)
+    return np.where(z < 1500.0, 0.9, np.where(z < 12000.0, 0.9 - 0.65 * frac ** 1.25, 0.25))
+
+
+def qv_sounding(cfg: Config) -> np.ndarray:
+    """Base-state water vapour mixing ratio q_v0 at cell centres (an input of
+    the moist base state).  The relative humidity is converted with the
+    saturation pressure of Bolton (1980), e_s = 611.2 exp(17.67 (T - 273.15)
+    / (T - 29.65)) Pa, q_vs = 0.622 e_s / (p - e_s), at the temperature and
+    pressure of a simple dry estimate of the sounding: the Exner function
+    integrated upward as d pi / dz = -g / (c_p theta) from the surface
+    pressure.  Only the profile is defined here; each side builds its own
+    hydrostatic base state from theta0 and this q_v0."""
+    z = cfg.z_centres()
+    th = theta_sounding(cfg)
+    pis = (cfg.p_surface / _P00) ** (_RD / _CP)
+    dz = np.asarray(cfg.dz, dtype=np.float64)
+    pi = np.empty(cfg.nz)
+    pi[0] = pis - cfg.grav * 0.5 * dz[0] / (_CP * th[0])
+    for k in range(1, cfg.nz):
+        pi[k] = pi[k - 1] - cfg.grav * 0.5 * (dz[k - 1] + dz[k]) / (_CP * 0.5 * (th[k - 1] + th[k]))
+    T = th * pi
+    p = _P00 * pi ** (_CP / _RD)
+    es = 611.2 * np.exp(17.67 * (T - 273.15) / (T - 29.65))
+    return relative_humidity(z) * 0.622 * es / (p - es)
+
+
 # ---------------------------------------------------------------------------
 # initial states.  Perturbations of theta are applied at constant pressure:
 # rho*theta keeps its base value and rho = Theta0 / (theta0 + dtheta).
@@ -177,8 +208,9 @@ def state_from_theta(cfg: Config, rho0: np.ndarray, theta0: np.ndarray, dtheta: 
 
 
 def initial_state(cfg: Config, rho0: np.ndarray, theta0: np.ndarray, p0: Optional[np.ndarray] = None,
-                  pi0: Optional[np.ndarray] = None) -> dict:
-    """Seeded initial state of workload ``cfg`` around the given base state."""
+                  pi0: Optional[np.ndarray] = None, qv0: Optional[np.ndarray] = None) -> dict:
+    """Seeded initial state of workload ``cfg`` around the given base state
+    (qv0: the base-state vapour of a moist workload)."""
     nz, ny, nx = cfg.nz, cfg.ny, cfg.nx
     x, y = _centres_xy(cfg)
     z = cfg.z_centres()
@@ -219,23 +251,27 @@ def initial_state(cfg: Config, rho0: np.ndarray, theta0: np.ndarray, p0: Optiona
         raise ValueError(f"unknown workload {cfg.name}")
     S = state_from_theta(cfg, rho0, theta0, dth, u0, v0)
     if cfg.n_scalars > 0:
-        S["rq"] = scalar_layers(cfg, S["rho"], rho0, theta0, p0, pi0)
+        S["rq"] = scalar_layers(cfg, S["rho"], rho0, theta0, p0, pi0, qv0)
     return S
 
 
-def scalar_layers(cfg: Config, rho: np.ndarray, rho0, theta0, p0, pi0) -> np.ndarray:
-    """rho*q for the advected tracers: q_v from a relative-humidity profile
-    (Bolton 1980 saturation pressure), q_c and q_r smooth layers."""
+def scalar_layers(cfg: Config, rho: np.ndarray, rho0, theta0, p0, pi0, qv0=None) -> np.ndarray:
+    """rho*q for the advected tracers: q_v the base-state profile qv0 of a
+    moist workload, else from the relative-humidity profile (Bolton 1980
+    saturation pressure at the given base state); q_c and q_r smooth layers;
+    each with a seeded 5 % relative perturbation."""
     nz, ny, nx = cfg.nz, cfg.ny, cfg.nx
     z = cfg.z_centres()
     q = np.zeros((cfg.n_scalars, nz, ny, nx))
-    if p0 is not None and pi0 is not None:
+    if cfg.moist:
+        if qv0 is None:
+            raise ValueError("a moist workload needs the base-state vapour qv0")
+        qv = np.asarray(qv0, dtype=np.float64)
+    elif p0 is not None and pi0 is not None:
         T = theta0 * pi0
         es = 611.2 * np.exp(17.67 * (T - 273.15) / (T - 29.65))
         qvs = 0.622 * es / (p0 - es)
-        rh = np.where(z < 1500.0, 0.9,
-                      np.where(z < 12000.0, 0.9 - 0.65 * (np.maximum(z - 1500.0, 0.0) / 10500.0) ** 1.25, 0.25))
-        qv = rh * qvs
+        qv = relative_humidity(z) * qvs
     else:
         qv = 0.01 * np.exp(-z / 3000.0)
     qc = 1e-4 * np.exp(-((z - 3000.0) / 1000.0) ** 2)
@@ -311,12 +347,14 @@ def ensemble(sizes=((96, 96, 64), (128, 128, 64), (192, 192, 96)), per_size: int
 
 
 def deep(**kw) -> Config:
-    """80-level deep atmosphere, stretched dz 50-500 m to 20 km, 250 m horizontal,
-    3 tracers by WENO5, 3rd-order momentum, dt = 2 s, 8 substeps."""
+    """80-level moist deep atmosphere, stretched dz 50-500 m to 20 km, 250 m
+    horizontal, q_v, q_c, q_r by WENO5 and in the dynamics (moist EOS,
+    buoyancy and acoustic coefficients; no phase change), 3rd-order momentum,
+    dt = 2 s, 8 substeps."""
     nz = kw.pop("nz", 80)
     c = Config(name="deep", nx=512, ny=512, nz=nz, dx=250.0, dy=250.0,
                dz=stretched_dz(nz, 50.0, 500.0, 20000.0), dt=2.0, n_substeps=8, steps=20,
-               adv_order_h=3, adv_order_v=3, scalar_scheme=1, n_scalars=3, prec="fp32", seed=3)
+               adv_order_h=3, adv_order_v=3, scalar_scheme=1, n_scalars=3, prec="fp32", seed=3, moist=1)
     return c.replace(**kw)
 
 
