@@ -78,6 +78,11 @@ SCALAR_VALUES = {"mixing_ratio": lambda nq: (2 * nq + 1, 0), "scalar": lambda nq
 # (13 bulk values fewer) and its substep reads none of the 6 S'' inputs
 # (Theta'' twice, U'', V'', rho'', W'').
 ZERO_START_SAVED = {"stage_init": 13, "substep": 6}
+# Moist dynamics, per stage: the primitives pass also reads rho q_v, rho q_c,
+# rho q_r and writes 1 + q_v + q_c and the total-density departure, which the
+# tendencies read; the stage init reads the three species and writes the moist
+# Exner function and rho_d / rho_m, which the coefficients read.
+MOIST_STAGE_VALUES = {"prep": 5, "rhs": 2, "stage_init": 5, "coef": 2}
 
 
 def _kernel_bytes(kernel: str, sgs: int, prec: str) -> float:
@@ -134,9 +139,9 @@ def run_gpu(cfg: W.Config, steps: int, warmup: int):
     from paper_2412_04395_amd import erf
 
     s = erf.Solver(cfg)
-    th0 = W.theta_sounding(cfg)
-    b = s.init_base_state(th0)
-    S = s.from_full(W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"]))
+    th0, qv0 = W.theta_sounding(cfg), W.qv0_of(cfg)
+    b = s.init_base_state(th0, qv0=qv0)
+    S = s.from_full(W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"], qv0))
     for _ in range(warmup):
         s.rk3_step(S)
     tune = s.autotune(S, trials=2, cache_path=_tune_cache())
@@ -369,6 +374,8 @@ def _step_values(cfg):
         b, f = KERNEL_VALUES[k](sgs)
         bulk += n * b - (ZERO_START_SAVED.get(k, 0) if n else 0)
         f64 += n * f
+    if getattr(cfg, "moist", 0):
+        bulk += 3 * sum(MOIST_STAGE_VALUES.values())
     if not cfg.n_scalars:
         bulk += 3 * 5  # the stage end written by the last substep of each stage
     if cfg.n_scalars:
@@ -425,7 +432,8 @@ def run_scalars(steps: int, warmup: int) -> dict:
     tracers advected by WENO5 after every stage (the scalar-heavy case)."""
     cfg = W.deep()
     el, dom, kms, kn, shares, diag = run_gpu(cfg, steps, warmup)
-    out = {"workload": "deep atmosphere 512x512x80, stretched dz, 3 WENO5 tracers", "grid": [cfg.nx, cfg.ny, cfg.nz],
+    out = {"workload": "moist deep atmosphere 512x512x80, stretched dz, q_v, q_c, q_r by WENO5 and in the dynamics",
+           "grid": [cfg.nx, cfg.ny, cfg.nz],
            "precision": "FP32 storage, FP64 arithmetic, solve and sums", "n_scalars": cfg.n_scalars,
            "n_substeps": cfg.n_substeps, "value": cfg.cells * steps / el, "unit": "cell-updates/s",
            "ms_per_step": 1e3 * el / steps, "substep_shape": diag["substep_shape"],

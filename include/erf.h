@@ -86,6 +86,15 @@ typedef struct {
     double surf_heat_flux;   /* prescribed kinematic surface heat flux [K m/s]    */
     double grav;             /* magnitude of gravity [m/s^2]                      */
     int32_t precision;       /* erf_precision                                     */
+    int32_t moist;           /* 1: rhoq components 0, 1, 2 are rho q_v, rho q_c,
+                                rho q_r and enter the dynamics (Sec. 2.1): the
+                                equation of state with water vapour, the factor
+                                1/(1 + q_v + q_c) on the pressure gradient and
+                                the buoyancy, buoyancy from the total density,
+                                and the acoustic coefficients of App. C with
+                                the moist Exner function.  No phase change.
+                                Needs n_scalars >= 3; 0: dry, the scalars are
+                                passive                                          */
 } erf_params;
 
 /* Device pointers to one state (or tendency, or flux) set; unused members may
@@ -139,9 +148,13 @@ typedef struct {
 /* Hydrostatic base state on the host, no GPU involved (Sec. 2, Sec. 3.8):
  * dp0/dz = -rho0 g discretised between level centres with the trapezoidal
  * density, p0 = EOS(rho0 theta0) (Sec. 2.1), solved level by level with
- * Newton-Raphson from p(0) = p_surface.  Outputs are host arrays of nz values;
- * pi0 (Exner function) may be NULL. */
-erf_status erf_base_state_host(int32_t nz, const double *dz, const double *theta0,
+ * Newton-Raphson from p(0) = p_surface.  qv0 [nz] (may be NULL: dry) is the
+ * base-state water vapour mixing ratio: rho0 is then the dry density, the
+ * column weighs rho0 (1 + qv0) and p0 is the moist equation of state of
+ * rho0 theta0 and qv0; qv0 = 0 gives the dry state bit for bit.  Outputs are
+ * host arrays of nz values; pi0 (Exner function) may be NULL.  ERF_E_ARG for a
+ * non-positive theta0 or dz, or a negative qv0. */
+erf_status erf_base_state_host(int32_t nz, const double *dz, const double *theta0, const double *qv0,
                                double p_surface, double grav, double *rho0, double *p0,
                                double *pi0);
 
@@ -164,9 +177,11 @@ const char *erf_last_error(const erf_ctx *ctx);
 int64_t erf_workspace_bytes(const erf_ctx *ctx);
 
 /* Build the hydrostatic base state (as erf_base_state_host) from theta0 [nz]
- * (host) and upload it.  Must precede the calls below.  Optional host outputs
- * rho0, p0, pi0 [nz] may be NULL.  Synchronous. */
-erf_status erf_init_base_state(erf_ctx *ctx, const double *theta0, double p_surface,
+ * and qv0 [nz] (host; qv0 may be NULL: dry) and upload it.  Must precede the
+ * calls below.  A moist context (erf_params.moist) uses qv0 in the pressure
+ * perturbation and the buoyancy; a dry one refuses a non-NULL qv0 (ERF_E_ARG).
+ * Optional host outputs rho0, p0, pi0 [nz] may be NULL.  Synchronous. */
+erf_status erf_init_base_state(erf_ctx *ctx, const double *theta0, const double *qv0, double p_surface,
                                double *rho0, double *p0, double *pi0);
 
 /* Slow right-hand side f(S) of eqs. (con), (mom), (theta) (Sec. 2.1): flux-form
@@ -174,8 +189,11 @@ erf_status erf_init_base_state(erf_ctx *ctx, const double *theta0, double p_surf
  * gradient, buoyancy -(rho - rho0) g on z-faces, the stress tensor of
  * eq. (stresstensor) with constant or Smagorinsky viscosity (Sec. 2.3),
  * f-plane Coriolis with geostrophic forcing and the surface heat flux
- * (Sec. 3.7-3.8).  S and R use the state layout; R->rhoq is ignored and may be
- * NULL.  R->rhow is zero on faces 0 and nz. */
+ * (Sec. 3.7-3.8).  Moist contexts: the pressure gradient and the buoyancy
+ * -g (rho (1 + q_v + q_c + q_r) - rho0 (1 + qv0)) are divided by the face
+ * mean of 1 + q_v + q_c, and p' follows the moist equation of state; S->rhoq
+ * must then be given.  S and R use the state layout; R->rhoq is ignored and
+ * may be NULL.  R->rhow is zero on faces 0 and nz. */
 erf_status erf_slow_rhs(erf_ctx *ctx, const erf_state *S, erf_state *R);
 
 /* One RK stage of semi-implicit acoustic substepping (Sec. 3.1, App. C).
@@ -183,7 +201,13 @@ erf_status erf_slow_rhs(erf_ctx *ctx, const erf_state *S, erf_state *R);
  * linearisation frozen at S_t and the slow tendencies R_t, and writes the stage
  * end S_t + S'' to S_out (rho, rhotheta, rhou, rhov, rhow; rhoq untouched) and
  * the stage-averaged normal momenta used for scalar transport to
- * flux_avg->rhou / rhov / rhow (may be NULL).  S_out may alias S_n. */
+ * flux_avg->rhou / rhov / rhow (may be NULL).  S_out may alias S_n.  Moist
+ * contexts freeze the mixing ratios of S_t->rhoq (required) with the rest of
+ * the linearisation: the pressure-gradient coefficient gamma R_d pi^t becomes
+ * gamma R_d pi^t (1 + R_v/R_d q_v)/(1 + q_v + q_c), the exact dp/dTheta over
+ * the momentum equation's moisture factor, with pi^t the moist Exner
+ * function, and the buoyancy coefficient carries the base state's total
+ * density and rho_d / rho_m. */
 erf_status erf_acoustic_substeps(erf_ctx *ctx, const erf_state *S_n, const erf_state *S_t,
                                  const erf_state *R_t, int32_t n_sub, double dtau,
                                  erf_state *S_out, erf_state *flux_avg);

@@ -5,6 +5,8 @@
 //
 // Kernels of one stage:
 //   k_stage_init  S'' = S^n - S^t, frozen theta^t and Exner pi^t, zero sums
+//                 (moist: the pressure-gradient factor, the moist Exner
+//                 function and rho_d / rho_m of the stage state)
 //                 (a stage that starts from S^t = S^n with a single substep,
 //                 the first of RK3, has S'' = 0 exactly: its stage init and
 //                 substep are instances that neither write nor read the zeros)
@@ -48,12 +50,18 @@ struct StageArgs {
     const double *dz, *idz, *idzf;
     double g, b1, b2, bd, dtau;
     const double *rho0, *pi0, *Theta0;
+    // moist: base-state vapour and total density rho0 (1 + qv0); the stage
+    // state's rho q_v, rho q_c, rho q_r (n apart)
+    const double *qv0, *rho0t;
+    const T *t_q;
     // S^n, S^t, R^t
     const T *n_r, *n_t, *n_u, *n_v, *n_w;
     const T *t_r, *t_t, *t_u, *t_v, *t_w;
     const T *R_r, *R_t, *R_u, *R_v, *R_w;
-    // frozen fields
-    T *tht, *pit;
+    // frozen fields: theta^t and the pressure-gradient factor pi^t (moist: pi^t
+    // (1 + R_v/R_d q_v)/(1 + q_v + q_c)); moist also the Exner function pi^t and
+    // rho_d / rho_m, read by k_coef for the buoyancy coefficient
+    T *tht, *pit, *pex, *rdm;
     // perturbations (Theta'' three levels, U'' and V'' double-buffered) and sums
     T *T2cur, *T2prv, *T2nxt, *r2, *u2in, *u2out, *v2in, *v2out, *w2, *su, *sv, *sw;
     int sums;
@@ -67,7 +75,7 @@ struct StageArgs {
     T *o_r, *o_t, *o_u, *o_v, *o_w;
 };
 
-template <typename T, bool kZero>
+template <typename T, bool kZero, bool kMoist>
 __global__ __launch_bounds__(256) void k_stage_init(StageArgs<T> a)
 {
     const Dims &d = a.d;
@@ -90,12 +98,34 @@ __global__ __launch_bounds__(256) void k_stage_init(StageArgs<T> a)
     const double Tt = kPert<T> ? T0 + (double)tt : (double)tt;
     const double rt = kPert<T> ? a.rho0[k] + (double)tr : (double)tr;
     st_stream(a.tht + c, (T)(Tt / rt));
-    // Exner function of the stage state: (R_d Theta / P00)^(gamma - 1); from
-    // the perturbation in FP32 storage, pi0 (1 + Theta'/Theta0)^(gamma - 1)
-    if constexpr (kPert<T>)
-        st_stream(a.pit + c, (T)(a.pi0[k] * exp((kGamma - 1.0) * log1p((double)tt / T0))));
-    else
-        st_stream(a.pit + c, (T)pow(kRd * Tt / kP00, kGamma - 1.0));
+    if constexpr (kMoist) {
+        // Moist: the Exner function of Theta (1 + eps q_v) (Sec. 2.1), from the
+        // perturbation X/X0 - 1 about the moist base state in FP32 storage; the
+        // horizontal pressure gradient and A use gamma R_d pi^t (1 + eps q_v) /
+        // (1 + q_v + q_c), the exact dp/dTheta over the moisture factor of the
+        // momentum equation
+        const double qv = (double)ld_stream(a.t_q + c) / rt, qc = (double)ld_stream(a.t_q + c + d.n) / rt;
+        const double qr = (double)ld_stream(a.t_q + c + 2 * d.n) / rt;
+        const double fv = 1.0 + kEpsV * qv;
+        double pex;
+        if constexpr (kPert<T>) {
+            const double qv0 = a.qv0[k];
+            const double x = ((double)tt * fv + kEpsV * T0 * (qv - qv0)) / (T0 * (1.0 + kEpsV * qv0));
+            pex = a.pi0[k] * exp((kGamma - 1.0) * log1p(x));
+        } else {
+            pex = pow(kRd * (Tt * fv) / kP00, kGamma - 1.0);
+        }
+        st_stream(a.pit + c, (T)(pex * (fv / (1.0 + qv + qc))));
+        st_stream(a.pex + c, (T)pex);
+        st_stream(a.rdm + c, (T)(1.0 / (1.0 + qv + qc + qr)));
+    } else {
+        // Exner function of the stage state: (R_d Theta / P00)^(gamma - 1); from
+        // the perturbation in FP32 storage, pi0 (1 + Theta'/Theta0)^(gamma - 1)
+        if constexpr (kPert<T>)
+            st_stream(a.pit + c, (T)(a.pi0[k] * exp((kGamma - 1.0) * log1p((double)tt / T0))));
+        else
+            st_stream(a.pit + c, (T)pow(kRd * Tt / kP00, kGamma - 1.0));
+    }
     if constexpr (!kZero) {
         st_stream(a.T2cur + c, (T)((double)ld_stream(a.n_t + c) - (double)tt));
         st_stream(a.r2 + c, (T)((double)ld_stream(a.n_r + c) - (double)tr));
@@ -128,8 +158,10 @@ __device__ __forceinline__ void w_row_offdiag(double D, double g, double A, doub
 // dtau b2 delta_z(W)/dz into the W'' equation of App. C couples W_{k-1}, W_k,
 // W_{k+1} with coefficients of the frozen state only.  Factorised here (Thomas,
 // no pivoting; the rows are diagonally dominant).  C enters the rows as
-// stored (rounded to the bulk type), as the substep reads it.
-template <typename T>
+// stored (rounded to the bulk type), as the substep reads it.  kMoist: C from
+// the moist Exner function, the base state's total density and the face mean
+// of rho_d / rho_m (App. C with the moist equation of state).
+template <typename T, bool kMoist>
 __global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
 {
     const Dims &d = a.d;
@@ -147,10 +179,15 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
     double cprev = 0.0;
     for (int k0 = 1; k0 < nz; k0 += kChunk) {
         double P[kChunk + 1], TT[kChunk + 1], H[kChunk + 3];
+        double PX[kMoist ? kChunk + 1 : 1], RD[kMoist ? kChunk + 1 : 1];
 #pragma unroll
         for (int q = 0; q <= kChunk; ++q) {
-            P[q] = a.pit[lev(k0 - 1 + q)];      // Exner at level k0 - 1 + q
+            P[q] = a.pit[lev(k0 - 1 + q)];      // pressure-gradient factor (dry: Exner) at level k0 - 1 + q
             TT[q] = a.t_t[lev(k0 - 1 + q)];     // rho theta (stored form)
+            if constexpr (kMoist) {
+                PX[q] = a.pex[lev(k0 - 1 + q)];  // moist Exner function
+                RD[q] = a.rdm[lev(k0 - 1 + q)];  // rho_d / rho_m
+            }
         }
 #pragma unroll
         for (int q = 0; q < kChunk + 3; ++q) H[q] = a.tht[lev(k0 - 2 + q)];  // theta at k0 - 2 + q
@@ -165,8 +202,15 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
             double A = kGamma * kRd * pif;
             const double Tm = kPert<T> ? a.Theta0[k - 1] + TT[l] : TT[l];
             const double Tk = kPert<T> ? a.Theta0[k] + TT[l + 1] : TT[l + 1];
-            const T Cst = (T)(g * 0.5 * (a.rho0[k - 1] + a.rho0[k]) * (kRd / kCv) *
-                              (pif / (0.5 * (a.pi0[k - 1] + a.pi0[k]))) / (0.5 * (Tm + Tk)));
+            T Cst;
+            if constexpr (kMoist) {
+                const double pxf = 0.5 * (PX[l] + PX[l + 1]);
+                Cst = (T)(g * 0.5 * (a.rho0t[k - 1] + a.rho0t[k]) * (kRd / kCv) *
+                          (pxf / (0.5 * (a.pi0[k - 1] + a.pi0[k]))) / (0.5 * (Tm + Tk)) * (0.5 * (RD[l] + RD[l + 1])));
+            } else {
+                Cst = (T)(g * 0.5 * (a.rho0[k - 1] + a.rho0[k]) * (kRd / kCv) *
+                          (pif / (0.5 * (a.pi0[k - 1] + a.pi0[k]))) / (0.5 * (Tm + Tk)));
+            }
             const double C = Cst;
             const double idzm = a.idz[k - 1], idz = a.idz[k], idzf = a.idzf[k];
             const double tfm = tface(k - 1, l), tf = tface(k, l + 1), tfp = tface(k + 1, l + 2);
@@ -615,8 +659,8 @@ hipError_t allow_lds(size_t lds)
 }
 
 template <typename T>
-hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const St_[5], const void *const Rt_[5],
-                      int n_sub, double dtau, void *const Sout_[5], T *Fu, T *Fv, T *Fw)
+hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const St_[5], const void *rq_t,
+                      const void *const Rt_[5], int n_sub, double dtau, void *const Sout_[5], T *Fu, T *Fv, T *Fw)
 {
     const T *Sn[5], *St[5], *Rt[5];
     T *Sout[5];
@@ -642,6 +686,13 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
     a.rho0 = cx->base.rho0;
     a.pi0 = cx->base.pi0;
     a.Theta0 = cx->base.Theta0;
+    a.qv0 = cx->base.qv0;
+    a.rho0t = cx->base.rho0t;
+    const bool moist = cx->prm.moist != 0;
+    if (moist && !rq_t) return hipErrorInvalidValue;
+    a.t_q = (const T *)rq_t;
+    a.pex = (T *)w.pex;
+    a.rdm = (T *)w.rdm;
     a.n_r = Sn[0]; a.n_t = Sn[1]; a.n_u = Sn[2]; a.n_v = Sn[3]; a.n_w = Sn[4];
     a.t_r = St[0]; a.t_t = St[1]; a.t_u = St[2]; a.t_v = St[3]; a.t_w = St[4];
     a.R_r = Rt[0]; a.R_t = Rt[1]; a.R_u = Rt[2]; a.R_v = Rt[3]; a.R_w = Rt[4];
@@ -692,12 +743,21 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
     dim3 g3w((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz + 1);
     dim3 g2((d.nx + 63) / 64, (d.ny + 3) / 4, 1);
     timing_start(cx, K_STAGE_INIT);
-    if (zero)
-        hipLaunchKernelGGL((k_stage_init<T, true>), g3w, blk, 0, cx->stream, a);
+    if (zero && moist)
+        hipLaunchKernelGGL((k_stage_init<T, true, true>), g3w, blk, 0, cx->stream, a);
+    else if (zero)
+        hipLaunchKernelGGL((k_stage_init<T, true, false>), g3w, blk, 0, cx->stream, a);
+    else if (moist)
+        hipLaunchKernelGGL((k_stage_init<T, false, true>), g3w, blk, 0, cx->stream, a);
     else
-        hipLaunchKernelGGL((k_stage_init<T, false>), g3w, blk, 0, cx->stream, a);
+        hipLaunchKernelGGL((k_stage_init<T, false, false>), g3w, blk, 0, cx->stream, a);
     timing_stop(cx, K_STAGE_INIT);
-    timing_start(cx, K_COEF); hipLaunchKernelGGL(k_coef<T>, g2, blk, 0, cx->stream, a); timing_stop(cx, K_COEF);
+    timing_start(cx, K_COEF);
+    if (moist)
+        hipLaunchKernelGGL((k_coef<T, true>), g2, blk, 0, cx->stream, a);
+    else
+        hipLaunchKernelGGL((k_coef<T, false>), g2, blk, 0, cx->stream, a);
+    timing_stop(cx, K_COEF);
     for (int s = 0; s < n_sub; ++s) {
         const int t_nxt = 3 - t_cur - t_prv;
         a.T2cur = t2[t_cur];
@@ -739,13 +799,13 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
 }
 }  // namespace
 
-hipError_t launch_acoustic_stage(erf_ctx *cx, const void *const Sn[5], const void *const St[5],
+hipError_t launch_acoustic_stage(erf_ctx *cx, const void *const Sn[5], const void *const St[5], const void *rq_t,
                                  const void *const Rt[5], int n_sub, double dtau, void *const Sout[5],
                                  void *Fu, void *Fv, void *Fw)
 {
     if (cx->prm.precision == ERF_FP32_MIXED)
-        return acoustic_t<float>(cx, Sn, St, Rt, n_sub, dtau, Sout, (float *)Fu, (float *)Fv, (float *)Fw);
-    return acoustic_t<double>(cx, Sn, St, Rt, n_sub, dtau, Sout, (double *)Fu, (double *)Fv, (double *)Fw);
+        return acoustic_t<float>(cx, Sn, St, rq_t, Rt, n_sub, dtau, Sout, (float *)Fu, (float *)Fv, (float *)Fw);
+    return acoustic_t<double>(cx, Sn, St, rq_t, Rt, n_sub, dtau, Sout, (double *)Fu, (double *)Fv, (double *)Fw);
 }
 
 }  // namespace erfk

@@ -35,38 +35,44 @@ erf_status hip_fail(erf_ctx *c, hipError_t e, const char *where)
     } while (0)
 
 double eos_p(double Theta) { return kP00 * std::pow(kRd * Theta / kP00, kGamma); }
+// the moist equation of state: water vapour scales rho theta by 1 + (R_v/R_d) q_v
+double eos_p_moist(double Theta, double qv) { return eos_p(Theta * (1.0 + kEpsV * qv)); }
 
 // Newton-Raphson for the hydrostatic base state, level by level upward from
-// the surface: p_k = EOS(rho_k theta_k), p_0 = p_s - g (dz_0/2) rho_0 and
-// p_k - p_{k-1} = -g dzf_k (rho_k + rho_{k-1}) / 2.
-erf_status base_state(int nz, const double *dz, const double *theta0, double ps, double g,
+// the surface: p_k = EOS(rho_k theta_k, qv_k), p_0 = p_s - g (dz_0/2) rho_0
+// (1 + qv_0) and p_k - p_{k-1} = -g dzf_k (rho_k (1 + qv_k) + rho_{k-1}
+// (1 + qv_{k-1})) / 2: rho is the dry density and the vapour adds its weight.
+// Without vapour (qv0 NULL) every factor is exactly 1.
+erf_status base_state(int nz, const double *dz, const double *theta0, const double *qv0, double ps, double g,
                       double *rho0, double *p0, double *pi0)
 {
     if (nz < 1 || !dz || !theta0 || !rho0 || !p0) return ERF_E_ARG;
-    double p_prev = ps, rho_prev = 0.0;
+    double p_prev = ps, rho_prev = 0.0, q_prev = 0.0;
     for (int k = 0; k < nz; ++k) {
-        if (!(theta0[k] > 0.0) || !(dz[k] > 0.0)) return ERF_E_ARG;
+        const double q = qv0 ? qv0[k] : 0.0;
+        if (!(theta0[k] > 0.0) || !(dz[k] > 0.0) || !(q >= 0.0)) return ERF_E_ARG;
         const double h = (k == 0) ? 0.5 * dz[0] : 0.5 * (dz[k - 1] + dz[k]);
-        double rho = (k == 0) ? ps / (kRd * theta0[0]) : rho_prev;
+        double rho = (k == 0) ? ps / (kRd * theta0[0] * (1.0 + kEpsV * q)) : rho_prev;
         for (int it = 0; it < 30; ++it) {
-            const double p = eos_p(rho * theta0[k]);
+            const double p = eos_p_moist(rho * theta0[k], q);
             double f, fp;
             if (k == 0) {
-                f = p - p_prev + g * h * rho;
-                fp = kGamma * p / rho + g * h;
+                f = p - p_prev + g * h * (rho * (1.0 + q));
+                fp = kGamma * p / rho + g * h * (1.0 + q);
             } else {
-                f = p - p_prev + g * h * 0.5 * (rho + rho_prev);
-                fp = kGamma * p / rho + g * h * 0.5;
+                f = p - p_prev + g * h * 0.5 * (rho * (1.0 + q) + rho_prev * (1.0 + q_prev));
+                fp = kGamma * p / rho + g * h * 0.5 * (1.0 + q);
             }
             const double step = f / fp;
             rho = rho - step;
             if (std::fabs(step) <= 1e-15 * rho) break;
         }
         rho0[k] = rho;
-        p0[k] = eos_p(rho * theta0[k]);
+        p0[k] = eos_p_moist(rho * theta0[k], q);
         if (pi0) pi0[k] = std::pow(p0[k] / kP00, kRd / kCp);
         p_prev = p0[k];
         rho_prev = rho;
+        q_prev = q;
     }
     return ERF_OK;
 }
@@ -77,10 +83,10 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 extern "C" {
 
-erf_status erf_base_state_host(int32_t nz, const double *dz, const double *theta0, double p_surface,
-                               double grav, double *rho0, double *p0, double *pi0)
+erf_status erf_base_state_host(int32_t nz, const double *dz, const double *theta0, const double *qv0,
+                               double p_surface, double grav, double *rho0, double *p0, double *pi0)
 {
-    return base_state(nz, dz, theta0, p_surface, grav, rho0, p0, pi0);
+    return base_state(nz, dz, theta0, qv0, p_surface, grav, rho0, p0, pi0);
 }
 
 const char *erf_last_error(const erf_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -109,6 +115,8 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     if (prm->scalar_scheme != ERF_SCALAR_INTERP && prm->scalar_scheme != ERF_SCALAR_WENO5) return ERF_E_ARG;
     if (prm->precision != ERF_FP64 && prm->precision != ERF_FP32_MIXED) return ERF_E_ARG;
     if (nq > 0 && (prm->sgs != ERF_SGS_NONE || prm->alpha_m != 0.0)) return ERF_E_UNSUPPORTED;
+    if (prm->moist != 0 && prm->moist != 1) return ERF_E_ARG;
+    if (prm->moist && nq < 3) return ERF_E_ARG;  // rho q_v, rho q_c, rho q_r
     if (!(prm->dt > 0.0) || !(prm->beta_s >= 0.0 && prm->beta_s <= 1.0)) return ERF_E_ARG;
 
     erf_ctx *c = new (std::nothrow) erf_ctx();
@@ -136,6 +144,7 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     const size_t N = n * es, Wb = w * es, Q = q * es, D = sizeof(double);
     const size_t nzs = (size_t)grid->nz;
     const size_t G = prm->sgs == ERF_SGS_MLP ? N : 0;
+    const size_t M = prm->moist ? N : 0;
     Req reqs[] = {
         {&ws.sa[0], N}, {&ws.sa[1], N}, {&ws.sa[2], N}, {&ws.sa[3], N}, {&ws.sa[4], Wb}, {&ws.sa[5], Q},
         {&ws.sb[0], N}, {&ws.sb[1], N}, {&ws.sb[2], N}, {&ws.sb[3], N}, {&ws.sb[4], Wb}, {&ws.sb[5], Q},
@@ -151,8 +160,10 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
         {(void **)&ws.diag, diag_slots_needed() * D},
         {&ws.sg[0], G}, {&ws.sg[1], G}, {&ws.sg[2], G}, {&ws.sg[3], G}, {&ws.sg[4], G}, {&ws.sg[5], G},
         {&ws.sg[6], G}, {&ws.sg[7], G}, {&ws.sg[8], G},
+        {&ws.qf, M}, {&ws.bm, M}, {&ws.pex, M}, {&ws.rdm, M},
         {(void **)&b.rho0, nzs * D}, {(void **)&b.theta0, nzs * D}, {(void **)&b.Theta0, nzs * D},
         {(void **)&b.p0, nzs * D}, {(void **)&b.pi0, nzs * D}, {(void **)&b.dz, (5 * nzs + 1) * D},
+        {(void **)&b.qv0, nzs * D}, {(void **)&b.rho0t, nzs * D},
     };
     size_t total = 0;
     for (const Req &r : reqs) total += align_up(r.bytes);
@@ -209,28 +220,34 @@ void erf_destroy(erf_ctx *c)
     delete c;
 }
 
-erf_status erf_init_base_state(erf_ctx *c, const double *theta0, double p_surface, double *rho0_out,
-                               double *p0_out, double *pi0_out)
+erf_status erf_init_base_state(erf_ctx *c, const double *theta0, const double *qv0, double p_surface,
+                               double *rho0_out, double *p0_out, double *pi0_out)
 {
     ERF_CHECK_CTX(c);
     if (!theta0) return fail(c, ERF_E_ARG, "theta0 is NULL");
+    if (qv0 && !c->prm.moist) return fail(c, ERF_E_ARG, "qv0 given to a dry context");
     const int nz = c->d.nz;
-    double *h = new double[5 * nz];
+    double *h = new double[7 * nz];
     double *rho0 = h, *p0 = h + nz, *pi0 = h + 2 * nz, *Th0 = h + 3 * nz, *th0 = h + 4 * nz;
-    erf_status s = base_state(nz, c->dz_host, theta0, p_surface, c->prm.grav, rho0, p0, pi0);
+    double *qv = h + 5 * nz, *rho0t = h + 6 * nz;
+    erf_status s = base_state(nz, c->dz_host, theta0, qv0, p_surface, c->prm.grav, rho0, p0, pi0);
     if (s != ERF_OK) {
         delete[] h;
-        return fail(c, s, "base state: invalid theta0 or dz");
+        return fail(c, s, "base state: invalid theta0, qv0 or dz");
     }
     for (int k = 0; k < nz; ++k) {
         th0[k] = theta0[k];
         Th0[k] = rho0[k] * theta0[k];
+        qv[k] = qv0 ? qv0[k] : 0.0;
+        rho0t[k] = rho0[k] * (1.0 + qv[k]);
     }
     hipError_t e = hipMemcpyAsync(c->base.rho0, rho0, nz * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->base.p0, p0, nz * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->base.pi0, pi0, nz * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->base.Theta0, Th0, nz * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->base.theta0, th0, nz * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->base.qv0, qv, nz * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->base.rho0t, rho0t, nz * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         delete[] h;
@@ -256,9 +273,10 @@ erf_status erf_slow_rhs(erf_ctx *c, const erf_state *S, erf_state *R)
     if (!state_ok(S, false, 0) || !state_ok(R, false, 0)) return fail(c, ERF_E_ARG, "null field pointer");
     if (c->prm.sgs == ERF_SGS_MLP && !c->mlp.have_weights)
         return fail(c, ERF_E_STATE, "erf_mlp_set_weights must precede the learned closure");
+    if (c->prm.moist && !S->rhoq) return fail(c, ERF_E_ARG, "a moist context needs S->rhoq");
     const void *s5[5] = {S->rho, S->rhotheta, S->rhou, S->rhov, S->rhow};
     void *r5[5] = {R->rho, R->rhotheta, R->rhou, R->rhov, R->rhow};
-    hipError_t e = launch_slow_rhs(c, s5, r5);
+    hipError_t e = launch_slow_rhs(c, s5, c->prm.moist ? S->rhoq : nullptr, r5);
     return e == hipSuccess ? ERF_OK : hip_fail(c, e, "slow rhs launch");
 }
 
@@ -270,11 +288,13 @@ erf_status erf_acoustic_substeps(erf_ctx *c, const erf_state *Sn, const erf_stat
     if (!state_ok(Sn, false, 0) || !state_ok(St, false, 0) || !state_ok(Rt, false, 0) || !state_ok(Sout, false, 0))
         return fail(c, ERF_E_ARG, "null field pointer");
     if (n_sub < 1 || !(dtau > 0.0)) return fail(c, ERF_E_ARG, "n_sub >= 1 and dtau > 0 required");
+    if (c->prm.moist && !St->rhoq) return fail(c, ERF_E_ARG, "a moist context needs S_t->rhoq");
     const void *sn[5] = {Sn->rho, Sn->rhotheta, Sn->rhou, Sn->rhov, Sn->rhow};
     const void *st[5] = {St->rho, St->rhotheta, St->rhou, St->rhov, St->rhow};
     const void *rt[5] = {Rt->rho, Rt->rhotheta, Rt->rhou, Rt->rhov, Rt->rhow};
     void *so[5] = {Sout->rho, Sout->rhotheta, Sout->rhou, Sout->rhov, Sout->rhow};
-    hipError_t e = launch_acoustic_stage(c, sn, st, rt, n_sub, dtau, so, flux ? flux->rhou : nullptr,
+    hipError_t e = launch_acoustic_stage(c, sn, st, c->prm.moist ? St->rhoq : nullptr, rt, n_sub, dtau, so,
+                                         flux ? flux->rhou : nullptr,
                                          flux ? flux->rhov : nullptr, flux ? flux->rhow : nullptr);
     return e == hipSuccess ? ERF_OK : hip_fail(c, e, "acoustic substeps launch");
 }

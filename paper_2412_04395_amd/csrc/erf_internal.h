@@ -23,6 +23,10 @@ constexpr double kCp = 1004.5;
 constexpr double kCv = kCp - kRd;
 constexpr double kGamma = kCp / (kCp - kRd);
 constexpr double kP00 = 1.0e5;
+// gas constant of water vapour (usual value); water vapour enters the equation
+// of state through the factor 1 + (R_v / R_d) q_v on rho theta (Sec. 2.1)
+constexpr double kRv = 461.6;
+constexpr double kEpsV = kRv / kRd;
 
 // learned closure: 10 -> 64 -> 64 -> 64 -> 9, parameters W1[10][64], b1,
 // W2[64][64], b2, W3[64][64], b3, W4[64][9], b4 (row = input unit)
@@ -224,6 +228,11 @@ struct Workspace {
     void *fu = nullptr, *fv = nullptr, *fw = nullptr;
     // diagnostics partial sums
     double *diag = nullptr;
+    // moist contexts only: 1 + q_v + q_c and the total-density departure
+    // rho (1 + q_v + q_c + q_r) - rho0 (1 + qv0) of the slow right-hand side;
+    // the moist Exner function pi^t and rho_d / rho_m = 1/(1 + q_v + q_c + q_r)
+    // of the stage state (the acoustic coefficients)
+    void *qf = nullptr, *bm = nullptr, *pex = nullptr, *rdm = nullptr;
     // learned closure: rho tau_11, 22, 33, 12, 13, 23 and rho q_1, 2, 3 at
     // centres (allocated for the learned closure only)
     void *sg[9] = {};
@@ -251,6 +260,9 @@ struct MlpState {
 
 struct Base {
     double *rho0 = nullptr, *theta0 = nullptr, *Theta0 = nullptr, *p0 = nullptr, *pi0 = nullptr;
+    // base-state vapour qv0 and total density rho0 (1 + qv0) [nz] (zero and
+    // rho0 for a dry context)
+    double *qv0 = nullptr, *rho0t = nullptr;
     // device: dz [nz], centre heights [nz], 1/dz [nz], the reciprocal
     // centre-to-centre distances across the z-faces, 2/(dz_{k-1} + dz_k) [nz + 1]
     // (zero on the lids), and the squared Smagorinsky length (Cs Delta_k)^2 with
@@ -317,11 +329,13 @@ inline void timing_stop(erf_ctx *c, int id)
 // launchers (host), one translation unit each
 // ---------------------------------------------------------------------------
 // rhs.hip
-hipError_t launch_slow_rhs(erf_ctx *c, const void *const S[5], void *const R[5]);
+// rq: the state's scalars (read by moist contexts only; may be NULL otherwise)
+hipError_t launch_slow_rhs(erf_ctx *c, const void *const S[5], const void *rq, void *const R[5]);
 // primitive fields of S (theta, p', u, v, w) into the workspace only
 hipError_t launch_prep(erf_ctx *c, const void *const S[5]);
 // acoustic.hip
-hipError_t launch_acoustic_stage(erf_ctx *c, const void *const Sn[5], const void *const St[5],
+// rq_t: the stage state's scalars (read by moist contexts only)
+hipError_t launch_acoustic_stage(erf_ctx *c, const void *const Sn[5], const void *const St[5], const void *rq_t,
                                  const void *const Rt[5], int n_sub, double dtau, void *const Sout[5],
                                  void *Fu, void *Fv, void *Fw);
 // scalars.hip

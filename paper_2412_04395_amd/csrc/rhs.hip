@@ -4,7 +4,8 @@
 // state); all arithmetic is double.
 //
 // Passes per call:
-//   k_prep    primitive fields: theta, p' at centres, u, v, w on faces
+//   k_prep    primitive fields: theta, p' at centres, u, v, w on faces (moist:
+//             also 1 + q_v + q_c and the total-density departure)
 //   k_mut     Smagorinsky eddy viscosity at centres (SGS model only)
 //   k_stress  stress tensor of eq. (stresstensor) at its staggered points
 //             (normal stresses at centres, shear stresses on edges) and the
@@ -37,9 +38,12 @@ struct RhsArgs {
     // state
     const T *rho, *rt, *ru, *rv, *rw;
     // base state
-    const double *rho0, *Theta0, *theta0, *p0;
-    // primitives and stresses (workspace)
-    T *th, *pp, *u, *v, *w, *mut;
+    const double *rho0, *Theta0, *theta0, *p0, *qv0;
+    // moist: rho q_v, rho q_c, rho q_r (components 0..2 of the scalars, n apart)
+    const T *rq;
+    // primitives and stresses (workspace); moist: 1 + q_v + q_c and the
+    // total-density departure at centres
+    T *th, *pp, *u, *v, *w, *mut, *qf, *bm;
     T *t11, *t22, *t33, *t12, *t13, *t23, *kap;
     // outputs
     T *Rr, *Rt, *Ru, *Rv, *Rw;
@@ -50,7 +54,7 @@ __device__ __forceinline__ int cidx(const Dims &d, int i, int j, int k) { return
 // ---------------------------------------------------------------------------
 // primitives
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool kMoist>
 __global__ __launch_bounds__(256) void k_prep(RhsArgs<T> a)
 {
     const Dims &d = a.d;
@@ -77,8 +81,24 @@ __global__ __launch_bounds__(256) void k_prep(RhsArgs<T> a)
     st_stream(a.v + c, (T)(V / (0.5 * (rs + r))));
     st_stream(a.w + c, (T)w);
     if (k == d.nz - 1) a.w[c + d.nxy] = 0.0;
-    // p' = p0 ((Theta/Theta0)^gamma - 1) without cancellation (EOS, Sec. 2.1)
-    st_stream(a.pp + c, (T)(p0k * expm1(kGamma * log1p(Tp / T0))));
+    if constexpr (kMoist) {
+        // Moist EOS (Sec. 2.1): water vapour scales rho theta by 1 + (R_v/R_d) q_v.
+        // With X = Theta (1 + eps q_v) and X0 = Theta0 (1 + eps qv0),
+        // p' = p0 ((X/X0)^gamma - 1) and X - X0 = (Theta - Theta0)(1 + eps q_v)
+        // + eps Theta0 (q_v - qv0): the small differences stay apart from the
+        // large values.
+        const double rqv = a.rq[c], rqc = a.rq[c + d.n], rqr = a.rq[c + 2 * d.n], qv0 = a.qv0[k];
+        const double qv = rqv / r, qc = rqc / r;
+        const double x = (Tp * (1.0 + kEpsV * qv) + kEpsV * T0 * (qv - qv0)) / (T0 * (1.0 + kEpsV * qv0));
+        // the momentum equation's 1 + q_v + q_c and the departure of the total
+        // density rho (1 + q_v + q_c + q_r) from the base state's rho0 (1 + qv0)
+        st_stream(a.qf + c, (T)(1.0 + qv + qc));
+        st_stream(a.bm + c, (T)(pert_of(a.rho, c, r0) + (rqv + rqc + rqr) - r0 * qv0));
+        st_stream(a.pp + c, (T)(p0k * expm1(kGamma * log1p(x))));
+    } else {
+        // p' = p0 ((Theta/Theta0)^gamma - 1) without cancellation (EOS, Sec. 2.1)
+        st_stream(a.pp + c, (T)(p0k * expm1(kGamma * log1p(Tp / T0))));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -241,7 +261,9 @@ __device__ __forceinline__ double interp(int order, const double (&q)[7], int o,
 // Three wavefronts per SIMD (the occupancy its registers give anyway): told
 // so, the scheduler keeps each section's gathers in a few large groups
 // rather than trading round trips for registers.
-template <typename T, int OH, int OV, bool kNear, bool kVisc>
+// kMoist: the pressure gradient and the buoyancy are divided by the face mean of
+// 1 + q_v + q_c, and the buoyancy is that of the total density (eq. mom).
+template <typename T, int OH, int OV, bool kNear, bool kVisc, bool kMoist>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_rhs(RhsArgs<T> a)
 {
     const Dims &d = a.d;
@@ -352,7 +374,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         const double fxz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0)) * not_bot;
         const double fxz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1)) * not_top;
         const double adv = (fxx_r - fxx_l) * a.idx + (fxy1 - fxy0) * a.idy + (fxz1 - fxz0) * idz;
-        const double pgf = (a.pp[c] - a.pp[c + ox(2)]) * a.idx;
+        double pgf = (a.pp[c] - a.pp[c + ox(2)]) * a.idx;
+        if constexpr (kMoist) pgf = pgf / (0.5 * ((double)a.qf[c + ox(2)] + (double)a.qf[c]));
         const double rho_f = 0.5 * (full_of(a.rho, c + ox(2), r0k) + rc);
         const double vbar = 0.25 * (Vw + V0 + Vwn + V1);
         double r = -adv - pgf + a.f * (vbar - rho_f * a.Vg);
@@ -381,7 +404,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         const double fyz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0)) * not_bot;
         const double fyz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1)) * not_top;
         const double adv = (fyx1 - fyx0) * a.idx + (fyy_r - fyy_l) * a.idy + (fyz1 - fyz0) * idz;
-        const double pgf = (a.pp[c] - a.pp[c + oy(2)]) * a.idy;
+        double pgf = (a.pp[c] - a.pp[c + oy(2)]) * a.idy;
+        if constexpr (kMoist) pgf = pgf / (0.5 * ((double)a.qf[c + oy(2)] + (double)a.qf[c]));
         const double rho_f = 0.5 * (full_of(a.rho, c + oy(2), r0k) + rc);
         const double ubar = 0.25 * (Us + Use + U0 + U1);
         double r = -adv - pgf - a.f * (ubar - rho_f * a.Ug);
@@ -412,9 +436,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         const double fzz_u = eu * interp<OV>(ov, q, 1, sign_of(eu)), fzz_d = ed * interp<OV>(ov, q, 0, sign_of(ed));
         const double adv = (fzx1 - fzx0) * a.idx + (fzy1 - fzy0) * a.idy + (fzz_u - fzz_d) * idzf;
         const double pgf = (a.pp[c] - a.pp[cm]) * idzf;
-        // buoyancy B = -(rho - rho0) g on the face; heavier air sinks
-        const double buoy = -a.g * 0.5 * (pert_of(a.rho, c, r0k) + pert_of(a.rho, cm, a.rho0[k > 0 ? k - 1 : 0]));
-        double r = -adv - pgf + buoy;
+        double r;
+        if constexpr (kMoist) {
+            // B = -g (rho_m - rho_m0) from the total densities; -grad p' + B over
+            // the face mean of 1 + q_v + q_c
+            const double buoy = -a.g * 0.5 * ((double)a.bm[c] + (double)a.bm[cm]);
+            const double qfm = 0.5 * ((double)a.qf[cm] + (double)a.qf[c]);
+            r = -adv - pgf / qfm + buoy / qfm;
+        } else {
+            // buoyancy B = -(rho - rho0) g on the face; heavier air sinks
+            const double buoy =
+                -a.g * 0.5 * (pert_of(a.rho, c, r0k) + pert_of(a.rho, cm, a.rho0[k > 0 ? k - 1 : 0]));
+            r = -adv - pgf + buoy;
+        }
         if constexpr (kVisc)
             r -= (a.t13[c + ox(4)] - a.t13[c]) * a.idx + (a.t23[c + oy(4)] - a.t23[c]) * a.idy +
                  (a.t33[c] - a.t33[cm]) * idzf;
@@ -432,25 +466,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 
 namespace {
 // orders 2, 3 and 5 in both directions have their own instances; any other
-// combination, and domains narrower than the stencil, take the general one
+// combination, and domains narrower than the stencil, take the general one.
+// Moist dynamics: 3rd order (the moist workload's) and the general instances.
 template <typename T, bool kVisc>
-void launch_rhs(const RhsArgs<T> &a, dim3 grd, dim3 blk, hipStream_t st)
+void launch_rhs(const RhsArgs<T> &a, bool moist, dim3 grd, dim3 blk, hipStream_t st)
 {
     const bool near = a.d.nx >= 3 && a.d.ny >= 3 && a.d.nz >= 3;
-    if (near && a.oh == 5 && a.ov == 5)
-        hipLaunchKernelGGL((k_rhs<T, 5, 5, true, kVisc>), grd, blk, 0, st, a);
+    if (moist) {
+        if (near && a.oh == 3 && a.ov == 3)
+            hipLaunchKernelGGL((k_rhs<T, 3, 3, true, kVisc, true>), grd, blk, 0, st, a);
+        else if (near)
+            hipLaunchKernelGGL((k_rhs<T, 0, 0, true, kVisc, true>), grd, blk, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_rhs<T, 0, 0, false, kVisc, true>), grd, blk, 0, st, a);
+    } else if (near && a.oh == 5 && a.ov == 5)
+        hipLaunchKernelGGL((k_rhs<T, 5, 5, true, kVisc, false>), grd, blk, 0, st, a);
     else if (near && a.oh == 3 && a.ov == 3)
-        hipLaunchKernelGGL((k_rhs<T, 3, 3, true, kVisc>), grd, blk, 0, st, a);
+        hipLaunchKernelGGL((k_rhs<T, 3, 3, true, kVisc, false>), grd, blk, 0, st, a);
     else if (near && a.oh == 2 && a.ov == 2)
-        hipLaunchKernelGGL((k_rhs<T, 2, 2, true, kVisc>), grd, blk, 0, st, a);
+        hipLaunchKernelGGL((k_rhs<T, 2, 2, true, kVisc, false>), grd, blk, 0, st, a);
     else if (near)
-        hipLaunchKernelGGL((k_rhs<T, 0, 0, true, kVisc>), grd, blk, 0, st, a);
+        hipLaunchKernelGGL((k_rhs<T, 0, 0, true, kVisc, false>), grd, blk, 0, st, a);
     else
-        hipLaunchKernelGGL((k_rhs<T, 0, 0, false, kVisc>), grd, blk, 0, st, a);
+        hipLaunchKernelGGL((k_rhs<T, 0, 0, false, kVisc, false>), grd, blk, 0, st, a);
 }
 
 template <typename T>
-hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5], bool prep_only)
+hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], const void *rq, void *const R[5], bool prep_only)
 {
     const erf_params &p = cx->prm;
     Workspace &ws = cx->ws;
@@ -488,6 +530,13 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5], boo
     a.Theta0 = cx->base.Theta0;
     a.theta0 = cx->base.theta0;
     a.p0 = cx->base.p0;
+    a.qv0 = cx->base.qv0;
+    // moist dynamics need the water species; without them (the closure's
+    // feature pass, which uses no pressure) the dry primitives are computed
+    const bool moist = p.moist != 0 && rq != nullptr;
+    a.rq = (const T *)rq;
+    a.qf = (T *)ws.qf;
+    a.bm = (T *)ws.bm;
     a.th = (T *)ws.th;
     a.pp = (T *)ws.pp;
     a.u = (T *)ws.u;
@@ -512,15 +561,20 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5], boo
     a.ntx = (d.nx + tx - 1) / tx;
     a.nty = (d.ny + ty - 1) / ty;
     dim3 blk(tx, ty, 1), grd(a.ntx * a.nty * d.nz), grdw(a.ntx * a.nty * (d.nz + 1));
-    timing_start(cx, K_PREP); hipLaunchKernelGGL(k_prep<T>, grd, blk, 0, cx->stream, a); timing_stop(cx, K_PREP);
+    timing_start(cx, K_PREP);
+    if (moist)
+        hipLaunchKernelGGL((k_prep<T, true>), grd, blk, 0, cx->stream, a);
+    else
+        hipLaunchKernelGGL((k_prep<T, false>), grd, blk, 0, cx->stream, a);
+    timing_stop(cx, K_PREP);
     if (prep_only) return hipGetLastError();
     if (a.sgs) { timing_start(cx, K_MUT); hipLaunchKernelGGL(k_mut<T>, grd, blk, 0, cx->stream, a); timing_stop(cx, K_MUT); }
     if (a.visc) { timing_start(cx, K_STRESS); hipLaunchKernelGGL(k_stress<T>, grdw, blk, 0, cx->stream, a); timing_stop(cx, K_STRESS); }
     timing_start(cx, K_RHS);
     if (a.visc)
-        launch_rhs<T, true>(a, grd, blk, cx->stream);
+        launch_rhs<T, true>(a, moist, grd, blk, cx->stream);
     else
-        launch_rhs<T, false>(a, grd, blk, cx->stream);
+        launch_rhs<T, false>(a, moist, grd, blk, cx->stream);
     timing_stop(cx, K_RHS);
     if (mlp) {
         hipError_t e = hipGetLastError();
@@ -531,17 +585,17 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], void *const R[5], boo
 }
 }  // namespace
 
-hipError_t launch_slow_rhs(erf_ctx *cx, const void *const S[5], void *const R[5])
+hipError_t launch_slow_rhs(erf_ctx *cx, const void *const S[5], const void *rq, void *const R[5])
 {
-    if (cx->prm.precision == ERF_FP32_MIXED) return slow_rhs_t<float>(cx, S, R, false);
-    return slow_rhs_t<double>(cx, S, R, false);
+    if (cx->prm.precision == ERF_FP32_MIXED) return slow_rhs_t<float>(cx, S, rq, R, false);
+    return slow_rhs_t<double>(cx, S, rq, R, false);
 }
 
 hipError_t launch_prep(erf_ctx *cx, const void *const S[5])
 {
     void *const none[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    if (cx->prm.precision == ERF_FP32_MIXED) return slow_rhs_t<float>(cx, S, none, true);
-    return slow_rhs_t<double>(cx, S, none, true);
+    if (cx->prm.precision == ERF_FP32_MIXED) return slow_rhs_t<float>(cx, S, nullptr, none, true);
+    return slow_rhs_t<double>(cx, S, nullptr, none, true);
 }
 
 }  // namespace erfk

@@ -59,7 +59,8 @@ class Params(C.Structure):
                 ("scalar_scheme", C.c_int32), ("n_scalars", C.c_int32), ("sgs", C.c_int32),
                 ("Cs", C.c_double), ("Pr_t", C.c_double), ("nu_m", C.c_double), ("alpha_m", C.c_double),
                 ("f_cor", C.c_double), ("Ug", C.c_double), ("Vg", C.c_double),
-                ("surf_heat_flux", C.c_double), ("grav", C.c_double), ("precision", C.c_int32)]
+                ("surf_heat_flux", C.c_double), ("grav", C.c_double), ("precision", C.c_int32),
+                ("moist", C.c_int32)]
 
 
 class State(C.Structure):
@@ -103,7 +104,7 @@ def load(path: str = LIB_PATH):
             # allocates with, not to a second copy of it
             import torch  # noqa: F401
             L = C.CDLL(path)
-            L.erf_base_state_host.argtypes = [C.c_int32, _DP, _DP, C.c_double, C.c_double, _DP, _DP, _DP]
+            L.erf_base_state_host.argtypes = [C.c_int32, _DP, _DP, _DP, C.c_double, C.c_double, _DP, _DP, _DP]
             L.erf_create.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_void_p, C.POINTER(C.c_void_p)]
             L.erf_destroy.argtypes = [C.c_void_p]
             L.erf_destroy.restype = None
@@ -111,7 +112,7 @@ def load(path: str = LIB_PATH):
             L.erf_last_error.restype = C.c_char_p
             L.erf_workspace_bytes.argtypes = [C.c_void_p]
             L.erf_workspace_bytes.restype = C.c_int64
-            L.erf_init_base_state.argtypes = [C.c_void_p, _DP, C.c_double, _DP, _DP, _DP]
+            L.erf_init_base_state.argtypes = [C.c_void_p, _DP, _DP, C.c_double, _DP, _DP, _DP]
             L.erf_slow_rhs.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(State)]
             L.erf_acoustic_substeps.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(State), C.POINTER(State),
                                                 C.c_int32, C.c_double, C.POINTER(State), C.POINTER(State)]
@@ -162,14 +163,26 @@ def _np_ptr(a: np.ndarray):
     return a.ctypes.data_as(_DP)
 
 
-def base_state_host(dz, theta0, p_surface: float, grav: float = 9.81):
-    """Hydrostatic base state computed by the library's host code (no GPU)."""
+def _opt_ptr(a, n: int):
+    """Pointer to a float64 copy of a length-n array, or NULL for None."""
+    if a is None:
+        return None, None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != (n,):
+        raise ValueError(f"expected {n} values, got shape {a.shape}")
+    return a, _np_ptr(a)
+
+
+def base_state_host(dz, theta0, p_surface: float, grav: float = 9.81, qv0=None):
+    """Hydrostatic base state computed by the library's host code (no GPU);
+    qv0: base-state water vapour mixing ratio [nz] or None (dry)."""
     L = load()
     dz = np.ascontiguousarray(dz, dtype=np.float64)
     th = np.ascontiguousarray(theta0, dtype=np.float64)
     nz = len(dz)
+    qv, qp = _opt_ptr(qv0, nz)
     rho0, p0, pi0 = np.zeros(nz), np.zeros(nz), np.zeros(nz)
-    st = L.erf_base_state_host(nz, _np_ptr(dz), _np_ptr(th), p_surface, grav, _np_ptr(rho0), _np_ptr(p0),
+    st = L.erf_base_state_host(nz, _np_ptr(dz), _np_ptr(th), qp, p_surface, grav, _np_ptr(rho0), _np_ptr(p0),
                                _np_ptr(pi0))
     if st != ERF_OK:
         raise ErfError(st, "erf_base_state_host")
@@ -180,7 +193,7 @@ def params_from_config(cfg) -> Params:
     prec = {"fp64": ERF_FP64, "fp32": ERF_FP32_MIXED}[cfg.prec]
     return Params(cfg.dt, cfg.n_substeps, cfg.beta_s, cfg.beta_d, cfg.adv_order_h, cfg.adv_order_v,
                   cfg.scalar_scheme, cfg.n_scalars, cfg.sgs, cfg.Cs, cfg.Pr_t, cfg.nu_m, cfg.alpha_m,
-                  cfg.f_cor, cfg.Ug, cfg.Vg, cfg.surf_heat_flux, cfg.grav, prec)
+                  cfg.f_cor, cfg.Ug, cfg.Vg, cfg.surf_heat_flux, cfg.grav, prec, int(getattr(cfg, "moist", 0)))
 
 
 def layout(cfg, field: str) -> dict:
@@ -246,14 +259,17 @@ class Solver:
         return int(self.L.erf_workspace_bytes(self.h))
 
     # -- base state ----------------------------------------------------------
-    def init_base_state(self, theta0, p_surface=None):
+    def init_base_state(self, theta0, p_surface=None, qv0=None):
+        """erf_init_base_state; qv0 [nz]: base-state water vapour of a moist
+        context (None: dry)."""
         nz = self.cfg.nz
         th = np.ascontiguousarray(theta0, dtype=np.float64)
+        qv, qp = _opt_ptr(qv0, nz)
         rho0, p0, pi0 = np.zeros(nz), np.zeros(nz), np.zeros(nz)
         ps = self.cfg.p_surface if p_surface is None else p_surface
-        self._check(self.L.erf_init_base_state(self.h, _np_ptr(th), ps, _np_ptr(rho0), _np_ptr(p0), _np_ptr(pi0)),
-                    "erf_init_base_state")
-        self.base = {"rho0": rho0, "theta0": th, "p0": p0, "pi0": pi0}
+        self._check(self.L.erf_init_base_state(self.h, _np_ptr(th), qp, ps, _np_ptr(rho0), _np_ptr(p0),
+                                               _np_ptr(pi0)), "erf_init_base_state")
+        self.base = {"rho0": rho0, "theta0": th, "p0": p0, "pi0": pi0, "qv0": np.zeros(nz) if qv is None else qv}
         return self.base
 
     # -- states ----------------------------------------------------------------

@@ -172,6 +172,11 @@ def qv_sounding(cfg: Config) -> np.ndarray:
     return relative_humidity(z) * 0.622 * es / (p - es)
 
 
+def qv0_of(cfg: Config):
+    """The base-state vapour of a moist workload (qv_sounding), None for a dry one."""
+    return qv_sounding(cfg) if cfg.moist else None
+
+
 # ---------------------------------------------------------------------------
 # initial states.  Perturbations of theta are applied at constant pressure:
 # rho*theta keeps its base value and rho = Theta0 / (theta0 + dtheta).

@@ -53,6 +53,34 @@ def test_host_base_state_equals_oracle_bitwise(kind):
         assert np.array_equal(x, y)
 
 
+def test_host_moist_base_state_equals_oracle_bitwise():
+    # with the deep workload's vapour sounding the Newton steps are again the
+    # oracle's; with qv0 = 0 the moist iteration is the dry one bit for bit
+    cfg = W.deep()
+    th0, qv0 = W.theta_sounding(cfg), W.qv_sounding(cfg)
+    a = erf.base_state_host(cfg.dz, th0, cfg.p_surface, cfg.grav, qv0=qv0)
+    b = oracle.base_state(cfg.dz, th0, cfg.p_surface, cfg.grav, qv0=qv0)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    z = erf.base_state_host(cfg.dz, th0, cfg.p_surface, cfg.grav, qv0=np.zeros(cfg.nz))
+    d = erf.base_state_host(cfg.dz, th0, cfg.p_surface, cfg.grav)
+    for x, y in zip(z, d):
+        assert np.array_equal(x, y)
+    assert not np.array_equal(a[0], d[0])
+    with pytest.raises(erf.ErfError):
+        erf.base_state_host(cfg.dz, th0, cfg.p_surface, cfg.grav, qv0=-qv0)
+
+
+def test_create_checks_the_moist_flag():
+    cfg = W.small(n_scalars=3, moist=1)
+    L = erf.load()
+    st, h = _create(cfg)
+    if st == erf.ERF_OK:  # created (a GPU is present): release it
+        L.erf_destroy(h)
+    assert _create(W.small(n_scalars=2, moist=1))[0] == erf.ERF_E_ARG
+    assert _create(W.small(n_scalars=3, moist=2))[0] == erf.ERF_E_ARG
+
+
 def _create(cfg, **kw):
     L = erf.load()
     dz = np.ascontiguousarray(cfg.dz, dtype=np.float64)

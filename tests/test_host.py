@@ -38,9 +38,12 @@ def test_bench_constants():
     # the deep workload (3 WENO5 tracers, 13 substeps, no SGS): prep 3 x 10,
     # tendencies 3 x 14, stage init 3 x 17 - 13, coefficients 3 x 5, substeps
     # 13 x 20 - 6, finalize 3 x 15, flux sums 13 x 6 + 3 x 3 + 3 x 7, mixing
-    # ratios 3 x 7 and the scalar update 3 x 12
+    # ratios 3 x 7 and the scalar update 3 x 12; moist dynamics add 3 x 14
+    # (species in and two moist fields out of the primitives pass and of the
+    # stage init, each read back by the next kernel)
     deep = W.deep()
-    assert sum(bench._step_values(deep)) == 30 + 42 + 38 + 15 + 254 + 45 + 108 + 21 + 36
+    assert sum(bench._step_values(deep)) == 30 + 42 + 38 + 15 + 254 + 45 + 108 + 21 + 36 + 42
+    assert sum(bench._step_values(deep.replace(moist=0))) == 30 + 42 + 38 + 15 + 254 + 45 + 108 + 21 + 36
 
 
 def test_ensemble_recipe():
