@@ -96,6 +96,23 @@ erf_status erf_mlp_loss_grad(erf_ctx *ctx, const float *x, const float *t, int64
 erf_status erf_mlp_train_step(erf_ctx *ctx, const float *x, const float *t, int64_t n, double lr,
                               double *loss);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid hipMalloc):
+ * erf_mlp_loss_grad without any allocation and without waiting.  The training
+ * activations and partial sums live in one fixed scratch array per GPU (about
+ * 12 MB, held until the process ends) instead of buffers grown on demand; the
+ * kernels and the results are those of erf_mlp_loss_grad, bit for bit.
+ * n <= ERF_MLP_NOALLOC_MAX_BATCH (ERF_E_ARG beyond).  loss_dev (device double,
+ * may be NULL) receives the loss; the call is asynchronous on the context's
+ * stream.  The weights must be set (erf_mlp_set_weights, ERF_E_STATE
+ * otherwise).  Every call on one GPU shares that GPU's scratch: calls that
+ * overlap on one GPU (two streams, two threads, two contexts) race and must be
+ * serialised by the caller; nothing in the scratch needs clearing between
+ * calls. */
+#define ERF_MLP_NOALLOC_MAX_BATCH 8192
+erf_status erf_mlp_loss_grad_noalloc(erf_ctx *ctx, const float *x, const float *t, int64_t n, float *grad,
+                                     double *loss_dev);
+
 /* Number of cells that fell back to Smagorinsky since the closure state was
  * allocated (cumulative over calls).  Synchronous. */
 erf_status erf_mlp_fallback_count(erf_ctx *ctx, int64_t *count);

@@ -356,8 +356,14 @@ hipError_t launch_standardize(erf_ctx *c, const double *X, int64_t n, int ncol, 
                               const double *sd, float *out);
 size_t train_floats(int64_t cap);
 size_t train_partial_floats();
+// split-K partial space with which a batch of n samples takes the same splits
+// as with train_partial_floats() (results identical to the last bit)
+size_t train_partial_floats_for(int64_t n);
 size_t train_partial_doubles(int64_t cap);
-hipError_t launch_loss_grad(erf_ctx *c, const float *X, const float *T, int64_t n, float *G, double *loss_dev);
+// training buffers: tbuf train_floats(n), part pf floats (split-K partials),
+// dpart train_partial_doubles(n); every value is written before it is read
+hipError_t launch_loss_grad(erf_ctx *c, const float *X, const float *T, int64_t n, float *G, double *loss_dev,
+                            float *tbuf, float *part, size_t pf, double *dpart);
 hipError_t launch_adam(erf_ctx *c, double lr, int64_t step);
 // diag.hip
 size_t diag_slots_needed();

@@ -1138,17 +1138,21 @@ size_t train_floats(int64_t cap)
     return (size_t)cap * (5 * 64 + 2 * 9);
 }
 size_t train_partial_floats() { return (size_t)kMaxSplits * 64 * 64; }
+size_t train_partial_floats_for(int64_t n)
+{
+    // the split-K partials of the longest reduction (K = n samples): one 64 x 64
+    // tile per chunk of 256, the count gemm() takes when space allows
+    return (size_t)((n + 255) / 256) * 64 * 64;
+}
 size_t train_partial_doubles(int64_t cap) { return (size_t)((cap + kStatRows - 1) / kStatRows + 1) * 64 + (size_t)((cap * 9 + 255) / 256 + 1); }
 
-hipError_t launch_loss_grad(erf_ctx *cx, const float *X, const float *Tt, int64_t n, float *G, double *loss_dev)
+hipError_t launch_loss_grad(erf_ctx *cx, const float *X, const float *Tt, int64_t n, float *G, double *loss_dev,
+                            float *tbuf, float *part, size_t pf, double *dpart)
 {
     MlpState &m = cx->mlp;
     const float *P = m.master;
-    float *H1 = m.tbuf, *H2 = H1 + n * 64, *H3 = H2 + n * 64, *Da = H3 + n * 64, *Db = Da + n * 64;
+    float *H1 = tbuf, *H2 = H1 + n * 64, *H3 = H2 + n * 64, *Da = H3 + n * 64, *Db = Da + n * 64;
     float *Y = Db + n * 64, *dY = Y + n * 9;
-    float *part = m.tpart;
-    const size_t pf = train_partial_floats();
-    double *dpart = m.tdpart;
     const int N = (int)n;
     hipError_t e;
     // forward

@@ -2,6 +2,7 @@
 // closure state allocation, weights, training and data-preparation calls.
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/erf_mlp.h"
@@ -32,6 +33,7 @@ erf_status hip_fail(erf_ctx *c, hipError_t e, const char *where)
     } while (0)
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t al_c(size_t x) { return (x + 255) & ~size_t(255); }
 
 // one allocation for parameters, Adam moments, gradient, packed operands,
 // biases, statistics, fallback counter and loss slot
@@ -93,6 +95,60 @@ erf_status ensure_train(erf_ctx *c, int64_t n)
 }
 
 bool state5(const erf_state *S) { return S && S->rho && S->rhotheta && S->rhou && S->rhov && S->rhow; }
+
+// ---------------------------------------------------------------------------
+// fixed training scratch of erf_mlp_loss_grad_noalloc
+// ---------------------------------------------------------------------------
+// Activations (train_floats), split-K partials (train_partial_floats_for) and
+// FP64 partial sums (train_partial_doubles) of a batch of at most
+// ERF_MLP_NOALLOC_MAX_BATCH samples, each region 256-byte aligned.  Bounds
+// evaluated here for the maximum batch (checked against the library's sizing
+// functions at the first call): 338 floats per sample; one 64 x 64 tile per
+// 256 samples; (n / 1024 + 2) x 64 + n x 9 / 256 + 2 doubles.
+constexpr int64_t kNaMax = ERF_MLP_NOALLOC_MAX_BATCH;
+constexpr size_t kNaAct = (size_t)kNaMax * 338 * sizeof(float);
+constexpr size_t kNaPart = (size_t)((kNaMax + 255) / 256) * 64 * 64 * sizeof(float);
+constexpr size_t kNaDbl = ((size_t)(kNaMax / 1024 + 2) * 64 + (size_t)(kNaMax * 9 / 256 + 2)) * sizeof(double);
+constexpr size_t kNaBytes = al_c(kNaAct) + al_c(kNaPart) + al_c(kNaDbl);
+}  // namespace
+
+// One copy per GPU, held from the library's load until the process ends.  In
+// host code `scratch` is a host-side stand-in: its device address comes from
+// hipGetSymbolAddress, per device (na_scratch).
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+constexpr int kNaMaxDevices = 64;
+std::mutex na_mutex;
+void *na_ptr[kNaMaxDevices] = {};
+
+// The device address of `scratch` on the context's GPU, looked up once per
+// device with that device current.
+erf_status na_scratch(erf_ctx *c, char **out)
+{
+    const int dev = c->device;
+    if (dev < 0 || dev >= kNaMaxDevices) return fail(c, ERF_E_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(na_mutex);
+    if (!na_ptr[dev]) {
+        if (train_floats(kNaMax) * sizeof(float) > kNaAct || train_partial_floats_for(kNaMax) * sizeof(float) > kNaPart ||
+            train_partial_doubles(kNaMax) * sizeof(double) > kNaDbl)
+            return fail(c, ERF_E_UNSUPPORTED, "training scratch smaller than the maximum batch needs");
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+        void *p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return hip_fail(c, e != hipSuccess ? e : hipErrorInvalidSymbol, "locating the training scratch");
+        }
+        na_ptr[dev] = p;
+    }
+    *out = (char *)na_ptr[dev];
+    return ERF_OK;
+}
 
 }  // namespace
 
@@ -218,10 +274,32 @@ erf_status erf_mlp_loss_grad(erf_ctx *c, const float *x, const float *t, int64_t
     if (n > ((int64_t)1 << 31) / 64) return fail(c, ERF_E_ARG, "batch too large");
     erf_status s = ensure_train(c, n);
     if (s != ERF_OK) return s;
-    hipError_t e = launch_loss_grad(c, x, t, n, grad, c->mlp.loss);
+    MlpState &m = c->mlp;
+    hipError_t e = launch_loss_grad(c, x, t, n, grad, m.loss, m.tbuf, m.tpart, train_partial_floats(), m.tdpart);
     if (e == hipSuccess && loss) e = hipMemcpyAsync(loss, c->mlp.loss, sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess && loss) e = hipStreamSynchronize(c->stream);
     return e == hipSuccess ? ERF_OK : hip_fail(c, e, "closure gradient");
+}
+
+erf_status erf_mlp_loss_grad_noalloc(erf_ctx *c, const float *x, const float *t, int64_t n, float *grad,
+                                     double *loss_dev)
+{
+    CHECK_CTX(c);
+    if (!c->mlp.have_weights) return fail(c, ERF_E_STATE, "no closure weights set");
+    if (!x || !t || !grad || n < 1) return fail(c, ERF_E_ARG, "x, t, grad and n >= 1 required");
+    if (n > kNaMax) return fail(c, ERF_E_ARG, "batch larger than ERF_MLP_NOALLOC_MAX_BATCH");
+    char *p = nullptr;
+    erf_status s = na_scratch(c, &p);
+    if (s != ERF_OK) return s;
+    // the same kernels as erf_mlp_loss_grad on slices of the fixed scratch;
+    // nothing in it has to start at zero (every partial is written before it
+    // is read)
+    float *tbuf = (float *)p;
+    float *part = (float *)(p + al_c(kNaAct));
+    double *dpart = (double *)(p + al_c(kNaAct) + al_c(kNaPart));
+    hipError_t e = launch_loss_grad(c, x, t, n, grad, loss_dev ? loss_dev : c->mlp.loss, tbuf, part,
+                                    train_partial_floats_for(n), dpart);
+    return e == hipSuccess ? ERF_OK : hip_fail(c, e, "closure gradient (fixed scratch)");
 }
 
 erf_status erf_mlp_train_step(erf_ctx *c, const float *x, const float *t, int64_t n, double lr, double *loss)

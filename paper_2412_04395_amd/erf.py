@@ -28,6 +28,7 @@ ERF_FP64, ERF_FP32_MIXED = 0, 1
 
 ERF_SGS_NONE, ERF_SGS_SMAGORINSKY, ERF_SGS_MLP = 0, 1, 2
 MLP_NPARAMS, MLP_NNORM = 9609, 38
+MLP_NOALLOC_MAX_BATCH = 8192  # ERF_MLP_NOALLOC_MAX_BATCH of include/erf_mlp.h
 
 # every symbol include/erf.h, include/erf_mlp.h and include/erf_ensemble.h declare
 EXPORTS = ("erf_base_state_host", "erf_create", "erf_destroy", "erf_last_error", "erf_workspace_bytes",
@@ -35,7 +36,7 @@ EXPORTS = ("erf_base_state_host", "erf_create", "erf_destroy", "erf_last_error",
            "erf_rk3_step", "erf_diagnostics", "erf_timing_begin", "erf_timing_end", "erf_layout", "erf_autotune",
            "erf_mlp_set_weights", "erf_mlp_get_weights", "erf_mlp_forward", "erf_mlp_features",
            "erf_box_filter", "erf_mlp_fit_norm", "erf_mlp_standardize", "erf_mlp_loss_grad",
-           "erf_mlp_train_step", "erf_mlp_fallback_count",
+           "erf_mlp_train_step", "erf_mlp_loss_grad_noalloc", "erf_mlp_fallback_count",
            "erf_ensemble_create", "erf_ensemble_destroy", "erf_ensemble_last_error", "erf_ensemble_member",
            "erf_ensemble_set_branches", "erf_ensemble_branches", "erf_ensemble_rk3_step", "erf_ensemble_autotune")
 _NOT_STATUS = ("erf_destroy", "erf_last_error", "erf_workspace_bytes", "erf_ensemble_destroy",
@@ -135,6 +136,8 @@ def load(path: str = LIB_PATH):
             L.erf_mlp_standardize.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                               C.c_void_p]
             L.erf_mlp_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, _DP]
+            L.erf_mlp_loss_grad_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                                    C.c_void_p]
             L.erf_mlp_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, _DP]
             L.erf_mlp_fallback_count.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
             L.erf_ensemble_create.argtypes = [C.c_int32, C.POINTER(Grid), C.POINTER(Params), C.c_void_p,
@@ -465,6 +468,21 @@ class Solver:
                                              self._dev(t, torch.float32, (n, 9), "t"), n,
                                              C.c_void_p(g.data_ptr()), C.byref(loss)), "erf_mlp_loss_grad")
         return loss.value, g
+
+    def mlp_loss_grad_noalloc(self, x, t, grad=None, loss=None):
+        """erf_mlp_loss_grad_noalloc: gradient into grad (float32[9609]) and the
+        loss into loss (float64[1]) on the device, with nothing allocated by
+        the library and nothing waited for."""
+        torch = self.torch
+        n = x.shape[0]
+        g = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=self.device) if grad is None else grad
+        self._check(self.L.erf_mlp_loss_grad_noalloc(self.h, self._dev(x, torch.float32, (n, 10), "x"),
+                                                     self._dev(t, torch.float32, (n, 9), "t"), n,
+                                                     self._dev(g, torch.float32, (MLP_NPARAMS,), "grad"),
+                                                     None if loss is None else
+                                                     self._dev(loss, torch.float64, (1,), "loss")),
+                    "erf_mlp_loss_grad_noalloc")
+        return g
 
     def mlp_train_step(self, x, t, lr: float, want_loss: bool = True):
         torch = self.torch

@@ -53,6 +53,13 @@ def test_host_base_state_equals_oracle_bitwise(kind):
         assert np.array_equal(x, y)
 
 
+def test_noalloc_batch_limit_matches_the_header():
+    import re
+    text = open(os.path.join(ROOT, "include", "erf_mlp.h")).read()
+    m = re.search(r"#define ERF_MLP_NOALLOC_MAX_BATCH (\d+)", text)
+    assert m and int(m.group(1)) == erf.MLP_NOALLOC_MAX_BATCH
+
+
 def test_host_moist_base_state_equals_oracle_bitwise():
     # with the deep workload's vapour sounding the Newton steps are again the
     # oracle's; with qv0 = 0 the moist iteration is the dry one bit for bit
