@@ -1,7 +1,10 @@
 // acoustic.hip -- one RK stage of semi-implicit acoustic substepping (App. C of
 // the ERF paper, Sec. 3.1).  Bulk fields are stored as T (double, or float with
-// rho and rho*theta as perturbations about the base state); all arithmetic,
-// the tridiagonal factors and the Thomas sweeps are double.
+// rho and rho*theta as perturbations about the base state).  The explicit
+// horizontal part of a substep (U'', V'' and the horizontal divergences of
+// Theta'' and rho'') is computed in T; the frozen coefficients, the right-hand
+// sides of the vertical W'' rows, their factors, the Thomas sweeps and the
+// implicit finish of Theta'' and rho'' are always double.
 //
 // Kernels of one stage:
 //   k_stage_init  S'' = S^n - S^t, frozen theta^t and Exner pi^t, zero sums
@@ -249,13 +252,15 @@ __device__ __forceinline__ void substep_explicit(
     double (&lo)[kLevels <= 8 ? kLevels : 1], double (&up)[kLevels <= 8 ? kLevels : 1], double &e_first,
     double &f_first)
 {
+    using R = T;  // arithmetic type of the explicit horizontal part
     // an S'' value on entry
-    auto in = [&](const T *__restrict__ p, int i) -> double {
+    auto in = [&](const T *__restrict__ p, int i) -> R {
         if constexpr (kZero)
-            return 0.0;
+            return R(0);
         else
-            return (double)p[i];
+            return p[i];
     };
+    const R dtR = (R)dt, gRdR = (R)gRd, idxR = (R)idx, idyR = (R)idy, bdR = (R)bd, h = R(0.5);
     if (act && k0 < nz) {
         double e_prev = 0.0, f_prev = 0.0, tf_prev = 0.0;
         double pi_below = (k0 > 0) ? pit[col + (k0 - 1) * nxy] : 0.0;
@@ -274,23 +279,20 @@ __device__ __forceinline__ void substep_explicit(
                     sv0 = sv[c];
                 }
                 // forward-predicted Theta'' at the centre and its four neighbours
-                const double Tc = in(T2cur, c);
-                const double ttc = Tc + bd * (Tc - in(T2prv, c));
-                const double Tw = in(T2cur, c + o_w), Te = in(T2cur, c + o_e), Ts = in(T2cur, c + o_s),
-                             Tn = in(T2cur, c + o_n);
-                const double ttw = Tw + bd * (Tw - in(T2prv, c + o_w));
-                const double tte = Te + bd * (Te - in(T2prv, c + o_e));
-                const double tts = Ts + bd * (Ts - in(T2prv, c + o_s));
-                const double ttn = Tn + bd * (Tn - in(T2prv, c + o_n));
-                const double pc = pit[c], pw = pit[c + o_w], pe = pit[c + o_e], ps = pit[c + o_s],
-                             pn = pit[c + o_n];
+                const R Tc = in(T2cur, c);
+                const R ttc = Tc + bdR * (Tc - in(T2prv, c));
+                const R Tw = in(T2cur, c + o_w), Te = in(T2cur, c + o_e), Ts = in(T2cur, c + o_s),
+                        Tn = in(T2cur, c + o_n);
+                const R ttw = Tw + bdR * (Tw - in(T2prv, c + o_w));
+                const R tte = Te + bdR * (Te - in(T2prv, c + o_e));
+                const R tts = Ts + bdR * (Ts - in(T2prv, c + o_s));
+                const R ttn = Tn + bdR * (Tn - in(T2prv, c + o_n));
+                const R pc = pit[c], pw = pit[c + o_w], pe = pit[c + o_e], ps = pit[c + o_s], pn = pit[c + o_n];
                 // U'' on this column's x-face and on the next one, V'' likewise
-                const double Uw = in(u2in, c) + dt * (-gRd * (0.5 * (pw + pc)) * (ttc - ttw) * idx + R_u[c]);
-                const double Ue =
-                    in(u2in, c + o_e) + dt * (-gRd * (0.5 * (pc + pe)) * (tte - ttc) * idx + R_u[c + o_e]);
-                const double Vs = in(v2in, c) + dt * (-gRd * (0.5 * (ps + pc)) * (ttc - tts) * idy + R_v[c]);
-                const double Vn =
-                    in(v2in, c + o_n) + dt * (-gRd * (0.5 * (pc + pn)) * (ttn - ttc) * idy + R_v[c + o_n]);
+                const R Uw = in(u2in, c) + dtR * (-gRdR * (h * (pw + pc)) * (ttc - ttw) * idxR + R_u[c]);
+                const R Ue = in(u2in, c + o_e) + dtR * (-gRdR * (h * (pc + pe)) * (tte - ttc) * idxR + R_u[c + o_e]);
+                const R Vs = in(v2in, c) + dtR * (-gRdR * (h * (ps + pc)) * (ttc - tts) * idyR + R_v[c]);
+                const R Vn = in(v2in, c + o_n) + dtR * (-gRdR * (h * (pc + pn)) * (ttn - ttc) * idyR + R_v[c + o_n]);
                 if constexpr (kLast) {
                     // the stage's last substep writes S^t + S'' (u2out, v2out
                     // point to the stage-end momenta; S'' rounded as if stored)
@@ -300,12 +302,14 @@ __device__ __forceinline__ void substep_explicit(
                     st_stream(u2out + c, (T)Uw);
                     st_stream(v2out + c, (T)Vs);
                 }
-                // explicit parts of Theta'' and rho''
-                const double thc = tht[c];
-                const double thx0 = 0.5 * (tht[c + o_w] + thc), thx1 = 0.5 * (thc + tht[c + o_e]);
-                const double thy0 = 0.5 * (tht[c + o_s] + thc), thy1 = 0.5 * (thc + tht[c + o_n]);
-                const double hdiv_t = (Ue * thx1 - Uw * thx0) * idx + (Vn * thy1 - Vs * thy0) * idy;
-                const double hdiv_r = (Ue - Uw) * idx + (Vn - Vs) * idy;
+                // explicit parts of Theta'' and rho'': horizontal divergences in
+                // the arithmetic type, the vertical terms in double
+                const R thcR = tht[c];
+                const R thx0 = h * ((R)tht[c + o_w] + thcR), thx1 = h * (thcR + (R)tht[c + o_e]);
+                const R thy0 = h * ((R)tht[c + o_s] + thcR), thy1 = h * (thcR + (R)tht[c + o_n]);
+                const double hdiv_t = (Ue * thx1 - Uw * thx0) * idxR + (Vn * thy1 - Vs * thy0) * idyR;
+                const double hdiv_r = (Ue - Uw) * idxR + (Vn - Vs) * idyR;
+                const double thc = thcR;
                 // the level above, clamped at the lid (its value unused there)
                 const double th_above = tht[c + (k < nz - 1 ? nxy : 0)];
                 const double tfk = (k == 0) ? 0.0 : 0.5 * (th_below + thc);

@@ -150,7 +150,11 @@ inline int tile_width(int nx, int ny, int lanes)
     return best;
 }
 
-__device__ __forceinline__ double sign_of(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+template <typename R>
+__device__ __forceinline__ R sign_of(R x)
+{
+    return x > R(0) ? R(1) : (x < R(0) ? R(-1) : R(0));
+}
 
 // Storage conventions.  FP64 storage holds full rho and rho*theta; FP32
 // storage holds their perturbations about the base state.  These return the
@@ -175,21 +179,41 @@ __device__ __forceinline__ double pert_of(const T *f, int c, double base)
         return f[c] - base;
 }
 
+// The same in the storage type T itself (the arithmetic type of the FP32
+// path, double for the FP64 path): the base value rounded to T.
+template <typename T>
+__device__ __forceinline__ T full_in(const T *f, int c, double base)
+{
+    if constexpr (kPert<T>)
+        return (T)base + f[c];
+    else
+        return f[c];
+}
+template <typename T>
+__device__ __forceinline__ T pert_in(const T *f, int c, double base)
+{
+    if constexpr (kPert<T>)
+        return f[c];
+    else
+        return f[c] - base;
+}
+
 // Interpolated face value q_{m-1/2} (Sec. 3.6) from q[0..5] = q_{m-3..m+2};
 // s is the sign of the normal momentum at the face (-1, 0 or 1, so that
-// s * (1/12) and s * (1/60) equal s / 12 and s / 60 exactly).
-__device__ __forceinline__ double face_interp(int order, double qm3, double qm2, double qm1,
-                                              double q0, double qp1, double qp2, double s)
+// s * (1/12) and s * (1/60) equal s / 12 and s / 60 exactly).  R is the
+// arithmetic type (the coefficients rounded to it).
+template <typename R>
+__device__ __forceinline__ R face_interp(int order, R qm3, R qm2, R qm1, R q0, R qp1, R qp2, R s)
 {
-    if (order == 2) return 0.5 * (q0 + qm1);
+    if (order == 2) return R(0.5) * (q0 + qm1);
     if (order == 3 || order == 4) {
-        double c4 = 7.0 / 12.0 * (q0 + qm1) - 1.0 / 12.0 * (qp1 + qm2);
+        R c4 = R(7.0 / 12.0) * (q0 + qm1) - R(1.0 / 12.0) * (qp1 + qm2);
         if (order == 4) return c4;
-        return c4 + s * (1.0 / 12.0) * ((qp1 - qm2) - 3.0 * (q0 - qm1));
+        return c4 + s * R(1.0 / 12.0) * ((qp1 - qm2) - R(3) * (q0 - qm1));
     }
-    double c6 = 37.0 / 60.0 * (q0 + qm1) - 2.0 / 15.0 * (qp1 + qm2) + 1.0 / 60.0 * (qp2 + qm3);
+    R c6 = R(37.0 / 60.0) * (q0 + qm1) - R(2.0 / 15.0) * (qp1 + qm2) + R(1.0 / 60.0) * (qp2 + qm3);
     if (order == 6) return c6;
-    return c6 - s * (1.0 / 60.0) * ((qp2 - qm3) - 5.0 * (qp1 - qm2) + 10.0 * (q0 - qm1));
+    return c6 - s * R(1.0 / 60.0) * ((qp2 - qm3) - R(5) * (qp1 - qm2) + R(10) * (q0 - qm1));
 }
 
 // ---------------------------------------------------------------------------

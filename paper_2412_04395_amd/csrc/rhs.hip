@@ -1,7 +1,8 @@
 // rhs.hip -- slow right-hand side f(S) of the compressible equations
 // (eqs. con, mom, theta of Sec. 2.1) on the C-grid.  Fields are stored as T
 // (double, or float holding perturbations of rho and rho*theta about the base
-// state); all arithmetic is double.
+// state).  Arithmetic is in T as well: FP64 for the FP64 path, FP32 for the
+// FP32 path (base-state values enter as small level differences).
 //
 // Passes per call:
 //   k_prep    primitive fields: theta, p' at centres, u, v, w on faces (moist:
@@ -19,8 +20,8 @@
 // cells wide), so the stencil loads are base + offset and can all be issued
 // ahead of the arithmetic.  The interpolation order is a template parameter for
 // the orders the workloads use.
-// In the FP32 storage theta is kept as theta - theta0(z) and the base value is
-// added back per level before interpolating.
+// In the FP32 storage theta is kept as theta - theta0(z); the FP32 flux of
+// rho theta is U theta0(k) plus U times the interpolant of theta - theta0(k).
 #include "erf_internal.h"
 
 namespace erfk {
@@ -54,9 +55,13 @@ __device__ __forceinline__ int cidx(const Dims &d, int i, int j, int k) { return
 // ---------------------------------------------------------------------------
 // primitives
 // ---------------------------------------------------------------------------
+// Arithmetic type R = T: double for the FP64 path, float for the FP32 path
+// (bulk stencil arithmetic in FP32; base-state values enter rounded to float,
+// and only as the small differences between levels where they are subtracted).
 template <typename T, bool kMoist>
 __global__ __launch_bounds__(256) void k_prep(RhsArgs<T> a)
 {
+    using R = T;
     const Dims &d = a.d;
     const TileIdx t = tile_cell(a.ntx, a.nty);
     const int i = t.i, j = t.j, k = t.k;
@@ -66,19 +71,24 @@ __global__ __launch_bounds__(256) void k_prep(RhsArgs<T> a)
     const int cw = cidx(d, i == 0 ? d.nx - 1 : i - 1, j, k), cs = cidx(d, i, j == 0 ? d.ny - 1 : j - 1, k);
     const int kb = k > 0 ? k - 1 : 0, cb = c - (k - kb) * d.nxy;
     const double r0 = a.rho0[k], T0 = a.Theta0[k], r0b = a.rho0[kb], p0k = a.p0[k];
-    const double r = full_of(a.rho, c, r0), rw_ = full_of(a.rho, cw, r0), rs = full_of(a.rho, cs, r0);
-    const double rb = full_of(a.rho, cb, r0b);
-    const double Tf = full_of(a.rt, c, T0), Tp = pert_of(a.rt, c, T0);
-    const double U = a.ru[c], V = a.rv[c], Wc = a.rw[c];
-    const double th = Tf / r;
-    const double w = (k == 0) ? 0.0 : Wc / (0.5 * (rb + r));
+    const R r = full_in(a.rho, c, r0), rw_ = full_in(a.rho, cw, r0), rs = full_in(a.rho, cs, r0);
+    const R rb = full_in(a.rho, cb, r0b);
+    const R Tp = pert_in(a.rt, c, T0);
+    const R U = a.ru[c], V = a.rv[c], Wc = a.rw[c];
+    const R w = (k == 0) ? R(0) : Wc / (R(0.5) * (rb + r));
     // outputs are read by later launches only: streaming stores, so that no
     // dirty lines are left in the caches for the next kernel to write back.
     // The divisions are stored before the EOS, whose library calls branch:
     // a store keeps every load of the thread ahead of it.
-    st_stream(a.th + c, kPert<T> ? (T)(th - a.theta0[k]) : (T)th);
-    st_stream(a.u + c, (T)(U / (0.5 * (rw_ + r))));
-    st_stream(a.v + c, (T)(V / (0.5 * (rs + r))));
+    if constexpr (kPert<T>) {
+        // theta - theta0 = (Theta' - theta0 rho') / rho, formed from the two
+        // perturbations (no cancellation against the base values in float)
+        st_stream(a.th + c, (T)((Tp - (R)a.theta0[k] * a.rho[c]) / r));
+    } else {
+        st_stream(a.th + c, (T)(full_of(a.rt, c, T0) / r));
+    }
+    st_stream(a.u + c, (T)(U / (R(0.5) * (rw_ + r))));
+    st_stream(a.v + c, (T)(V / (R(0.5) * (rs + r))));
     st_stream(a.w + c, (T)w);
     if (k == d.nz - 1) a.w[c + d.nxy] = 0.0;
     if constexpr (kMoist) {
@@ -87,39 +97,24 @@ __global__ __launch_bounds__(256) void k_prep(RhsArgs<T> a)
         // p' = p0 ((X/X0)^gamma - 1) and X - X0 = (Theta - Theta0)(1 + eps q_v)
         // + eps Theta0 (q_v - qv0): the small differences stay apart from the
         // large values.
-        const double rqv = a.rq[c], rqc = a.rq[c + d.n], rqr = a.rq[c + 2 * d.n], qv0 = a.qv0[k];
-        const double qv = rqv / r, qc = rqc / r;
-        const double x = (Tp * (1.0 + kEpsV * qv) + kEpsV * T0 * (qv - qv0)) / (T0 * (1.0 + kEpsV * qv0));
+        const R rqv = a.rq[c], rqc = a.rq[c + d.n], rqr = a.rq[c + 2 * d.n];
+        const R qv0 = (R)a.qv0[k], eps = (R)kEpsV, T0r = (R)T0;
+        const R qv = rqv / r, qc = rqc / r;
+        const R x = (Tp * (R(1) + eps * qv) + eps * T0r * (qv - qv0)) / (T0r * (R(1) + eps * qv0));
         // the momentum equation's 1 + q_v + q_c and the departure of the total
         // density rho (1 + q_v + q_c + q_r) from the base state's rho0 (1 + qv0)
-        st_stream(a.qf + c, (T)(1.0 + qv + qc));
-        st_stream(a.bm + c, (T)(pert_of(a.rho, c, r0) + (rqv + rqc + rqr) - r0 * qv0));
-        st_stream(a.pp + c, (T)(p0k * expm1(kGamma * log1p(x))));
+        st_stream(a.qf + c, (T)(R(1) + qv + qc));
+        st_stream(a.bm + c, (T)(pert_in(a.rho, c, r0) + (rqv + rqc + rqr) - (R)r0 * qv0));
+        st_stream(a.pp + c, (T)((R)p0k * expm1(R(kGamma) * log1p(x))));
     } else {
         // p' = p0 ((Theta/Theta0)^gamma - 1) without cancellation (EOS, Sec. 2.1)
-        st_stream(a.pp + c, (T)(p0k * expm1(kGamma * log1p(Tp / T0))));
+        st_stream(a.pp + c, (T)((R)p0k * expm1(R(kGamma) * log1p(Tp / (R)T0))));
     }
 }
 
 // ---------------------------------------------------------------------------
 // strain rates and stresses (Sec. 2.3)
 // ---------------------------------------------------------------------------
-// Neighbour offsets of one thread: x and y wrap periodically.
-struct Nbr {
-    int c, im, ip, jm, jp;  // c and the signed offsets of i-1, i+1, j-1, j+1
-};
-
-__device__ __forceinline__ Nbr nbr(const Dims &d, int i, int j, int k)
-{
-    Nbr n;
-    n.c = cidx(d, i, j, k);
-    n.im = wrap_idx(i - 1, d.nx) - i;
-    n.ip = wrap_idx(i + 1, d.nx) - i;
-    n.jm = (wrap_idx(j - 1, d.ny) - j) * d.nx;
-    n.jp = (wrap_idx(j + 1, d.ny) - j) * d.nx;
-    return n;
-}
-
 // Smagorinsky eddy viscosity mu_t = rho (Cs Delta)^2 sqrt(2 S:S), Delta = (dx dy dz)^(1/3);
 // off-diagonal strains are averaged from the four edges around the centre.
 // Branch-free: neighbours by selects, vertical neighbours clamped; the lid
@@ -128,6 +123,7 @@ __device__ __forceinline__ Nbr nbr(const Dims &d, int i, int j, int k)
 template <typename T>
 __global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
 {
+    using R = T;
     const Dims &d = a.d;
     const TileIdx t = tile_cell(a.ntx, a.nty);
     const int i = t.i, j = t.j, k = t.k;
@@ -136,36 +132,32 @@ __global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
     const int im = i == 0 ? nx - 1 : i - 1, ip = i == nx - 1 ? 0 : i + 1;
     const int rj = j * nx, rjm = (j == 0 ? ny - 1 : j - 1) * nx, rjp = (j == ny - 1 ? 0 : j + 1) * nx;
     const int lk = k * P, lkm = (k > 0 ? k - 1 : 0) * P, lkp = (k < nz - 1 ? k + 1 : nz - 1) * P, lk1 = (k + 1) * P;
-    auto U = [&](int ii, int r, int l) { return (double)a.u[l + r + ii]; };
-    auto V = [&](int ii, int r, int l) { return (double)a.v[l + r + ii]; };
-    auto Wf = [&](int ii, int r, int l) { return (double)a.w[l + r + ii]; };
-    const double gz0 = a.idzf[k], gz1 = a.idzf[k + 1];
-    const double u_c = U(i, rj, lk), u_e = U(ip, rj, lk), u_s = U(i, rjm, lk), u_se = U(ip, rjm, lk);
-    const double u_n = U(i, rjp, lk), u_ne = U(ip, rjp, lk);
-    const double u_b = U(i, rj, lkm), u_be = U(ip, rj, lkm), u_t = U(i, rj, lkp), u_te = U(ip, rj, lkp);
-    const double v_c = V(i, rj, lk), v_n = V(i, rjp, lk), v_w = V(im, rj, lk), v_e = V(ip, rj, lk);
-    const double v_nw = V(im, rjp, lk), v_ne = V(ip, rjp, lk);
-    const double v_b = V(i, rj, lkm), v_bn = V(i, rjp, lkm), v_t = V(i, rj, lkp), v_tn = V(i, rjp, lkp);
-    const double w_c = Wf(i, rj, lk), w_u = Wf(i, rj, lk1), w_w = Wf(im, rj, lk), w_e = Wf(ip, rj, lk);
-    const double w_wu = Wf(im, rj, lk1), w_eu = Wf(ip, rj, lk1), w_s = Wf(i, rjm, lk), w_n = Wf(i, rjp, lk);
-    const double w_su = Wf(i, rjm, lk1), w_nu = Wf(i, rjp, lk1);
-    const double rc = full_of(a.rho, lk + rj + i, a.rho0[k]);
-    const double e11 = (u_e - u_c) * a.idx, e22 = (v_n - v_c) * a.idy, e33 = (w_u - w_c) * a.idz[k];
+    auto U = [&](int ii, int r, int l) { return (R)a.u[l + r + ii]; };
+    auto V = [&](int ii, int r, int l) { return (R)a.v[l + r + ii]; };
+    auto Wf = [&](int ii, int r, int l) { return (R)a.w[l + r + ii]; };
+    const R idx = (R)a.idx, idy = (R)a.idy;
+    const R gz0 = (R)a.idzf[k], gz1 = (R)a.idzf[k + 1];
+    const R u_c = U(i, rj, lk), u_e = U(ip, rj, lk), u_s = U(i, rjm, lk), u_se = U(ip, rjm, lk);
+    const R u_n = U(i, rjp, lk), u_ne = U(ip, rjp, lk);
+    const R u_b = U(i, rj, lkm), u_be = U(ip, rj, lkm), u_t = U(i, rj, lkp), u_te = U(ip, rj, lkp);
+    const R v_c = V(i, rj, lk), v_n = V(i, rjp, lk), v_w = V(im, rj, lk), v_e = V(ip, rj, lk);
+    const R v_nw = V(im, rjp, lk), v_ne = V(ip, rjp, lk);
+    const R v_b = V(i, rj, lkm), v_bn = V(i, rjp, lkm), v_t = V(i, rj, lkp), v_tn = V(i, rjp, lkp);
+    const R w_c = Wf(i, rj, lk), w_u = Wf(i, rj, lk1), w_w = Wf(im, rj, lk), w_e = Wf(ip, rj, lk);
+    const R w_wu = Wf(im, rj, lk1), w_eu = Wf(ip, rj, lk1), w_s = Wf(i, rjm, lk), w_n = Wf(i, rjp, lk);
+    const R w_su = Wf(i, rjm, lk1), w_nu = Wf(i, rjp, lk1);
+    const R rc = full_in(a.rho, lk + rj + i, a.rho0[k]);
+    const R e11 = (u_e - u_c) * idx, e22 = (v_n - v_c) * idy, e33 = (w_u - w_c) * (R)a.idz[k];
+    const R h = R(0.5), q4 = R(0.25);
     // S12 on the four xy-edges; S13 on the x-face edges of faces k, k+1; S23 likewise
-    const double a12 = 0.25 * (0.5 * ((u_c - u_s) * a.idy + (v_c - v_w) * a.idx) +
-                               0.5 * ((u_e - u_se) * a.idy + (v_e - v_c) * a.idx) +
-                               0.5 * ((u_n - u_c) * a.idy + (v_n - v_nw) * a.idx) +
-                               0.5 * ((u_ne - u_e) * a.idy + (v_ne - v_n) * a.idx));
-    const double a13 = 0.25 * (0.5 * ((u_c - u_b) * gz0 + (w_c - w_w) * a.idx) +
-                               0.5 * ((u_e - u_be) * gz0 + (w_e - w_c) * a.idx) +
-                               0.5 * ((u_t - u_c) * gz1 + (w_u - w_wu) * a.idx) +
-                               0.5 * ((u_te - u_e) * gz1 + (w_eu - w_u) * a.idx));
-    const double a23 = 0.25 * (0.5 * ((v_c - v_b) * gz0 + (w_c - w_s) * a.idy) +
-                               0.5 * ((v_n - v_bn) * gz0 + (w_n - w_c) * a.idy) +
-                               0.5 * ((v_t - v_c) * gz1 + (w_u - w_su) * a.idy) +
-                               0.5 * ((v_tn - v_n) * gz1 + (w_nu - w_u) * a.idy));
-    const double ss = 2.0 * (e11 * e11 + e22 * e22 + e33 * e33) + 4.0 * (a12 * a12 + a13 * a13 + a23 * a23);
-    st_stream(a.mut + lk + rj + i, (T)(rc * a.cs2[k] * sqrt(ss)));  // read by a later launch only
+    const R a12 = q4 * (h * ((u_c - u_s) * idy + (v_c - v_w) * idx) + h * ((u_e - u_se) * idy + (v_e - v_c) * idx) +
+                        h * ((u_n - u_c) * idy + (v_n - v_nw) * idx) + h * ((u_ne - u_e) * idy + (v_ne - v_n) * idx));
+    const R a13 = q4 * (h * ((u_c - u_b) * gz0 + (w_c - w_w) * idx) + h * ((u_e - u_be) * gz0 + (w_e - w_c) * idx) +
+                        h * ((u_t - u_c) * gz1 + (w_u - w_wu) * idx) + h * ((u_te - u_e) * gz1 + (w_eu - w_u) * idx));
+    const R a23 = q4 * (h * ((v_c - v_b) * gz0 + (w_c - w_s) * idy) + h * ((v_n - v_bn) * gz0 + (w_n - w_c) * idy) +
+                        h * ((v_t - v_c) * gz1 + (w_u - w_su) * idy) + h * ((v_tn - v_n) * gz1 + (w_nu - w_u) * idy));
+    const R ss = R(2) * (e11 * e11 + e22 * e22 + e33 * e33) + R(4) * (a12 * a12 + a13 * a13 + a23 * a23);
+    st_stream(a.mut + lk + rj + i, (T)(rc * (R)a.cs2[k] * sqrt(ss)));  // read by a later launch only
 }
 
 // Stresses tau = -2 mu (S - D) at their points, mu = rho nu_m + mu_t averaged
@@ -176,6 +168,7 @@ __global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void k_stress(RhsArgs<T> a)
 {
+    using R = T;
     const Dims &d = a.d;
     const TileIdx t = tile_cell(a.ntx, a.nty);
     const int i = t.i, j = t.j, k = t.k;  // k = 0..nz: face k and, below the top, cell k
@@ -189,46 +182,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
     const int lc = kc * P, lb = kb * P, lf = k * P, lc1 = (kc + 1) * P;
     const double rc0 = a.rho0[kc], rb0 = a.rho0[kb];
     const bool sgs = a.sgs != 0;
+    const R nu = (R)a.nu, idx = (R)a.idx, idy = (R)a.idy, q4 = R(0.25), h = R(0.5), m2 = R(-2);
     // mu = rho nu_m + mu_t (mu_t read always and used only with the SGS model)
     auto mu = [&](int cc, double r0) {
-        const double mt = (double)a.mut[cc];
-        return full_of(a.rho, cc, r0) * a.nu + (sgs ? mt : 0.0);
+        const R mt = (R)a.mut[cc];
+        return full_in(a.rho, cc, r0) * nu + (sgs ? mt : R(0));
     };
-    const double u_f = a.u[lc + rj + i], u_fb = a.u[lb + rj + i];
-    const double v_f = a.v[lc + rj + i], v_fb = a.v[lb + rj + i];
-    const double w_f = a.w[lf + rj + i], w_fw = a.w[lf + rj + im], w_fs = a.w[lf + rjm + i];
-    const double m_c = mu(lc + rj + i, rc0), m_w = mu(lc + rj + im, rc0), m_s = mu(lc + rjm + i, rc0);
-    const double m_ws = mu(lc + rjm + im, rc0);
-    const double m_b = mu(lb + rj + i, rb0), m_bw = mu(lb + rj + im, rb0), m_bs = mu(lb + rjm + i, rb0);
-    const double u_e = a.u[lc + rj + ip], u_s = a.u[lc + rjm + i];
-    const double v_n = a.v[lc + rjp + i], v_w = a.v[lc + rj + im];
-    const double w_u = a.w[lc1 + rj + i], w_c = a.w[lc + rj + i];
-    const double rc = full_of(a.rho, lc + rj + i, rc0), mtc = (double)a.mut[lc + rj + i];
+    const R u_f = a.u[lc + rj + i], u_fb = a.u[lb + rj + i];
+    const R v_f = a.v[lc + rj + i], v_fb = a.v[lb + rj + i];
+    const R w_f = a.w[lf + rj + i], w_fw = a.w[lf + rj + im], w_fs = a.w[lf + rjm + i];
+    const R m_c = mu(lc + rj + i, rc0), m_w = mu(lc + rj + im, rc0), m_s = mu(lc + rjm + i, rc0);
+    const R m_ws = mu(lc + rjm + im, rc0);
+    const R m_b = mu(lb + rj + i, rb0), m_bw = mu(lb + rj + im, rb0), m_bs = mu(lb + rjm + i, rb0);
+    const R u_e = a.u[lc + rj + ip], u_s = a.u[lc + rjm + i];
+    const R v_n = a.v[lc + rjp + i], v_w = a.v[lc + rj + im];
+    const R w_u = a.w[lc1 + rj + i], w_c = a.w[lc + rj + i];
+    const R rc = full_in(a.rho, lc + rj + i, rc0), mtc = (R)a.mut[lc + rj + i];
     // shear stresses on the z-face edges of face k (zero on the lids)
     const bool inner = k > 0 && k < nz;
-    const double idzf = a.idzf[k];
-    const double s13 = 0.5 * ((u_f - u_fb) * idzf + (w_f - w_fw) * a.idx);
-    const double s23 = 0.5 * ((v_f - v_fb) * idzf + (w_f - w_fs) * a.idy);
-    const double mxz = 0.25 * (m_bw + m_b + m_w + m_c);
-    const double myz = 0.25 * (m_bs + m_b + m_s + m_c);
+    const R idzf = (R)a.idzf[k];
+    const R s13 = h * ((u_f - u_fb) * idzf + (w_f - w_fw) * idx);
+    const R s23 = h * ((v_f - v_fb) * idzf + (w_f - w_fs) * idy);
+    const R mxz = q4 * (m_bw + m_b + m_w + m_c);
+    const R myz = q4 * (m_bs + m_b + m_s + m_c);
     // centre values of the level (the top face plane computes them for
     // level nz - 1 again and does not store them)
-    const double idz = a.idz[kc];
-    const double e11 = (u_e - u_f) * a.idx;
-    const double e22 = (v_n - v_f) * a.idy;
-    const double e33 = (w_u - w_c) * idz;
-    const double dd = (e11 + e22 + e33) / 3.0;
-    const double s12 = 0.5 * ((u_f - u_s) * a.idy + (v_f - v_w) * a.idx);
-    const double me = 0.25 * (m_ws + m_s + m_w + m_c);
-    st_stream(a.t13 + lf + rj + i, (T)(inner ? -2.0 * mxz * s13 : 0.0));
-    st_stream(a.t23 + lf + rj + i, (T)(inner ? -2.0 * myz * s23 : 0.0));
+    const R idz = (R)a.idz[kc];
+    const R e11 = (u_e - u_f) * idx;
+    const R e22 = (v_n - v_f) * idy;
+    const R e33 = (w_u - w_c) * idz;
+    const R dd = (e11 + e22 + e33) / R(3);
+    const R s12 = h * ((u_f - u_s) * idy + (v_f - v_w) * idx);
+    const R me = q4 * (m_ws + m_s + m_w + m_c);
+    st_stream(a.t13 + lf + rj + i, (T)(inner ? m2 * mxz * s13 : R(0)));
+    st_stream(a.t23 + lf + rj + i, (T)(inner ? m2 * myz * s23 : R(0)));
     if (k < nz) {
         const int c = lc + rj + i;
-        st_stream(a.t11 + c, (T)(-2.0 * m_c * (e11 - dd)));
-        st_stream(a.t22 + c, (T)(-2.0 * m_c * (e22 - dd)));
-        st_stream(a.t33 + c, (T)(-2.0 * m_c * (e33 - dd)));
-        st_stream(a.t12 + c, (T)(-2.0 * me * s12));
-        st_stream(a.kap + c, (T)(rc * a.alpha + (sgs ? mtc / a.Pr_t : 0.0)));
+        st_stream(a.t11 + c, (T)(m2 * m_c * (e11 - dd)));
+        st_stream(a.t22 + c, (T)(m2 * m_c * (e22 - dd)));
+        st_stream(a.t33 + c, (T)(m2 * m_c * (e33 - dd)));
+        st_stream(a.t12 + c, (T)(m2 * me * s12));
+        st_stream(a.kap + c, (T)(rc * (R)a.alpha + (sgs ? mtc / (R)a.Pr_t : R(0))));
     }
 }
 
@@ -239,18 +233,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
 // q_{m-3..m+2}: o = 0 for the face on the low side of the point, o = 1 for the
 // face on the high side.  s is a sign (-1, 0 or 1), so s * (1/12) and
 // s * (1/60) are exactly s / 12 and s / 60, without a division.
-template <int O>
-__device__ __forceinline__ double interp(int order, const double (&q)[7], int o, double s)
+template <int O, typename R>
+__device__ __forceinline__ R interp(int order, const R (&q)[7], int o, R s)
 {
-    const double qm3 = q[o], qm2 = q[o + 1], qm1 = q[o + 2], q0 = q[o + 3], qp1 = q[o + 4], qp2 = q[o + 5];
+    const R qm3 = q[o], qm2 = q[o + 1], qm1 = q[o + 2], q0 = q[o + 3], qp1 = q[o + 4], qp2 = q[o + 5];
     const int ord = O ? O : order;
-    if (ord == 2) return 0.5 * (q0 + qm1);
+    if (ord == 2) return R(0.5) * (q0 + qm1);
     if (ord == 3 || ord == 4) {
-        const double c4 = 7.0 / 12.0 * (q0 + qm1) - 1.0 / 12.0 * (qp1 + qm2);
-        return ord == 4 ? c4 : c4 + s * (1.0 / 12.0) * ((qp1 - qm2) - 3.0 * (q0 - qm1));
+        const R c4 = R(7.0 / 12.0) * (q0 + qm1) - R(1.0 / 12.0) * (qp1 + qm2);
+        return ord == 4 ? c4 : c4 + s * R(1.0 / 12.0) * ((qp1 - qm2) - R(3) * (q0 - qm1));
     }
-    const double c6 = 37.0 / 60.0 * (q0 + qm1) - 2.0 / 15.0 * (qp1 + qm2) + 1.0 / 60.0 * (qp2 + qm3);
-    return ord == 6 ? c6 : c6 - s * (1.0 / 60.0) * ((qp2 - qm3) - 5.0 * (qp1 - qm2) + 10.0 * (q0 - qm1));
+    const R c6 = R(37.0 / 60.0) * (q0 + qm1) - R(2.0 / 15.0) * (qp1 + qm2) + R(1.0 / 60.0) * (qp2 + qm3);
+    return ord == 6 ? c6 : c6 - s * R(1.0 / 60.0) * ((qp2 - qm3) - R(5) * (qp1 - qm2) + R(10) * (q0 - qm1));
 }
 
 // kNear: the domain is at least 3 cells wide and 3 levels high, so that one
@@ -258,14 +252,15 @@ __device__ __forceinline__ double interp(int order, const double (&q)[7], int o,
 // into it; the periodic and reflected indices are then selects instead of
 // branches, and every load of a section can be issued before its arithmetic.
 // kVisc: the viscous and diffusive terms (stress and diffusivity arrays).
+// kMoist: the pressure gradient and the buoyancy are divided by the face mean of
+// 1 + q_v + q_c, and the buoyancy is that of the total density (eq. mom).
 // Three wavefronts per SIMD (the occupancy its registers give anyway): told
 // so, the scheduler keeps each section's gathers in a few large groups
 // rather than trading round trips for registers.
-// kMoist: the pressure gradient and the buoyancy are divided by the face mean of
-// 1 + q_v + q_c, and the buoyancy is that of the total density (eq. mom).
 template <typename T, int OH, int OV, bool kNear, bool kVisc, bool kMoist>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_rhs(RhsArgs<T> a)
 {
+    using R = T;
     const Dims &d = a.d;
     const TileIdx tc = tile_cell(a.ntx, a.nty);
     const int i = tc.i, j = tc.j, k = tc.k;
@@ -292,7 +287,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     auto ox = [&](int t) { return wrap(i + t - 3, d.nx) - i; };
     auto oy = [&](int t) { return (wrap(j + t - 3, d.ny) - j) * d.nx; };
     auto ozc = [&](int t) { return (reflc(k + t - 3) - k) * P; };
-    auto thz0 = [&](int t) { return kPert<T> ? a.theta0[reflc(k + t - 3)] : 0.0; };
+    // FP32 storage: theta0 of the level k + t - 3 relative to level k (the
+    // base-state difference formed in double, then rounded)
+    auto dthz0 = [&](int t) { return (R)(a.theta0[reflc(k + t - 3)] - a.theta0[k]); };
     auto ozw = [&](int t) {
         double sg;
         return (reflf(k + t - 3, sg) - k) * P;
@@ -300,118 +297,140 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     auto szw = [&](int t) {
         double sg;
         reflf(k + t - 3, sg);
-        return sg;
+        return (R)sg;
     };
     // the cell below, clamped at the bottom (its values unused there)
     const int dn = k > 0 ? P : 0;
     // 1 away from the bottom (top) lid, 0 on it: the lid fluxes are masked by
     // a product rather than a conditional, which the compiler would make a
     // branch with part of the stencil loads behind it
-    const double not_bot = (double)(k > 0), not_top = (double)(k < nz - 1);
-    const double idz = a.idz[k];
+    const R not_bot = (R)(k > 0), not_top = (R)(k < nz - 1);
+    const R idx = (R)a.idx, idy = (R)a.idy, idz = (R)a.idz[k], h = R(0.5), q4 = R(0.25);
     const int oh = a.oh, ov = a.ov;
-    double q[7];
+    R q[7];
     // the five tendencies, stored together at the end: a store between the
     // sections would keep every later load behind it (the compiler cannot
     // rule out that it aliases them)
-    double out_r, out_t, out_u, out_v, out_w;
+    R out_r, out_t, out_u, out_v, out_w;
 
     // ---------------- cell: continuity and rho*theta ----------------
-    const double U0 = a.ru[c], U1 = a.ru[c + ox(4)];
-    const double V0 = a.rv[c], V1 = a.rv[c + oy(4)];
-    const double W0 = a.rw[c], W1 = a.rw[c + P];
-    const double r0k = a.rho0[k], rc = full_of(a.rho, c, r0k);
-    const double th0k = kPert<T> ? a.theta0[k] : 0.0;
+    const R U0 = a.ru[c], U1 = a.ru[c + ox(4)];
+    const R V0 = a.rv[c], V1 = a.rv[c + oy(4)];
+    const R W0 = a.rw[c], W1 = a.rw[c + P];
+    const double r0k = a.rho0[k];
+    const R rc = full_in(a.rho, c, r0k);
     {
         // tendencies are read by later launches only: streaming stores
-        out_r = -((U1 - U0) * a.idx + (V1 - V0) * a.idy + (W1 - W0) * idz);
+        out_r = -((U1 - U0) * idx + (V1 - V0) * idy + (W1 - W0) * idz);
         const T *th = a.th;
+        R r;
+        if constexpr (kPert<T>) {
+            // FP32: the flux U theta^ split as U theta0(k) + U (theta^ - theta0(k)),
+            // theta^ - theta0(k) interpolated from theta - theta0(k) (horizontally
+            // the stored perturbation, vertically plus the base-state difference
+            // of the levels), so that no float sum carries theta0 ~ 300 K
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = th0k + th[c + ox(t)];
-        const double fx0 = U0 * interp<OH>(oh, q, 0, sign_of(U0)), fx1 = U1 * interp<OH>(oh, q, 1, sign_of(U1));
+            for (int t = 0; t < 7; ++t) q[t] = th[c + ox(t)];
+            const R fx0 = U0 * interp<OH>(oh, q, 0, sign_of(U0)), fx1 = U1 * interp<OH>(oh, q, 1, sign_of(U1));
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = th0k + th[c + oy(t)];
-        const double fy0 = V0 * interp<OH>(oh, q, 0, sign_of(V0)), fy1 = V1 * interp<OH>(oh, q, 1, sign_of(V1));
+            for (int t = 0; t < 7; ++t) q[t] = th[c + oy(t)];
+            const R fy0 = V0 * interp<OH>(oh, q, 0, sign_of(V0)), fy1 = V1 * interp<OH>(oh, q, 1, sign_of(V1));
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = thz0(t) + th[c + ozc(t)];
-        const double fz0 = W0 * interp<OV>(ov, q, 0, sign_of(W0)) * not_bot;
-        const double fz1 = W1 * interp<OV>(ov, q, 1, sign_of(W1)) * not_top;
-        double r = -((fx1 - fx0) * a.idx + (fy1 - fy0) * a.idy + (fz1 - fz0) * idz);
+            for (int t = 0; t < 7; ++t) q[t] = dthz0(t) + th[c + ozc(t)];
+            const R fz0 = W0 * interp<OV>(ov, q, 0, sign_of(W0)) * not_bot;
+            const R fz1 = W1 * interp<OV>(ov, q, 1, sign_of(W1)) * not_top;
+            r = (R)a.theta0[k] * out_r - ((fx1 - fx0) * idx + (fy1 - fy0) * idy + (fz1 - fz0) * idz);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 7; ++t) q[t] = th[c + ox(t)];
+            const R fx0 = U0 * interp<OH>(oh, q, 0, sign_of(U0)), fx1 = U1 * interp<OH>(oh, q, 1, sign_of(U1));
+#pragma unroll
+            for (int t = 0; t < 7; ++t) q[t] = th[c + oy(t)];
+            const R fy0 = V0 * interp<OH>(oh, q, 0, sign_of(V0)), fy1 = V1 * interp<OH>(oh, q, 1, sign_of(V1));
+#pragma unroll
+            for (int t = 0; t < 7; ++t) q[t] = th[c + ozc(t)];
+            const R fz0 = W0 * interp<OV>(ov, q, 0, sign_of(W0)) * not_bot;
+            const R fz1 = W1 * interp<OV>(ov, q, 1, sign_of(W1)) * not_top;
+            r = -((fx1 - fx0) * idx + (fy1 - fy0) * idy + (fz1 - fz0) * idz);
+        }
         if constexpr (kVisc) {
             const T *kp = a.kap;
             const int up = k < nz - 1 ? P : 0;  // the cell above, clamped at the top
-            const double kc = kp[c], thc = th0k + th[c];
-            const double hx0 = -0.5 * (kp[c + ox(2)] + kc) * (thc - (th0k + th[c + ox(2)])) * a.idx;
-            const double hx1 = -0.5 * (kc + kp[c + ox(4)]) * ((th0k + th[c + ox(4)]) - thc) * a.idx;
-            const double hy0 = -0.5 * (kp[c + oy(2)] + kc) * (thc - (th0k + th[c + oy(2)])) * a.idy;
-            const double hy1 = -0.5 * (kc + kp[c + oy(4)]) * ((th0k + th[c + oy(4)]) - thc) * a.idy;
-            const double kb = kp[c - dn], tb = th[c - dn], ka = kp[c + up], ta = th[c + up];
-            const double hz0 = -0.5 * (kb + kc) * (thc - (thz0(2) + tb)) * a.idzf[k] * not_bot;
-            const double hz1 = -0.5 * (kc + ka) * ((thz0(4) + ta) - thc) * a.idzf[k + 1] * not_top;
-            r -= (hx1 - hx0) * a.idx + (hy1 - hy0) * a.idy + (hz1 - hz0) * idz;
+            const R kc = kp[c], thc = th[c];
+            // differences of theta: on one level the base value cancels; across
+            // levels (FP32 storage) the base-state difference is added
+            const R dzb = kPert<T> ? dthz0(2) : R(0), dza = kPert<T> ? dthz0(4) : R(0);
+            const R hx0 = -h * (kp[c + ox(2)] + kc) * (thc - (R)th[c + ox(2)]) * idx;
+            const R hx1 = -h * (kc + kp[c + ox(4)]) * ((R)th[c + ox(4)] - thc) * idx;
+            const R hy0 = -h * (kp[c + oy(2)] + kc) * (thc - (R)th[c + oy(2)]) * idy;
+            const R hy1 = -h * (kc + kp[c + oy(4)]) * ((R)th[c + oy(4)] - thc) * idy;
+            const R kb = kp[c - dn], tb = th[c - dn], ka = kp[c + up], ta = th[c + up];
+            const R hz0 = -h * (kb + kc) * (thc - (dzb + tb)) * (R)a.idzf[k] * not_bot;
+            const R hz1 = -h * (kc + ka) * ((dza + ta) - thc) * (R)a.idzf[k + 1] * not_top;
+            r -= (hx1 - hx0) * idx + (hy1 - hy0) * idy + (hz1 - hz0) * idz;
         }
-        if (k == 0 && a.Qs != 0.0) r += rc * a.Qs * idz;
+        if (k == 0 && a.Qs != 0.0) r += rc * (R)a.Qs * idz;
         out_t = r;
     }
 
     // ---------------- x-momentum on x-face (i, j, k) ----------------
     {
-        const double Um = a.ru[c + ox(2)];
-        const double ar = 0.5 * (U0 + U1), al = 0.5 * (Um + U0);
+        const R Um = a.ru[c + ox(2)];
+        const R ar = h * (U0 + U1), al = h * (Um + U0);
         const T *u = a.u;
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = u[c + ox(t)];
-        const double fxx_r = ar * interp<OH>(oh, q, 1, sign_of(ar)), fxx_l = al * interp<OH>(oh, q, 0, sign_of(al));
-        const double Vw = a.rv[c + ox(2)], Vwn = a.rv[c + ox(2) + oy(4)];
-        const double b0 = 0.5 * (Vw + V0), b1 = 0.5 * (Vwn + V1);
+        const R fxx_r = ar * interp<OH>(oh, q, 1, sign_of(ar)), fxx_l = al * interp<OH>(oh, q, 0, sign_of(al));
+        const R Vw = a.rv[c + ox(2)], Vwn = a.rv[c + ox(2) + oy(4)];
+        const R b0 = h * (Vw + V0), b1 = h * (Vwn + V1);
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = u[c + oy(t)];
-        const double fxy0 = b0 * interp<OH>(oh, q, 0, sign_of(b0)), fxy1 = b1 * interp<OH>(oh, q, 1, sign_of(b1));
+        const R fxy0 = b0 * interp<OH>(oh, q, 0, sign_of(b0)), fxy1 = b1 * interp<OH>(oh, q, 1, sign_of(b1));
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = u[c + ozc(t)];
         // z-face momenta (faces 0..nz all exist; the lid fluxes are zero)
-        const double e0 = 0.5 * (a.rw[c + ox(2)] + W0), e1 = 0.5 * (a.rw[c + ox(2) + P] + W1);
-        const double fxz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0)) * not_bot;
-        const double fxz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1)) * not_top;
-        const double adv = (fxx_r - fxx_l) * a.idx + (fxy1 - fxy0) * a.idy + (fxz1 - fxz0) * idz;
-        double pgf = (a.pp[c] - a.pp[c + ox(2)]) * a.idx;
-        if constexpr (kMoist) pgf = pgf / (0.5 * ((double)a.qf[c + ox(2)] + (double)a.qf[c]));
-        const double rho_f = 0.5 * (full_of(a.rho, c + ox(2), r0k) + rc);
-        const double vbar = 0.25 * (Vw + V0 + Vwn + V1);
-        double r = -adv - pgf + a.f * (vbar - rho_f * a.Vg);
+        const R e0 = h * ((R)a.rw[c + ox(2)] + W0), e1 = h * ((R)a.rw[c + ox(2) + P] + W1);
+        const R fxz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0)) * not_bot;
+        const R fxz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1)) * not_top;
+        const R adv = (fxx_r - fxx_l) * idx + (fxy1 - fxy0) * idy + (fxz1 - fxz0) * idz;
+        R pgf = ((R)a.pp[c] - (R)a.pp[c + ox(2)]) * idx;
+        if constexpr (kMoist) pgf = pgf / (h * ((R)a.qf[c + ox(2)] + (R)a.qf[c]));
+        const R rho_f = h * (full_in(a.rho, c + ox(2), r0k) + rc);
+        const R vbar = q4 * (Vw + V0 + Vwn + V1);
+        R r = -adv - pgf + (R)a.f * (vbar - rho_f * (R)a.Vg);
         if constexpr (kVisc)
-            r -= (a.t11[c] - a.t11[c + ox(2)]) * a.idx + (a.t12[c + oy(4)] - a.t12[c]) * a.idy +
-                 (a.t13[c + P] - a.t13[c]) * idz;
+            r -= ((R)a.t11[c] - (R)a.t11[c + ox(2)]) * idx + ((R)a.t12[c + oy(4)] - (R)a.t12[c]) * idy +
+                 ((R)a.t13[c + P] - (R)a.t13[c]) * idz;
         out_u = r;
     }
 
     // ---------------- y-momentum on y-face (i, j, k) ----------------
     {
-        const double Vs = a.rv[c + oy(2)];
-        const double br = 0.5 * (V0 + V1), bl = 0.5 * (Vs + V0);
+        const R Vs = a.rv[c + oy(2)];
+        const R br = h * (V0 + V1), bl = h * (Vs + V0);
         const T *v = a.v;
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = v[c + oy(t)];
-        const double fyy_r = br * interp<OH>(oh, q, 1, sign_of(br)), fyy_l = bl * interp<OH>(oh, q, 0, sign_of(bl));
-        const double Us = a.ru[c + oy(2)], Use = a.ru[c + oy(2) + ox(4)];
-        const double a0 = 0.5 * (Us + U0), a1 = 0.5 * (Use + U1);
+        const R fyy_r = br * interp<OH>(oh, q, 1, sign_of(br)), fyy_l = bl * interp<OH>(oh, q, 0, sign_of(bl));
+        const R Us = a.ru[c + oy(2)], Use = a.ru[c + oy(2) + ox(4)];
+        const R a0 = h * (Us + U0), a1 = h * (Use + U1);
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = v[c + ox(t)];
-        const double fyx0 = a0 * interp<OH>(oh, q, 0, sign_of(a0)), fyx1 = a1 * interp<OH>(oh, q, 1, sign_of(a1));
+        const R fyx0 = a0 * interp<OH>(oh, q, 0, sign_of(a0)), fyx1 = a1 * interp<OH>(oh, q, 1, sign_of(a1));
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = v[c + ozc(t)];
-        const double e0 = 0.5 * (a.rw[c + oy(2)] + W0), e1 = 0.5 * (a.rw[c + oy(2) + P] + W1);
-        const double fyz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0)) * not_bot;
-        const double fyz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1)) * not_top;
-        const double adv = (fyx1 - fyx0) * a.idx + (fyy_r - fyy_l) * a.idy + (fyz1 - fyz0) * idz;
-        double pgf = (a.pp[c] - a.pp[c + oy(2)]) * a.idy;
-        if constexpr (kMoist) pgf = pgf / (0.5 * ((double)a.qf[c + oy(2)] + (double)a.qf[c]));
-        const double rho_f = 0.5 * (full_of(a.rho, c + oy(2), r0k) + rc);
-        const double ubar = 0.25 * (Us + Use + U0 + U1);
-        double r = -adv - pgf - a.f * (ubar - rho_f * a.Ug);
+        const R e0 = h * ((R)a.rw[c + oy(2)] + W0), e1 = h * ((R)a.rw[c + oy(2) + P] + W1);
+        const R fyz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0)) * not_bot;
+        const R fyz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1)) * not_top;
+        const R adv = (fyx1 - fyx0) * idx + (fyy_r - fyy_l) * idy + (fyz1 - fyz0) * idz;
+        R pgf = ((R)a.pp[c] - (R)a.pp[c + oy(2)]) * idy;
+        if constexpr (kMoist) pgf = pgf / (h * ((R)a.qf[c + oy(2)] + (R)a.qf[c]));
+        const R rho_f = h * (full_in(a.rho, c + oy(2), r0k) + rc);
+        const R ubar = q4 * (Us + Use + U0 + U1);
+        R r = -adv - pgf - (R)a.f * (ubar - rho_f * (R)a.Ug);
         if constexpr (kVisc)
-            r -= (a.t12[c + ox(4)] - a.t12[c]) * a.idx + (a.t22[c] - a.t22[c + oy(2)]) * a.idy +
-                 (a.t23[c + P] - a.t23[c]) * idz;
+            r -= ((R)a.t12[c + ox(4)] - (R)a.t12[c]) * idx + ((R)a.t22[c] - (R)a.t22[c + oy(2)]) * idy +
+                 ((R)a.t23[c + P] - (R)a.t23[c]) * idz;
         out_v = r;
     }
 
@@ -420,39 +439,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     // clamped (in-range) indices and stored as zero
     {
         const int cm = c - dn;
-        const double idzf = a.idzf[k];
-        const double a0 = 0.5 * (a.ru[cm] + U0), a1 = 0.5 * (a.ru[cm + ox(4)] + U1);
+        const R idzf = (R)a.idzf[k];
+        const R a0 = h * ((R)a.ru[cm] + U0), a1 = h * ((R)a.ru[cm + ox(4)] + U1);
         const T *w = a.w;
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = w[c + ox(t)];
-        const double fzx0 = a0 * interp<OH>(oh, q, 0, sign_of(a0)), fzx1 = a1 * interp<OH>(oh, q, 1, sign_of(a1));
-        const double b0 = 0.5 * (a.rv[cm] + V0), b1 = 0.5 * (a.rv[cm + oy(4)] + V1);
+        const R fzx0 = a0 * interp<OH>(oh, q, 0, sign_of(a0)), fzx1 = a1 * interp<OH>(oh, q, 1, sign_of(a1));
+        const R b0 = h * ((R)a.rv[cm] + V0), b1 = h * ((R)a.rv[cm + oy(4)] + V1);
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = w[c + oy(t)];
-        const double fzy0 = b0 * interp<OH>(oh, q, 0, sign_of(b0)), fzy1 = b1 * interp<OH>(oh, q, 1, sign_of(b1));
-        const double eu = 0.5 * (W0 + W1), ed = 0.5 * (a.rw[cm] + W0);
+        const R fzy0 = b0 * interp<OH>(oh, q, 0, sign_of(b0)), fzy1 = b1 * interp<OH>(oh, q, 1, sign_of(b1));
+        const R eu = h * (W0 + W1), ed = h * ((R)a.rw[cm] + W0);
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = szw(t) * w[c + ozw(t)];
-        const double fzz_u = eu * interp<OV>(ov, q, 1, sign_of(eu)), fzz_d = ed * interp<OV>(ov, q, 0, sign_of(ed));
-        const double adv = (fzx1 - fzx0) * a.idx + (fzy1 - fzy0) * a.idy + (fzz_u - fzz_d) * idzf;
-        const double pgf = (a.pp[c] - a.pp[cm]) * idzf;
-        double r;
+        const R fzz_u = eu * interp<OV>(ov, q, 1, sign_of(eu)), fzz_d = ed * interp<OV>(ov, q, 0, sign_of(ed));
+        const R adv = (fzx1 - fzx0) * idx + (fzy1 - fzy0) * idy + (fzz_u - fzz_d) * idzf;
+        const R pgf = ((R)a.pp[c] - (R)a.pp[cm]) * idzf;
+        R r;
         if constexpr (kMoist) {
             // B = -g (rho_m - rho_m0) from the total densities; -grad p' + B over
             // the face mean of 1 + q_v + q_c
-            const double buoy = -a.g * 0.5 * ((double)a.bm[c] + (double)a.bm[cm]);
-            const double qfm = 0.5 * ((double)a.qf[cm] + (double)a.qf[c]);
+            const R buoy = -(R)a.g * h * ((R)a.bm[c] + (R)a.bm[cm]);
+            const R qfm = h * ((R)a.qf[cm] + (R)a.qf[c]);
             r = -adv - pgf / qfm + buoy / qfm;
         } else {
             // buoyancy B = -(rho - rho0) g on the face; heavier air sinks
-            const double buoy =
-                -a.g * 0.5 * (pert_of(a.rho, c, r0k) + pert_of(a.rho, cm, a.rho0[k > 0 ? k - 1 : 0]));
+            const R buoy = -(R)a.g * h * (pert_in(a.rho, c, r0k) + pert_in(a.rho, cm, a.rho0[k > 0 ? k - 1 : 0]));
             r = -adv - pgf + buoy;
         }
         if constexpr (kVisc)
-            r -= (a.t13[c + ox(4)] - a.t13[c]) * a.idx + (a.t23[c + oy(4)] - a.t23[c]) * a.idy +
-                 (a.t33[c] - a.t33[cm]) * idzf;
-        out_w = k > 0 ? r : 0.0;
+            r -= ((R)a.t13[c + ox(4)] - (R)a.t13[c]) * idx + ((R)a.t23[c + oy(4)] - (R)a.t23[c]) * idy +
+                 ((R)a.t33[c] - (R)a.t33[cm]) * idzf;
+        out_w = k > 0 ? r : R(0);
     }
     st_stream(a.Rr + c, (T)out_r);
     st_stream(a.Rt + c, (T)out_t);

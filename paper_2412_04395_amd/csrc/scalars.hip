@@ -2,7 +2,8 @@
 //   (rho q)^new = (rho q)^n - dts * div(F q^t),  q^t = (rho q)^t / rho^t,
 // F the stage-averaged momenta.  Face values of q^t come from the interpolants
 // of Sec. 3.6 or from WENO5-JS (Jiang & Shu 1996, cited in Sec. 3.6), upwinded
-// by the sign of F.  Stored as T (double or float); arithmetic in double.
+// by the sign of F.  Stored and computed as T: double, or float for the FP32
+// path (the bulk stencil arithmetic of the mixed-precision mode).
 #include "erf_internal.h"
 
 namespace erfk {
@@ -26,10 +27,11 @@ __global__ __launch_bounds__(256) void k_mixing_ratio(ScalArgs<T> a)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.d.n) return;
-    const double r = full_of(a.rho_t, c, a.rho0[c / a.d.nxy]);
+    // full rho^t: stored (FP64) or base + perturbation (FP32 storage), in T
+    const T r = kPert<T> ? (T)a.rho0[c / a.d.nxy] + a.rho_t[c] : a.rho_t[c];
     for (int s = 0; s < a.nq; ++s) {
         const size_t o = (size_t)s * a.d.n + c;
-        a.q[o] = (double)a.rq_t[o] / r;
+        a.q[o] = a.rq_t[o] / r;
     }
 }
 
@@ -38,23 +40,25 @@ __global__ __launch_bounds__(256) void k_mixing_ratio(ScalArgs<T> a)
 // beta_k)^2, d = (0.1, 0.6, 0.3), normalised.  Written over one common
 // denominator: the weights are multiplied by the product of the three (eps +
 // beta)^2 and the 1/6 of the p_k moves into the final quotient, so a face
-// takes one FP64 division instead of seven; equal to the three-weight form up
-// to rounding.
-__device__ __forceinline__ double weno5_face(double v0, double v1, double v2, double v3, double v4)
+// takes one division instead of seven; equal to the three-weight form up to
+// rounding.  In float the product of two (eps + beta)^2 stays above 1e-24 and
+// below 1e30 for the mixing ratios and stencil jumps of the workloads.
+template <typename R>
+__device__ __forceinline__ R weno5_face(R v0, R v1, R v2, R v3, R v4)
 {
-    const double eps = 1.0e-6;
-    const double P0 = 2.0 * v0 - 7.0 * v1 + 11.0 * v2;  // 6 p0
-    const double P1 = -v1 + 5.0 * v2 + 2.0 * v3;        // 6 p1
-    const double P2 = 2.0 * v2 + 5.0 * v3 - v4;         // 6 p2
-    const double s0 = v0 - 2.0 * v1 + v2, t0 = v0 - 4.0 * v1 + 3.0 * v2;
-    const double s1 = v1 - 2.0 * v2 + v3, t1 = v1 - v3;
-    const double s2 = v2 - 2.0 * v3 + v4, t2 = 3.0 * v2 - 4.0 * v3 + v4;
-    const double be0 = 13.0 / 12.0 * s0 * s0 + 0.25 * t0 * t0;
-    const double be1 = 13.0 / 12.0 * s1 * s1 + 0.25 * t1 * t1;
-    const double be2 = 13.0 / 12.0 * s2 * s2 + 0.25 * t2 * t2;
-    const double a0 = (eps + be0) * (eps + be0), a1 = (eps + be1) * (eps + be1), a2 = (eps + be2) * (eps + be2);
-    const double w0 = 0.1 * (a1 * a2), w1 = 0.6 * (a0 * a2), w2 = 0.3 * (a0 * a1);
-    return (w0 * P0 + w1 * P1 + w2 * P2) / (6.0 * (w0 + w1 + w2));
+    const R eps = R(1.0e-6);
+    const R P0 = R(2) * v0 - R(7) * v1 + R(11) * v2;  // 6 p0
+    const R P1 = -v1 + R(5) * v2 + R(2) * v3;         // 6 p1
+    const R P2 = R(2) * v2 + R(5) * v3 - v4;          // 6 p2
+    const R s0 = v0 - R(2) * v1 + v2, t0 = v0 - R(4) * v1 + R(3) * v2;
+    const R s1 = v1 - R(2) * v2 + v3, t1 = v1 - v3;
+    const R s2 = v2 - R(2) * v3 + v4, t2 = R(3) * v2 - R(4) * v3 + v4;
+    const R be0 = R(13.0 / 12.0) * s0 * s0 + R(0.25) * t0 * t0;
+    const R be1 = R(13.0 / 12.0) * s1 * s1 + R(0.25) * t1 * t1;
+    const R be2 = R(13.0 / 12.0) * s2 * s2 + R(0.25) * t2 * t2;
+    const R a0 = (eps + be0) * (eps + be0), a1 = (eps + be1) * (eps + be1), a2 = (eps + be2) * (eps + be2);
+    const R w0 = R(0.1) * (a1 * a2), w1 = R(0.6) * (a0 * a2), w2 = R(0.3) * (a0 * a1);
+    return (w0 * P0 + w1 * P1 + w2 * P2) / (R(6) * (w0 + w1 + w2));
 }
 
 // Tiles of kSX x kSY cells per block of (kSX + 1) x (kSY + 1) threads, one
@@ -73,7 +77,8 @@ constexpr int kSX = 63, kSY = 15;
 template <typename T, bool kWeno, bool kNear>
 __global__ __launch_bounds__(1024) void k_scalar(ScalArgs<T> a)
 {
-    __shared__ double fxs[kSY + 1][kSX + 1], fys[kSY + 1][kSX + 1];
+    using R = T;  // arithmetic type
+    __shared__ R fxs[kSY + 1][kSX + 1], fys[kSY + 1][kSX + 1];
     const Dims &d = a.d;
     const int lane = threadIdx.x, row = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.nxy;
@@ -94,44 +99,44 @@ __global__ __launch_bounds__(1024) void k_scalar(ScalArgs<T> a)
     };
     // face value on the low (oo = 0) or high (oo = 1) side of the cell,
     // upwinded by the sign sg of the flux through it
-    auto face = [&](const double (&v)[7], int oo, double sg, int order) {
-        const double qm3 = v[oo], qm2 = v[oo + 1], qm1 = v[oo + 2], q0 = v[oo + 3], qp1 = v[oo + 4], qp2 = v[oo + 5];
+    auto face = [&](const R (&v)[7], int oo, R sg, int order) {
+        const R qm3 = v[oo], qm2 = v[oo + 1], qm1 = v[oo + 2], q0 = v[oo + 3], qp1 = v[oo + 4], qp2 = v[oo + 5];
         if constexpr (kWeno) {
-            const bool pos = sg >= 0.0;
-            return weno5_face(pos ? qm3 : qp2, pos ? qm2 : qp1, pos ? qm1 : q0, pos ? q0 : qm1, pos ? qp1 : qm2);
+            const bool pos = sg >= R(0);
+            return weno5_face<R>(pos ? qm3 : qp2, pos ? qm2 : qp1, pos ? qm1 : q0, pos ? q0 : qm1, pos ? qp1 : qm2);
         } else {
-            return face_interp(order, qm3, qm2, qm1, q0, qp1, qp2, sg);
+            return face_interp<R>(order, qm3, qm2, qm1, q0, qp1, qp2, sg);
         }
     };
     // q at offsets -3..3 in x and y (the low faces use -3..2)
-    double qx[7], qy[7];
+    R qx[7], qy[7];
 #pragma unroll
     for (int t = 0; t < 7; ++t) {
         qx[t] = q[c + (wrap(i + t - 3, nx) - i)];
         qy[t] = q[c + (wrap(j + t - 3, ny) - j) * nx];
     }
-    const double Fx0 = a.Fu[c], Fy0 = a.Fv[c];
-    const double fx0 = Fx0 * face(qx, 0, sign_of(Fx0), a.oh), fy0 = Fy0 * face(qy, 0, sign_of(Fy0), a.oh);
+    const R Fx0 = a.Fu[c], Fy0 = a.Fv[c];
+    const R fx0 = Fx0 * face(qx, 0, sign_of(Fx0), a.oh), fy0 = Fy0 * face(qy, 0, sign_of(Fy0), a.oh);
     fxs[row][lane] = fx0;
     fys[row][lane] = fy0;
-    double fz0 = 0.0, fz1 = 0.0, rq = 0.0;
+    R fz0 = 0, fz1 = 0, rq = 0;
     const size_t o = (size_t)s * d.n + c;
     if (row < kSY) {  // the tile's rows: their z-faces (the lending row has none to give)
-        double qz[7];
+        R qz[7];
 #pragma unroll
         for (int t = 0; t < 7; ++t) qz[t] = q[c + (reflc(k + t - 3) - k) * P];
-        const double Fz0 = a.Fw[c], Fz1 = a.Fw[c + P];
-        const double not_bot = (double)(k > 0), not_top = (double)(k < nz - 1);
+        const R Fz0 = a.Fw[c], Fz1 = a.Fw[c + P];
+        const R not_bot = (R)(k > 0), not_top = (R)(k < nz - 1);
         rq = a.rqn[o];
         fz0 = Fz0 * face(qz, 0, sign_of(Fz0), a.ov) * not_bot;
         fz1 = Fz1 * face(qz, 1, sign_of(Fz1), a.ov) * not_top;
     }
     __syncthreads();
     if (!own || !lend) return;
-    const double fx1 = fxs[row][lane + 1], fy1 = fys[row + 1][lane];
-    const double div = (fx1 - fx0) * a.idx + (fy1 - fy0) * a.idy + (fz1 - fz0) * a.idz[k];
+    const R fx1 = fxs[row][lane + 1], fy1 = fys[row + 1][lane];
+    const R div = (fx1 - fx0) * (R)a.idx + (fy1 - fy0) * (R)a.idy + (fz1 - fz0) * (R)a.idz[k];
     // read by later launches only (and rqn[o], its only other use, is read above)
-    st_stream(a.out + o, (T)(rq - a.dts * div));
+    st_stream(a.out + o, (T)(rq - (R)a.dts * div));
 }
 
 }  // namespace

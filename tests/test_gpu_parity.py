@@ -317,3 +317,27 @@ def test_full_size_rk3_step_sampled_columns():
         gg = {f: gw[f][sl] for f in ("rho", "rt", "ru", "rv", "rw")}
         full = dict(ref)
         _compare(f"full-size column ({i0},{j0})", _pert(gg, bo), _pert(ref, bo), CALL_TOL, full=full)
+
+
+def test_budget_sums_are_compensated():
+    """The FP64 mass sum keeps contributions below one ulp of its partial
+    sums.  Unit cells hold rho = 1 except +2^53 and -2^53 in the first two
+    (each thread of the reduction sums four cells, the first thread 2^53 and
+    three ones): the total is exactly the number of cells minus two, which a
+    plain sum misses by the three ones that vanish against 2^53."""
+    erf = _erf()
+    cfg = W.small(nx=64, ny=64, nz=256, dx=1.0, dy=1.0, dz=W.uniform_dz(256, 1.0))
+    s = erf.Solver(cfg)
+    th0 = np.full(cfg.nz, 300.0)
+    s.init_base_state(th0)
+    n = cfg.nx * cfg.ny * cfg.nz
+    rho = np.ones((cfg.nz, cfg.ny, cfg.nx))
+    rho.flat[0] = 2.0 ** 53
+    rho.flat[1] = -(2.0 ** 53)
+    S = {"rho": rho, "rt": 300.0 * rho, "ru": np.zeros_like(rho), "rv": np.zeros_like(rho),
+         "rw": np.zeros((cfg.nz + 1, cfg.ny, cfg.nx)), "rq": np.zeros((0, cfg.nz, cfg.ny, cfg.nx))}
+    d = s.diagnostics(s.to_device(S))
+    _say("compensated mass", d["mass"], "exact", n - 2)
+    assert d["mass"] == float(n - 2)
+    assert d["theta_mass"] == 300.0 * (n - 2)
+    s.close()
