@@ -291,15 +291,12 @@ def run_training(steps: int, batches=(16384, 262144)):
             "flop_per_sample": TRAIN_FLOP_PER_SAMPLE, "peak_tflops": BF16_PEAK_TFLOPS, "batches": out}
 
 
-def run_ensemble(steps: int, warmup: int, per_size: int = 16):
-    """The 48-member ensemble (16 each of 96x96x64, 128x128x64, 192x192x96 at
-    40 m, FP32, odd members on the learned closure): member steps one after
-    another on one stream against one graph launch per ensemble step with the
-    autotuned branch count."""
+def _ensemble_leg(cfgs, steps: int, warmup: int):
+    """Member steps one after another on one stream, then the ensemble's graph
+    launches in the autotuned mode (batched or not, branch count)."""
     import torch
     from paper_2412_04395_amd import erf
 
-    cfgs = W.ensemble(per_size=per_size)
     ens = erf.Ensemble(cfgs)
     states, weights = [], None
     for s, c in zip(ens.members, cfgs):
@@ -310,7 +307,6 @@ def run_ensemble(steps: int, warmup: int, per_size: int = 16):
             weights = closure_weights(s, S, c.seed)
         states.append(S)
     cells = sum(c.cells for c in cfgs)
-    # members one after another, ordinary launches on one stream
     for _ in range(warmup):
         for s, S in zip(ens.members, states):
             s.rk3_step(S)
@@ -322,6 +318,7 @@ def run_ensemble(steps: int, warmup: int, per_size: int = 16):
     torch.cuda.synchronize()
     el_seq = time.perf_counter() - t0
     nb, tune_ms = ens.autotune(states, trials=2)
+    mode = f"{'batched' if ens.batched else 'unbatched'}, {nb} branches"
     for _ in range(warmup):
         ens.rk3_step(states)
     torch.cuda.synchronize()
@@ -332,11 +329,29 @@ def run_ensemble(steps: int, warmup: int, per_size: int = 16):
     el = time.perf_counter() - t0
     bad = sum(s.diagnostics(S, allow_nonfinite=True)["nonfinite"] for s, S in zip(ens.members, states))
     ens.close()
-    return {"workload": f"ensemble of {len(cfgs)} boundary-layer members", "members": len(cfgs), "cells": cells,
-            "precision": "FP32 storage; odd members BF16 closure", "weights": weights,
-            "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": 1e3 * el / steps,
-            "branches": nb, "sequential_ms_per_step": 1e3 * el_seq / steps, "speedup_vs_sequential": el_seq / el,
-            "nonfinite": bad}
+    del states
+    torch.cuda.empty_cache()
+    return {"value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": 1e3 * el / steps,
+            "mode": mode, "weights": weights,
+            "sequential_ms_per_step": 1e3 * el_seq / steps, "speedup_vs_sequential": el_seq / el,
+            "nonfinite": bad}, cells
+
+
+def run_ensemble(steps: int, warmup: int, per_size: int = 16):
+    """The 48-member ensemble (16 each of 96x96x64, 128x128x64, 192x192x96 at
+    40 m, FP32 path, odd members on the learned closure) and the same 48 grids
+    as FP64 members on Smagorinsky (the reference the FP32 + closure ensemble is
+    compared with): member steps one after another on one stream against one
+    graph launch per ensemble step in the autotuned mode."""
+    cfgs = W.ensemble(per_size=per_size)
+    out, cells = _ensemble_leg(cfgs, steps, warmup)
+    ref, _ = _ensemble_leg([c.replace(prec="fp64", sgs=1) for c in cfgs], steps, warmup)
+    out.update({"workload": f"ensemble of {len(cfgs)} boundary-layer members", "members": len(cfgs),
+                "cells": cells, "precision": "FP32 storage and bulk arithmetic; odd members BF16 closure",
+                "fp64_smagorinsky": {k: ref[k] for k in ("value", "ms_per_step", "mode", "sequential_ms_per_step",
+                                                         "speedup_vs_sequential", "nonfinite")},
+                "ratio_vs_fp64_smagorinsky": out["value"] / ref["value"]})
+    return out
 
 
 def _omp_threads(n=None):

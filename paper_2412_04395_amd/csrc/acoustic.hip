@@ -79,12 +79,12 @@ struct StageArgs {
 };
 
 template <typename T, bool kZero, bool kMoist>
-__global__ __launch_bounds__(256) void k_stage_init(StageArgs<T> a)
+__device__ __forceinline__ void k_stage_init_body(StageArgs<T> a, VBlock vb)
 {
     const Dims &d = a.d;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y * blockDim.y + threadIdx.y;
-    int k = blockIdx.z;  // 0..nz (the extra plane handles the top z-face)
+    int i = vb.x * blockDim.x + threadIdx.x;
+    int j = vb.y * blockDim.y + threadIdx.y;
+    int k = vb.z;  // 0..nz (the extra plane handles the top z-face)
     if (i >= d.nx || j >= d.ny) return;
     int c = cidx(d, i, j, k);
     // every value is read and written once: streaming accesses throughout
@@ -140,6 +140,18 @@ __global__ __launch_bounds__(256) void k_stage_init(StageArgs<T> a)
         st_stream(a.sv + c, (T)0);
     }
 }
+template <typename T, bool kZero, bool kMoist>
+__global__ __launch_bounds__(256) void k_stage_init(StageArgs<T> a)
+{
+    k_stage_init_body<T, kZero, kMoist>(a, hw_block());
+}
+template <typename T, bool kZero, bool kMoist>
+__global__ __launch_bounds__(256) void k_stage_init_batch(const StageArgs<T> *args, BatchMap bm)
+{
+    int m;
+    VBlock vb;
+    if (batch_block(bm, m, vb)) k_stage_init_body<T, kZero, kMoist>(args[m], vb);
+}
 
 // Off-diagonal entries of the W'' row on face k (1 <= k <= nz - 1): lo
 // multiplies W''_{k-1}, up multiplies W''_{k+1}.  A = gamma R_d pi^t and C on
@@ -165,11 +177,11 @@ __device__ __forceinline__ void w_row_offdiag(double D, double g, double A, doub
 // the moist Exner function, the base state's total density and the face mean
 // of rho_d / rho_m (App. C with the moist equation of state).
 template <typename T, bool kMoist>
-__global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
+__device__ __forceinline__ void k_coef_body(StageArgs<T> a, VBlock vb)
 {
     const Dims &d = a.d;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y * blockDim.y + threadIdx.y;
+    int i = vb.x * blockDim.x + threadIdx.x;
+    int j = vb.y * blockDim.y + threadIdx.y;
     if (i >= d.nx || j >= d.ny) return;
     const int col = j * d.nx + i, nxy = d.nxy, nz = d.nz;
     const double D = a.dtau * a.dtau * a.b2 * a.b2, g = a.g;
@@ -227,6 +239,18 @@ __global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
             cprev = up * m;
         }
     }
+}
+template <typename T, bool kMoist>
+__global__ __launch_bounds__(256) void k_coef(StageArgs<T> a)
+{
+    k_coef_body<T, kMoist>(a, hw_block());
+}
+template <typename T, bool kMoist>
+__global__ __launch_bounds__(256) void k_coef_batch(const StageArgs<T> *args, BatchMap bm)
+{
+    int m;
+    VBlock vb;
+    if (batch_block(bm, m, vb)) k_coef_body<T, kMoist>(args[m], vb);
 }
 
 // Phase 1 of a substep on one wavefront's levels of one column: U'', V'' with
@@ -364,7 +388,7 @@ __device__ __forceinline__ void substep_explicit(
 // wavefront; dynamic LDS holds the (nz + 1) x 64 solve buffer and the
 // chunk-boundary values.
 template <typename T, int kLevels, bool kLast, bool kZero, bool kSums>
-__global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
+__device__ __forceinline__ void k_substep_body(StageArgs<T> a, VBlock vb)
 {
     extern __shared__ double lds[];
     const Dims &d = a.d;
@@ -377,7 +401,7 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
     double *bnd = lds + (nz + 1) * kLanes;  // [KG][2][64]
     double *thl = bnd + 2 * blockDim.y * kLanes;  // [nz][64] when kLevels <= 8
 
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = xcd_remap(vb.x, vb.gx);
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int i = tx * a.TX + lane % a.TX, j = ty * a.TY + lane / a.TX;
     const bool act = (i < d.nx) && (j < d.ny);
@@ -579,6 +603,18 @@ __global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
         }
     }
 }
+template <typename T, int kLevels, bool kLast, bool kZero, bool kSums>
+__global__ __launch_bounds__(1024) void k_substep(StageArgs<T> a)
+{
+    k_substep_body<T, kLevels, kLast, kZero, kSums>(a, hw_block());
+}
+template <typename T, int kLevels, bool kLast, bool kZero, bool kSums>
+__global__ __launch_bounds__(1024) void k_substep_batch(const StageArgs<T> *args, BatchMap bm)
+{
+    int m;
+    VBlock vb;
+    if (batch_block(bm, m, vb)) k_substep_body<T, kLevels, kLast, kZero, kSums>(args[m], vb);
+}
 
 template <typename T>
 struct FinArgs {
@@ -596,12 +632,12 @@ struct FinArgs {
 // In both storages S^t and S'' are added as stored: full + perturbation in FP64,
 // perturbation about the base state + perturbation in FP32.
 template <typename T>
-__global__ __launch_bounds__(256) void k_finalize(FinArgs<T> a)
+__device__ __forceinline__ void k_finalize_body(FinArgs<T> a, VBlock vb)
 {
     const Dims &d = a.d;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y * blockDim.y + threadIdx.y;
-    int k = blockIdx.z;
+    int i = vb.x * blockDim.x + threadIdx.x;
+    int j = vb.y * blockDim.y + threadIdx.y;
+    int k = vb.z;
     if (i >= d.nx || j >= d.ny) return;
     int c = cidx(d, i, j, k);
     // every value is read and written once: streaming accesses throughout
@@ -621,6 +657,18 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs<T> a)
     if (a.Fu) st_stream(a.Fu + c, (T)(ut + (double)ld_stream(a.su + c) * inv));
     if (a.Fv) st_stream(a.Fv + c, (T)(vt + (double)ld_stream(a.sv + c) * inv));
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_finalize(FinArgs<T> a)
+{
+    k_finalize_body<T>(a, hw_block());
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_finalize_batch(const FinArgs<T> *args, BatchMap bm)
+{
+    int m;
+    VBlock vb;
+    if (batch_block(bm, m, vb)) k_finalize_body<T>(args[m], vb);
+}
 
 }  // namespace
 
@@ -628,22 +676,28 @@ namespace {
 // one substep launch: the instance for the level count, the stage end, a zero
 // S'' on entry and the flux sums (never together with the stage end: the sums
 // keep a separate finalize)
+template <typename T, int L, bool kLast, bool kZero, bool kSums>
+void substep_one(erf_ctx *cx, dim3 grid, dim3 block, size_t lds, const StageArgs<T> &a)
+{
+    run<StageArgs<T>, k_substep<T, L, kLast, kZero, kSums>, k_substep_batch<T, L, kLast, kZero, kSums>>(cx, grid, block,
+                                                                                                       lds, a);
+}
 template <typename T, int L>
-void launch_substep(bool last, bool zero, bool sums, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+void launch_substep(erf_ctx *cx, bool last, bool zero, bool sums, dim3 grid, dim3 block, size_t lds,
                     const StageArgs<T> &a)
 {
     if (last && zero)
-        hipLaunchKernelGGL((k_substep<T, L, true, true, false>), grid, block, lds, st, a);
+        substep_one<T, L, true, true, false>(cx, grid, block, lds, a);
     else if (last)
-        hipLaunchKernelGGL((k_substep<T, L, true, false, false>), grid, block, lds, st, a);
+        substep_one<T, L, true, false, false>(cx, grid, block, lds, a);
     else if (sums && zero)
-        hipLaunchKernelGGL((k_substep<T, L, false, true, true>), grid, block, lds, st, a);
+        substep_one<T, L, false, true, true>(cx, grid, block, lds, a);
     else if (sums)
-        hipLaunchKernelGGL((k_substep<T, L, false, false, true>), grid, block, lds, st, a);
+        substep_one<T, L, false, false, true>(cx, grid, block, lds, a);
     else if (zero)
-        hipLaunchKernelGGL((k_substep<T, L, false, true, false>), grid, block, lds, st, a);
+        substep_one<T, L, false, true, false>(cx, grid, block, lds, a);
     else
-        hipLaunchKernelGGL((k_substep<T, L, false, false, false>), grid, block, lds, st, a);
+        substep_one<T, L, false, false, false>(cx, grid, block, lds, a);
 }
 
 template <typename T, int L>
@@ -748,19 +802,19 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
     dim3 g2((d.nx + 63) / 64, (d.ny + 3) / 4, 1);
     timing_start(cx, K_STAGE_INIT);
     if (zero && moist)
-        hipLaunchKernelGGL((k_stage_init<T, true, true>), g3w, blk, 0, cx->stream, a);
+        run<StageArgs<T>, k_stage_init<T, true, true>, k_stage_init_batch<T, true, true>>(cx, g3w, blk, 0, a);
     else if (zero)
-        hipLaunchKernelGGL((k_stage_init<T, true, false>), g3w, blk, 0, cx->stream, a);
+        run<StageArgs<T>, k_stage_init<T, true, false>, k_stage_init_batch<T, true, false>>(cx, g3w, blk, 0, a);
     else if (moist)
-        hipLaunchKernelGGL((k_stage_init<T, false, true>), g3w, blk, 0, cx->stream, a);
+        run<StageArgs<T>, k_stage_init<T, false, true>, k_stage_init_batch<T, false, true>>(cx, g3w, blk, 0, a);
     else
-        hipLaunchKernelGGL((k_stage_init<T, false, false>), g3w, blk, 0, cx->stream, a);
+        run<StageArgs<T>, k_stage_init<T, false, false>, k_stage_init_batch<T, false, false>>(cx, g3w, blk, 0, a);
     timing_stop(cx, K_STAGE_INIT);
     timing_start(cx, K_COEF);
     if (moist)
-        hipLaunchKernelGGL((k_coef<T, true>), g2, blk, 0, cx->stream, a);
+        run<StageArgs<T>, k_coef<T, true>, k_coef_batch<T, true>>(cx, g2, blk, 0, a);
     else
-        hipLaunchKernelGGL((k_coef<T, false>), g2, blk, 0, cx->stream, a);
+        run<StageArgs<T>, k_coef<T, false>, k_coef_batch<T, false>>(cx, g2, blk, 0, a);
     timing_stop(cx, K_COEF);
     for (int s = 0; s < n_sub; ++s) {
         const int t_nxt = 3 - t_cur - t_prv;
@@ -780,9 +834,9 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
         const dim3 grid(a.ntx * a.nty), block(kLanes, KG);
         timing_start(cx, K_SUBSTEP);
         if (L == 8)
-            launch_substep<T, 8>(last, zero && s == 0, a.sums != 0, grid, block, lds, cx->stream, a);
+            launch_substep<T, 8>(cx, last, zero && s == 0, a.sums != 0, grid, block, lds, a);
         else
-            launch_substep<T, 16>(last, zero && s == 0, a.sums != 0, grid, block, lds, cx->stream, a);
+            launch_substep<T, 16>(cx, last, zero && s == 0, a.sums != 0, grid, block, lds, a);
         timing_stop(cx, K_SUBSTEP);
         t_prv = t_cur;
         t_cur = t_nxt;
@@ -798,7 +852,9 @@ hipError_t acoustic_t(erf_ctx *cx, const void *const Sn_[5], const void *const S
     f.su = (T *)w.su; f.sv = (T *)w.sv; f.sw = (T *)w.sw;
     f.o_r = Sout[0]; f.o_t = Sout[1]; f.o_u = Sout[2]; f.o_v = Sout[3]; f.o_w = Sout[4];
     f.Fu = Fu; f.Fv = Fv; f.Fw = Fw;
-    timing_start(cx, K_FINALIZE); hipLaunchKernelGGL(k_finalize<T>, g3w, blk, 0, cx->stream, f); timing_stop(cx, K_FINALIZE);
+    timing_start(cx, K_FINALIZE);
+    run<FinArgs<T>, k_finalize<T>, k_finalize_batch<T>>(cx, g3w, blk, 0, f);
+    timing_stop(cx, K_FINALIZE);
     return hipGetLastError();
 }
 }  // namespace

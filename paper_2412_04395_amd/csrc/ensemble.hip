@@ -1,5 +1,9 @@
 // ensemble.hip -- batched RK3 steps of independent members (include/erf_ensemble.h):
 // one HIP graph per ensemble step, members spread over forked branch streams.
+// Batched mode (the default): every member's step is recorded once, launch by
+// launch, and on each branch the k-th launches of its members that run the
+// same kernel instance with the same block shape become one launch over a
+// (member, block) work list.  Unbatched mode: the members' own launches.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -24,6 +28,20 @@ struct erf_ens {
     std::vector<erf_state> captured;  // state pointers the graph was captured with
     erf_status sticky = ERF_OK;
     std::string err;
+    // batched mode: the launch list of the captured step and the device buffer
+    // holding its argument structures and block maps
+    int batched = 1;
+    struct Batch {
+        erfk::BatchFn fn;
+        dim3 block;
+        size_t lds;
+        int n, blocks;
+        size_t args_off, map_off;
+        int branch;
+    };
+    std::vector<Batch> plan;
+    void *plan_dev = nullptr;
+    size_t plan_cap = 0;
 };
 
 namespace {
@@ -75,8 +93,135 @@ bool same_states(const std::vector<erf_state> &a, const erf_state *b, size_t n)
     return std::memcmp(a.data(), b, n * sizeof(erf_state)) == 0;
 }
 
+// Record every member's step, group the k-th launches of the members by
+// kernel instance, block shape and LDS, and upload the argument structures and
+// block maps of the resulting batched launches.
+erf_status build_plan(erf_ens *e, const erf_state *states)
+{
+    const int n = (int)e->members.size();
+    std::vector<erfk::Recorder> rec(n);
+    size_t maxlen = 0;
+    for (int m = 0; m < n; ++m) {
+        erf_state s = states[m];
+        e->members[m]->rec = &rec[m];
+        const erf_status st = erf_rk3_step(e->members[m], &s);
+        e->members[m]->rec = nullptr;
+        if (st != ERF_OK) return efail(e, st, std::string("member ") + std::to_string(m) + ": " +
+                                                  erf_last_error(e->members[m]));
+        maxlen = std::max(maxlen, rec[m].recs.size());
+    }
+    std::vector<unsigned char> hb;
+    auto align = [&](size_t a) { hb.resize((hb.size() + a - 1) / a * a); };
+    e->plan.clear();
+    std::vector<char> used(n);
+    for (int br = 0; br < e->n_branches; ++br)
+    for (size_t p = 0; p < maxlen; ++p) {
+        // members of other branches count as used: batches stay within a branch
+        for (int m = 0; m < n; ++m) used[m] = e->branch_of[m] != br;
+        for (int m = 0; m < n; ++m) {
+            if (used[m] || p >= rec[m].recs.size()) continue;
+            const erfk::LaunchRec &r0 = rec[m].recs[p];
+            std::vector<int> grp;
+            for (int q = m; q < n; ++q) {
+                if (used[q] || p >= rec[q].recs.size()) continue;
+                const erfk::LaunchRec &r = rec[q].recs[p];
+                if (r.fn == r0.fn && r.block.x == r0.block.x && r.block.y == r0.block.y &&
+                    r.block.z == r0.block.z && r.lds == r0.lds && r.args.size() == r0.args.size()) {
+                    grp.push_back(q);
+                    used[q] = 1;
+                }
+            }
+            erf_ens::Batch b{r0.fn, r0.block, r0.lds, (int)grp.size(), 0, 0, 0, br};
+            align(256);
+            b.args_off = hb.size();
+            for (int q : grp) hb.insert(hb.end(), rec[q].recs[p].args.begin(), rec[q].recs[p].args.end());
+            align(256);
+            b.map_off = hb.size();
+            std::vector<int> first(grp.size() + 1), grid(3 * grp.size());
+            int64_t tot = 0;
+            for (size_t g = 0; g < grp.size(); ++g) {
+                const erfk::LaunchRec &r = rec[grp[g]].recs[p];
+                first[g] = (int)tot;
+                grid[3 * g] = (int)r.grid.x;
+                grid[3 * g + 1] = (int)r.grid.y;
+                grid[3 * g + 2] = (int)r.grid.z;
+                const int64_t nb = (int64_t)r.grid.x * r.grid.y * r.grid.z;
+                tot += (nb + 7) / 8 * 8;  // each range starts on a multiple of 8
+            }
+            if (tot >= ((int64_t)1 << 31)) return efail(e, ERF_E_SHAPE, "batched launch too large");
+            first[grp.size()] = (int)tot;
+            b.blocks = (int)tot;
+            const unsigned char *pf = (const unsigned char *)first.data(), *pg = (const unsigned char *)grid.data();
+            hb.insert(hb.end(), pf, pf + first.size() * sizeof(int));
+            hb.insert(hb.end(), pg, pg + grid.size() * sizeof(int));
+            e->plan.push_back(b);
+        }
+    }
+    hipError_t h = hipSuccess;
+    if (hb.size() > e->plan_cap) {
+        // a buffer an earlier graph still reads is freed only once that graph is done
+        h = hipStreamSynchronize(e->main);
+        if (h == hipSuccess && e->plan_dev) h = hipFree(e->plan_dev);
+        e->plan_dev = nullptr;
+        e->plan_cap = 0;
+        if (h == hipSuccess) h = hipMalloc(&e->plan_dev, hb.size());
+        if (h != hipSuccess) {
+            (void)hipGetLastError();
+            e->plan_dev = nullptr;
+            return efail(e, ERF_E_NOMEM, "ensemble launch list allocation failed");
+        }
+        e->plan_cap = hb.size();
+    } else {
+        h = hipStreamSynchronize(e->main);
+    }
+    if (h == hipSuccess && !hb.empty()) h = hipMemcpy(e->plan_dev, hb.data(), hb.size(), hipMemcpyHostToDevice);
+    for (const erf_ens::Batch &b : e->plan)
+        if (h == hipSuccess) h = b.fn(nullptr, erfk::BatchMap{}, 0, b.block, b.lds, nullptr, true);
+    return h == hipSuccess ? ERF_OK : ehip(e, h, "uploading the ensemble launch list");
+}
+
+erf_status capture_batched(erf_ens *e, const erf_state *states)
+{
+    drop_graph(e);
+    erf_status st = build_plan(e, states);
+    if (st != ERF_OK) return st;
+    hipError_t h = hipStreamBeginCapture(e->main, hipStreamCaptureModeThreadLocal);
+    if (h != hipSuccess) return ehip(e, h, "begin capture");
+    char *base = (char *)e->plan_dev;
+    // each branch's batched launches on its own stream, forked from and joined
+    // back to the capture stream
+    h = hipEventRecord(e->fork, e->main);
+    for (int b = 0; h == hipSuccess && b < e->n_branches; ++b) h = hipStreamWaitEvent(e->branch[b], e->fork, 0);
+    for (const erf_ens::Batch &b : e->plan) {
+        if (h != hipSuccess) break;
+        const int *first = (const int *)(base + b.map_off);
+        erfk::BatchMap map{first, first + b.n + 1, b.n};
+        h = b.fn(base + b.args_off, map, b.blocks, b.block, b.lds, e->branch[b.branch], false);
+    }
+    for (int b = 0; h == hipSuccess && b < e->n_branches; ++b) {
+        h = hipEventRecord(e->join[b], e->branch[b]);
+        if (h == hipSuccess) h = hipStreamWaitEvent(e->main, e->join[b], 0);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t he = hipStreamEndCapture(e->main, &g);
+    if (h != hipSuccess || he != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return ehip(e, h != hipSuccess ? h : he, "capturing the batched ensemble step");
+    }
+    e->graph = g;
+    h = hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0);
+    if (h != hipSuccess) {
+        e->exec = nullptr;
+        drop_graph(e);
+        return ehip(e, h, "instantiating the batched ensemble graph");
+    }
+    e->captured.assign(states, states + e->members.size());
+    return ERF_OK;
+}
+
 erf_status capture(erf_ens *e, const erf_state *states)
 {
+    if (e->batched) return capture_batched(e, states);
     drop_graph(e);
     const int n = (int)e->members.size();
     hipError_t h = hipStreamBeginCapture(e->main, hipStreamCaptureModeThreadLocal);
@@ -172,6 +317,7 @@ void erf_ensemble_destroy(erf_ens *e)
     if (e->fork) (void)hipEventDestroy(e->fork);
     if (e->done) (void)hipEventDestroy(e->done);
     if (e->main) (void)hipStreamDestroy(e->main);
+    if (e->plan_dev) (void)hipFree(e->plan_dev);
     delete e;
 }
 
@@ -198,6 +344,20 @@ erf_status erf_ensemble_set_branches(erf_ens *e, int32_t nb)
 }
 
 int32_t erf_ensemble_branches(const erf_ens *e) { return e ? e->n_branches : 0; }
+
+erf_status erf_ensemble_set_batched(erf_ens *e, int32_t on)
+{
+    if (!e) return ERF_E_ARG;
+    if (e->sticky != ERF_OK) return e->sticky;
+    if (on != 0 && on != 1) return efail(e, ERF_E_ARG, "batched must be 0 or 1");
+    hipError_t h = hipStreamSynchronize(e->main);
+    if (h != hipSuccess) return ehip(e, h, "draining the ensemble stream");
+    drop_graph(e);
+    e->batched = on;
+    return ERF_OK;
+}
+
+int32_t erf_ensemble_batched(const erf_ens *e) { return e ? e->batched : 0; }
 
 erf_status erf_ensemble_rk3_step(erf_ens *e, const erf_state *states)
 {
@@ -226,12 +386,15 @@ erf_status erf_ensemble_autotune(erf_ens *e, const erf_state *states, int32_t tr
     hipError_t h = hipEventCreate(&t0);
     if (h == hipSuccess) h = hipEventCreate(&t1);
     if (h != hipSuccess) return ehip(e, h, "timing events");
-    int best = e->n_branches;
+    int best = e->n_branches, best_batched = e->batched;
     double best_t = 1e300;
     erf_status st = ERF_OK;
+    // batched and unbatched launches, each on 1, 2, 4, 8, 16 branch streams
     const int cands[] = {1, 2, 4, 8, 16};
+    for (int bat = 1; bat >= 0 && st == ERF_OK; --bat)
     for (int nb : cands) {
-        if (nb > (int)e->members.size() && nb != 1) break;
+        if (nb > (int)e->members.size() && nb > 1) break;
+        if ((st = erf_ensemble_set_batched(e, bat)) != ERF_OK) break;
         if ((st = erf_ensemble_set_branches(e, nb)) != ERF_OK) break;
         if ((st = erf_ensemble_rk3_step(e, states)) != ERF_OK) break;  // capture + warm-up
         h = hipEventRecord(t0, e->main);
@@ -247,11 +410,13 @@ erf_status erf_ensemble_autotune(erf_ens *e, const erf_state *states, int32_t tr
         if (ms / trials < best_t) {
             best_t = ms / trials;
             best = nb;
+            best_batched = bat;
         }
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (st != ERF_OK) return st;
+    if ((st = erf_ensemble_set_batched(e, best_batched)) != ERF_OK) return st;
     if ((st = erf_ensemble_set_branches(e, best)) != ERF_OK) return st;
     if (best_branches) *best_branches = e->n_branches;
     if (best_ms) *best_ms = best_t;

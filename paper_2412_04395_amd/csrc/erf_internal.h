@@ -116,12 +116,58 @@ __device__ __forceinline__ void st_stream(T *p, T v)
     __builtin_nontemporal_store(v, p);
 }
 
+// ---------------------------------------------------------------------------
+// block geometry: the hardware's, or one context's share of a batched launch
+// ---------------------------------------------------------------------------
+// Kernel bodies read their block index and grid size from a VBlock.  A plain
+// launch passes the hardware values; a batched launch (one launch running one
+// kernel for the contexts of an ensemble) gives every context a contiguous
+// range of blocks and passes each block its index within its context's own
+// grid, so the body runs exactly as in the context's own launch.
+struct VBlock {
+    int x, y, z;     // block index in the context's grid
+    int gx, gy, gz;  // the context's grid
+};
+__device__ __forceinline__ VBlock hw_block()
+{
+    return {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, (int)gridDim.x, (int)gridDim.y, (int)gridDim.z};
+}
+
+// Block ranges of a batched launch (device arrays): context m owns launch
+// blocks [first[m], first[m + 1]); its own grid is grid[3m .. 3m + 2].  Ranges
+// start on multiples of 8 (each XCD then sees every context's blocks in the
+// round-robin order of a plain launch); blocks past a context's own grid are
+// padding and exit at once.
+struct BatchMap {
+    const int *first;
+    const int *grid;
+    int n;
+};
+__device__ __forceinline__ bool batch_block(const BatchMap &bm, int &m, VBlock &vb)
+{
+    const int b = blockIdx.x;
+    int lo = 0, hi = bm.n - 1;  // the last m with first[m] <= b (uniform: scalar loads)
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bm.first[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    m = lo;
+    const int gx = bm.grid[3 * m], gy = bm.grid[3 * m + 1], gz = bm.grid[3 * m + 2];
+    const int l = b - bm.first[m];
+    if (l >= gx * gy * gz) return false;
+    vb = {l % gx, (l / gx) % gy, l / (gx * gy), gx, gy, gz};
+    return true;
+}
+
 struct TileIdx {
     int i, j, k;
 };
-__device__ __forceinline__ TileIdx tile_cell(int ntx, int nty)
+__device__ __forceinline__ TileIdx tile_cell(VBlock vb, int ntx, int nty)
 {
-    const int nrow = ntx * nty, b = blockIdx.x;
+    const int nrow = ntx * nty, b = vb.x;
     int t = b;
     if (nrow % 8 == 0) {
         const int rows = nrow / 8, x = b % 8, m = b / 8;
@@ -301,6 +347,23 @@ struct Base {
 
 }  // namespace erfk
 
+namespace erfk {
+// A kernel launch recorded instead of enqueued (for a batched ensemble step):
+// the batched instance of the kernel, the context's own grid and block, the
+// dynamic LDS, and the bytes of the argument structure.
+using BatchFn = hipError_t (*)(const void *args, BatchMap map, int blocks, dim3 block, size_t lds, hipStream_t st,
+                               bool prepare);
+struct LaunchRec {
+    BatchFn fn;
+    dim3 grid, block;
+    size_t lds;
+    std::vector<unsigned char> args;
+};
+struct Recorder {
+    std::vector<LaunchRec> recs;
+};
+}  // namespace erfk
+
 struct erf_ctx {
     erf_grid grid{};
     erf_params prm{};
@@ -318,6 +381,9 @@ struct erf_ctx {
     void *arena = nullptr;  // the single device allocation behind the workspace
     // acoustic substep launch shape chosen by erf_autotune (0: the default rule)
     int tune_levels = 0, tune_rows = 0;
+    // while set, launches are recorded here instead of enqueued (the batched
+    // ensemble step records each member's step once, then replays batches)
+    erfk::Recorder *rec = nullptr;
     // kernel timing (erf_timing_begin / erf_timing_end)
     int timed_kernel = -1;
     int timed_count = 0;
@@ -335,14 +401,50 @@ inline const char *kernel_name(int id)
                                          "finalize", "mixing_ratio", "scalar", "mlp", "mlp_div"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
+// The batched instance KB of a kernel, launched over the block ranges of map
+// (prepare: only allow its dynamic LDS, before a graph capture).
+template <typename Args, void (*KB)(const Args *, BatchMap)>
+hipError_t batch_launch(const void *args, BatchMap map, int blocks, dim3 block, size_t lds, hipStream_t st,
+                        bool prepare)
+{
+    if (prepare)
+        return lds > 65536 ? hipFuncSetAttribute((const void *)KB, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+                           : hipSuccess;
+    const Args *ap = (const Args *)args;
+    void *argv[] = {(void *)&ap, (void *)&map};
+    return hipLaunchKernel((const void *)KB, dim3(blocks), block, argv, lds, st);
+}
+// record one launch of a recording context
+template <typename Args>
+void record(erf_ctx *c, BatchFn fn, dim3 grid, dim3 block, size_t lds, const Args &a)
+{
+    LaunchRec r{fn, grid, block, lds, {}};
+    r.args.assign((const unsigned char *)&a, (const unsigned char *)&a + sizeof(Args));
+    c->rec->recs.push_back(std::move(r));
+}
+// Enqueue kernel K on the context's stream, or, while the context records,
+// record the launch with KB, K's batched instance.
+template <typename Args, void (*K)(Args), void (*KB)(const Args *, BatchMap)>
+void run(erf_ctx *c, dim3 grid, dim3 block, size_t lds, const Args &a)
+{
+    if (c->rec) {
+        record(c, &batch_launch<Args, KB>, grid, block, lds, a);
+        return;
+    }
+    void *argv[] = {(void *)&a};
+    (void)hipLaunchKernel((const void *)K, grid, block, argv, lds, c->stream);
+}
+
 // bracket a launch with events when its kernel is being timed
 inline void timing_start(erf_ctx *c, int id)
 {
+    if (c->rec) return;
     if (c->timed_kernel == id && 2 * c->timed_count + 1 < (int)c->timing_events.size())
         (void)hipEventRecord(c->timing_events[2 * c->timed_count], c->stream);
 }
 inline void timing_stop(erf_ctx *c, int id)
 {
+    if (c->rec) return;
     if (c->timed_kernel == id && 2 * c->timed_count + 1 < (int)c->timing_events.size()) {
         (void)hipEventRecord(c->timing_events[2 * c->timed_count + 1], c->stream);
         ++c->timed_count;

@@ -363,7 +363,7 @@ constexpr int kClosureMaxBlocks = 512;
 // grid): inputs in FP64 into LDS as BF16, the network on four groups of 16,
 // then per cell the de-standardised stresses, the fallback test and rho tau.
 template <typename T>
-__global__ __launch_bounds__(kClosureBlock, 4) void k_mlp_closure(ClosureArgs<T> a)
+__device__ __forceinline__ void k_mlp_closure_body(ClosureArgs<T> a, VBlock vb)
 {
     __shared__ u32x4 wl[22 * 64];
     __shared__ u32x4 xs_all[kClosureBlock / 64][128];
@@ -379,9 +379,9 @@ __global__ __launch_bounds__(kClosureBlock, 4) void k_mlp_closure(ClosureArgs<T>
     float *ys = ys_all[wave];
     const Dims &d = a.in.d;
     __syncthreads();
-    const int64_t stride = (int64_t)gridDim.x * kClosureBlock;
+    const int64_t stride = (int64_t)vb.gx * kClosureBlock;
     unsigned int nfb = 0;  // fallback cells of this wavefront
-    for (int64_t base = (int64_t)blockIdx.x * kClosureBlock + wave * 64; base < d.n; base += stride) {
+    for (int64_t base = (int64_t)vb.x * kClosureBlock + wave * 64; base < d.n; base += stride) {
         const int c = (int)base + lane;
         const bool valid = c < d.n;
         double f[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, dthx = 0.0, dthy = 0.0, r = 0.0;
@@ -444,8 +444,20 @@ __global__ __launch_bounds__(kClosureBlock, 4) void k_mlp_closure(ClosureArgs<T>
     if (threadIdx.x == 0) {
         unsigned long long sum = 0;
         for (int w = 0; w < kClosureBlock / 64; ++w) sum += wcount[w];
-        a.fallbacks[blockIdx.x] += sum;
+        a.fallbacks[vb.x] += sum;
     }
+}
+template <typename T>
+__global__ __launch_bounds__(kClosureBlock, 4) void k_mlp_closure(ClosureArgs<T> a)
+{
+    k_mlp_closure_body<T>(a, hw_block());
+}
+template <typename T>
+__global__ __launch_bounds__(kClosureBlock, 4) void k_mlp_closure_batch(const ClosureArgs<T> *args, BatchMap bm)
+{
+    int m;
+    VBlock vb;
+    if (batch_block(bm, m, vb)) k_mlp_closure_body<T>(args[m], vb);
 }
 
 // ---------------------------------------------------------------------------
@@ -469,10 +481,10 @@ struct DivArgs {
 // the compiler splits the loads into dependent groups.  The tendencies are
 // read by later launches only: streaming stores.
 template <typename T>
-__global__ __launch_bounds__(256) void k_mlp_div(DivArgs<T> a)
+__device__ __forceinline__ void k_mlp_div_body(DivArgs<T> a, VBlock vb)
 {
     const Dims &d = a.d;
-    const TileIdx tc = tile_cell(a.ntx, a.nty);
+    const TileIdx tc = tile_cell(vb, a.ntx, a.nty);
     const int i = tc.i, j = tc.j, k = tc.k;
     if (i >= d.nx || j >= d.ny) return;
     const int nz = d.nz, nx = d.nx, P = d.nxy;
@@ -520,6 +532,18 @@ __global__ __launch_bounds__(256) void k_mlp_div(DivArgs<T> a)
     st_stream(a.Rv + c, (T)(Rv - dv));
     if (k > 0) st_stream(a.Rw + c, (T)(Rw - dw));  // the bottom lid face keeps its tendency
     st_stream(a.Rt + c, (T)(Rt - ((hx1 - hx0) * a.idx + (hy1 - hy0) * a.idy + (hz1 - hz0) * idz)));
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_mlp_div(DivArgs<T> a)
+{
+    k_mlp_div_body<T>(a, hw_block());
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_mlp_div_batch(const DivArgs<T> *args, BatchMap bm)
+{
+    int m;
+    VBlock vb;
+    if (batch_block(bm, m, vb)) k_mlp_div_body<T>(args[m], vb);
 }
 
 // ---------------------------------------------------------------------------
@@ -950,8 +974,8 @@ hipError_t closure_t(erf_ctx *cx, const void *rho, void *const R[5])
     a.fallbacks = m.fallbacks;
     const Dims &d = cx->d;
     timing_start(cx, K_MLP);
-    hipLaunchKernelGGL(k_mlp_closure<T>, dim3(grid_for(d.n, kClosureBlock, kClosureMaxBlocks)),
-                       dim3(kClosureBlock), 0, cx->stream, a);
+    run<ClosureArgs<T>, k_mlp_closure<T>, k_mlp_closure_batch<T>>(
+        cx, dim3(grid_for(d.n, kClosureBlock, kClosureMaxBlocks)), dim3(kClosureBlock), 0, a);
     timing_stop(cx, K_MLP);
     DivArgs<T> v{};
     v.d = d;
@@ -968,7 +992,7 @@ hipError_t closure_t(erf_ctx *cx, const void *rho, void *const R[5])
     v.ntx = (d.nx + tx - 1) / tx;
     v.nty = (d.ny + ty - 1) / ty;
     timing_start(cx, K_MLP_DIV);
-    hipLaunchKernelGGL(k_mlp_div<T>, dim3(v.ntx * v.nty * d.nz), dim3(tx, ty, 1), 0, cx->stream, v);
+    run<DivArgs<T>, k_mlp_div<T>, k_mlp_div_batch<T>>(cx, dim3(v.ntx * v.nty * d.nz), dim3(tx, ty, 1), 0, v);
     timing_stop(cx, K_MLP_DIV);
     return hipGetLastError();
 }

@@ -59,11 +59,11 @@ __device__ __forceinline__ int cidx(const Dims &d, int i, int j, int k) { return
 // (bulk stencil arithmetic in FP32; base-state values enter rounded to float,
 // and only as the small differences between levels where they are subtracted).
 template <typename T, bool kMoist>
-__global__ __launch_bounds__(256) void k_prep(RhsArgs<T> a)
+__device__ __forceinline__ void k_prep_body(RhsArgs<T> a, VBlock vb)
 {
     using R = T;
     const Dims &d = a.d;
-    const TileIdx t = tile_cell(a.ntx, a.nty);
+    const TileIdx t = tile_cell(vb, a.ntx, a.nty);
     const int i = t.i, j = t.j, k = t.k;
     if (i >= d.nx || j >= d.ny) return;
     const int c = cidx(d, i, j, k);
@@ -111,6 +111,18 @@ __global__ __launch_bounds__(256) void k_prep(RhsArgs<T> a)
         st_stream(a.pp + c, (T)((R)p0k * expm1(R(kGamma) * log1p(Tp / (R)T0))));
     }
 }
+template <typename T, bool kMoist>
+__global__ __launch_bounds__(256) void k_prep(RhsArgs<T> a)
+{
+    k_prep_body<T, kMoist>(a, hw_block());
+}
+template <typename T, bool kMoist>
+__global__ __launch_bounds__(256) void k_prep_batch(const RhsArgs<T> *args, BatchMap bm)
+{
+    int m;
+    VBlock vb;
+    if (batch_block(bm, m, vb)) k_prep_body<T, kMoist>(args[m], vb);
+}
 
 // ---------------------------------------------------------------------------
 // strain rates and stresses (Sec. 2.3)
@@ -121,11 +133,11 @@ __global__ __launch_bounds__(256) void k_prep(RhsArgs<T> a)
 // edges drop out because 2/(dz_{k-1} + dz_k) is zero on the lids and w is zero
 // on the lid faces.
 template <typename T>
-__global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
+__device__ __forceinline__ void k_mut_body(RhsArgs<T> a, VBlock vb)
 {
     using R = T;
     const Dims &d = a.d;
-    const TileIdx t = tile_cell(a.ntx, a.nty);
+    const TileIdx t = tile_cell(vb, a.ntx, a.nty);
     const int i = t.i, j = t.j, k = t.k;
     if (i >= d.nx || j >= d.ny) return;
     const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.nxy;
@@ -159,6 +171,18 @@ __global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
     const R ss = R(2) * (e11 * e11 + e22 * e22 + e33 * e33) + R(4) * (a12 * a12 + a13 * a13 + a23 * a23);
     st_stream(a.mut + lk + rj + i, (T)(rc * (R)a.cs2[k] * sqrt(ss)));  // read by a later launch only
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
+{
+    k_mut_body<T>(a, hw_block());
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_mut_batch(const RhsArgs<T> *args, BatchMap bm)
+{
+    int m;
+    VBlock vb;
+    if (batch_block(bm, m, vb)) k_mut_body<T>(args[m], vb);
+}
 
 // Stresses tau = -2 mu (S - D) at their points, mu = rho nu_m + mu_t averaged
 // from the four cells around an edge; heat diffusivity rho alpha_m + mu_t/Pr_t.
@@ -166,11 +190,11 @@ __global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
 // (at most 4 wavefronts per SIMD: the register budget lets the scheduler issue
 // all 27 gathers at once instead of in two dependent groups)
 template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void k_stress(RhsArgs<T> a)
+__device__ __forceinline__ void k_stress_body(RhsArgs<T> a, VBlock vb)
 {
     using R = T;
     const Dims &d = a.d;
-    const TileIdx t = tile_cell(a.ntx, a.nty);
+    const TileIdx t = tile_cell(vb, a.ntx, a.nty);
     const int i = t.i, j = t.j, k = t.k;  // k = 0..nz: face k and, below the top, cell k
     if (i >= d.nx || j >= d.ny) return;
     const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.nxy;
@@ -225,6 +249,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
         st_stream(a.kap + c, (T)(rc * (R)a.alpha + (sgs ? mtc / (R)a.Pr_t : R(0))));
     }
 }
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void k_stress(RhsArgs<T> a)
+{
+    k_stress_body<T>(a, hw_block());
+}
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void k_stress_batch(const RhsArgs<T> *args, BatchMap bm)
+{
+    int m;
+    VBlock vb;
+    if (batch_block(bm, m, vb)) k_stress_body<T>(args[m], vb);
+}
 
 // ---------------------------------------------------------------------------
 // interpolants (Sec. 3.6), order fixed at compile time (O = 0: runtime order)
@@ -258,11 +294,11 @@ __device__ __forceinline__ R interp(int order, const R (&q)[7], int o, R s)
 // so, the scheduler keeps each section's gathers in a few large groups
 // rather than trading round trips for registers.
 template <typename T, int OH, int OV, bool kNear, bool kVisc, bool kMoist>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_rhs(RhsArgs<T> a)
+__device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
 {
     using R = T;
     const Dims &d = a.d;
-    const TileIdx tc = tile_cell(a.ntx, a.nty);
+    const TileIdx tc = tile_cell(vb, a.ntx, a.nty);
     const int i = tc.i, j = tc.j, k = tc.k;
     if (i >= d.nx || j >= d.ny) return;
     const int nz = d.nz, P = d.nxy;
@@ -479,6 +515,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     st_stream(a.Rw + c, (T)out_w);
     if (k == 0) a.Rw[c + nz * P] = 0.0;
 }
+template <typename T, int OH, int OV, bool kNear, bool kVisc, bool kMoist>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_rhs(RhsArgs<T> a)
+{
+    k_rhs_body<T, OH, OV, kNear, kVisc, kMoist>(a, hw_block());
+}
+template <typename T, int OH, int OV, bool kNear, bool kVisc, bool kMoist>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_rhs_batch(const RhsArgs<T> *args, BatchMap bm)
+{
+    int m;
+    VBlock vb;
+    if (batch_block(bm, m, vb)) k_rhs_body<T, OH, OV, kNear, kVisc, kMoist>(args[m], vb);
+}
 
 }  // namespace
 
@@ -486,27 +534,33 @@ namespace {
 // orders 2, 3 and 5 in both directions have their own instances; any other
 // combination, and domains narrower than the stencil, take the general one.
 // Moist dynamics: 3rd order (the moist workload's) and the general instances.
+template <typename T, int OH, int OV, bool kNear, bool kVisc, bool kMoist>
+void rhs_one(erf_ctx *cx, const RhsArgs<T> &a, dim3 grd, dim3 blk)
+{
+    run<RhsArgs<T>, k_rhs<T, OH, OV, kNear, kVisc, kMoist>, k_rhs_batch<T, OH, OV, kNear, kVisc, kMoist>>(
+        cx, grd, blk, 0, a);
+}
 template <typename T, bool kVisc>
-void launch_rhs(const RhsArgs<T> &a, bool moist, dim3 grd, dim3 blk, hipStream_t st)
+void launch_rhs(erf_ctx *cx, const RhsArgs<T> &a, bool moist, dim3 grd, dim3 blk)
 {
     const bool near = a.d.nx >= 3 && a.d.ny >= 3 && a.d.nz >= 3;
     if (moist) {
         if (near && a.oh == 3 && a.ov == 3)
-            hipLaunchKernelGGL((k_rhs<T, 3, 3, true, kVisc, true>), grd, blk, 0, st, a);
+            rhs_one<T, 3, 3, true, kVisc, true>(cx, a, grd, blk);
         else if (near)
-            hipLaunchKernelGGL((k_rhs<T, 0, 0, true, kVisc, true>), grd, blk, 0, st, a);
+            rhs_one<T, 0, 0, true, kVisc, true>(cx, a, grd, blk);
         else
-            hipLaunchKernelGGL((k_rhs<T, 0, 0, false, kVisc, true>), grd, blk, 0, st, a);
+            rhs_one<T, 0, 0, false, kVisc, true>(cx, a, grd, blk);
     } else if (near && a.oh == 5 && a.ov == 5)
-        hipLaunchKernelGGL((k_rhs<T, 5, 5, true, kVisc, false>), grd, blk, 0, st, a);
+        rhs_one<T, 5, 5, true, kVisc, false>(cx, a, grd, blk);
     else if (near && a.oh == 3 && a.ov == 3)
-        hipLaunchKernelGGL((k_rhs<T, 3, 3, true, kVisc, false>), grd, blk, 0, st, a);
+        rhs_one<T, 3, 3, true, kVisc, false>(cx, a, grd, blk);
     else if (near && a.oh == 2 && a.ov == 2)
-        hipLaunchKernelGGL((k_rhs<T, 2, 2, true, kVisc, false>), grd, blk, 0, st, a);
+        rhs_one<T, 2, 2, true, kVisc, false>(cx, a, grd, blk);
     else if (near)
-        hipLaunchKernelGGL((k_rhs<T, 0, 0, true, kVisc, false>), grd, blk, 0, st, a);
+        rhs_one<T, 0, 0, true, kVisc, false>(cx, a, grd, blk);
     else
-        hipLaunchKernelGGL((k_rhs<T, 0, 0, false, kVisc, false>), grd, blk, 0, st, a);
+        rhs_one<T, 0, 0, false, kVisc, false>(cx, a, grd, blk);
 }
 
 template <typename T>
@@ -581,18 +635,26 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], const void *rq, void 
     dim3 blk(tx, ty, 1), grd(a.ntx * a.nty * d.nz), grdw(a.ntx * a.nty * (d.nz + 1));
     timing_start(cx, K_PREP);
     if (moist)
-        hipLaunchKernelGGL((k_prep<T, true>), grd, blk, 0, cx->stream, a);
+        run<RhsArgs<T>, k_prep<T, true>, k_prep_batch<T, true>>(cx, grd, blk, 0, a);
     else
-        hipLaunchKernelGGL((k_prep<T, false>), grd, blk, 0, cx->stream, a);
+        run<RhsArgs<T>, k_prep<T, false>, k_prep_batch<T, false>>(cx, grd, blk, 0, a);
     timing_stop(cx, K_PREP);
     if (prep_only) return hipGetLastError();
-    if (a.sgs) { timing_start(cx, K_MUT); hipLaunchKernelGGL(k_mut<T>, grd, blk, 0, cx->stream, a); timing_stop(cx, K_MUT); }
-    if (a.visc) { timing_start(cx, K_STRESS); hipLaunchKernelGGL(k_stress<T>, grdw, blk, 0, cx->stream, a); timing_stop(cx, K_STRESS); }
+    if (a.sgs) {
+        timing_start(cx, K_MUT);
+        run<RhsArgs<T>, k_mut<T>, k_mut_batch<T>>(cx, grd, blk, 0, a);
+        timing_stop(cx, K_MUT);
+    }
+    if (a.visc) {
+        timing_start(cx, K_STRESS);
+        run<RhsArgs<T>, k_stress<T>, k_stress_batch<T>>(cx, grdw, blk, 0, a);
+        timing_stop(cx, K_STRESS);
+    }
     timing_start(cx, K_RHS);
     if (a.visc)
-        launch_rhs<T, true>(a, moist, grd, blk, cx->stream);
+        launch_rhs<T, true>(cx, a, moist, grd, blk);
     else
-        launch_rhs<T, false>(a, moist, grd, blk, cx->stream);
+        launch_rhs<T, false>(cx, a, moist, grd, blk);
     timing_stop(cx, K_RHS);
     if (mlp) {
         hipError_t e = hipGetLastError();

@@ -23,9 +23,9 @@ struct ScalArgs {
 
 // q^t = (rho q)^t / rho^t; one thread per cell for every scalar (rho read once)
 template <typename T>
-__global__ __launch_bounds__(256) void k_mixing_ratio(ScalArgs<T> a)
+__device__ __forceinline__ void k_mixing_ratio_body(ScalArgs<T> a, VBlock vb)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = vb.x * blockDim.x + threadIdx.x;
     if (c >= a.d.n) return;
     // full rho^t: stored (FP64) or base + perturbation (FP32 storage), in T
     const T r = kPert<T> ? (T)a.rho0[c / a.d.nxy] + a.rho_t[c] : a.rho_t[c];
@@ -33,6 +33,18 @@ __global__ __launch_bounds__(256) void k_mixing_ratio(ScalArgs<T> a)
         const size_t o = (size_t)s * a.d.n + c;
         a.q[o] = a.rq_t[o] / r;
     }
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_mixing_ratio(ScalArgs<T> a)
+{
+    k_mixing_ratio_body<T>(a, hw_block());
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_mixing_ratio_batch(const ScalArgs<T> *args, BatchMap bm)
+{
+    int m;
+    VBlock vb;
+    if (batch_block(bm, m, vb)) k_mixing_ratio_body<T>(args[m], vb);
 }
 
 // a / b for the WENO5 weights: the hardware reciprocal (1 ulp) in float, an
@@ -89,7 +101,7 @@ __device__ __forceinline__ R weno5_face(R v0, R v1, R v2, R v3, R v4)
 constexpr int kSX = 63, kSY = 15, kLev = 16;
 constexpr int kHX = kSX + 1 + 6, kHY = kSY + 1 + 6;  // staged plane with halo
 template <typename T, bool kWeno, bool kNear>
-__global__ __launch_bounds__(1024) void k_scalar(ScalArgs<T> a)
+__device__ __forceinline__ void k_scalar_body(ScalArgs<T> a, VBlock vb)
 {
     using R = T;  // arithmetic type
     __shared__ R qs[kHY][kHX];
@@ -98,9 +110,9 @@ __global__ __launch_bounds__(1024) void k_scalar(ScalArgs<T> a)
     const int lane = threadIdx.x, row = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.nxy;
     const int nchunk = (nz + kLev - 1) / kLev;
-    const int kc = blockIdx.z % nchunk, s = blockIdx.z / nchunk;
+    const int kc = vb.z % nchunk, s = vb.z / nchunk;
     const int k0 = kc * kLev, k1 = min(k0 + kLev, nz);
-    const int x0 = blockIdx.x * kSX, y0 = blockIdx.y * kSY;
+    const int x0 = vb.x * kSX, y0 = vb.y * kSY;
     // the thread's cell, wrapped periodically (the lending lane and row may lie
     // past the domain's end); threads beyond them only stage and wait
     const int iu = x0 + lane, ju = y0 + row;
@@ -198,6 +210,18 @@ __global__ __launch_bounds__(1024) void k_scalar(ScalArgs<T> a)
         fz_below = fz1;
     }
 }
+template <typename T, bool kWeno, bool kNear>
+__global__ __launch_bounds__(1024) void k_scalar(ScalArgs<T> a)
+{
+    k_scalar_body<T, kWeno, kNear>(a, hw_block());
+}
+template <typename T, bool kWeno, bool kNear>
+__global__ __launch_bounds__(1024) void k_scalar_batch(const ScalArgs<T> *args, BatchMap bm)
+{
+    int m;
+    VBlock vb;
+    if (batch_block(bm, m, vb)) k_scalar_body<T, kWeno, kNear>(args[m], vb);
+}
 
 }  // namespace
 
@@ -228,20 +252,20 @@ hipError_t scalar_t(erf_ctx *cx, const void *rqn, const void *rho_t, const void 
     a.out = (T *)rq_out;
     if (a.nq <= 0) return hipSuccess;
     timing_start(cx, K_MIXRATIO);
-    hipLaunchKernelGGL(k_mixing_ratio<T>, dim3((d.n + 255) / 256), dim3(256), 0, cx->stream, a);
+    run<ScalArgs<T>, k_mixing_ratio<T>, k_mixing_ratio_batch<T>>(cx, dim3((d.n + 255) / 256), dim3(256), 0, a);
     timing_stop(cx, K_MIXRATIO);
     const int nchunk = (d.nz + kLev - 1) / kLev;
     dim3 blk(kSX + 1, kSY + 1, 1), grd((d.nx + kSX - 1) / kSX, (d.ny + kSY - 1) / kSY, nchunk * a.nq);
     const bool near = d.nx >= 3 && d.ny >= 3 && d.nz >= 3;
     timing_start(cx, K_SCALAR);
     if (a.weno && near)
-        hipLaunchKernelGGL((k_scalar<T, true, true>), grd, blk, 0, cx->stream, a);
+        run<ScalArgs<T>, k_scalar<T, true, true>, k_scalar_batch<T, true, true>>(cx, grd, blk, 0, a);
     else if (a.weno)
-        hipLaunchKernelGGL((k_scalar<T, true, false>), grd, blk, 0, cx->stream, a);
+        run<ScalArgs<T>, k_scalar<T, true, false>, k_scalar_batch<T, true, false>>(cx, grd, blk, 0, a);
     else if (near)
-        hipLaunchKernelGGL((k_scalar<T, false, true>), grd, blk, 0, cx->stream, a);
+        run<ScalArgs<T>, k_scalar<T, false, true>, k_scalar_batch<T, false, true>>(cx, grd, blk, 0, a);
     else
-        hipLaunchKernelGGL((k_scalar<T, false, false>), grd, blk, 0, cx->stream, a);
+        run<ScalArgs<T>, k_scalar<T, false, false>, k_scalar_batch<T, false, false>>(cx, grd, blk, 0, a);
     timing_stop(cx, K_SCALAR);
     return hipGetLastError();
 }

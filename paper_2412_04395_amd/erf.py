@@ -38,9 +38,10 @@ EXPORTS = ("erf_base_state_host", "erf_create", "erf_destroy", "erf_last_error",
            "erf_box_filter", "erf_mlp_fit_norm", "erf_mlp_standardize", "erf_mlp_loss_grad",
            "erf_mlp_train_step", "erf_mlp_loss_grad_noalloc", "erf_mlp_fallback_count",
            "erf_ensemble_create", "erf_ensemble_destroy", "erf_ensemble_last_error", "erf_ensemble_member",
-           "erf_ensemble_set_branches", "erf_ensemble_branches", "erf_ensemble_rk3_step", "erf_ensemble_autotune")
+           "erf_ensemble_set_branches", "erf_ensemble_branches", "erf_ensemble_set_batched", "erf_ensemble_batched",
+           "erf_ensemble_rk3_step", "erf_ensemble_autotune")
 _NOT_STATUS = ("erf_destroy", "erf_last_error", "erf_workspace_bytes", "erf_ensemble_destroy",
-               "erf_ensemble_last_error", "erf_ensemble_member", "erf_ensemble_branches")
+               "erf_ensemble_last_error", "erf_ensemble_member", "erf_ensemble_branches", "erf_ensemble_batched")
 
 
 class ErfError(RuntimeError):
@@ -151,6 +152,9 @@ def load(path: str = LIB_PATH):
             L.erf_ensemble_set_branches.argtypes = [C.c_void_p, C.c_int32]
             L.erf_ensemble_branches.argtypes = [C.c_void_p]
             L.erf_ensemble_branches.restype = C.c_int32
+            L.erf_ensemble_set_batched.argtypes = [C.c_void_p, C.c_int32]
+            L.erf_ensemble_batched.argtypes = [C.c_void_p]
+            L.erf_ensemble_batched.restype = C.c_int32
             L.erf_ensemble_rk3_step.argtypes = [C.c_void_p, C.POINTER(State)]
             L.erf_ensemble_autotune.argtypes = [C.c_void_p, C.POINTER(State), C.c_int32, C.POINTER(C.c_int32),
                                                 C.POINTER(C.c_double)]
@@ -561,6 +565,13 @@ class Ensemble:
 
     def set_branches(self, n: int):
         self._check(self.L.erf_ensemble_set_branches(self.h, int(n)), "erf_ensemble_set_branches")
+
+    @property
+    def batched(self) -> bool:
+        return bool(self.L.erf_ensemble_batched(self.h))
+
+    def set_batched(self, on: bool):
+        self._check(self.L.erf_ensemble_set_batched(self.h, int(bool(on))), "erf_ensemble_set_batched")
 
     def rk3_step(self, states):
         self._states_keep = self._states(states)

@@ -1,9 +1,12 @@
 """Ensemble batching (include/erf_ensemble.h) on the GPU.
 
-Members are independent contexts and the batched step runs each member's own
-kernels, so a batched step must equal stepping the members one after another
-bitwise, whatever the branch layout, the graph re-captures and the autotuner's
-trials.  One FP64 member is also checked against the oracle.
+Members are independent contexts and both modes run each member's own kernel
+bodies on forked branch streams (batched mode: the k-th launches of a branch's
+members fused into one launch over a (member, block) work list; unbatched: the
+members' own launches), so an ensemble step must equal stepping the members one
+after another bitwise, whatever the mode, the branch layout, the graph
+re-captures and the autotuner's trials.  One FP64 member is also checked against the
+oracle.
 """
 import sys
 
@@ -43,11 +46,11 @@ def _weights(seed):
 
 
 def _setup(solver, cfg):
-    th0 = W.theta_sounding(cfg)
-    b = solver.init_base_state(th0)
+    th0, qv0 = W.theta_sounding(cfg), W.qv0_of(cfg)
+    b = solver.init_base_state(th0, qv0=qv0)
     if cfg.sgs == 2:
         solver.mlp_set_weights(*_weights(cfg.seed))
-    return solver.from_full(W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"]))
+    return solver.from_full(W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"], qv0))
 
 
 def _sequential(cfgs, steps):
@@ -64,24 +67,49 @@ def _sequential(cfgs, steps):
 
 
 def _same(a, b):
-    return all(np.array_equal(x[f], y[f]) for x, y in zip(a, b) for f in ("rho", "rt", "ru", "rv", "rw"))
+    return all(np.array_equal(x[f], y[f]) for x, y in zip(a, b) for f in ("rho", "rt", "ru", "rv", "rw", "rq"))
 
 
-@pytest.mark.parametrize("branches", [1, 3, 6])
-def test_batched_step_equals_sequential_bitwise(branches):
+@pytest.mark.parametrize("batched,branches", [(1, 1), (1, 3), (0, 1), (0, 3), (0, 6)])
+def test_batched_step_equals_sequential_bitwise(batched, branches):
     from paper_2412_04395_amd import erf
     cfgs = _members()
     ens = erf.Ensemble(cfgs)
+    assert ens.batched  # the default
+    ens.set_batched(bool(batched))
     ens.set_branches(branches)
     states = [_setup(s, c) for s, c in zip(ens.members, cfgs)]
     for _ in range(3):
         ens.rk3_step(states)
     got = [m.to_numpy(S) for m, S in zip(ens.members, states)]
     ref = _sequential(cfgs, 3)
-    _say(f"ensemble, {ens.branches} branches: bitwise equal {_same(got, ref)}")
+    mode = f"{'batched' if ens.batched else 'unbatched'}, {ens.branches} branches"
+    _say(f"ensemble, {mode}: bitwise equal {_same(got, ref)}")
     assert _same(got, ref)
     for m, S in zip(ens.members, states):
         assert m.diagnostics(S)["nonfinite"] == 0
+    ens.close()
+
+
+def test_batched_with_scalars_and_moisture():
+    """Members that transport scalars (WENO5 and an interpolant, FP32 and FP64,
+    one moist) beside plain ones: the batched mixing-ratio, scalar, finalize and
+    moist launches give the sequential result bitwise."""
+    from paper_2412_04395_amd import erf
+    base = dict(dx=250.0, dy=250.0, dt=2.0, n_substeps=8, adv_order_h=3, adv_order_v=3)
+    cfgs = [W.small(name="deep_small", nx=36, ny=20, nz=14, dz=W.stretched_dz(14, 50.0, 500.0, 4000.0), seed=81,
+                    n_scalars=3, scalar_scheme=1, moist=1, prec="fp32", **base),
+            W.small(name="deep_small", nx=24, ny=30, nz=12, dz=W.uniform_dz(12, 200.0), seed=82, n_scalars=3,
+                    scalar_scheme=0, prec="fp64", **base),
+            W.small(name="deep_small", nx=40, ny=16, nz=14, dz=W.stretched_dz(14, 50.0, 500.0, 4000.0), seed=83,
+                    n_scalars=3, scalar_scheme=1, moist=1, prec="fp64", **base),
+            W.small(name="bubble_small", nx=28, ny=20, nz=16, seed=84, prec="fp32")]
+    ens = erf.Ensemble(cfgs)
+    states = [_setup(s, c) for s, c in zip(ens.members, cfgs)]
+    for _ in range(2):
+        ens.rk3_step(states)
+    got = [m.to_numpy(S) for m, S in zip(ens.members, states)]
+    assert _same(got, _sequential(cfgs, 2))
     ens.close()
 
 
@@ -108,10 +136,12 @@ def test_autotune_keeps_results_bitwise():
     states = [_setup(s, c) for s, c in zip(ens.members, cfgs)]
     trials = 2
     nb, ms = ens.autotune(states, trials)
-    # one capture step and `trials` timed steps per candidate 1, 2, 4 (6 members: 8 and 16 skipped)
-    steps = 3 * (1 + trials)
-    _say(f"autotune: {nb} branches, {ms:.3f} ms per ensemble step, {steps} steps taken")
-    assert nb in (1, 2, 4) and ens.branches == nb and ms > 0
+    # one capture step and `trials` timed steps per candidate: batched and
+    # unbatched, each on 1, 2, 4 branches (6 members: 8 and 16 skipped)
+    steps = 2 * 3 * (1 + trials)
+    _say(f"autotune: {'batched' if ens.batched else 'unbatched'}, {nb} branches, {ms:.3f} ms per ensemble step, "
+         f"{steps} steps")
+    assert nb in (1, 2, 4) and ms > 0 and ens.branches == nb
     got = [m.to_numpy(S) for m, S in zip(ens.members, states)]
     assert _same(got, _sequential(cfgs, steps))
     ens.close()
