@@ -22,6 +22,16 @@ Recipe
 Writes DIR/closure_les40m.npz (params float32[9609], norm float64[38]) and
 DIR/closure_les40m.json (recipe, losses, a-posteriori errors).  Prints one
 progress line at least every minute of GPU work.
+
+    python -m paper_2412_04395_amd.closure_training --gain-fixture PATH
+
+writes the reduced a-posteriori case that the GPU test of the closure's gain
+runs: the held-out fine run (seed 44) after its spin-up, box-filtered onto the
+coarse grid (the coarse initial state, as the FP32 perturbations the coarse
+context stores), and the filtered continuation's k(z), heat-flux profiles and
+1-D spectra of u and w at z_i / 2 (the reference the coarse runs are judged
+against).  The reference is the dycore's own filtered fine FP64 run: the
+method's judge of the closure, not a parity value.
 """
 from __future__ import annotations
 
@@ -109,6 +119,59 @@ def _rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+SPECTRUM_HEIGHT_M = 500.0  # z_i / 2 for the 1 km inversion of the sounding
+
+
+def spectra(S, cfg):
+    """1-D power spectra along x of the centre velocities u and w, averaged
+    over y, at the level nearest z_i / 2: (E_u, E_w) for wavenumbers 1 .. nx/2."""
+    uc, _, wc, _ = _centre_fields(S)
+    k = int(np.argmin(np.abs(cfg.z_centres() - SPECTRUM_HEIGHT_M)))
+    out = []
+    for f in (uc[k], wc[k]):
+        F = np.fft.rfft(f - f.mean(axis=1, keepdims=True), axis=1)
+        out.append((np.abs(F[:, 1:cfg.nx // 2 + 1]) ** 2).mean(axis=0) / cfg.nx ** 2)
+    return out
+
+
+def _log_spectral_error(a, b):
+    """rms of ln(a / b) over the wavenumbers 1 .. nx/4 (wavelengths of at least
+    four coarse cells): above them the 4x box filter of the reference and the
+    two-point centring of u (which removes the shortest wave exactly) shape
+    both spectra more than the closure does"""
+    m = len(b) // 2
+    return float(np.sqrt(np.mean(np.log(np.maximum(a[:m], 1e-300) / np.maximum(b[:m], 1e-300)) ** 2)))
+
+
+def a_posteriori(c: "Coarse", init_state, ref_profiles, steps_per_eval: int, evals: int, nrm=None, ref_spectra=None):
+    """Run the coarse context c from init_state (device, its storage) and
+    compare, after every steps_per_eval steps, its k(z) and total heat flux
+    with ref_profiles[e] = (k, flux); with ref_spectra (E_u, E_w at the end)
+    also the final 1-D spectra.  nrm: the network's statistics (closure runs).
+    Returns the per-evaluation errors and their means over e >= 1."""
+    S = init_state
+    errs = []
+    for e in range(evals + 1):
+        if e > 0:
+            for _ in range(steps_per_eval):
+                c.s.rk3_step(S)
+        full = c.s.to_full(S)
+        if c.cfg.sgs == erf.ERF_SGS_MLP:
+            q3 = network_q3(c, S, nrm)
+        else:
+            q3 = smagorinsky_q3(c.s.mlp_features(S).cpu().numpy(), c.cfg)
+        k, flux = profiles(full, q3)
+        errs.append({"tke": _rel_l2(k, ref_profiles[e][0]), "heat_flux": _rel_l2(flux, ref_profiles[e][1])})
+    out = {"errors": errs, "mean_tke_error": float(np.mean([x["tke"] for x in errs[1:]])),
+           "mean_heat_flux_error": float(np.mean([x["heat_flux"] for x in errs[1:]]))}
+    out["nonfinite"] = c.s.diagnostics(S, allow_nonfinite=True)["nonfinite"]
+    if ref_spectra is not None:
+        eu, ew = spectra(c.s.to_full(S), c.cfg)
+        out["spectrum_u_error"] = _log_spectral_error(eu, ref_spectra[0])
+        out["spectrum_w_error"] = _log_spectral_error(ew, ref_spectra[1])
+    return out
+
+
 # -- fine runs ----------------------------------------------------------------------
 def fine_run(cfg, spin, every, nsnap, on_snapshot):
     import torch
@@ -134,10 +197,47 @@ def fine_run(cfg, spin, every, nsnap, on_snapshot):
     return d
 
 
+def gain_fixture(path, spin=12000, every=1200, evals=5, nx=256, nz=128):
+    """The reduced a-posteriori case of the module docstring, written to path
+    (.npz): coarse initial state (float32 perturbations rho - rho0, rho theta -
+    rho0 theta0, and the momenta), reference profiles k[evals + 1][nz_c],
+    flux[evals + 1][nz_c] and final spectra E_u, E_w, and the recipe."""
+    fine = W.les_fine(nx=nx, ny=nx, nz=nz, dz=W.uniform_dz(nz, 10.0), seed=44)
+    cm = Coarse(coarse_config(fine, erf.ERF_SGS_SMAGORINSKY))
+    ks, fluxes, keep = [], [], {}
+
+    def snap(k, s, S):
+        Cst, tg = s.box_filter(S, R_FILTER, Cs=fine.Cs, Pr_t=fine.Pr_t)
+        full = {f: Cst[f].cpu().numpy() for f in ("rho", "rt", "ru", "rv", "rw")}
+        q3 = tg[:, 8].cpu().numpy().reshape(cm.cfg.nz, cm.cfg.ny, cm.cfg.nx)
+        kz, fl = profiles(full, q3)
+        ks.append(kz)
+        fluxes.append(fl)
+        if k == 0:
+            keep["init"] = full
+        if k == evals:
+            keep["spectra"] = spectra(full, cm.cfg)
+
+    fine_run(fine, spin, every, evals + 1, snap)
+    init = keep["init"]
+    rho0 = cm.b["rho0"][:, None, None]
+    T0 = (cm.b["rho0"] * cm.b["theta0"])[:, None, None]
+    recipe = {"fine_grid": [fine.nx, fine.ny, fine.nz], "fine_dx_m": fine.dx, "fine_dt_s": fine.dt, "seed": fine.seed,
+              "spin_up_s": spin * fine.dt, "eval_every_s": every * fine.dt, "evals": evals, "filter": R_FILTER,
+              "coarse_grid": [cm.cfg.nx, cm.cfg.ny, cm.cfg.nz], "spectrum_height_m": SPECTRUM_HEIGHT_M}
+    np.savez_compressed(path, rho_p=(init["rho"] - rho0).astype(np.float32),
+                        rt_p=(init["rt"] - T0).astype(np.float32), ru=init["ru"].astype(np.float32),
+                        rv=init["rv"].astype(np.float32), rw=init["rw"].astype(np.float32),
+                        k_ref=np.array(ks), flux_ref=np.array(fluxes), spec_u_ref=keep["spectra"][0],
+                        spec_w_ref=keep["spectra"][1], recipe=json.dumps(recipe))
+    _log(f"gain fixture written to {path}")
+
+
 def main(argv=None):
     import torch
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--gain-fixture", help="write the reduced a-posteriori case to this .npz and stop")
+    ap.add_argument("--out")
     ap.add_argument("--spin", type=int, default=12000, help="fine spin-up steps (0.1 s each)")
     ap.add_argument("--every", type=int, default=600, help="fine steps between snapshots")
     ap.add_argument("--snaps", type=int, default=10, help="training snapshots")
@@ -149,6 +249,11 @@ def main(argv=None):
     ap.add_argument("--nx", type=int, default=256)
     ap.add_argument("--nz", type=int, default=128)
     a = ap.parse_args(argv)
+    if a.gain_fixture:
+        gain_fixture(a.gain_fixture, spin=a.spin, every=a.eval_every, evals=a.evals, nx=a.nx, nz=a.nz)
+        return 0
+    if not a.out:
+        ap.error("--out is required")
     os.makedirs(a.out, exist_ok=True)
     fine = W.les_fine(nx=a.nx, ny=a.nx, nz=a.nz, dz=W.uniform_dz(a.nz, 10.0), seed=41)
     held = fine.replace(seed=44)

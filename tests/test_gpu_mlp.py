@@ -497,3 +497,52 @@ def test_trained_weights_run_stable():
     frac = s.mlp_fallback_count() / (3 * steps * cfg.cells)
     _say(f"trained closure, {steps} steps: max w {d['max_w']:.3f} m/s, fallback fraction {frac:.3f}")
     assert d["nonfinite"] == 0 and frac < 0.9
+
+
+def test_trained_closure_beats_smagorinsky_a_posteriori():
+    """What the learned closure gains (the closure's judge, not a parity
+    check): from the box-filtered state of the held-out fine FP64 run after its
+    20 min spin-up (paper_2412_04395_amd/data/closure_gain_heldout.npz, written
+    by closure_training.py --gain-fixture through the library), the 40 m coarse
+    run with the stored network and the same run with Smagorinsky advance for
+    10 min; their plane-averaged resolved kinetic energy k(z) and total
+    vertical heat flux (resolved + subgrid) are compared every 2 min with the
+    filtered continuation of the fine run.  The network's mean relative L2
+    errors must be below Smagorinsky's on both profiles.  The 1-D u and w
+    spectra at z_i / 2 after the window are reported."""
+    import json
+    import os
+
+    from paper_2412_04395_amd import closure_training as CT
+    from paper_2412_04395_amd import erf
+
+    data = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2412_04395_amd", "data")
+    fx = np.load(os.path.join(data, "closure_gain_heldout.npz"), allow_pickle=False)
+    recipe = json.loads(str(fx["recipe"]))
+    wz = np.load(os.path.join(data, "closure_les40m.npz"), allow_pickle=False)
+    fine = W.les_fine(nx=recipe["fine_grid"][0], ny=recipe["fine_grid"][1], nz=recipe["fine_grid"][2],
+                      dz=W.uniform_dz(recipe["fine_grid"][2], recipe["fine_dx_m"]), seed=recipe["seed"])
+    steps = recipe["eval_every_s"] / 0.4
+    assert abs(steps - round(steps)) < 1e-9
+    steps = int(round(steps))
+    ref_p = [(fx["k_ref"][e], fx["flux_ref"][e]) for e in range(recipe["evals"] + 1)]
+    res = {}
+    for name, sgs in (("network", erf.ERF_SGS_MLP), ("smagorinsky", erf.ERF_SGS_SMAGORINSKY)):
+        c = CT.Coarse(CT.coarse_config(fine, sgs))
+        assert [c.cfg.nx, c.cfg.ny, c.cfg.nz] == recipe["coarse_grid"]
+        if sgs == erf.ERF_SGS_MLP:
+            c.s.mlp_set_weights(wz["params"], wz["norm"])
+        rho0 = c.b["rho0"][:, None, None]
+        T0 = (c.b["rho0"] * c.b["theta0"])[:, None, None]
+        init = {"rho": rho0 + fx["rho_p"].astype(np.float64), "rt": T0 + fx["rt_p"].astype(np.float64),
+                "ru": fx["ru"].astype(np.float64), "rv": fx["rv"].astype(np.float64),
+                "rw": fx["rw"].astype(np.float64), "rq": np.zeros((0,) + fx["rho_p"].shape)}
+        r = CT.a_posteriori(c, c.s.from_full(init), ref_p, steps, recipe["evals"], nrm=wz["norm"],
+                            ref_spectra=(fx["spec_u_ref"], fx["spec_w_ref"]))
+        assert r["nonfinite"] == 0
+        res[name] = r
+        _say(f"a posteriori {name}: k(z) {r['mean_tke_error']:.3f}, heat flux {r['mean_heat_flux_error']:.3f}, "
+             f"spectra u {r['spectrum_u_error']:.3f} w {r['spectrum_w_error']:.3f}")
+        c.s.close()
+    assert res["network"]["mean_tke_error"] < res["smagorinsky"]["mean_tke_error"]
+    assert res["network"]["mean_heat_flux_error"] < res["smagorinsky"]["mean_heat_flux_error"]
