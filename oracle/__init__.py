@@ -92,6 +92,14 @@ def lib():
                                        C.POINTER(_State)]
             L.orc_diagnostics.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Base),
                                           C.POINTER(_State), _DP]
+            L.orc_kessler.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Base), C.POINTER(_State),
+                                      C.c_double, _DP]
+            L.orc_esat.restype = C.c_double
+            L.orc_esat.argtypes = [C.c_double]
+            L.orc_qvsat.restype = C.c_double
+            L.orc_qvsat.argtypes = [C.c_double, C.c_double]
+            L.orc_sat_adjust.restype = C.c_double
+            L.orc_sat_adjust.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
             L.orc_bf16.restype = C.c_double
             L.orc_bf16.argtypes = [C.c_double]
             L.orc_mlp_forward.argtypes = [_DP, _DP, C.c_int64, _DP, C.c_int]
@@ -210,9 +218,22 @@ class Oracle:
         return rq
 
     def rk3_step(self, S):
-        """Advance S (modified in place) by one RK3 step."""
+        """Advance S (modified in place) by one RK3 step; with the workload's
+        microphysics switched on, the Kessler step over dt follows (the rain
+        reaching the ground accumulates in self.precip)."""
         self._check(lib().orc_rk3_step(C.byref(self._grid), C.byref(self._params), C.byref(self._base),
                                        C.byref(self._st(S))), "orc_rk3_step")
+        if getattr(self.cfg, "microphysics", 0):
+            self.kessler(S, self.cfg.dt)
+        return S
+
+    def kessler(self, S, dt: float):
+        """Kessler warm-rain microphysics over dt, in place (Sec. 2.4); the rain
+        reaching the ground [kg/m^2] accumulates in self.precip [ny][nx]."""
+        if getattr(self, "precip", None) is None:
+            self.precip = np.zeros((self.ny, self.nx))
+        self._check(lib().orc_kessler(C.byref(self._grid), C.byref(self._params), C.byref(self._base),
+                                      C.byref(self._st(S)), float(dt), _p(self.precip)), "orc_kessler")
         return S
 
     def diagnostics(self, S):
@@ -363,6 +384,18 @@ def eos_p(Theta: float) -> float:
 
 def eos_pprime(Theta: float, Theta0: float, p0: float) -> float:
     return lib().orc_eos_pprime(Theta, Theta0, p0)
+
+
+def esat(T: float) -> float:
+    return lib().orc_esat(T)
+
+
+def qvsat(T: float, p: float) -> float:
+    return lib().orc_qvsat(T, p)
+
+
+def sat_adjust(T: float, p: float, qv: float, qc: float) -> float:
+    return lib().orc_sat_adjust(T, p, qv, qc)
 
 
 def eos_p_moist(Theta: float, qv: float) -> float:

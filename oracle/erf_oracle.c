@@ -1480,3 +1480,145 @@ int orc_slow_rhs_mlp(const orc_grid *g, const orc_params *P, const orc_base *B, 
     free(feat); free(xs); free(ys); free(th); free(u); free(v); free(w); free(T);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Kessler warm-rain microphysics (Sec. 2.4, the scheme of Kessler 1969 in   */
+/* the form of Klemp & Wilhelmson 1978), applied after a dynamics step       */
+/* ------------------------------------------------------------------------ */
+/* Readings (the paper names the scheme, not its constants):
+ *  - latent heat of vaporisation 2.5e6 J/kg;
+ *  - saturation vapour pressure over water of Bolton (1980), in place of
+ *    the polynomial fit the paper cites without its coefficients;
+ *    q_vs = (R_d/R_v) e_s / (p - e_s);
+ *  - autoconversion k1 (q_c - a)^+ with k1 = 1e-3 1/s, a = 1e-3 kg/kg;
+ *    accretion k2 q_c q_r^0.875 with k2 = 2.2 1/s;
+ *  - rain evaporation (1 - q_v/q_vs) C (rho q_r)^0.525 / (rho (5.4e5 +
+ *    2.55e6 / (p q_vs))), C = 1.6 + 124.9 (rho q_r)^0.2046, with rho in
+ *    g/cm^3 and p in hPa, limited by the rain present and by saturation;
+ *  - terminal velocity of rain 36.34 (rho q_r)^0.1364 (rho_s / rho)^(1/2)
+ *    m/s (rho q_r in g/cm^3, rho_s the base state's lowest density);
+ *  - order within a step: rain sedimentation (upwind, sub-stepped at a
+ *    fall Courant number of at most 0.8), then autoconversion and
+ *    accretion, rain evaporation, and the saturation adjustment of cloud
+ *    water; the pressure (hence the Exner function) is that of the state
+ *    at the start of the step and is held during it;
+ *  - the saturation adjustment solves q_v - d = q_vs(T + L d / c_p, p) for
+ *    the condensed amount d by six Newton steps from d = 0, clamped to
+ *    [-q_c, q_v] (all cloud evaporates where the air stays subsaturated). */
+static const double L_V = 2.5e6;
+
+double orc_esat(double T) { return 611.2 * exp(17.67 * (T - 273.15) / (T - 29.65)); }
+
+double orc_qvsat(double T, double p)
+{
+    double e = orc_esat(T);
+    return (R_D / R_V) * e / (p - e);
+}
+
+/* d q_vs / dT at fixed pressure */
+static double dqvsat_dT(double T, double p)
+{
+    double e = orc_esat(T);
+    double dlne = 17.67 * (273.15 - 29.65) / ((T - 29.65) * (T - 29.65));
+    return (R_D / R_V) * p * e * dlne / ((p - e) * (p - e));
+}
+
+/* the condensed amount d of the saturation adjustment (module comment) */
+double orc_sat_adjust(double T, double p, double qv, double qc)
+{
+    if (qc <= 0.0 && qv <= orc_qvsat(T, p)) return 0.0;
+    double d = 0.0;
+    for (int it = 0; it < 6; ++it) {
+        double Tn = T + L_V * d / C_P;
+        double f = qv - d - orc_qvsat(Tn, p);
+        double df = -1.0 - dqvsat_dT(Tn, p) * L_V / C_P;
+        d = d - f / df;
+    }
+    if (d < -qc) d = -qc;
+    if (d > qv) d = qv;
+    return d;
+}
+
+static double fall_speed(double rho, double qr, double rho_s)
+{
+    double rqr = 1e-3 * rho * qr;
+    return rqr > 0.0 ? 36.34 * pow(rqr, 0.1364) * sqrt(rho_s / rho) : 0.0;
+}
+
+int orc_kessler(const orc_grid *g, const orc_params *P, const orc_base *B, orc_state *S, double dt,
+                double *precip)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    size_t n = (size_t)nx * ny * nz, nxy = (size_t)nx * ny;
+    if (P->n_scalars < 3 || !S->rq || !(dt > 0.0)) return -1;
+    double *rqv = S->rq, *rqc = S->rq + n, *rqr = S->rq + 2 * n;
+    double rho_s = B->rho0[0];
+#pragma omp parallel for schedule(static)
+    for (size_t col = 0; col < nxy; ++col) {
+        double *V = dalloc(nz);
+        /* 1. sedimentation of rain, flux form, upwind from above */
+        double cmax = 0.0;
+        for (int k = 0; k < nz; ++k) {
+            size_t c = col + (size_t)k * nxy;
+            V[k] = fall_speed(S->rho[c], rqr[c] / S->rho[c], rho_s);
+            if (V[k] * dt / g->dz[k] > cmax) cmax = V[k] * dt / g->dz[k];
+        }
+        int nsub = (int)ceil(cmax / 0.8);
+        if (nsub < 1) nsub = 1;
+        double dts = dt / nsub;
+        for (int s = 0; s < nsub; ++s) {
+            if (s > 0)
+                for (int k = 0; k < nz; ++k) {
+                    size_t c = col + (size_t)k * nxy;
+                    V[k] = fall_speed(S->rho[c], rqr[c] / S->rho[c], rho_s);
+                }
+            /* flux out of cell k through its bottom face: (rho q_r)_k V_k */
+            double out0 = rqr[col] * V[0];
+            for (int k = 0; k < nz; ++k) {
+                size_t c = col + (size_t)k * nxy;
+                double fin = (k + 1 < nz) ? rqr[c + nxy] * V[k + 1] : 0.0;
+                double fout = rqr[c] * V[k];
+                rqr[c] = rqr[c] + dts * (fin - fout) / g->dz[k];
+            }
+            if (precip) precip[col] += dts * out0;
+        }
+        free(V);
+        /* 2-4. the cell processes */
+        for (int k = 0; k < nz; ++k) {
+            size_t c = col + (size_t)k * nxy;
+            double rho = S->rho[c], theta = S->rt[c] / rho;
+            double qv = rqv[c] / rho, qc = rqc[c] / rho, qr = rqr[c] / rho;
+            double pi = exner(S->rt[c] * (1.0 + EPS_V * qv));
+            double p = P_00 * pow(pi, C_P / R_D);
+            double T = theta * pi;
+            /* autoconversion and accretion */
+            double auto_ = qc > 1e-3 ? 1e-3 * (qc - 1e-3) : 0.0;
+            double accr = qr > 0.0 ? 2.2 * qc * pow(qr, 0.875) : 0.0;
+            double prod = dt * (auto_ + accr);
+            if (prod > qc) prod = qc;
+            qc -= prod;
+            qr += prod;
+            /* evaporation of rain into subsaturated air */
+            double qvs = orc_qvsat(T, p), ev = 0.0;
+            if (qr > 0.0 && qv < qvs) {
+                double rg = 1e-3 * rho, rqr_g = rg * qr;
+                double cv = 1.6 + 124.9 * pow(rqr_g, 0.2046);
+                double er = (1.0 - qv / qvs) * cv * pow(rqr_g, 0.525) / (rg * (5.4e5 + 2.55e6 / (1e-2 * p * qvs)));
+                ev = dt * er;
+                if (ev > qr) ev = qr;
+                if (ev > qvs - qv) ev = qvs - qv;
+                qv += ev;
+                T -= L_V * ev / C_P;
+            }
+            /* saturation adjustment of cloud water */
+            double d = orc_sat_adjust(T, p, qv, qc);
+            /* the state changes by the increments of the three processes, so
+             * that a cell where nothing happens keeps its values bit for bit */
+            rqv[c] += rho * (ev - d);
+            rqc[c] += rho * (d - prod);
+            rqr[c] += rho * (prod - ev);
+            S->rt[c] += rho * L_V * (d - ev) / (C_P * pi);
+        }
+    }
+    return 0;
+}

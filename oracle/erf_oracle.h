@@ -178,6 +178,20 @@ int orc_box_filter(const orc_grid *g, const orc_state *S, int32_t r, double Cs, 
 int orc_slow_rhs_mlp(const orc_grid *g, const orc_params *P, const orc_base *B, const orc_state *S,
                      const double *params, const double *norm, int bf16, orc_state *R, int64_t *fallback_out);
 
+/* Kessler warm-rain microphysics (Sec. 2.4; the scheme of Kessler 1969 in the
+ * form of Klemp & Wilhelmson 1978) over dt, after a dynamics step: rain
+ * sedimentation, autoconversion, accretion, rain evaporation and the
+ * saturation adjustment of cloud water, on scalars 0, 1, 2 = rho q_v, rho q_c,
+ * rho q_r and rho theta (latent heat), in place.  precip [ny][nx] (may be
+ * NULL) accumulates the rain mass reaching the ground [kg/m^2]. */
+int orc_kessler(const orc_grid *g, const orc_params *P, const orc_base *B, orc_state *S, double dt,
+                double *precip);
+/* saturation vapour pressure [Pa] over water and mixing ratio at (T, p) */
+double orc_esat(double T);
+double orc_qvsat(double T, double p);
+/* the condensed amount of the saturation adjustment at fixed pressure */
+double orc_sat_adjust(double T, double p, double qv, double qc);
+
 #ifdef __cplusplus
 }
 #endif
