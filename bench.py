@@ -73,6 +73,9 @@ KERNEL_VALUES = {
 # q^t = (rho q)^t / rho^t (rho q and rho read, q written); the scalar update
 # (q, the three averaged momenta and (rho q)^n read, (rho q)^new written).
 SCALAR_VALUES = {"mixing_ratio": lambda nq: (2 * nq + 1, 0), "scalar": lambda nq: (3 * nq + 3, 0)}
+# Kessler microphysics once per step: rho, rho theta and the three species read,
+# rho theta and the species written (the fall of rain re-reads its column)
+MICRO_VALUES = {"kessler": lambda nq: (5 + 4, 0)}
 # The first RK3 stage starts from S^t = S^n with one substep, so S'' = 0 on
 # entry: its stage init moves only Theta^t, rho^t in and theta^t, Exner out
 # (13 bulk values fewer) and its substep reads none of the 6 S'' inputs
@@ -147,7 +150,8 @@ def run_gpu(cfg: W.Config, steps: int, warmup: int):
     tune = s.autotune(S, trials=2, cache_path=_tune_cache())
     # find the kernel with the largest share of a step (one short timed step per kernel)
     shares = {}
-    for k in list(KERNEL_VALUES) + (list(SCALAR_VALUES) if cfg.n_scalars else []):
+    for k in (list(KERNEL_VALUES) + (list(SCALAR_VALUES) if cfg.n_scalars else []) +
+              (list(MICRO_VALUES) if getattr(cfg, "microphysics", 0) else [])):
         if k == "mut" and not cfg.sgs:
             continue
         _, (ms, n) = _time_steps(s, S, 1, torch, kernel=k)
@@ -487,6 +491,12 @@ def run_scalars(steps: int, warmup: int) -> dict:
                                 "achieved_gbs": round(byts / (us * 1e-6) / 1e9, 1),
                                 "frac": round(byts / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
     out["step_roofline"] = _step_roofline(cfg, 1e3 * el / steps, _copy_gbs())
+    # the same workload with Kessler warm rain after every step
+    cfg_k = cfg.replace(microphysics=1)
+    el_k, _, _, _, shares_k, diag_k = run_gpu(cfg_k, steps, warmup)
+    out["with_kessler"] = {"ms_per_step": 1e3 * el_k / steps, "value": cfg.cells * steps / el_k,
+                           "kessler_ms_per_step": round(shares_k.get("kessler", (0.0, 0))[0], 4),
+                           "nonfinite": diag_k["nonfinite"]}
     return out
 
 

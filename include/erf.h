@@ -95,6 +95,9 @@ typedef struct {
                                 the moist Exner function.  No phase change.
                                 Needs n_scalars >= 3; 0: dry, the scalars are
                                 passive                                          */
+    int32_t microphysics;    /* 1: Kessler warm rain (erf_kessler) over dt after
+                                every erf_rk3_step, the rain reaching the ground
+                                accumulated by the context; needs moist.  0: none */
 } erf_params;
 
 /* Device pointers to one state (or tendency, or flux) set; unused members may
@@ -225,6 +228,21 @@ erf_status erf_scalar_advance(erf_ctx *ctx, const erf_state *S_n, const erf_stat
  * entry and S^{n+1} on return (in place). */
 erf_status erf_rk3_step(erf_ctx *ctx, erf_state *S);
 
+/* Kessler warm-rain microphysics (Sec. 2.4: the scheme of Kessler 1969 in the
+ * form of Klemp & Wilhelmson 1978) over dt on a moist context's state S
+ * (rhoq components rho q_v, rho q_c, rho q_r and rho theta for the latent
+ * heat, in place), process-split after a dynamics step: sedimentation of
+ * rain (flux form, sub-stepped), autoconversion, accretion, evaporation of
+ * rain and the saturation adjustment of cloud water, at the pressure of the
+ * step's start.  The rain reaching the ground [kg/m^2] is added to precip
+ * (device double[ny][nx]; NULL: the context's own accumulator).  Saturation
+ * pressure of Bolton (1980) (the paper's polynomial fit is not printed).
+ * ERF_E_UNSUPPORTED for a dry context. */
+erf_status erf_kessler(erf_ctx *ctx, erf_state *S, double dt, double *precip);
+/* Copy the context's accumulated precipitation [kg/m^2] to host_out (host
+ * double[ny][nx]); reset = 1 then sets it to zero.  Synchronous. */
+erf_status erf_precipitation(erf_ctx *ctx, double *host_out, int32_t reset);
+
 /* FP64 global sums of the mass and energy budgets (Sec. 4.1.2) and a count of
  * non-finite values.  Synchronous.  Returns ERF_E_NONFINITE (with *out filled)
  * if any state value is NaN or Inf. */
@@ -249,7 +267,7 @@ erf_status erf_autotune(erf_ctx *ctx, erf_state *S, int32_t trials, const char *
  * max_launches launches are timed, later ones run untimed.  Kernel names:
  * "prep", "mut", "stress", "rhs", "stage_init", "coef", "substep", "finalize",
  * "mixing_ratio", "scalar", "mlp" (closure network), "mlp_div" (its stress
- * divergence).  erf_timing_begin allocates the events
+ * divergence), "kessler" (microphysics).  erf_timing_begin allocates the events
  * (ERF_E_NOMEM on failure) and returns ERF_E_ARG for an unknown name. */
 erf_status erf_timing_begin(erf_ctx *ctx, const char *kernel, int32_t max_launches);
 /* Waits for the stream, returns the summed event time [ms] of the timed

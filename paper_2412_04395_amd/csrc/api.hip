@@ -117,6 +117,8 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     if (nq > 0 && (prm->sgs != ERF_SGS_NONE || prm->alpha_m != 0.0)) return ERF_E_UNSUPPORTED;
     if (prm->moist != 0 && prm->moist != 1) return ERF_E_ARG;
     if (prm->moist && nq < 3) return ERF_E_ARG;  // rho q_v, rho q_c, rho q_r
+    if (prm->microphysics != 0 && prm->microphysics != 1) return ERF_E_ARG;
+    if (prm->microphysics && !prm->moist) return ERF_E_ARG;
     if (!(prm->dt > 0.0) || !(prm->beta_s >= 0.0 && prm->beta_s <= 1.0)) return ERF_E_ARG;
 
     erf_ctx *c = new (std::nothrow) erf_ctx();
@@ -160,7 +162,7 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
         {(void **)&ws.diag, diag_slots_needed() * D},
         {&ws.sg[0], G}, {&ws.sg[1], G}, {&ws.sg[2], G}, {&ws.sg[3], G}, {&ws.sg[4], G}, {&ws.sg[5], G},
         {&ws.sg[6], G}, {&ws.sg[7], G}, {&ws.sg[8], G},
-        {&ws.qf, M}, {&ws.bm, M}, {&ws.pex, M}, {&ws.rdm, M},
+        {&ws.qf, M}, {&ws.bm, M}, {&ws.pex, M}, {&ws.rdm, M}, {(void **)&ws.precip, (size_t)nxy * D},
         {(void **)&b.rho0, nzs * D}, {(void **)&b.theta0, nzs * D}, {(void **)&b.Theta0, nzs * D},
         {(void **)&b.p0, nzs * D}, {(void **)&b.pi0, nzs * D}, {(void **)&b.dz, (5 * nzs + 1) * D},
         {(void **)&b.qv0, nzs * D}, {(void **)&b.rho0t, nzs * D},
@@ -193,6 +195,13 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
         zc += grid->dz[k];
     }
     hz[4 * nz] = 0.0;
+    // no rain has fallen yet
+    e = hipMemset(ws.precip, 0, (size_t)nxy * sizeof(double));
+    if (e != hipSuccess) {
+        delete[] hz;
+        erf_destroy(c);
+        return ERF_E_HIP;
+    }
     for (int k = 0; k < nz; ++k) {
         const double cd = prm->Cs * std::cbrt(grid->dx * grid->dy * grid->dz[k]);
         hz[4 * nz + 1 + k] = cd * cd;
@@ -342,7 +351,34 @@ erf_status erf_rk3_step(erf_ctx *c, erf_state *S)
         }
         St = outs[stage];
     }
+    // process-split microphysics after the dynamics step (Sec. 2.4)
+    if (c->prm.microphysics) {
+        hipError_t e = launch_kessler(c, S->rho, S->rhotheta, S->rhoq, dt, w.precip);
+        if (e != hipSuccess) return hip_fail(c, e, "microphysics launch");
+    }
     return ERF_OK;
+}
+
+erf_status erf_kessler(erf_ctx *c, erf_state *S, double dt, double *precip)
+{
+    ERF_CHECK_CTX(c);
+    if (!c->have_base) return fail(c, ERF_E_STATE, "erf_init_base_state must come first");
+    if (!c->prm.moist) return fail(c, ERF_E_UNSUPPORTED, "the microphysics needs a moist context");
+    if (!S || !S->rho || !S->rhotheta || !S->rhoq || !(dt > 0.0)) return fail(c, ERF_E_ARG, "S with rhoq and dt > 0");
+    hipError_t e = launch_kessler(c, S->rho, S->rhotheta, S->rhoq, dt, precip ? precip : c->ws.precip);
+    return e == hipSuccess ? ERF_OK : hip_fail(c, e, "microphysics launch");
+}
+
+erf_status erf_precipitation(erf_ctx *c, double *host_out, int32_t reset)
+{
+    ERF_CHECK_CTX(c);
+    if (!host_out) return fail(c, ERF_E_ARG, "host_out is NULL");
+    const size_t bytes = (size_t)c->d.nxy * sizeof(double);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(host_out, c->ws.precip, bytes, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && reset) e = hipMemsetAsync(c->ws.precip, 0, bytes, c->stream);
+    if (e == hipSuccess && reset) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? ERF_OK : hip_fail(c, e, "reading the precipitation");
 }
 
 erf_status erf_timing_begin(erf_ctx *c, const char *kernel, int32_t max_launches)

@@ -303,6 +303,8 @@ struct Workspace {
     // the moist Exner function pi^t and rho_d / rho_m = 1/(1 + q_v + q_c + q_r)
     // of the stage state (the acoustic coefficients)
     void *qf = nullptr, *bm = nullptr, *pex = nullptr, *rdm = nullptr;
+    // rain accumulated at the ground by the microphysics [kg/m^2], [ny][nx]
+    double *precip = nullptr;
     // learned closure: rho tau_11, 22, 33, 12, 13, 23 and rho q_1, 2, 3 at
     // centres (allocated for the learned closure only)
     void *sg[9] = {};
@@ -394,11 +396,11 @@ namespace erfk {
 
 // kernel ids for the timing instrumentation
 enum KernelId { K_PREP, K_MUT, K_STRESS, K_RHS, K_STAGE_INIT, K_COEF, K_SUBSTEP, K_FINALIZE, K_MIXRATIO, K_SCALAR,
-                K_MLP, K_MLP_DIV, K_COUNT };
+                K_MLP, K_MLP_DIV, K_KESSLER, K_COUNT };
 inline const char *kernel_name(int id)
 {
     static const char *names[K_COUNT] = {"prep", "mut", "stress", "rhs", "stage_init", "coef", "substep",
-                                         "finalize", "mixing_ratio", "scalar", "mlp", "mlp_div"};
+                                         "finalize", "mixing_ratio", "scalar", "mlp", "mlp_div", "kessler"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 // The batched instance KB of a kernel, launched over the block ranges of map
@@ -491,6 +493,9 @@ size_t train_partial_doubles(int64_t cap);
 hipError_t launch_loss_grad(erf_ctx *c, const float *X, const float *T, int64_t n, float *G, double *loss_dev,
                             float *tbuf, float *part, size_t pf, double *dpart);
 hipError_t launch_adam(erf_ctx *c, double lr, int64_t step);
+// micro.hip: Kessler microphysics over dt on S (rho, rho theta, rho q);
+// precip (may be null) accumulates the rain reaching the ground
+hipError_t launch_kessler(erf_ctx *c, void *rho, void *rt, void *rq, double dt, double *precip);
 // diag.hip
 size_t diag_slots_needed();
 hipError_t launch_diagnostics(erf_ctx *c, const void *const S[6], double *host_out);

@@ -33,7 +33,7 @@ MLP_NOALLOC_MAX_BATCH = 8192  # ERF_MLP_NOALLOC_MAX_BATCH of include/erf_mlp.h
 # every symbol include/erf.h, include/erf_mlp.h and include/erf_ensemble.h declare
 EXPORTS = ("erf_base_state_host", "erf_create", "erf_destroy", "erf_last_error", "erf_workspace_bytes",
            "erf_init_base_state", "erf_slow_rhs", "erf_acoustic_substeps", "erf_scalar_advance",
-           "erf_rk3_step", "erf_diagnostics", "erf_timing_begin", "erf_timing_end", "erf_layout", "erf_autotune",
+           "erf_rk3_step", "erf_kessler", "erf_precipitation", "erf_diagnostics", "erf_timing_begin", "erf_timing_end", "erf_layout", "erf_autotune",
            "erf_mlp_set_weights", "erf_mlp_get_weights", "erf_mlp_forward", "erf_mlp_features",
            "erf_box_filter", "erf_mlp_fit_norm", "erf_mlp_standardize", "erf_mlp_loss_grad",
            "erf_mlp_train_step", "erf_mlp_loss_grad_noalloc", "erf_mlp_fallback_count",
@@ -62,7 +62,7 @@ class Params(C.Structure):
                 ("Cs", C.c_double), ("Pr_t", C.c_double), ("nu_m", C.c_double), ("alpha_m", C.c_double),
                 ("f_cor", C.c_double), ("Ug", C.c_double), ("Vg", C.c_double),
                 ("surf_heat_flux", C.c_double), ("grav", C.c_double), ("precision", C.c_int32),
-                ("moist", C.c_int32)]
+                ("moist", C.c_int32), ("microphysics", C.c_int32)]
 
 
 class State(C.Structure):
@@ -121,6 +121,8 @@ def load(path: str = LIB_PATH):
             L.erf_scalar_advance.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(State), C.POINTER(State),
                                              C.c_double, C.c_void_p]
             L.erf_rk3_step.argtypes = [C.c_void_p, C.POINTER(State)]
+            L.erf_kessler.argtypes = [C.c_void_p, C.POINTER(State), C.c_double, C.c_void_p]
+            L.erf_precipitation.argtypes = [C.c_void_p, _DP, C.c_int32]
             L.erf_diagnostics.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(Diag)]
             L.erf_timing_begin.argtypes = [C.c_void_p, C.c_char_p, C.c_int32]
             L.erf_timing_end.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -200,7 +202,8 @@ def params_from_config(cfg) -> Params:
     prec = {"fp64": ERF_FP64, "fp32": ERF_FP32_MIXED}[cfg.prec]
     return Params(cfg.dt, cfg.n_substeps, cfg.beta_s, cfg.beta_d, cfg.adv_order_h, cfg.adv_order_v,
                   cfg.scalar_scheme, cfg.n_scalars, cfg.sgs, cfg.Cs, cfg.Pr_t, cfg.nu_m, cfg.alpha_m,
-                  cfg.f_cor, cfg.Ug, cfg.Vg, cfg.surf_heat_flux, cfg.grav, prec, int(getattr(cfg, "moist", 0)))
+                  cfg.f_cor, cfg.Ug, cfg.Vg, cfg.surf_heat_flux, cfg.grav, prec, int(getattr(cfg, "moist", 0)),
+                  int(getattr(cfg, "microphysics", 0)))
 
 
 def layout(cfg, field: str) -> dict:
@@ -372,6 +375,22 @@ class Solver:
     def rk3_step(self, S):
         self._check(self.L.erf_rk3_step(self.h, C.byref(self._st(S))), "erf_rk3_step")
         return S
+
+    def kessler(self, S, dt: float, precip=None):
+        """erf_kessler: Kessler microphysics over dt on S in place; precip (a
+        float64 tensor [ny][nx] on the device) accumulates the rain reaching
+        the ground, else the context's own accumulator does."""
+        self._check(self.L.erf_kessler(self.h, C.byref(self._st(S)), float(dt),
+                                       None if precip is None else
+                                       self._dev(precip, self.torch.float64, (self.cfg.ny, self.cfg.nx), "precip")),
+                    "erf_kessler")
+        return S
+
+    def precipitation(self, reset: bool = False) -> np.ndarray:
+        """The context's accumulated precipitation [kg/m^2], [ny][nx]."""
+        out = np.zeros((self.cfg.ny, self.cfg.nx))
+        self._check(self.L.erf_precipitation(self.h, _np_ptr(out), int(bool(reset))), "erf_precipitation")
+        return out
 
     def autotune(self, S, trials: int = 3, cache_path: str | None = None) -> dict:
         """erf_autotune: time the acoustic substep's launch shapes on S (which

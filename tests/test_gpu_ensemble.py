@@ -93,12 +93,13 @@ def test_batched_step_equals_sequential_bitwise(batched, branches):
 
 def test_batched_with_scalars_and_moisture():
     """Members that transport scalars (WENO5 and an interpolant, FP32 and FP64,
-    one moist) beside plain ones: the batched mixing-ratio, scalar, finalize and
-    moist launches give the sequential result bitwise."""
+    moist, one with Kessler microphysics) beside plain ones: the batched
+    mixing-ratio, scalar, finalize, moist and microphysics launches give the
+    sequential result bitwise."""
     from paper_2412_04395_amd import erf
     base = dict(dx=250.0, dy=250.0, dt=2.0, n_substeps=8, adv_order_h=3, adv_order_v=3)
     cfgs = [W.small(name="deep_small", nx=36, ny=20, nz=14, dz=W.stretched_dz(14, 50.0, 500.0, 4000.0), seed=81,
-                    n_scalars=3, scalar_scheme=1, moist=1, prec="fp32", **base),
+                    n_scalars=3, scalar_scheme=1, moist=1, microphysics=1, prec="fp32", **base),
             W.small(name="deep_small", nx=24, ny=30, nz=12, dz=W.uniform_dz(12, 200.0), seed=82, n_scalars=3,
                     scalar_scheme=0, prec="fp64", **base),
             W.small(name="deep_small", nx=40, ny=16, nz=14, dz=W.stretched_dz(14, 50.0, 500.0, 4000.0), seed=83,
