@@ -39,7 +39,8 @@ class _Params(C.Structure):
                 ("alpha_m", C.c_double), ("f_cor", C.c_double), ("Ug", C.c_double),
                 ("Vg", C.c_double), ("surf_heat_flux", C.c_double), ("grav", C.c_double),
                 ("mlp_params", C.POINTER(C.c_double)), ("mlp_norm", C.POINTER(C.c_double)),
-                ("mlp_bf16", C.c_int32), ("moist", C.c_int32)]
+                ("mlp_bf16", C.c_int32), ("moist", C.c_int32), ("anelastic", C.c_int32),
+                ("p_anel", C.POINTER(C.c_double))]
 
 
 class _Base(C.Structure):
@@ -112,6 +113,11 @@ def lib():
             L.orc_sgs_features.argtypes = [C.POINTER(_Grid), C.POINTER(_State), _DP]
             L.orc_box_filter.argtypes = [C.POINTER(_Grid), C.POINTER(_State), C.c_int32, C.c_double, C.c_double,
                                          C.POINTER(_State), _DP]
+            L.orc_divergence.argtypes = [C.POINTER(_Grid), _DP, _DP, _DP, _DP]
+            L.orc_poisson.argtypes = [C.POINTER(_Grid), _DP, _DP]
+            L.orc_project.argtypes = [C.POINTER(_Grid), _DP, _DP, _DP, C.c_double, _DP]
+            L.orc_ssprk2_step.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Base),
+                                          C.POINTER(_State), _DP]
             L.orc_slow_rhs_mlp.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Base),
                                            C.POINTER(_State), _DP, _DP, C.c_int, C.POINTER(_State),
                                            C.POINTER(C.c_int64)]
@@ -139,8 +145,12 @@ class Oracle:
         self._params = _Params(cfg.dt, cfg.n_substeps, cfg.beta_s, cfg.beta_d, cfg.adv_order_h,
                                cfg.adv_order_v, cfg.scalar_scheme, cfg.n_scalars, cfg.sgs, cfg.Cs,
                                cfg.Pr_t, cfg.nu_m, cfg.alpha_m, cfg.f_cor, cfg.Ug, cfg.Vg,
-                               cfg.surf_heat_flux, cfg.grav, None, None, 0, int(cfg.moist))
+                               cfg.surf_heat_flux, cfg.grav, None, None, 0, int(cfg.moist),
+                               int(getattr(cfg, "anelastic", 0)), None)
         self.base = None
+        # anelastic mode: the lagged perturbation pressure (Sec. 3.2)
+        self.p_anel = np.zeros((cfg.nz, cfg.ny, cfg.nx))
+        self._params.p_anel = _p(self.p_anel)
         self._mlp = None
 
     def set_mlp(self, params, norm, bf16: bool = False):
@@ -225,6 +235,37 @@ class Oracle:
                                        C.byref(self._st(S))), "orc_rk3_step")
         if getattr(self.cfg, "microphysics", 0):
             self.kessler(S, self.cfg.dt)
+        return S
+
+    # -- anelastic mode (Sec. 2.2, Sec. 3.2) --------------------------------
+    def divergence(self, ru, rv, rw):
+        """Finite-volume divergence of face momenta at the cell centres."""
+        D = np.zeros((self.nz, self.ny, self.nx))
+        a = [np.ascontiguousarray(x, dtype=np.float64) for x in (ru, rv, rw)]
+        self._check(lib().orc_divergence(C.byref(self._grid), _p(a[0]), _p(a[1]), _p(a[2]), _p(D)),
+                    "orc_divergence")
+        return D
+
+    def poisson(self, D):
+        """phi with D(G(phi)) = D (gauge: the horizontal mean of phi in the
+        lowest cell is zero)."""
+        Dc = np.ascontiguousarray(D, dtype=np.float64)
+        phi = np.zeros_like(Dc)
+        self._check(lib().orc_poisson(C.byref(self._grid), _p(Dc), _p(phi)), "orc_poisson")
+        return phi
+
+    def project(self, S, dt: float, pp=None):
+        """Project the face momenta of S in place; pp (in place, may be None)
+        gains psi = phi / dt."""
+        self._check(lib().orc_project(C.byref(self._grid), _p(S["ru"]), _p(S["rv"]), _p(S["rw"]), float(dt),
+                                      None if pp is None else _p(pp)), "orc_project")
+        return S
+
+    def ssprk2_step(self, S):
+        """One anelastic SSP-RK2 step in place; self.p_anel is the lagged
+        perturbation pressure, updated in place."""
+        self._check(lib().orc_ssprk2_step(C.byref(self._grid), C.byref(self._params), C.byref(self._base),
+                                          C.byref(self._st(S)), _p(self.p_anel)), "orc_ssprk2_step")
         return S
 
     def kessler(self, S, dt: float):

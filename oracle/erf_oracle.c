@@ -445,6 +445,7 @@ int orc_slow_rhs_mlp(const orc_grid *g, const orc_params *P, const orc_base *B, 
 int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                  const orc_state *S, orc_state *R)
 {
+    if (P->anelastic && (P->moist || P->sgs == 2 || !P->p_anel)) return -1;
     if (P->sgs == 2) {
         if (!P->mlp_params || !P->mlp_norm) return -1;
         return orc_slow_rhs_mlp(g, P, B, S, P->mlp_params, P->mlp_norm, P->mlp_bf16, R, NULL);
@@ -474,6 +475,10 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                 pp[c] = orc_eos_pprime_moist(S->rt[c], qv, T0, qv0, B->p0[k]);
                 qf[c] = 1.0 + qv + qc;
                 bm[c] = (S->rho[c] - B->rho0[k]) + (rqv + rqc + rqr) - B->rho0[k] * qv0;
+            } else if (P->anelastic) {
+                /* anelastic: the pressure perturbation is the one the
+                 * projections left, not a function of the state (Sec. 2.2) */
+                pp[c] = P->p_anel[c];
             } else {
                 pp[c] = orc_eos_pprime(S->rt[c], T0, B->p0[k]);
             }
@@ -594,6 +599,12 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                     double buoy = -gr * 0.5 * (bm[c] + bm[cm]);
                     double qfm = 0.5 * (qf[cm] + qf[c]);
                     R->rw[c] = -adv - pgf / qfm + buoy / qfm;
+                } else if (P->anelastic) {
+                    /* anelastic buoyancy g rho0 (theta - theta0) / theta0
+                     * (Sec. 2.2), the mean of the two cells on the face */
+                    double b_up = B->rho0[k] * (th[c] - B->theta0[k]) / B->theta0[k];
+                    double b_dn = B->rho0[k - 1] * (th[cm] - B->theta0[k - 1]) / B->theta0[k - 1];
+                    R->rw[c] = -adv - pgf + gr * 0.5 * (b_up + b_dn);
                 } else {
                     double buoy = -gr * 0.5 * ((S->rho[c] - B->rho0[k]) + (S->rho[cm] - B->rho0[k - 1]));
                     R->rw[c] = -adv - pgf + buoy;
@@ -1621,4 +1632,194 @@ int orc_kessler(const orc_grid *g, const orc_params *P, const orc_base *B, orc_s
         }
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* anelastic mode (Sec. 2.2, Sec. 3.2)                                       */
+/* ------------------------------------------------------------------------ */
+static const double TWO_PI = 6.283185307179586476925286766559;
+
+/* finite-volume divergence of the face momenta, eq. (anelastic) */
+int orc_divergence(const orc_grid *g, const double *ru, const double *rv, const double *rw, double *D)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                D[c] = (cget(g, ru, i + 1, j, k) - ru[c]) / g->dx + (cget(g, rv, i, j + 1, k) - rv[c]) / g->dy +
+                       (rw[CIDX(g, i, j, k + 1)] - rw[c]) / g->dz[k];
+            }
+    return 0;
+}
+
+/* The discrete Fourier transform by its definition, out_m = sum_t in_t
+ * exp(sign 2 pi i m t / n), of n values read with stride s, written to
+ * contiguous out arrays; cs/sn hold cos and sin of 2 pi r / n for r < n,
+ * indexed by the phase m t reduced modulo n. */
+static void dft(int n, int s, const double *re, const double *im, double *ore, double *oim, int sign,
+                const double *cs, const double *sn)
+{
+    for (int m = 0; m < n; ++m) {
+        double sr = 0.0, si = 0.0;
+        for (int t = 0; t < n; ++t) {
+            long r = ((long)m * t) % n;
+            double cr = cs[r], ci = sign * sn[r];
+            sr += re[(size_t)t * s] * cr - im[(size_t)t * s] * ci;
+            si += re[(size_t)t * s] * ci + im[(size_t)t * s] * cr;
+        }
+        ore[m] = sr;
+        oim[m] = si;
+    }
+}
+
+/* transform every x-line (dir 0) or y-line (dir 1) of every level in place */
+static void dft_lines(const orc_grid *g, double *re, double *im, int dir, int sign)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    int len = dir == 0 ? nx : ny, stride = dir == 0 ? 1 : nx, lines = dir == 0 ? ny : nx;
+    double *tr = dalloc(len), *ti = dalloc(len), *cs = dalloc(len), *sn = dalloc(len);
+    for (int r = 0; r < len; ++r) {
+        cs[r] = cos(TWO_PI * r / len);
+        sn[r] = sin(TWO_PI * r / len);
+    }
+    for (int k = 0; k < nz; ++k)
+        for (int l = 0; l < lines; ++l) {
+            size_t b = dir == 0 ? CIDX(g, 0, l, k) : CIDX(g, l, 0, k);
+            dft(len, stride, re + b, im + b, tr, ti, sign, cs, sn);
+            for (int t = 0; t < len; ++t) {
+                re[b + (size_t)t * stride] = tr[t];
+                im[b + (size_t)t * stride] = ti[t];
+            }
+        }
+    free(tr);
+    free(ti);
+    free(cs);
+    free(sn);
+}
+
+int orc_poisson(const orc_grid *g, const double *D, double *phi)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    if (nx < 1 || ny < 1 || nz < 1) return -2;
+    size_t n = (size_t)nx * ny * nz;
+    double *re = dalloc(n), *im = dalloc(n);
+    memcpy(re, D, n * sizeof(double));
+    dft_lines(g, re, im, 0, -1);
+    dft_lines(g, re, im, 1, -1);
+    /* per horizontal wavenumber (m, l): the x and y second differences act
+     * on exp(2 pi i (m x/nx dx + l y/ny dy)) as multiplication by
+     * -4 sin^2(pi m/nx)/dx^2 - 4 sin^2(pi l/ny)/dy^2; the z operator stays a
+     * tridiagonal matrix, with no flux through the lids */
+    double *a = dalloc(nz), *b = dalloc(nz), *c = dalloc(nz), *rr = dalloc(nz), *ri = dalloc(nz);
+    double *xr = dalloc(nz), *xi = dalloc(nz);
+    for (int l = 0; l < ny; ++l)
+        for (int m = 0; m < nx; ++m) {
+            double sx = sin(0.5 * TWO_PI * m / nx), sy = sin(0.5 * TWO_PI * l / ny);
+            double lam = -4.0 * sx * sx / (g->dx * g->dx) - 4.0 * sy * sy / (g->dy * g->dy);
+            for (int k = 0; k < nz; ++k) {
+                a[k] = k > 0 ? 1.0 / (g->dz[k] * 0.5 * (g->dz[k - 1] + g->dz[k])) : 0.0;
+                c[k] = k < nz - 1 ? 1.0 / (g->dz[k] * 0.5 * (g->dz[k] + g->dz[k + 1])) : 0.0;
+                b[k] = -a[k] - c[k] + lam;
+                rr[k] = re[CIDX(g, m, l, k)];
+                ri[k] = im[CIDX(g, m, l, k)];
+            }
+            if (m == 0 && l == 0) {
+                /* the gauge: this mode's value in the lowest cell is zero */
+                b[0] = 1.0;
+                c[0] = 0.0;
+                rr[0] = 0.0;
+                ri[0] = 0.0;
+            }
+            orc_thomas(nz, a, b, c, rr, xr);
+            orc_thomas(nz, a, b, c, ri, xi);
+            for (int k = 0; k < nz; ++k) {
+                re[CIDX(g, m, l, k)] = xr[k];
+                im[CIDX(g, m, l, k)] = xi[k];
+            }
+        }
+    dft_lines(g, re, im, 1, 1);
+    dft_lines(g, re, im, 0, 1);
+    for (size_t q = 0; q < n; ++q) phi[q] = re[q] / ((double)nx * ny);
+    free(re); free(im); free(a); free(b); free(c); free(rr); free(ri); free(xr); free(xi);
+    return 0;
+}
+
+int orc_project(const orc_grid *g, double *ru, double *rv, double *rw, double dt, double *pp)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    size_t n = (size_t)nx * ny * nz;
+    double *D = dalloc(n), *phi = dalloc(n);
+    orc_divergence(g, ru, rv, rw, D);
+    int rc = orc_poisson(g, D, phi);
+    if (rc == 0) {
+        /* (rho0 u)^new = (rho0 u)^* - dt grad psi with dt psi = phi */
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    size_t c = CIDX(g, i, j, k);
+                    ru[c] -= (phi[c] - cget(g, phi, i - 1, j, k)) / g->dx;
+                    rv[c] -= (phi[c] - cget(g, phi, i, j - 1, k)) / g->dy;
+                    if (k > 0) rw[c] -= (phi[c] - phi[CIDX(g, i, j, k - 1)]) / (0.5 * (g->dz[k - 1] + g->dz[k]));
+                    if (pp) pp[c] += phi[c] / dt;
+                }
+    }
+    free(D);
+    free(phi);
+    return rc;
+}
+
+/* S^* = S^n + dt f(S^n), projected; S^{n+1} = S^n + dt (f(S^n) + f(S^*)) / 2,
+ * projected.  The slow right-hand side uses the latest perturbation pressure
+ * (lagged in the first stage).  Scalars follow the same two stages with the
+ * current momenta as fluxes (continuity is the constraint, so the mixing
+ * ratio is rho q / rho0). */
+int orc_ssprk2_step(const orc_grid *g, const orc_params *P, const orc_base *B, orc_state *S, double *pp)
+{
+    if (!P->anelastic || !pp) return -1;
+    int nx = g->nx, ny = g->ny, nz = g->nz, nq = P->n_scalars;
+    size_t n = (size_t)nx * ny * nz, nw = (size_t)nx * ny * (nz + 1), nqn = (size_t)(nq > 0 ? nq : 0) * n;
+    double dt = P->dt;
+    orc_params Q = *P;
+    Q.p_anel = pp;
+    orc_state R1, R2, Ss;
+    double *bufs[3][6];
+    size_t sz[6] = {n, n, n, n, nw, nqn};
+    for (int b = 0; b < 3; ++b)
+        for (int f = 0; f < 6; ++f) bufs[b][f] = dalloc(sz[f]);
+#define BIND(st, b) st.rho = bufs[b][0], st.rt = bufs[b][1], st.ru = bufs[b][2], st.rv = bufs[b][3], st.rw = bufs[b][4], st.rq = bufs[b][5]
+    BIND(R1, 0);
+    BIND(R2, 1);
+    BIND(Ss, 2);
+#undef BIND
+    double *tmp = dalloc(nqn);
+    int rc = orc_slow_rhs(g, &Q, B, S, &R1);
+    if (rc == 0) {
+        memcpy(Ss.rho, S->rho, n * 8);
+        for (size_t c = 0; c < n; ++c) {
+            Ss.rt[c] = S->rt[c] + dt * R1.rt[c];
+            Ss.ru[c] = S->ru[c] + dt * R1.ru[c];
+            Ss.rv[c] = S->rv[c] + dt * R1.rv[c];
+        }
+        for (size_t c = 0; c < nw; ++c) Ss.rw[c] = S->rw[c] + dt * R1.rw[c];
+        if (nq > 0) rc = orc_scalar_advance(g, &Q, S, S, S->ru, S->rv, S->rw, dt, Ss.rq);
+    }
+    if (rc == 0) rc = orc_project(g, Ss.ru, Ss.rv, Ss.rw, dt, pp);
+    if (rc == 0) rc = orc_slow_rhs(g, &Q, B, &Ss, &R2);
+    if (rc == 0 && nq > 0) rc = orc_scalar_advance(g, &Q, S, &Ss, Ss.ru, Ss.rv, Ss.rw, dt, tmp);
+    if (rc == 0) {
+        for (size_t c = 0; c < n; ++c) {
+            S->rt[c] = S->rt[c] + 0.5 * dt * (R1.rt[c] + R2.rt[c]);
+            S->ru[c] = S->ru[c] + 0.5 * dt * (R1.ru[c] + R2.ru[c]);
+            S->rv[c] = S->rv[c] + 0.5 * dt * (R1.rv[c] + R2.rv[c]);
+        }
+        for (size_t c = 0; c < nw; ++c) S->rw[c] = S->rw[c] + 0.5 * dt * (R1.rw[c] + R2.rw[c]);
+        /* (rho q)^n - dt (div^n + div^*)/2 = ((rho q)^* + (rho q)^n - dt div^*)/2 */
+        for (size_t c = 0; c < nqn; ++c) S->rq[c] = 0.5 * (Ss.rq[c] + tmp[c]);
+        rc = orc_project(g, S->ru, S->rv, S->rw, dt, pp);
+    }
+    for (int b = 0; b < 3; ++b)
+        for (int f = 0; f < 6; ++f) free(bufs[b][f]);
+    free(tmp);
+    return rc;
 }

@@ -53,6 +53,12 @@ typedef struct {
      * they enter the EOS, the pressure-gradient and buoyancy terms and the
      * acoustic coefficients (Sec. 2.1, App. C); needs n_scalars >= 3 */
     int32_t moist;
+    /* anelastic equation set (Sec. 2.2): rho stays at rho0, the pressure
+     * gradient uses the lagged perturbation pressure p_anel [nz][ny][nx]
+     * instead of the equation of state, and the buoyancy is
+     * g rho0 (theta - theta0) / theta0; dry only */
+    int32_t anelastic;
+    const double *p_anel;
 } orc_params;
 
 typedef struct {
@@ -191,6 +197,27 @@ double orc_esat(double T);
 double orc_qvsat(double T, double p);
 /* the condensed amount of the saturation adjustment at fixed pressure */
 double orc_sat_adjust(double T, double p, double qv, double qc);
+
+/* ---------------- anelastic mode (Sec. 2.2, Sec. 3.2) ---------------- */
+/* Discrete divergence of face momenta at the cell centres: the left side of
+ * the constraint div(rho0 u) = 0, eq. (anelastic).  rw is zero on the lids. */
+int orc_divergence(const orc_grid *g, const double *ru, const double *rv, const double *rw, double *D);
+/* Poisson problem of the projection: L phi = D with L = D(G(.)) the C-grid
+ * divergence of the face gradient (periodic in x and y, no flux through the
+ * lids).  Solved by discrete Fourier transforms in x and y and a tridiagonal
+ * solve per horizontal wavenumber in z.  The constant null space is fixed by
+ * giving the horizontally uniform part of phi the value 0 in the lowest cell.
+ * D must have zero volume-weighted sum (the divergence of lid-bounded face
+ * fields has it). */
+int orc_poisson(const orc_grid *g, const double *D, double *phi);
+/* Projection (Sec. 3.2): solves L phi = div(rho u) with phi = dt psi,
+ * subtracts grad phi from the face momenta (in place) and adds psi = phi / dt
+ * to the perturbation pressure pp [nz][ny][nx] (NULL: not kept). */
+int orc_project(const orc_grid *g, double *ru, double *rv, double *rw, double dt, double *pp);
+/* One SSP-RK2 step of the anelastic equations with projections after each
+ * stage (Sec. 3.2), in place; pp is the lagged perturbation pressure
+ * [nz][ny][nx], updated in place.  S->rho must hold rho0 of each level. */
+int orc_ssprk2_step(const orc_grid *g, const orc_params *P, const orc_base *B, orc_state *S, double *pp);
 
 #ifdef __cplusplus
 }

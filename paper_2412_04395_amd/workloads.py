@@ -58,6 +58,7 @@ class Config:
     prec: str = "fp64"  # "fp64" or "fp32" (FP32 bulk, FP64 column solve and sums)
     moist: int = 0  # 1: scalars 0, 1, 2 are rho q_v, rho q_c, rho q_r and enter the dynamics
     microphysics: int = 0  # 1: Kessler warm rain after every RK3 step (needs moist)
+    anelastic: int = 0  # 1: anelastic equation set, SSP-RK2 with projections (dry, FP64)
     p_surface: float = 1.0e5
     seed: int = 1
 
