@@ -98,6 +98,15 @@ typedef struct {
     int32_t microphysics;    /* 1: Kessler warm rain (erf_kessler) over dt after
                                 every erf_rk3_step, the rain reaching the ground
                                 accumulated by the context; needs moist.  0: none */
+    int32_t anelastic;       /* 1: the anelastic equation set (Sec. 2.2): density
+                                fixed at rho0(z), the constraint div(rho0 u) = 0,
+                                buoyancy g rho0 (theta - theta0) / theta0 and a
+                                perturbation pressure that only the projections
+                                set; stepped by erf_ssprk2_step (Sec. 3.2).
+                                Needs ERF_FP64, a dry context, no learned
+                                closure, and nx, ny powers of two <= 2048
+                                (ERF_E_SHAPE otherwise); n_substeps is then
+                                ignored.  0: compressible                        */
 } erf_params;
 
 /* Device pointers to one state (or tendency, or flux) set; unused members may
@@ -195,7 +204,10 @@ erf_status erf_init_base_state(erf_ctx *ctx, const double *theta0, const double 
  * (Sec. 3.7-3.8).  Moist contexts: the pressure gradient and the buoyancy
  * -g (rho (1 + q_v + q_c + q_r) - rho0 (1 + qv0)) are divided by the face
  * mean of 1 + q_v + q_c, and p' follows the moist equation of state; S->rhoq
- * must then be given.  S and R use the state layout; R->rhoq is ignored and
+ * must then be given.  Anelastic contexts: p' is the context's perturbation
+ * pressure (erf_anelastic_pressure) and the buoyancy g rho0 (theta - theta0) /
+ * theta0 on the face (mean of its two cells); R->rho is then -div(rho0 u).
+ * S and R use the state layout; R->rhoq is ignored and
  * may be NULL.  R->rhow is zero on faces 0 and nz. */
 erf_status erf_slow_rhs(erf_ctx *ctx, const erf_state *S, erf_state *R);
 
@@ -243,6 +255,34 @@ erf_status erf_kessler(erf_ctx *ctx, erf_state *S, double dt, double *precip);
  * double[ny][nx]); reset = 1 then sets it to zero.  Synchronous. */
 erf_status erf_precipitation(erf_ctx *ctx, double *host_out, int32_t reset);
 
+/* Anelastic contexts (erf_params.anelastic).
+ *
+ * erf_project: the projection of Sec. 3.2.  Solves dt div grad psi =
+ * div(rho u) for the face momenta of S (the C-grid divergence, periodic in x
+ * and y, no flux through the lids) by discrete Fourier transforms in x and y
+ * and a tridiagonal solve per horizontal wavenumber in z, the horizontally
+ * uniform part of psi being zero in the lowest cell; then rho u -= dt grad psi
+ * on every face (S->rhou, rhov, rhow in place; only those three are used) and
+ * adds psi to the context's perturbation pressure.  ERF_E_UNSUPPORTED on a
+ * compressible context.
+ *
+ * erf_ssprk2_step: one step of dt (Sec. 3.2): S* = S^n + dt f(S^n) with the
+ * lagged perturbation pressure, projected; S^{n+1} = S^n + dt (f(S^n) +
+ * f(S*)) / 2, projected; each projection adds its psi to the pressure.
+ * Scalars take the same two stages with the current momenta as fluxes and
+ * q = rho q / rho (erf_scalar_advance).  S->rho must hold rho0 of each level
+ * and is not changed; S holds S^n on entry and S^{n+1} on return (in place).
+ * Uses the workspace of the RK3 driver.  ERF_E_UNSUPPORTED on a compressible
+ * context, which steps with erf_rk3_step (which an anelastic context refuses,
+ * as it refuses erf_acoustic_substeps and erf_autotune).
+ *
+ * erf_anelastic_pressure: copies the context's perturbation pressure p'
+ * (device double[nz][ny][nx], zero when the context is created) to p
+ * (set = 0) or from p (set = 1), device to device on the context's stream. */
+erf_status erf_project(erf_ctx *ctx, erf_state *S, double dt);
+erf_status erf_ssprk2_step(erf_ctx *ctx, erf_state *S);
+erf_status erf_anelastic_pressure(erf_ctx *ctx, void *p, int32_t set);
+
 /* FP64 global sums of the mass and energy budgets (Sec. 4.1.2) and a count of
  * non-finite values.  Synchronous.  Returns ERF_E_NONFINITE (with *out filled)
  * if any state value is NaN or Inf. */
@@ -267,7 +307,9 @@ erf_status erf_autotune(erf_ctx *ctx, erf_state *S, int32_t trials, const char *
  * max_launches launches are timed, later ones run untimed.  Kernel names:
  * "prep", "mut", "stress", "rhs", "stage_init", "coef", "substep", "finalize",
  * "mixing_ratio", "scalar", "mlp" (closure network), "mlp_div" (its stress
- * divergence), "kessler" (microphysics).  erf_timing_begin allocates the events
+ * divergence), "kessler" (microphysics), and of the anelastic step
+ * "ssp_update", "div_fftx", "ffty" (both directions), "poisson_z", "ifftx",
+ * "project".  erf_timing_begin allocates the events
  * (ERF_E_NOMEM on failure) and returns ERF_E_ARG for an unknown name. */
 erf_status erf_timing_begin(erf_ctx *ctx, const char *kernel, int32_t max_launches);
 /* Waits for the stream, returns the summed event time [ms] of the timed

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "erf_internal.h"
 
@@ -106,7 +107,15 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     if (!(grid->dx > 0.0) || !(grid->dy > 0.0)) return ERF_E_ARG;
     for (int k = 0; k < grid->nz; ++k)
         if (!(grid->dz[k] > 0.0)) return ERF_E_ARG;
-    if (prm->n_substeps < 2 || prm->n_substeps % 2 != 0) return ERF_E_ARG;
+    if (prm->anelastic != 0 && prm->anelastic != 1) return ERF_E_ARG;
+    const bool anel = prm->anelastic != 0;
+    if (!anel && (prm->n_substeps < 2 || prm->n_substeps % 2 != 0)) return ERF_E_ARG;
+    if (anel) {
+        // the projection's transforms: powers of two up to 2048 in x and y
+        auto pow2 = [](int v) { return v >= 1 && v <= 2048 && (v & (v - 1)) == 0; };
+        if (!pow2(grid->nx) || !pow2(grid->ny)) return ERF_E_SHAPE;
+        if (prm->precision != ERF_FP64 || prm->moist || prm->sgs == ERF_SGS_MLP) return ERF_E_UNSUPPORTED;
+    }
     if (prm->adv_order_h < 2 || prm->adv_order_h > 6 || prm->adv_order_v < 2 || prm->adv_order_v > 6)
         return ERF_E_ARG;
     if (nq < 0 || nq > 8) return ERF_E_ARG;
@@ -147,6 +156,8 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     const size_t nzs = (size_t)grid->nz;
     const size_t G = prm->sgs == ERF_SGS_MLP ? N : 0;
     const size_t M = prm->moist ? N : 0;
+    const size_t A8 = anel ? n * sizeof(double) : 0, A16 = anel ? n * sizeof(double2) : 0;
+    Anel &an = c->an;
     Req reqs[] = {
         {&ws.sa[0], N}, {&ws.sa[1], N}, {&ws.sa[2], N}, {&ws.sa[3], N}, {&ws.sa[4], Wb}, {&ws.sa[5], Q},
         {&ws.sb[0], N}, {&ws.sb[1], N}, {&ws.sb[2], N}, {&ws.sb[3], N}, {&ws.sb[4], Wb}, {&ws.sb[5], Q},
@@ -166,6 +177,9 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
         {(void **)&b.rho0, nzs * D}, {(void **)&b.theta0, nzs * D}, {(void **)&b.Theta0, nzs * D},
         {(void **)&b.p0, nzs * D}, {(void **)&b.pi0, nzs * D}, {(void **)&b.dz, (5 * nzs + 1) * D},
         {(void **)&b.qv0, nzs * D}, {(void **)&b.rho0t, nzs * D},
+        {(void **)&an.pa, A8}, {(void **)&an.Z, A16}, {(void **)&an.cp, A8}, {(void **)&an.phi, A8},
+        {(void **)&an.twx, anel ? (size_t)(grid->nx / 2) * sizeof(double2) : 0},
+        {(void **)&an.twy, anel ? (size_t)(grid->ny / 2) * sizeof(double2) : 0},
     };
     size_t total = 0;
     for (const Req &r : reqs) total += align_up(r.bytes);
@@ -211,6 +225,25 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     if (e != hipSuccess) {
         erf_destroy(c);
         return ERF_E_HIP;
+    }
+    if (anel) {
+        // twiddle factors exp(-2 pi i t / N), t < N/2, of the two transform lengths
+        for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
+            const int N = dir == 0 ? grid->nx : grid->ny;
+            int lg = 0;
+            while ((1 << lg) < N) ++lg;
+            (dir == 0 ? an.lgx : an.lgy) = lg;
+            if (N < 2) continue;
+            std::vector<double2> tw(N / 2);
+            const double two_pi = 6.283185307179586476925286766559;
+            for (int q = 0; q < N / 2; ++q) tw[q] = make_double2(std::cos(two_pi * q / N), -std::sin(two_pi * q / N));
+            e = hipMemcpy(dir == 0 ? an.twx : an.twy, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice);
+        }
+        if (e == hipSuccess) e = hipMemset(an.pa, 0, n * sizeof(double));
+        if (e != hipSuccess) {
+            erf_destroy(c);
+            return ERF_E_HIP;
+        }
     }
     *out = c;
     return ERF_OK;
@@ -296,6 +329,7 @@ erf_status erf_acoustic_substeps(erf_ctx *c, const erf_state *Sn, const erf_stat
     if (!c->have_base) return fail(c, ERF_E_STATE, "erf_init_base_state must come first");
     if (!state_ok(Sn, false, 0) || !state_ok(St, false, 0) || !state_ok(Rt, false, 0) || !state_ok(Sout, false, 0))
         return fail(c, ERF_E_ARG, "null field pointer");
+    if (c->prm.anelastic) return fail(c, ERF_E_UNSUPPORTED, "an anelastic context has no acoustic substeps");
     if (n_sub < 1 || !(dtau > 0.0)) return fail(c, ERF_E_ARG, "n_sub >= 1 and dtau > 0 required");
     if (c->prm.moist && !St->rhoq) return fail(c, ERF_E_ARG, "a moist context needs S_t->rhoq");
     const void *sn[5] = {Sn->rho, Sn->rhotheta, Sn->rhou, Sn->rhov, Sn->rhow};
@@ -324,6 +358,7 @@ erf_status erf_scalar_advance(erf_ctx *c, const erf_state *Sn, const erf_state *
 erf_status erf_rk3_step(erf_ctx *c, erf_state *S)
 {
     ERF_CHECK_CTX(c);
+    if (c->prm.anelastic) return fail(c, ERF_E_UNSUPPORTED, "an anelastic context steps with erf_ssprk2_step");
     if (!c->have_base) return fail(c, ERF_E_STATE, "erf_init_base_state must come first");
     const int nq = c->prm.n_scalars;
     if (!state_ok(S, true, nq)) return fail(c, ERF_E_ARG, "null field pointer");
@@ -357,6 +392,65 @@ erf_status erf_rk3_step(erf_ctx *c, erf_state *S)
         if (e != hipSuccess) return hip_fail(c, e, "microphysics launch");
     }
     return ERF_OK;
+}
+
+erf_status erf_project(erf_ctx *c, erf_state *S, double dt)
+{
+    ERF_CHECK_CTX(c);
+    if (!c->prm.anelastic) return fail(c, ERF_E_UNSUPPORTED, "erf_project needs an anelastic context");
+    if (!c->have_base) return fail(c, ERF_E_STATE, "erf_init_base_state must come first");
+    if (!S || !S->rhou || !S->rhov || !S->rhow) return fail(c, ERF_E_ARG, "null field pointer");
+    if (!(dt > 0.0)) return fail(c, ERF_E_ARG, "dt > 0 required");
+    if (c->rec) return fail(c, ERF_E_UNSUPPORTED, "anelastic calls are not recorded");
+    hipError_t e = launch_project(c, S->rhou, S->rhov, S->rhow, dt);
+    return e == hipSuccess ? ERF_OK : hip_fail(c, e, "projection launch");
+}
+
+erf_status erf_ssprk2_step(erf_ctx *c, erf_state *S)
+{
+    ERF_CHECK_CTX(c);
+    if (!c->prm.anelastic) return fail(c, ERF_E_UNSUPPORTED, "erf_ssprk2_step needs an anelastic context");
+    if (!c->have_base) return fail(c, ERF_E_STATE, "erf_init_base_state must come first");
+    const int nq = c->prm.n_scalars;
+    if (!state_ok(S, true, nq)) return fail(c, ERF_E_ARG, "null field pointer");
+    if (c->rec) return fail(c, ERF_E_UNSUPPORTED, "anelastic calls are not recorded");
+    Workspace &w = c->ws;
+    const double dt = c->prm.dt;
+    // S* (its density is the state's: rho0), the two stages' tendencies
+    erf_state A{S->rho, w.sa[1], w.sa[2], w.sa[3], w.sa[4], w.sa[5]};
+    erf_state R1{w.R[0], w.R[1], w.R[2], w.R[3], w.R[4], nullptr};
+    erf_state R2{w.sb[0], w.sb[1], w.sb[2], w.sb[3], w.sb[4], nullptr};
+    const void *sn[5] = {S->rho, S->rhotheta, S->rhou, S->rhov, S->rhow};
+    const void *r1[5] = {R1.rho, R1.rhotheta, R1.rhou, R1.rhov, R1.rhow};
+    const void *r2[5] = {R2.rho, R2.rhotheta, R2.rhou, R2.rhov, R2.rhow};
+    void *sa[5] = {A.rho, A.rhotheta, A.rhou, A.rhov, A.rhow};
+    void *so[5] = {S->rho, S->rhotheta, S->rhou, S->rhov, S->rhow};
+    // stage 1 with the lagged pressure
+    erf_status s = erf_slow_rhs(c, S, &R1);
+    if (s != ERF_OK) return s;
+    hipError_t e = launch_ssp_update(c, 1, sn, r1, nullptr, sa, dt);
+    if (e != hipSuccess) return hip_fail(c, e, "stage update launch");
+    if (nq > 0 && (s = erf_scalar_advance(c, S, S, S, dt, A.rhoq)) != ERF_OK) return s;
+    e = launch_project(c, A.rhou, A.rhov, A.rhow, dt);
+    if (e != hipSuccess) return hip_fail(c, e, "projection launch");
+    // stage 2
+    if ((s = erf_slow_rhs(c, &A, &R2)) != ERF_OK) return s;
+    if (nq > 0 && (s = erf_scalar_advance(c, S, &A, &A, dt, w.sb[5])) != ERF_OK) return s;
+    e = launch_ssp_update(c, 2, sn, r1, r2, so, dt);
+    if (e == hipSuccess && nq > 0) e = launch_qavg(c, A.rhoq, w.sb[5], S->rhoq, (int64_t)nq * c->d.n);
+    if (e == hipSuccess) e = launch_project(c, S->rhou, S->rhov, S->rhow, dt);
+    return e == hipSuccess ? ERF_OK : hip_fail(c, e, "stage update / projection launch");
+}
+
+erf_status erf_anelastic_pressure(erf_ctx *c, void *p, int32_t set)
+{
+    ERF_CHECK_CTX(c);
+    if (!c->prm.anelastic) return fail(c, ERF_E_UNSUPPORTED, "no perturbation pressure in a compressible context");
+    if (!p || (set != 0 && set != 1)) return fail(c, ERF_E_ARG, "null buffer or set not 0 / 1");
+    const size_t bytes = (size_t)c->d.n * sizeof(double);
+    hipError_t e = set ? hipMemcpyAsync(c->an.pa, p, bytes, hipMemcpyDeviceToDevice, c->stream)
+                       : hipMemcpyAsync(p, c->an.pa, bytes, hipMemcpyDeviceToDevice, c->stream);
+    return e == hipSuccess ? ERF_OK : hip_fail(c, e, "pressure copy");
 }
 
 erf_status erf_kessler(erf_ctx *c, erf_state *S, double dt, double *precip)

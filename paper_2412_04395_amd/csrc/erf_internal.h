@@ -310,6 +310,19 @@ struct Workspace {
     void *sg[9] = {};
 };
 
+// Anelastic contexts only (FP64): the perturbation pressure the projections
+// accumulate (lagged into the next right-hand side), the spectral work array of
+// the Poisson solve, the Thomas factors c'_k of its z solves, the potential
+// phi = dt psi, and the twiddle factors exp(-2 pi i t / N), t < N/2, of the x
+// and y transforms.
+struct Anel {
+    double *pa = nullptr;
+    double2 *Z = nullptr;
+    double *cp = nullptr, *phi = nullptr;
+    double2 *twx = nullptr, *twy = nullptr;
+    int lgx = 0, lgy = 0;  // log2 nx, log2 ny
+};
+
 // Learned-closure state: FP32 master parameters with Adam moments, the BF16
 // operands packed for the matrix cores, biases, input/output statistics, the
 // running count of cells that fell back to Smagorinsky, and training buffers.
@@ -375,6 +388,7 @@ struct erf_ctx {
     erfk::Base base;
     erfk::Workspace ws;
     erfk::MlpState mlp;
+    erfk::Anel an;
     bool have_base = false;
     erf_status sticky = ERF_OK;
     std::string err;
@@ -396,11 +410,12 @@ namespace erfk {
 
 // kernel ids for the timing instrumentation
 enum KernelId { K_PREP, K_MUT, K_STRESS, K_RHS, K_STAGE_INIT, K_COEF, K_SUBSTEP, K_FINALIZE, K_MIXRATIO, K_SCALAR,
-                K_MLP, K_MLP_DIV, K_KESSLER, K_COUNT };
+                K_MLP, K_MLP_DIV, K_KESSLER, K_SSP, K_DIVFFTX, K_FFTY, K_POISSON, K_IFFTX, K_PROJECT, K_COUNT };
 inline const char *kernel_name(int id)
 {
     static const char *names[K_COUNT] = {"prep", "mut", "stress", "rhs", "stage_init", "coef", "substep",
-                                         "finalize", "mixing_ratio", "scalar", "mlp", "mlp_div", "kessler"};
+                                         "finalize", "mixing_ratio", "scalar", "mlp", "mlp_div", "kessler",
+                                         "ssp_update", "div_fftx", "ffty", "poisson_z", "ifftx", "project"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 // The batched instance KB of a kernel, launched over the block ranges of map
@@ -496,6 +511,16 @@ hipError_t launch_adam(erf_ctx *c, double lr, int64_t step);
 // micro.hip: Kessler microphysics over dt on S (rho, rho theta, rho q);
 // precip (may be null) accumulates the rain reaching the ground
 hipError_t launch_kessler(erf_ctx *c, void *rho, void *rt, void *rq, double dt, double *precip);
+// anelastic.hip (FP64 contexts): stage 1 out = Sn + dt R1, stage 2 out = Sn +
+// dt (R1 + R2) / 2 for rho theta and the face momenta (out may alias Sn);
+// out_q = (a + b) / 2 over count values; the projection of the face momenta
+// ru, rv, rw in place, adding psi = phi / dt to the context's pressure
+hipError_t launch_ssp_update(erf_ctx *c, int stage, const void *const Sn[5], const void *const R1[5],
+                             const void *const R2[5], void *const out[5], double dt);
+hipError_t launch_qavg(erf_ctx *c, const void *a, const void *b, void *out, int64_t count);
+hipError_t launch_project(erf_ctx *c, void *ru, void *rv, void *rw, double dt);
+// x-lines per block of the y transform for an ny-point transform
+int anel_ffty_cols(int nx, int ny);
 // diag.hip
 size_t diag_slots_needed();
 hipError_t launch_diagnostics(erf_ctx *c, const void *const S[6], double *host_out);

@@ -35,6 +35,9 @@ struct RhsArgs {
     int oh, ov;
     int ntx, nty;  // tiles per level (blockDim.x x blockDim.y cells each)
     int sgs, visc;
+    // anelastic equation set: p' is the projections' (read, not written) and
+    // the buoyancy is g rho0 (theta - theta0) / theta0 (Sec. 2.2)
+    int anel;
     double Cs, Pr_t, nu, alpha, f, Ug, Vg, Qs, g;
     // state
     const T *rho, *rt, *ru, *rv, *rw;
@@ -106,7 +109,7 @@ __device__ __forceinline__ void k_prep_body(RhsArgs<T> a, VBlock vb)
         st_stream(a.qf + c, (T)(R(1) + qv + qc));
         st_stream(a.bm + c, (T)(pert_in(a.rho, c, r0) + (rqv + rqc + rqr) - (R)r0 * qv0));
         st_stream(a.pp + c, (T)((R)p0k * expm1(R(kGamma) * log1p(x))));
-    } else {
+    } else if (!a.anel) {
         // p' = p0 ((Theta/Theta0)^gamma - 1) without cancellation (EOS, Sec. 2.1)
         st_stream(a.pp + c, (T)((R)p0k * expm1(R(kGamma) * log1p(Tp / (R)T0))));
     }
@@ -498,6 +501,14 @@ __device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
             const R buoy = -(R)a.g * h * ((R)a.bm[c] + (R)a.bm[cm]);
             const R qfm = h * ((R)a.qf[cm] + (R)a.qf[c]);
             r = -adv - pgf / qfm + buoy / qfm;
+        } else if (a.anel) {
+            // anelastic buoyancy g rho0 (theta - theta0) / theta0, the mean of
+            // the two cells on the face
+            const int kb = k > 0 ? k - 1 : 0;
+            const R tu = kPert<T> ? (R)a.th[c] : (R)a.th[c] - (R)a.theta0[k];
+            const R td = kPert<T> ? (R)a.th[cm] : (R)a.th[cm] - (R)a.theta0[kb];
+            const R bu = (R)a.rho0[k] * tu / (R)a.theta0[k], bd = (R)a.rho0[kb] * td / (R)a.theta0[kb];
+            r = -adv - pgf + (R)a.g * h * (bu + bd);
         } else {
             // buoyancy B = -(rho - rho0) g on the face; heavier air sinks
             const R buoy = -(R)a.g * h * (pert_in(a.rho, c, r0k) + pert_in(a.rho, cm, a.rho0[k > 0 ? k - 1 : 0]));
@@ -610,7 +621,8 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], const void *rq, void 
     a.qf = (T *)ws.qf;
     a.bm = (T *)ws.bm;
     a.th = (T *)ws.th;
-    a.pp = (T *)ws.pp;
+    a.anel = p.anelastic ? 1 : 0;
+    a.pp = p.anelastic ? (T *)cx->an.pa : (T *)ws.pp;
     a.u = (T *)ws.u;
     a.v = (T *)ws.v;
     a.w = (T *)ws.w;

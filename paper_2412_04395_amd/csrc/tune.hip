@@ -22,6 +22,9 @@ erf_status check_sizes(const erf_grid *g, const erf_params *p)
     if (nw * (p->n_scalars > 1 ? p->n_scalars : 1) >= ((int64_t)1 << 31)) return ERF_E_SHAPE;
     if (p->precision != ERF_FP64 && p->precision != ERF_FP32_MIXED) return ERF_E_ARG;
     if (p->n_scalars < 0 || p->n_scalars > 8) return ERF_E_ARG;
+    // anelastic contexts: the projection's transform lengths
+    auto pow2 = [](int v) { return v >= 1 && v <= 2048 && (v & (v - 1)) == 0; };
+    if (p->anelastic == 1 && (!pow2(g->nx) || !pow2(g->ny))) return ERF_E_SHAPE;
     return ERF_OK;
 }
 
@@ -92,6 +95,7 @@ erf_status erf_autotune(erf_ctx *c, erf_state *S, int32_t trials, const char *ca
 {
     if (!c) return ERF_E_ARG;
     if (c->sticky != ERF_OK) return c->sticky;
+    if (c->prm.anelastic) return tune_fail(c, ERF_E_UNSUPPORTED, "an anelastic context has no acoustic substeps");
     if (!c->have_base) return tune_fail(c, ERF_E_STATE, "erf_init_base_state must come first");
     if (!S || !S->rho || !S->rhotheta || !S->rhou || !S->rhov || !S->rhow || (c->prm.n_scalars > 0 && !S->rhoq))
         return tune_fail(c, ERF_E_ARG, "null field pointer");

@@ -33,7 +33,8 @@ MLP_NOALLOC_MAX_BATCH = 8192  # ERF_MLP_NOALLOC_MAX_BATCH of include/erf_mlp.h
 # every symbol include/erf.h, include/erf_mlp.h and include/erf_ensemble.h declare
 EXPORTS = ("erf_base_state_host", "erf_create", "erf_destroy", "erf_last_error", "erf_workspace_bytes",
            "erf_init_base_state", "erf_slow_rhs", "erf_acoustic_substeps", "erf_scalar_advance",
-           "erf_rk3_step", "erf_kessler", "erf_precipitation", "erf_diagnostics", "erf_timing_begin", "erf_timing_end", "erf_layout", "erf_autotune",
+           "erf_rk3_step", "erf_kessler", "erf_precipitation", "erf_project", "erf_ssprk2_step",
+           "erf_anelastic_pressure", "erf_diagnostics", "erf_timing_begin", "erf_timing_end", "erf_layout", "erf_autotune",
            "erf_mlp_set_weights", "erf_mlp_get_weights", "erf_mlp_forward", "erf_mlp_features",
            "erf_box_filter", "erf_mlp_fit_norm", "erf_mlp_standardize", "erf_mlp_loss_grad",
            "erf_mlp_train_step", "erf_mlp_loss_grad_noalloc", "erf_mlp_fallback_count",
@@ -62,7 +63,7 @@ class Params(C.Structure):
                 ("Cs", C.c_double), ("Pr_t", C.c_double), ("nu_m", C.c_double), ("alpha_m", C.c_double),
                 ("f_cor", C.c_double), ("Ug", C.c_double), ("Vg", C.c_double),
                 ("surf_heat_flux", C.c_double), ("grav", C.c_double), ("precision", C.c_int32),
-                ("moist", C.c_int32), ("microphysics", C.c_int32)]
+                ("moist", C.c_int32), ("microphysics", C.c_int32), ("anelastic", C.c_int32)]
 
 
 class State(C.Structure):
@@ -123,6 +124,9 @@ def load(path: str = LIB_PATH):
             L.erf_rk3_step.argtypes = [C.c_void_p, C.POINTER(State)]
             L.erf_kessler.argtypes = [C.c_void_p, C.POINTER(State), C.c_double, C.c_void_p]
             L.erf_precipitation.argtypes = [C.c_void_p, _DP, C.c_int32]
+            L.erf_project.argtypes = [C.c_void_p, C.POINTER(State), C.c_double]
+            L.erf_ssprk2_step.argtypes = [C.c_void_p, C.POINTER(State)]
+            L.erf_anelastic_pressure.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
             L.erf_diagnostics.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(Diag)]
             L.erf_timing_begin.argtypes = [C.c_void_p, C.c_char_p, C.c_int32]
             L.erf_timing_end.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -203,7 +207,7 @@ def params_from_config(cfg) -> Params:
     return Params(cfg.dt, cfg.n_substeps, cfg.beta_s, cfg.beta_d, cfg.adv_order_h, cfg.adv_order_v,
                   cfg.scalar_scheme, cfg.n_scalars, cfg.sgs, cfg.Cs, cfg.Pr_t, cfg.nu_m, cfg.alpha_m,
                   cfg.f_cor, cfg.Ug, cfg.Vg, cfg.surf_heat_flux, cfg.grav, prec, int(getattr(cfg, "moist", 0)),
-                  int(getattr(cfg, "microphysics", 0)))
+                  int(getattr(cfg, "microphysics", 0)), int(getattr(cfg, "anelastic", 0)))
 
 
 def layout(cfg, field: str) -> dict:
@@ -375,6 +379,30 @@ class Solver:
     def rk3_step(self, S):
         self._check(self.L.erf_rk3_step(self.h, C.byref(self._st(S))), "erf_rk3_step")
         return S
+
+    # -- anelastic contexts (Sec. 2.2, Sec. 3.2) ----------------------------
+    def ssprk2_step(self, S):
+        """erf_ssprk2_step: one anelastic SSP-RK2 step with projections, in place."""
+        self._check(self.L.erf_ssprk2_step(self.h, C.byref(self._st(S))), "erf_ssprk2_step")
+        return S
+
+    def project(self, S, dt: float):
+        """erf_project: project the face momenta of S in place; the context's
+        perturbation pressure gains psi."""
+        self._check(self.L.erf_project(self.h, C.byref(self._st(S)), float(dt)), "erf_project")
+        return S
+
+    def anelastic_pressure(self, set_to=None):
+        """The context's perturbation pressure as a float64 tensor [nz][ny][nx]
+        (a copy); with set_to (a tensor of that shape) it is replaced first."""
+        t = self.torch
+        shp = (self.cfg.nz, self.cfg.ny, self.cfg.nx)
+        if set_to is not None:
+            self._check(self.L.erf_anelastic_pressure(self.h, self._dev(set_to, t.float64, shp, "p"), 1),
+                        "erf_anelastic_pressure")
+        out = t.empty(shp, dtype=t.float64, device=self.device)
+        self._check(self.L.erf_anelastic_pressure(self.h, C.c_void_p(out.data_ptr()), 0), "erf_anelastic_pressure")
+        return out
 
     def kessler(self, S, dt: float, precip=None):
         """erf_kessler: Kessler microphysics over dt on S in place; precip (a

@@ -121,6 +121,30 @@ def test_create_rejects_bad_arguments_before_touching_the_gpu():
     assert L.erf_box_filter(None, None, 2, 0.0, 1.0, None, None) == erf.ERF_E_ARG
 
 
+def test_create_checks_the_anelastic_restrictions():
+    cfg = W.small(nx=32, ny=16, anelastic=1)
+    L = erf.load()
+    st, h = _create(cfg)
+    if st == erf.ERF_OK:  # created (a GPU is present): release it
+        L.erf_destroy(h)
+    # the transforms need powers of two up to 2048
+    assert _create(cfg, nx=37)[0] == erf.ERF_E_SHAPE
+    assert _create(cfg, ny=24)[0] == erf.ERF_E_SHAPE
+    assert _create(cfg, nx=4096)[0] == erf.ERF_E_SHAPE
+    assert _create(cfg.replace(prec="fp32"))[0] == erf.ERF_E_UNSUPPORTED
+    assert _create(cfg.replace(sgs=2))[0] == erf.ERF_E_UNSUPPORTED
+    assert _create(cfg.replace(n_scalars=3, moist=1))[0] == erf.ERF_E_UNSUPPORTED
+    assert _create(cfg.replace(anelastic=2))[0] == erf.ERF_E_ARG
+    out = erf.FieldLayout()
+    dz = np.ascontiguousarray(cfg.dz, dtype=np.float64)
+    g = erf.Grid(37, cfg.ny, cfg.nz, cfg.dx, cfg.dy, dz.ctypes.data_as(C.POINTER(C.c_double)))
+    assert L.erf_layout(C.byref(g), C.byref(erf.params_from_config(cfg)), 0, C.byref(out)) == erf.ERF_E_SHAPE
+    # the anelastic calls refuse a missing context
+    assert L.erf_ssprk2_step(None, None) == erf.ERF_E_ARG
+    assert L.erf_project(None, None, 1.0) == erf.ERF_E_ARG
+    assert L.erf_anelastic_pressure(None, None, 0) == erf.ERF_E_ARG
+
+
 def test_product_path_has_no_oracle_dependency():
     # the product package never imports the oracle
     pkg = os.path.join(ROOT, "paper_2412_04395_amd")
