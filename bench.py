@@ -81,6 +81,18 @@ MICRO_VALUES = {"kessler": lambda nq: (5 + 4, 0)}
 # (13 bulk values fewer) and its substep reads none of the 6 S'' inputs
 # (Theta'' twice, U'', V'', rho'', W'').
 ZERO_START_SAVED = {"stage_init": 13, "substep": 6}
+# Anelastic step (SSP-RK2 with two projections), per cell of one launch, all
+# FP64: the stage update reads S^n, R1 (and R2) for rho theta and the three
+# momenta and writes four fields (12 values in stage 1, 16 in stage 2: 14 on
+# average); the projection's divergence and x transform read three momenta
+# and write a complex value; each y transform reads and writes a complex
+# value; the z solve reads and writes the complex value twice and writes and
+# reads the Thomas factor; the inverse x transform reads a complex value and
+# writes phi; the correction reads three momenta, phi, the pressure and writes
+# the momenta and the pressure.
+ANEL_VALUES = {"ssp_update": 14, "div_fftx": 5, "ffty": 4, "poisson_z": 10, "ifftx": 3, "project": 9}
+ANEL_KERNELS = ("prep", "mut", "stress", "rhs") + tuple(ANEL_VALUES)
+
 # Moist dynamics, per stage: the primitives pass also reads rho q_v, rho q_c,
 # rho q_r and writes 1 + q_v + q_c and the total-density departure, which the
 # tendencies read; the stage init reads the three species and writes the moist
@@ -500,6 +512,56 @@ def run_scalars(steps: int, warmup: int) -> dict:
     return out
 
 
+def run_anelastic(steps: int, warmup: int) -> dict:
+    """The boundary-layer workload in the anelastic equation set: 256 x 256 x
+    128, FP64, Smagorinsky, SSP-RK2 with a projection after each stage, the
+    same dt."""
+    import torch
+    from paper_2412_04395_amd import erf
+
+    cfg = W.cbl(anelastic=1, name="cbl_anelastic")
+    s = erf.Solver(cfg)
+    th0 = W.theta_sounding(cfg)
+    b = s.init_base_state(th0)
+    S = s.to_device(W.initial_state(cfg, b["rho0"], th0, b["p0"], b["pi0"]))
+    s.project(S, cfg.dt)  # a divergence-free start
+    for _ in range(warmup):
+        s.ssprk2_step(S)
+
+    def timed(n, kernel=None):
+        if kernel:
+            s.timing_begin(kernel, max_launches=16 * n + 16)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            s.ssprk2_step(S)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        return el, (s.timing_end() if kernel else (0.0, 0))
+
+    shares = {}
+    for k in ANEL_KERNELS:
+        _, (ms, n) = timed(1, k)
+        if n:
+            shares[k] = (ms, n)
+    dom = max(shares, key=lambda k: shares[k][0])
+    el, (kms, kn) = timed(steps, dom)
+    d = s.diagnostics(S, allow_nonfinite=True)
+    s.close()
+    avg_ms = kms / max(kn, 1)
+    vals = ANEL_VALUES[dom] if dom in ANEL_VALUES else KERNEL_VALUES[dom](1)[0]
+    byts = vals * 8.0 * cfg.cells
+    gbs = byts / (avg_ms * 1e-3) / 1e9
+    return {"workload": "boundary-layer LES 256x256x128 in the anelastic equation set (SSP-RK2, projections)",
+            "grid": [cfg.nx, cfg.ny, cfg.nz], "precision": "fp64", "dt": cfg.dt,
+            "value": cfg.cells * steps / el, "unit": "cell-updates/s", "ms_per_step": 1e3 * el / steps,
+            "kernel_ms_per_step": {k: round(v[0], 4) for k, v in shares.items()},
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": byts,
+                         "avg_launch_ms": round(avg_ms, 4), "launches_timed": kn},
+            "final_diag": {"max_w": d["max_w"], "nonfinite": d["nonfinite"]}}
+
+
 def _substep_value_adjust(cfg) -> float:
     """Bulk values per cell by which the average substep launch of a step
     differs from KERNEL_VALUES: +5 for the one per stage that writes the stage
@@ -537,6 +599,7 @@ def main(argv=None):
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-training", action="store_true")
     ap.add_argument("--no-scalars", action="store_true")
+    ap.add_argument("--no-anelastic", action="store_true")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first run one plain device copy of this many GiB (reference for HBM counters)")
     a = ap.parse_args(argv)
@@ -546,14 +609,6 @@ def main(argv=None):
         return 2
     rank = int(os.environ.get("RANK", "0"))
 
-    # single legs, each printed as its own JSON object (for profiling them alone)
-    if a.workload == "ensemble":
-        print(json.dumps(run_ensemble(min(a.steps, 5), min(a.warmup, 1))), flush=True)
-        return 0
-    if a.workload == "closure_training":
-        print(json.dumps(run_training(a.steps)), flush=True)
-        return 0
-    cfg = _cfg(a.workload)
     if a.copy_gib > 0:
         import torch
         n = int(a.copy_gib * (1 << 30)) // 8
@@ -563,6 +618,17 @@ def main(argv=None):
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    # single legs, each printed as its own JSON object (for profiling them alone)
+    if a.workload == "ensemble":
+        print(json.dumps(run_ensemble(min(a.steps, 5), min(a.warmup, 1))), flush=True)
+        return 0
+    if a.workload == "anelastic":
+        print(json.dumps(run_anelastic(a.steps, a.warmup)), flush=True)
+        return 0
+    if a.workload == "closure_training":
+        print(json.dumps(run_training(a.steps)), flush=True)
+        return 0
+    cfg = _cfg(a.workload)
     el, dom, kms, kn, shares, diag = run_gpu(cfg, a.steps, a.warmup)
     value = cfg.cells * a.steps / el
     roof = _roofline(cfg, dom, kms, kn)
@@ -604,6 +670,8 @@ def main(argv=None):
         out["training"] = run_training(a.steps)
     if a.workload == "cbl" and not a.no_scalars:
         out["scalars"] = run_scalars(min(a.steps, 10), min(a.warmup, 2))
+    if a.workload == "cbl" and not a.no_anelastic:
+        out["anelastic"] = run_anelastic(a.steps, a.warmup)
     if a.workload == "cbl" and not a.no_ensemble:
         out["ensemble"] = run_ensemble(min(a.steps, 5), min(a.warmup, 1))
     if rank == 0 and not a.no_cpu_baseline:

@@ -55,6 +55,9 @@ struct RhsArgs {
 
 __device__ __forceinline__ int cidx(const Dims &d, int i, int j, int k) { return (k * d.ny + j) * d.nx + i; }
 
+// equation sets of the tendency kernel
+constexpr int kDryEq = 0, kMoistEq = 1, kAnelEq = 2;
+
 // ---------------------------------------------------------------------------
 // primitives
 // ---------------------------------------------------------------------------
@@ -291,14 +294,16 @@ __device__ __forceinline__ R interp(int order, const R (&q)[7], int o, R s)
 // into it; the periodic and reflected indices are then selects instead of
 // branches, and every load of a section can be issued before its arithmetic.
 // kVisc: the viscous and diffusive terms (stress and diffusivity arrays).
-// kMoist: the pressure gradient and the buoyancy are divided by the face mean of
+// kEq: the equation set (kDryEq, kMoistEq, kAnelEq).
+// kMoistEq: the pressure gradient and the buoyancy are divided by the face mean of
 // 1 + q_v + q_c, and the buoyancy is that of the total density (eq. mom).
 // Three wavefronts per SIMD (the occupancy its registers give anyway): told
 // so, the scheduler keeps each section's gathers in a few large groups
 // rather than trading round trips for registers.
-template <typename T, int OH, int OV, bool kNear, bool kVisc, bool kMoist>
+template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
 __device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
 {
+    constexpr bool kMoist = kEq == kMoistEq;
     using R = T;
     const Dims &d = a.d;
     const TileIdx tc = tile_cell(vb, a.ntx, a.nty);
@@ -501,7 +506,7 @@ __device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
             const R buoy = -(R)a.g * h * ((R)a.bm[c] + (R)a.bm[cm]);
             const R qfm = h * ((R)a.qf[cm] + (R)a.qf[c]);
             r = -adv - pgf / qfm + buoy / qfm;
-        } else if (a.anel) {
+        } else if constexpr (kEq == kAnelEq) {
             // anelastic buoyancy g rho0 (theta - theta0) / theta0, the mean of
             // the two cells on the face
             const int kb = k > 0 ? k - 1 : 0;
@@ -526,17 +531,17 @@ __device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
     st_stream(a.Rw + c, (T)out_w);
     if (k == 0) a.Rw[c + nz * P] = 0.0;
 }
-template <typename T, int OH, int OV, bool kNear, bool kVisc, bool kMoist>
+template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_rhs(RhsArgs<T> a)
 {
-    k_rhs_body<T, OH, OV, kNear, kVisc, kMoist>(a, hw_block());
+    k_rhs_body<T, OH, OV, kNear, kVisc, kEq>(a, hw_block());
 }
-template <typename T, int OH, int OV, bool kNear, bool kVisc, bool kMoist>
+template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_rhs_batch(const RhsArgs<T> *args, BatchMap bm)
 {
     int m;
     VBlock vb;
-    if (batch_block(bm, m, vb)) k_rhs_body<T, OH, OV, kNear, kVisc, kMoist>(args[m], vb);
+    if (batch_block(bm, m, vb)) k_rhs_body<T, OH, OV, kNear, kVisc, kEq>(args[m], vb);
 }
 
 }  // namespace
@@ -545,11 +550,27 @@ namespace {
 // orders 2, 3 and 5 in both directions have their own instances; any other
 // combination, and domains narrower than the stencil, take the general one.
 // Moist dynamics: 3rd order (the moist workload's) and the general instances.
-template <typename T, int OH, int OV, bool kNear, bool kVisc, bool kMoist>
+// The anelastic set (FP64 only): orders 2, 3 and 5 and the general instances.
+template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
 void rhs_one(erf_ctx *cx, const RhsArgs<T> &a, dim3 grd, dim3 blk)
 {
-    run<RhsArgs<T>, k_rhs<T, OH, OV, kNear, kVisc, kMoist>, k_rhs_batch<T, OH, OV, kNear, kVisc, kMoist>>(
+    run<RhsArgs<T>, k_rhs<T, OH, OV, kNear, kVisc, kEq>, k_rhs_batch<T, OH, OV, kNear, kVisc, kEq>>(
         cx, grd, blk, 0, a);
+}
+template <typename T, bool kVisc, int kEq>
+void launch_rhs_eq(erf_ctx *cx, const RhsArgs<T> &a, dim3 grd, dim3 blk)
+{
+    const bool near = a.d.nx >= 3 && a.d.ny >= 3 && a.d.nz >= 3;
+    if (near && a.oh == 5 && a.ov == 5)
+        rhs_one<T, 5, 5, true, kVisc, kEq>(cx, a, grd, blk);
+    else if (near && a.oh == 3 && a.ov == 3)
+        rhs_one<T, 3, 3, true, kVisc, kEq>(cx, a, grd, blk);
+    else if (near && a.oh == 2 && a.ov == 2)
+        rhs_one<T, 2, 2, true, kVisc, kEq>(cx, a, grd, blk);
+    else if (near)
+        rhs_one<T, 0, 0, true, kVisc, kEq>(cx, a, grd, blk);
+    else
+        rhs_one<T, 0, 0, false, kVisc, kEq>(cx, a, grd, blk);
 }
 template <typename T, bool kVisc>
 void launch_rhs(erf_ctx *cx, const RhsArgs<T> &a, bool moist, dim3 grd, dim3 blk)
@@ -557,21 +578,19 @@ void launch_rhs(erf_ctx *cx, const RhsArgs<T> &a, bool moist, dim3 grd, dim3 blk
     const bool near = a.d.nx >= 3 && a.d.ny >= 3 && a.d.nz >= 3;
     if (moist) {
         if (near && a.oh == 3 && a.ov == 3)
-            rhs_one<T, 3, 3, true, kVisc, true>(cx, a, grd, blk);
+            rhs_one<T, 3, 3, true, kVisc, kMoistEq>(cx, a, grd, blk);
         else if (near)
-            rhs_one<T, 0, 0, true, kVisc, true>(cx, a, grd, blk);
+            rhs_one<T, 0, 0, true, kVisc, kMoistEq>(cx, a, grd, blk);
         else
-            rhs_one<T, 0, 0, false, kVisc, true>(cx, a, grd, blk);
-    } else if (near && a.oh == 5 && a.ov == 5)
-        rhs_one<T, 5, 5, true, kVisc, false>(cx, a, grd, blk);
-    else if (near && a.oh == 3 && a.ov == 3)
-        rhs_one<T, 3, 3, true, kVisc, false>(cx, a, grd, blk);
-    else if (near && a.oh == 2 && a.ov == 2)
-        rhs_one<T, 2, 2, true, kVisc, false>(cx, a, grd, blk);
-    else if (near)
-        rhs_one<T, 0, 0, true, kVisc, false>(cx, a, grd, blk);
-    else
-        rhs_one<T, 0, 0, false, kVisc, false>(cx, a, grd, blk);
+            rhs_one<T, 0, 0, false, kVisc, kMoistEq>(cx, a, grd, blk);
+    } else if constexpr (std::is_same_v<T, double>) {
+        if (a.anel)
+            launch_rhs_eq<T, kVisc, kAnelEq>(cx, a, grd, blk);
+        else
+            launch_rhs_eq<T, kVisc, kDryEq>(cx, a, grd, blk);
+    } else {
+        launch_rhs_eq<T, kVisc, kDryEq>(cx, a, grd, blk);
+    }
 }
 
 template <typename T>

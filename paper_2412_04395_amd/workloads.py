@@ -203,6 +203,10 @@ def state_from_theta(cfg: Config, rho0: np.ndarray, theta0: np.ndarray, dtheta: 
     Theta0 = (rho0 * theta0)[:, None, None] * np.ones((nz, ny, nx))
     th = theta0[:, None, None] + dtheta
     rho = Theta0 / th
+    if getattr(cfg, "anelastic", 0):
+        # the anelastic state: density rho0, the same potential temperature
+        rho = rho0[:, None, None] * np.ones((nz, ny, nx))
+        Theta0 = rho * th
     S = {
         "rho": np.ascontiguousarray(rho),
         "rt": np.ascontiguousarray(Theta0),
