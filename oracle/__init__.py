@@ -40,7 +40,7 @@ class _Params(C.Structure):
                 ("Vg", C.c_double), ("surf_heat_flux", C.c_double), ("grav", C.c_double),
                 ("mlp_params", C.POINTER(C.c_double)), ("mlp_norm", C.POINTER(C.c_double)),
                 ("mlp_bf16", C.c_int32), ("moist", C.c_int32), ("anelastic", C.c_int32),
-                ("p_anel", C.POINTER(C.c_double))]
+                ("p_anel", C.POINTER(C.c_double)), ("most_z0", C.c_double)]
 
 
 class _Base(C.Structure):
@@ -88,7 +88,9 @@ def lib():
                                                 C.POINTER(_State), C.POINTER(_State), C.POINTER(_State),
                                                 C.c_int32, C.c_double, C.POINTER(_State), _DP, _DP, _DP]
             L.orc_scalar_advance.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_State),
-                                             C.POINTER(_State), _DP, _DP, _DP, C.c_double, _DP]
+                                             C.POINTER(_State), _DP, _DP, _DP, C.c_double, _DP, _DP]
+            L.orc_most_ustar.restype = C.c_double
+            L.orc_most_ustar.argtypes = [C.c_double] * 6
             L.orc_rk3_step.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Base),
                                        C.POINTER(_State)]
             L.orc_diagnostics.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Base),
@@ -146,7 +148,7 @@ class Oracle:
                                cfg.adv_order_v, cfg.scalar_scheme, cfg.n_scalars, cfg.sgs, cfg.Cs,
                                cfg.Pr_t, cfg.nu_m, cfg.alpha_m, cfg.f_cor, cfg.Ug, cfg.Vg,
                                cfg.surf_heat_flux, cfg.grav, None, None, 0, int(cfg.moist),
-                               int(getattr(cfg, "anelastic", 0)), None)
+                               int(getattr(cfg, "anelastic", 0)), None, float(getattr(cfg, "most_z0", 0.0)))
         self.base = None
         # anelastic mode: the lagged perturbation pressure (Sec. 3.2)
         self.p_anel = np.zeros((cfg.nz, cfg.ny, cfg.nx))
@@ -218,11 +220,15 @@ class Oracle:
                                                 _p(Fu), _p(Fv), _p(Fw)), "orc_acoustic_substeps")
         return out, (Fu, Fv, Fw)
 
-    def scalar_advance(self, Sn, St, F, dts: float):
+    def scalar_advance(self, Sn, St, F, dts: float, src=None):
+        """src: the Deardorff closure's source of rho e at S^t (slow_rhs's
+        R["rq"]), required with that closure."""
         rq = np.zeros_like(Sn["rq"])
         Fu, Fv, Fw = (np.ascontiguousarray(f, dtype=np.float64) for f in F)
+        sp = None if src is None else np.ascontiguousarray(src, dtype=np.float64)
         self._check(lib().orc_scalar_advance(C.byref(self._grid), C.byref(self._params), C.byref(self._st(Sn)),
                                              C.byref(self._st(St)), _p(Fu), _p(Fv), _p(Fw), dts,
+                                             None if sp is None else _p(sp),
                                              _p(rq) if rq.size else C.cast(C.c_void_p(0), _DP)),
                     "orc_scalar_advance")
         return rq
@@ -401,6 +407,11 @@ def adam(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1
 
 
 # -- pointwise helpers used by the pin tests ---------------------------------
+def most_ustar(U: float, z1: float, z0: float, Qs: float, th1: float, grav: float = 9.81) -> float:
+    """Friction velocity of the Monin-Obukhov surface layer."""
+    return lib().orc_most_ustar(U, z1, z0, Qs, th1, grav)
+
+
 def interp(order: int, q6, sgn: float) -> float:
     q = np.ascontiguousarray(q6, dtype=np.float64)
     return lib().orc_interp(order, _p(q), sgn)

@@ -306,6 +306,39 @@ static double iyw(const orc_grid *g, const double *f, int i, int j, int k, int o
 }
 
 /* ------------------------------------------------------------------------ */
+/* Monin-Obukhov surface layer (Sec. 3.8)                                    */
+/* ------------------------------------------------------------------------ */
+/* reading: von Karman constant 0.4; Businger-Dyer stability function for
+ * momentum, psi_m = 2 ln((1+x)/2) + ln((1+x^2)/2) - 2 atan(x) + pi/2 with
+ * x = (1 - 16 zeta)^(1/4) for zeta < 0 and psi_m = -5 zeta for zeta >= 0;
+ * zeta = z1/L with L = -u_star^3 theta_1 / (kappa g Qs), clamped to [-5, 1]; u_star
+ * from the log law U = (u_star / kappa)(ln(z1/z0) - psi_m(zeta)) by twenty fixed-point
+ * steps from the neutral value. */
+static const double KARMAN = 0.4;
+static double psi_m(double zeta)
+{
+    if (zeta >= 0.0) return -5.0 * zeta;
+    double x = pow(1.0 - 16.0 * zeta, 0.25);
+    return 2.0 * log(0.5 * (1.0 + x)) + log(0.5 * (1.0 + x * x)) - 2.0 * atan(x) + 2.0 * atan(1.0);
+}
+
+double orc_most_ustar(double U, double z1, double z0, double Qs, double th1, double grav)
+{
+    double lnz = log(z1 / z0);
+    double ust = KARMAN * U / lnz;
+    for (int it = 0; it < 20; ++it) {
+        double zeta = 0.0;
+        if (Qs != 0.0) {
+            zeta = -z1 * KARMAN * grav * Qs / (ust * ust * ust * th1);
+            if (zeta < -5.0) zeta = -5.0;
+            if (zeta > 1.0) zeta = 1.0;
+        }
+        ust = KARMAN * U / (lnz - psi_m(zeta));
+    }
+    return ust;
+}
+
+/* ------------------------------------------------------------------------ */
 /* stress tensor and heat flux, eq. (stresstensor), Sec. 2.3                 */
 /* ------------------------------------------------------------------------ */
 /* reading: tau = -2 mu (S - D), mu = rho nu_m + rho (Cs Delta)^2 |S| with
@@ -313,7 +346,7 @@ static double iyw(const orc_grid *g, const double *f, int i, int j, int k, int o
  * centres, off-diagonal strain on cell edges, mu averaged from the four cells
  * around an edge.  Heat diffusivity rho alpha_m + mu_t / Pr_t.  Free-slip lids:
  * S13 = S23 = 0 on the bottom and top faces. */
-static void add_diffusion(const orc_grid *g, const orc_params *P, const orc_state *S,
+static void add_diffusion(const orc_grid *g, const orc_params *P, const orc_base *B, const orc_state *S,
                           const double *th, const double *u, const double *v, const double *w,
                           orc_state *R)
 {
@@ -324,6 +357,9 @@ static void add_diffusion(const orc_grid *g, const orc_params *P, const orc_stat
     double *s11 = dalloc(n), *s22 = dalloc(n), *s33 = dalloc(n);
     double *s12 = dalloc(n), *s13 = dalloc(nw), *s23 = dalloc(nw);
     double *mu = dalloc(n), *kh = dalloc(n);
+    /* Deardorff closure: e (clipped at zero), rho K_m and the local part of the
+     * source of rho e */
+    double *ee = dalloc(n), *rkm = dalloc(n), *esrc = dalloc(n);
 
     /* strain rates */
 #pragma omp parallel for collapse(2) schedule(static)
@@ -368,9 +404,65 @@ static void add_diffusion(const orc_grid *g, const orc_params *P, const orc_stat
                     double cd = P->Cs * delta;
                     mut = S->rho[c] * cd * cd * sqrt(ss);
                 }
+                double khs = P->sgs == 1 ? mut / P->Pr_t : 0.0;
+                if (P->sgs == 3) {
+                    /* Deardorff (1980) 1.5-order closure, the coefficients of
+                     * Moeng (1984) (Sec. 2.3 and the LES cases of Sec. 4):
+                     * length l = Delta, or 0.76 sqrt(e)/N where that is
+                     * smaller in stable air; K_m = 0.1 l sqrt(e);
+                     * K_h = (1 + 2 l/Delta) K_m; production K_m 2 S:S
+                     * - K_h N^2; dissipation C_eps e^(3/2)/l with
+                     * C_eps = 0.19 + 0.51 l/Delta.  N^2 = g/theta0 dtheta/dz,
+                     * dtheta/dz the mean of the two face differences (zero
+                     * through the lids). */
+                    double a12 = 0.25 * (s12[c] + cget(g, s12, i + 1, j, k) + cget(g, s12, i, j + 1, k) + cget(g, s12, i + 1, j + 1, k));
+                    double a13 = 0.25 * (s13[c] + wget(g, s13, i + 1, j, k) + s13[CIDX(g, i, j, k + 1)] + wget(g, s13, i + 1, j, k + 1));
+                    double a23 = 0.25 * (s23[c] + wget(g, s23, i, j + 1, k) + s23[CIDX(g, i, j, k + 1)] + wget(g, s23, i, j + 1, k + 1));
+                    double ss = 2.0 * (s11[c] * s11[c] + s22[c] * s22[c] + s33[c] * s33[c])
+                              + 4.0 * (a12 * a12 + a13 * a13 + a23 * a23);
+                    double e = S->rq[c] / S->rho[c];
+                    if (e < 0.0) e = 0.0;
+                    double up = k < nz - 1 ? (th[CIDX(g, i, j, k + 1)] - th[c]) / (0.5 * (dz[k] + dz[k + 1])) : 0.0;
+                    double dn = k > 0 ? (th[c] - th[CIDX(g, i, j, k - 1)]) / (0.5 * (dz[k - 1] + dz[k])) : 0.0;
+                    double N2 = P->grav / B->theta0[k] * 0.5 * (up + dn);
+                    double delta = cbrt(dx * dy * dz[k]);
+                    double l = delta, eps;
+                    int limited = N2 > 0.0 && 0.76 * sqrt(e) / sqrt(N2) < delta;
+                    if (limited) l = 0.76 * sqrt(e) / sqrt(N2);
+                    double Km = 0.1 * l * sqrt(e), Kh = (1.0 + 2.0 * l / delta) * Km;
+                    double ceps = 0.19 + 0.51 * l / delta;
+                    /* e^(3/2)/l, written as e N/0.76 where l is the stable length */
+                    eps = limited ? ceps * e * sqrt(N2) / 0.76 : ceps * e * sqrt(e) / delta;
+                    mut = S->rho[c] * Km;
+                    khs = S->rho[c] * Kh;
+                    ee[c] = e;
+                    rkm[c] = mut;
+                    esrc[c] = S->rho[c] * (Km * ss - Kh * N2 - eps);
+                }
                 mu[c] = S->rho[c] * P->nu_m + mut;
-                kh[c] = S->rho[c] * P->alpha_m + (P->sgs == 1 ? mut / P->Pr_t : 0.0);
+                kh[c] = S->rho[c] * P->alpha_m + khs;
             }
+    if (P->sgs == 3) {
+        /* source of rho e: the local terms plus the diffusion div(2 rho K_m
+         * grad e), face coefficients the mean of the two cells, no flux
+         * through the lids */
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    size_t c = CIDX(g, i, j, k);
+                    double fx0 = -(cget(g, rkm, i - 1, j, k) + rkm[c]) * (ee[c] - cget(g, ee, i - 1, j, k)) / dx;
+                    double fx1 = -(rkm[c] + cget(g, rkm, i + 1, j, k)) * (cget(g, ee, i + 1, j, k) - ee[c]) / dx;
+                    double fy0 = -(cget(g, rkm, i, j - 1, k) + rkm[c]) * (ee[c] - cget(g, ee, i, j - 1, k)) / dy;
+                    double fy1 = -(rkm[c] + cget(g, rkm, i, j + 1, k)) * (cget(g, ee, i, j + 1, k) - ee[c]) / dy;
+                    double fz0 = 0.0, fz1 = 0.0;
+                    if (k > 0)
+                        fz0 = -(rkm[CIDX(g, i, j, k - 1)] + rkm[c]) * (ee[c] - ee[CIDX(g, i, j, k - 1)]) / (0.5 * (dz[k - 1] + dz[k]));
+                    if (k < nz - 1)
+                        fz1 = -(rkm[c] + rkm[CIDX(g, i, j, k + 1)]) * (ee[CIDX(g, i, j, k + 1)] - ee[c]) / (0.5 * (dz[k] + dz[k + 1]));
+                    R->rq[c] = esrc[c] - ((fx1 - fx0) / dx + (fy1 - fy0) / dy + (fz1 - fz0) / dz[k]);
+                }
+    }
 
     /* stress components: tau_ii at centres, tau_12 at xy-edges, tau_13/23 at z-face edges */
     double *t11 = dalloc(n), *t22 = dalloc(n), *t33 = dalloc(n), *t12 = dalloc(n);
@@ -387,6 +479,33 @@ static void add_diffusion(const orc_grid *g, const orc_params *P, const orc_stat
                 double me = 0.25 * (cget(g, mu, i - 1, j - 1, k) + cget(g, mu, i, j - 1, k) + cget(g, mu, i - 1, j, k) + mu[c]);
                 t12[c] = -2.0 * me * s12[c];
             }
+    if (P->most_z0 > 0.0) {
+        /* surface stresses of the Monin-Obukhov layer on the bottom faces:
+         * per column -rho u_star^2 (u, v)/U from the lowest cell's centre wind
+         * (reading: U at least 0.1 m/s), on each face edge the mean of the two
+         * columns beside it */
+        double *c13 = dalloc((size_t)nx * ny), *c23 = dalloc((size_t)nx * ny);
+        double z1 = 0.5 * dz[0];
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, 0);
+                double u1 = 0.5 * (u[c] + cget(g, u, i + 1, j, 0));
+                double v1 = 0.5 * (v[c] + cget(g, v, i, j + 1, 0));
+                double U = sqrt(u1 * u1 + v1 * v1);
+                if (U < 0.1) U = 0.1;
+                double ust = orc_most_ustar(U, z1, P->most_z0, P->surf_heat_flux, th[c], P->grav);
+                c13[c] = -S->rho[c] * ust * ust * u1 / U;
+                c23[c] = -S->rho[c] * ust * ust * v1 / U;
+            }
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, 0);
+                t13[c] = 0.5 * (cget(g, c13, i - 1, j, 0) + c13[c]);
+                t23[c] = 0.5 * (cget(g, c23, i, j - 1, 0) + c23[c]);
+            }
+        free(c13);
+        free(c23);
+    }
 #pragma omp parallel for collapse(2) schedule(static)
     for (int k = 1; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
@@ -434,6 +553,7 @@ static void add_diffusion(const orc_grid *g, const orc_params *P, const orc_stat
             }
     free(s11); free(s22); free(s33); free(s12); free(s13); free(s23);
     free(mu); free(kh); free(t11); free(t22); free(t33); free(t12); free(t13); free(t23);
+    free(ee); free(rkm); free(esrc);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -445,7 +565,10 @@ int orc_slow_rhs_mlp(const orc_grid *g, const orc_params *P, const orc_base *B, 
 int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                  const orc_state *S, orc_state *R)
 {
-    if (P->anelastic && (P->moist || P->sgs == 2 || !P->p_anel)) return -1;
+    if (P->anelastic && (P->moist || P->sgs == 2 || P->sgs == 3 || !P->p_anel)) return -1;
+    /* the Deardorff closure carries rho e as scalar 0 and nothing else */
+    if (P->sgs == 3 && (P->n_scalars != 1 || P->moist || !S->rq || !R->rq)) return -1;
+    if (P->most_z0 < 0.0 || (P->most_z0 > 0.0 && !(P->most_z0 < 0.5 * g->dz[0]))) return -1;
     if (P->sgs == 2) {
         if (!P->mlp_params || !P->mlp_norm) return -1;
         return orc_slow_rhs_mlp(g, P, B, S, P->mlp_params, P->mlp_norm, P->mlp_bf16, R, NULL);
@@ -611,7 +734,8 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                 }
             }
 
-    if (P->sgs == 1 || P->nu_m != 0.0 || P->alpha_m != 0.0) add_diffusion(g, P, S, th, u, v, w, R);
+    if (P->sgs == 1 || P->sgs == 3 || P->nu_m != 0.0 || P->alpha_m != 0.0 || P->most_z0 > 0.0)
+        add_diffusion(g, P, B, S, th, u, v, w, R);
 
     /* prescribed kinematic surface heat flux enters the lowest cell (Sec. 3.8) */
     if (P->surf_heat_flux != 0.0)
@@ -799,11 +923,13 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
 /* ------------------------------------------------------------------------ */
 int orc_scalar_advance(const orc_grid *g, const orc_params *P, const orc_state *Sn,
                        const orc_state *St, const double *Fu, const double *Fv,
-                       const double *Fw, double dts, double *rq_out)
+                       const double *Fw, double dts, const double *src, double *rq_out)
 {
     int nx = g->nx, ny = g->ny, nz = g->nz, nq = P->n_scalars;
     if (nq <= 0) return 0;
-    if (P->sgs != 0 || P->alpha_m != 0.0) return -5; /* scalar diffusion not provided */
+    /* scalar diffusion is provided for the Deardorff closure's rho e only */
+    if ((P->sgs != 0 && P->sgs != 3) || P->alpha_m != 0.0) return -5;
+    if (P->sgs == 3 && (nq != 1 || !src)) return -5;
     size_t n = (size_t)nx * ny * nz;
     int oh = P->adv_order_h, ov = P->adv_order_v;
     double *q = dalloc(n);
@@ -838,6 +964,11 @@ int orc_scalar_advance(const orc_grid *g, const orc_params *P, const orc_state *
                     }
                     double div = (f[1] - f[0]) / g->dx + (f[3] - f[2]) / g->dy + (f[5] - f[4]) / g->dz[k];
                     out[c] = rqn[c] - dts * div;
+                    if (P->sgs == 3 && s == 0) {
+                        /* rho e: its source at S^t; negative values are cut to zero */
+                        out[c] = out[c] + dts * src[c];
+                        if (out[c] < 0.0) out[c] = 0.0;
+                    }
                 }
     }
     free(q);
@@ -884,7 +1015,7 @@ int orc_rk3_step(const orc_grid *g, const orc_params *P, const orc_base *B, orc_
         if (rc) break;
         rc = orc_acoustic_substeps(g, P, B, &Sn, &St, &Rt, nsub, dtau, &Snew, Fu, Fv, Fw);
         if (rc) break;
-        if (nq > 0) rc = orc_scalar_advance(g, P, &Sn, &St, Fu, Fv, Fw, dts, Snew.rq);
+        if (nq > 0) rc = orc_scalar_advance(g, P, &Sn, &St, Fu, Fv, Fw, dts, P->sgs == 3 ? Rt.rq : NULL, Snew.rq);
         /* the new stage state */
         orc_state tmp = St;
         St = Snew;
@@ -1802,11 +1933,11 @@ int orc_ssprk2_step(const orc_grid *g, const orc_params *P, const orc_base *B, o
             Ss.rv[c] = S->rv[c] + dt * R1.rv[c];
         }
         for (size_t c = 0; c < nw; ++c) Ss.rw[c] = S->rw[c] + dt * R1.rw[c];
-        if (nq > 0) rc = orc_scalar_advance(g, &Q, S, S, S->ru, S->rv, S->rw, dt, Ss.rq);
+        if (nq > 0) rc = orc_scalar_advance(g, &Q, S, S, S->ru, S->rv, S->rw, dt, NULL, Ss.rq);
     }
     if (rc == 0) rc = orc_project(g, Ss.ru, Ss.rv, Ss.rw, dt, pp);
     if (rc == 0) rc = orc_slow_rhs(g, &Q, B, &Ss, &R2);
-    if (rc == 0 && nq > 0) rc = orc_scalar_advance(g, &Q, S, &Ss, Ss.ru, Ss.rv, Ss.rw, dt, tmp);
+    if (rc == 0 && nq > 0) rc = orc_scalar_advance(g, &Q, S, &Ss, Ss.ru, Ss.rv, Ss.rw, dt, NULL, tmp);
     if (rc == 0) {
         for (size_t c = 0; c < n; ++c) {
             S->rt[c] = S->rt[c] + 0.5 * dt * (R1.rt[c] + R2.rt[c]);

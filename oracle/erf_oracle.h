@@ -40,7 +40,8 @@ typedef struct {
     int32_t adv_order_v;    /* 2..6                                            */
     int32_t scalar_scheme;  /* 0: same interpolants as momentum; 1: WENO5-JS   */
     int32_t n_scalars;
-    int32_t sgs;            /* 0 none, 1 Smagorinsky, 2 learned closure (MLP)   */
+    int32_t sgs;            /* 0 none, 1 Smagorinsky, 2 learned closure (MLP),
+                               3 Deardorff 1.5-order TKE (scalar 0 is rho e)    */
     double Cs, Pr_t;
     double nu_m, alpha_m;   /* constant kinematic viscosity / diffusivity       */
     double f_cor, Ug, Vg;   /* f-plane Coriolis and geostrophic wind           */
@@ -59,6 +60,10 @@ typedef struct {
      * g rho0 (theta - theta0) / theta0; dry only */
     int32_t anelastic;
     const double *p_anel;
+    /* bottom boundary: 0 a free-slip wall; > 0 the roughness length z0 [m] of
+     * a Monin-Obukhov surface layer (Sec. 3.8) giving the surface stress from
+     * the lowest level's wind, with the surface heat flux surf_heat_flux */
+    double most_z0;
 } orc_params;
 
 typedef struct {
@@ -101,7 +106,9 @@ int orc_thomas(int32_t n, const double *a, const double *b, const double *c,
                const double *r, double *x);
 
 /* Slow right-hand side f(S) of eqs. (con), (mom), (theta) (Sec. 2.1, 2.3,
- * 3.6, 3.7, 3.8).  R->rq is not touched. */
+ * 3.6, 3.7, 3.8).  R->rq is not touched, except with the Deardorff closure
+ * (sgs 3): R->rq (component 0) then receives the source of rho e, everything
+ * but its advection (shear and buoyancy production, dissipation, diffusion). */
 int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                  const orc_state *S, orc_state *R);
 
@@ -115,10 +122,12 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
                           double *Fu, double *Fv, double *Fw);
 
 /* Scalar update with time-averaged fluxes (Sec. 3.1):
- * (rho q)^new = (rho q)^n - dts div(F q^t). */
+ * (rho q)^new = (rho q)^n - dts div(F q^t).  With the Deardorff closure,
+ * component 0 (rho e) also gains dts src (src: the slow right-hand side's
+ * R->rq at S^t; may be NULL otherwise) and is clipped at zero. */
 int orc_scalar_advance(const orc_grid *g, const orc_params *P, const orc_state *Sn,
                        const orc_state *St, const double *Fu, const double *Fv,
-                       const double *Fw, double dts, double *rq_out);
+                       const double *Fw, double dts, const double *src, double *rq_out);
 
 /* One full RK3 step with substeps (Sec. 3.1, 3.3), in place. */
 int orc_rk3_step(const orc_grid *g, const orc_params *P, const orc_base *B, orc_state *S);
@@ -192,6 +201,11 @@ int orc_slow_rhs_mlp(const orc_grid *g, const orc_params *P, const orc_base *B, 
  * NULL) accumulates the rain mass reaching the ground [kg/m^2]. */
 int orc_kessler(const orc_grid *g, const orc_params *P, const orc_base *B, orc_state *S, double dt,
                 double *precip);
+/* Monin-Obukhov surface layer (Sec. 3.8): the friction velocity u_star for wind
+ * speed U at height z1 over roughness z0 with kinematic surface heat flux Qs
+ * and potential temperature th1 (Businger-Dyer stability functions). */
+double orc_most_ustar(double U, double z1, double z0, double Qs, double th1, double grav);
+
 /* saturation vapour pressure [Pa] over water and mixing ratio at (T, p) */
 double orc_esat(double T);
 double orc_qvsat(double T, double p);

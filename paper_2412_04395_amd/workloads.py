@@ -45,7 +45,7 @@ class Config:
     adv_order_v: int = 2
     scalar_scheme: int = 0  # 0: momentum interpolants, 1: WENO5-JS
     n_scalars: int = 0
-    sgs: int = 0  # 0 none, 1 Smagorinsky
+    sgs: int = 0  # 0 none, 1 Smagorinsky, 2 learned closure, 3 Deardorff TKE (scalar 0 is rho e)
     Cs: float = 0.1
     Pr_t: float = 1.0 / 3.0
     nu_m: float = 0.0
@@ -59,6 +59,7 @@ class Config:
     moist: int = 0  # 1: scalars 0, 1, 2 are rho q_v, rho q_c, rho q_r and enter the dynamics
     microphysics: int = 0  # 1: Kessler warm rain after every RK3 step (needs moist)
     anelastic: int = 0  # 1: anelastic equation set, SSP-RK2 with projections (dry, FP64)
+    most_z0: float = 0.0  # > 0: Monin-Obukhov surface layer with this roughness length [m]
     p_surface: float = 1.0e5
     seed: int = 1
 
