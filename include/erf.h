@@ -58,7 +58,16 @@ typedef enum { ERF_FP64 = 0, ERF_FP32_MIXED = 1 } erf_precision;
 /* ERF_SGS_MLP: the learned closure of erf_mlp.h in place of the Smagorinsky
  * stresses; needs erf_mlp_set_weights before the first right-hand side, and
  * nu_m = alpha_m = 0, n_scalars = 0. */
-typedef enum { ERF_SGS_NONE = 0, ERF_SGS_SMAGORINSKY = 1, ERF_SGS_MLP = 2 } erf_sgs_model;
+/* ERF_SGS_DEARDORFF: the 1.5-order TKE closure of Deardorff (1980) with the
+ * coefficients of Moeng (1984) (Sec. 2.3): rhoq component 0 is rho e (TKE e
+ * [m^2/s^2]), the only scalar (n_scalars = 1, dry, alpha_m = 0).  Length
+ * l = Delta = (dx dy dz)^(1/3), or 0.76 sqrt(e)/N where smaller in stable air
+ * (N^2 = g/theta0 dtheta/dz); K_m = 0.1 l sqrt(e) gives mu_t = rho K_m, the
+ * heat diffusivity is rho (1 + 2 l/Delta) K_m; rho e gains rho (K_m 2 S:S -
+ * K_h N^2 - (0.19 + 0.51 l/Delta) e^(3/2)/l) + div(2 rho K_m grad e), which
+ * erf_slow_rhs computes and erf_scalar_advance adds (times dts), clipping
+ * rho e at zero. */
+typedef enum { ERF_SGS_NONE = 0, ERF_SGS_SMAGORINSKY = 1, ERF_SGS_MLP = 2, ERF_SGS_DEARDORFF = 3 } erf_sgs_model;
 typedef enum { ERF_SCALAR_INTERP = 0, ERF_SCALAR_WENO5 = 1 } erf_scalar_scheme;
 
 typedef struct {
@@ -107,6 +116,16 @@ typedef struct {
                                 closure, and nx, ny powers of two <= 2048
                                 (ERF_E_SHAPE otherwise); n_substeps is then
                                 ignored.  0: compressible                        */
+    double most_z0;          /* bottom boundary: 0 a free-slip wall; > 0 (and
+                                < dz_0/2) the roughness length [m] of a
+                                Monin-Obukhov surface layer (Sec. 3.8): per
+                                column u* from the lowest cell's centre wind U
+                                (at least 0.1 m/s) by the log law with the
+                                Businger-Dyer psi_m, von Karman 0.4, Obukhov
+                                length from surf_heat_flux (z1/L clamped to
+                                [-5, 1]), twenty fixed-point steps; the surface
+                                stresses -rho u*^2 (u, v)/U act on the bottom
+                                faces (means of the two columns at each face) */
 } erf_params;
 
 /* Device pointers to one state (or tendency, or flux) set; unused members may
@@ -230,7 +249,9 @@ erf_status erf_acoustic_substeps(erf_ctx *ctx, const erf_state *S_n, const erf_s
 /* Scalar update after substepping (Sec. 3.1): (rho q)^new = (rho q)^n
  * - dts div(F q^t), q^t = (rho q)^t / rho^t, with F the stage-averaged momenta
  * (flux_avg) and the interpolant or WENO5 of Sec. 3.6 upwinded by the sign of
- * F.  rhoq_out [n_scalars][nz][ny][nx] may alias S_n->rhoq. */
+ * F.  rhoq_out [n_scalars][nz][ny][nx] may alias S_n->rhoq.  Deardorff
+ * contexts add dts times the source of rho e that the latest erf_slow_rhs
+ * computed (from its S: S_t in the RK3 driver) and clip rho e at zero. */
 erf_status erf_scalar_advance(erf_ctx *ctx, const erf_state *S_n, const erf_state *S_t,
                               const erf_state *flux_avg, double dts, void *rhoq_out);
 
@@ -309,7 +330,7 @@ erf_status erf_autotune(erf_ctx *ctx, erf_state *S, int32_t trials, const char *
  * "mixing_ratio", "scalar", "mlp" (closure network), "mlp_div" (its stress
  * divergence), "kessler" (microphysics), and of the anelastic step
  * "ssp_update", "div_fftx", "ffty" (both directions), "poisson_z", "ifftx",
- * "project".  erf_timing_begin allocates the events
+ * "project", the surface layer "most" and the TKE diffusion "tke".  erf_timing_begin allocates the events
  * (ERF_E_NOMEM on failure) and returns ERF_E_ARG for an unknown name. */
 erf_status erf_timing_begin(erf_ctx *ctx, const char *kernel, int32_t max_launches);
 /* Waits for the stream, returns the summed event time [ms] of the timed

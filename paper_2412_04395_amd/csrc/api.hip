@@ -119,11 +119,18 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     if (prm->adv_order_h < 2 || prm->adv_order_h > 6 || prm->adv_order_v < 2 || prm->adv_order_v > 6)
         return ERF_E_ARG;
     if (nq < 0 || nq > 8) return ERF_E_ARG;
-    if (prm->sgs != ERF_SGS_NONE && prm->sgs != ERF_SGS_SMAGORINSKY && prm->sgs != ERF_SGS_MLP) return ERF_E_ARG;
+    if (prm->sgs != ERF_SGS_NONE && prm->sgs != ERF_SGS_SMAGORINSKY && prm->sgs != ERF_SGS_MLP &&
+        prm->sgs != ERF_SGS_DEARDORFF)
+        return ERF_E_ARG;
+    // the Deardorff closure carries rho e as scalar 0 and no other scalar
+    if (prm->sgs == ERF_SGS_DEARDORFF && (nq != 1 || prm->moist || prm->anelastic || prm->alpha_m != 0.0))
+        return ERF_E_UNSUPPORTED;
+    if (!(prm->most_z0 >= 0.0) || (prm->most_z0 > 0.0 && !(prm->most_z0 < 0.5 * grid->dz[0]))) return ERF_E_ARG;
     if (prm->sgs == ERF_SGS_MLP && (prm->nu_m != 0.0 || prm->alpha_m != 0.0)) return ERF_E_UNSUPPORTED;
     if (prm->scalar_scheme != ERF_SCALAR_INTERP && prm->scalar_scheme != ERF_SCALAR_WENO5) return ERF_E_ARG;
     if (prm->precision != ERF_FP64 && prm->precision != ERF_FP32_MIXED) return ERF_E_ARG;
-    if (nq > 0 && (prm->sgs != ERF_SGS_NONE || prm->alpha_m != 0.0)) return ERF_E_UNSUPPORTED;
+    if (nq > 0 && ((prm->sgs != ERF_SGS_NONE && prm->sgs != ERF_SGS_DEARDORFF) || prm->alpha_m != 0.0))
+        return ERF_E_UNSUPPORTED;
     if (prm->moist != 0 && prm->moist != 1) return ERF_E_ARG;
     if (prm->moist && nq < 3) return ERF_E_ARG;  // rho q_v, rho q_c, rho q_r
     if (prm->microphysics != 0 && prm->microphysics != 1) return ERF_E_ARG;
@@ -157,6 +164,7 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
     const size_t G = prm->sgs == ERF_SGS_MLP ? N : 0;
     const size_t M = prm->moist ? N : 0;
     const size_t A8 = anel ? n * sizeof(double) : 0, A16 = anel ? n * sizeof(double2) : 0;
+    const size_t E = prm->sgs == ERF_SGS_DEARDORFF ? N : 0, MO = prm->most_z0 > 0.0 ? 2 * (size_t)nxy * es : 0;
     Anel &an = c->an;
     Req reqs[] = {
         {&ws.sa[0], N}, {&ws.sa[1], N}, {&ws.sa[2], N}, {&ws.sa[3], N}, {&ws.sa[4], Wb}, {&ws.sa[5], Q},
@@ -174,6 +182,7 @@ erf_status erf_create(const erf_grid *grid, const erf_params *prm, void *hip_str
         {&ws.sg[0], G}, {&ws.sg[1], G}, {&ws.sg[2], G}, {&ws.sg[3], G}, {&ws.sg[4], G}, {&ws.sg[5], G},
         {&ws.sg[6], G}, {&ws.sg[7], G}, {&ws.sg[8], G},
         {&ws.qf, M}, {&ws.bm, M}, {&ws.pex, M}, {&ws.rdm, M}, {(void **)&ws.precip, (size_t)nxy * D},
+        {&ws.esrc, E}, {&ws.most, MO},
         {(void **)&b.rho0, nzs * D}, {(void **)&b.theta0, nzs * D}, {(void **)&b.Theta0, nzs * D},
         {(void **)&b.p0, nzs * D}, {(void **)&b.pi0, nzs * D}, {(void **)&b.dz, (5 * nzs + 1) * D},
         {(void **)&b.qv0, nzs * D}, {(void **)&b.rho0t, nzs * D},
@@ -315,10 +324,11 @@ erf_status erf_slow_rhs(erf_ctx *c, const erf_state *S, erf_state *R)
     if (!state_ok(S, false, 0) || !state_ok(R, false, 0)) return fail(c, ERF_E_ARG, "null field pointer");
     if (c->prm.sgs == ERF_SGS_MLP && !c->mlp.have_weights)
         return fail(c, ERF_E_STATE, "erf_mlp_set_weights must precede the learned closure");
-    if (c->prm.moist && !S->rhoq) return fail(c, ERF_E_ARG, "a moist context needs S->rhoq");
+    const bool tke = c->prm.sgs == ERF_SGS_DEARDORFF;
+    if ((c->prm.moist || tke) && !S->rhoq) return fail(c, ERF_E_ARG, "this context needs S->rhoq");
     const void *s5[5] = {S->rho, S->rhotheta, S->rhou, S->rhov, S->rhow};
     void *r5[5] = {R->rho, R->rhotheta, R->rhou, R->rhov, R->rhow};
-    hipError_t e = launch_slow_rhs(c, s5, c->prm.moist ? S->rhoq : nullptr, r5);
+    hipError_t e = launch_slow_rhs(c, s5, (c->prm.moist || tke) ? S->rhoq : nullptr, r5);
     return e == hipSuccess ? ERF_OK : hip_fail(c, e, "slow rhs launch");
 }
 

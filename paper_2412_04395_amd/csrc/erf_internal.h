@@ -305,6 +305,9 @@ struct Workspace {
     void *qf = nullptr, *bm = nullptr, *pex = nullptr, *rdm = nullptr;
     // rain accumulated at the ground by the microphysics [kg/m^2], [ny][nx]
     double *precip = nullptr;
+    // Deardorff closure: the source of rho e at the latest right-hand side's
+    // state (centres); surface layer: tau_13, tau_23 per column ([2][ny][nx])
+    void *esrc = nullptr, *most = nullptr;
     // learned closure: rho tau_11, 22, 33, 12, 13, 23 and rho q_1, 2, 3 at
     // centres (allocated for the learned closure only)
     void *sg[9] = {};
@@ -410,12 +413,14 @@ namespace erfk {
 
 // kernel ids for the timing instrumentation
 enum KernelId { K_PREP, K_MUT, K_STRESS, K_RHS, K_STAGE_INIT, K_COEF, K_SUBSTEP, K_FINALIZE, K_MIXRATIO, K_SCALAR,
-                K_MLP, K_MLP_DIV, K_KESSLER, K_SSP, K_DIVFFTX, K_FFTY, K_POISSON, K_IFFTX, K_PROJECT, K_COUNT };
+                K_MLP, K_MLP_DIV, K_KESSLER, K_SSP, K_DIVFFTX, K_FFTY, K_POISSON, K_IFFTX, K_PROJECT, K_MOST,
+                K_TKE, K_COUNT };
 inline const char *kernel_name(int id)
 {
     static const char *names[K_COUNT] = {"prep", "mut", "stress", "rhs", "stage_init", "coef", "substep",
                                          "finalize", "mixing_ratio", "scalar", "mlp", "mlp_div", "kessler",
-                                         "ssp_update", "div_fftx", "ffty", "poisson_z", "ifftx", "project"};
+                                         "ssp_update", "div_fftx", "ffty", "poisson_z", "ifftx", "project",
+                                         "most", "tke"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 // The batched instance KB of a kernel, launched over the block ranges of map

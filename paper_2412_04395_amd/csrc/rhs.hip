@@ -7,7 +7,11 @@
 // Passes per call:
 //   k_prep    primitive fields: theta, p' at centres, u, v, w on faces (moist:
 //             also 1 + q_v + q_c and the total-density departure)
-//   k_mut     Smagorinsky eddy viscosity at centres (SGS model only)
+//   k_most    Monin-Obukhov surface layer (Sec. 3.8): per column the friction
+//             velocity and the surface stresses (with a roughness length only)
+//   k_mut     eddy viscosity at centres: Smagorinsky, or the Deardorff TKE
+//             closure (Sec. 2.3) with its heat diffusivity and the local
+//             source of rho e; k_tke adds that source's diffusion
 //   k_stress  stress tensor of eq. (stresstensor) at its staggered points
 //             (normal stresses at centres, shear stresses on edges) and the
 //             heat diffusivity (any viscous run)
@@ -49,6 +53,11 @@ struct RhsArgs {
     // total-density departure at centres
     T *th, *pp, *u, *v, *w, *mut, *qf, *bm;
     T *t11, *t22, *t33, *t12, *t13, *t23, *kap;
+    // Deardorff closure: the source of rho e (scalar 0 of rq); surface layer:
+    // per column the surface stresses tau_13, tau_23 at the cell centre
+    // ([2][ny][nx], null without one) and the roughness length
+    T *esrc, *most;
+    double z0;
     // outputs
     T *Rr, *Rt, *Ru, *Rv, *Rw;
 };
@@ -138,7 +147,7 @@ __global__ __launch_bounds__(256) void k_prep_batch(const RhsArgs<T> *args, Batc
 // Branch-free: neighbours by selects, vertical neighbours clamped; the lid
 // edges drop out because 2/(dz_{k-1} + dz_k) is zero on the lids and w is zero
 // on the lid faces.
-template <typename T>
+template <typename T, bool kTke>
 __device__ __forceinline__ void k_mut_body(RhsArgs<T> a, VBlock vb)
 {
     using R = T;
@@ -175,19 +184,148 @@ __device__ __forceinline__ void k_mut_body(RhsArgs<T> a, VBlock vb)
     const R a23 = q4 * (h * ((v_c - v_b) * gz0 + (w_c - w_s) * idy) + h * ((v_n - v_bn) * gz0 + (w_n - w_c) * idy) +
                         h * ((v_t - v_c) * gz1 + (w_u - w_su) * idy) + h * ((v_tn - v_n) * gz1 + (w_nu - w_u) * idy));
     const R ss = R(2) * (e11 * e11 + e22 * e22 + e33 * e33) + R(4) * (a12 * a12 + a13 * a13 + a23 * a23);
-    st_stream(a.mut + lk + rj + i, (T)(rc * (R)a.cs2[k] * sqrt(ss)));  // read by a later launch only
+    const int c = lk + rj + i;
+    if constexpr (!kTke) {
+        st_stream(a.mut + c, (T)(rc * (R)a.cs2[k] * sqrt(ss)));  // read by a later launch only
+    } else {
+        // Deardorff (1980) 1.5-order closure, coefficients of Moeng (1984):
+        // l = Delta, or 0.76 sqrt(e)/N where smaller in stable air;
+        // K_m = 0.1 l sqrt(e), K_h = (1 + 2 l/Delta) K_m; source of rho e
+        // rho (K_m 2 S:S - K_h N^2 - C_eps e^(3/2)/l), C_eps = 0.19 + 0.51 l/Delta;
+        // N^2 = g/theta0 dtheta/dz with dtheta/dz the mean of the two face
+        // differences (zero through the lids)
+        R e = (R)a.rq[c] / rc;
+        e = e < R(0) ? R(0) : e;
+        const R dth0u = k < nz - 1 ? (R)(a.theta0[k + 1] - a.theta0[k]) : R(0);
+        const R dth0d = k > 0 ? (R)(a.theta0[k] - a.theta0[k - 1]) : R(0);
+        const R thc = (R)a.th[c], thu = (R)a.th[lkp + rj + i], thd = (R)a.th[lkm + rj + i];
+        // FP32 storage holds theta - theta0(k): the base difference is added
+        const R up = k < nz - 1 ? ((thu - thc) + (kPert<T> ? dth0u : R(0))) * gz1 : R(0);
+        const R dn = k > 0 ? ((thc - thd) + (kPert<T> ? dth0d : R(0))) * gz0 : R(0);
+        const R N2 = (R)a.g / (R)a.theta0[k] * (h * (up + dn));
+        const R delta = (R)cbrt(a.dx * a.dy * a.dz[k]);
+        const R se = sqrt(e), sn = sqrt(N2 > R(0) ? N2 : R(0));
+        const bool limited = N2 > R(0) && R(0.76) * se / sn < delta;
+        const R l = limited ? R(0.76) * se / sn : delta;
+        const R Km = R(0.1) * l * se, Kh = (R(1) + R(2) * l / delta) * Km;
+        const R ceps = R(0.19) + R(0.51) * l / delta;
+        // e^(3/2)/l, written as e N/0.76 where l is the stable length
+        const R eps = limited ? ceps * e * sn / R(0.76) : ceps * e * se / delta;
+        st_stream(a.mut + c, (T)(rc * Km));
+        st_stream(a.kap + c, (T)(rc * (R)a.alpha + rc * Kh));
+        a.esrc[c] = (T)(rc * (Km * ss - Kh * N2 - eps));
+    }
 }
-template <typename T>
+template <typename T, bool kTke>
 __global__ __launch_bounds__(256) void k_mut(RhsArgs<T> a)
 {
-    k_mut_body<T>(a, hw_block());
+    k_mut_body<T, kTke>(a, hw_block());
 }
-template <typename T>
+template <typename T, bool kTke>
 __global__ __launch_bounds__(256) void k_mut_batch(const RhsArgs<T> *args, BatchMap bm)
 {
     int m;
     VBlock vb;
-    if (batch_block(bm, m, vb)) k_mut_body<T>(args[m], vb);
+    if (batch_block(bm, m, vb)) k_mut_body<T, kTke>(args[m], vb);
+}
+
+// The diffusion of rho e, div(2 rho K_m grad e) with rho K_m = mu_t, face
+// coefficients the mean of the two cells, no flux through the lids, added to
+// the local source of k_mut.
+template <typename T>
+__device__ __forceinline__ void k_tke_body(RhsArgs<T> a, VBlock vb)
+{
+    using R = T;
+    const Dims &d = a.d;
+    const TileIdx t = tile_cell(vb, a.ntx, a.nty);
+    const int i = t.i, j = t.j, k = t.k;
+    if (i >= d.nx || j >= d.ny) return;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.nxy;
+    const int c = (k * ny + j) * nx + i;
+    const int cw = c + (i == 0 ? nx - 1 : -1), ce = c + (i == nx - 1 ? 1 - nx : 1);
+    const int cs = c + (j == 0 ? (ny - 1) * nx : -nx), cn = c + (j == ny - 1 ? (1 - ny) * nx : nx);
+    const int cb = k > 0 ? c - P : c, ct = k < nz - 1 ? c + P : c;
+    const int kb = k > 0 ? k - 1 : 0, kt = k < nz - 1 ? k + 1 : nz - 1;
+    auto ev = [&](int cc, int kk) {
+        const R r = full_in(a.rho, cc, a.rho0[kk]);
+        const R e = (R)a.rq[cc] / r;
+        return e < R(0) ? R(0) : e;
+    };
+    const R e_c = ev(c, k), e_w = ev(cw, k), e_e = ev(ce, k), e_s = ev(cs, k), e_n = ev(cn, k);
+    const R e_b = ev(cb, kb), e_t = ev(ct, kt);
+    const R m_c = a.mut[c], m_w = a.mut[cw], m_e = a.mut[ce], m_s = a.mut[cs], m_n = a.mut[cn];
+    const R m_b = a.mut[cb], m_t = a.mut[ct];
+    const R idx = (R)a.idx, idy = (R)a.idy;
+    const R fx0 = -(m_w + m_c) * (e_c - e_w) * idx, fx1 = -(m_c + m_e) * (e_e - e_c) * idx;
+    const R fy0 = -(m_s + m_c) * (e_c - e_s) * idy, fy1 = -(m_c + m_n) * (e_n - e_c) * idy;
+    const R fz0 = k > 0 ? -(m_b + m_c) * (e_c - e_b) * (R)a.idzf[k] : R(0);
+    const R fz1 = k < nz - 1 ? -(m_c + m_t) * (e_t - e_c) * (R)a.idzf[k + 1] : R(0);
+    const R src = (R)a.esrc[c];
+    a.esrc[c] = (T)(src - ((fx1 - fx0) * idx + (fy1 - fy0) * idy + (fz1 - fz0) * (R)a.idz[k]));
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_tke(RhsArgs<T> a)
+{
+    k_tke_body<T>(a, hw_block());
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_tke_batch(const RhsArgs<T> *args, BatchMap bm)
+{
+    int m;
+    VBlock vb;
+    if (batch_block(bm, m, vb)) k_tke_body<T>(args[m], vb);
+}
+
+// Monin-Obukhov surface layer (Sec. 3.8), one thread per column: von Karman
+// constant 0.4, Businger-Dyer psi_m (x = (1 - 16 zeta)^(1/4) for zeta < 0,
+// -5 zeta otherwise), zeta = z1/L with L = -u*^3 theta_1/(kappa g Qs) clamped
+// to [-5, 1], u* from the log law by twenty fixed-point steps from the
+// neutral value; the surface stresses -rho u*^2 (u, v)/U at the lowest cell
+// centre from its centre wind (U at least 0.1 m/s), in FP64.
+__device__ __forceinline__ double most_psi_m(double zeta)
+{
+    if (zeta >= 0.0) return -5.0 * zeta;
+    const double x = pow(1.0 - 16.0 * zeta, 0.25);
+    return 2.0 * log(0.5 * (1.0 + x)) + log(0.5 * (1.0 + x * x)) - 2.0 * atan(x) + 2.0 * atan(1.0);
+}
+template <typename T>
+__device__ __forceinline__ void k_most_body(RhsArgs<T> a, VBlock vb)
+{
+    const Dims &d = a.d;
+    const int col = vb.x * blockDim.x + threadIdx.x;
+    if (col >= d.nxy) return;
+    const int j = col / d.nx, i = col - j * d.nx;
+    const int ce = col + (i == d.nx - 1 ? 1 - d.nx : 1), cn = col + (j == d.ny - 1 ? (1 - d.ny) * d.nx : d.nx);
+    const double u1 = 0.5 * ((double)a.u[col] + (double)a.u[ce]);
+    const double v1 = 0.5 * ((double)a.v[col] + (double)a.v[cn]);
+    double U = sqrt(u1 * u1 + v1 * v1);
+    if (U < 0.1) U = 0.1;
+    const double th1 = kPert<T> ? (double)a.th[col] + a.theta0[0] : (double)a.th[col];
+    const double rho1 = kPert<T> ? a.rho0[0] + (double)a.rho[col] : (double)a.rho[col];
+    const double z1 = 0.5 * a.dz[0], lnz = log(z1 / a.z0), kap = 0.4;
+    double ust = kap * U / lnz;
+    for (int it = 0; it < 20; ++it) {
+        double zeta = 0.0;
+        if (a.Qs != 0.0) {
+            zeta = -z1 * kap * a.g * a.Qs / (ust * ust * ust * th1);
+            zeta = zeta < -5.0 ? -5.0 : (zeta > 1.0 ? 1.0 : zeta);
+        }
+        ust = kap * U / (lnz - most_psi_m(zeta));
+    }
+    a.most[col] = (T)(-rho1 * ust * ust * u1 / U);
+    a.most[d.nxy + col] = (T)(-rho1 * ust * ust * v1 / U);
+}
+template <typename T>
+__global__ __launch_bounds__(64) void k_most(RhsArgs<T> a)
+{
+    k_most_body<T>(a, hw_block());
+}
+template <typename T>
+__global__ __launch_bounds__(64) void k_most_batch(const RhsArgs<T> *args, BatchMap bm)
+{
+    int m;
+    VBlock vb;
+    if (batch_block(bm, m, vb)) k_most_body<T>(args[m], vb);
 }
 
 // Stresses tau = -2 mu (S - D) at their points, mu = rho nu_m + mu_t averaged
@@ -244,15 +382,23 @@ __device__ __forceinline__ void k_stress_body(RhsArgs<T> a, VBlock vb)
     const R dd = (e11 + e22 + e33) / R(3);
     const R s12 = h * ((u_f - u_s) * idy + (v_f - v_w) * idx);
     const R me = q4 * (m_ws + m_s + m_w + m_c);
-    st_stream(a.t13 + lf + rj + i, (T)(inner ? m2 * mxz * s13 : R(0)));
-    st_stream(a.t23 + lf + rj + i, (T)(inner ? m2 * myz * s23 : R(0)));
+    // the bottom faces carry the surface layer's stresses (means of the two
+    // columns beside the edge), else zero as the top's
+    R s13b = R(0), s23b = R(0);
+    if (k == 0 && a.most) {
+        s13b = h * ((R)a.most[rj + im] + (R)a.most[rj + i]);
+        s23b = h * ((R)a.most[P + rjm + i] + (R)a.most[P + rj + i]);
+    }
+    st_stream(a.t13 + lf + rj + i, (T)(inner ? m2 * mxz * s13 : s13b));
+    st_stream(a.t23 + lf + rj + i, (T)(inner ? m2 * myz * s23 : s23b));
     if (k < nz) {
         const int c = lc + rj + i;
         st_stream(a.t11 + c, (T)(m2 * m_c * (e11 - dd)));
         st_stream(a.t22 + c, (T)(m2 * m_c * (e22 - dd)));
         st_stream(a.t33 + c, (T)(m2 * m_c * (e33 - dd)));
         st_stream(a.t12 + c, (T)(m2 * me * s12));
-        st_stream(a.kap + c, (T)(rc * (R)a.alpha + (sgs ? mtc / (R)a.Pr_t : R(0))));
+        // (the Deardorff closure's diffusivity is k_mut's)
+        if (a.sgs != 3) st_stream(a.kap + c, (T)(rc * (R)a.alpha + (sgs ? mtc / (R)a.Pr_t : R(0))));
     }
 }
 template <typename T>
@@ -613,7 +759,10 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], const void *rq, void 
     // the learned closure adds its own stress divergence after k_rhs
     const bool mlp = p.sgs == ERF_SGS_MLP;
     a.sgs = mlp ? 0 : p.sgs;
-    a.visc = (a.sgs != 0 || p.nu_m != 0.0 || p.alpha_m != 0.0) ? 1 : 0;
+    a.visc = (a.sgs != 0 || p.nu_m != 0.0 || p.alpha_m != 0.0 || p.most_z0 > 0.0) ? 1 : 0;
+    a.z0 = p.most_z0;
+    a.most = p.most_z0 > 0.0 ? (T *)ws.most : nullptr;
+    a.esrc = (T *)ws.esrc;
     a.Cs = p.Cs;
     a.Pr_t = p.Pr_t;
     a.nu = p.nu_m;
@@ -636,6 +785,7 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], const void *rq, void 
     // moist dynamics need the water species; without them (the closure's
     // feature pass, which uses no pressure) the dry primitives are computed
     const bool moist = p.moist != 0 && rq != nullptr;
+    const bool tke = p.sgs == ERF_SGS_DEARDORFF;
     a.rq = (const T *)rq;
     a.qf = (T *)ws.qf;
     a.bm = (T *)ws.bm;
@@ -671,10 +821,23 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], const void *rq, void 
         run<RhsArgs<T>, k_prep<T, false>, k_prep_batch<T, false>>(cx, grd, blk, 0, a);
     timing_stop(cx, K_PREP);
     if (prep_only) return hipGetLastError();
+    if (a.most) {
+        timing_start(cx, K_MOST);
+        run<RhsArgs<T>, k_most<T>, k_most_batch<T>>(cx, dim3((d.nxy + 63) / 64), dim3(64), 0, a);
+        timing_stop(cx, K_MOST);
+    }
     if (a.sgs) {
         timing_start(cx, K_MUT);
-        run<RhsArgs<T>, k_mut<T>, k_mut_batch<T>>(cx, grd, blk, 0, a);
+        if (tke)
+            run<RhsArgs<T>, k_mut<T, true>, k_mut_batch<T, true>>(cx, grd, blk, 0, a);
+        else
+            run<RhsArgs<T>, k_mut<T, false>, k_mut_batch<T, false>>(cx, grd, blk, 0, a);
         timing_stop(cx, K_MUT);
+    }
+    if (tke) {
+        timing_start(cx, K_TKE);
+        run<RhsArgs<T>, k_tke<T>, k_tke_batch<T>>(cx, grd, blk, 0, a);
+        timing_stop(cx, K_TKE);
     }
     if (a.visc) {
         timing_start(cx, K_STRESS);

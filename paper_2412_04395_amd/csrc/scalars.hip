@@ -19,6 +19,9 @@ struct ScalArgs {
     const double *idz, *rho0;
     const T *rqn, *rho_t, *rq_t, *Fu, *Fv, *Fw;
     T *q, *out;
+    // the Deardorff closure: the source of rho e (scalar 0), added times dts
+    // and the result clipped at zero (null otherwise)
+    const T *src;
 };
 
 // q^t = (rho q)^t / rho^t; one thread per cell for every scalar (rho read once)
@@ -204,8 +207,13 @@ __device__ __forceinline__ void k_scalar_body(ScalArgs<T> a, VBlock vb)
         if (own) {
             const R fx1 = fxs[row][lane + 1], fy1 = fys[row + 1][lane];
             const R div = (fx1 - fx0) * idx + (fy1 - fy0) * idy + (fz1 - fz_below) * (R)a.idz[k];
+            R v = rq - dts * div;
+            if (s == 0 && a.src) {
+                v = v + dts * (R)a.src[pl + col];
+                v = v < R(0) ? R(0) : v;
+            }
             // read by later launches only (and rqn[o], its only other use, is read above)
-            st_stream(a.out + o, (T)(rq - dts * div));
+            st_stream(a.out + o, (T)v);
         }
         fz_below = fz1;
     }
@@ -250,6 +258,7 @@ hipError_t scalar_t(erf_ctx *cx, const void *rqn, const void *rho_t, const void 
     a.Fw = (const T *)Fw;
     a.q = (T *)cx->ws.q;
     a.out = (T *)rq_out;
+    a.src = cx->prm.sgs == ERF_SGS_DEARDORFF ? (const T *)cx->ws.esrc : nullptr;
     if (a.nq <= 0) return hipSuccess;
     timing_start(cx, K_MIXRATIO);
     run<ScalArgs<T>, k_mixing_ratio<T>, k_mixing_ratio_batch<T>>(cx, dim3((d.n + 255) / 256), dim3(256), 0, a);

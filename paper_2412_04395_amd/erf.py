@@ -63,7 +63,8 @@ class Params(C.Structure):
                 ("Cs", C.c_double), ("Pr_t", C.c_double), ("nu_m", C.c_double), ("alpha_m", C.c_double),
                 ("f_cor", C.c_double), ("Ug", C.c_double), ("Vg", C.c_double),
                 ("surf_heat_flux", C.c_double), ("grav", C.c_double), ("precision", C.c_int32),
-                ("moist", C.c_int32), ("microphysics", C.c_int32), ("anelastic", C.c_int32)]
+                ("moist", C.c_int32), ("microphysics", C.c_int32), ("anelastic", C.c_int32),
+                ("most_z0", C.c_double)]
 
 
 class State(C.Structure):
@@ -207,7 +208,8 @@ def params_from_config(cfg) -> Params:
     return Params(cfg.dt, cfg.n_substeps, cfg.beta_s, cfg.beta_d, cfg.adv_order_h, cfg.adv_order_v,
                   cfg.scalar_scheme, cfg.n_scalars, cfg.sgs, cfg.Cs, cfg.Pr_t, cfg.nu_m, cfg.alpha_m,
                   cfg.f_cor, cfg.Ug, cfg.Vg, cfg.surf_heat_flux, cfg.grav, prec, int(getattr(cfg, "moist", 0)),
-                  int(getattr(cfg, "microphysics", 0)), int(getattr(cfg, "anelastic", 0)))
+                  int(getattr(cfg, "microphysics", 0)), int(getattr(cfg, "anelastic", 0)),
+                  float(getattr(cfg, "most_z0", 0.0)))
 
 
 def layout(cfg, field: str) -> dict:

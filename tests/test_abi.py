@@ -109,7 +109,15 @@ def test_create_rejects_bad_arguments_before_touching_the_gpu():
     assert _create(cfg.replace(n_scalars=9))[0] == erf.ERF_E_ARG
     assert _create(cfg.replace(n_scalars=1, sgs=1))[0] == erf.ERF_E_UNSUPPORTED
     assert _create(cfg.replace(dt=0.0))[0] == erf.ERF_E_ARG
-    assert _create(cfg.replace(sgs=3))[0] == erf.ERF_E_ARG
+    assert _create(cfg.replace(sgs=4))[0] == erf.ERF_E_ARG
+    # the Deardorff closure needs rho e as its one scalar, dry, compressible
+    assert _create(cfg.replace(sgs=3))[0] == erf.ERF_E_UNSUPPORTED
+    assert _create(cfg.replace(sgs=3, n_scalars=2))[0] == erf.ERF_E_UNSUPPORTED
+    assert _create(cfg.replace(sgs=3, n_scalars=3, moist=1))[0] == erf.ERF_E_UNSUPPORTED
+    assert _create(cfg.replace(sgs=3, n_scalars=1, alpha_m=1.0))[0] == erf.ERF_E_UNSUPPORTED
+    # the roughness length lies between 0 and half the lowest cell
+    assert _create(cfg.replace(most_z0=-0.1))[0] == erf.ERF_E_ARG
+    assert _create(cfg.replace(most_z0=0.5 * cfg.dz[0]))[0] == erf.ERF_E_ARG
     assert _create(cfg.replace(sgs=2, nu_m=1e-3))[0] == erf.ERF_E_UNSUPPORTED
     assert _create(cfg.replace(sgs=2, n_scalars=1))[0] == erf.ERF_E_UNSUPPORTED
     L = erf.load()
