@@ -68,6 +68,8 @@ KERNEL_VALUES = {
     "coef": lambda sgs: (3 + 1, 1),
     # S^t and S'' read; S_out written
     "finalize": lambda sgs: (10 + 5, 0),
+    # Deardorff closure: rho e, rho, mu_t and the local source read; the source written
+    "tke": lambda sgs: (4 + 1, 0),
 }
 # Advected scalars (nq of them), per cell of one launch: the mixing ratios
 # q^t = (rho q)^t / rho^t (rho q and rho read, q written); the scalar update
@@ -163,7 +165,8 @@ def run_gpu(cfg: W.Config, steps: int, warmup: int):
     # find the kernel with the largest share of a step (one short timed step per kernel)
     shares = {}
     for k in (list(KERNEL_VALUES) + (list(SCALAR_VALUES) if cfg.n_scalars else []) +
-              (list(MICRO_VALUES) if getattr(cfg, "microphysics", 0) else [])):
+              (list(MICRO_VALUES) if getattr(cfg, "microphysics", 0) else []) +
+              (["tke"] if cfg.sgs == 3 else []) + (["most"] if getattr(cfg, "most_z0", 0.0) > 0 else [])):
         if k == "mut" and not cfg.sgs:
             continue
         _, (ms, n) = _time_steps(s, S, 1, torch, kernel=k)
@@ -512,6 +515,19 @@ def run_scalars(steps: int, warmup: int) -> dict:
     return out
 
 
+def run_tke(steps: int, warmup: int) -> dict:
+    """The 256 x 256 x 128 boundary layer with the Deardorff TKE closure and a
+    Monin-Obukhov surface layer (FP64, 14 substeps)."""
+    cfg = W.cbl_tke()
+    el, dom, kms, kn, shares, diag = run_gpu(cfg, steps, warmup)
+    return {"workload": "boundary-layer LES 256x256x128, Deardorff TKE closure, surface layer z0 = 0.1 m",
+            "grid": [cfg.nx, cfg.ny, cfg.nz], "precision": "fp64", "n_substeps": cfg.n_substeps,
+            "value": cfg.cells * steps / el, "unit": "cell-updates/s", "ms_per_step": 1e3 * el / steps,
+            "kernel_ms_per_step": {k: round(v[0], 4) for k, v in shares.items()},
+            "roofline": _roofline(cfg, dom, kms, kn),
+            "final_diag": {"max_w": diag["max_w"], "nonfinite": diag["nonfinite"]}}
+
+
 def run_anelastic(steps: int, warmup: int) -> dict:
     """The boundary-layer workload in the anelastic equation set: 256 x 256 x
     128, FP64, Smagorinsky, SSP-RK2 with a projection after each stage, the
@@ -573,6 +589,8 @@ def _substep_value_adjust(cfg) -> float:
 
 
 def _roofline(cfg, dom, kms, kn):
+    if dom not in KERNEL_VALUES:
+        return {"kernel": dom, "avg_launch_ms": round(kms / max(kn, 1), 4), "note": "no per-cell byte count"}
     sgs = 1 if cfg.sgs else 0
     avg_ms = kms / max(kn, 1)
     bytes_per_launch = _kernel_bytes(dom, sgs, cfg.prec) * cfg.cells
@@ -600,6 +618,7 @@ def main(argv=None):
     ap.add_argument("--no-training", action="store_true")
     ap.add_argument("--no-scalars", action="store_true")
     ap.add_argument("--no-anelastic", action="store_true")
+    ap.add_argument("--no-tke", action="store_true")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first run one plain device copy of this many GiB (reference for HBM counters)")
     a = ap.parse_args(argv)
@@ -624,6 +643,9 @@ def main(argv=None):
         return 0
     if a.workload == "anelastic":
         print(json.dumps(run_anelastic(a.steps, a.warmup)), flush=True)
+        return 0
+    if a.workload == "tke":
+        print(json.dumps(run_tke(a.steps, a.warmup)), flush=True)
         return 0
     if a.workload == "closure_training":
         print(json.dumps(run_training(a.steps)), flush=True)
@@ -670,6 +692,8 @@ def main(argv=None):
         out["training"] = run_training(a.steps)
     if a.workload == "cbl" and not a.no_scalars:
         out["scalars"] = run_scalars(min(a.steps, 10), min(a.warmup, 2))
+    if a.workload == "cbl" and not a.no_tke:
+        out["tke"] = run_tke(a.steps, a.warmup)
     if a.workload == "cbl" and not a.no_anelastic:
         out["anelastic"] = run_anelastic(a.steps, a.warmup)
     if a.workload == "cbl" and not a.no_ensemble:

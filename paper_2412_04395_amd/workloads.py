@@ -264,6 +264,9 @@ def initial_state(cfg: Config, rho0: np.ndarray, theta0: np.ndarray, p0: Optiona
     S = state_from_theta(cfg, rho0, theta0, dth, u0, v0)
     if cfg.n_scalars > 0:
         S["rq"] = scalar_layers(cfg, S["rho"], rho0, theta0, p0, pi0, qv0)
+    if cfg.sgs == 3:
+        # the Deardorff closure's rho e: a seed of 0.1 m^2/s^2 below 400 m
+        S["rq"][0] = S["rho"] * np.where(Z < 400.0, 0.1, 0.0)
     return S
 
 
@@ -314,6 +317,15 @@ def cbl(n_substeps: int = 6, **kw) -> Config:
     c = Config(name="cbl", nx=256, ny=256, nz=128, dx=20.0, dy=20.0, dz=uniform_dz(128, 10.0),
                dt=0.5, n_substeps=n_substeps, steps=20, adv_order_h=5, adv_order_v=5, sgs=1,
                Cs=0.1, Pr_t=1.0 / 3.0, f_cor=1.0e-4, Ug=10.0, Vg=0.0, surf_heat_flux=0.2, seed=2)
+    return c.replace(**kw)
+
+
+def cbl_tke(**kw) -> Config:
+    """The boundary layer of cbl() with the Deardorff TKE closure (rho e as
+    its one scalar, 5th-order upwind like momentum) and a Monin-Obukhov
+    surface layer over z0 = 0.1 m, as the paper's ABL cases (Sec. 4.2), with
+    the stable 14 substeps."""
+    c = cbl(n_substeps=14, name="cbl_tke", sgs=3, n_scalars=1, scalar_scheme=0, most_z0=0.1)
     return c.replace(**kw)
 
 
