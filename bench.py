@@ -87,13 +87,19 @@ ZERO_START_SAVED = {"stage_init": 13, "substep": 6}
 # FP64: the stage update reads S^n, R1 (and R2) for rho theta and the three
 # momenta and writes four fields (12 values in stage 1, 16 in stage 2: 14 on
 # average); the projection's divergence and x transform read three momenta
-# and write a complex value; each y transform reads and writes a complex
-# value; the z solve reads and writes the complex value twice and writes and
-# reads the Thomas factor; the inverse x transform reads a complex value and
-# writes phi; the correction reads three momenta, phi, the pressure and writes
-# the momenta and the pressure.
-ANEL_VALUES = {"ssp_update": 14, "div_fftx": 5, "ffty": 4, "poisson_z": 10, "ifftx": 3, "project": 9}
-ANEL_KERNELS = ("prep", "mut", "stress", "rhs") + tuple(ANEL_VALUES)
+# and write a complex value of the half spectrum (nx/2 + 1 of nx per line);
+# each y transform reads and writes a complex value of it; the z solve reads
+# and writes the complex value twice and writes and reads the Thomas factor;
+# the inverse x transform reads a complex value and writes phi; the
+# correction reads three momenta, phi, the pressure and writes the momenta
+# and the pressure.  h = (nx/2 + 1)/nx.
+def anel_values(nx: int) -> dict:
+    h = (nx // 2 + 1) / nx
+    return {"ssp_update": 14, "div_fftx": 3 + 2 * h, "ffty": 4 * h, "poisson_z": 10 * h, "ifftx": 2 * h + 1,
+            "project": 9}
+
+
+ANEL_KERNELS = ("prep", "mut", "stress", "rhs", "ssp_update", "div_fftx", "ffty", "poisson_z", "ifftx", "project")
 
 # Moist dynamics, per stage: the primitives pass also reads rho q_v, rho q_c,
 # rho q_r and writes 1 + q_v + q_c and the total-density departure, which the
@@ -565,7 +571,8 @@ def run_anelastic(steps: int, warmup: int) -> dict:
     d = s.diagnostics(S, allow_nonfinite=True)
     s.close()
     avg_ms = kms / max(kn, 1)
-    vals = ANEL_VALUES[dom] if dom in ANEL_VALUES else KERNEL_VALUES[dom](1)[0]
+    av = anel_values(cfg.nx)
+    vals = av[dom] if dom in av else KERNEL_VALUES[dom](1)[0]
     byts = vals * 8.0 * cfg.cells
     gbs = byts / (avg_ms * 1e-3) / 1e9
     return {"workload": "boundary-layer LES 256x256x128 in the anelastic equation set (SSP-RK2, projections)",
@@ -598,10 +605,19 @@ def _roofline(cfg, dom, kms, kn):
         bytes_per_launch += _substep_value_adjust(cfg) * (8.0 if cfg.prec == "fp64" else 4.0) * cfg.cells
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic, tsrc = _profiled_traffic(dom, cfg.prec) if "stable" in cfg.name else (None, None)
-    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": tsrc,
-            "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_ms, 4),
-            "launches_timed": kn}
+    out = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": tsrc,
+           "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_ms, 4),
+           "launches_timed": kn}
+    if dom == "substep":
+        # the streaming model's substep: F perturbations, F tendencies, two
+        # coefficients and the previous Theta'' read, F perturbations written
+        # (3F + 3 values, F = 5), plus 6 for the flux sums with scalars
+        mv = 3 * 5 + 3 + (6 if cfg.n_scalars else 0)
+        mb = mv * (8.0 if cfg.prec == "fp64" else 4.0) * cfg.cells
+        out["model_values_per_cell"] = mv
+        out["model_frac"] = round(mb / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
 
 
 def main(argv=None):

@@ -9,12 +9,17 @@
 //                 div(U* q*)) / 2
 //   projection    dt div grad psi = div(rho0 u); with phi = dt psi:
 //     k_div_fftx  the divergence of the face momenta along one x-line and its
-//                 discrete Fourier transform in x
-//     k_ffty      the transform in y of a few adjacent x-columns per block
+//                 discrete Fourier transform in x, of which the x-wavenumbers
+//                 0..nx/2 are kept (the divergence is real: the others are
+//                 their complex conjugates)
+//     k_ffty      the transform in y of a few adjacent x-wavenumbers per block
 //     k_poisson_z per horizontal wavenumber the tridiagonal z solve (Thomas;
 //                 real coefficients, complex right-hand side)
-//     k_ffty      (inverse), then k_ifftx: the inverse in x and 1/(nx ny)
+//     k_ffty      (inverse), then k_ifftx: the line completed by conjugate
+//                 symmetry, the inverse in x and 1/(nx ny)
 //     k_project   face momenta minus grad phi; the pressure plus phi / dt
+// The half spectrum holds nh = nx/2 + 1 wavenumbers per line ([nz][ny][nh]):
+// the y transforms and the z solves run over nh (not nx) columns.
 //
 // The transforms are radix-2 Stockham passes in LDS (no bit-reversal pass):
 // nx and ny are powers of two up to 2048, so that a whole line of complex
@@ -121,22 +126,30 @@ __global__ __launch_bounds__(256) void k_div_fftx(ProjArgs a)
     }
     __syncthreads();
     const double2 *r = fft_lds(A, B, a.lgx, 1, a.twx, false);
-    for (int i = threadIdx.x; i < nx; i += blockDim.x) a.Z[base + i] = r[i];
+    const int nh = nx / 2 + 1;
+    for (int m = threadIdx.x; m < nh; m += blockDim.x) a.Z[row * nh + m] = r[m];
 }
 
-// one block per (level, group of `cols` adjacent x-columns): transform in y
+// one block per (level, group of `cols` adjacent x-wavenumbers): transform in
+// y (the last group of a level may be partly past nh: zeros, not stored)
 __global__ __launch_bounds__(256) void k_ffty(ProjArgs a, int inverse)
 {
     extern __shared__ double2 lds[];
     const Dims &d = a.d;
-    const int cols = a.cols, ny = d.ny, groups = d.nx / cols;
-    const int k = blockIdx.x / groups, i0 = (blockIdx.x - k * groups) * cols;
+    const int nh = d.nx / 2 + 1, cols = a.cols, ny = d.ny, groups = (nh + cols - 1) / cols;
+    const int k = blockIdx.x / groups, m0 = (blockIdx.x - k * groups) * cols;
     double2 *A = lds, *B = lds + ny * cols;
-    double2 *Z = a.Z + (size_t)k * d.nxy + i0;
-    for (int t = threadIdx.x; t < ny * cols; t += blockDim.x) A[t] = Z[(t / cols) * d.nx + t % cols];
+    double2 *Z = a.Z + (size_t)k * ny * nh + m0;
+    for (int t = threadIdx.x; t < ny * cols; t += blockDim.x) {
+        const int q = t % cols;
+        A[t] = m0 + q < nh ? Z[(t / cols) * nh + q] : make_double2(0.0, 0.0);
+    }
     __syncthreads();
     const double2 *r = fft_lds(A, B, a.lgy, cols, a.twy, inverse != 0);
-    for (int t = threadIdx.x; t < ny * cols; t += blockDim.x) Z[(t / cols) * d.nx + t % cols] = r[t];
+    for (int t = threadIdx.x; t < ny * cols; t += blockDim.x) {
+        const int q = t % cols;
+        if (m0 + q < nh) Z[(t / cols) * nh + q] = r[t];
+    }
 }
 
 // one thread per horizontal wavenumber (m, l): the z operator
@@ -144,12 +157,13 @@ __global__ __launch_bounds__(256) void k_ffty(ProjArgs a, int inverse)
 // c_k = 1/(dz_k dzc_{k+1}) (dzc: distance between centres; no flux through
 // the lids) and b_k = -a_k - c_k - 4 sin^2(pi m/nx)/dx^2 - 4 sin^2(pi l/ny)/dy^2,
 // solved by the Thomas algorithm; mode (0, 0) takes the gauge phi_0 = 0.
-__global__ __launch_bounds__(256) void k_poisson_z(ProjArgs a)
+__global__ __launch_bounds__(64) void k_poisson_z(ProjArgs a)
 {
     const Dims &d = a.d;
+    const int nh = d.nx / 2 + 1;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= d.nxy) return;
-    const int l = q / d.nx, m = q - l * d.nx, nz = d.nz, P = d.nxy;
+    if (q >= nh * d.ny) return;
+    const int l = q / nh, m = q - l * nh, nz = d.nz, P = nh * d.ny;
     const double *dz = a.dz;
     const double sx = sin(0.5 * kTwoPi * m / d.nx), sy = sin(0.5 * kTwoPi * l / d.ny);
     const double lam = -4.0 * sx * sx / (a.dx * a.dx) - 4.0 * sy * sy / (a.dy * a.dy);
@@ -197,9 +211,14 @@ __global__ __launch_bounds__(256) void k_ifftx(ProjArgs a)
 {
     extern __shared__ double2 lds[];
     const Dims &d = a.d;
-    const int nx = d.nx, base = blockIdx.x * nx;
+    const int nx = d.nx, base = blockIdx.x * nx, nh = nx / 2 + 1;
     double2 *A = lds, *B = lds + nx;
-    for (int i = threadIdx.x; i < nx; i += blockDim.x) A[i] = a.Z[base + i];
+    // the line from its half spectrum: X(nx - m) = conj(X(m))
+    for (int m = threadIdx.x; m < nh; m += blockDim.x) {
+        const double2 z = a.Z[blockIdx.x * nh + m];
+        A[m] = z;
+        if (m > 0 && m < nx - m) A[nx - m] = make_double2(z.x, -z.y);
+    }
     __syncthreads();
     const double2 *r = fft_lds(A, B, a.lgx, 1, a.twx, true);
     const double s = (double)d.nx * d.ny;
@@ -231,8 +250,9 @@ int grid_for(int64_t count)
 
 int anel_ffty_cols(int nx, int ny)
 {
+    const int nh = nx / 2 + 1;
     int c = 8;
-    while (c > 1 && (c > nx || c * ny > 2048)) c >>= 1;
+    while (c > 1 && (c > nh || c * ny > 2048)) c >>= 1;
     return c;
 }
 
@@ -290,7 +310,8 @@ hipError_t launch_project(erf_ctx *cx, void *ru, void *rv, void *rw, double dt)
     a.cols = anel_ffty_cols(d.nx, d.ny);
     const int tx = d.nx / 2 < 64 ? 64 : (d.nx / 2 > 256 ? 256 : d.nx / 2);
     const size_t ldsx = 2 * (size_t)d.nx * sizeof(double2), ldsy = 2 * (size_t)d.ny * a.cols * sizeof(double2);
-    const int rows = d.ny * d.nz, ygroups = d.nz * (d.nx / a.cols);
+    const int nh = d.nx / 2 + 1;
+    const int rows = d.ny * d.nz, ygroups = d.nz * ((nh + a.cols - 1) / a.cols);
     timing_start(cx, K_DIVFFTX);
     hipLaunchKernelGGL(k_div_fftx, dim3(rows), dim3(tx), ldsx, cx->stream, a);
     timing_stop(cx, K_DIVFFTX);
@@ -298,7 +319,9 @@ hipError_t launch_project(erf_ctx *cx, void *ru, void *rv, void *rw, double dt)
     hipLaunchKernelGGL(k_ffty, dim3(ygroups), dim3(256), ldsy, cx->stream, a, 0);
     timing_stop(cx, K_FFTY);
     timing_start(cx, K_POISSON);
-    hipLaunchKernelGGL(k_poisson_z, dim3((d.nxy + 255) / 256), dim3(256), 0, cx->stream, a);
+    // 64-lane blocks: one column per lane and a few tens of thousands of
+    // columns, spread over every compute unit
+    hipLaunchKernelGGL(k_poisson_z, dim3((nh * d.ny + 63) / 64), dim3(64), 0, cx->stream, a);
     timing_stop(cx, K_POISSON);
     timing_start(cx, K_FFTY);
     hipLaunchKernelGGL(k_ffty, dim3(ygroups), dim3(256), ldsy, cx->stream, a, 1);
