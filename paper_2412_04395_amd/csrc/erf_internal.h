@@ -333,16 +333,17 @@ struct MlpState {
     void *alloc = nullptr;
     float *master = nullptr, *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
     void *wpk = nullptr;            // 22 operands x 64 lanes x 16 bytes
+    unsigned short *tw = nullptr;   // BF16 operands of the training pass
     float *bias = nullptr;          // b1, b2, b3, b4 padded to 16: 208
     double *norm = nullptr;         // mean_x[10], std_x[10], mean_y[9], std_y[9]
     unsigned long long *fallbacks = nullptr;  // per-workgroup running counts
     double *loss = nullptr;
     bool have_weights = false;
     int64_t step = 0;
-    // training activations and partials, grown on demand
+    // training partials, grown on demand
     void *talloc = nullptr;
     int64_t cap = 0;
-    float *tbuf = nullptr, *tpart = nullptr;
+    float *tpart = nullptr;
     double *tdpart = nullptr;
 };
 
@@ -502,16 +503,19 @@ hipError_t launch_col_stats(erf_ctx *c, const double *X, int64_t n, int ncol, do
                             double *part);
 hipError_t launch_standardize(erf_ctx *c, const double *X, int64_t n, int ncol, const double *mean,
                               const double *sd, float *out);
-size_t train_floats(int64_t cap);
-size_t train_partial_floats();
-// split-K partial space with which a batch of n samples takes the same splits
-// as with train_partial_floats() (results identical to the last bit)
-size_t train_partial_floats_for(int64_t n);
-size_t train_partial_doubles(int64_t cap);
-// training buffers: tbuf train_floats(n), part pf floats (split-K partials),
-// dpart train_partial_doubles(n); every value is written before it is read
+// fused training pass: blocks for a batch of n samples (a function of n only,
+// so that every caller of the same n gets the same partial sums), its FP32
+// and FP64 partial space, and the packed BF16 weight operands (MlpState::tw)
+int train_blocks(int64_t n);
+size_t train_part_floats(int64_t n);
+size_t train_part_doubles(int64_t n);
+size_t train_weight_shorts();
+// allow the training kernel its LDS (once per device, before any capture)
+hipError_t mlp_train_prepare();
+// loss and gradient of n samples; part and dpart hold train_part_floats(n)
+// and train_part_doubles(n) values, every one written before it is read
 hipError_t launch_loss_grad(erf_ctx *c, const float *X, const float *T, int64_t n, float *G, double *loss_dev,
-                            float *tbuf, float *part, size_t pf, double *dpart);
+                            float *part, double *dpart);
 hipError_t launch_adam(erf_ctx *c, double lr, int64_t step);
 // micro.hip: Kessler microphysics over dt on S (rho, rho theta, rho q);
 // precip (may be null) accumulates the rain reaching the ground

@@ -727,192 +727,314 @@ __global__ __launch_bounds__(256) void k_standardize(const double *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// training: BF16 MFMA products, FP32 buffers, FP64 loss and Adam arithmetic
+// training: one fused pass per chunk of 64 samples (forward, loss, backward and
+// the weight-gradient products), BF16 MFMA operands with FP32 accumulation,
+// FP64 loss and bias sums; per-block partials reduced in a fixed order
 // ---------------------------------------------------------------------------
-// C(m, n) = sum_k A(m, k) B(k, n), A(m, k) = A[m sam + k sak],
-// B(k, n) = B[k sbk + n sbn]; operands rounded to BF16, FP32 accumulation.
-// blockIdx.y splits K into chunks of kchunk (multiple of 32); with one split
-// the epilogue is applied here, otherwise k_gemm_reduce applies it.
-struct GemmArgs {
-    const float *A;
-    int64_t sam, sak;
-    const float *B;
-    int64_t sbk, sbn;
-    float *C;          // one split: C[m ldc + n]; several: partials [split][M][N]
-    int64_t ldc;
-    int M, N, K, kchunk, splits;
-    const float *bias;  // epilogue: + bias[n]
-    int relu;           // epilogue: max(., 0)
-    const float *mask;  // epilogue: * (mask[m ldm + n] > 0)
-    int64_t ldm;
-    // the 8 consecutive k of a lane are contiguous and 16-byte aligned (and
-    // every K-step is whole): two 16-byte loads instead of eight 4-byte ones
-    int vecA, vecB;
+// The BF16 rounding points are those of the layer-by-layer products: every
+// matrix operand (inputs, post-ReLU activations, the output error and the
+// back-propagated errors, the weights) is rounded to BF16 from its FP32 value;
+// biases, ReLU, the masks and dY = 2 (Y - T)/(9 n) are FP32 (dY formed in FP64).
+//
+// Each wavefront takes 16 samples of the block's chunk: the layer products run
+// as C[sample][unit] = sum_k A[sample][k] B[k][unit] on the 16 x 16 x 32 BF16
+// matrix instruction, with the activations and errors in LDS twice, sample-major
+// (A operands of the next product) and unit-major (K = samples for the weight
+// gradients).  After a block barrier the four wavefronts share the 40 weight-
+// gradient tiles (10 each, accumulated in registers over all of the block's
+// chunks): dW = H_in^T D over the chunk's 64 samples.
+constexpr int kTrainChunk = 64;
+constexpr int kTrainMaxBlocks = 256;
+constexpr int kTrainDbl = 256;  // per block: b1, b2, b3 (64 each), b4 (9), loss at 208
+// training weight operands (BF16 bits), row-major with 16-byte aligned rows:
+// WT* forward (row = output unit, column = input), WN* backward (row = input
+// unit, column = output unit); padding zero
+constexpr int kTW1 = 0, kTW2 = kTW1 + 64 * 32, kTW3 = kTW2 + 64 * 64, kTW4 = kTW3 + 64 * 64;
+constexpr int kTN4 = kTW4 + 16 * 64, kTN3 = kTN4 + 64 * 32, kTN2 = kTN3 + 64 * 64, kTWords = kTN2 + 64 * 64;
+// LDS (bytes): weights, biases, per-wavefront sample-major arrays, block unit-major arrays
+constexpr int kSU_X = 0, kSU_H1 = kSU_X + 16 * 32, kSU_H2 = kSU_H1 + 16 * 64, kSU_H3 = kSU_H2 + 16 * 64;
+constexpr int kSU_DY = kSU_H3 + 16 * 64, kSU_D3 = kSU_DY + 16 * 32, kSU_D2 = kSU_D3 + 16 * 64, kSU_Words = kSU_D2 + 16 * 64;
+constexpr int kUS_X = 0, kUS_H1 = kUS_X + 16 * 64, kUS_H2 = kUS_H1 + 64 * 64, kUS_H3 = kUS_H2 + 64 * 64;
+constexpr int kUS_D1 = kUS_H3 + 64 * 64, kUS_D2 = kUS_D1 + 64 * 64, kUS_D3 = kUS_D2 + 64 * 64;
+constexpr int kUS_DY = kUS_D3 + 64 * 64, kUS_Words = kUS_DY + 16 * 64;
+constexpr int kL_W = 0, kL_B = kL_W + kTWords * 2, kL_SU = kL_B + 208 * 4, kL_US = kL_SU + 4 * kSU_Words * 2;
+constexpr int kL_Total = kL_US + kUS_Words * 2;
+static_assert(kL_SU % 16 == 0 && kL_US % 16 == 0 && kL_Total <= 160 * 1024, "training LDS layout");
+static_assert(4 * 4 * 13 * 16 * 8 + 256 * 8 <= kUS_Words * 2, "bias reduction fits the unit-major area");
+
+__device__ __forceinline__ unsigned short bf(float v) { return (unsigned short)(pack2(v, 0.f) & 0xffffu); }
+__device__ __forceinline__ bf16x8 ld8(const unsigned short *p) { return as_bf16x8(*(const u32x4 *)p); }
+
+// packed training operands from the FP32 master parameters
+__global__ __launch_bounds__(256) void k_train_pack(const float *__restrict__ P, unsigned short *__restrict__ tw)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= kTWords) return;
+    float v = 0.f;
+    if (e < kTW2) {
+        const int o = (e - kTW1) / 32, i = (e - kTW1) % 32;
+        if (i < kMlpIn) v = P[kMlpW1 + i * kMlpH + o];
+    } else if (e < kTW3) {
+        const int o = (e - kTW2) / 64, i = (e - kTW2) % 64;
+        v = P[kMlpW2 + i * kMlpH + o];
+    } else if (e < kTW4) {
+        const int o = (e - kTW3) / 64, i = (e - kTW3) % 64;
+        v = P[kMlpW3 + i * kMlpH + o];
+    } else if (e < kTN4) {
+        const int o = (e - kTW4) / 64, i = (e - kTW4) % 64;
+        if (o < kMlpOut) v = P[kMlpW4 + i * kMlpOut + o];
+    } else if (e < kTN3) {
+        const int i = (e - kTN4) / 32, o = (e - kTN4) % 32;
+        if (o < kMlpOut) v = P[kMlpW4 + i * kMlpOut + o];
+    } else if (e < kTN2) {
+        const int i = (e - kTN3) / 64, o = (e - kTN3) % 64;
+        v = P[kMlpW3 + i * kMlpH + o];
+    } else {
+        const int i = (e - kTN2) / 64, o = (e - kTN2) % 64;
+        v = P[kMlpW2 + i * kMlpH + o];
+    }
+    tw[e] = bf(v);
+}
+
+struct TrainArgs {
+    const float *X, *T;
+    int64_t n;
+    int chunks;
+    const unsigned short *tw;
+    const float *P;
+    float *part;    // [blocks][kMlpParams] weight-gradient partials (bias slots unused)
+    double *dpart;  // [blocks][kTrainDbl] bias-gradient and loss partials
+    double scale;   // 2 / (9 n)
 };
 
-__device__ __forceinline__ float epilogue(const GemmArgs &a, int m, int n, float v)
+// one product tile's result (lane: samples 4g + r, unit u) into both LDS
+// layouts, as BF16; su is the wavefront's sample-major array (row length su_len;
+// null: not stored), us the block's unit-major one (64 samples per row, the
+// wavefront's 16 at s0)
+__device__ __forceinline__ void put_tile(unsigned short *su, int su_len, unsigned short *us, int s0, int g, int u,
+                                         const float v[4])
 {
-    if (a.bias) v += a.bias[n];
-    if (a.relu) v = fmaxf(v, 0.f);
-    if (a.mask && !(a.mask[(int64_t)m * a.ldm + n] > 0.f)) v = 0.f;
-    return v;
+    if (su)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) su[(4 * g + r) * su_len + u] = bf(v[r]);
+    uint2 w;
+    w.x = pack2(v[0], v[1]);
+    w.y = pack2(v[2], v[3]);
+    *(uint2 *)(us + u * 64 + s0 + 4 * g) = w;
 }
 
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
+__global__ __launch_bounds__(256, 1) void k_mlp_train(TrainArgs a)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
-    const int tiles_n = (a.N + 15) / 16, tiles = ((a.M + 15) / 16) * tiles_n;
-    const int tile = blockIdx.x * 4 + wave;
-    if (tile >= tiles) return;
-    const int m0 = (tile / tiles_n) * 16, n0 = (tile % tiles_n) * 16;
-    const int split = blockIdx.y;
-    const int kb = split * a.kchunk, ke = kb + a.kchunk < a.K ? kb + a.kchunk : a.K;
-    const int am = m0 + col, bn = n0 + col;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = kb; k0 < ke; k0 += 32) {
-        float av[8], bv[8];
-        if (a.vecA) {
-            const float4 *p = (const float4 *)(a.A + (int64_t)(am < a.M ? am : 0) * a.sam + k0 + 8 * g);
-            const float4 u = p[0], v = p[1];
-            const bool in = am < a.M;
-            av[0] = in ? u.x : 0.f; av[1] = in ? u.y : 0.f; av[2] = in ? u.z : 0.f; av[3] = in ? u.w : 0.f;
-            av[4] = in ? v.x : 0.f; av[5] = in ? v.y : 0.f; av[6] = in ? v.z : 0.f; av[7] = in ? v.w : 0.f;
-        } else {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int k = k0 + 8 * g + i;
-                av[i] = (k < ke && am < a.M) ? a.A[(int64_t)am * a.sam + (int64_t)k * a.sak] : 0.f;
-            }
-        }
-        if (a.vecB) {
-            const float4 *p = (const float4 *)(a.B + (int64_t)(bn < a.N ? bn : 0) * a.sbn + k0 + 8 * g);
-            const float4 u = p[0], v = p[1];
-            const bool in = bn < a.N;
-            bv[0] = in ? u.x : 0.f; bv[1] = in ? u.y : 0.f; bv[2] = in ? u.z : 0.f; bv[3] = in ? u.w : 0.f;
-            bv[4] = in ? v.x : 0.f; bv[5] = in ? v.y : 0.f; bv[6] = in ? v.z : 0.f; bv[7] = in ? v.w : 0.f;
-        } else {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int k = k0 + 8 * g + i;
-                bv[i] = (k < ke && bn < a.N) ? a.B[(int64_t)k * a.sbk + (int64_t)bn * a.sbn] : 0.f;
-            }
-        }
-        u32x4 pa, pb;
-        pa.x = pack2(av[0], av[1]);
-        pa.y = pack2(av[2], av[3]);
-        pa.z = pack2(av[4], av[5]);
-        pa.w = pack2(av[6], av[7]);
-        pb.x = pack2(bv[0], bv[1]);
-        pb.y = pack2(bv[2], bv[3]);
-        pb.z = pack2(bv[4], bv[5]);
-        pb.w = pack2(bv[6], bv[7]);
-        acc = mfma(as_bf16x8(pa), as_bf16x8(pb), acc);
+    extern __shared__ __align__(16) unsigned char sm[];
+    unsigned short *W = (unsigned short *)(sm + kL_W);
+    float *bias = (float *)(sm + kL_B);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, col = lane & 15;
+    unsigned short *SU = (unsigned short *)(sm + kL_SU) + wave * kSU_Words;
+    unsigned short *US = (unsigned short *)(sm + kL_US);
+    const int s0 = wave * 16;  // the wavefront's samples within the chunk
+    for (int e = tid; e < kTWords / 8; e += 256) ((u32x4 *)W)[e] = ((const u32x4 *)a.tw)[e];
+    for (int e = tid; e < 208; e += 256) {
+        float b = 0.f;
+        if (e < 64) b = a.P[kMlpB1 + e];
+        else if (e < 128) b = a.P[kMlpB2 + e - 64];
+        else if (e < 192) b = a.P[kMlpB3 + e - 128];
+        else if (e - 192 < kMlpOut) b = a.P[kMlpB4 + e - 192];
+        bias[e] = b;
     }
-    // acc[r]: row m0 + 4g + r, column n0 + col
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int m = m0 + 4 * g + r, n = n0 + col;
-        if (m >= a.M || n >= a.N) continue;
-        if (a.splits == 1)
-            a.C[(int64_t)m * a.ldc + n] = epilogue(a, m, n, acc[r]);
-        else
-            a.C[((int64_t)split * a.M + m) * a.N + n] = acc[r];
-    }
-}
-
-// sum of the split-K partials: a block of 256 covers 64 outputs (lane =
-// output), each wavefront every fourth split, combined in LDS in a fixed
-// order; FP64 sums
-__global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs a, const float *__restrict__ part, float *__restrict__ C)
-{
-    __shared__ double red[4][64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t mn = (int64_t)a.M * a.N;
-    const int e = blockIdx.x * 64 + lane;
-    double acc = 0.0;
-    if (e < mn)
-        for (int p = w; p < a.splits; p += 4) acc += (double)part[(int64_t)p * mn + e];
-    red[w][lane] = acc;
+    // the activation arrays start at zero: their padding (inputs 10..31,
+    // outputs 9..31) is never written
+    for (int e = tid; e < (4 * kSU_Words + kUS_Words) / 8; e += 256) ((u32x4 *)(sm + kL_SU))[e] = u32x4{0u, 0u, 0u, 0u};
     __syncthreads();
-    if (w == 0 && e < mn) {
-        const int m = e / a.N, n = e - m * a.N;
-        C[(int64_t)m * a.ldc + n] = epilogue(a, m, n, (float)((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])));
-    }
-}
 
-// loss partials and dY = 2 (Y - T) / (n 9)
-__global__ __launch_bounds__(256) void k_loss_dy(const float *__restrict__ Y, const float *__restrict__ T, int64_t n,
-                                                 float *__restrict__ dY, double *__restrict__ part)
-{
-    __shared__ double red[256];
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const floatx4 z4 = {0.f, 0.f, 0.f, 0.f};
+    floatx4 acc[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) acc[j] = z4;
+    double db[13];
+#pragma unroll
+    for (int j = 0; j < 13; ++j) db[j] = 0.0;
     double sq = 0.0;
-    if (e < n * 9) {
-        const double err = (double)Y[e] - (double)T[e];
-        sq = err * err;
-        dY[e] = (float)(2.0 / ((double)n * 9.0) * err);
-    }
-    red[threadIdx.x] = sq;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
 
-// one block of 256: strided partial sums, then a tree in LDS (fixed order)
-__global__ __launch_bounds__(256) void k_loss_finish(const double *__restrict__ part, int nblk, int64_t n,
-                                                     double *__restrict__ loss)
-{
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) s += part[b];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *loss = red[0] / ((double)n * 9.0);
-}
-
-// bias gradients: column sums of D[n][ncol] (FP64, fixed order).  A block of
-// 256 covers kStatRows rows: lane = column, each wavefront every fourth row
-// with four independent accumulators (loads in flight instead of one
-// dependent add per load), the wavefronts combined in LDS.
-__global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ D, int64_t n, int ncol,
-                                                     double *__restrict__ part)
-{
-    __shared__ double red[4][64];
-    const int col = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t r0 = (int64_t)blockIdx.x * kStatRows, r1 = r0 + kStatRows < n ? r0 + kStatRows : n;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (col < ncol) {
-        int64_t r = r0 + w;
-        for (; r + 12 < r1; r += 16) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] += (double)D[(r + 4 * u) * ncol + col];
+    for (int ch = blockIdx.x; ch < a.chunks; ch += gridDim.x) {
+        const int64_t sb = (int64_t)ch * kTrainChunk + s0;
+        // inputs of the wavefront's 16 samples (zero past n)
+        for (int e = lane; e < 16 * kMlpIn; e += 64) {
+            const int sl = e / kMlpIn, k = e - sl * kMlpIn;
+            const int64_t s = sb + sl;
+            const unsigned short b = bf(s < a.n ? a.X[s * kMlpIn + k] : 0.f);
+            SU[kSU_X + sl * 32 + k] = b;
+            US[kUS_X + k * 64 + s0 + sl] = b;
         }
-        for (int u = 0; r < r1; r += 4, ++u) acc[u & 3] += (double)D[r * ncol + col];
+        wave_sync();
+        unsigned mask[3] = {0u, 0u, 0u};
+        // hidden layers: H = ReLU(A W + b)
+        auto hidden = [&](int L, const unsigned short *Ain, int alen, int ksteps, int wofs, unsigned short *su_out,
+                          unsigned short *us_out) {
+            bf16x8 A[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                if (s < ksteps) A[s] = ld8(Ain + col * alen + 32 * s + 8 * g);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int u = 16 * nt + col;
+                floatx4 c = z4;
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+                    if (s < ksteps) c = mfma(A[s], ld8(W + wofs + u * (32 * ksteps) + 32 * s + 8 * g), c);
+                float v[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    v[r] = fmaxf(c[r] + bias[64 * L + u], 0.f);
+                    if (v[r] > 0.f) mask[L] |= 1u << (4 * nt + r);
+                }
+                put_tile(su_out, 64, us_out, s0, g, u, v);
+            }
+            wave_sync();
+        };
+        hidden(0, SU + kSU_X, 32, 1, kTW1, SU + kSU_H1, US + kUS_H1);
+        hidden(1, SU + kSU_H1, 64, 2, kTW2, SU + kSU_H2, US + kUS_H2);
+        hidden(2, SU + kSU_H2, 64, 2, kTW3, SU + kSU_H3, US + kUS_H3);
+        // output layer, loss and dY = 2 (Y - T)/(9 n)
+        {
+            floatx4 c = z4;
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                c = mfma(ld8(SU + kSU_H3 + col * 64 + 32 * s + 8 * g), ld8(W + kTW4 + col * 64 + 32 * s + 8 * g), c);
+            float v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t s = sb + 4 * g + r;
+                v[r] = 0.f;
+                if (col < kMlpOut && s < a.n) {
+                    const float y = c[r] + bias[192 + col];
+                    const double err = (double)y - (double)a.T[s * kMlpOut + col];
+                    sq += err * err;
+                    v[r] = (float)(a.scale * err);
+                    db[0] += (double)v[r];
+                }
+            }
+            // sample-major rows of 32 outputs (16..31 stay zero)
+            put_tile(SU + kSU_DY, 32, US + kUS_DY, s0, g, col, v);
+            wave_sync();
+        }
+        // errors back through the layers: D = (D_next W_next^T) * [H > 0]
+        auto back = [&](int L, const unsigned short *Din, int dlen, int ksteps, int wofs, int slot,
+                        unsigned short *su_out, unsigned short *us_out) {
+            bf16x8 A[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                if (s < ksteps) A[s] = ld8(Din + col * dlen + 32 * s + 8 * g);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int u = 16 * nt + col;
+                floatx4 c = z4;
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+                    if (s < ksteps) c = mfma(A[s], ld8(W + wofs + u * (32 * ksteps) + 32 * s + 8 * g), c);
+                float v[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    v[r] = (mask[L] >> (4 * nt + r)) & 1u ? c[r] : 0.f;
+                    db[slot + nt] += (double)v[r];
+                }
+                put_tile(su_out, 64, us_out, s0, g, u, v);  // (no sample-major copy of D1: nothing reads it)
+            }
+            wave_sync();
+        };
+        back(2, SU + kSU_DY, 32, 1, kTN4, 1, SU + kSU_D3, US + kUS_D3);
+        back(1, SU + kSU_D3, 64, 2, kTN3, 5, SU + kSU_D2, US + kUS_D2);
+        back(0, SU + kSU_D2, 64, 2, kTN2, 9, nullptr, US + kUS_D1);
+        __syncthreads();
+        // weight gradients over the chunk's 64 samples: tile q = wave + 4 j of
+        // dW4 (4 tiles), dW3 (16), dW2 (16), dW1 (4)
+#pragma unroll
+        for (int j = 0; j < 10; ++j) {
+            const int q = wave + 4 * j;
+            int mt, nt, ain, bin;
+            if (q < 4) { mt = q; nt = 0; ain = kUS_H3; bin = kUS_DY; }
+            else if (q < 20) { mt = (q - 4) >> 2; nt = (q - 4) & 3; ain = kUS_H2; bin = kUS_D3; }
+            else if (q < 36) { mt = (q - 20) >> 2; nt = (q - 20) & 3; ain = kUS_H1; bin = kUS_D2; }
+            else { mt = 0; nt = q - 36; ain = kUS_X; bin = kUS_D1; }
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+                acc[j] = mfma(ld8(US + ain + (16 * mt + col) * 64 + 32 * ks + 8 * g),
+                              ld8(US + bin + (16 * nt + col) * 64 + 32 * ks + 8 * g), acc[j]);
+        }
+        __syncthreads();
     }
-    red[w][col] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+
+    // weight-gradient partials (lane: input unit 16 mt + 4 g + r, output 16 nt + col)
+    float *part = a.part + (size_t)blockIdx.x * kMlpParams;
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+        const int q = wave + 4 * j;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int idx = -1;
+            if (q < 4) {
+                const int in = 16 * q + 4 * g + r;
+                if (col < kMlpOut) idx = kMlpW4 + in * kMlpOut + col;
+            } else if (q < 20) {
+                const int in = 16 * ((q - 4) >> 2) + 4 * g + r, out = 16 * ((q - 4) & 3) + col;
+                idx = kMlpW3 + in * kMlpH + out;
+            } else if (q < 36) {
+                const int in = 16 * ((q - 20) >> 2) + 4 * g + r, out = 16 * ((q - 20) & 3) + col;
+                idx = kMlpW2 + in * kMlpH + out;
+            } else {
+                const int in = 4 * g + r, out = 16 * (q - 36) + col;
+                if (in < kMlpIn) idx = kMlpW1 + in * kMlpH + out;
+            }
+            if (idx >= 0) part[idx] = acc[j][r];
+        }
+    }
+    // bias and loss partials: the 16 lane groups of the block combined in LDS
+    // in a fixed order (the unit-major area is free after the last barrier)
+    double *red = (double *)(sm + kL_US);
+#pragma unroll
+    for (int j = 0; j < 13; ++j) red[((wave * 4 + g) * 13 + j) * 16 + col] = db[j];
+    double *lred = red + 4 * 4 * 13 * 16;
+    lred[tid] = sq;
     __syncthreads();
-    if (w == 0 && col < ncol)
-        part[(int64_t)blockIdx.x * ncol + col] = (red[0][col] + red[1][col]) + (red[2][col] + red[3][col]);
+    if (tid < 208) {
+        int slot, c;
+        if (tid < 64) { slot = 9 + tid / 16; c = tid % 16; }
+        else if (tid < 128) { slot = 5 + (tid - 64) / 16; c = (tid - 64) % 16; }
+        else if (tid < 192) { slot = 1 + (tid - 128) / 16; c = (tid - 128) % 16; }
+        else { slot = 0; c = tid - 192; }
+        double s = 0.0;
+        for (int wg = 0; wg < 16; ++wg) s += red[(wg * 13 + slot) * 16 + c];
+        a.dpart[(size_t)blockIdx.x * kTrainDbl + tid] = s;
+    }
+    if (tid == 255) {
+        double s = 0.0;
+        for (int l = 0; l < 256; ++l) s += lred[l];
+        a.dpart[(size_t)blockIdx.x * kTrainDbl + 208] = s;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_colsum_finish(const double *__restrict__ part, int nblk, int ncol,
-                                                       float *__restrict__ out)
+// G[p] and the loss from the block partials, FP64 sums in block order
+__global__ __launch_bounds__(256) void k_train_reduce(const float *__restrict__ part, const double *__restrict__ dpart,
+                                                      int nblk, int64_t n, float *__restrict__ G, double *__restrict__ loss)
 {
-    __shared__ double red[4][64];
-    const int col = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double acc = 0.0;
-    if (col < ncol)
-        for (int b = w; b < nblk; b += 4) acc += part[(int64_t)b * ncol + col];
-    red[w][col] = acc;
-    __syncthreads();
-    if (w == 0 && col < ncol) out[col] = (float)((red[0][col] + red[1][col]) + (red[2][col] + red[3][col]));
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p < kMlpParams) {
+        int bi = -1;
+        if (p >= kMlpB1 && p < kMlpB1 + kMlpH) bi = p - kMlpB1;
+        else if (p >= kMlpB2 && p < kMlpB2 + kMlpH) bi = 64 + p - kMlpB2;
+        else if (p >= kMlpB3 && p < kMlpB3 + kMlpH) bi = 128 + p - kMlpB3;
+        else if (p >= kMlpB4) bi = 192 + p - kMlpB4;
+        double s = 0.0;
+        if (bi >= 0)
+            for (int b = 0; b < nblk; ++b) s += dpart[(size_t)b * kTrainDbl + bi];
+        else
+            for (int b = 0; b < nblk; ++b) s += (double)part[(size_t)b * kMlpParams + p];
+        G[p] = (float)s;
+    }
+    if (p == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += dpart[(size_t)b * kTrainDbl + 208];
+        *loss = s / ((double)n * 9.0);
+    }
 }
 
 // Adam (Kingma & Ba) with bias correction; FP32 storage, FP64 arithmetic
@@ -1102,137 +1224,40 @@ hipError_t launch_standardize(erf_ctx *cx, const double *X, int64_t n, int ncol,
     return hipGetLastError();
 }
 
-namespace {
-// one product with its epilogue; K split over blocks when long
-constexpr int kMaxSplits = 1024;  // split-K partials: at most this many of 64 x 64
+int train_blocks(int64_t n)
+{
+    const int64_t chunks = (n + kTrainChunk - 1) / kTrainChunk;
+    return (int)(chunks < kTrainMaxBlocks ? (chunks > 0 ? chunks : 1) : kTrainMaxBlocks);
+}
+size_t train_part_floats(int64_t n) { return (size_t)train_blocks(n) * kMlpParams; }
+size_t train_part_doubles(int64_t n) { return (size_t)train_blocks(n) * kTrainDbl; }
+size_t train_weight_shorts() { return kTWords; }
 
-hipError_t gemm(erf_ctx *cx, GemmArgs a, float *C, float *part, size_t part_floats)
+hipError_t mlp_train_prepare()
 {
-    // long reductions (the weight gradients, K = samples) are split into
-    // chunks of 256 so that every tile has hundreds of wavefronts behind it
-    int splits = 1;
-    if (a.K > 4096) {
-        splits = (a.K + 255) / 256;
-        const size_t per = (size_t)a.M * a.N;
-        const int cap = (int)(part_floats / (per ? per : 1));
-        if (splits > cap) splits = cap;
-        if (splits > kMaxSplits) splits = kMaxSplits;
-        if (splits < 1) splits = 1;
-    }
-    int kchunk = (a.K + splits - 1) / splits;
-    kchunk = (kchunk + 31) / 32 * 32;
-    splits = (a.K + kchunk - 1) / kchunk;
-    if (splits < 1) splits = 1;
-    a.kchunk = kchunk > 0 ? kchunk : 32;
-    a.splits = splits;
-    // whole K-steps only (no partial chunk), rows 16-byte aligned
-    const bool whole = a.K % 32 == 0 && a.kchunk % 32 == 0;
-    a.vecA = whole && a.sak == 1 && a.sam % 4 == 0 && ((uintptr_t)a.A & 15) == 0;
-    a.vecB = whole && a.sbk == 1 && a.sbn % 4 == 0 && ((uintptr_t)a.B & 15) == 0;
-    const int tiles = ((a.M + 15) / 16) * ((a.N + 15) / 16);
-    a.C = splits == 1 ? C : part;
-    hipLaunchKernelGGL(k_gemm, dim3((tiles + 3) / 4, splits), dim3(256), 0, cx->stream, a);
-    if (splits > 1)
-        hipLaunchKernelGGL(k_gemm_reduce, dim3((a.M * a.N + 63) / 64), dim3(256), 0, cx->stream, a,
-                           (const float *)part, C);
-    return hipGetLastError();
+    return hipFuncSetAttribute((const void *)k_mlp_train, hipFuncAttributeMaxDynamicSharedMemorySize, kL_Total);
 }
-
-GemmArgs gargs(const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbk, int64_t sbn, int M, int N,
-               int K, int64_t ldc)
-{
-    GemmArgs a{};
-    a.A = A;
-    a.sam = sam;
-    a.sak = sak;
-    a.B = B;
-    a.sbk = sbk;
-    a.sbn = sbn;
-    a.M = M;
-    a.N = N;
-    a.K = K;
-    a.ldc = ldc;
-    return a;
-}
-}  // namespace
-
-size_t train_floats(int64_t cap)
-{
-    // H1, H2, H3, D (two), each cap x 64; Y, dY cap x 9
-    return (size_t)cap * (5 * 64 + 2 * 9);
-}
-size_t train_partial_floats() { return (size_t)kMaxSplits * 64 * 64; }
-size_t train_partial_floats_for(int64_t n)
-{
-    // the split-K partials of the longest reduction (K = n samples): one 64 x 64
-    // tile per chunk of 256, the count gemm() takes when space allows
-    return (size_t)((n + 255) / 256) * 64 * 64;
-}
-size_t train_partial_doubles(int64_t cap) { return (size_t)((cap + kStatRows - 1) / kStatRows + 1) * 64 + (size_t)((cap * 9 + 255) / 256 + 1); }
 
 hipError_t launch_loss_grad(erf_ctx *cx, const float *X, const float *Tt, int64_t n, float *G, double *loss_dev,
-                            float *tbuf, float *part, size_t pf, double *dpart)
+                            float *part, double *dpart)
 {
     MlpState &m = cx->mlp;
-    const float *P = m.master;
-    float *H1 = tbuf, *H2 = H1 + n * 64, *H3 = H2 + n * 64, *Da = H3 + n * 64, *Db = Da + n * 64;
-    float *Y = Db + n * 64, *dY = Y + n * 9;
-    const int N = (int)n;
-    hipError_t e;
-    // forward
-    GemmArgs a = gargs(X, 10, 1, P + kMlpW1, 64, 1, N, 64, 10, 64);
-    a.bias = P + kMlpB1;
-    a.relu = 1;
-    if ((e = gemm(cx, a, H1, part, pf)) != hipSuccess) return e;
-    a = gargs(H1, 64, 1, P + kMlpW2, 64, 1, N, 64, 64, 64);
-    a.bias = P + kMlpB2;
-    a.relu = 1;
-    if ((e = gemm(cx, a, H2, part, pf)) != hipSuccess) return e;
-    a = gargs(H2, 64, 1, P + kMlpW3, 64, 1, N, 64, 64, 64);
-    a.bias = P + kMlpB3;
-    a.relu = 1;
-    if ((e = gemm(cx, a, H3, part, pf)) != hipSuccess) return e;
-    a = gargs(H3, 64, 1, P + kMlpW4, 9, 1, N, 9, 64, 9);
-    a.bias = P + kMlpB4;
-    if ((e = gemm(cx, a, Y, part, pf)) != hipSuccess) return e;
-    // loss and dY
-    const int lblk = (int)((n * 9 + 255) / 256);
-    double *lpart = dpart + ((n + kStatRows - 1) / kStatRows + 1) * 64;
-    hipLaunchKernelGGL(k_loss_dy, dim3(lblk), dim3(256), 0, cx->stream, (const float *)Y, Tt, n, dY, lpart);
-    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, cx->stream, (const double *)lpart, lblk, n, loss_dev);
-    const int cblk = (int)((n + kStatRows - 1) / kStatRows);
-    auto colsum = [&](const float *D, int ncol, float *out) {
-        hipLaunchKernelGGL(k_colsum_part, dim3(cblk), dim3(256), 0, cx->stream, D, n, ncol, dpart);
-        hipLaunchKernelGGL(k_colsum_finish, dim3(1), dim3(256), 0, cx->stream, (const double *)dpart, cblk, ncol, out);
-    };
-    // layer 4
-    a = gargs(H3, 1, 64, dY, 9, 1, 64, 9, N, 9);
-    if ((e = gemm(cx, a, G + kMlpW4, part, pf)) != hipSuccess) return e;
-    colsum(dY, 9, G + kMlpB4);
-    a = gargs(dY, 9, 1, P + kMlpW4, 1, 9, N, 64, 9, 64);
-    a.mask = H3;
-    a.ldm = 64;
-    if ((e = gemm(cx, a, Da, part, pf)) != hipSuccess) return e;
-    // layer 3
-    a = gargs(H2, 1, 64, Da, 64, 1, 64, 64, N, 64);
-    if ((e = gemm(cx, a, G + kMlpW3, part, pf)) != hipSuccess) return e;
-    colsum(Da, 64, G + kMlpB3);
-    a = gargs(Da, 64, 1, P + kMlpW3, 1, 64, N, 64, 64, 64);
-    a.mask = H2;
-    a.ldm = 64;
-    if ((e = gemm(cx, a, Db, part, pf)) != hipSuccess) return e;
-    // layer 2
-    a = gargs(H1, 1, 64, Db, 64, 1, 64, 64, N, 64);
-    if ((e = gemm(cx, a, G + kMlpW2, part, pf)) != hipSuccess) return e;
-    colsum(Db, 64, G + kMlpB2);
-    a = gargs(Db, 64, 1, P + kMlpW2, 1, 64, N, 64, 64, 64);
-    a.mask = H1;
-    a.ldm = 64;
-    if ((e = gemm(cx, a, Da, part, pf)) != hipSuccess) return e;
-    // layer 1
-    a = gargs(X, 1, 10, Da, 64, 1, 10, 64, N, 64);
-    if ((e = gemm(cx, a, G + kMlpW1, part, pf)) != hipSuccess) return e;
-    colsum(Da, 64, G + kMlpB1);
+    hipLaunchKernelGGL(k_train_pack, dim3((kTWords + 255) / 256), dim3(256), 0, cx->stream, (const float *)m.master,
+                       m.tw);
+    TrainArgs a{};
+    a.X = X;
+    a.T = Tt;
+    a.n = n;
+    a.chunks = (int)((n + kTrainChunk - 1) / kTrainChunk);
+    a.tw = m.tw;
+    a.P = m.master;
+    a.part = part;
+    a.dpart = dpart;
+    a.scale = 2.0 / ((double)n * 9.0);
+    const int nblk = train_blocks(n);
+    hipLaunchKernelGGL(k_mlp_train, dim3(nblk), dim3(256), kL_Total, cx->stream, a);
+    hipLaunchKernelGGL(k_train_reduce, dim3((kMlpParams + 255) / 256), dim3(256), 0, cx->stream,
+                       (const float *)part, (const double *)dpart, nblk, n, G, loss_dev);
     return hipGetLastError();
 }
 

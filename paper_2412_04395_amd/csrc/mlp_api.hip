@@ -43,7 +43,8 @@ erf_status ensure_state(erf_ctx *c)
     if (m.alloc) return ERF_OK;
     const size_t P = kMlpParams * sizeof(float);
     const size_t sizes[] = {P, P, P, P, 22 * 64 * 16, 208 * sizeof(float), kMlpNorm * sizeof(double),
-                            closure_count_slots() * sizeof(unsigned long long), sizeof(double)};
+                            closure_count_slots() * sizeof(unsigned long long), sizeof(double),
+                            train_weight_shorts() * sizeof(unsigned short)};
     size_t total = 0;
     for (size_t s : sizes) total += al(s);
     hipError_t e = hipMalloc(&m.alloc, total);
@@ -54,13 +55,15 @@ erf_status ensure_state(erf_ctx *c)
     }
     char *p = (char *)m.alloc;
     void **dst[] = {(void **)&m.master, (void **)&m.adam_m, (void **)&m.adam_v, (void **)&m.grad, &m.wpk,
-                    (void **)&m.bias, (void **)&m.norm, (void **)&m.fallbacks, (void **)&m.loss};
-    for (int i = 0; i < 9; ++i) {
+                    (void **)&m.bias, (void **)&m.norm, (void **)&m.fallbacks, (void **)&m.loss, (void **)&m.tw};
+    for (int i = 0; i < 10; ++i) {
         *dst[i] = p;
         p += al(sizes[i]);
     }
     e = hipMemsetAsync(m.alloc, 0, total, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "clearing the closure state");
+    e = mlp_train_prepare();
+    if (e != hipSuccess) return hip_fail(c, e, "training kernel attributes");
     double nrm[kMlpNorm];
     for (int i = 0; i < kMlpNorm; ++i) nrm[i] = (i >= kMlpIn && i < 2 * kMlpIn) || i >= 2 * kMlpIn + kMlpOut ? 1.0 : 0.0;
     e = hipMemcpyAsync(m.norm, nrm, sizeof nrm, hipMemcpyHostToDevice, c->stream);
@@ -79,17 +82,15 @@ erf_status ensure_train(erf_ctx *c, int64_t n)
         m.talloc = nullptr;
         m.cap = 0;
     }
-    const size_t a = al(train_floats(n) * sizeof(float)), b = al(train_partial_floats() * sizeof(float));
-    const size_t d = al(train_partial_doubles(n) * sizeof(double));
-    hipError_t e = hipMalloc(&m.talloc, a + b + d);
+    const size_t b = al(train_part_floats(n) * sizeof(float)), d = al(train_part_doubles(n) * sizeof(double));
+    hipError_t e = hipMalloc(&m.talloc, b + d);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         m.talloc = nullptr;
         return fail(c, ERF_E_NOMEM, "training buffers allocation failed");
     }
-    m.tbuf = (float *)m.talloc;
-    m.tpart = (float *)((char *)m.talloc + a);
-    m.tdpart = (double *)((char *)m.talloc + a + b);
+    m.tpart = (float *)m.talloc;
+    m.tdpart = (double *)((char *)m.talloc + b);
     m.cap = n;
     return ERF_OK;
 }
@@ -99,17 +100,16 @@ bool state5(const erf_state *S) { return S && S->rho && S->rhotheta && S->rhou &
 // ---------------------------------------------------------------------------
 // fixed training scratch of erf_mlp_loss_grad_noalloc
 // ---------------------------------------------------------------------------
-// Activations (train_floats), split-K partials (train_partial_floats_for) and
-// FP64 partial sums (train_partial_doubles) of a batch of at most
-// ERF_MLP_NOALLOC_MAX_BATCH samples, each region 256-byte aligned.  Bounds
-// evaluated here for the maximum batch (checked against the library's sizing
-// functions at the first call): 338 floats per sample; one 64 x 64 tile per
-// 256 samples; (n / 1024 + 2) x 64 + n x 9 / 256 + 2 doubles.
+// Partial sums of the fused training pass (FP32 weight gradients and FP64 bias
+// and loss sums per block) for a batch of at most ERF_MLP_NOALLOC_MAX_BATCH
+// samples, each region 256-byte aligned: one block per 64 samples up to 256
+// blocks (8192 samples: 128 blocks), 9609 floats and 256 doubles each
+// (checked against the library's sizing functions at the first call).
 constexpr int64_t kNaMax = ERF_MLP_NOALLOC_MAX_BATCH;
-constexpr size_t kNaAct = (size_t)kNaMax * 338 * sizeof(float);
-constexpr size_t kNaPart = (size_t)((kNaMax + 255) / 256) * 64 * 64 * sizeof(float);
-constexpr size_t kNaDbl = ((size_t)(kNaMax / 1024 + 2) * 64 + (size_t)(kNaMax * 9 / 256 + 2)) * sizeof(double);
-constexpr size_t kNaBytes = al_c(kNaAct) + al_c(kNaPart) + al_c(kNaDbl);
+constexpr int64_t kNaBlocks = (kNaMax + 63) / 64 < 256 ? (kNaMax + 63) / 64 : 256;
+constexpr size_t kNaPart = (size_t)kNaBlocks * 9609 * sizeof(float);
+constexpr size_t kNaDbl = (size_t)kNaBlocks * 256 * sizeof(double);
+constexpr size_t kNaBytes = al_c(kNaPart) + al_c(kNaDbl);
 }  // namespace
 
 // One copy per GPU, held from the library's load until the process ends.  In
@@ -131,8 +131,7 @@ erf_status na_scratch(erf_ctx *c, char **out)
     if (dev < 0 || dev >= kNaMaxDevices) return fail(c, ERF_E_UNSUPPORTED, "device index beyond the scratch table");
     std::lock_guard<std::mutex> lock(na_mutex);
     if (!na_ptr[dev]) {
-        if (train_floats(kNaMax) * sizeof(float) > kNaAct || train_partial_floats_for(kNaMax) * sizeof(float) > kNaPart ||
-            train_partial_doubles(kNaMax) * sizeof(double) > kNaDbl)
+        if (train_part_floats(kNaMax) * sizeof(float) > kNaPart || train_part_doubles(kNaMax) * sizeof(double) > kNaDbl)
             return fail(c, ERF_E_UNSUPPORTED, "training scratch smaller than the maximum batch needs");
         int cur = -1;
         hipError_t e = hipGetDevice(&cur);
@@ -275,7 +274,7 @@ erf_status erf_mlp_loss_grad(erf_ctx *c, const float *x, const float *t, int64_t
     erf_status s = ensure_train(c, n);
     if (s != ERF_OK) return s;
     MlpState &m = c->mlp;
-    hipError_t e = launch_loss_grad(c, x, t, n, grad, m.loss, m.tbuf, m.tpart, train_partial_floats(), m.tdpart);
+    hipError_t e = launch_loss_grad(c, x, t, n, grad, m.loss, m.tpart, m.tdpart);
     if (e == hipSuccess && loss) e = hipMemcpyAsync(loss, c->mlp.loss, sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess && loss) e = hipStreamSynchronize(c->stream);
     return e == hipSuccess ? ERF_OK : hip_fail(c, e, "closure gradient");
@@ -291,14 +290,12 @@ erf_status erf_mlp_loss_grad_noalloc(erf_ctx *c, const float *x, const float *t,
     char *p = nullptr;
     erf_status s = na_scratch(c, &p);
     if (s != ERF_OK) return s;
-    // the same kernels as erf_mlp_loss_grad on slices of the fixed scratch;
-    // nothing in it has to start at zero (every partial is written before it
-    // is read)
-    float *tbuf = (float *)p;
-    float *part = (float *)(p + al_c(kNaAct));
-    double *dpart = (double *)(p + al_c(kNaAct) + al_c(kNaPart));
-    hipError_t e = launch_loss_grad(c, x, t, n, grad, loss_dev ? loss_dev : c->mlp.loss, tbuf, part,
-                                    train_partial_floats_for(n), dpart);
+    // the same kernels as erf_mlp_loss_grad (the same blocks for the same n)
+    // on slices of the fixed scratch; nothing in it has to start at zero
+    // (every partial is written before it is read)
+    float *part = (float *)p;
+    double *dpart = (double *)(p + al_c(kNaPart));
+    hipError_t e = launch_loss_grad(c, x, t, n, grad, loss_dev ? loss_dev : c->mlp.loss, part, dpart);
     return e == hipSuccess ? ERF_OK : hip_fail(c, e, "closure gradient (fixed scratch)");
 }
 
