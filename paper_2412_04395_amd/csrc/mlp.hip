@@ -1012,28 +1012,46 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train(TrainArgs a)
     }
 }
 
-// G[p] and the loss from the block partials, FP64 sums in block order
+// G[p] and the loss from the block partials, FP64 sums in a fixed order: a
+// workgroup of 256 covers 64 parameters (lane = parameter); wavefront w sums
+// the blocks b = w mod 4 in eight interleaved chains (eight loads in flight),
+// the chains and the wavefronts combined in fixed order
 __global__ __launch_bounds__(256) void k_train_reduce(const float *__restrict__ part, const double *__restrict__ dpart,
                                                       int nblk, int64_t n, float *__restrict__ G, double *__restrict__ loss)
 {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p < kMlpParams) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + lane;
+    double s = 0.0;
+    if (p < kMlpParams + 1) {
+        // p == kMlpParams: the loss
         int bi = -1;
-        if (p >= kMlpB1 && p < kMlpB1 + kMlpH) bi = p - kMlpB1;
+        if (p == kMlpParams) bi = 208;
+        else if (p >= kMlpB1 && p < kMlpB1 + kMlpH) bi = p - kMlpB1;
         else if (p >= kMlpB2 && p < kMlpB2 + kMlpH) bi = 64 + p - kMlpB2;
         else if (p >= kMlpB3 && p < kMlpB3 + kMlpH) bi = 128 + p - kMlpB3;
         else if (p >= kMlpB4) bi = 192 + p - kMlpB4;
-        double s = 0.0;
-        if (bi >= 0)
-            for (int b = 0; b < nblk; ++b) s += dpart[(size_t)b * kTrainDbl + bi];
-        else
-            for (int b = 0; b < nblk; ++b) s += (double)part[(size_t)b * kMlpParams + p];
-        G[p] = (float)s;
+        double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int b = w;
+        for (; b + 28 < nblk; b += 32) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int bb = b + 4 * u;
+                c[u] += bi >= 0 ? dpart[(size_t)bb * kTrainDbl + bi] : (double)part[(size_t)bb * kMlpParams + p];
+            }
+        }
+        for (int u = 0; b < nblk; b += 4, ++u)
+            c[u & 7] += bi >= 0 ? dpart[(size_t)b * kTrainDbl + bi] : (double)part[(size_t)b * kMlpParams + p];
+        s = ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
     }
-    if (p == 0) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += dpart[(size_t)b * kTrainDbl + 208];
-        *loss = s / ((double)n * 9.0);
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && p < kMlpParams + 1) {
+        const double v = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+        if (p < kMlpParams)
+            G[p] = (float)v;
+        else
+            *loss = v / ((double)n * 9.0);
     }
 }
 
@@ -1256,7 +1274,7 @@ hipError_t launch_loss_grad(erf_ctx *cx, const float *X, const float *Tt, int64_
     a.scale = 2.0 / ((double)n * 9.0);
     const int nblk = train_blocks(n);
     hipLaunchKernelGGL(k_mlp_train, dim3(nblk), dim3(256), kL_Total, cx->stream, a);
-    hipLaunchKernelGGL(k_train_reduce, dim3((kMlpParams + 255) / 256), dim3(256), 0, cx->stream,
+    hipLaunchKernelGGL(k_train_reduce, dim3((kMlpParams + 1 + 63) / 64), dim3(256), 0, cx->stream,
                        (const float *)part, (const double *)dpart, nblk, n, G, loss_dev);
     return hipGetLastError();
 }
