@@ -66,6 +66,12 @@ __device__ __forceinline__ int cidx(const Dims &d, int i, int j, int k) { return
 
 // equation sets of the tendency kernel
 constexpr int kDryEq = 0, kMoistEq = 1, kAnelEq = 2;
+// wavefronts per SIMD the tendency kernel is compiled for: 3 in FP64 (its
+// registers hold all of a section's gathers), 4 in FP32 (measured at
+// 256 x 256 x 128: 284 against 316 us per launch at 3; FP64 is the same at 3
+// and 4, slower at 2)
+template <typename T>
+constexpr int kRhsWaves = sizeof(T) == 4 ? 4 : 3;
 
 // ---------------------------------------------------------------------------
 // primitives
@@ -678,12 +684,12 @@ __device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
     if (k == 0) a.Rw[c + nz * P] = 0.0;
 }
 template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_rhs(RhsArgs<T> a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kRhsWaves<T>, kRhsWaves<T>))) void k_rhs(RhsArgs<T> a)
 {
     k_rhs_body<T, OH, OV, kNear, kVisc, kEq>(a, hw_block());
 }
 template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_rhs_batch(const RhsArgs<T> *args, BatchMap bm)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kRhsWaves<T>, kRhsWaves<T>))) void k_rhs_batch(const RhsArgs<T> *args, BatchMap bm)
 {
     int m;
     VBlock vb;
