@@ -296,6 +296,7 @@ erf_status erf_ensemble_create(int32_t n, const erf_grid *grids, const erf_param
             erf_ensemble_destroy(e);
             return s;
         }
+        c->member = true;
         e->members.push_back(c);
     }
     e->n_branches = std::min(n, 4);

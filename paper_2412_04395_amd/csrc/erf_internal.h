@@ -404,6 +404,9 @@ struct erf_ctx {
     // while set, launches are recorded here instead of enqueued (the batched
     // ensemble step records each member's step once, then replays batches)
     erfk::Recorder *rec = nullptr;
+    // a member of an ensemble: its slow right-hand side keeps the single-level
+    // tendency kernel (the z-marching one is not used inside ensemble graphs)
+    bool member = false;
     // kernel timing (erf_timing_begin / erf_timing_end)
     int timed_kernel = -1;
     int timed_count = 0;

@@ -38,6 +38,7 @@ struct RhsArgs {
     const double *dz, *idz, *idzf, *cs2;
     int oh, ov;
     int ntx, nty;  // tiles per level (blockDim.x x blockDim.y cells each)
+    int kch;       // levels per block of the z-marching tendency kernel
     int sgs, visc;
     // anelastic equation set: p' is the projections' (read, not written) and
     // the buoyancy is g rho0 (theta - theta0) / theta0 (Sec. 2.2)
@@ -72,6 +73,9 @@ constexpr int kDryEq = 0, kMoistEq = 1, kAnelEq = 2;
 // and 4, slower at 2)
 template <typename T>
 constexpr int kRhsWaves = sizeof(T) == 4 ? 4 : 3;
+// compute units of an MI355X (the z-marching kernel's chunking aims at two
+// blocks per unit; the results do not depend on it)
+constexpr int kNumCUs = 256;
 
 // ---------------------------------------------------------------------------
 // primitives
@@ -441,6 +445,27 @@ __device__ __forceinline__ R interp(int order, const R (&q)[7], int o, R s)
     return ord == 6 ? c6 : c6 - s * R(1.0 / 60.0) * ((qp2 - qm3) - R(5) * (qp1 - qm2) + R(10) * (q0 - qm1));
 }
 
+// What k_rhs takes from the thread's own column at levels other than its
+// own, and the values of its own level that the next level needs again: the
+// vertical stencils of theta, u, v and w over levels k-3..k+3 (reflected at
+// the lids, w with the sign of its odd reflection) and the momenta, pressure,
+// density, stresses and diffusivity of the neighbouring levels.  The
+// single-level kernel loads them for each cell; the z-marching kernel loads
+// each value once and carries it in registers from level to level.
+template <typename T>
+struct RhsCol {
+    T th[7], u[7], v[7], w[7];  // levels (faces for w) k-3 .. k+3
+    T U0, U1, V0, V1;           // ru at x-faces i, i+1 and rv at y-faces j, j+1 of level k
+    T Um, U1m, Vm, V1m;         // the same at level k-1 (level 0: its own)
+    T W0, W1, Wm;               // rw on faces k, k+1, k-1 (face 0: its own)
+    T Wx0, Wx1, Wy0, Wy1;       // rw on faces k, k+1 of the columns i-1 and j-1
+    T rho, rhom, pp, ppm;       // stored rho and p' of levels k and k-1 (level 0: its own)
+    T qf, qfm, bm, bmm;         // moist: 1 + q_v + q_c and the density departure, k and k-1
+    T t33, t33m;                // tau_33 of levels k and k-1
+    T t13, t13p, t23, t23p;     // tau_13, tau_23 on faces k and k+1
+    T kb, kc, ka;               // heat diffusivity of levels k-1, k, k+1 (clamped at the lids)
+};
+
 // kNear: the domain is at least 3 cells wide and 3 levels high, so that one
 // conditional add or reflection brings any stencil offset (at most 3) back
 // into it; the periodic and reflected indices are then selects instead of
@@ -449,60 +474,158 @@ __device__ __forceinline__ R interp(int order, const R (&q)[7], int o, R s)
 // kEq: the equation set (kDryEq, kMoistEq, kAnelEq).
 // kMoistEq: the pressure gradient and the buoyancy are divided by the face mean of
 // 1 + q_v + q_c, and the buoyancy is that of the total density (eq. mom).
-// Three wavefronts per SIMD (the occupancy its registers give anyway): told
-// so, the scheduler keeps each section's gathers in a few large groups
-// rather than trading round trips for registers.
+template <bool kNear>
+__device__ __forceinline__ int rhs_wrap(int v, int n)
+{
+    return kNear ? v + (v < 0 ? n : 0) - (v >= n ? n : 0) : wrap_idx(v, n);
+}
+// (two plain selects each rather than nested conditionals, which the
+// compiler turns into branches)
+template <bool kNear>
+__device__ __forceinline__ int rhs_reflc(int kk, int nz)
+{
+    if constexpr (!kNear) return refl_centre(kk, nz);
+    const int r = kk < 0 ? -1 - kk : kk;
+    return r >= nz ? 2 * nz - 1 - r : r;
+}
+template <bool kNear>
+__device__ __forceinline__ int rhs_reflf(int kk, int nz, double &sg)
+{
+    if constexpr (!kNear) return refl_face(kk, nz, sg);
+    sg = ((kk < 0) | (kk > nz)) ? -1.0 : 1.0;
+    const int r = kk < 0 ? -kk : kk;
+    return r > nz ? 2 * nz - r : r;
+}
+
+// slot t (0..6) of the vertical windows: level (face) L = k + t - 3 of the
+// column col
+template <typename T, bool kNear>
+__device__ __forceinline__ void rhs_window_load(const RhsArgs<T> &a, RhsCol<T> &z, int col, int t, int L)
+{
+    const int nz = a.d.nz, P = a.d.nxy;
+    const int lc = rhs_reflc<kNear>(L, nz) * P + col;
+    double sg;
+    const int lf = rhs_reflf<kNear>(L, nz, sg) * P + col;
+    z.th[t] = a.th[lc];
+    z.u[t] = a.u[lc];
+    z.v[t] = a.v[lc];
+    z.w[t] = (T)sg * a.w[lf];
+}
+
+// the values of level k that the z-march does not carry from level k-1
+// (oxp, oym...: the offsets of the neighbouring columns)
+template <typename T, bool kVisc, int kEq>
+__device__ __forceinline__ void rhs_level_load(const RhsArgs<T> &a, RhsCol<T> &z, int c, int k, int oxm, int oxp,
+                                               int oym, int oyp)
+{
+    const int nz = a.d.nz, P = a.d.nxy;
+    z.U0 = a.ru[c];
+    z.U1 = a.ru[c + oxp];
+    z.V0 = a.rv[c];
+    z.V1 = a.rv[c + oyp];
+    z.W1 = a.rw[c + P];
+    z.Wx1 = a.rw[c + oxm + P];
+    z.Wy1 = a.rw[c + oym + P];
+    z.rho = a.rho[c];
+    z.pp = a.pp[c];
+    if constexpr (kEq == kMoistEq) {
+        z.qf = a.qf[c];
+        z.bm = a.bm[c];
+    }
+    if constexpr (kVisc) {
+        z.t33 = a.t33[c];
+        z.t13p = a.t13[c + P];
+        z.t23p = a.t23[c + P];
+        z.ka = a.kap[c + (k < nz - 1 ? P : 0)];
+    }
+}
+
+// the values of level k-1 (level 0: of level 0) and of level k's own faces
+// that the z-march carries; loaded at the start of a march and by the
+// single-level kernel
+template <typename T, bool kVisc, int kEq>
+__device__ __forceinline__ void rhs_carry_load(const RhsArgs<T> &a, RhsCol<T> &z, int col, int k, int oxm, int oxp,
+                                               int oym, int oyp)
+{
+    const int P = a.d.nxy;
+    const int c = col + k * P, cm = col + (k > 0 ? k - 1 : 0) * P;
+    z.W0 = a.rw[c];
+    z.Wx0 = a.rw[c + oxm];
+    z.Wy0 = a.rw[c + oym];
+    z.Um = a.ru[cm];
+    z.U1m = a.ru[cm + oxp];
+    z.Vm = a.rv[cm];
+    z.V1m = a.rv[cm + oyp];
+    z.Wm = a.rw[cm];
+    z.rhom = a.rho[cm];
+    z.ppm = a.pp[cm];
+    if constexpr (kEq == kMoistEq) {
+        z.qfm = a.qf[cm];
+        z.bmm = a.bm[cm];
+    }
+    if constexpr (kVisc) {
+        z.t33m = a.t33[cm];
+        z.t13 = a.t13[c];
+        z.t23 = a.t23[c];
+        z.kb = a.kap[cm];
+        z.kc = a.kap[c];
+    }
+}
+
+// from level k to level k+1: the windows move up one slot, this level's
+// values become the level-below values and the face-(k+1) values this level's
+template <typename T>
+__device__ __forceinline__ void rhs_carry_up(RhsCol<T> &z)
+{
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        z.th[t] = z.th[t + 1];
+        z.u[t] = z.u[t + 1];
+        z.v[t] = z.v[t + 1];
+        z.w[t] = z.w[t + 1];
+    }
+    z.Um = z.U0;
+    z.U1m = z.U1;
+    z.Vm = z.V0;
+    z.V1m = z.V1;
+    z.Wm = z.W0;
+    z.W0 = z.W1;
+    z.Wx0 = z.Wx1;
+    z.Wy0 = z.Wy1;
+    z.rhom = z.rho;
+    z.ppm = z.pp;
+    z.qfm = z.qf;
+    z.bmm = z.bm;
+    z.t33m = z.t33;
+    z.t13 = z.t13p;
+    z.t23 = z.t23p;
+    z.kb = z.kc;
+    z.kc = z.ka;
+}
+
+// The five tendencies of cell (i, j, k) (c its index) from the column values
+// z and the horizontal neighbours of level k.
 template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
-__device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
+__device__ __forceinline__ void rhs_level(const RhsArgs<T> &a, const RhsCol<T> &z, int i, int j, int k, int c)
 {
     constexpr bool kMoist = kEq == kMoistEq;
     using R = T;
     const Dims &d = a.d;
-    const TileIdx tc = tile_cell(vb, a.ntx, a.nty);
-    const int i = tc.i, j = tc.j, k = tc.k;
-    if (i >= d.nx || j >= d.ny) return;
     const int nz = d.nz, P = d.nxy;
-    const int c = cidx(d, i, j, k);
-    // neighbour offsets: x and y periodic; z reflected (even for centre and
-    // horizontal-face fields, odd with a sign for z-face fields); computed
-    // where used: cheap integer work instead of 42 registers
-    auto wrap = [&](int v, int n) { return kNear ? v + (v < 0 ? n : 0) - (v >= n ? n : 0) : wrap_idx(v, n); };
-    // (two plain selects each rather than nested conditionals, which the
-    // compiler turns into branches)
-    auto reflc = [&](int kk) {
-        if constexpr (!kNear) return refl_centre(kk, nz);
-        const int r = kk < 0 ? -1 - kk : kk;
-        return r >= nz ? 2 * nz - 1 - r : r;
-    };
-    auto reflf = [&](int kk, double &sg) {
-        if constexpr (!kNear) return refl_face(kk, nz, sg);
-        sg = ((kk < 0) | (kk > nz)) ? -1.0 : 1.0;
-        const int r = kk < 0 ? -kk : kk;
-        return r > nz ? 2 * nz - r : r;
-    };
-    auto ox = [&](int t) { return wrap(i + t - 3, d.nx) - i; };
-    auto oy = [&](int t) { return (wrap(j + t - 3, d.ny) - j) * d.nx; };
-    auto ozc = [&](int t) { return (reflc(k + t - 3) - k) * P; };
+    // horizontal neighbour offsets (x and y periodic), computed where used:
+    // cheap integer work instead of registers
+    auto ox = [&](int t) { return rhs_wrap<kNear>(i + t - 3, d.nx) - i; };
+    auto oy = [&](int t) { return (rhs_wrap<kNear>(j + t - 3, d.ny) - j) * d.nx; };
     // FP32 storage: theta0 of the level k + t - 3 relative to level k (the
     // base-state difference formed in double, then rounded)
-    auto dthz0 = [&](int t) { return (R)(a.theta0[reflc(k + t - 3)] - a.theta0[k]); };
-    auto ozw = [&](int t) {
-        double sg;
-        return (reflf(k + t - 3, sg) - k) * P;
-    };
-    auto szw = [&](int t) {
-        double sg;
-        reflf(k + t - 3, sg);
-        return (R)sg;
-    };
-    // the cell below, clamped at the bottom (its values unused there)
-    const int dn = k > 0 ? P : 0;
+    auto dthz0 = [&](int t) { return (R)(a.theta0[rhs_reflc<kNear>(k + t - 3, nz)] - a.theta0[k]); };
     // 1 away from the bottom (top) lid, 0 on it: the lid fluxes are masked by
     // a product rather than a conditional, which the compiler would make a
     // branch with part of the stencil loads behind it
     const R not_bot = (R)(k > 0), not_top = (R)(k < nz - 1);
     const R idx = (R)a.idx, idy = (R)a.idy, idz = (R)a.idz[k], h = R(0.5), q4 = R(0.25);
     const int oh = a.oh, ov = a.ov;
+    const int kb = k > 0 ? k - 1 : 0;
     R q[7];
     // the five tendencies, stored together at the end: a store between the
     // sections would keep every later load behind it (the compiler cannot
@@ -510,13 +633,10 @@ __device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
     R out_r, out_t, out_u, out_v, out_w;
 
     // ---------------- cell: continuity and rho*theta ----------------
-    const R U0 = a.ru[c], U1 = a.ru[c + ox(4)];
-    const R V0 = a.rv[c], V1 = a.rv[c + oy(4)];
-    const R W0 = a.rw[c], W1 = a.rw[c + P];
+    const R U0 = z.U0, U1 = z.U1, V0 = z.V0, V1 = z.V1, W0 = z.W0, W1 = z.W1;
     const double r0k = a.rho0[k];
-    const R rc = full_in(a.rho, c, r0k);
+    const R rc = kPert<T> ? (R)r0k + z.rho : z.rho;
     {
-        // tendencies are read by later launches only: streaming stores
         out_r = -((U1 - U0) * idx + (V1 - V0) * idy + (W1 - W0) * idz);
         const T *th = a.th;
         R r;
@@ -532,7 +652,7 @@ __device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
             for (int t = 0; t < 7; ++t) q[t] = th[c + oy(t)];
             const R fy0 = V0 * interp<OH>(oh, q, 0, sign_of(V0)), fy1 = V1 * interp<OH>(oh, q, 1, sign_of(V1));
 #pragma unroll
-            for (int t = 0; t < 7; ++t) q[t] = dthz0(t) + th[c + ozc(t)];
+            for (int t = 0; t < 7; ++t) q[t] = dthz0(t) + z.th[t];
             const R fz0 = W0 * interp<OV>(ov, q, 0, sign_of(W0)) * not_bot;
             const R fz1 = W1 * interp<OV>(ov, q, 1, sign_of(W1)) * not_top;
             r = (R)a.theta0[k] * out_r - ((fx1 - fx0) * idx + (fy1 - fy0) * idy + (fz1 - fz0) * idz);
@@ -544,15 +664,14 @@ __device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
             for (int t = 0; t < 7; ++t) q[t] = th[c + oy(t)];
             const R fy0 = V0 * interp<OH>(oh, q, 0, sign_of(V0)), fy1 = V1 * interp<OH>(oh, q, 1, sign_of(V1));
 #pragma unroll
-            for (int t = 0; t < 7; ++t) q[t] = th[c + ozc(t)];
+            for (int t = 0; t < 7; ++t) q[t] = z.th[t];
             const R fz0 = W0 * interp<OV>(ov, q, 0, sign_of(W0)) * not_bot;
             const R fz1 = W1 * interp<OV>(ov, q, 1, sign_of(W1)) * not_top;
             r = -((fx1 - fx0) * idx + (fy1 - fy0) * idy + (fz1 - fz0) * idz);
         }
         if constexpr (kVisc) {
             const T *kp = a.kap;
-            const int up = k < nz - 1 ? P : 0;  // the cell above, clamped at the top
-            const R kc = kp[c], thc = th[c];
+            const R kc = z.kc, thc = z.th[3];
             // differences of theta: on one level the base value cancels; across
             // levels (FP32 storage) the base-state difference is added
             const R dzb = kPert<T> ? dthz0(2) : R(0), dza = kPert<T> ? dthz0(4) : R(0);
@@ -560,9 +679,9 @@ __device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
             const R hx1 = -h * (kc + kp[c + ox(4)]) * ((R)th[c + ox(4)] - thc) * idx;
             const R hy0 = -h * (kp[c + oy(2)] + kc) * (thc - (R)th[c + oy(2)]) * idy;
             const R hy1 = -h * (kc + kp[c + oy(4)]) * ((R)th[c + oy(4)] - thc) * idy;
-            const R kb = kp[c - dn], tb = th[c - dn], ka = kp[c + up], ta = th[c + up];
-            const R hz0 = -h * (kb + kc) * (thc - (dzb + tb)) * (R)a.idzf[k] * not_bot;
-            const R hz1 = -h * (kc + ka) * ((dza + ta) - thc) * (R)a.idzf[k + 1] * not_top;
+            // the levels below and above (clamped at the lids: the cell itself)
+            const R hz0 = -h * (z.kb + kc) * (thc - (dzb + z.th[2])) * (R)a.idzf[k] * not_bot;
+            const R hz1 = -h * (kc + z.ka) * ((dza + z.th[4]) - thc) * (R)a.idzf[k + 1] * not_top;
             r -= (hx1 - hx0) * idx + (hy1 - hy0) * idy + (hz1 - hz0) * idz;
         }
         if (k == 0 && a.Qs != 0.0) r += rc * (R)a.Qs * idz;
@@ -583,20 +702,20 @@ __device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
         for (int t = 0; t < 7; ++t) q[t] = u[c + oy(t)];
         const R fxy0 = b0 * interp<OH>(oh, q, 0, sign_of(b0)), fxy1 = b1 * interp<OH>(oh, q, 1, sign_of(b1));
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = u[c + ozc(t)];
+        for (int t = 0; t < 7; ++t) q[t] = z.u[t];
         // z-face momenta (faces 0..nz all exist; the lid fluxes are zero)
-        const R e0 = h * ((R)a.rw[c + ox(2)] + W0), e1 = h * ((R)a.rw[c + ox(2) + P] + W1);
+        const R e0 = h * (z.Wx0 + W0), e1 = h * (z.Wx1 + W1);
         const R fxz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0)) * not_bot;
         const R fxz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1)) * not_top;
         const R adv = (fxx_r - fxx_l) * idx + (fxy1 - fxy0) * idy + (fxz1 - fxz0) * idz;
-        R pgf = ((R)a.pp[c] - (R)a.pp[c + ox(2)]) * idx;
-        if constexpr (kMoist) pgf = pgf / (h * ((R)a.qf[c + ox(2)] + (R)a.qf[c]));
+        R pgf = (z.pp - (R)a.pp[c + ox(2)]) * idx;
+        if constexpr (kMoist) pgf = pgf / (h * ((R)a.qf[c + ox(2)] + z.qf));
         const R rho_f = h * (full_in(a.rho, c + ox(2), r0k) + rc);
         const R vbar = q4 * (Vw + V0 + Vwn + V1);
         R r = -adv - pgf + (R)a.f * (vbar - rho_f * (R)a.Vg);
         if constexpr (kVisc)
             r -= ((R)a.t11[c] - (R)a.t11[c + ox(2)]) * idx + ((R)a.t12[c + oy(4)] - (R)a.t12[c]) * idy +
-                 ((R)a.t13[c + P] - (R)a.t13[c]) * idz;
+                 (z.t13p - z.t13) * idz;
         out_u = r;
     }
 
@@ -614,68 +733,68 @@ __device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
         for (int t = 0; t < 7; ++t) q[t] = v[c + ox(t)];
         const R fyx0 = a0 * interp<OH>(oh, q, 0, sign_of(a0)), fyx1 = a1 * interp<OH>(oh, q, 1, sign_of(a1));
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = v[c + ozc(t)];
-        const R e0 = h * ((R)a.rw[c + oy(2)] + W0), e1 = h * ((R)a.rw[c + oy(2) + P] + W1);
+        for (int t = 0; t < 7; ++t) q[t] = z.v[t];
+        const R e0 = h * (z.Wy0 + W0), e1 = h * (z.Wy1 + W1);
         const R fyz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0)) * not_bot;
         const R fyz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1)) * not_top;
         const R adv = (fyx1 - fyx0) * idx + (fyy_r - fyy_l) * idy + (fyz1 - fyz0) * idz;
-        R pgf = ((R)a.pp[c] - (R)a.pp[c + oy(2)]) * idy;
-        if constexpr (kMoist) pgf = pgf / (h * ((R)a.qf[c + oy(2)] + (R)a.qf[c]));
+        R pgf = (z.pp - (R)a.pp[c + oy(2)]) * idy;
+        if constexpr (kMoist) pgf = pgf / (h * ((R)a.qf[c + oy(2)] + z.qf));
         const R rho_f = h * (full_in(a.rho, c + oy(2), r0k) + rc);
         const R ubar = q4 * (Us + Use + U0 + U1);
         R r = -adv - pgf - (R)a.f * (ubar - rho_f * (R)a.Ug);
         if constexpr (kVisc)
             r -= ((R)a.t12[c + ox(4)] - (R)a.t12[c]) * idx + ((R)a.t22[c] - (R)a.t22[c + oy(2)]) * idy +
-                 ((R)a.t23[c + P] - (R)a.t23[c]) * idz;
+                 (z.t23p - z.t23) * idz;
         out_v = r;
     }
 
     // ---------------- z-momentum on z-face (i, j, k) ----------------
     // the lid faces carry W = 0: the bottom face's tendency is computed from
-    // clamped (in-range) indices and stored as zero
+    // the level's own values in place of the level below and stored as zero
     {
-        const int cm = c - dn;
         const R idzf = (R)a.idzf[k];
-        const R a0 = h * ((R)a.ru[cm] + U0), a1 = h * ((R)a.ru[cm + ox(4)] + U1);
+        const R a0 = h * (z.Um + U0), a1 = h * (z.U1m + U1);
         const T *w = a.w;
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = w[c + ox(t)];
         const R fzx0 = a0 * interp<OH>(oh, q, 0, sign_of(a0)), fzx1 = a1 * interp<OH>(oh, q, 1, sign_of(a1));
-        const R b0 = h * ((R)a.rv[cm] + V0), b1 = h * ((R)a.rv[cm + oy(4)] + V1);
+        const R b0 = h * (z.Vm + V0), b1 = h * (z.V1m + V1);
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = w[c + oy(t)];
         const R fzy0 = b0 * interp<OH>(oh, q, 0, sign_of(b0)), fzy1 = b1 * interp<OH>(oh, q, 1, sign_of(b1));
-        const R eu = h * (W0 + W1), ed = h * ((R)a.rw[cm] + W0);
+        const R eu = h * (W0 + W1), ed = h * (z.Wm + W0);
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = szw(t) * w[c + ozw(t)];
+        for (int t = 0; t < 7; ++t) q[t] = z.w[t];
         const R fzz_u = eu * interp<OV>(ov, q, 1, sign_of(eu)), fzz_d = ed * interp<OV>(ov, q, 0, sign_of(ed));
         const R adv = (fzx1 - fzx0) * idx + (fzy1 - fzy0) * idy + (fzz_u - fzz_d) * idzf;
-        const R pgf = ((R)a.pp[c] - (R)a.pp[cm]) * idzf;
+        const R pgf = (z.pp - z.ppm) * idzf;
         R r;
         if constexpr (kMoist) {
             // B = -g (rho_m - rho_m0) from the total densities; -grad p' + B over
             // the face mean of 1 + q_v + q_c
-            const R buoy = -(R)a.g * h * ((R)a.bm[c] + (R)a.bm[cm]);
-            const R qfm = h * ((R)a.qf[cm] + (R)a.qf[c]);
+            const R buoy = -(R)a.g * h * (z.bm + z.bmm);
+            const R qfm = h * (z.qfm + z.qf);
             r = -adv - pgf / qfm + buoy / qfm;
         } else if constexpr (kEq == kAnelEq) {
             // anelastic buoyancy g rho0 (theta - theta0) / theta0, the mean of
             // the two cells on the face
-            const int kb = k > 0 ? k - 1 : 0;
-            const R tu = kPert<T> ? (R)a.th[c] : (R)a.th[c] - (R)a.theta0[k];
-            const R td = kPert<T> ? (R)a.th[cm] : (R)a.th[cm] - (R)a.theta0[kb];
+            const R tu = kPert<T> ? z.th[3] : z.th[3] - (R)a.theta0[k];
+            const R td = kPert<T> ? z.th[2] : z.th[2] - (R)a.theta0[kb];
             const R bu = (R)a.rho0[k] * tu / (R)a.theta0[k], bd = (R)a.rho0[kb] * td / (R)a.theta0[kb];
             r = -adv - pgf + (R)a.g * h * (bu + bd);
         } else {
             // buoyancy B = -(rho - rho0) g on the face; heavier air sinks
-            const R buoy = -(R)a.g * h * (pert_in(a.rho, c, r0k) + pert_in(a.rho, cm, a.rho0[k > 0 ? k - 1 : 0]));
+            const R pu = kPert<T> ? z.rho : z.rho - (R)r0k;
+            const R pd = kPert<T> ? z.rhom : z.rhom - (R)a.rho0[kb];
+            const R buoy = -(R)a.g * h * (pu + pd);
             r = -adv - pgf + buoy;
         }
         if constexpr (kVisc)
-            r -= ((R)a.t13[c + ox(4)] - (R)a.t13[c]) * idx + ((R)a.t23[c + oy(4)] - (R)a.t23[c]) * idy +
-                 ((R)a.t33[c] - (R)a.t33[cm]) * idzf;
+            r -= ((R)a.t13[c + ox(4)] - z.t13) * idx + ((R)a.t23[c + oy(4)] - z.t23) * idy + (z.t33 - z.t33m) * idzf;
         out_w = k > 0 ? r : R(0);
     }
+    // tendencies are read by later launches only: streaming stores
     st_stream(a.Rr + c, (T)out_r);
     st_stream(a.Rt + c, (T)out_t);
     st_stream(a.Ru + c, (T)out_u);
@@ -683,10 +802,71 @@ __device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
     st_stream(a.Rw + c, (T)out_w);
     if (k == 0) a.Rw[c + nz * P] = 0.0;
 }
+
+// One thread per cell (i, j, k): every column value loaded for the cell.
+// The general kernel (domains narrower than the stencil), and the ensemble
+// members' batched launches.
+template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
+__device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
+{
+    const Dims &d = a.d;
+    const TileIdx tc = tile_cell(vb, a.ntx, a.nty);
+    const int i = tc.i, j = tc.j, k = tc.k;
+    if (i >= d.nx || j >= d.ny) return;
+    const int col = j * d.nx + i, c = col + k * d.nxy;
+    const int oxm = rhs_wrap<kNear>(i - 1, d.nx) - i, oxp = rhs_wrap<kNear>(i + 1, d.nx) - i;
+    const int oym = (rhs_wrap<kNear>(j - 1, d.ny) - j) * d.nx, oyp = (rhs_wrap<kNear>(j + 1, d.ny) - j) * d.nx;
+    RhsCol<T> z{};
+#pragma unroll
+    for (int t = 0; t < 7; ++t) rhs_window_load<T, kNear>(a, z, col, t, k + t - 3);
+    rhs_carry_load<T, kVisc, kEq>(a, z, col, k, oxm, oxp, oym, oyp);
+    rhs_level_load<T, kVisc, kEq>(a, z, c, k, oxm, oxp, oym, oyp);
+    rhs_level<T, OH, OV, kNear, kVisc, kEq>(a, z, i, j, k, c);
+}
+
+// One thread per column of a tile, marching up through a chunk of a.kch
+// levels: each value of the thread's own column is loaded once (the windows'
+// three levels below and above the chunk once more) and carried in
+// registers; the horizontal neighbours of a level are read while the
+// neighbouring tiles work on the same levels, from the caches.
+template <typename T, int OH, int OV, bool kVisc, int kEq>
+__device__ __forceinline__ void k_rhs_march_body(RhsArgs<T> a, VBlock vb)
+{
+    const Dims &d = a.d;
+    const TileIdx tc = tile_cell(vb, a.ntx, a.nty);
+    const int i = tc.i, j = tc.j;
+    if (i >= d.nx || j >= d.ny) return;
+    const int nz = d.nz, P = d.nxy;
+    const int k0 = tc.k * a.kch, k1 = min(k0 + a.kch, nz);
+    const int col = j * d.nx + i;
+    const int oxm = rhs_wrap<true>(i - 1, d.nx) - i, oxp = rhs_wrap<true>(i + 1, d.nx) - i;
+    const int oym = (rhs_wrap<true>(j - 1, d.ny) - j) * d.nx, oyp = (rhs_wrap<true>(j + 1, d.ny) - j) * d.nx;
+    RhsCol<T> z{};
+#pragma unroll
+    for (int t = 0; t < 6; ++t) rhs_window_load<T, true>(a, z, col, t, k0 + t - 3);
+    rhs_carry_load<T, kVisc, kEq>(a, z, col, k0, oxm, oxp, oym, oyp);
+    for (int k = k0; k < k1; ++k) {
+        const int c = col + k * P;
+        rhs_window_load<T, true>(a, z, col, 6, k + 3);
+        rhs_level_load<T, kVisc, kEq>(a, z, c, k, oxm, oxp, oym, oyp);
+        rhs_level<T, OH, OV, true, kVisc, kEq>(a, z, i, j, k, c);
+        rhs_carry_up(z);
+    }
+}
+
+// Wavefronts per SIMD of the z-marching kernel (FP64): its registers also
+// hold the four seven-level windows and the carried values.
+constexpr int kMarchWaves = 2;
+
 template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kRhsWaves<T>, kRhsWaves<T>))) void k_rhs(RhsArgs<T> a)
 {
     k_rhs_body<T, OH, OV, kNear, kVisc, kEq>(a, hw_block());
+}
+template <typename T, int OH, int OV, bool kVisc, int kEq>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMarchWaves, kMarchWaves))) void k_rhs_march(RhsArgs<T> a)
+{
+    k_rhs_march_body<T, OH, OV, kVisc, kEq>(a, hw_block());
 }
 template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kRhsWaves<T>, kRhsWaves<T>))) void k_rhs_batch(const RhsArgs<T> *args, BatchMap bm)
@@ -703,45 +883,59 @@ namespace {
 // combination, and domains narrower than the stencil, take the general one.
 // Moist dynamics: 3rd order (the moist workload's) and the general instances.
 // The anelastic set (FP64 only): orders 2, 3 and 5 and the general instances.
+// FP64 on domains at least 3 cells wide and 3 levels high takes the
+// z-marching kernel (grdm: tiles x chunks of a.kch levels); FP32, narrower
+// domains and ensemble members take the single-level kernel (grd: tiles x
+// levels).  Both give the same results bit for bit.  In FP32 the
+// single-level kernel's re-reads fit the caches (1.06 of its compulsory
+// bytes at 256 x 256 x 128) and its four wavefronts per SIMD make it the
+// faster one (284 against 315 us per launch); inside the ensemble's graphs
+// the z-marching kernel is not used.
 template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
-void rhs_one(erf_ctx *cx, const RhsArgs<T> &a, dim3 grd, dim3 blk)
+void rhs_one(erf_ctx *cx, const RhsArgs<T> &a, dim3 grd, dim3 grdm, dim3 blk)
 {
-    run<RhsArgs<T>, k_rhs<T, OH, OV, kNear, kVisc, kEq>, k_rhs_batch<T, OH, OV, kNear, kVisc, kEq>>(
-        cx, grd, blk, 0, a);
+    if constexpr (kNear && sizeof(T) == 8) {
+        if (!cx->member && !cx->rec) {
+            void *argv[] = {(void *)&a};
+            (void)hipLaunchKernel((const void *)k_rhs_march<T, OH, OV, kVisc, kEq>, grdm, blk, argv, 0, cx->stream);
+            return;
+        }
+    }
+    run<RhsArgs<T>, k_rhs<T, OH, OV, kNear, kVisc, kEq>, k_rhs_batch<T, OH, OV, kNear, kVisc, kEq>>(cx, grd, blk, 0, a);
 }
 template <typename T, bool kVisc, int kEq>
-void launch_rhs_eq(erf_ctx *cx, const RhsArgs<T> &a, dim3 grd, dim3 blk)
+void launch_rhs_eq(erf_ctx *cx, const RhsArgs<T> &a, dim3 grd, dim3 grdm, dim3 blk)
 {
     const bool near = a.d.nx >= 3 && a.d.ny >= 3 && a.d.nz >= 3;
     if (near && a.oh == 5 && a.ov == 5)
-        rhs_one<T, 5, 5, true, kVisc, kEq>(cx, a, grd, blk);
+        rhs_one<T, 5, 5, true, kVisc, kEq>(cx, a, grd, grdm, blk);
     else if (near && a.oh == 3 && a.ov == 3)
-        rhs_one<T, 3, 3, true, kVisc, kEq>(cx, a, grd, blk);
+        rhs_one<T, 3, 3, true, kVisc, kEq>(cx, a, grd, grdm, blk);
     else if (near && a.oh == 2 && a.ov == 2)
-        rhs_one<T, 2, 2, true, kVisc, kEq>(cx, a, grd, blk);
+        rhs_one<T, 2, 2, true, kVisc, kEq>(cx, a, grd, grdm, blk);
     else if (near)
-        rhs_one<T, 0, 0, true, kVisc, kEq>(cx, a, grd, blk);
+        rhs_one<T, 0, 0, true, kVisc, kEq>(cx, a, grd, grdm, blk);
     else
-        rhs_one<T, 0, 0, false, kVisc, kEq>(cx, a, grd, blk);
+        rhs_one<T, 0, 0, false, kVisc, kEq>(cx, a, grd, grdm, blk);
 }
 template <typename T, bool kVisc>
-void launch_rhs(erf_ctx *cx, const RhsArgs<T> &a, bool moist, dim3 grd, dim3 blk)
+void launch_rhs(erf_ctx *cx, const RhsArgs<T> &a, bool moist, dim3 grd, dim3 grdm, dim3 blk)
 {
     const bool near = a.d.nx >= 3 && a.d.ny >= 3 && a.d.nz >= 3;
     if (moist) {
         if (near && a.oh == 3 && a.ov == 3)
-            rhs_one<T, 3, 3, true, kVisc, kMoistEq>(cx, a, grd, blk);
+            rhs_one<T, 3, 3, true, kVisc, kMoistEq>(cx, a, grd, grdm, blk);
         else if (near)
-            rhs_one<T, 0, 0, true, kVisc, kMoistEq>(cx, a, grd, blk);
+            rhs_one<T, 0, 0, true, kVisc, kMoistEq>(cx, a, grd, grdm, blk);
         else
-            rhs_one<T, 0, 0, false, kVisc, kMoistEq>(cx, a, grd, blk);
+            rhs_one<T, 0, 0, false, kVisc, kMoistEq>(cx, a, grd, grdm, blk);
     } else if constexpr (std::is_same_v<T, double>) {
         if (a.anel)
-            launch_rhs_eq<T, kVisc, kAnelEq>(cx, a, grd, blk);
+            launch_rhs_eq<T, kVisc, kAnelEq>(cx, a, grd, grdm, blk);
         else
-            launch_rhs_eq<T, kVisc, kDryEq>(cx, a, grd, blk);
+            launch_rhs_eq<T, kVisc, kDryEq>(cx, a, grd, grdm, blk);
     } else {
-        launch_rhs_eq<T, kVisc, kDryEq>(cx, a, grd, blk);
+        launch_rhs_eq<T, kVisc, kDryEq>(cx, a, grd, grdm, blk);
     }
 }
 
@@ -819,7 +1013,13 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], const void *rq, void 
     const int tx = tile_width(d.nx, d.ny, 256), ty = 256 / tx;
     a.ntx = (d.nx + tx - 1) / tx;
     a.nty = (d.ny + ty - 1) / ty;
-    dim3 blk(tx, ty, 1), grd(a.ntx * a.nty * d.nz), grdw(a.ntx * a.nty * (d.nz + 1));
+    // the z-march: levels in chunks, enough of them for about two blocks per
+    // compute unit, at least 16 levels each (the windows reload 6 levels per
+    // chunk)
+    const int tiles = a.ntx * a.nty;
+    const int nch = std::max(1, std::min((2 * kNumCUs + tiles - 1) / tiles, d.nz / 16));
+    a.kch = (d.nz + nch - 1) / nch;
+    dim3 blk(tx, ty, 1), grd(tiles * d.nz), grdw(tiles * (d.nz + 1)), grdm(tiles * ((d.nz + a.kch - 1) / a.kch));
     timing_start(cx, K_PREP);
     if (moist)
         run<RhsArgs<T>, k_prep<T, true>, k_prep_batch<T, true>>(cx, grd, blk, 0, a);
@@ -852,9 +1052,9 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], const void *rq, void 
     }
     timing_start(cx, K_RHS);
     if (a.visc)
-        launch_rhs<T, true>(cx, a, moist, grd, blk);
+        launch_rhs<T, true>(cx, a, moist, grd, grdm, blk);
     else
-        launch_rhs<T, false>(cx, a, moist, grd, blk);
+        launch_rhs<T, false>(cx, a, moist, grd, grdm, blk);
     timing_stop(cx, K_RHS);
     if (mlp) {
         hipError_t e = hipGetLastError();
