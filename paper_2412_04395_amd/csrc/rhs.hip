@@ -450,8 +450,8 @@ __device__ __forceinline__ R interp(int order, const R (&q)[7], int o, R s)
 // vertical stencils of theta, u, v and w over levels k-3..k+3 (reflected at
 // the lids, w with the sign of its odd reflection) and the momenta, pressure,
 // density, stresses and diffusivity of the neighbouring levels.  The
-// single-level kernel loads them for each cell; the z-marching kernel loads
-// each value once and carries it in registers from level to level.
+// single-level kernel loads them for each cell; the z-marching kernel takes
+// them from its LDS planes or carries them in registers from level to level.
 template <typename T>
 struct RhsCol {
     T th[7], u[7], v[7], w[7];  // levels (faces for w) k-3 .. k+3
@@ -512,8 +512,8 @@ __device__ __forceinline__ void rhs_window_load(const RhsArgs<T> &a, RhsCol<T> &
     z.w[t] = (T)sg * a.w[lf];
 }
 
-// the values of level k that the z-march does not carry from level k-1
-// (oxp, oym...: the offsets of the neighbouring columns)
+// the single-level kernel's loads of level k and face k+1 (oxp, oym...: the
+// offsets of the neighbouring columns)
 template <typename T, bool kVisc, int kEq>
 __device__ __forceinline__ void rhs_level_load(const RhsArgs<T> &a, RhsCol<T> &z, int c, int k, int oxm, int oxp,
                                                int oym, int oyp)
@@ -540,9 +540,8 @@ __device__ __forceinline__ void rhs_level_load(const RhsArgs<T> &a, RhsCol<T> &z
     }
 }
 
-// the values of level k-1 (level 0: of level 0) and of level k's own faces
-// that the z-march carries; loaded at the start of a march and by the
-// single-level kernel
+// the single-level kernel's loads of level k-1 (level 0: of level 0) and of
+// face k
 template <typename T, bool kVisc, int kEq>
 __device__ __forceinline__ void rhs_carry_load(const RhsArgs<T> &a, RhsCol<T> &z, int col, int k, int oxm, int oxp,
                                                int oym, int oyp)
@@ -603,19 +602,55 @@ __device__ __forceinline__ void rhs_carry_up(RhsCol<T> &z)
     z.kc = z.ka;
 }
 
+// full value from a stored one (FP32 storage: a perturbation of base)
+template <typename T>
+__device__ __forceinline__ T full_v(T stored, double base)
+{
+    if constexpr (kPert<T>)
+        return (T)base + stored;
+    else
+        return stored;
+}
+
+// Horizontal neighbours of level k (and of face k for w, rw, tau_13,
+// tau_23) at offsets (dx, dy) from the thread's cell, read from the arrays
+// in memory: x and y periodic, the offsets computed where used (cheap integer
+// work instead of registers).
+template <typename T, bool kNear>
+struct GlobalNbr {
+    const RhsArgs<T> &a;
+    int i, j, c;
+    __device__ __forceinline__ int off(int dx, int dy) const
+    {
+        const Dims &d = a.d;
+        return (rhs_wrap<kNear>(i + dx, d.nx) - i) + (rhs_wrap<kNear>(j + dy, d.ny) - j) * d.nx;
+    }
+    __device__ __forceinline__ T th(int dx, int dy) const { return a.th[c + off(dx, dy)]; }
+    __device__ __forceinline__ T u(int dx, int dy) const { return a.u[c + off(dx, dy)]; }
+    __device__ __forceinline__ T v(int dx, int dy) const { return a.v[c + off(dx, dy)]; }
+    __device__ __forceinline__ T w(int dx, int dy) const { return a.w[c + off(dx, dy)]; }
+    __device__ __forceinline__ T ru(int dx, int dy) const { return a.ru[c + off(dx, dy)]; }
+    __device__ __forceinline__ T rv(int dx, int dy) const { return a.rv[c + off(dx, dy)]; }
+    __device__ __forceinline__ T rho(int dx, int dy) const { return a.rho[c + off(dx, dy)]; }
+    __device__ __forceinline__ T pp(int dx, int dy) const { return a.pp[c + off(dx, dy)]; }
+    __device__ __forceinline__ T qf(int dx, int dy) const { return a.qf[c + off(dx, dy)]; }
+    __device__ __forceinline__ T kap(int dx, int dy) const { return a.kap[c + off(dx, dy)]; }
+    __device__ __forceinline__ T t11(int dx, int dy) const { return a.t11[c + off(dx, dy)]; }
+    __device__ __forceinline__ T t12(int dx, int dy) const { return a.t12[c + off(dx, dy)]; }
+    __device__ __forceinline__ T t22(int dx, int dy) const { return a.t22[c + off(dx, dy)]; }
+    __device__ __forceinline__ T t13(int dx, int dy) const { return a.t13[c + off(dx, dy)]; }
+    __device__ __forceinline__ T t23(int dx, int dy) const { return a.t23[c + off(dx, dy)]; }
+};
+
 // The five tendencies of cell (i, j, k) (c its index) from the column values
-// z and the horizontal neighbours of level k.
-template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
-__device__ __forceinline__ void rhs_level(const RhsArgs<T> &a, const RhsCol<T> &z, int i, int j, int k, int c)
+// z and the horizontal neighbours H of level k (GlobalNbr or LdsNbr).
+template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq, typename Nbr>
+__device__ __forceinline__ void rhs_level(const RhsArgs<T> &a, const RhsCol<T> &z, const Nbr &H, int k, int c)
 {
     constexpr bool kMoist = kEq == kMoistEq;
     using R = T;
     const Dims &d = a.d;
     const int nz = d.nz, P = d.nxy;
-    // horizontal neighbour offsets (x and y periodic), computed where used:
-    // cheap integer work instead of registers
-    auto ox = [&](int t) { return rhs_wrap<kNear>(i + t - 3, d.nx) - i; };
-    auto oy = [&](int t) { return (rhs_wrap<kNear>(j + t - 3, d.ny) - j) * d.nx; };
     // FP32 storage: theta0 of the level k + t - 3 relative to level k (the
     // base-state difference formed in double, then rounded)
     auto dthz0 = [&](int t) { return (R)(a.theta0[rhs_reflc<kNear>(k + t - 3, nz)] - a.theta0[k]); };
@@ -638,7 +673,6 @@ __device__ __forceinline__ void rhs_level(const RhsArgs<T> &a, const RhsCol<T> &
     const R rc = kPert<T> ? (R)r0k + z.rho : z.rho;
     {
         out_r = -((U1 - U0) * idx + (V1 - V0) * idy + (W1 - W0) * idz);
-        const T *th = a.th;
         R r;
         if constexpr (kPert<T>) {
             // FP32: the flux U theta^ split as U theta0(k) + U (theta^ - theta0(k)),
@@ -646,10 +680,10 @@ __device__ __forceinline__ void rhs_level(const RhsArgs<T> &a, const RhsCol<T> &
             // the stored perturbation, vertically plus the base-state difference
             // of the levels), so that no float sum carries theta0 ~ 300 K
 #pragma unroll
-            for (int t = 0; t < 7; ++t) q[t] = th[c + ox(t)];
+            for (int t = 0; t < 7; ++t) q[t] = H.th(t - 3, 0);
             const R fx0 = U0 * interp<OH>(oh, q, 0, sign_of(U0)), fx1 = U1 * interp<OH>(oh, q, 1, sign_of(U1));
 #pragma unroll
-            for (int t = 0; t < 7; ++t) q[t] = th[c + oy(t)];
+            for (int t = 0; t < 7; ++t) q[t] = H.th(0, t - 3);
             const R fy0 = V0 * interp<OH>(oh, q, 0, sign_of(V0)), fy1 = V1 * interp<OH>(oh, q, 1, sign_of(V1));
 #pragma unroll
             for (int t = 0; t < 7; ++t) q[t] = dthz0(t) + z.th[t];
@@ -658,10 +692,10 @@ __device__ __forceinline__ void rhs_level(const RhsArgs<T> &a, const RhsCol<T> &
             r = (R)a.theta0[k] * out_r - ((fx1 - fx0) * idx + (fy1 - fy0) * idy + (fz1 - fz0) * idz);
         } else {
 #pragma unroll
-            for (int t = 0; t < 7; ++t) q[t] = th[c + ox(t)];
+            for (int t = 0; t < 7; ++t) q[t] = H.th(t - 3, 0);
             const R fx0 = U0 * interp<OH>(oh, q, 0, sign_of(U0)), fx1 = U1 * interp<OH>(oh, q, 1, sign_of(U1));
 #pragma unroll
-            for (int t = 0; t < 7; ++t) q[t] = th[c + oy(t)];
+            for (int t = 0; t < 7; ++t) q[t] = H.th(0, t - 3);
             const R fy0 = V0 * interp<OH>(oh, q, 0, sign_of(V0)), fy1 = V1 * interp<OH>(oh, q, 1, sign_of(V1));
 #pragma unroll
             for (int t = 0; t < 7; ++t) q[t] = z.th[t];
@@ -670,15 +704,14 @@ __device__ __forceinline__ void rhs_level(const RhsArgs<T> &a, const RhsCol<T> &
             r = -((fx1 - fx0) * idx + (fy1 - fy0) * idy + (fz1 - fz0) * idz);
         }
         if constexpr (kVisc) {
-            const T *kp = a.kap;
             const R kc = z.kc, thc = z.th[3];
             // differences of theta: on one level the base value cancels; across
             // levels (FP32 storage) the base-state difference is added
             const R dzb = kPert<T> ? dthz0(2) : R(0), dza = kPert<T> ? dthz0(4) : R(0);
-            const R hx0 = -h * (kp[c + ox(2)] + kc) * (thc - (R)th[c + ox(2)]) * idx;
-            const R hx1 = -h * (kc + kp[c + ox(4)]) * ((R)th[c + ox(4)] - thc) * idx;
-            const R hy0 = -h * (kp[c + oy(2)] + kc) * (thc - (R)th[c + oy(2)]) * idy;
-            const R hy1 = -h * (kc + kp[c + oy(4)]) * ((R)th[c + oy(4)] - thc) * idy;
+            const R hx0 = -h * (H.kap(-1, 0) + kc) * (thc - (R)H.th(-1, 0)) * idx;
+            const R hx1 = -h * (kc + H.kap(1, 0)) * ((R)H.th(1, 0) - thc) * idx;
+            const R hy0 = -h * (H.kap(0, -1) + kc) * (thc - (R)H.th(0, -1)) * idy;
+            const R hy1 = -h * (kc + H.kap(0, 1)) * ((R)H.th(0, 1) - thc) * idy;
             // the levels below and above (clamped at the lids: the cell itself)
             const R hz0 = -h * (z.kb + kc) * (thc - (dzb + z.th[2])) * (R)a.idzf[k] * not_bot;
             const R hz1 = -h * (kc + z.ka) * ((dza + z.th[4]) - thc) * (R)a.idzf[k + 1] * not_top;
@@ -690,16 +723,15 @@ __device__ __forceinline__ void rhs_level(const RhsArgs<T> &a, const RhsCol<T> &
 
     // ---------------- x-momentum on x-face (i, j, k) ----------------
     {
-        const R Um = a.ru[c + ox(2)];
+        const R Um = H.ru(-1, 0);
         const R ar = h * (U0 + U1), al = h * (Um + U0);
-        const T *u = a.u;
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = u[c + ox(t)];
+        for (int t = 0; t < 7; ++t) q[t] = H.u(t - 3, 0);
         const R fxx_r = ar * interp<OH>(oh, q, 1, sign_of(ar)), fxx_l = al * interp<OH>(oh, q, 0, sign_of(al));
-        const R Vw = a.rv[c + ox(2)], Vwn = a.rv[c + ox(2) + oy(4)];
+        const R Vw = H.rv(-1, 0), Vwn = H.rv(-1, 1);
         const R b0 = h * (Vw + V0), b1 = h * (Vwn + V1);
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = u[c + oy(t)];
+        for (int t = 0; t < 7; ++t) q[t] = H.u(0, t - 3);
         const R fxy0 = b0 * interp<OH>(oh, q, 0, sign_of(b0)), fxy1 = b1 * interp<OH>(oh, q, 1, sign_of(b1));
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = z.u[t];
@@ -708,29 +740,28 @@ __device__ __forceinline__ void rhs_level(const RhsArgs<T> &a, const RhsCol<T> &
         const R fxz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0)) * not_bot;
         const R fxz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1)) * not_top;
         const R adv = (fxx_r - fxx_l) * idx + (fxy1 - fxy0) * idy + (fxz1 - fxz0) * idz;
-        R pgf = (z.pp - (R)a.pp[c + ox(2)]) * idx;
-        if constexpr (kMoist) pgf = pgf / (h * ((R)a.qf[c + ox(2)] + z.qf));
-        const R rho_f = h * (full_in(a.rho, c + ox(2), r0k) + rc);
+        R pgf = (z.pp - (R)H.pp(-1, 0)) * idx;
+        if constexpr (kMoist) pgf = pgf / (h * ((R)H.qf(-1, 0) + z.qf));
+        const R rho_f = h * (full_v<T>(H.rho(-1, 0), r0k) + rc);
         const R vbar = q4 * (Vw + V0 + Vwn + V1);
         R r = -adv - pgf + (R)a.f * (vbar - rho_f * (R)a.Vg);
         if constexpr (kVisc)
-            r -= ((R)a.t11[c] - (R)a.t11[c + ox(2)]) * idx + ((R)a.t12[c + oy(4)] - (R)a.t12[c]) * idy +
+            r -= ((R)H.t11(0, 0) - (R)H.t11(-1, 0)) * idx + ((R)H.t12(0, 1) - (R)H.t12(0, 0)) * idy +
                  (z.t13p - z.t13) * idz;
         out_u = r;
     }
 
     // ---------------- y-momentum on y-face (i, j, k) ----------------
     {
-        const R Vs = a.rv[c + oy(2)];
+        const R Vs = H.rv(0, -1);
         const R br = h * (V0 + V1), bl = h * (Vs + V0);
-        const T *v = a.v;
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = v[c + oy(t)];
+        for (int t = 0; t < 7; ++t) q[t] = H.v(0, t - 3);
         const R fyy_r = br * interp<OH>(oh, q, 1, sign_of(br)), fyy_l = bl * interp<OH>(oh, q, 0, sign_of(bl));
-        const R Us = a.ru[c + oy(2)], Use = a.ru[c + oy(2) + ox(4)];
+        const R Us = H.ru(0, -1), Use = H.ru(1, -1);
         const R a0 = h * (Us + U0), a1 = h * (Use + U1);
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = v[c + ox(t)];
+        for (int t = 0; t < 7; ++t) q[t] = H.v(t - 3, 0);
         const R fyx0 = a0 * interp<OH>(oh, q, 0, sign_of(a0)), fyx1 = a1 * interp<OH>(oh, q, 1, sign_of(a1));
 #pragma unroll
         for (int t = 0; t < 7; ++t) q[t] = z.v[t];
@@ -738,13 +769,13 @@ __device__ __forceinline__ void rhs_level(const RhsArgs<T> &a, const RhsCol<T> &
         const R fyz0 = e0 * interp<OV>(ov, q, 0, sign_of(e0)) * not_bot;
         const R fyz1 = e1 * interp<OV>(ov, q, 1, sign_of(e1)) * not_top;
         const R adv = (fyx1 - fyx0) * idx + (fyy_r - fyy_l) * idy + (fyz1 - fyz0) * idz;
-        R pgf = (z.pp - (R)a.pp[c + oy(2)]) * idy;
-        if constexpr (kMoist) pgf = pgf / (h * ((R)a.qf[c + oy(2)] + z.qf));
-        const R rho_f = h * (full_in(a.rho, c + oy(2), r0k) + rc);
+        R pgf = (z.pp - (R)H.pp(0, -1)) * idy;
+        if constexpr (kMoist) pgf = pgf / (h * ((R)H.qf(0, -1) + z.qf));
+        const R rho_f = h * (full_v<T>(H.rho(0, -1), r0k) + rc);
         const R ubar = q4 * (Us + Use + U0 + U1);
         R r = -adv - pgf - (R)a.f * (ubar - rho_f * (R)a.Ug);
         if constexpr (kVisc)
-            r -= ((R)a.t12[c + ox(4)] - (R)a.t12[c]) * idx + ((R)a.t22[c] - (R)a.t22[c + oy(2)]) * idy +
+            r -= ((R)H.t12(1, 0) - (R)H.t12(0, 0)) * idx + ((R)H.t22(0, 0) - (R)H.t22(0, -1)) * idy +
                  (z.t23p - z.t23) * idz;
         out_v = r;
     }
@@ -755,13 +786,12 @@ __device__ __forceinline__ void rhs_level(const RhsArgs<T> &a, const RhsCol<T> &
     {
         const R idzf = (R)a.idzf[k];
         const R a0 = h * (z.Um + U0), a1 = h * (z.U1m + U1);
-        const T *w = a.w;
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = w[c + ox(t)];
+        for (int t = 0; t < 7; ++t) q[t] = H.w(t - 3, 0);
         const R fzx0 = a0 * interp<OH>(oh, q, 0, sign_of(a0)), fzx1 = a1 * interp<OH>(oh, q, 1, sign_of(a1));
         const R b0 = h * (z.Vm + V0), b1 = h * (z.V1m + V1);
 #pragma unroll
-        for (int t = 0; t < 7; ++t) q[t] = w[c + oy(t)];
+        for (int t = 0; t < 7; ++t) q[t] = H.w(0, t - 3);
         const R fzy0 = b0 * interp<OH>(oh, q, 0, sign_of(b0)), fzy1 = b1 * interp<OH>(oh, q, 1, sign_of(b1));
         const R eu = h * (W0 + W1), ed = h * (z.Wm + W0);
 #pragma unroll
@@ -791,7 +821,7 @@ __device__ __forceinline__ void rhs_level(const RhsArgs<T> &a, const RhsCol<T> &
             r = -adv - pgf + buoy;
         }
         if constexpr (kVisc)
-            r -= ((R)a.t13[c + ox(4)] - z.t13) * idx + ((R)a.t23[c + oy(4)] - z.t23) * idy + (z.t33 - z.t33m) * idzf;
+            r -= ((R)H.t13(1, 0) - z.t13) * idx + ((R)H.t23(0, 1) - z.t23) * idy + (z.t33 - z.t33m) * idzf;
         out_w = k > 0 ? r : R(0);
     }
     // tendencies are read by later launches only: streaming stores
@@ -821,52 +851,254 @@ __device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
     for (int t = 0; t < 7; ++t) rhs_window_load<T, kNear>(a, z, col, t, k + t - 3);
     rhs_carry_load<T, kVisc, kEq>(a, z, col, k, oxm, oxp, oym, oyp);
     rhs_level_load<T, kVisc, kEq>(a, z, c, k, oxm, oxp, oym, oyp);
-    rhs_level<T, OH, OV, kNear, kVisc, kEq>(a, z, i, j, k, c);
+    rhs_level<T, OH, OV, kNear, kVisc, kEq>(a, z, GlobalNbr<T, kNear>{a, i, j, c}, k, c);
 }
 
-// One thread per column of a tile, marching up through a chunk of a.kch
-// levels: each value of the thread's own column is loaded once (the windows'
-// three levels below and above the chunk once more) and carried in
-// registers; the horizontal neighbours of a level are read while the
-// neighbouring tiles work on the same levels, from the caches.
-template <typename T, int OH, int OV, bool kVisc, int kEq>
-__device__ __forceinline__ void k_rhs_march_body(RhsArgs<T> a, VBlock vb)
+// ---------------------------------------------------------------------------
+// z-marching tendency kernel with the horizontal neighbours staged in LDS
+// ---------------------------------------------------------------------------
+// A block owns a 64 x 4 tile of columns and marches up a chunk of levels.  Per
+// level it reads the planes of the tile with their halos from memory into
+// LDS -- theta, u, v, w with three cells on each side, the other fields with
+// one -- and then computes every cell of the level from LDS: the compute
+// phase issues no memory loads, and the other block on the compute unit
+// loads while this one computes.  Face fields (rw, tau_13, tau_23) and the
+// heat diffusivity are kept for two faces (levels) in a ring of two slots;
+// the vertical stencils of the thread's own column stay in registers.
+constexpr int kLX = 64, kLY = 4;                        // tile
+constexpr int kBW = kLX + 6, kBH = kLY + 6;             // planes with 3-cell halos
+constexpr int kBN = kBW * kBH;                          // 700
+constexpr int kSW = kLX + 2, kSH = kLY + 2;             // planes with 1-cell halos
+constexpr int kSN = kSW * kSH;                          // 396
+constexpr int kBLoads = (kBN + 255) / 256, kSLoads = (kSN + 255) / 256;
+
+// plane indices
+constexpr int kPlRu = 0, kPlRv = 1, kPlRho = 2, kPlPp = 3, kPlT11 = 4, kPlT22 = 5, kPlT12 = 6;
+template <bool kVisc>
+constexpr int kPlQf = kVisc ? 7 : 4;
+template <bool kVisc, bool kMoist>
+constexpr int kNSmall = 4 + (kVisc ? 3 : 0) + (kMoist ? 1 : 0);
+constexpr int kRgRw = 0, kRgT13 = 1, kRgT23 = 2, kRgKap = 3;
+template <bool kVisc>
+constexpr int kNRing = kVisc ? 4 : 1;
+template <typename T, bool kVisc, bool kMoist>
+constexpr size_t kLdsBytes = sizeof(T) * (4 * kBN + kNSmall<kVisc, kMoist> * kSN + 2 * kNRing<kVisc> * kSN);
+
+// Neighbours from the LDS planes: b = the big planes (theta, u, v, w), s = the
+// small ones, r0 = the ring slot of level (face) k, p3 and p1 the thread's
+// centre in the two plane shapes.
+template <typename T, bool kVisc>
+struct LdsNbr {
+    const T *b, *s, *r0;
+    int p3, p1;
+    __device__ __forceinline__ T big(int f, int dx, int dy) const { return b[f * kBN + p3 + dy * kBW + dx]; }
+    __device__ __forceinline__ T sml(int f, int dx, int dy) const { return s[f * kSN + p1 + dy * kSW + dx]; }
+    __device__ __forceinline__ T rng(int f, int dx, int dy) const { return r0[f * kSN + p1 + dy * kSW + dx]; }
+    __device__ __forceinline__ T th(int dx, int dy) const { return big(0, dx, dy); }
+    __device__ __forceinline__ T u(int dx, int dy) const { return big(1, dx, dy); }
+    __device__ __forceinline__ T v(int dx, int dy) const { return big(2, dx, dy); }
+    __device__ __forceinline__ T w(int dx, int dy) const { return big(3, dx, dy); }
+    __device__ __forceinline__ T ru(int dx, int dy) const { return sml(kPlRu, dx, dy); }
+    __device__ __forceinline__ T rv(int dx, int dy) const { return sml(kPlRv, dx, dy); }
+    __device__ __forceinline__ T rho(int dx, int dy) const { return sml(kPlRho, dx, dy); }
+    __device__ __forceinline__ T pp(int dx, int dy) const { return sml(kPlPp, dx, dy); }
+    __device__ __forceinline__ T qf(int dx, int dy) const { return sml(kPlQf<kVisc>, dx, dy); }
+    __device__ __forceinline__ T t11(int dx, int dy) const { return sml(kPlT11, dx, dy); }
+    __device__ __forceinline__ T t22(int dx, int dy) const { return sml(kPlT22, dx, dy); }
+    __device__ __forceinline__ T t12(int dx, int dy) const { return sml(kPlT12, dx, dy); }
+    __device__ __forceinline__ T kap(int dx, int dy) const { return rng(kRgKap, dx, dy); }
+    __device__ __forceinline__ T t13(int dx, int dy) const { return rng(kRgT13, dx, dy); }
+    __device__ __forceinline__ T t23(int dx, int dy) const { return rng(kRgT23, dx, dy); }
+};
+
+// offset within a level of plane element e of a plane of width pw whose
+// corner is (x0, y0): periodic in x and y (any number of wraps)
+__device__ __forceinline__ int plane_off(const Dims &d, int e, int pw, int x0, int y0)
 {
+    const int gx = x0 + e % pw, gy = y0 + e / pw;
+    const int wx = ((gx % d.nx) + d.nx) % d.nx, wy = ((gy % d.ny) + d.ny) % d.ny;
+    return wy * d.nx + wx;
+}
+
+template <typename T, int OH, int OV, bool kVisc, int kEq>
+__device__ __forceinline__ void k_rhs_lds_body(const RhsArgs<T> &a, VBlock vb, T *lds)
+{
+    constexpr bool kMoist = kEq == kMoistEq;
+    constexpr int NS = kNSmall<kVisc, kMoist>, NR = kNRing<kVisc>;
     const Dims &d = a.d;
-    const TileIdx tc = tile_cell(vb, a.ntx, a.nty);
-    const int i = tc.i, j = tc.j;
-    if (i >= d.nx || j >= d.ny) return;
     const int nz = d.nz, P = d.nxy;
+    const TileIdx tc = tile_cell(vb, a.ntx, a.nty);  // blockDim = (64, 4)
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kLX + tx;
+    const int i = tc.i, j = tc.j, i0 = i - tx, j0 = j - ty;
+    const bool active = i < d.nx && j < d.ny;
     const int k0 = tc.k * a.kch, k1 = min(k0 + a.kch, nz);
-    const int col = j * d.nx + i;
-    const int oxm = rhs_wrap<true>(i - 1, d.nx) - i, oxp = rhs_wrap<true>(i + 1, d.nx) - i;
-    const int oym = (rhs_wrap<true>(j - 1, d.ny) - j) * d.nx, oyp = (rhs_wrap<true>(j + 1, d.ny) - j) * d.nx;
-    RhsCol<T> z{};
+    T *big = lds, *sml = lds + 4 * kBN, *ring = sml + NS * kSN;
+    // plane elements this thread loads, as offsets within a level (the same
+    // on every level)
+    int ob[kBLoads], os[kSLoads];
 #pragma unroll
-    for (int t = 0; t < 6; ++t) rhs_window_load<T, true>(a, z, col, t, k0 + t - 3);
-    rhs_carry_load<T, kVisc, kEq>(a, z, col, k0, oxm, oxp, oym, oyp);
+    for (int r = 0; r < kBLoads; ++r) ob[r] = tid + 256 * r < kBN ? plane_off(d, tid + 256 * r, kBW, i0 - 3, j0 - 3) : 0;
+#pragma unroll
+    for (int r = 0; r < kSLoads; ++r) os[r] = tid + 256 * r < kSN ? plane_off(d, tid + 256 * r, kSW, i0 - 1, j0 - 1) : 0;
+    const T *const bsrc[4] = {a.th, a.u, a.v, a.w};
+    const T *ssrc[NS];
+    ssrc[kPlRu] = a.ru;
+    ssrc[kPlRv] = a.rv;
+    ssrc[kPlRho] = a.rho;
+    ssrc[kPlPp] = a.pp;
+    if constexpr (kVisc) {
+        ssrc[kPlT11] = a.t11;
+        ssrc[kPlT22] = a.t22;
+        ssrc[kPlT12] = a.t12;
+    }
+    if constexpr (kMoist) ssrc[kPlQf<kVisc>] = a.qf;
+    const T *rsrc[NR];
+    rsrc[kRgRw] = a.rw;
+    if constexpr (kVisc) {
+        rsrc[kRgT13] = a.t13;
+        rsrc[kRgT23] = a.t23;
+        rsrc[kRgKap] = a.kap;
+    }
+    // ring slot s: the planes of face (level) l; the diffusivity of level
+    // min(l, nz - 1)
+    auto load_ring = [&](T (&v)[NR][kSLoads], int l) {
+#pragma unroll
+        for (int f = 0; f < NR; ++f) {
+            const int L = (kVisc && f == kRgKap) ? min(l, nz - 1) : l;
+#pragma unroll
+            for (int r = 0; r < kSLoads; ++r) v[f][r] = rsrc[f][L * P + os[r]];
+        }
+    };
+    auto store_ring = [&](const T (&v)[NR][kSLoads], int l) {
+        T *dst = ring + (l & 1) * NR * kSN;
+#pragma unroll
+        for (int f = 0; f < NR; ++f)
+#pragma unroll
+            for (int r = 0; r < kSLoads; ++r)
+                if (tid + 256 * r < kSN) dst[f * kSN + tid + 256 * r] = v[f][r];
+    };
+    const int col = j * d.nx + i;
+    const int oxp = rhs_wrap<true>(i + 1, d.nx) - i, oyp = (rhs_wrap<true>(j + 1, d.ny) - j) * d.nx;
+    RhsCol<T> z{};
+    // the start of the chunk: windows of levels k0-3 .. k0+2 and the values of
+    // level k0-1 (own column), the ring slot of face k0
+    if (active) {
+#pragma unroll
+        for (int t = 0; t < 6; ++t) rhs_window_load<T, true>(a, z, col, t, k0 + t - 3);
+        const int cm = col + (k0 > 0 ? k0 - 1 : 0) * P;
+        z.Um = a.ru[cm];
+        z.U1m = a.ru[cm + oxp];
+        z.Vm = a.rv[cm];
+        z.V1m = a.rv[cm + oyp];
+        z.Wm = a.rw[cm];
+        z.rhom = a.rho[cm];
+        z.ppm = a.pp[cm];
+        if constexpr (kMoist) {
+            z.qfm = a.qf[cm];
+            z.bmm = a.bm[cm];
+        }
+        if constexpr (kVisc) {
+            z.t33m = a.t33[cm];
+            z.kb = a.kap[cm];
+        }
+    }
+    {
+        T v[NR][kSLoads];
+        load_ring(v, k0);
+        store_ring(v, k0);
+    }
+    const int p3 = (ty + 3) * kBW + tx + 3, p1 = (ty + 1) * kSW + tx + 1;
+    // Level k's planes, the ring slot of face (level) k+1 and the own column's
+    // values that no plane holds, read into registers one level ahead: the
+    // loads of level k+1 are in flight while level k is computed from LDS
+    // (whose phase issues no memory loads of its own).
+    T vb_[4][kBLoads], vs[NS][kSLoads], vr[NR][kSLoads];
+    T w6th = 0, w6u = 0, w6v = 0, w6w = 0, t33 = 0, bm = 0;
+    auto load_level = [&](int k) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int r = 0; r < kBLoads; ++r) vb_[f][r] = bsrc[f][k * P + ob[r]];
+#pragma unroll
+        for (int f = 0; f < NS; ++f)
+#pragma unroll
+            for (int r = 0; r < kSLoads; ++r) vs[f][r] = ssrc[f][k * P + os[r]];
+        load_ring(vr, k + 1);
+        if (active) {
+            RhsCol<T> w6{};
+            rhs_window_load<T, true>(a, w6, col, 6, k + 3);
+            w6th = w6.th[6];
+            w6u = w6.u[6];
+            w6v = w6.v[6];
+            w6w = w6.w[6];
+            if constexpr (kVisc) t33 = a.t33[col + k * P];
+            if constexpr (kMoist) bm = a.bm[col + k * P];
+        }
+    };
+    load_level(k0);
     for (int k = k0; k < k1; ++k) {
-        const int c = col + k * P;
-        rhs_window_load<T, true>(a, z, col, 6, k + 3);
-        rhs_level_load<T, kVisc, kEq>(a, z, c, k, oxm, oxp, oym, oyp);
-        rhs_level<T, OH, OV, true, kVisc, kEq>(a, z, i, j, k, c);
-        rhs_carry_up(z);
+        __syncthreads();  // level k-1 computed: its planes and slot (k+1)&1 are free
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int r = 0; r < kBLoads; ++r)
+                if (tid + 256 * r < kBN) big[f * kBN + tid + 256 * r] = vb_[f][r];
+#pragma unroll
+        for (int f = 0; f < NS; ++f)
+#pragma unroll
+            for (int r = 0; r < kSLoads; ++r)
+                if (tid + 256 * r < kSN) sml[f * kSN + tid + 256 * r] = vs[f][r];
+        store_ring(vr, k + 1);
+        z.th[6] = w6th;
+        z.u[6] = w6u;
+        z.v[6] = w6v;
+        z.w[6] = w6w;
+        z.t33 = t33;
+        z.bm = bm;
+        __syncthreads();
+        if (k + 1 < k1) load_level(k + 1);
+        if (active) {
+            const LdsNbr<T, kVisc> H{big, sml, ring + (k & 1) * NR * kSN, p3, p1};
+            const T *r1 = ring + ((k + 1) & 1) * NR * kSN;
+            z.U0 = H.ru(0, 0);
+            z.U1 = H.ru(1, 0);
+            z.V0 = H.rv(0, 0);
+            z.V1 = H.rv(0, 1);
+            z.W0 = H.rng(kRgRw, 0, 0);
+            z.Wx0 = H.rng(kRgRw, -1, 0);
+            z.Wy0 = H.rng(kRgRw, 0, -1);
+            z.W1 = r1[kRgRw * kSN + p1];
+            z.Wx1 = r1[kRgRw * kSN + p1 - 1];
+            z.Wy1 = r1[kRgRw * kSN + p1 - kSW];
+            z.rho = H.rho(0, 0);
+            z.pp = H.pp(0, 0);
+            if constexpr (kMoist) z.qf = H.qf(0, 0);
+            if constexpr (kVisc) {
+                z.t13 = H.t13(0, 0);
+                z.t23 = H.t23(0, 0);
+                z.t13p = r1[kRgT13 * kSN + p1];
+                z.t23p = r1[kRgT23 * kSN + p1];
+                z.kc = H.kap(0, 0);
+                z.ka = r1[kRgKap * kSN + p1];
+            }
+            rhs_level<T, OH, OV, true, kVisc, kEq>(a, z, H, k, col + k * P);
+            rhs_carry_up(z);
+        }
     }
 }
-
-// Wavefronts per SIMD of the z-marching kernel (FP64): its registers also
-// hold the four seven-level windows and the carried values.
-constexpr int kMarchWaves = 2;
 
 template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kRhsWaves<T>, kRhsWaves<T>))) void k_rhs(RhsArgs<T> a)
 {
     k_rhs_body<T, OH, OV, kNear, kVisc, kEq>(a, hw_block());
 }
+// two blocks per compute unit (the LDS of one FP64 viscous block is 68 KiB,
+// its registers 255 per lane with the loads of the next level in flight)
 template <typename T, int OH, int OV, bool kVisc, int kEq>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMarchWaves, kMarchWaves))) void k_rhs_march(RhsArgs<T> a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_rhs_lds(RhsArgs<T> a)
 {
-    k_rhs_march_body<T, OH, OV, kVisc, kEq>(a, hw_block());
+    extern __shared__ __align__(16) unsigned char rhs_lds_raw[];
+    k_rhs_lds_body<T, OH, OV, kVisc, kEq>(a, hw_block(), (T *)rhs_lds_raw);
 }
 template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kRhsWaves<T>, kRhsWaves<T>))) void k_rhs_batch(const RhsArgs<T> *args, BatchMap bm)
@@ -884,58 +1116,68 @@ namespace {
 // Moist dynamics: 3rd order (the moist workload's) and the general instances.
 // The anelastic set (FP64 only): orders 2, 3 and 5 and the general instances.
 // FP64 on domains at least 3 cells wide and 3 levels high takes the
-// z-marching kernel (grdm: tiles x chunks of a.kch levels); FP32, narrower
-// domains and ensemble members take the single-level kernel (grd: tiles x
-// levels).  Both give the same results bit for bit.  In FP32 the
-// single-level kernel's re-reads fit the caches (1.06 of its compulsory
-// bytes at 256 x 256 x 128) and its four wavefronts per SIMD make it the
-// faster one (284 against 315 us per launch); inside the ensemble's graphs
-// the z-marching kernel is not used.
+// LDS-staged z-marching kernel (al: its 64 x 4 tiles and chunks of al.kch
+// levels, grid grdl); FP32, narrower domains and ensemble members take the
+// single-level kernel (a, grd: tiles x levels).  Both give the same results
+// bit for bit.  At 256 x 256 x 128 the FP64 single-level kernel re-reads its
+// stencil operands from HBM (2.85 times its compulsory bytes: its FP64
+// footprint outgrows the caches) and takes 704 us per launch, the z-march
+// 467 us; in FP32 the single-level kernel's operands fit the caches (1.06
+// times) and its four wavefronts per SIMD make it the faster one (290 us
+// against 324).  Inside the ensemble's graphs the z-marching kernel is not
+// used.
 template <typename T, int OH, int OV, bool kNear, bool kVisc, int kEq>
-void rhs_one(erf_ctx *cx, const RhsArgs<T> &a, dim3 grd, dim3 grdm, dim3 blk)
+hipError_t rhs_one(erf_ctx *cx, const RhsArgs<T> &a, const RhsArgs<T> &al, dim3 grd, dim3 grdl, dim3 blk)
 {
     if constexpr (kNear && sizeof(T) == 8) {
         if (!cx->member && !cx->rec) {
-            void *argv[] = {(void *)&a};
-            (void)hipLaunchKernel((const void *)k_rhs_march<T, OH, OV, kVisc, kEq>, grdm, blk, argv, 0, cx->stream);
-            return;
+            constexpr size_t lds = kLdsBytes<T, kVisc, kEq == kMoistEq>;
+            const void *fn = (const void *)k_rhs_lds<T, OH, OV, kVisc, kEq>;
+            if (lds > 64 * 1024) {
+                const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                if (e != hipSuccess) return e;
+            }
+            void *argv[] = {(void *)&al};
+            return hipLaunchKernel(fn, grdl, dim3(kLX, kLY, 1), argv, lds, cx->stream);
         }
     }
     run<RhsArgs<T>, k_rhs<T, OH, OV, kNear, kVisc, kEq>, k_rhs_batch<T, OH, OV, kNear, kVisc, kEq>>(cx, grd, blk, 0, a);
+    return hipSuccess;
 }
 template <typename T, bool kVisc, int kEq>
-void launch_rhs_eq(erf_ctx *cx, const RhsArgs<T> &a, dim3 grd, dim3 grdm, dim3 blk)
+hipError_t launch_rhs_eq(erf_ctx *cx, const RhsArgs<T> &a, const RhsArgs<T> &al, dim3 grd, dim3 grdl, dim3 blk)
 {
     const bool near = a.d.nx >= 3 && a.d.ny >= 3 && a.d.nz >= 3;
     if (near && a.oh == 5 && a.ov == 5)
-        rhs_one<T, 5, 5, true, kVisc, kEq>(cx, a, grd, grdm, blk);
+        return rhs_one<T, 5, 5, true, kVisc, kEq>(cx, a, al, grd, grdl, blk);
     else if (near && a.oh == 3 && a.ov == 3)
-        rhs_one<T, 3, 3, true, kVisc, kEq>(cx, a, grd, grdm, blk);
+        return rhs_one<T, 3, 3, true, kVisc, kEq>(cx, a, al, grd, grdl, blk);
     else if (near && a.oh == 2 && a.ov == 2)
-        rhs_one<T, 2, 2, true, kVisc, kEq>(cx, a, grd, grdm, blk);
+        return rhs_one<T, 2, 2, true, kVisc, kEq>(cx, a, al, grd, grdl, blk);
     else if (near)
-        rhs_one<T, 0, 0, true, kVisc, kEq>(cx, a, grd, grdm, blk);
+        return rhs_one<T, 0, 0, true, kVisc, kEq>(cx, a, al, grd, grdl, blk);
     else
-        rhs_one<T, 0, 0, false, kVisc, kEq>(cx, a, grd, grdm, blk);
+        return rhs_one<T, 0, 0, false, kVisc, kEq>(cx, a, al, grd, grdl, blk);
 }
 template <typename T, bool kVisc>
-void launch_rhs(erf_ctx *cx, const RhsArgs<T> &a, bool moist, dim3 grd, dim3 grdm, dim3 blk)
+hipError_t launch_rhs(erf_ctx *cx, const RhsArgs<T> &a, const RhsArgs<T> &al, bool moist, dim3 grd, dim3 grdl,
+                      dim3 blk)
 {
     const bool near = a.d.nx >= 3 && a.d.ny >= 3 && a.d.nz >= 3;
     if (moist) {
         if (near && a.oh == 3 && a.ov == 3)
-            rhs_one<T, 3, 3, true, kVisc, kMoistEq>(cx, a, grd, grdm, blk);
+            return rhs_one<T, 3, 3, true, kVisc, kMoistEq>(cx, a, al, grd, grdl, blk);
         else if (near)
-            rhs_one<T, 0, 0, true, kVisc, kMoistEq>(cx, a, grd, grdm, blk);
+            return rhs_one<T, 0, 0, true, kVisc, kMoistEq>(cx, a, al, grd, grdl, blk);
         else
-            rhs_one<T, 0, 0, false, kVisc, kMoistEq>(cx, a, grd, grdm, blk);
+            return rhs_one<T, 0, 0, false, kVisc, kMoistEq>(cx, a, al, grd, grdl, blk);
     } else if constexpr (std::is_same_v<T, double>) {
         if (a.anel)
-            launch_rhs_eq<T, kVisc, kAnelEq>(cx, a, grd, grdm, blk);
+            return launch_rhs_eq<T, kVisc, kAnelEq>(cx, a, al, grd, grdl, blk);
         else
-            launch_rhs_eq<T, kVisc, kDryEq>(cx, a, grd, grdm, blk);
+            return launch_rhs_eq<T, kVisc, kDryEq>(cx, a, al, grd, grdl, blk);
     } else {
-        launch_rhs_eq<T, kVisc, kDryEq>(cx, a, grd, grdm, blk);
+        return launch_rhs_eq<T, kVisc, kDryEq>(cx, a, al, grd, grdl, blk);
     }
 }
 
@@ -1013,13 +1255,18 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], const void *rq, void 
     const int tx = tile_width(d.nx, d.ny, 256), ty = 256 / tx;
     a.ntx = (d.nx + tx - 1) / tx;
     a.nty = (d.ny + ty - 1) / ty;
-    // the z-march: levels in chunks, enough of them for about two blocks per
-    // compute unit, at least 16 levels each (the windows reload 6 levels per
-    // chunk)
     const int tiles = a.ntx * a.nty;
-    const int nch = std::max(1, std::min((2 * kNumCUs + tiles - 1) / tiles, d.nz / 16));
-    a.kch = (d.nz + nch - 1) / nch;
-    dim3 blk(tx, ty, 1), grd(tiles * d.nz), grdw(tiles * (d.nz + 1)), grdm(tiles * ((d.nz + a.kch - 1) / a.kch));
+    dim3 blk(tx, ty, 1), grd(tiles * d.nz), grdw(tiles * (d.nz + 1));
+    // the z-marching tendency kernel: 64 x 4 tiles, levels in chunks, enough
+    // of them for about two blocks per compute unit, at least 16 levels each
+    // (the windows reload 6 levels per chunk)
+    RhsArgs<T> al = a;
+    al.ntx = (d.nx + kLX - 1) / kLX;
+    al.nty = (d.ny + kLY - 1) / kLY;
+    const int ltiles = al.ntx * al.nty;
+    const int nch = std::max(1, std::min((2 * kNumCUs + ltiles - 1) / ltiles, d.nz / 16));
+    al.kch = (d.nz + nch - 1) / nch;
+    const dim3 grdl(ltiles * ((d.nz + al.kch - 1) / al.kch));
     timing_start(cx, K_PREP);
     if (moist)
         run<RhsArgs<T>, k_prep<T, true>, k_prep_batch<T, true>>(cx, grd, blk, 0, a);
@@ -1051,11 +1298,10 @@ hipError_t slow_rhs_t(erf_ctx *cx, const void *const S[5], const void *rq, void 
         timing_stop(cx, K_STRESS);
     }
     timing_start(cx, K_RHS);
-    if (a.visc)
-        launch_rhs<T, true>(cx, a, moist, grd, grdm, blk);
-    else
-        launch_rhs<T, false>(cx, a, moist, grd, grdm, blk);
+    const hipError_t er =
+        a.visc ? launch_rhs<T, true>(cx, a, al, moist, grd, grdl, blk) : launch_rhs<T, false>(cx, a, al, moist, grd, grdl, blk);
     timing_stop(cx, K_RHS);
+    if (er != hipSuccess) return er;
     if (mlp) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
