@@ -78,9 +78,12 @@ def _err(got, ref, fields=("rt", "ru", "rv", "rw")):
     return {f: float(np.max(np.abs(got[f] - ref[f])) / max(np.max(np.abs(ref[f])), 1e-300)) for f in fields}
 
 
-def test_anelastic_slow_rhs_matches_oracle():
+@pytest.mark.parametrize("shape", [(64, 32, 23), (16, 8, 40)])
+def test_anelastic_slow_rhs_matches_oracle(shape):
+    """(16, 8, 40): two chunks of levels in the z-marching FP64 tendency kernel"""
     import torch
-    cfg = _cfg()
+    nx, ny, nz = shape
+    cfg = _cfg(nx=nx, ny=ny, nz=nz, dz=W.stretched_dz(nz, 30.0, 200.0, 2500.0 * nz / 23))
     o, s, th0, b = _sides(cfg)
     S = _state(cfg, o, b, th0, 100)
     p = W.uniform_noise(7, (cfg.nz, cfg.ny, cfg.nx), 30.0)
@@ -89,9 +92,18 @@ def test_anelastic_slow_rhs_matches_oracle():
     ref = o.slow_rhs(S)
     got = s.to_numpy(s.slow_rhs(s.to_device(S)))
     e = _err(got, ref)
-    _say("anelastic slow rhs:", {k: f"{v:.2e}" for k, v in e.items()})
+    # With the projected (divergence-free) winds, R_Theta is the small
+    # difference of face fluxes rho u theta / delta that are hundreds of times
+    # larger: each side rounds a sum of at most 8 such terms, so the two may
+    # differ by up to 16 eps times the flux scale (relative to max |R_Theta|).
+    theta = S["rt"] / S["rho"]
+    flux = np.max(theta) * (np.max(np.abs(S["ru"])) / cfg.dx + np.max(np.abs(S["rv"])) / cfg.dy
+                            + np.max(np.abs(S["rw"])) / np.min(cfg.dz))
+    bound = {k: CALL_TOL for k in e}
+    bound["rt"] = max(CALL_TOL, 16 * np.finfo(float).eps * flux / np.max(np.abs(ref["rt"])))
+    _say("anelastic slow rhs:", {k: f"{v:.2e}/{bound[k]:.1e}" for k, v in e.items()})
     for k, v in e.items():
-        assert v <= CALL_TOL, (k, v)
+        assert v <= bound[k], (k, v, bound[k])
     # the perturbation pressure round trip is exact
     assert np.array_equal(s.anelastic_pressure().cpu().numpy(), p)
 

@@ -112,6 +112,9 @@ MOIST_CASES = {
     "o53_visc": dict(adv_order_h=5, adv_order_v=5, nu_m=40.0),
     # narrower than the stencil in x: the general wrap path
     "narrow": dict(nx=2, ny=9),
+    # 40 levels in two chunks of the z-marching FP64 tendency kernel, with
+    # viscous stresses: the second chunk starts from the moist values below it
+    "tall_visc": dict(nx=20, ny=9, nz=40, dz=W.stretched_dz(40, 50.0, 500.0, 8000.0), nu_m=40.0),
 }
 
 

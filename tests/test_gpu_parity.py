@@ -128,6 +128,9 @@ CASES = {
                                           220.0]), adv_order_h=3, adv_order_v=5, sgs=1, Cs=0.15),
     "two_d": dict(name="bubble2d", nx=70, ny=1, nz=24, dz=W.uniform_dz(24, 125.0), dx=125.0),
     "tall": dict(nx=9, ny=6, nz=140, dz=W.uniform_dz(140, 50.0), adv_order_h=3, adv_order_v=3),
+    # chunks of levels in the z-marching FP64 tendency kernel: 8 chunks of 18
+    # levels, each started from the levels below it, with the viscous terms
+    "tall_smag": dict(nx=9, ny=6, nz=140, dz=W.uniform_dz(140, 50.0), sgs=1, Cs=0.15, surf_heat_flux=0.1),
     # edge sizes: the fewest levels, the most levels a substep block holds, and
     # a single column (every horizontal neighbour is the cell itself)
     "min_nz": dict(nz=2, dz=W.uniform_dz(2, 100.0), sgs=1, Cs=0.15),

@@ -93,10 +93,12 @@ def _errs(got, ref, b, fields):
     return out
 
 
-@pytest.mark.parametrize("case", ["tke_most", "tke_slip", "smag_most", "tke_stable"])
+@pytest.mark.parametrize("case", ["tke_most", "tke_slip", "smag_most", "tke_stable", "tke_tall"])
 def test_slow_rhs_and_tke_source_match_oracle(case):
+    # tke_tall: 40 levels, two chunks of the z-marching FP64 tendency kernel
     kw = {"tke_most": {}, "tke_slip": dict(most_z0=0.0), "smag_most": dict(sgs=1, n_scalars=0),
-          "tke_stable": dict(surf_heat_flux=-0.02)}[case]
+          "tke_stable": dict(surf_heat_flux=-0.02),
+          "tke_tall": dict(nx=20, ny=9, nz=40, dz=W.stretched_dz(40, 10.0, 40.0, 1000.0))}[case]
     cfg = _cfg(**kw)
     o, s, th0, b = _sides(cfg)
     S = _state(cfg, b, th0, 100, e0=0.2 if case != "tke_stable" else 2e-3)
