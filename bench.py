@@ -56,6 +56,10 @@ KERNEL_VALUES = {
     "mut": lambda sgs: (4 + 1, 0),
     # u, v, w, rho, mu_t read; 6 stresses and the diffusivity written
     "stress": lambda sgs: (5 + 7, 0),
+    # FP64 outside the Deardorff closure: mu_t evaluated in the stress pass
+    # itself (u, v, w, rho read; 6 stresses and the diffusivity written), no
+    # separate mu_t pass
+    "stress_fused": lambda sgs: (4 + 7, 0),
     # one fused substep: Theta'' (two levels), U'', V'', rho'', W'', the five
     # tendencies, theta^t, Exner and the buoyancy coefficient read, the Thomas
     # pivots read; Theta'', U'', V'', rho'', W'' written
@@ -106,6 +110,11 @@ ANEL_KERNELS = ("prep", "mut", "stress", "rhs", "ssp_update", "div_fftx", "ffty"
 # tendencies read; the stage init reads the three species and writes the moist
 # Exner function and rho_d / rho_m, which the coefficients read.
 MOIST_STAGE_VALUES = {"prep": 5, "rhs": 2, "stage_init": 5, "coef": 2}
+
+
+def _stress_fused(cfg) -> bool:
+    """FP64 runs with Smagorinsky evaluate mu_t inside the stress pass."""
+    return cfg.prec == "fp64" and cfg.sgs == 1
 
 
 def _kernel_bytes(kernel: str, sgs: int, prec: str) -> float:
@@ -433,6 +442,9 @@ def _step_values(cfg):
     ns = cfg.n_substeps
     counts = {"prep": 3, "rhs": 3, "mut": 3 * sgs, "stress": 3 * sgs, "stage_init": 3, "coef": 3,
               "substep": 1 + ns // 2 + ns, "finalize": 3 if cfg.n_scalars else 0}
+    if _stress_fused(cfg):
+        counts["mut"] = counts["stress"] = 0
+        counts["stress_fused"] = 3
     bulk = f64 = 0
     for k, n in counts.items():
         b, f = KERNEL_VALUES[k](sgs)
