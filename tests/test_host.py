@@ -29,11 +29,14 @@ def test_bench_constants():
     assert bench._kernel_bytes("substep", 1, "fp64") == 20 * 8
     assert bench._kernel_bytes("substep", 1, "fp32") == 19 * 4 + 1 * 8
     # whole step of the 14-substep boundary layer: 22 substeps of 20 values,
-    # 5 more in each stage's last, 48 + 17 + 5 per stage; the first stage,
-    # with S'' = 0 on entry, moves 13 + 6 values fewer
+    # 5 more in each stage's last, 48 + 17 + 5 per stage (slow right-hand side,
+    # stage init, coefficients); the first stage, with S'' = 0 on entry, moves
+    # 13 + 6 values fewer.  In FP64 the stress pass evaluates mu_t itself: the
+    # slow right-hand side is then 10 + 11 + 21 = 42 values, not 10 + 5 + 12 + 21
     cfg = bench._cfg("cbl")
     bulk, f64 = bench._step_values(cfg)
-    assert bulk + f64 == 22 * 20 + 3 * 5 + 3 * (48 + 17 + 5) - 19
+    assert bulk + f64 == 22 * 20 + 3 * 5 + 3 * (42 + 17 + 5) - 19
+    assert sum(bench._step_values(cfg.replace(prec="fp32"))) == 22 * 20 + 3 * 5 + 3 * (48 + 17 + 5) - 19
     assert bench._one_pass_values(cfg) == 13 * 5 + 6 + 22 * (3 * 5 + 3)
     # the deep workload (3 WENO5 tracers, 13 substeps, no SGS): prep 3 x 10,
     # tendencies 3 x 14, stage init 3 x 17 - 13, coefficients 3 x 5, substeps
