@@ -182,7 +182,7 @@ def run_gpu(cfg: W.Config, steps: int, warmup: int):
     for k in (list(KERNEL_VALUES) + (list(SCALAR_VALUES) if cfg.n_scalars else []) +
               (list(MICRO_VALUES) if getattr(cfg, "microphysics", 0) else []) +
               (["tke"] if cfg.sgs == 3 else []) + (["most"] if getattr(cfg, "most_z0", 0.0) > 0 else [])):
-        if k == "mut" and not cfg.sgs:
+        if (k == "mut" and not cfg.sgs) or k == "stress_fused":  # (an accounting entry, timed as "stress")
             continue
         _, (ms, n) = _time_steps(s, S, 1, torch, kernel=k)
         if n:
