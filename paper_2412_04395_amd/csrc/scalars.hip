@@ -61,6 +61,17 @@ __device__ __forceinline__ R wdiv(R a, R b)
         return a / b;
 }
 
+// a * b + c: one fused operation (one rounding) in float, the product and the
+// sum as written (two roundings) in double
+template <typename R>
+__device__ __forceinline__ R mad(R a, R b, R c)
+{
+    if constexpr (std::is_same<R, float>::value)
+        return __builtin_fmaf(a, b, c);
+    else
+        return a * b + c;
+}
+
 // WENO5-JS face value; v2 is the upwind cell, candidate stencils of three cells
 // with values p_k, smoothness indicators beta_k and weights d_k / (eps +
 // beta_k)^2, d = (0.1, 0.6, 0.3), normalised.  Written over one common
@@ -68,47 +79,72 @@ __device__ __forceinline__ R wdiv(R a, R b)
 // beta)^2 and the 1/6 of the p_k moves into the final quotient, so a face
 // takes one division instead of seven (wdiv); equal to the three-weight form
 // up to rounding.  In float the product of two (eps + beta)^2 stays above 1e-24 and
-// below 1e30 for the mixing ratios and stencil jumps of the workloads.
+// below 1e30 for the mixing ratios and stencil jumps of the workloads (times
+// 256 with the float form's 4 beta and 4 eps: still below 3e32).
+// The sums of products are written as mad chains: fused in float; in double
+// the same operations and roundings as the sums written out (an addition's
+// operands commute exactly, and x + (-a) b equals x - a b).
 template <typename R>
 __device__ __forceinline__ R weno5_face(R v0, R v1, R v2, R v3, R v4)
 {
+    if constexpr (std::is_same<R, float>::value) {
+        // float: 4 beta_k = (13/3) s_k^2 + t_k^2 against 4 eps, and the weights
+        // without the common factor 0.1: both scale every weight alike, which
+        // the normalisation cancels (4 fewer operations per face)
+        const float eps4 = 4.0e-6f;
+        const float P0 = mad(11.0f, v2, mad(-7.0f, v1, 2.0f * v0));
+        const float P1 = mad(2.0f, v3, mad(5.0f, v2, -v1));
+        const float P2 = mad(5.0f, v3, 2.0f * v2) - v4;
+        const float s0 = mad(-2.0f, v1, v0) + v2, t0 = mad(3.0f, v2, mad(-4.0f, v1, v0));
+        const float s1 = mad(-2.0f, v2, v1) + v3, t1 = v1 - v3;
+        const float s2 = mad(-2.0f, v3, v2) + v4, t2 = mad(-4.0f, v3, 3.0f * v2) + v4;
+        const float b0 = mad(float(13.0 / 3.0) * s0, s0, t0 * t0);
+        const float b1 = mad(float(13.0 / 3.0) * s1, s1, t1 * t1);
+        const float b2 = mad(float(13.0 / 3.0) * s2, s2, t2 * t2);
+        const float a0 = (eps4 + b0) * (eps4 + b0), a1 = (eps4 + b1) * (eps4 + b1), a2 = (eps4 + b2) * (eps4 + b2);
+        const float w0 = a1 * a2, w1 = 6.0f * (a0 * a2), w2 = 3.0f * (a0 * a1);
+        return wdiv(mad(w2, P2, mad(w1, P1, w0 * P0)), 6.0f * (w0 + w1 + w2));
+    }
     const R eps = R(1.0e-6);
-    const R P0 = R(2) * v0 - R(7) * v1 + R(11) * v2;
-    const R P1 = -v1 + R(5) * v2 + R(2) * v3;
-    const R P2 = R(2) * v2 + R(5) * v3 - v4;
-    const R s0 = v0 - R(2) * v1 + v2, t0 = v0 - R(4) * v1 + R(3) * v2;
-    const R s1 = v1 - R(2) * v2 + v3, t1 = v1 - v3;
-    const R s2 = v2 - R(2) * v3 + v4, t2 = R(3) * v2 - R(4) * v3 + v4;
-    const R be0 = R(13.0 / 12.0) * s0 * s0 + R(0.25) * t0 * t0;
-    const R be1 = R(13.0 / 12.0) * s1 * s1 + R(0.25) * t1 * t1;
-    const R be2 = R(13.0 / 12.0) * s2 * s2 + R(0.25) * t2 * t2;
+    const R P0 = mad(R(11), v2, mad(R(-7), v1, R(2) * v0));  // 2 v0 - 7 v1 + 11 v2
+    const R P1 = mad(R(2), v3, mad(R(5), v2, -v1));           // -v1 + 5 v2 + 2 v3
+    const R P2 = mad(R(5), v3, R(2) * v2) - v4;               // 2 v2 + 5 v3 - v4
+    const R s0 = mad(R(-2), v1, v0) + v2, t0 = mad(R(3), v2, mad(R(-4), v1, v0));
+    const R s1 = mad(R(-2), v2, v1) + v3, t1 = v1 - v3;
+    const R s2 = mad(R(-2), v3, v2) + v4, t2 = mad(R(-4), v3, R(3) * v2) + v4;
+    const R be0 = mad(R(13.0 / 12.0) * s0, s0, R(0.25) * t0 * t0);
+    const R be1 = mad(R(13.0 / 12.0) * s1, s1, R(0.25) * t1 * t1);
+    const R be2 = mad(R(13.0 / 12.0) * s2, s2, R(0.25) * t2 * t2);
     const R a0 = (eps + be0) * (eps + be0), a1 = (eps + be1) * (eps + be1), a2 = (eps + be2) * (eps + be2);
     const R w0 = R(0.1) * (a1 * a2), w1 = R(0.6) * (a0 * a2), w2 = R(0.3) * (a0 * a1);
-    return wdiv(w0 * P0 + w1 * P1 + w2 * P2, R(6) * (w0 + w1 + w2));
+    return wdiv(mad(w2, P2, mad(w1, P1, w0 * P0)), R(6) * (w0 + w1 + w2));
 }
 
-// Tiles of kSX x kSY cells per block of (kSX + 1) x (kSY + 1) threads, one
-// chunk of up to kLev levels of one scalar, marched upward level by level.
-// Per level the block stages the plane of q^t over the tile and a 3-cell halo
-// in LDS (periodic wrap resolved once, at the staging), so the horizontal
-// stencils read LDS instead of gathering from memory.  Every thread evaluates
-// the x- and y-face on the low side of its cell; the last lane and the last
-// row of threads hold the cells just past the tile and only lend those faces,
-// through LDS, to their neighbours, so each interior face is evaluated once.
+// Tiles of kSX x kSY cells per block of kSX x (kSY + 1) threads (one
+// wavefront per row), one chunk of up to kLev levels of one scalar, marched
+// upward level by level.  Per level the block stages the plane of q^t over the
+// tile and a 3-cell halo in LDS (periodic wrap resolved once, at the staging),
+// so the horizontal stencils read LDS instead of gathering from memory.  The
+// threads of the first kSY rows evaluate the x- and y-face on the low side of
+// their cells.  The last row evaluates the y-faces just past the tile, and its
+// first kSY lanes the x-faces just past the tile, one per row.  The faces go
+// through LDS to the cells on both sides, so each face is evaluated once; the
+// tiles are 64 cells wide, so grids whose width is a multiple of 64 carry no
+// idle columns.
 // Vertically each owning thread keeps q of its column at k - 3 .. k + 3 in
 // registers (one new load per level) and evaluates only the face above its
 // cell; the face below is the one it evaluated one level earlier.  kWeno:
 // WENO5-JS faces, else the interpolant of the run's order.  kNear: the domain
 // is at least 3 cells wide and 3 levels high (selects instead of general
 // wraps for the column window).
-constexpr int kSX = 63, kSY = 15, kLev = 16;
-constexpr int kHX = kSX + 1 + 6, kHY = kSY + 1 + 6;  // staged plane with halo
+constexpr int kSX = 64, kSY = 15, kLev = 16;
+constexpr int kHX = kSX + 7, kHY = kSY + 1 + 6;  // staged plane with halo
 template <typename T, bool kWeno, bool kNear>
 __device__ __forceinline__ void k_scalar_body(ScalArgs<T> a, VBlock vb)
 {
     using R = T;  // arithmetic type
     __shared__ R qs[kHY][kHX];
-    __shared__ R fxs[kSY + 1][kSX + 1], fys[kSY + 1][kSX + 1];
+    __shared__ R fxs[kSY][kSX + 1], fys[kSY + 1][kSX];
     const Dims &d = a.d;
     const int lane = threadIdx.x, row = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int nx = d.nx, ny = d.ny, nz = d.nz, P = d.nxy;
@@ -116,13 +152,19 @@ __device__ __forceinline__ void k_scalar_body(ScalArgs<T> a, VBlock vb)
     const int kc = vb.z % nchunk, s = vb.z / nchunk;
     const int k0 = kc * kLev, k1 = min(k0 + kLev, nz);
     const int x0 = vb.x * kSX, y0 = vb.y * kSY;
-    // the thread's cell, wrapped periodically (the lending lane and row may lie
-    // past the domain's end); threads beyond them only stage and wait
+    // the thread's cell, wrapped periodically (the last row and the cells of a
+    // partial tile may lie past the domain's end)
     const int iu = x0 + lane, ju = y0 + row;
-    const bool lend = iu <= nx && ju <= ny;
-    const bool own = lane < kSX && row < kSY && iu < nx && ju < ny;
+    const bool own = row < kSY && iu < nx && ju < ny;
+    // the faces it evaluates where a cell of the domain needs them: in the first
+    // kSY rows the low x- and y-face of its cell; in the last row the y-face
+    // past the tile and, in lane r < kSY, the x-face past the tile in row r
+    const bool fx_need = row < kSY ? (iu <= nx && ju < ny) : (lane < kSY && x0 + kSX <= nx && y0 + lane < ny);
+    const bool fy_need = iu < nx && ju <= ny;
     const int i = iu % nx, j = ju % ny;
     const int col = j * nx + i;
+    // (last row) the cell whose low x-face is the one past the tile in row lane
+    const int xe_col = ((y0 + lane) % ny) * nx + (x0 + kSX) % nx;
     const T *q = a.q + (size_t)s * d.n;
     auto reflc = [&](int kk) {
         if constexpr (!kNear) return refl_centre(kk, nz);
@@ -165,35 +207,56 @@ __device__ __forceinline__ void k_scalar_body(ScalArgs<T> a, VBlock vb)
         for (int t = 0; t < 7; ++t) qb[t] = qz[t];
         fz_below = k0 > 0 ? Fz0 * face(qb, 1, sign_of(Fz0), a.ov) : R(0);
     }
+    // a level's memory reads (its plane elements, the own column's values and
+    // the fluxes of the faces the thread evaluates), issued one level ahead:
+    // those of level k+1 are in flight while level k is computed
+    R sv[kStage], nrq = 0, nFz1 = 0, nqn = 0, nFx = 0, nFy = 0, nsrc = 0;
+    auto load_level = [&](int k) {
+        const int pl = k * P;
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) sv[u] = soff[u] >= 0 ? q[pl + soff[u]] : R(0);
+        if (own) {
+            nrq = a.rqn[(size_t)s * d.n + pl + col];
+            nFz1 = a.Fw[col + pl + P];
+            nqn = q[col + reflc(k + 3) * P];
+            if (s == 0 && a.src) nsrc = a.src[pl + col];
+        }
+        if (fx_need) nFx = a.Fu[pl + (row < kSY ? col : xe_col)];
+        if (fy_need) nFy = a.Fv[pl + col];
+    };
+    load_level(k0);
     for (int k = k0; k < k1; ++k) {
         const int pl = k * P;
 #pragma unroll
         for (int u = 0; u < kStage; ++u)
-            if (soff[u] >= 0) (&qs[0][0])[tid + u * nthr] = q[pl + soff[u]];
-        R rq = 0, Fz1 = 0, qn = 0;
+            if (soff[u] >= 0) (&qs[0][0])[tid + u * nthr] = sv[u];
+        const R rq = nrq, Fz1 = nFz1, qn = nqn, Fx0 = nFx, Fy0 = nFy, srcv = nsrc;
         const size_t o = (size_t)s * d.n + pl + col;
-        if (own) {
-            // loads of this level issued before the barrier
-            rq = a.rqn[o];
-            Fz1 = a.Fw[col + pl + P];
-            qn = q[col + reflc(k + 3) * P];
-        }
         __syncthreads();
+        if (k + 1 < k1) load_level(k + 1);
         R fx0 = 0, fy0 = 0;
-        if (lend) {
-            R qx[7], qy[7];
+        {
+            // x: the low face of the cell, or (last row) the face past the tile
+            // in row `lane`; y: the low face of the cell (past the tile in the
+            // last row)
+            const int xr = row < kSY ? row : lane, xl = row < kSY ? lane : kSX;
+            if (fx_need) {
+                R qx[7];
 #pragma unroll
-            for (int t = 0; t < 7; ++t) {
-                qx[t] = qs[row + 3][lane + t];
-                qy[t] = qs[row + t][lane + 3];
+                for (int t = 0; t < 7; ++t) qx[t] = qs[xr + 3][xl + t];
+                fx0 = Fx0 * face(qx, 0, sign_of(Fx0), a.oh);
             }
-            const R Fx0 = a.Fu[pl + col], Fy0 = a.Fv[pl + col];
-            fx0 = Fx0 * face(qx, 0, sign_of(Fx0), a.oh);
-            fy0 = Fy0 * face(qy, 0, sign_of(Fy0), a.oh);
-            if (lane <= kSX && row <= kSY) {
+            if (fy_need) {
+                R qy[7];
+#pragma unroll
+                for (int t = 0; t < 7; ++t) qy[t] = qs[row + t][lane + 3];
+                fy0 = Fy0 * face(qy, 0, sign_of(Fy0), a.oh);
+            }
+            if (row < kSY)
                 fxs[row][lane] = fx0;
-                fys[row][lane] = fy0;
-            }
+            else if (lane < kSY)
+                fxs[lane][kSX] = fx0;
+            fys[row][lane] = fy0;
         }
         R fz1 = 0;
         if (own) {
@@ -209,10 +272,10 @@ __device__ __forceinline__ void k_scalar_body(ScalArgs<T> a, VBlock vb)
             const R div = (fx1 - fx0) * idx + (fy1 - fy0) * idy + (fz1 - fz_below) * (R)a.idz[k];
             R v = rq - dts * div;
             if (s == 0 && a.src) {
-                v = v + dts * (R)a.src[pl + col];
+                v = v + dts * srcv;
                 v = v < R(0) ? R(0) : v;
             }
-            // read by later launches only (and rqn[o], its only other use, is read above)
+            // read by later launches only (and rqn[o], its only other use, was read before)
             st_stream(a.out + o, (T)v);
         }
         fz_below = fz1;
@@ -264,7 +327,7 @@ hipError_t scalar_t(erf_ctx *cx, const void *rqn, const void *rho_t, const void 
     run<ScalArgs<T>, k_mixing_ratio<T>, k_mixing_ratio_batch<T>>(cx, dim3((d.n + 255) / 256), dim3(256), 0, a);
     timing_stop(cx, K_MIXRATIO);
     const int nchunk = (d.nz + kLev - 1) / kLev;
-    dim3 blk(kSX + 1, kSY + 1, 1), grd((d.nx + kSX - 1) / kSX, (d.ny + kSY - 1) / kSY, nchunk * a.nq);
+    dim3 blk(kSX, kSY + 1, 1), grd((d.nx + kSX - 1) / kSX, (d.ny + kSY - 1) / kSY, nchunk * a.nq);
     const bool near = d.nx >= 3 && d.ny >= 3 && d.nz >= 3;
     timing_start(cx, K_SCALAR);
     if (a.weno && near)
