@@ -171,37 +171,74 @@ __global__ __launch_bounds__(64) void k_poisson_z(ProjArgs a)
     double *cp = a.cp + q;
     double cpm = 0.0;
     double2 dpm = make_double2(0.0, 0.0);
-    for (int k = 0; k < nz; ++k) {
-        const double ak = k > 0 ? 1.0 / (dz[k] * 0.5 * (dz[k - 1] + dz[k])) : 0.0;
-        const double ck = k < nz - 1 ? 1.0 / (dz[k] * 0.5 * (dz[k] + dz[k + 1])) : 0.0;
-        double bk = -ak - ck + lam, cc = ck;
-        double2 r = Z[(size_t)k * P];
-        if (q == 0 && k == 0) {
-            bk = 1.0;
-            cc = 0.0;
-            r = make_double2(0.0, 0.0);
+    // Both sweeps walk the column in chunks of kB levels; the values of the
+    // next chunk are read before the current one is stored, so their loads are
+    // in flight while it is eliminated (a load issued after a store to the same
+    // array would wait for it).
+    constexpr int kB = 8;
+    double2 zb[kB], zn[kB];
+#pragma unroll
+    for (int t = 0; t < kB; ++t) zb[t] = t < nz ? Z[(size_t)t * P] : make_double2(0.0, 0.0);
+    for (int k0 = 0; k0 < nz; k0 += kB) {
+#pragma unroll
+        for (int t = 0; t < kB; ++t) zn[t] = k0 + kB + t < nz ? Z[(size_t)(k0 + kB + t) * P] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < kB; ++t) {
+            const int k = k0 + t;
+            if (k >= nz) break;
+            const double ak = k > 0 ? 1.0 / (dz[k] * 0.5 * (dz[k - 1] + dz[k])) : 0.0;
+            const double ck = k < nz - 1 ? 1.0 / (dz[k] * 0.5 * (dz[k] + dz[k + 1])) : 0.0;
+            double bk = -ak - ck + lam, cc = ck;
+            double2 r = zb[t];
+            if (q == 0 && k == 0) {
+                bk = 1.0;
+                cc = 0.0;
+                r = make_double2(0.0, 0.0);
+            }
+            double cpk;
+            double2 dp;
+            if (k == 0) {
+                cpk = cc / bk;
+                dp = make_double2(r.x / bk, r.y / bk);
+            } else {
+                const double den = bk - ak * cpm;
+                cpk = cc / den;
+                dp = make_double2((r.x - ak * dpm.x) / den, (r.y - ak * dpm.y) / den);
+            }
+            cp[(size_t)k * P] = cpk;
+            Z[(size_t)k * P] = dp;
+            cpm = cpk;
+            dpm = dp;
         }
-        double cpk;
-        double2 dp;
-        if (k == 0) {
-            cpk = cc / bk;
-            dp = make_double2(r.x / bk, r.y / bk);
-        } else {
-            const double den = bk - ak * cpm;
-            cpk = cc / den;
-            dp = make_double2((r.x - ak * dpm.x) / den, (r.y - ak * dpm.y) / den);
-        }
-        cp[(size_t)k * P] = cpk;
-        Z[(size_t)k * P] = dp;
-        cpm = cpk;
-        dpm = dp;
+#pragma unroll
+        for (int t = 0; t < kB; ++t) zb[t] = zn[t];
     }
+    // back substitution from level nz - 2 down
     double2 x = dpm;
-    for (int k = nz - 2; k >= 0; --k) {
-        const double2 dp = Z[(size_t)k * P];
-        const double c = cp[(size_t)k * P];
-        x = make_double2(dp.x - c * x.x, dp.y - c * x.y);
-        Z[(size_t)k * P] = x;
+    double cb[kB], cn[kB];
+    auto load_down = [&](double2 (&zv)[kB], double (&cv)[kB], int ktop) {
+#pragma unroll
+        for (int t = 0; t < kB; ++t) {
+            const int k = ktop - t;
+            zv[t] = k >= 0 ? Z[(size_t)k * P] : make_double2(0.0, 0.0);
+            cv[t] = k >= 0 ? cp[(size_t)k * P] : 0.0;
+        }
+    };
+    load_down(zb, cb, nz - 2);
+    for (int k1 = nz - 2; k1 >= 0; k1 -= kB) {
+        load_down(zn, cn, k1 - kB);
+#pragma unroll
+        for (int t = 0; t < kB; ++t) {
+            const int k = k1 - t;
+            if (k < 0) break;
+            x = make_double2(zb[t].x - cb[t] * x.x, zb[t].y - cb[t] * x.y);
+            Z[(size_t)k * P] = x;
+        }
+#pragma unroll
+        for (int t = 0; t < kB; ++t) {
+            zb[t] = zn[t];
+            cb[t] = cn[t];
+        }
     }
 }
 
