@@ -858,13 +858,14 @@ __device__ __forceinline__ void k_rhs_body(RhsArgs<T> a, VBlock vb)
 // z-marching tendency kernel with the horizontal neighbours staged in LDS
 // ---------------------------------------------------------------------------
 // A block owns a 64 x 4 tile of columns and marches up a chunk of levels.  Per
-// level it reads the planes of the tile with their halos from memory into
-// LDS -- theta, u, v, w with three cells on each side, the other fields with
-// one -- and then computes every cell of the level from LDS: the compute
-// phase issues no memory loads, and the other block on the compute unit
-// loads while this one computes.  Face fields (rw, tau_13, tau_23) and the
-// heat diffusivity are kept for two faces (levels) in a ring of two slots;
-// the vertical stencils of the thread's own column stay in registers.
+// level it writes the planes of the tile with their halos into LDS -- theta,
+// u, v, w with three cells on each side, the other fields with one -- and
+// computes every cell of the level from LDS.  The planes of level k+1 are
+// read from memory into registers while level k is computed; that phase
+// issues no memory loads of its own, so no wait for the memory counter holds
+// it behind them.  Face fields (rw, tau_13, tau_23) and the heat diffusivity
+// are kept for two faces (levels) in a ring of two slots; the vertical
+// stencils of the thread's own column stay in registers.
 constexpr int kLX = 64, kLY = 4;                        // tile
 constexpr int kBW = kLX + 6, kBH = kLY + 6;             // planes with 3-cell halos
 constexpr int kBN = kBW * kBH;                          // 700
