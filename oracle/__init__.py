@@ -28,7 +28,8 @@ FIELDS = ("rho", "rt", "ru", "rv", "rw", "rq")
 
 class _Grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
-                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.POINTER(C.c_double))]
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.POINTER(C.c_double)),
+                ("terrain", C.POINTER(C.c_double)), ("terrain_beta", C.c_double)]
 
 
 class _Params(C.Structure):
@@ -82,6 +83,8 @@ def lib():
             L.orc_weno5.argtypes = [_DP, C.c_double, C.c_double]
             L.orc_thomas.argtypes = [C.c_int32, _DP, _DP, _DP, _DP, _DP]
             L.orc_base_state.argtypes = [C.c_int32, _DP, _DP, C.c_double, C.c_double, _DP, _DP, _DP]
+            L.orc_terrain_heights.argtypes = [C.POINTER(_Grid), _DP, _DP]
+            L.orc_base_state_columns.argtypes = [C.POINTER(_Grid), _DP, _DP, C.c_double, _DP, _DP, _DP]
             L.orc_slow_rhs.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Base),
                                        C.POINTER(_State), C.POINTER(_State)]
             L.orc_acoustic_substeps.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Base),
@@ -143,7 +146,8 @@ class Oracle:
         self.cfg = cfg
         self.nx, self.ny, self.nz = cfg.nx, cfg.ny, cfg.nz
         self.dz = np.ascontiguousarray(cfg.dz, dtype=np.float64)
-        self._grid = _Grid(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, _p(self.dz))
+        self._grid = _Grid(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, _p(self.dz), None, 0.0)
+        self.terrain = None
         self._params = _Params(cfg.dt, cfg.n_substeps, cfg.beta_s, cfg.beta_d, cfg.adv_order_h,
                                cfg.adv_order_v, cfg.scalar_scheme, cfg.n_scalars, cfg.sgs, cfg.Cs,
                                cfg.Pr_t, cfg.nu_m, cfg.alpha_m, cfg.f_cor, cfg.Ug, cfg.Vg,
@@ -165,6 +169,38 @@ class Oracle:
         self._params.mlp_params = _p(pa)
         self._params.mlp_norm = _p(no)
         self._params.mlp_bf16 = int(bool(bf16))
+
+    # -- terrain-following coordinates (App. A, App. B) -------------------------
+    def set_terrain(self, h_nodes, beta: float = 1.0):
+        """Terrain heights h[ny][nx] at the nodes (node (i, j) the low-x, low-y
+        corner of cell (i, j)); beta 1 basic terrain following, 3 Sullivan.
+        Set before the base state, which then holds one value per cell."""
+        h = np.ascontiguousarray(h_nodes, dtype=np.float64)
+        if h.shape != (self.ny, self.nx):
+            raise ValueError("terrain heights must be (ny, nx)")
+        self.terrain = h
+        self._grid.terrain = _p(h)
+        self._grid.terrain_beta = float(beta)
+        self.base = None
+
+    def terrain_heights(self):
+        """(Hc, zc): physical cell heights and centre heights, (nz, ny, nx)."""
+        Hc, zc = np.zeros((self.nz, self.ny, self.nx)), np.zeros((self.nz, self.ny, self.nx))
+        self._check(lib().orc_terrain_heights(C.byref(self._grid), _p(Hc), _p(zc)), "orc_terrain_heights")
+        return Hc, zc
+
+    def init_base_state_columns(self, theta0, p_surf):
+        """Hydrostatic base state of every column from theta0 (nz, ny, nx) at
+        the cell centres and the ground pressure p_surf (ny, nx)."""
+        shp = (self.nz, self.ny, self.nx)
+        th = np.ascontiguousarray(np.broadcast_to(theta0, shp), dtype=np.float64)
+        ps = np.ascontiguousarray(np.broadcast_to(p_surf, shp[1:]), dtype=np.float64)
+        rho0, p0, pi0 = np.zeros(shp), np.zeros(shp), np.zeros(shp)
+        self._check(lib().orc_base_state_columns(C.byref(self._grid), _p(th), _p(ps), self.cfg.grav,
+                                                 _p(rho0), _p(p0), _p(pi0)), "orc_base_state_columns")
+        self.base = {"rho0": rho0, "theta0": th, "p0": p0, "pi0": pi0, "qv0": None}
+        self._base = _Base(_p(rho0), _p(th), _p(p0), _p(pi0), None)
+        return self.base
 
     # -- base state -------------------------------------------------------
     def init_base_state(self, theta0: np.ndarray, p_surface: float, qv0=None):

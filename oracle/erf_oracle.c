@@ -83,6 +83,157 @@ static double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 static double *dalloc(size_t n) { return (double *)calloc(n ? n : 1, sizeof(double)); }
 
 /* ------------------------------------------------------------------------ */
+/* terrain-following coordinates (App. A, App. B)                             */
+/* ------------------------------------------------------------------------ */
+/* Node heights z = zeta + s(zeta) h(x, y) with s = (1 - zeta/z_t)^beta (the
+ * canonical form of Sec. 3.4).  Readings: the flat grid's levels are
+ * zeta_k = dz_0 + ... + dz_{k-1} and z_t = zeta_nz; a cell's physical height
+ * is the mean of its four vertical edges, Hc = dz_k + (s_{k+1} - s_k) hbar
+ * with hbar the mean of its four corner heights, and the Jacobian
+ * h_zeta = Hc / dz_k; heights are kept as displacements from the flat grid so
+ * that flat terrain gives dz, 1 and 0 exactly. */
+typedef struct {
+    int on;
+    double *s;  /* nz + 1 node levels */
+    double *hb; /* ny * nx, corner mean of h per column */
+    double *Hc; /* nz * ny * nx */
+} ter_t;
+
+static double node_h(const orc_grid *g, int i, int j)
+{
+    return g->terrain[(size_t)wrap(j, g->ny) * g->nx + wrap(i, g->nx)];
+}
+
+static ter_t ter_build(const orc_grid *g)
+{
+    ter_t T = {0, NULL, NULL, NULL};
+    if (!g->terrain) return T;
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    T.on = 1;
+    T.s = dalloc((size_t)nz + 1);
+    T.hb = dalloc((size_t)nx * ny);
+    T.Hc = dalloc((size_t)nx * ny * nz);
+    double zt = 0.0;
+    for (int k = 0; k < nz; ++k) zt += g->dz[k];
+    double zeta = 0.0;
+    for (int k = 0; k <= nz; ++k) {
+        T.s[k] = (k == nz) ? 0.0 : pow(1.0 - zeta / zt, g->terrain_beta);
+        if (k < nz) zeta += g->dz[k];
+    }
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i)
+            T.hb[(size_t)j * nx + i] = 0.25 * ((node_h(g, i, j) + node_h(g, i + 1, j)) +
+                                               (node_h(g, i, j + 1) + node_h(g, i + 1, j + 1)));
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                T.Hc[CIDX(g, i, j, k)] = g->dz[k] + (T.s[k + 1] - T.s[k]) * T.hb[(size_t)j * nx + i];
+    return T;
+}
+
+static void ter_free(ter_t *T)
+{
+    free(T->s); free(T->hb); free(T->Hc);
+}
+
+static double t_hb(const orc_grid *g, const ter_t *T, int i, int j)
+{
+    return T->hb[(size_t)wrap(j, g->ny) * g->nx + wrap(i, g->nx)];
+}
+/* physical cell height and Jacobian h_zeta at a cell (periodic in x, y) */
+static double t_Hc(const orc_grid *g, const ter_t *T, int i, int j, int k)
+{
+    return T->on ? T->Hc[CIDX(g, wrap(i, g->nx), wrap(j, g->ny), k)] : g->dz[k];
+}
+static double t_J(const orc_grid *g, const ter_t *T, int i, int j, int k)
+{
+    return T->on ? t_Hc(g, T, i, j, k) / g->dz[k] : 1.0;
+}
+/* h_zeta on the x-face i (between cells i-1 and i) and on the y-face j */
+static double t_JU(const orc_grid *g, const ter_t *T, int i, int j, int k)
+{
+    return T->on ? 0.5 * (t_J(g, T, i - 1, j, k) + t_J(g, T, i, j, k)) : 1.0;
+}
+static double t_JV(const orc_grid *g, const ter_t *T, int i, int j, int k)
+{
+    return T->on ? 0.5 * (t_J(g, T, i, j - 1, k) + t_J(g, T, i, j, k)) : 1.0;
+}
+/* h_xi on the x-face i at level k: the difference of the two cells' centre
+ * heights over dx (App. B, second order); h_eta on the y-face j likewise */
+static double t_hxU(const orc_grid *g, const ter_t *T, int i, int j, int k)
+{
+    if (!T->on) return 0.0;
+    return 0.5 * (T->s[k] + T->s[k + 1]) * (t_hb(g, T, i, j) - t_hb(g, T, i - 1, j)) / g->dx;
+}
+static double t_heV(const orc_grid *g, const ter_t *T, int i, int j, int k)
+{
+    if (!T->on) return 0.0;
+    return 0.5 * (T->s[k] + T->s[k + 1]) * (t_hb(g, T, i, j) - t_hb(g, T, i, j - 1)) / g->dy;
+}
+/* h_xi and h_eta on the z-face (i, j, k): the fourth-order centred difference
+ * of the face-centre heights (the mean of the face's four nodes) (App. B) */
+static double t_hxW(const orc_grid *g, const ter_t *T, int i, int j, int k)
+{
+    if (!T->on) return 0.0;
+    return T->s[k] * ((t_hb(g, T, i - 2, j) - t_hb(g, T, i + 2, j)) + 8.0 * (t_hb(g, T, i + 1, j) - t_hb(g, T, i - 1, j))) /
+           (12.0 * g->dx);
+}
+static double t_heW(const orc_grid *g, const ter_t *T, int i, int j, int k)
+{
+    if (!T->on) return 0.0;
+    return T->s[k] * ((t_hb(g, T, i, j - 2) - t_hb(g, T, i, j + 2)) + 8.0 * (t_hb(g, T, i, j + 1) - t_hb(g, T, i, j - 1))) /
+           (12.0 * g->dy);
+}
+/* rho Omega on the z-face (i, j, k), the momentum normal to the face (App. A):
+ * rho w - h_xi (rho u) - h_eta (rho v), the horizontal momenta averaged from the
+ * four x-faces (y-faces) around the face (App. B); the lid faces keep rho w */
+static double t_M(const orc_grid *g, const ter_t *T, const double *ru, const double *rv, int i, int j, int k)
+{
+    if (!T->on || k == 0 || k == g->nz) return 0.0;
+    double su = (cget(g, ru, i, j, k) + cget(g, ru, i + 1, j, k)) + (cget(g, ru, i, j, k - 1) + cget(g, ru, i + 1, j, k - 1));
+    double sv = (cget(g, rv, i, j, k) + cget(g, rv, i, j + 1, k)) + (cget(g, rv, i, j, k - 1) + cget(g, rv, i, j + 1, k - 1));
+    return 0.25 * t_hxW(g, T, i, j, k) * su + 0.25 * t_heW(g, T, i, j, k) * sv;
+}
+static double t_rOm(const orc_grid *g, const ter_t *T, const double *ru, const double *rv, const double *rw,
+                    int i, int j, int k)
+{
+    double W = rw[CIDX(g, wrap(i, g->nx), wrap(j, g->ny), k)];
+    if (!T->on || k == 0 || k == g->nz) return W;
+    return W - t_M(g, T, ru, rv, i, j, k);
+}
+/* (f_zeta / h_zeta) at a cell: the centred difference of f over the physical
+ * distance of the centres above and below (App. B); one-sided in the lowest
+ * and highest cells (reading), zero in a single-level column */
+static double t_fz(const orc_grid *g, const ter_t *T, const double *f, int i, int j, int k)
+{
+    int nz = g->nz;
+    if (nz < 2) return 0.0;
+    int kl = k > 0 ? k - 1 : 0, ku = k < nz - 1 ? k + 1 : nz - 1;
+    double dzc = 0.5 * t_Hc(g, T, i, j, kl) + 0.5 * t_Hc(g, T, i, j, ku);
+    for (int m = kl + 1; m < ku; ++m) dzc += t_Hc(g, T, i, j, m);
+    return (cget(g, f, i, j, ku) - cget(g, f, i, j, kl)) / dzc;
+}
+
+int orc_terrain_heights(const orc_grid *g, double *Hc, double *zc)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    if (nx < 1 || ny < 1 || nz < 1 || !g->dz) return -1;
+    ter_t T = ter_build(g);
+    double zeta = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = CIDX(g, i, j, k);
+                if (Hc) Hc[c] = t_Hc(g, &T, i, j, k);
+                if (zc) zc[c] = (zeta + 0.5 * g->dz[k]) + (T.on ? 0.5 * (T.s[k] + T.s[k + 1]) * t_hb(g, &T, i, j) : 0.0);
+            }
+        zeta += g->dz[k];
+    }
+    ter_free(&T);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* equation of state, Sec. 2.1                                               */
 /* ------------------------------------------------------------------------ */
 double orc_eos_p(double Theta) { return P_00 * pow(R_D * Theta / P_00, GAM); }
@@ -162,6 +313,35 @@ int orc_base_state_moist(int32_t nz, const double *dz, const double *theta0, con
         q_below = q;
     }
     return 0;
+}
+
+/* reading (terrain, App. A): the base state is hydrostatic in every column,
+ * along the column's physical cell heights, from the pressure at its ground */
+int orc_base_state_columns(const orc_grid *g, const double *theta0, const double *p_surf, double grav,
+                           double *rho0, double *p0, double *pi0)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    if (nx < 1 || ny < 1 || nz < 1 || !theta0 || !p_surf || !rho0 || !p0 || !pi0) return -1;
+    ter_t T = ter_build(g);
+    double *dzc = dalloc(nz), *th = dalloc(nz), *r = dalloc(nz), *p = dalloc(nz), *pi = dalloc(nz);
+    int rc = 0;
+    for (int j = 0; j < ny && rc == 0; ++j)
+        for (int i = 0; i < nx && rc == 0; ++i) {
+            for (int k = 0; k < nz; ++k) {
+                dzc[k] = t_Hc(g, &T, i, j, k);
+                th[k] = theta0[CIDX(g, i, j, k)];
+            }
+            rc = orc_base_state_moist(nz, dzc, th, NULL, p_surf[(size_t)j * nx + i], grav, r, p, pi);
+            for (int k = 0; k < nz; ++k) {
+                size_t c = CIDX(g, i, j, k);
+                rho0[c] = r[k];
+                p0[c] = p[k];
+                pi0[c] = pi[k];
+            }
+        }
+    free(dzc); free(th); free(r); free(p); free(pi);
+    ter_free(&T);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -566,6 +746,9 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                  const orc_state *S, orc_state *R)
 {
     if (P->anelastic && (P->moist || P->sgs == 2 || P->sgs == 3 || !P->p_anel)) return -1;
+    if (g->terrain && (P->moist || P->anelastic || P->sgs != 0 || P->nu_m != 0.0 || P->alpha_m != 0.0 ||
+                       P->most_z0 > 0.0 || P->surf_heat_flux != 0.0 || P->n_scalars > 0))
+        return -1;
     /* the Deardorff closure carries rho e as scalar 0 and nothing else */
     if (P->sgs == 3 && (P->n_scalars != 1 || P->moist || !S->rq || !R->rq)) return -1;
     if (P->most_z0 < 0.0 || (P->most_z0 > 0.0 && !(P->most_z0 < 0.5 * g->dz[0]))) return -1;
@@ -588,10 +771,12 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
      * + q_r) from the base state's rho0 (1 + q_v0) (the buoyancy) */
     double *qf = moist ? dalloc(n) : NULL, *bm = moist ? dalloc(n) : NULL;
     primitives(g, S, th, u, v, w);
+    ter_t T = ter_build(g);
     for (int k = 0; k < nz; ++k) {
-        double T0 = B->rho0[k] * B->theta0[k];
         double qv0 = B->qv0 ? B->qv0[k] : 0.0;
         for (size_t c = (size_t)k * nx * ny; c < (size_t)(k + 1) * nx * ny; ++c) {
+            size_t kb = T.on ? c : (size_t)k; /* base state per cell with terrain */
+            double T0 = B->rho0[kb] * B->theta0[kb];
             if (moist) {
                 double rqv = S->rq[c], rqc = S->rq[n + c], rqr = S->rq[2 * n + c];
                 double qv = rqv / S->rho[c], qc = rqc / S->rho[c];
@@ -603,7 +788,7 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                  * projections left, not a function of the state (Sec. 2.2) */
                 pp[c] = P->p_anel[c];
             } else {
-                pp[c] = orc_eos_pprime(S->rt[c], T0, B->p0[k]);
+                pp[c] = orc_eos_pprime(S->rt[c], T0, B->p0[kb]);
             }
         }
     }
@@ -614,17 +799,20 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t c = CIDX(g, i, j, k);
-                double U0 = S->ru[c], U1 = cget(g, S->ru, i + 1, j, k);
-                double V0 = S->rv[c], V1 = cget(g, S->rv, i, j + 1, k);
-                double W0 = S->rw[c], W1 = S->rw[CIDX(g, i, j, k + 1)];
-                R->rho[c] = -((U1 - U0) / dx + (V1 - V0) / dy + (W1 - W0) / dz[k]);
+                /* terrain (App. A): h_zeta-weighted horizontal fluxes, rho Omega
+                 * on the z-faces, the divergence divided by the cell's h_zeta */
+                double U0 = t_JU(g, &T, i, j, k) * S->ru[c], U1 = t_JU(g, &T, i + 1, j, k) * cget(g, S->ru, i + 1, j, k);
+                double V0 = t_JV(g, &T, i, j, k) * S->rv[c], V1 = t_JV(g, &T, i, j + 1, k) * cget(g, S->rv, i, j + 1, k);
+                double W0 = t_rOm(g, &T, S->ru, S->rv, S->rw, i, j, k), W1 = t_rOm(g, &T, S->ru, S->rv, S->rw, i, j, k + 1);
+                double Jc = t_J(g, &T, i, j, k);
+                R->rho[c] = -((U1 - U0) / dx + (V1 - V0) / dy + (W1 - W0) / dz[k]) / Jc;
                 double fx0 = U0 * ix(g, th, i, j, k, oh, sgn(U0));
                 double fx1 = U1 * ix(g, th, i + 1, j, k, oh, sgn(U1));
                 double fy0 = V0 * iy(g, th, i, j, k, oh, sgn(V0));
                 double fy1 = V1 * iy(g, th, i, j + 1, k, oh, sgn(V1));
                 double fz0 = (k == 0) ? 0.0 : W0 * izc(g, th, i, j, k, ov, sgn(W0));
                 double fz1 = (k == nz - 1) ? 0.0 : W1 * izc(g, th, i, j, k + 1, ov, sgn(W1));
-                R->rt[c] = -((fx1 - fx0) / dx + (fy1 - fy0) / dy + (fz1 - fz0) / dz[k]);
+                R->rt[c] = -((fx1 - fx0) / dx + (fy1 - fy0) / dy + (fz1 - fz0) / dz[k]) / Jc;
             }
 
     /* --- x-momentum on x-faces, eq. (mom) --- */
@@ -634,22 +822,28 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
             for (int i = 0; i < nx; ++i) {
                 size_t c = CIDX(g, i, j, k);
                 /* xx-flux at the centres right (i) and left (i-1) of the face */
-                double a_r = 0.5 * (S->ru[c] + cget(g, S->ru, i + 1, j, k));
-                double a_l = 0.5 * (cget(g, S->ru, i - 1, j, k) + S->ru[c]);
+                /* terrain: the mass fluxes carry h_zeta (rho Omega vertically)
+                 * and the divergence is divided by h_zeta of the x-face */
+                double a_r = 0.5 * (t_JU(g, &T, i, j, k) * S->ru[c] + t_JU(g, &T, i + 1, j, k) * cget(g, S->ru, i + 1, j, k));
+                double a_l = 0.5 * (t_JU(g, &T, i - 1, j, k) * cget(g, S->ru, i - 1, j, k) + t_JU(g, &T, i, j, k) * S->ru[c]);
                 double fxx_r = a_r * ix(g, u, i + 1, j, k, oh, sgn(a_r));
                 double fxx_l = a_l * ix(g, u, i, j, k, oh, sgn(a_l));
                 /* xy-flux on the edges at y-faces j and j+1 */
-                double b_0 = 0.5 * (cget(g, S->rv, i - 1, j, k) + S->rv[c]);
-                double b_1 = 0.5 * (cget(g, S->rv, i - 1, j + 1, k) + cget(g, S->rv, i, j + 1, k));
+                double b_0 = 0.5 * (t_JV(g, &T, i - 1, j, k) * cget(g, S->rv, i - 1, j, k) + t_JV(g, &T, i, j, k) * S->rv[c]);
+                double b_1 = 0.5 * (t_JV(g, &T, i - 1, j + 1, k) * cget(g, S->rv, i - 1, j + 1, k) +
+                                    t_JV(g, &T, i, j + 1, k) * cget(g, S->rv, i, j + 1, k));
                 double fxy0 = b_0 * iy(g, u, i, j, k, oh, sgn(b_0));
                 double fxy1 = b_1 * iy(g, u, i, j + 1, k, oh, sgn(b_1));
                 /* xz-flux on the edges at z-faces k and k+1 */
-                double e_0 = (k == 0) ? 0.0 : 0.5 * (wget(g, S->rw, i - 1, j, k) + S->rw[c]);
-                double e_1 = (k == nz - 1) ? 0.0 : 0.5 * (wget(g, S->rw, i - 1, j, k + 1) + S->rw[CIDX(g, i, j, k + 1)]);
+                double e_0 = (k == 0) ? 0.0 : 0.5 * (t_rOm(g, &T, S->ru, S->rv, S->rw, i - 1, j, k) + t_rOm(g, &T, S->ru, S->rv, S->rw, i, j, k));
+                double e_1 = (k == nz - 1) ? 0.0 : 0.5 * (t_rOm(g, &T, S->ru, S->rv, S->rw, i - 1, j, k + 1) + t_rOm(g, &T, S->ru, S->rv, S->rw, i, j, k + 1));
                 double fxz0 = (k == 0) ? 0.0 : e_0 * izc(g, u, i, j, k, ov, sgn(e_0));
                 double fxz1 = (k == nz - 1) ? 0.0 : e_1 * izc(g, u, i, j, k + 1, ov, sgn(e_1));
-                double adv = (fxx_r - fxx_l) / dx + (fxy1 - fxy0) / dy + (fxz1 - fxz0) / dz[k];
+                double adv = ((fxx_r - fxx_l) / dx + (fxy1 - fxy0) / dy + (fxz1 - fxz0) / dz[k]) / t_JU(g, &T, i, j, k);
                 double pgf = (pp[c] - cget(g, pp, i - 1, j, k)) / dx;
+                /* terrain: p_x = p_xi - h_xi (p_zeta / h_zeta), the last factor
+                 * the mean of the two cells' vertical differences (App. B) */
+                if (T.on) pgf -= 0.5 * t_hxU(g, &T, i, j, k) * (t_fz(g, &T, pp, i, j, k) + t_fz(g, &T, pp, i - 1, j, k));
                 /* reading (moist): 1 + q_v + q_c on the face is the mean of its two cells */
                 if (moist) pgf = pgf / (0.5 * (cget(g, qf, i - 1, j, k) + qf[c]));
                 double rho_f = 0.5 * (cget(g, S->rho, i - 1, j, k) + S->rho[c]);
@@ -666,20 +860,22 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t c = CIDX(g, i, j, k);
-                double b_r = 0.5 * (S->rv[c] + cget(g, S->rv, i, j + 1, k));
-                double b_l = 0.5 * (cget(g, S->rv, i, j - 1, k) + S->rv[c]);
+                double b_r = 0.5 * (t_JV(g, &T, i, j, k) * S->rv[c] + t_JV(g, &T, i, j + 1, k) * cget(g, S->rv, i, j + 1, k));
+                double b_l = 0.5 * (t_JV(g, &T, i, j - 1, k) * cget(g, S->rv, i, j - 1, k) + t_JV(g, &T, i, j, k) * S->rv[c]);
                 double fyy_r = b_r * iy(g, v, i, j + 1, k, oh, sgn(b_r));
                 double fyy_l = b_l * iy(g, v, i, j, k, oh, sgn(b_l));
-                double a_0 = 0.5 * (cget(g, S->ru, i, j - 1, k) + S->ru[c]);
-                double a_1 = 0.5 * (cget(g, S->ru, i + 1, j - 1, k) + cget(g, S->ru, i + 1, j, k));
+                double a_0 = 0.5 * (t_JU(g, &T, i, j - 1, k) * cget(g, S->ru, i, j - 1, k) + t_JU(g, &T, i, j, k) * S->ru[c]);
+                double a_1 = 0.5 * (t_JU(g, &T, i + 1, j - 1, k) * cget(g, S->ru, i + 1, j - 1, k) +
+                                    t_JU(g, &T, i + 1, j, k) * cget(g, S->ru, i + 1, j, k));
                 double fyx0 = a_0 * ix(g, v, i, j, k, oh, sgn(a_0));
                 double fyx1 = a_1 * ix(g, v, i + 1, j, k, oh, sgn(a_1));
-                double e_0 = (k == 0) ? 0.0 : 0.5 * (wget(g, S->rw, i, j - 1, k) + S->rw[c]);
-                double e_1 = (k == nz - 1) ? 0.0 : 0.5 * (wget(g, S->rw, i, j - 1, k + 1) + S->rw[CIDX(g, i, j, k + 1)]);
+                double e_0 = (k == 0) ? 0.0 : 0.5 * (t_rOm(g, &T, S->ru, S->rv, S->rw, i, j - 1, k) + t_rOm(g, &T, S->ru, S->rv, S->rw, i, j, k));
+                double e_1 = (k == nz - 1) ? 0.0 : 0.5 * (t_rOm(g, &T, S->ru, S->rv, S->rw, i, j - 1, k + 1) + t_rOm(g, &T, S->ru, S->rv, S->rw, i, j, k + 1));
                 double fyz0 = (k == 0) ? 0.0 : e_0 * izc(g, v, i, j, k, ov, sgn(e_0));
                 double fyz1 = (k == nz - 1) ? 0.0 : e_1 * izc(g, v, i, j, k + 1, ov, sgn(e_1));
-                double adv = (fyx1 - fyx0) / dx + (fyy_r - fyy_l) / dy + (fyz1 - fyz0) / dz[k];
+                double adv = ((fyx1 - fyx0) / dx + (fyy_r - fyy_l) / dy + (fyz1 - fyz0) / dz[k]) / t_JV(g, &T, i, j, k);
                 double pgf = (pp[c] - cget(g, pp, i, j - 1, k)) / dy;
+                if (T.on) pgf -= 0.5 * t_heV(g, &T, i, j, k) * (t_fz(g, &T, pp, i, j, k) + t_fz(g, &T, pp, i, j - 1, k));
                 if (moist) pgf = pgf / (0.5 * (cget(g, qf, i, j - 1, k) + qf[c]));
                 double rho_f = 0.5 * (cget(g, S->rho, i, j - 1, k) + S->rho[c]);
                 double ubar = 0.25 * (cget(g, S->ru, i, j - 1, k) + cget(g, S->ru, i + 1, j - 1, k) + S->ru[c] + cget(g, S->ru, i + 1, j, k));
@@ -698,23 +894,31 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t c = CIDX(g, i, j, k), cm = CIDX(g, i, j, k - 1);
+                size_t kb = T.on ? c : (size_t)k, kbm = T.on ? cm : (size_t)(k - 1);
                 double dzf = 0.5 * (dz[k - 1] + dz[k]);
+                /* terrain: the physical distance of the two centres and h_zeta
+                 * of the z-face */
+                double dzp = T.on ? 0.5 * (t_Hc(g, &T, i, j, k - 1) + t_Hc(g, &T, i, j, k)) : dzf;
+                double JW = T.on ? dzp / dzf : 1.0;
                 /* zx-flux on the edges at x-faces i and i+1 */
-                double a_0 = 0.5 * (S->ru[cm] + S->ru[c]);
-                double a_1 = 0.5 * (cget(g, S->ru, i + 1, j, k - 1) + cget(g, S->ru, i + 1, j, k));
+                double a_0 = 0.5 * (t_JU(g, &T, i, j, k - 1) * S->ru[cm] + t_JU(g, &T, i, j, k) * S->ru[c]);
+                double a_1 = 0.5 * (t_JU(g, &T, i + 1, j, k - 1) * cget(g, S->ru, i + 1, j, k - 1) +
+                                    t_JU(g, &T, i + 1, j, k) * cget(g, S->ru, i + 1, j, k));
                 double fzx0 = a_0 * ixw(g, w, i, j, k, oh, sgn(a_0));
                 double fzx1 = a_1 * ixw(g, w, i + 1, j, k, oh, sgn(a_1));
-                double b_0 = 0.5 * (S->rv[cm] + S->rv[c]);
-                double b_1 = 0.5 * (cget(g, S->rv, i, j + 1, k - 1) + cget(g, S->rv, i, j + 1, k));
+                double b_0 = 0.5 * (t_JV(g, &T, i, j, k - 1) * S->rv[cm] + t_JV(g, &T, i, j, k) * S->rv[c]);
+                double b_1 = 0.5 * (t_JV(g, &T, i, j + 1, k - 1) * cget(g, S->rv, i, j + 1, k - 1) +
+                                    t_JV(g, &T, i, j + 1, k) * cget(g, S->rv, i, j + 1, k));
                 double fzy0 = b_0 * iyw(g, w, i, j, k, oh, sgn(b_0));
                 double fzy1 = b_1 * iyw(g, w, i, j + 1, k, oh, sgn(b_1));
                 /* zz-flux at the centres above (k) and below (k-1) the face */
-                double e_u = 0.5 * (S->rw[c] + S->rw[CIDX(g, i, j, k + 1)]);
-                double e_d = 0.5 * (S->rw[cm] + S->rw[c]);
+                double Om = t_rOm(g, &T, S->ru, S->rv, S->rw, i, j, k);
+                double e_u = 0.5 * (Om + t_rOm(g, &T, S->ru, S->rv, S->rw, i, j, k + 1));
+                double e_d = 0.5 * (t_rOm(g, &T, S->ru, S->rv, S->rw, i, j, k - 1) + Om);
                 double fzz_u = e_u * izw(g, w, i, j, k + 1, ov, sgn(e_u));
                 double fzz_d = e_d * izw(g, w, i, j, k, ov, sgn(e_d));
-                double adv = (fzx1 - fzx0) / dx + (fzy1 - fzy0) / dy + (fzz_u - fzz_d) / dzf;
-                double pgf = (pp[c] - pp[cm]) / dzf;
+                double adv = ((fzx1 - fzx0) / dx + (fzy1 - fzy0) / dy + (fzz_u - fzz_d) / dzf) / JW;
+                double pgf = (pp[c] - pp[cm]) / dzp;
                 /* reading of the garbled sign: heavier-than-base air sinks */
                 if (moist) {
                     /* reading (moist): B = -g (rho_m - rho_m0) with the total
@@ -729,7 +933,7 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
                     double b_dn = B->rho0[k - 1] * (th[cm] - B->theta0[k - 1]) / B->theta0[k - 1];
                     R->rw[c] = -adv - pgf + gr * 0.5 * (b_up + b_dn);
                 } else {
-                    double buoy = -gr * 0.5 * ((S->rho[c] - B->rho0[k]) + (S->rho[cm] - B->rho0[k - 1]));
+                    double buoy = -gr * 0.5 * ((S->rho[c] - B->rho0[kb]) + (S->rho[cm] - B->rho0[kbm]));
                     R->rw[c] = -adv - pgf + buoy;
                 }
             }
@@ -746,6 +950,7 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
             }
 
     free(th); free(u); free(v); free(w); free(pp); free(qf); free(bm);
+    ter_free(&T);
     return 0;
 }
 
@@ -767,12 +972,15 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
     if (n_sub < 1) return -1;
     size_t n = (size_t)nx * ny * nz, nw = (size_t)nx * ny * (nz + 1);
     double dx = g->dx, dy = g->dy, gr = P->grav;
-    const double *dz = g->dz;
     double b1 = 0.5 * (1.0 - P->beta_s), b2 = 0.5 * (1.0 + P->beta_s), bd = P->beta_d;
 
     int moist = P->moist != 0;
     if (moist && (P->n_scalars < 3 || !St->rq)) return -1;
+    if (g->terrain && (moist || P->anelastic)) return -1;
+    ter_t T = ter_build(g);
     double *tht = dalloc(n), *pit = dalloc(n), *pim = dalloc(n), *rdm = dalloc(n);
+    /* terrain: the predicted Theta'' of the horizontal pressure gradient */
+    double *tt = T.on ? dalloc(n) : NULL;
     double *U2 = dalloc(n), *V2 = dalloc(n), *W2 = dalloc(nw), *T2 = dalloc(n), *R2 = dalloc(n);
     double *T2p = dalloc(n), *Un = dalloc(n), *Vn = dalloc(n), *Wn = dalloc(nw), *Tn = dalloc(n), *Rn = dalloc(n);
     double *sU = dalloc(n), *sV = dalloc(n), *sW = dalloc(nw);
@@ -805,6 +1013,8 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
     for (size_t c = 0; c < nw; ++c) W2[c] = Sn->rw[c] - St->rw[c];
 
     for (int s = 0; s < n_sub; ++s) {
+        if (T.on)
+            for (size_t c = 0; c < n; ++c) tt[c] = T2[c] + bd * (T2[c] - T2p[c]);
         /* 1. horizontal momenta, explicit forward step with the predicted Theta'' */
 #pragma omp parallel for collapse(2) schedule(static)
         for (int k = 0; k < nz; ++k)
@@ -816,14 +1026,32 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
                     double tt_s = cget(g, T2, i, j - 1, k) + bd * (cget(g, T2, i, j - 1, k) - cget(g, T2p, i, j - 1, k));
                     double pfx = 0.5 * (cget(g, pim, i - 1, j, k) + pim[c]);
                     double pfy = 0.5 * (cget(g, pim, i, j - 1, k) + pim[c]);
-                    Un[c] = U2[c] + dtau * (-GAM * R_D * pfx * (tt_c - tt_w) / dx + Rt->ru[c]);
-                    Vn[c] = V2[c] + dtau * (-GAM * R_D * pfy * (tt_c - tt_s) / dy + Rt->rv[c]);
+                    if (T.on) {
+                        /* App. C: d/dxi - (h_xi / h_zeta) d/dzeta of the predicted
+                         * Theta'', discretised as the pressure gradient (App. B) */
+                        double cx = 0.5 * t_hxU(g, &T, i, j, k) * (t_fz(g, &T, tt, i, j, k) + t_fz(g, &T, tt, i - 1, j, k));
+                        double cy = 0.5 * t_heV(g, &T, i, j, k) * (t_fz(g, &T, tt, i, j, k) + t_fz(g, &T, tt, i, j - 1, k));
+                        Un[c] = U2[c] + dtau * (-GAM * R_D * pfx * (tt_c - tt_w) / dx + GAM * R_D * pfx * cx + Rt->ru[c]);
+                        Vn[c] = V2[c] + dtau * (-GAM * R_D * pfy * (tt_c - tt_s) / dy + GAM * R_D * pfy * cy + Rt->rv[c]);
+                    } else {
+                        Un[c] = U2[c] + dtau * (-GAM * R_D * pfx * (tt_c - tt_w) / dx + Rt->ru[c]);
+                        Vn[c] = V2[c] + dtau * (-GAM * R_D * pfy * (tt_c - tt_s) / dy + Rt->rv[c]);
+                    }
                 }
         /* 2. per column: explicit parts of Theta'', rho''; implicit W'' */
 #pragma omp parallel for collapse(2) schedule(static)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 double th_hat[nz], rh_hat[nz], ta[nz + 1], tb[nz + 1], tc[nz + 1], tr[nz + 1], tx[nz + 1];
+                /* terrain: physical cell heights of the column; the metric part
+                 * h_xi U'' + h_eta V'' of Omega'' on its z-faces before (Mo) and
+                 * after (Mn) this substep's horizontal step (App. C) */
+                double Hc[nz], Mo[nz + 1], Mn[nz + 1];
+                for (int k = 0; k < nz; ++k) Hc[k] = t_Hc(g, &T, i, j, k);
+                for (int k = 0; k <= nz; ++k) {
+                    Mo[k] = t_M(g, &T, U2, V2, i, j, k);
+                    Mn[k] = t_M(g, &T, Un, Vn, i, j, k);
+                }
                 /* face theta^t in this column (lids carry W = 0, value unused) */
 #define THZ(kk) (((kk) <= 0 || (kk) >= nz) ? 0.0 : 0.5 * (tht[CIDX(g, i, j, (kk) - 1)] + tht[CIDX(g, i, j, (kk))]))
                 for (int k = 0; k < nz; ++k) {
@@ -832,13 +1060,21 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
                     double thx1 = 0.5 * (tht[c] + cget(g, tht, i + 1, j, k));
                     double thy0 = 0.5 * (cget(g, tht, i, j - 1, k) + tht[c]);
                     double thy1 = 0.5 * (tht[c] + cget(g, tht, i, j + 1, k));
-                    double Ue = cget(g, Un, i + 1, j, k), Uw = Un[c];
-                    double Vn_ = cget(g, Vn, i, j + 1, k), Vs = Vn[c];
-                    double Wt = W2[CIDX(g, i, j, k + 1)], Wb = W2[c];
+                    /* terrain: h_zeta-weighted horizontal fluxes and Omega'' on the
+                     * z-faces, divided by h_zeta (by the physical height) */
+                    double Ue = t_JU(g, &T, i + 1, j, k) * cget(g, Un, i + 1, j, k), Uw = t_JU(g, &T, i, j, k) * Un[c];
+                    double Vn_ = t_JV(g, &T, i, j + 1, k) * cget(g, Vn, i, j + 1, k), Vs = t_JV(g, &T, i, j, k) * Vn[c];
+                    double Wt = W2[CIDX(g, i, j, k + 1)] - Mo[k + 1], Wb = W2[c] - Mo[k];
+                    double Jc = t_J(g, &T, i, j, k);
                     double hdiv_t = (Ue * thx1 - Uw * thx0) / dx + (Vn_ * thy1 - Vs * thy0) / dy;
                     double hdiv_r = (Ue - Uw) / dx + (Vn_ - Vs) / dy;
-                    th_hat[k] = T2[c] + dtau * (-hdiv_t - b1 * (Wt * THZ(k + 1) - Wb * THZ(k)) / dz[k] + Rt->rt[c]);
-                    rh_hat[k] = R2[c] + dtau * (-hdiv_r - b1 * (Wt - Wb) / dz[k] + Rt->rho[c]);
+                    th_hat[k] = T2[c] + dtau * (-hdiv_t / Jc - b1 * (Wt * THZ(k + 1) - Wb * THZ(k)) / Hc[k] + Rt->rt[c]);
+                    rh_hat[k] = R2[c] + dtau * (-hdiv_r / Jc - b1 * (Wt - Wb) / Hc[k] + Rt->rho[c]);
+                    if (T.on) {
+                        /* the known part -h_xi U''_new - h_eta V''_new of Omega''_new */
+                        th_hat[k] += dtau * b2 * (Mn[k + 1] * THZ(k + 1) - Mn[k] * THZ(k)) / Hc[k];
+                        rh_hat[k] += dtau * b2 * (Mn[k + 1] - Mn[k]) / Hc[k];
+                    }
                 }
                 /* Tridiagonal system for W at faces 1..nz-1, obtained by
                  * substituting Theta''_new = th_hat - dtau b2 dz(W theta_f)/dz and
@@ -848,16 +1084,18 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
                 double D = dtau * dtau * b2 * b2;
                 for (int k = 1; k < nz; ++k) {
                     size_t c = CIDX(g, i, j, k), cm = CIDX(g, i, j, k - 1);
-                    double dzf = 0.5 * (dz[k - 1] + dz[k]);
+                    size_t kb = T.on ? c : (size_t)k, kbm = T.on ? cm : (size_t)(k - 1);
+                    /* terrain: the column's physical heights in place of dz */
+                    double dzf = 0.5 * (Hc[k - 1] + Hc[k]);
                     double pif = 0.5 * (pit[cm] + pit[c]);
                     double A = GAM * R_D * (0.5 * (pim[cm] + pim[c]));
                     /* rho-bar: the base state's total density on the face */
                     double qb0 = B->qv0 ? B->qv0[k - 1] : 0.0, qb1 = B->qv0 ? B->qv0[k] : 0.0;
-                    double Cc = gr * 0.5 * (B->rho0[k - 1] * (1.0 + qb0) + B->rho0[k] * (1.0 + qb1)) * (R_D / C_V)
-                              * (pif / (0.5 * (B->pi0[k - 1] + B->pi0[k])))
+                    double Cc = gr * 0.5 * (B->rho0[kbm] * (1.0 + qb0) + B->rho0[kb] * (1.0 + qb1)) * (R_D / C_V)
+                              * (pif / (0.5 * (B->pi0[kbm] + B->pi0[kb])))
                               / (0.5 * (St->rt[cm] + St->rt[c]))
                               * (0.5 * (rdm[cm] + rdm[c]));
-                    double idzm = 1.0 / dz[k - 1], idz = 1.0 / dz[k];
+                    double idzm = 1.0 / Hc[k - 1], idz = 1.0 / Hc[k];
                     double tfm = THZ(k - 1), tf = THZ(k), tfp = THZ(k + 1);
                     ta[k - 1] = -D * (A * tfm * idzm / dzf + 0.5 * Cc * tfm * idzm - 0.5 * gr * idzm);
                     tc[k - 1] = -D * (A * tfp * idz / dzf - 0.5 * Cc * tfp * idz + 0.5 * gr * idz);
@@ -877,8 +1115,8 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
                 for (int k = 0; k < nz; ++k) {
                     size_t c = CIDX(g, i, j, k);
                     double Wt = Wn[CIDX(g, i, j, k + 1)], Wb = Wn[c];
-                    Tn[c] = th_hat[k] - dtau * b2 * (Wt * THZ(k + 1) - Wb * THZ(k)) / dz[k];
-                    Rn[c] = rh_hat[k] - dtau * b2 * (Wt - Wb) / dz[k];
+                    Tn[c] = th_hat[k] - dtau * b2 * (Wt * THZ(k + 1) - Wb * THZ(k)) / Hc[k];
+                    Rn[c] = rh_hat[k] - dtau * b2 * (Wt - Wb) / Hc[k];
                 }
                 for (int k = 0; k <= nz; ++k) {
                     size_t c = CIDX(g, i, j, k);
@@ -914,7 +1152,8 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
     }
 
     free(tht); free(pit); free(pim); free(rdm); free(U2); free(V2); free(W2); free(T2); free(R2); free(T2p);
-    free(Un); free(Vn); free(Wn); free(Tn); free(Rn); free(sU); free(sV); free(sW);
+    free(Un); free(Vn); free(Wn); free(Tn); free(Rn); free(sU); free(sV); free(sW); free(tt);
+    ter_free(&T);
     return 0;
 }
 
@@ -1052,15 +1291,18 @@ int orc_diagnostics(const orc_grid *g, const orc_params *P, const orc_base *B,
     int nx = g->nx, ny = g->ny, nz = g->nz, nq = P->n_scalars;
     size_t n = (size_t)nx * ny * nz, nw = (size_t)nx * ny * (nz + 1);
     ksum mass = {0, 0}, theta = {0, 0}, energy = {0, 0};
+    /* terrain: cell volumes dx dy Hc and the centres' physical heights */
+    ter_t Tr = ter_build(g);
     ksum *qm = (ksum *)calloc((size_t)(nq > 0 ? nq : 1), sizeof(ksum));
     double wmax = 0.0, nonfinite = 0.0;
     double z = 0.0;
     for (int k = 0; k < nz; ++k) {
-        double zc = z + 0.5 * g->dz[k];
-        double vol = g->dx * g->dy * g->dz[k];
+        double zc0 = z + 0.5 * g->dz[k];
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t c = CIDX(g, i, j, k);
+                double vol = g->dx * g->dy * t_Hc(g, &Tr, i, j, k);
+                double zc = Tr.on ? zc0 + 0.5 * (Tr.s[k] + Tr.s[k + 1]) * t_hb(g, &Tr, i, j) : zc0;
                 double r = S->rho[c], T = S->rt[c];
                 kadd(&mass, r * vol);
                 kadd(&theta, T * vol);
@@ -1095,6 +1337,7 @@ int orc_diagnostics(const orc_grid *g, const orc_params *P, const orc_base *B,
     out[4] = nonfinite;
     for (int s = 0; s < nq; ++s) out[5 + s] = qm[s].s;
     free(qm);
+    ter_free(&Tr);
     return 0;
 }
 

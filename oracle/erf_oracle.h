@@ -29,6 +29,16 @@ typedef struct {
     int32_t nx, ny, nz;
     double dx, dy;
     const double *dz; /* nz cell thicknesses */
+    /* terrain-following coordinates (App. A, App. B); NULL: flat.  Terrain
+     * heights h[ny][nx] at the nodes, node (i, j) being the low-x, low-y corner
+     * of cell (i, j) (periodic); node heights z = zeta + (1 - zeta/z_t)^beta h
+     * with zeta the flat grid's level and z_t its top.  With terrain the base
+     * state (orc_base) holds one value per cell, and the slow right-hand side,
+     * the substeps and the diagnostics take the metric terms; dry, inviscid
+     * (sgs 0, no constant viscosity, no surface layer or surface flux), no
+     * scalars, compressible only. */
+    const double *terrain;
+    double terrain_beta; /* 1: basic terrain following; 3: Sullivan */
 } orc_grid;
 
 typedef struct {
@@ -67,7 +77,7 @@ typedef struct {
 } orc_params;
 
 typedef struct {
-    const double *rho0, *theta0, *p0, *pi0; /* nz each */
+    const double *rho0, *theta0, *p0, *pi0; /* nz each (with terrain: nz*ny*nx) */
     const double *qv0;                      /* nz, base-state vapour; NULL: dry */
 } orc_base;
 
@@ -85,6 +95,18 @@ int orc_base_state(int32_t nz, const double *dz, const double *theta0, double p_
  * the moist EOS and the weight of the vapour, dp0/dz = -g rho0 (1 + qv0). */
 int orc_base_state_moist(int32_t nz, const double *dz, const double *theta0, const double *qv0,
                          double p_surface, double grav, double *rho0, double *p0, double *pi0);
+
+/* Terrain geometry (App. A, App. B): the physical height Hc[n] of every cell
+ * (its four vertical edges averaged) and the height zc[n] of its centre (its
+ * eight nodes averaged); either may be NULL.  Flat grids give dz and the flat
+ * centre heights. */
+int orc_terrain_heights(const orc_grid *g, double *Hc, double *zc);
+/* Hydrostatic base state of every column (dry) from theta0[n] at the cell
+ * centres and the pressure p_surf[ny][nx] at each column's ground, with the
+ * column's physical cell heights; rho0, p0, pi0 [n].  On a flat grid every
+ * column equals orc_base_state's. */
+int orc_base_state_columns(const orc_grid *g, const double *theta0, const double *p_surf, double grav,
+                           double *rho0, double *p0, double *pi0);
 
 /* Equation of state, Sec. 2.1: p = P00 (R_d Theta / P00)^gamma. */
 double orc_eos_p(double Theta);

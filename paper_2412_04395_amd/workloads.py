@@ -402,6 +402,62 @@ def small(name: str = "bubble_small", **kw) -> Config:
     return Config(**base)
 
 
+# ---- terrain-following coordinates (Sec. 3.4, Sec. 4.3) --------------------
+def agnesi_nodes(cfg: Config, h_m: float, a: float, ridge: bool = False) -> np.ndarray:
+    """Terrain heights h[ny][nx] at the nodes (node (i, j) at x = i dx, y = j dy,
+    the low corner of cell (i, j)) of a Witch of Agnesi hill of height h_m and
+    half-width a centred in the periodic domain: h_m / (1 + r^2 / a^2), with r
+    the distance to the centre (ridge: the x distance only, a 2-D ridge along y)."""
+    x = np.arange(cfg.nx) * cfg.dx - 0.5 * cfg.nx * cfg.dx
+    y = np.arange(cfg.ny) * cfg.dy - 0.5 * cfg.ny * cfg.dy
+    X, Y = np.meshgrid(x, y)
+    r2 = X * X if ridge else X * X + Y * Y
+    return np.ascontiguousarray(h_m / (1.0 + r2 / (a * a)))
+
+
+def sinusoid_nodes(cfg: Config, amp: float, mx: int = 1, my: int = 0) -> np.ndarray:
+    """Periodic terrain amp (1 + sin(2 pi mx x / Lx) sin... ) / 2 >= 0 at the nodes:
+    amp (1 + sin(2 pi mx x / Lx + 2 pi my y / Ly)) / 2."""
+    x = np.arange(cfg.nx) / cfg.nx
+    y = np.arange(cfg.ny) / cfg.ny
+    X, Y = np.meshgrid(x, y)
+    return np.ascontiguousarray(0.5 * amp * (1.0 + np.sin(2.0 * np.pi * (mx * X + my * Y))))
+
+
+def stratified_theta(z: np.ndarray, theta_s: float, N: float, grav: float) -> np.ndarray:
+    """Potential temperature of constant buoyancy frequency N at heights z."""
+    return theta_s * np.exp(N * N * z / grav)
+
+
+def stratified_ground_pressure(h: np.ndarray, theta_s: float, N: float, p_sea: float, grav: float) -> np.ndarray:
+    """Pressure at height h of the hydrostatic, constant-N atmosphere with
+    p = p_sea at z = 0 (the Exner function falls by g/(c_p theta) per metre;
+    N = 0: constant theta): the ground pressure of a column standing on h."""
+    pi_s = (p_sea / _P00) ** (_RD / _CP)
+    if N == 0.0:
+        pi = pi_s - grav * h / (_CP * theta_s)
+    else:
+        pi = pi_s - grav * grav / (_CP * theta_s * N * N) * (1.0 - np.exp(-N * N * h / grav))
+    return _P00 * pi ** (_CP / _RD)
+
+
+def cell_mean_nodes(h: np.ndarray) -> np.ndarray:
+    """The mean of the four corner nodes of every cell (periodic), (ny, nx)."""
+    return 0.25 * (h + np.roll(h, -1, 1) + np.roll(h, -1, 0) + np.roll(np.roll(h, -1, 0), -1, 1))
+
+
+def terrain_hill(**kw) -> Config:
+    """Flow over a Witch of Agnesi hill like the terrain case of Sec. 4.3, in 3-D
+    and periodic: 256 x 256 x 128 cells of 200 m, levels stretched from 40 m to a
+    20 km lid, 10 m/s across a 400 m hill of 2 km half-width in a constant-N
+    (0.01 1/s) atmosphere; inviscid, 3rd-order advection."""
+    base = dict(name="terrain", nx=256, ny=256, nz=128, dx=200.0, dy=200.0,
+                dz=stretched_dz(128, 40.0, 400.0, 20000.0), dt=1.0, n_substeps=6, steps=10,
+                adv_order_h=3, adv_order_v=3, seed=91)
+    base.update(kw)
+    return Config(**base)
+
+
 CONFIGS = {
     "bubble2d": bubble2d,
     "cbl": cbl,
