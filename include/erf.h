@@ -215,6 +215,38 @@ int64_t erf_workspace_bytes(const erf_ctx *ctx);
 erf_status erf_init_base_state(erf_ctx *ctx, const double *theta0, const double *qv0, double p_surface,
                                double *rho0, double *p0, double *pi0);
 
+/* Terrain-following coordinates (Sec. 3.4, App. A, App. B, App. C).  h: host
+ * array [ny][nx] of terrain heights [m] at the nodes, node (i, j) being the
+ * low-x, low-y corner of cell (i, j), periodic; beta: the smoothing exponent
+ * of z = zeta + (1 - zeta / z_t)^beta h (1: basic terrain following, 3:
+ * Sullivan; 1 <= beta <= 8), zeta the flat grid's level and z_t its top.  The
+ * geometry is copied to the device.  From then on erf_slow_rhs,
+ * erf_acoustic_substeps, erf_rk3_step and erf_diagnostics take the metric
+ * terms: horizontal fluxes weighted by h_zeta, rho Omega = rho w - h_xi rho u -
+ * h_eta rho v through the z-faces (App. A; the momenta averaged from the four
+ * faces around each z-face and h_xi, h_eta there by fourth-order differences,
+ * App. B), divergences divided by h_zeta, and the horizontal pressure gradient
+ * p_xi - h_xi (p_zeta / h_zeta) (App. B; one-sided vertical differences in the
+ * lowest and highest cells); the substeps likewise with Omega'' (App. C).
+ * Needs a dry, inviscid (sgs none, nu_m = alpha_m = 0) ERF_FP64 compressible
+ * context without scalars, surface layer or surface flux, not an ensemble
+ * member (ERF_E_UNSUPPORTED otherwise); ERF_E_ARG for non-finite heights or a
+ * terrain so high that a cell would have no positive height.  Invalidates the
+ * base state: erf_init_base_state_columns must follow (erf_init_base_state is
+ * refused).  Synchronous; allocates the terrain arrays on the first call. */
+erf_status erf_set_terrain(erf_ctx *ctx, const double *h, double beta);
+/* The physical height Hc [n] of every cell (the mean of its four vertical
+ * edges) and the height zc [n] of its centre (the mean of its eight nodes),
+ * host arrays in cell order; either may be NULL.  ERF_E_STATE without terrain. */
+erf_status erf_terrain_heights(const erf_ctx *ctx, double *Hc, double *zc);
+/* Hydrostatic base state of every column of a terrain context (as
+ * erf_init_base_state, along the column's physical cell heights) from theta0
+ * [nz][ny][nx] at the cell centres and the pressure p_surf [ny][nx] at each
+ * column's ground (host arrays); optional host outputs rho0, p0, pi0 [n].
+ * ERF_E_STATE without terrain; synchronous. */
+erf_status erf_init_base_state_columns(erf_ctx *ctx, const double *theta0, const double *p_surf, double *rho0,
+                                       double *p0, double *pi0);
+
 /* Slow right-hand side f(S) of eqs. (con), (mom), (theta) (Sec. 2.1): flux-form
  * advection with the interpolants of Sec. 3.6, the perturbation pressure
  * gradient, buoyancy -(rho - rho0) g on z-faces, the stress tensor of

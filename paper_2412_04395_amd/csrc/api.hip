@@ -267,6 +267,7 @@ void erf_destroy(erf_ctx *c)
     if (c->arena) (void)hipFree(c->arena);
     if (c->mlp.alloc) (void)hipFree(c->mlp.alloc);
     if (c->mlp.talloc) (void)hipFree(c->mlp.talloc);
+    if (c->ter.mem) (void)hipFree(c->ter.mem);
     delete[] c->dz_host;
     delete c;
 }
@@ -277,6 +278,7 @@ erf_status erf_init_base_state(erf_ctx *c, const double *theta0, const double *q
     ERF_CHECK_CTX(c);
     if (!theta0) return fail(c, ERF_E_ARG, "theta0 is NULL");
     if (qv0 && !c->prm.moist) return fail(c, ERF_E_ARG, "qv0 given to a dry context");
+    if (c->ter.on) return fail(c, ERF_E_UNSUPPORTED, "a terrain context takes erf_init_base_state_columns");
     const int nz = c->d.nz;
     double *h = new double[7 * nz];
     double *rho0 = h, *p0 = h + nz, *pi0 = h + 2 * nz, *Th0 = h + 3 * nz, *th0 = h + 4 * nz;
@@ -312,6 +314,136 @@ erf_status erf_init_base_state(erf_ctx *c, const double *theta0, const double *q
     return ERF_OK;
 }
 
+// ---- terrain-following coordinates (Sec. 3.4, App. A, App. B) ----------------
+erf_status erf_set_terrain(erf_ctx *c, const double *h, double beta)
+{
+    ERF_CHECK_CTX(c);
+    if (!h) return fail(c, ERF_E_ARG, "terrain heights are NULL");
+    const erf_params &p = c->prm;
+    if (p.precision != ERF_FP64 || p.moist || p.anelastic || p.sgs != ERF_SGS_NONE || p.nu_m != 0.0 ||
+        p.alpha_m != 0.0 || p.most_z0 > 0.0 || p.surf_heat_flux != 0.0 || p.n_scalars != 0 || c->member)
+        return fail(c, ERF_E_UNSUPPORTED,
+                    "terrain needs a dry, inviscid ERF_FP64 compressible context without scalars, surface layer "
+                    "or surface flux");
+    if (!(beta >= 1.0 && beta <= 8.0)) return fail(c, ERF_E_ARG, "beta must lie in [1, 8]");
+    const int nx = c->d.nx, ny = c->d.ny, nz = c->d.nz, nxy = c->d.nxy;
+    const size_t n = (size_t)c->d.n, nw = (size_t)c->d.nw;
+    std::vector<double> sl(nz + 1), hb(nxy), Hc(n), zc(n);
+    double zt = 0.0;
+    for (int k = 0; k < nz; ++k) zt += c->dz_host[k];
+    double zeta = 0.0;
+    for (int k = 0; k <= nz; ++k) {
+        sl[k] = (k == nz) ? 0.0 : std::pow(1.0 - zeta / zt, beta);
+        if (k < nz) zeta += c->dz_host[k];
+    }
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const int i1 = (i + 1) % nx, j1 = (j + 1) % ny;
+            const double a = h[(size_t)j * nx + i], b = h[(size_t)j * nx + i1];
+            const double e = h[(size_t)j1 * nx + i], f = h[(size_t)j1 * nx + i1];
+            if (!std::isfinite(a)) return fail(c, ERF_E_ARG, "terrain heights must be finite");
+            hb[(size_t)j * nx + i] = 0.25 * ((a + b) + (e + f));
+        }
+    zeta = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        for (int q = 0; q < nxy; ++q) {
+            const size_t cc = (size_t)k * nxy + q;
+            Hc[cc] = c->dz_host[k] + (sl[k + 1] - sl[k]) * hb[q];
+            zc[cc] = (zeta + 0.5 * c->dz_host[k]) + 0.5 * (sl[k] + sl[k + 1]) * hb[q];
+            if (!(Hc[cc] > 0.0)) return fail(c, ERF_E_ARG, "terrain too high: a cell of non-positive height");
+        }
+        zeta += c->dz_host[k];
+    }
+    Terrain &t = c->ter;
+    if (!t.mem) {
+        const size_t doubles = (size_t)(nz + 1) + nxy + 8 * n + 3 * nw;
+        hipError_t e = hipMalloc(&t.mem, doubles * sizeof(double));
+        if (e != hipSuccess) {
+            t.mem = nullptr;
+            return fail(c, ERF_E_NOMEM, "terrain arrays do not fit");
+        }
+        double *m = (double *)t.mem;
+        t.s = m, m += nz + 1;
+        t.hb = m, m += nxy;
+        t.Hc = m, m += n;
+        t.rho0 = m, m += n;
+        t.theta0 = m, m += n;
+        t.Theta0 = m, m += n;
+        t.p0 = m, m += n;
+        t.pi0 = m, m += n;
+        t.tht = m, m += n;
+        t.rh = m, m += n;
+        t.om = m, m += nw;
+        t.cp = m, m += nw;
+        t.dp = m;
+    }
+    hipError_t e = hipMemcpyAsync(t.s, sl.data(), (nz + 1) * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(t.hb, hb.data(), nxy * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(t.Hc, Hc.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "uploading the terrain geometry");
+    t.Hc_host = std::move(Hc);
+    t.zc_host = std::move(zc);
+    t.beta = beta;
+    t.on = true;
+    c->have_base = false;
+    return ERF_OK;
+}
+
+erf_status erf_terrain_heights(const erf_ctx *c, double *Hc, double *zc)
+{
+    if (!c) return ERF_E_ARG;
+    if (!c->ter.on) return ERF_E_STATE;
+    const size_t n = (size_t)c->d.n;
+    if (Hc) std::memcpy(Hc, c->ter.Hc_host.data(), n * sizeof(double));
+    if (zc) std::memcpy(zc, c->ter.zc_host.data(), n * sizeof(double));
+    return ERF_OK;
+}
+
+erf_status erf_init_base_state_columns(erf_ctx *c, const double *theta0, const double *p_surf, double *rho0_out,
+                                       double *p0_out, double *pi0_out)
+{
+    ERF_CHECK_CTX(c);
+    if (!c->ter.on) return fail(c, ERF_E_STATE, "erf_set_terrain must come first");
+    if (!theta0 || !p_surf) return fail(c, ERF_E_ARG, "theta0 or p_surf is NULL");
+    const int nz = c->d.nz, nxy = c->d.nxy;
+    const size_t n = (size_t)c->d.n;
+    std::vector<double> rho0(n), p0(n), pi0(n), th(n), Th0(n);
+    std::vector<double> hcol(nz), tcol(nz), rc(nz), pc(nz), ic(nz);
+    for (int q = 0; q < nxy; ++q) {
+        for (int k = 0; k < nz; ++k) {
+            hcol[k] = c->ter.Hc_host[(size_t)k * nxy + q];
+            tcol[k] = theta0[(size_t)k * nxy + q];
+        }
+        if (!(p_surf[q] > 0.0)) return fail(c, ERF_E_ARG, "p_surf must be positive");
+        erf_status s = base_state(nz, hcol.data(), tcol.data(), nullptr, p_surf[q], c->prm.grav, rc.data(),
+                                  pc.data(), ic.data());
+        if (s != ERF_OK) return fail(c, s, "base state: invalid theta0");
+        for (int k = 0; k < nz; ++k) {
+            const size_t cc = (size_t)k * nxy + q;
+            rho0[cc] = rc[k];
+            p0[cc] = pc[k];
+            pi0[cc] = ic[k];
+            th[cc] = tcol[k];
+            Th0[cc] = rc[k] * tcol[k];
+        }
+    }
+    Terrain &t = c->ter;
+    const size_t B = n * sizeof(double);
+    hipError_t e = hipMemcpyAsync(t.rho0, rho0.data(), B, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(t.theta0, th.data(), B, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(t.Theta0, Th0.data(), B, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(t.p0, p0.data(), B, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(t.pi0, pi0.data(), B, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "uploading the base state");
+    if (rho0_out) std::memcpy(rho0_out, rho0.data(), B);
+    if (p0_out) std::memcpy(p0_out, p0.data(), B);
+    if (pi0_out) std::memcpy(pi0_out, pi0.data(), B);
+    c->have_base = true;
+    return ERF_OK;
+}
+
 static bool state_ok(const erf_state *S, bool need_q, int nq)
 {
     return S && S->rho && S->rhotheta && S->rhou && S->rhov && S->rhow && (!need_q || nq == 0 || S->rhoq);
@@ -328,6 +460,10 @@ erf_status erf_slow_rhs(erf_ctx *c, const erf_state *S, erf_state *R)
     if ((c->prm.moist || tke) && !S->rhoq) return fail(c, ERF_E_ARG, "this context needs S->rhoq");
     const void *s5[5] = {S->rho, S->rhotheta, S->rhou, S->rhov, S->rhow};
     void *r5[5] = {R->rho, R->rhotheta, R->rhou, R->rhov, R->rhow};
+    if (c->ter.on) {
+        hipError_t e = launch_terrain_rhs(c, s5, r5);
+        return e == hipSuccess ? ERF_OK : hip_fail(c, e, "terrain slow rhs launch");
+    }
     hipError_t e = launch_slow_rhs(c, s5, (c->prm.moist || tke) ? S->rhoq : nullptr, r5);
     return e == hipSuccess ? ERF_OK : hip_fail(c, e, "slow rhs launch");
 }
@@ -346,6 +482,12 @@ erf_status erf_acoustic_substeps(erf_ctx *c, const erf_state *Sn, const erf_stat
     const void *st[5] = {St->rho, St->rhotheta, St->rhou, St->rhov, St->rhow};
     const void *rt[5] = {Rt->rho, Rt->rhotheta, Rt->rhou, Rt->rhov, Rt->rhow};
     void *so[5] = {Sout->rho, Sout->rhotheta, Sout->rhou, Sout->rhov, Sout->rhow};
+    if (c->ter.on) {
+        // a terrain context has no scalars, so no stage-averaged fluxes are kept
+        if (flux) return fail(c, ERF_E_UNSUPPORTED, "a terrain context keeps no stage-averaged fluxes");
+        hipError_t e = launch_terrain_stage(c, sn, st, rt, n_sub, dtau, so);
+        return e == hipSuccess ? ERF_OK : hip_fail(c, e, "terrain acoustic substeps launch");
+    }
     hipError_t e = launch_acoustic_stage(c, sn, st, c->prm.moist ? St->rhoq : nullptr, rt, n_sub, dtau, so,
                                          flux ? flux->rhou : nullptr,
                                          flux ? flux->rhov : nullptr, flux ? flux->rhow : nullptr);

@@ -16,7 +16,7 @@ PKG = os.path.dirname(HERE)
 OUT = os.path.join(PKG, "liberf.so")
 BUILD = os.path.join(PKG, "_build")
 SOURCES = ["api.hip", "rhs.hip", "acoustic.hip", "scalars.hip", "diag.hip", "mlp.hip", "mlp_api.hip", "ensemble.hip",
-           "tune.hip", "micro.hip", "anelastic.hip"]
+           "tune.hip", "micro.hip", "anelastic.hip", "terrain.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -23,6 +23,9 @@ struct DiagArgs {
     int nq;
     double dx, dy, g;
     const double *dz, *zc, *rho0, *Theta0;
+    // terrain (null without): physical cell heights [n], corner-mean terrain
+    // height per column and s_k = (1 - zeta_k / z_t)^beta [nz + 1]
+    const double *Hc, *hb, *sl;
     const T *rho, *rt, *ru, *rv, *rw, *rq;
     double *part;
 };
@@ -95,7 +98,9 @@ __global__ __launch_bounds__(kThreads) void k_diag_partial(DiagArgs<T> a)
             acc[3].s = fmax(acc[3].s, wv);
         }
         if (k == d.nz) continue;
-        double vol = a.dx * a.dy * a.dz[k];
+        // terrain: the cell's physical volume and its centre's height
+        double vol = a.Hc ? a.dx * a.dy * a.Hc[c] : a.dx * a.dy * a.dz[k];
+        const double zck = a.Hc ? a.zc[k] + 0.5 * (a.sl[k] + a.sl[k + 1]) * a.hb[rem] : a.zc[k];
         double r = rh(c, k), Tf = full_of(a.rt, c, a.Theta0[k]), U = a.ru[c], V = a.rv[c];
         acc[4].s += (double)bad(r) + (double)bad(Tf) + (double)bad(U) + (double)bad(V);
         cadd(acc[0], r * vol);
@@ -109,7 +114,7 @@ __global__ __launch_bounds__(kThreads) void k_diag_partial(DiagArgs<T> a)
         double wt = (k == d.nz - 1) ? 0.0 : a.rw[c + d.nxy] / (0.5 * (r + rh(c + d.nxy, k + 1)));
         double wc = 0.5 * (wb + wt);
         double temp = (Tf / r) * pow(kRd * Tf / kP00, kGamma - 1.0);
-        cadd(acc[2], (0.5 * r * (uc * uc + vc * vc + wc * wc) + r * kCv * temp + r * a.g * a.zc[k]) * vol);
+        cadd(acc[2], (0.5 * r * (uc * uc + vc * vc + wc * wc) + r * kCv * temp + r * a.g * zck) * vol);
         for (int s = 0; s < a.nq && s < 8; ++s) cadd(acc[5 + s], (double)a.rq[(size_t)s * d.n + c] * vol);
     }
     // partials as (s, c) pairs: slot s of block b at part[(b * kSlots + s) * 2]
@@ -160,6 +165,9 @@ hipError_t diag_t(erf_ctx *cx, const void *const S[6], double *host_out)
     a.zc = cx->base.zc();
     a.rho0 = cx->base.rho0;
     a.Theta0 = cx->base.Theta0;
+    a.Hc = cx->ter.on ? cx->ter.Hc : nullptr;
+    a.hb = cx->ter.hb;
+    a.sl = cx->ter.s;
     a.rho = (const T *)S[0];
     a.rt = (const T *)S[1];
     a.ru = (const T *)S[2];

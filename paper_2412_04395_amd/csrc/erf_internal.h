@@ -364,6 +364,23 @@ struct Base {
     int nz = 0;
 };
 
+// Terrain-following coordinates (FP64 contexts): the geometry, the base state
+// per cell and the work arrays of the terrain kernels, in one allocation.
+struct Terrain {
+    bool on = false;
+    double beta = 1.0;
+    // s_k = (1 - zeta_k / z_t)^beta [nz + 1]; the mean of each cell's four
+    // corner heights [ny][nx]; physical cell heights [n]
+    double *s = nullptr, *hb = nullptr, *Hc = nullptr;
+    // base state per cell [n]
+    double *rho0 = nullptr, *theta0 = nullptr, *Theta0 = nullptr, *p0 = nullptr, *pi0 = nullptr;
+    // rho Omega on z-faces [nw]; theta^t [n]; the substeps' rho'' before the
+    // implicit part [n]; Thomas factors c', d' on z-faces [nw]
+    double *om = nullptr, *tht = nullptr, *rh = nullptr, *cp = nullptr, *dp = nullptr;
+    void *mem = nullptr;
+    std::vector<double> Hc_host, zc_host;  // for erf_terrain_heights
+};
+
 }  // namespace erfk
 
 namespace erfk {
@@ -407,6 +424,8 @@ struct erf_ctx {
     // a member of an ensemble: its slow right-hand side keeps the single-level
     // tendency kernel (the z-marching one is not used inside ensemble graphs)
     bool member = false;
+    // terrain-following coordinates (erf_set_terrain)
+    erfk::Terrain ter;
     // kernel timing (erf_timing_begin / erf_timing_end)
     int timed_kernel = -1;
     int timed_count = 0;
@@ -418,13 +437,13 @@ namespace erfk {
 // kernel ids for the timing instrumentation
 enum KernelId { K_PREP, K_MUT, K_STRESS, K_RHS, K_STAGE_INIT, K_COEF, K_SUBSTEP, K_FINALIZE, K_MIXRATIO, K_SCALAR,
                 K_MLP, K_MLP_DIV, K_KESSLER, K_SSP, K_DIVFFTX, K_FFTY, K_POISSON, K_IFFTX, K_PROJECT, K_MOST,
-                K_TKE, K_COUNT };
+                K_TKE, K_TER_RHS, K_TER_UV, K_TER_COL, K_COUNT };
 inline const char *kernel_name(int id)
 {
     static const char *names[K_COUNT] = {"prep", "mut", "stress", "rhs", "stage_init", "coef", "substep",
                                          "finalize", "mixing_ratio", "scalar", "mlp", "mlp_div", "kessler",
                                          "ssp_update", "div_fftx", "ffty", "poisson_z", "ifftx", "project",
-                                         "most", "tke"};
+                                         "most", "tke", "ter_rhs", "ter_uv", "ter_col"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 // The batched instance KB of a kernel, launched over the block ranges of map
@@ -533,6 +552,11 @@ hipError_t launch_qavg(erf_ctx *c, const void *a, const void *b, void *out, int6
 hipError_t launch_project(erf_ctx *c, void *ru, void *rv, void *rw, double dt);
 // x-lines per block of the y transform for an ny-point transform
 int anel_ffty_cols(int nx, int ny);
+// terrain.hip (FP64 contexts with terrain): the slow right-hand side and one
+// RK stage of acoustic substeps with the metric terms
+hipError_t launch_terrain_rhs(erf_ctx *c, const void *const S[5], void *const R[5]);
+hipError_t launch_terrain_stage(erf_ctx *c, const void *const Sn[5], const void *const St[5],
+                                const void *const Rt[5], int n_sub, double dtau, void *const Sout[5]);
 // diag.hip
 size_t diag_slots_needed();
 hipError_t launch_diagnostics(erf_ctx *c, const void *const S[6], double *host_out);

@@ -96,6 +96,7 @@ erf_status erf_autotune(erf_ctx *c, erf_state *S, int32_t trials, const char *ca
     if (!c) return ERF_E_ARG;
     if (c->sticky != ERF_OK) return c->sticky;
     if (c->prm.anelastic) return tune_fail(c, ERF_E_UNSUPPORTED, "an anelastic context has no acoustic substeps");
+    if (c->ter.on) return tune_fail(c, ERF_E_UNSUPPORTED, "the terrain substeps have no tunable launch shape");
     if (!c->have_base) return tune_fail(c, ERF_E_STATE, "erf_init_base_state must come first");
     if (!S || !S->rho || !S->rhotheta || !S->rhou || !S->rhov || !S->rhow || (c->prm.n_scalars > 0 && !S->rhoq))
         return tune_fail(c, ERF_E_ARG, "null field pointer");

@@ -40,7 +40,8 @@ EXPORTS = ("erf_base_state_host", "erf_create", "erf_destroy", "erf_last_error",
            "erf_mlp_train_step", "erf_mlp_loss_grad_noalloc", "erf_mlp_fallback_count",
            "erf_ensemble_create", "erf_ensemble_destroy", "erf_ensemble_last_error", "erf_ensemble_member",
            "erf_ensemble_set_branches", "erf_ensemble_branches", "erf_ensemble_set_batched", "erf_ensemble_batched",
-           "erf_ensemble_rk3_step", "erf_ensemble_autotune")
+           "erf_ensemble_rk3_step", "erf_ensemble_autotune", "erf_set_terrain", "erf_terrain_heights",
+           "erf_init_base_state_columns")
 _NOT_STATUS = ("erf_destroy", "erf_last_error", "erf_workspace_bytes", "erf_ensemble_destroy",
                "erf_ensemble_last_error", "erf_ensemble_member", "erf_ensemble_branches", "erf_ensemble_batched")
 
@@ -118,6 +119,9 @@ def load(path: str = LIB_PATH):
             L.erf_workspace_bytes.restype = C.c_int64
             L.erf_init_base_state.argtypes = [C.c_void_p, _DP, _DP, C.c_double, _DP, _DP, _DP]
             L.erf_slow_rhs.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(State)]
+            L.erf_set_terrain.argtypes = [C.c_void_p, _DP, C.c_double]
+            L.erf_terrain_heights.argtypes = [C.c_void_p, _DP, _DP]
+            L.erf_init_base_state_columns.argtypes = [C.c_void_p, _DP, _DP, _DP, _DP, _DP]
             L.erf_acoustic_substeps.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(State), C.POINTER(State),
                                                 C.c_int32, C.c_double, C.POINTER(State), C.POINTER(State)]
             L.erf_scalar_advance.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(State), C.POINTER(State),
@@ -286,6 +290,36 @@ class Solver:
         self._check(self.L.erf_init_base_state(self.h, _np_ptr(th), qp, ps, _np_ptr(rho0), _np_ptr(p0),
                                                _np_ptr(pi0)), "erf_init_base_state")
         self.base = {"rho0": rho0, "theta0": th, "p0": p0, "pi0": pi0, "qv0": np.zeros(nz) if qv is None else qv}
+        return self.base
+
+    # -- terrain-following coordinates ------------------------------------------
+    def set_terrain(self, h_nodes, beta: float = 1.0):
+        """erf_set_terrain: terrain heights h[ny][nx] at the nodes (node (i, j)
+        the low-x, low-y corner of cell (i, j)); beta 1 basic, 3 Sullivan."""
+        cfg = self.cfg
+        h = np.ascontiguousarray(h_nodes, dtype=np.float64)
+        if h.shape != (cfg.ny, cfg.nx):
+            raise ValueError("terrain heights must be (ny, nx)")
+        self._check(self.L.erf_set_terrain(self.h, _np_ptr(h), float(beta)), "erf_set_terrain")
+        self.base = None
+
+    def terrain_heights(self):
+        """(Hc, zc): physical cell heights and centre heights, (nz, ny, nx)."""
+        shp = (self.cfg.nz, self.cfg.ny, self.cfg.nx)
+        Hc, zc = np.zeros(shp), np.zeros(shp)
+        self._check(self.L.erf_terrain_heights(self.h, _np_ptr(Hc), _np_ptr(zc)), "erf_terrain_heights")
+        return Hc, zc
+
+    def init_base_state_columns(self, theta0, p_surf):
+        """erf_init_base_state_columns: theta0 (nz, ny, nx) at the cell centres,
+        p_surf (ny, nx) at each column's ground."""
+        shp = (self.cfg.nz, self.cfg.ny, self.cfg.nx)
+        th = np.ascontiguousarray(np.broadcast_to(theta0, shp), dtype=np.float64)
+        ps = np.ascontiguousarray(np.broadcast_to(p_surf, shp[1:]), dtype=np.float64)
+        rho0, p0, pi0 = np.zeros(shp), np.zeros(shp), np.zeros(shp)
+        self._check(self.L.erf_init_base_state_columns(self.h, _np_ptr(th), _np_ptr(ps), _np_ptr(rho0), _np_ptr(p0),
+                                                       _np_ptr(pi0)), "erf_init_base_state_columns")
+        self.base = {"rho0": rho0, "theta0": th, "p0": p0, "pi0": pi0, "qv0": None}
         return self.base
 
     # -- states ----------------------------------------------------------------

@@ -1,0 +1,203 @@
+"""Terrain-following coordinates (Sec. 3.4, App. A, App. B, App. C) of the HIP
+path against the FP64 oracle, through the C-ABI (include/erf.h:
+erf_set_terrain, erf_init_base_state_columns).
+
+Tolerances as for the flat compressible path: 1e-13 of each field's scale for
+one call, 1e-12 after a few RK3 steps.  The geometry and the per-column base
+state are host arithmetic in the same order on both sides and must agree bit
+for bit.  At the size of the benchmark's terrain workload (256 x 256 x 128,
+too large for the oracle in a test) the checks are properties that hold at any
+size: a resting atmosphere stays at rest bit for bit, and mass and sum rho
+theta dV are conserved to roundoff.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_04395_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CALL_TOL = 1e-13
+STEPS_TOL = 1e-12
+TH_S, N_BV, P_SEA = 300.0, 0.01, 1.0e5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cfg(**kw):
+    base = dict(name="terrain_small", nx=40, ny=21, nz=17, dx=200.0, dy=200.0,
+                dz=W.stretched_dz(17, 40.0, 400.0, 4000.0), dt=1.0, n_substeps=6, adv_order_h=3,
+                adv_order_v=3, f_cor=1e-4, Ug=10.0, Vg=2.0, seed=13)
+    base.update(kw)
+    return W.small(**base)
+
+
+def _inputs(cfg, h, Hc, zc):
+    th0 = W.stratified_theta(zc, TH_S, N_BV, cfg.grav)
+    ps = W.stratified_ground_pressure(W.cell_mean_nodes(h), TH_S, N_BV, P_SEA, cfg.grav)
+    return th0, ps
+
+
+def _sides(cfg, h, beta):
+    from paper_2412_04395_amd import erf
+    o = oracle.Oracle(cfg)
+    o.set_terrain(h, beta)
+    Hc, zc = o.terrain_heights()
+    s = erf.Solver(cfg)
+    s.set_terrain(h, beta)
+    Hg, zg = s.terrain_heights()
+    assert np.array_equal(Hc, Hg) and np.array_equal(zc, zg)
+    th0, ps = _inputs(cfg, h, Hc, zc)
+    b = o.init_base_state_columns(th0, ps)
+    bs = s.init_base_state_columns(th0, ps)
+    for f in ("rho0", "p0", "pi0"):
+        assert np.array_equal(b[f], bs[f]), f
+    return o, s, b, Hc
+
+
+def _flow(b, seed, U=10.0, V=2.0):
+    shp = b["rho0"].shape
+    nz, ny, nx = shp
+    rho = b["rho0"] * (1.0 + W.uniform_noise(seed, shp, 1e-3))
+    S = {"rho": rho, "rt": b["rho0"] * b["theta0"] * (1.0 + W.uniform_noise(seed + 1, shp, 1e-3)),
+         "ru": rho * (U + W.uniform_noise(seed + 2, shp, 1.0)),
+         "rv": rho * (V + W.uniform_noise(seed + 3, shp, 1.0)),
+         "rw": W.uniform_noise(seed + 4, (nz + 1, ny, nx), 0.3), "rq": np.zeros((0, nz, ny, nx))}
+    S["rw"][0] = S["rw"][-1] = 0.0
+    return {k: np.ascontiguousarray(v) for k, v in S.items()}
+
+
+def _errs(got, ref, b, fields):
+    out = {}
+    for f in fields:
+        g, r = got[f], ref[f]
+        if f == "rho":
+            g, r = g - b["rho0"], r - b["rho0"]
+        if f == "rt":
+            T0 = b["rho0"] * b["theta0"]
+            g, r = g - T0, r - T0
+        out[f] = float(np.max(np.abs(g - r)) / max(np.max(np.abs(r)), 1e-300))
+    return out
+
+
+CASES = {
+    "btf_o3": dict(beta=1.0, kw={}),
+    "sullivan_o5": dict(beta=3.0, kw=dict(adv_order_h=5, adv_order_v=3)),
+    "btf_o6_ragged": dict(beta=1.0, kw=dict(nx=70, ny=9, nz=20, dz=W.stretched_dz(20, 30.0, 400.0, 4000.0),
+                                            adv_order_h=6, adv_order_v=4)),
+    "ridge_o2": dict(beta=3.0, kw=dict(adv_order_h=2, adv_order_v=2), ridge=True),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_slow_rhs_and_substeps_match_oracle(case):
+    spec = CASES[case]
+    cfg = _cfg(**spec["kw"])
+    h = W.agnesi_nodes(cfg, 400.0, 1000.0, ridge=spec.get("ridge", False))
+    o, s, b, Hc = _sides(cfg, h, spec["beta"])
+    S = _flow(b, 100)
+    R = o.slow_rhs(S)
+    Sg = s.to_device(S)
+    Rg = s.slow_rhs(Sg)
+    e = _errs(s.to_numpy(Rg), R, b, ("rho", "rt", "ru", "rv", "rw"))
+    _say(f"terrain slow rhs {case}:", {k: f"{v:.2e}" for k, v in e.items()})
+    for k, v in e.items():
+        assert v <= CALL_TOL, (k, v)
+    # one stage of substeps from S'' = S_n - S_t with the oracle's tendencies
+    Sn = _flow(b, 200)
+    out, _ = o.acoustic_substeps(Sn, S, R, 3, cfg.dt / cfg.n_substeps)
+    outg, _ = s.acoustic_substeps(s.to_device(Sn), Sg, s.to_device(R), 3, cfg.dt / cfg.n_substeps, sums=False)
+    e = _errs(s.to_numpy(outg), out, b, ("rho", "rt", "ru", "rv", "rw"))
+    _say(f"terrain substeps {case}:", {k: f"{v:.2e}" for k, v in e.items()})
+    for k, v in e.items():
+        assert v <= CALL_TOL, (k, v)
+
+
+def test_rk3_steps_and_diagnostics_match_oracle():
+    cfg = _cfg()
+    h = W.agnesi_nodes(cfg, 400.0, 1000.0)
+    o, s, b, Hc = _sides(cfg, h, 3.0)
+    S = _flow(b, 300)
+    Sg = s.to_device(S)
+    for _ in range(3):
+        o.rk3_step(S)
+        s.rk3_step(Sg)
+    got = s.to_numpy(Sg)
+    e = _errs(got, S, b, ("rho", "rt", "ru", "rv", "rw"))
+    _say("terrain rk3 x3:", {k: f"{v:.2e}" for k, v in e.items()})
+    for k, v in e.items():
+        assert v <= STEPS_TOL, (k, v)
+    d_o, d_g = o.diagnostics(S), s.diagnostics(Sg)
+    for k in ("mass", "theta_mass", "energy"):
+        assert d_g[k] == pytest.approx(d_o[k], rel=1e-12), k
+
+
+def test_single_level_column():
+    # nz = 2: the one interior face's tridiagonal row and one-sided vertical
+    # differences everywhere
+    cfg = _cfg(nz=2, dz=np.array([300.0, 500.0]))
+    h = W.agnesi_nodes(cfg, 100.0, 800.0)
+    o, s, b, Hc = _sides(cfg, h, 1.0)
+    S = _flow(b, 400)
+    Sg = s.to_device(S)
+    for _ in range(2):
+        o.rk3_step(S)
+        s.rk3_step(Sg)
+    e = _errs(s.to_numpy(Sg), S, b, ("rho", "rt", "ru", "rv", "rw"))
+    _say("terrain nz=2 rk3 x2:", {k: f"{v:.2e}" for k, v in e.items()})
+    for k, v in e.items():
+        assert v <= STEPS_TOL, (k, v)
+
+
+def test_refusals():
+    from paper_2412_04395_amd import erf
+    cfg = _cfg()
+    h = W.agnesi_nodes(cfg, 400.0, 1000.0)
+    for kw in (dict(sgs=1), dict(n_scalars=1), dict(prec="fp32"), dict(nu_m=1.0)):
+        s = erf.Solver(cfg.replace(**kw))
+        with pytest.raises(RuntimeError):
+            s.set_terrain(h, 1.0)
+    s = erf.Solver(cfg)
+    with pytest.raises(RuntimeError):
+        s.set_terrain(np.full((cfg.ny, cfg.nx), 5000.0), 1.0)  # above the lid
+    s.set_terrain(h, 1.0)
+    with pytest.raises(RuntimeError):
+        s.init_base_state(np.full(cfg.nz, 300.0))
+
+
+def test_benchmark_size_rest_and_conservation():
+    from paper_2412_04395_amd import erf
+    cfg = W.terrain_hill()
+    h = W.agnesi_nodes(cfg, 400.0, 2000.0)
+    s = erf.Solver(cfg)
+    s.set_terrain(h, 1.0)
+    Hc, zc = s.terrain_heights()
+    th0, ps = _inputs(cfg, h, Hc, zc)
+    b = s.init_base_state_columns(th0, ps)
+    shp = b["rho0"].shape
+    rest = {"rho": b["rho0"], "rt": b["rho0"] * b["theta0"], "ru": np.zeros(shp), "rv": np.zeros(shp),
+            "rw": np.zeros((shp[0] + 1,) + shp[1:]), "rq": np.zeros((0,) + shp)}
+    Sg = s.to_device(rest)
+    s0 = {k: v.clone() for k, v in Sg.items()}
+    s.rk3_step(Sg)
+    for f in ("rho", "rt", "ru", "rv", "rw"):
+        assert bool((Sg[f] == s0[f]).all()), f
+    # a wind over the hill: mass and sum rho theta dV are conserved
+    S = {"rho": b["rho0"], "rt": b["rho0"] * b["theta0"], "ru": b["rho0"] * 10.0, "rv": np.zeros(shp),
+         "rw": np.zeros((shp[0] + 1,) + shp[1:]), "rq": np.zeros((0,) + shp)}
+    Sg = s.to_device({k: np.ascontiguousarray(v) for k, v in S.items()})
+    d0 = s.diagnostics(Sg)
+    for _ in range(3):
+        s.rk3_step(Sg)
+    d1 = s.diagnostics(Sg)
+    _say("terrain 256x256x128 mass, theta-mass drift:", d1["mass"] / d0["mass"] - 1.0,
+         d1["theta_mass"] / d0["theta_mass"] - 1.0, "max w", d1["max_w"])
+    assert abs(d1["mass"] / d0["mass"] - 1.0) < 1e-13
+    assert abs(d1["theta_mass"] / d0["theta_mass"] - 1.0) < 1e-13
+    assert 0.0 < d1["max_w"] < 20.0
