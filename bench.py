@@ -597,6 +597,64 @@ def run_anelastic(steps: int, warmup: int) -> dict:
             "final_diag": {"max_w": d["max_w"], "nonfinite": d["nonfinite"]}}
 
 
+# terrain kernels: compulsory FP64 values per cell of one launch (reads +
+# writes): the slow tendencies read rho, rho u, rho v, theta, u, v, w, p',
+# rho Omega, the cell height and rho0 and write five tendencies; the U'', V''
+# step reads Theta'' (two levels), pi^t, U'', V'', their tendencies and the
+# cell height and writes U'', V''; the metric part of Omega'' reads U'', V''
+# and writes one value per z-face; the explicit Theta'', rho'' read theta^t,
+# U'', V'', W'', Theta'', rho'', two tendencies, h_zeta, the cell height and
+# the old and new metric parts and write two; the column kernel reads the
+# cell height, pi^t, rho0, pi0, rho theta^t, theta^t, Theta'' (current and
+# explicit), rho'' (current and explicit), W'' and its tendency and writes
+# W'', Theta'', rho''
+TERRAIN_VALUES = {"ter_rhs": 16, "ter_uv": 10, "ter_m": 3, "ter_hat": 14, "ter_tri": 15}
+
+
+def run_terrain(steps: int, warmup: int) -> dict:
+    """Flow over a Witch of Agnesi hill in terrain-following coordinates (Sec.
+    3.4, 4.3): 256 x 256 x 128, FP64, basic terrain following, 10 m/s across a
+    400 m hill of 2 km half-width, constant N = 0.01 1/s, 6 substeps."""
+    import torch
+    from paper_2412_04395_amd import erf
+
+    cfg = W.terrain_hill()
+    h = W.agnesi_nodes(cfg, 400.0, 2000.0)
+    s = erf.Solver(cfg)
+    s.set_terrain(h, 1.0)
+    Hc, zc = s.terrain_heights()
+    th0 = W.stratified_theta(zc, 300.0, 0.01, cfg.grav)
+    ps = W.stratified_ground_pressure(W.cell_mean_nodes(h), 300.0, 0.01, cfg.p_surface, cfg.grav)
+    b = s.init_base_state_columns(th0, ps)
+    shp = b["rho0"].shape
+    S = s.to_device({"rho": b["rho0"], "rt": b["rho0"] * b["theta0"], "ru": b["rho0"] * 10.0,
+                     "rv": np.zeros(shp), "rw": np.zeros((shp[0] + 1,) + shp[1:]), "rq": np.zeros((0,) + shp)})
+    del Hc, zc, th0, b
+    for _ in range(warmup):
+        s.rk3_step(S)
+    shares = {}
+    for k in TERRAIN_VALUES:
+        _, (ms, n) = _time_steps(s, S, 1, torch, k)
+        if n:
+            shares[k] = (ms, n)
+    dom = max(shares, key=lambda k: shares[k][0])
+    el, (kms, kn) = _time_steps(s, S, steps, torch, dom)
+    d = s.diagnostics(S, allow_nonfinite=True)
+    s.close()
+    avg_ms = kms / max(kn, 1)
+    byts = TERRAIN_VALUES[dom] * 8.0 * cfg.cells
+    gbs = byts / (avg_ms * 1e-3) / 1e9
+    return {"workload": "flow over a Witch of Agnesi hill (400 m, half-width 2 km), terrain-following "
+                        "coordinates, 256x256x128, N = 0.01 1/s, 10 m/s",
+            "grid": [cfg.nx, cfg.ny, cfg.nz], "precision": "fp64", "n_substeps": cfg.n_substeps,
+            "value": cfg.cells * steps / el, "unit": "cell-updates/s", "ms_per_step": 1e3 * el / steps,
+            "kernel_ms_per_step": {k: round(v[0], 4) for k, v in shares.items()},
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": byts,
+                         "avg_launch_ms": round(avg_ms, 4), "launches_timed": kn},
+            "final_diag": {"max_w": d["max_w"], "nonfinite": d["nonfinite"]}}
+
+
 def _substep_value_adjust(cfg) -> float:
     """Bulk values per cell by which the average substep launch of a step
     differs from KERNEL_VALUES: +5 for the one per stage that writes the stage
@@ -647,6 +705,7 @@ def main(argv=None):
     ap.add_argument("--no-scalars", action="store_true")
     ap.add_argument("--no-anelastic", action="store_true")
     ap.add_argument("--no-tke", action="store_true")
+    ap.add_argument("--no-terrain", action="store_true")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first run one plain device copy of this many GiB (reference for HBM counters)")
     a = ap.parse_args(argv)
@@ -674,6 +733,9 @@ def main(argv=None):
         return 0
     if a.workload == "tke":
         print(json.dumps(run_tke(a.steps, a.warmup)), flush=True)
+        return 0
+    if a.workload == "terrain":
+        print(json.dumps(run_terrain(a.steps, a.warmup)), flush=True)
         return 0
     if a.workload == "closure_training":
         print(json.dumps(run_training(a.steps)), flush=True)
@@ -724,6 +786,8 @@ def main(argv=None):
         out["tke"] = run_tke(a.steps, a.warmup)
     if a.workload == "cbl" and not a.no_anelastic:
         out["anelastic"] = run_anelastic(a.steps, a.warmup)
+    if a.workload == "cbl" and not a.no_terrain:
+        out["terrain"] = run_terrain(a.steps, a.warmup)
     if a.workload == "cbl" and not a.no_ensemble:
         out["ensemble"] = run_ensemble(min(a.steps, 5), min(a.warmup, 1))
     if rank == 0 and not a.no_cpu_baseline:

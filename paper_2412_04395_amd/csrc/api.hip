@@ -356,7 +356,7 @@ erf_status erf_set_terrain(erf_ctx *c, const double *h, double beta)
     }
     Terrain &t = c->ter;
     if (!t.mem) {
-        const size_t doubles = (size_t)(nz + 1) + nxy + 8 * n + 3 * nw;
+        const size_t doubles = (size_t)(nz + 1) + nxy + 9 * n + 5 * nw;
         hipError_t e = hipMalloc(&t.mem, doubles * sizeof(double));
         if (e != hipSuccess) {
             t.mem = nullptr;
@@ -375,11 +375,18 @@ erf_status erf_set_terrain(erf_ctx *c, const double *h, double beta)
         t.rh = m, m += n;
         t.om = m, m += nw;
         t.cp = m, m += nw;
-        t.dp = m;
+        t.dp = m, m += nw;
+        t.J = m, m += n;
+        t.mo = m, m += nw;
+        t.mn = m;
     }
+    std::vector<double> Jc(n);
+    for (int k = 0; k < nz; ++k)
+        for (int q = 0; q < nxy; ++q) Jc[(size_t)k * nxy + q] = Hc[(size_t)k * nxy + q] / c->dz_host[k];
     hipError_t e = hipMemcpyAsync(t.s, sl.data(), (nz + 1) * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(t.hb, hb.data(), nxy * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(t.Hc, Hc.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(t.J, Jc.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "uploading the terrain geometry");
     t.Hc_host = std::move(Hc);

@@ -377,6 +377,9 @@ struct Terrain {
     // rho Omega on z-faces [nw]; theta^t [n]; the substeps' rho'' before the
     // implicit part [n]; Thomas factors c', d' on z-faces [nw]
     double *om = nullptr, *tht = nullptr, *rh = nullptr, *cp = nullptr, *dp = nullptr;
+    // h_zeta = Hc / dz_k per cell [n]; the metric part M of Omega'' of the old
+    // and new horizontal momenta on z-faces [nw]
+    double *J = nullptr, *mo = nullptr, *mn = nullptr;
     void *mem = nullptr;
     std::vector<double> Hc_host, zc_host;  // for erf_terrain_heights
 };
@@ -437,13 +440,13 @@ namespace erfk {
 // kernel ids for the timing instrumentation
 enum KernelId { K_PREP, K_MUT, K_STRESS, K_RHS, K_STAGE_INIT, K_COEF, K_SUBSTEP, K_FINALIZE, K_MIXRATIO, K_SCALAR,
                 K_MLP, K_MLP_DIV, K_KESSLER, K_SSP, K_DIVFFTX, K_FFTY, K_POISSON, K_IFFTX, K_PROJECT, K_MOST,
-                K_TKE, K_TER_RHS, K_TER_UV, K_TER_COL, K_COUNT };
+                K_TKE, K_TER_RHS, K_TER_UV, K_TER_COL, K_TER_M, K_TER_HAT, K_COUNT };
 inline const char *kernel_name(int id)
 {
     static const char *names[K_COUNT] = {"prep", "mut", "stress", "rhs", "stage_init", "coef", "substep",
                                          "finalize", "mixing_ratio", "scalar", "mlp", "mlp_div", "kessler",
                                          "ssp_update", "div_fftx", "ffty", "poisson_z", "ifftx", "project",
-                                         "most", "tke", "ter_rhs", "ter_uv", "ter_col"};
+                                         "most", "tke", "ter_rhs", "ter_uv", "ter_tri", "ter_m", "ter_hat"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 // The batched instance KB of a kernel, launched over the block ranges of map

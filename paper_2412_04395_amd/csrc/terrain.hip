@@ -27,10 +27,16 @@
 //   k_ter_init  S'' = S^n - S^t, theta^t and pi^t
 //   k_ter_uv    U'', V'' with the metric correction of the gradient of the
 //               predicted Theta''
-//   k_ter_col   one thread per column: explicit parts of Theta'' and rho''
-//               with Omega'' = W'' - M(U'', V''), the M of the new horizontal
-//               momenta moved to the known side, the tridiagonal W'' rows with
-//               the column's physical heights, Thomas sweeps, finish
+//   k_ter_m     M(U'', V'') of the new horizontal momenta on every z-face (the
+//               next substep reuses it as the old one)
+//   k_ter_hat   per cell, the explicit parts of Theta'' and rho'' with
+//               Omega'' = W'' - M, the M of the new horizontal momenta moved
+//               to the known side
+//   k_ter_tri   one thread per column: the tridiagonal W'' rows with the
+//               column's physical heights built on the fly, the forward sweep
+//               (the next level's values loaded while the current one is
+//               eliminated), and the back substitution fused with the
+//               implicit finish of Theta'' and rho''
 //   k_ter_fin   S_out = S^t + S''
 // All arithmetic is FP64, written in the order of the oracle's expressions so
 // that the two round alike.
@@ -45,7 +51,7 @@ constexpr int kCB = 64;   // columns per block of the column kernel
 struct Geo {
     Dims d;
     double dx, dy;
-    const double *dz, *s, *hb, *Hc;
+    const double *dz, *s, *hb, *Hc, *Jc;
 
     __device__ __forceinline__ int c(int i, int j, int k) const
     {
@@ -56,7 +62,8 @@ struct Geo {
         return hb[wrap_idx(j, d.ny) * d.nx + wrap_idx(i, d.nx)];
     }
     __device__ __forceinline__ double H(int i, int j, int k) const { return Hc[c(i, j, k)]; }
-    __device__ __forceinline__ double J(int i, int j, int k) const { return H(i, j, k) / dz[k]; }
+    // h_zeta = Hc / dz_k, tabulated at set-up
+    __device__ __forceinline__ double J(int i, int j, int k) const { return Jc[c(i, j, k)]; }
     __device__ __forceinline__ double JU(int i, int j, int k) const { return 0.5 * (J(i - 1, j, k) + J(i, j, k)); }
     __device__ __forceinline__ double JV(int i, int j, int k) const { return 0.5 * (J(i, j - 1, k) + J(i, j, k)); }
     __device__ __forceinline__ double hxU(int i, int j, int k) const
@@ -284,6 +291,7 @@ struct StA {
     const double *R_r, *R_t, *R_u, *R_v, *R_w;  // R^t
     double *tht, *pit;
     double *t2, *t2p, *u2, *v2, *un, *vn, *r2, *w2, *rh, *cp, *dp;
+    double *mo, *mn;  // M of the old and of the new horizontal momenta on z-faces
     double *o_r, *o_t, *o_u, *o_v, *o_w;
 };
 
@@ -328,90 +336,144 @@ __global__ void __launch_bounds__(kTB) k_ter_uv(StA a)
     a.vn[q] = a.v2[q] + a.dtau * (-kGamma * kRd * pfy * (tt_c - tt_s) / G.dy + kGamma * kRd * pfy * cy + a.R_v[q]);
 }
 
-// one thread per column; the column's per-level values go through the global
-// arrays (t2p receives the explicit Theta'', rh the explicit rho'', cp and dp
-// the Thomas factors), each thread touching only its own column there
-__global__ void __launch_bounds__(kCB) k_ter_col(StA a)
+// M(ru, rv) on every z-face (zero on the lids)
+__global__ void __launch_bounds__(kTB) k_ter_m(StA a, const double *ru, const double *rv, double *out)
+{
+    const Geo &G = a.G;
+    const int q = blockIdx.x * kTB + threadIdx.x;
+    if (q >= G.d.nw) return;
+    int i, j, k;
+    split(G.d, q, i, j, k);
+    out[q] = G.M(ru, rv, i, j, k);
+}
+
+__global__ void __launch_bounds__(kTB) k_ter_hat(StA a)
 {
     const Geo &G = a.G;
     const Dims &d = G.d;
+    const int c = blockIdx.x * kTB + threadIdx.x;
+    if (c >= d.n) return;
+    int i, j, k;
+    split(d, c, i, j, k);
+    const int nz = d.nz, nxy = d.nxy;
+    const double dtau = a.dtau, b1 = a.b1, b2 = a.b2;
+    const double *tht = a.tht;
+    const double thc = tht[c];
+    const double thx0 = 0.5 * (tht[G.c(i - 1, j, k)] + thc);
+    const double thx1 = 0.5 * (thc + tht[G.c(i + 1, j, k)]);
+    const double thy0 = 0.5 * (tht[G.c(i, j - 1, k)] + thc);
+    const double thy1 = 0.5 * (thc + tht[G.c(i, j + 1, k)]);
+    const double Ue = G.JU(i + 1, j, k) * a.un[G.c(i + 1, j, k)], Uw = G.JU(i, j, k) * a.un[c];
+    const double Vn_ = G.JV(i, j + 1, k) * a.vn[G.c(i, j + 1, k)], Vs = G.JV(i, j, k) * a.vn[c];
+    const double Wt = a.w2[c + nxy] - a.mo[c + nxy], Wb = a.w2[c] - a.mo[c];
+    const double Jc = G.J(i, j, k), Hk = G.Hc[c];
+    const double hdiv_t = (Ue * thx1 - Uw * thx0) / G.dx + (Vn_ * thy1 - Vs * thy0) / G.dy;
+    const double hdiv_r = (Ue - Uw) / G.dx + (Vn_ - Vs) / G.dy;
+    // face theta^t above and below the cell (zero on the lids)
+    const double tz1 = (k + 1 >= nz) ? 0.0 : 0.5 * (thc + tht[c + nxy]);
+    const double tz0 = (k <= 0) ? 0.0 : 0.5 * (tht[c - nxy] + thc);
+    double th_hat = a.t2[c] + dtau * (-hdiv_t / Jc - b1 * (Wt * tz1 - Wb * tz0) / Hk + a.R_t[c]);
+    double rh_hat = a.r2[c] + dtau * (-hdiv_r / Jc - b1 * (Wt - Wb) / Hk + a.R_r[c]);
+    const double Mn1 = a.mn[c + nxy], Mn0 = a.mn[c];
+    th_hat += dtau * b2 * (Mn1 * tz1 - Mn0 * tz0) / Hk;
+    rh_hat += dtau * b2 * (Mn1 - Mn0) / Hk;
+    a.t2p[c] = th_hat;
+    a.rh[c] = rh_hat;
+}
+
+// The per-level values of the forward sweep at one level of one column.
+struct TriLv {
+    double H, pit, r0, pi0, tt, th, t2, hat, r2, rh, w2, Rw;
+};
+
+// one thread per column; the Thomas factors go through cp, dp (own column)
+__global__ void __launch_bounds__(kCB) k_ter_tri(StA a)
+{
+    const Dims &d = a.G.d;
     const int col = blockIdx.x * kCB + threadIdx.x;
     if (col >= d.nxy) return;
-    const int j = col / d.nx, i = col - j * d.nx, nz = d.nz, nxy = d.nxy;
+    const int nz = d.nz, nxy = d.nxy, m = nz - 1;
     const double dtau = a.dtau, b1 = a.b1, b2 = a.b2, gr = a.g;
-    const double *tht = a.tht;
-    // face theta^t of this column (zero on the lids, where W is zero)
-    const auto THZ = [&](int kk) {
-        return (kk <= 0 || kk >= nz) ? 0.0 : 0.5 * (tht[col + (kk - 1) * nxy] + tht[col + kk * nxy]);
-    };
-    double Mo_k = 0.0, Mn_k = 0.0;
-    for (int k = 0; k < nz; ++k) {
+    const double *__restrict__ Hc = a.G.Hc;
+    const double *__restrict__ pit = a.pit;
+    const double *__restrict__ rho0 = a.rho0;
+    const double *__restrict__ pi0 = a.pi0;
+    const double *__restrict__ t_t = a.t_t;
+    const double *__restrict__ tht = a.tht;
+    const double *__restrict__ t2 = a.t2;
+    const double *__restrict__ R_w = a.R_w;
+    double *__restrict__ hat = a.t2p;
+    double *__restrict__ r2 = a.r2;
+    double *__restrict__ rh = a.rh;
+    double *__restrict__ w2 = a.w2;
+    double *__restrict__ cp = a.cp;
+    double *__restrict__ dp = a.dp;
+    const auto load = [&](int k) {
         const int c = col + k * nxy;
-        const double thx0 = 0.5 * (tht[G.c(i - 1, j, k)] + tht[c]);
-        const double thx1 = 0.5 * (tht[c] + tht[G.c(i + 1, j, k)]);
-        const double thy0 = 0.5 * (tht[G.c(i, j - 1, k)] + tht[c]);
-        const double thy1 = 0.5 * (tht[c] + tht[G.c(i, j + 1, k)]);
-        const double Ue = G.JU(i + 1, j, k) * a.un[G.c(i + 1, j, k)], Uw = G.JU(i, j, k) * a.un[c];
-        const double Vn_ = G.JV(i, j + 1, k) * a.vn[G.c(i, j + 1, k)], Vs = G.JV(i, j, k) * a.vn[c];
-        const double Mo_kp = G.M(a.u2, a.v2, i, j, k + 1), Mn_kp = G.M(a.un, a.vn, i, j, k + 1);
-        const double Wt = a.w2[c + nxy] - Mo_kp, Wb = a.w2[c] - Mo_k;
-        const double Jc = G.J(i, j, k), Hk = a.G.Hc[c];
-        const double hdiv_t = (Ue * thx1 - Uw * thx0) / G.dx + (Vn_ * thy1 - Vs * thy0) / G.dy;
-        const double hdiv_r = (Ue - Uw) / G.dx + (Vn_ - Vs) / G.dy;
-        const double tz1 = THZ(k + 1), tz0 = THZ(k);
-        double th_hat = a.t2[c] + dtau * (-hdiv_t / Jc - b1 * (Wt * tz1 - Wb * tz0) / Hk + a.R_t[c]);
-        double rh_hat = a.r2[c] + dtau * (-hdiv_r / Jc - b1 * (Wt - Wb) / Hk + a.R_r[c]);
-        th_hat += dtau * b2 * (Mn_kp * tz1 - Mn_k * tz0) / Hk;
-        rh_hat += dtau * b2 * (Mn_kp - Mn_k) / Hk;
-        a.t2p[c] = th_hat;
-        a.rh[c] = rh_hat;
-        Mo_k = Mo_kp;
-        Mn_k = Mn_kp;
-    }
-    // W'' at the interior faces: rows k = 1 .. nz-1, forward elimination
+        TriLv v;
+        v.H = Hc[c], v.pit = pit[c], v.r0 = rho0[c], v.pi0 = pi0[c], v.tt = t_t[c], v.th = tht[c];
+        v.t2 = t2[c], v.hat = hat[c], v.r2 = r2[c], v.rh = rh[c], v.w2 = w2[c], v.Rw = R_w[c];
+        return v;
+    };
     const double D = dtau * dtau * b2 * b2;
-    const int m = nz - 1;
-    for (int k = 1; k < nz; ++k) {
-        const int c = col + k * nxy, cm = c - nxy;
-        const double Hm = a.G.Hc[cm], Hk = a.G.Hc[c];
-        const double dzf = 0.5 * (Hm + Hk);
-        const double pif = 0.5 * (a.pit[cm] + a.pit[c]);
-        const double A = kGamma * kRd * (0.5 * (a.pit[cm] + a.pit[c]));
-        const double Cc = gr * 0.5 * (a.rho0[cm] + a.rho0[c]) * (kRd / kCv) * (pif / (0.5 * (a.pi0[cm] + a.pi0[c]))) /
-                          (0.5 * (a.t_t[cm] + a.t_t[c]));
-        const double idzm = 1.0 / Hm, idz = 1.0 / Hk;
-        const double tfm = THZ(k - 1), tf = THZ(k), tfp = THZ(k + 1);
+    TriLv lo = load(0), up = load(1);
+    double tfm = 0.0, cpm = 0.0, dpm = 0.0;  // face theta^t below, previous factors
+    for (int k = 1; k <= m; ++k) {
+        TriLv nx{};
+        if (k + 1 < nz) nx = load(k + 1);
+        const int c = col + k * nxy;
+        const double dzf = 0.5 * (lo.H + up.H);
+        const double pif = 0.5 * (lo.pit + up.pit);
+        const double A = kGamma * kRd * (0.5 * (lo.pit + up.pit));
+        const double Cc = gr * 0.5 * (lo.r0 + up.r0) * (kRd / kCv) * (pif / (0.5 * (lo.pi0 + up.pi0))) /
+                          (0.5 * (lo.tt + up.tt));
+        const double idzm = 1.0 / lo.H, idz = 1.0 / up.H;
+        const double tf = 0.5 * (lo.th + up.th), tfp = (k + 1 < nz) ? 0.5 * (up.th + nx.th) : 0.0;
         const double ta = (k == 1) ? 0.0 : -D * (A * tfm * idzm / dzf + 0.5 * Cc * tfm * idzm - 0.5 * gr * idzm);
         const double tc = (k == m) ? 0.0 : -D * (A * tfp * idz / dzf - 0.5 * Cc * tfp * idz + 0.5 * gr * idz);
         const double tb = 1.0 + D * (A * tf * (idz + idzm) / dzf + 0.5 * Cc * tf * (idzm - idz) - 0.5 * gr * (idzm - idz));
-        const double tbk = b1 * a.t2[c] + b2 * a.t2p[c], tbm = b1 * a.t2[cm] + b2 * a.t2p[cm];
-        const double rbk = b1 * a.r2[c] + b2 * a.rh[c], rbm = b1 * a.r2[cm] + b2 * a.rh[cm];
-        const double tr = a.w2[c] + dtau * (-A * (tbk - tbm) / dzf + 0.5 * Cc * (tbk + tbm) - 0.5 * gr * (rbk + rbm) + a.R_w[c]);
+        const double tbk = b1 * up.t2 + b2 * up.hat, tbm = b1 * lo.t2 + b2 * lo.hat;
+        const double rbk = b1 * up.r2 + b2 * up.rh, rbm = b1 * lo.r2 + b2 * lo.rh;
+        const double tr = up.w2 + dtau * (-A * (tbk - tbm) / dzf + 0.5 * Cc * (tbk + tbm) - 0.5 * gr * (rbk + rbm) + up.Rw);
+        double cpk, dpk;
         if (k == 1) {
-            a.cp[c] = tc / tb;
-            a.dp[c] = tr / tb;
+            cpk = tc / tb;
+            dpk = tr / tb;
         } else {
-            const double den = tb - ta * a.cp[cm];
-            a.cp[c] = tc / den;
-            a.dp[c] = (tr - ta * a.dp[cm]) / den;
+            const double den = tb - ta * cpm;
+            cpk = tc / den;
+            dpk = (tr - ta * dpm) / den;
         }
+        cp[c] = cpk;
+        dp[c] = dpk;
+        cpm = cpk, dpm = dpk;
+        tfm = tf;
+        lo = up;
+        up = nx;
     }
-    // back substitution into W'' (lids zero)
-    a.w2[col] = 0.0;
-    a.w2[col + nz * nxy] = 0.0;
-    double x = 0.0;
+    // back substitution (faces m .. 1) with the implicit finish of the cell
+    // above each face; the lids carry W'' = 0
+    w2[col] = 0.0;
+    w2[col + nz * nxy] = 0.0;
+    const auto finish = [&](int k, double Wt, double Wb, double tz1, double tz0) {
+        const int c = col + k * nxy;
+        const double H = Hc[c];
+        hat[c] = hat[c] - dtau * b2 * (Wt * tz1 - Wb * tz0) / H;
+        r2[c] = rh[c] - dtau * b2 * (Wt - Wb) / H;
+    };
+    double xup = 0.0, thu = tht[col + m * nxy], tzu = 0.0;  // W'' above, theta^t of cell k, face theta above
     for (int k = m; k >= 1; --k) {
         const int c = col + k * nxy;
-        x = (k == m) ? a.dp[c] : a.dp[c] - a.cp[c] * x;
-        a.w2[c] = x;
+        const double x = (k == m) ? dp[c] : dp[c] - cp[c] * xup;
+        w2[c] = x;
+        const double thl = tht[c - nxy];
+        const double tz = 0.5 * (thl + thu);
+        finish(k, xup, x, tzu, tz);
+        xup = x;
+        tzu = tz;
+        thu = thl;
     }
-    // implicit finish of Theta'' (into t2p, the new level) and rho''
-    for (int k = 0; k < nz; ++k) {
-        const int c = col + k * nxy;
-        const double Wt = a.w2[c + nxy], Wb = a.w2[c], Hk = a.G.Hc[c];
-        a.t2p[c] = a.t2p[c] - dtau * b2 * (Wt * THZ(k + 1) - Wb * THZ(k)) / Hk;
-        a.r2[c] = a.rh[c] - dtau * b2 * (Wt - Wb) / Hk;
-    }
+    finish(0, xup, 0.0, tzu, 0.0);
 }
 
 __global__ void __launch_bounds__(kTB) k_ter_fin(StA a)
@@ -438,6 +500,7 @@ Geo geo_of(const erf_ctx *cx)
     G.s = cx->ter.s;
     G.hb = cx->ter.hb;
     G.Hc = cx->ter.Hc;
+    G.Jc = cx->ter.J;
     return G;
 }
 
@@ -515,21 +578,34 @@ hipError_t launch_terrain_stage(erf_ctx *cx, const void *const Sn[5], const void
     a.rh = cx->ter.rh;
     a.cp = cx->ter.cp;
     a.dp = cx->ter.dp;
+    a.mo = cx->ter.mo;
+    a.mn = cx->ter.mn;
     double *const *so = (double *const *)Sout;
     a.o_r = so[0], a.o_t = so[1], a.o_u = so[2], a.o_v = so[3], a.o_w = so[4];
     const dim3 gw((cx->d.nw + kTB - 1) / kTB), gc((cx->d.n + kTB - 1) / kTB), gcol((cx->d.nxy + kCB - 1) / kCB);
     k_ter_init<<<gw, kTB, 0, cx->stream>>>(a);
+    k_ter_m<<<gw, kTB, 0, cx->stream>>>(a, a.u2, a.v2, a.mo);
     hipError_t e = hipGetLastError();
     for (int s = 0; s < n_sub && e == hipSuccess; ++s) {
         timing_start(cx, K_TER_UV);
         k_ter_uv<<<gc, kTB, 0, cx->stream>>>(a);
         timing_stop(cx, K_TER_UV);
+        timing_start(cx, K_TER_M);
+        k_ter_m<<<gw, kTB, 0, cx->stream>>>(a, a.un, a.vn, a.mn);
+        timing_stop(cx, K_TER_M);
+        timing_start(cx, K_TER_HAT);
+        k_ter_hat<<<gc, kTB, 0, cx->stream>>>(a);
+        timing_stop(cx, K_TER_HAT);
         timing_start(cx, K_TER_COL);
-        k_ter_col<<<gcol, kCB, 0, cx->stream>>>(a);
+        k_ter_tri<<<gcol, kCB, 0, cx->stream>>>(a);
         timing_stop(cx, K_TER_COL);
         e = hipGetLastError();
-        // the new Theta'' is in t2p; the new U'', V'' in un, vn
-        double *t = a.t2;
+        // the new Theta'' is in t2p, the new U'', V'' in un, vn and their M in
+        // mn (the next substep's old M)
+        double *t = a.mo;
+        a.mo = a.mn;
+        a.mn = t;
+        t = a.t2;
         a.t2 = a.t2p;
         a.t2p = t;
         t = a.u2;
