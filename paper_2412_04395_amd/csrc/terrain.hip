@@ -175,6 +175,10 @@ __device__ __forceinline__ double izw(const Geo &G, const double *f, int i, int 
     return face_interp<double>(o, q[0], q[1], q[2], q[3], q[4], q[5], sg);
 }
 
+// P selects the equations of one launch: 0 continuity and potential
+// temperature, 1 x-momentum, 2 y-momentum, 3 z-momentum (four smaller kernels
+// keep more wavefronts resident than one that evaluates all five)
+template <int P>
 __global__ void __launch_bounds__(kTB) k_ter_rhs(RhsA a)
 {
     const Geo &G = a.G;
@@ -186,10 +190,11 @@ __global__ void __launch_bounds__(kTB) k_ter_rhs(RhsA a)
     const int nz = d.nz, oh = a.oh, ov = a.ov;
     const double dx = G.dx, dy = G.dy;
     const double *ru = a.ru, *rv = a.rv, *om = a.om, *pp = a.pp;
-    if (k < nz) {
+    if (P < 3) {
+        if (k >= nz) return;
         const int c = q;
         // continuity and potential temperature
-        {
+        if (P == 0) {
             const double U0 = G.JU(i, j, k) * ru[c], U1 = G.JU(i + 1, j, k) * ru[G.c(i + 1, j, k)];
             const double V0 = G.JV(i, j, k) * rv[c], V1 = G.JV(i, j + 1, k) * rv[G.c(i, j + 1, k)];
             const double W0 = om[c], W1 = om[c + d.nxy];
@@ -205,7 +210,7 @@ __global__ void __launch_bounds__(kTB) k_ter_rhs(RhsA a)
         }
         const auto pf = [&](int cc) { return pp[cc]; };
         // x-momentum on the x-face i
-        {
+        if (P == 1) {
             const double a_r = 0.5 * (G.JU(i, j, k) * ru[c] + G.JU(i + 1, j, k) * ru[G.c(i + 1, j, k)]);
             const double a_l = 0.5 * (G.JU(i - 1, j, k) * ru[G.c(i - 1, j, k)] + G.JU(i, j, k) * ru[c]);
             const double fxx_r = a_r * ix(G, a.u, i + 1, j, k, oh, sign_of(a_r));
@@ -228,7 +233,7 @@ __global__ void __launch_bounds__(kTB) k_ter_rhs(RhsA a)
             a.Ru[c] = -adv - pgf + cor;
         }
         // y-momentum on the y-face j
-        {
+        if (P == 2) {
             const double b_r = 0.5 * (G.JV(i, j, k) * rv[c] + G.JV(i, j + 1, k) * rv[G.c(i, j + 1, k)]);
             const double b_l = 0.5 * (G.JV(i, j - 1, k) * rv[G.c(i, j - 1, k)] + G.JV(i, j, k) * rv[c]);
             const double fyy_r = b_r * iy(G, a.v, i, j + 1, k, oh, sign_of(b_r));
@@ -250,6 +255,7 @@ __global__ void __launch_bounds__(kTB) k_ter_rhs(RhsA a)
             const double cor = -a.f_cor * (ubar - rho_f * a.Ug);
             a.Rv[c] = -adv - pgf + cor;
         }
+        return;
     }
     // z-momentum on the z-face k (zero on the lids)
     if (k == 0 || k == nz) {
@@ -536,12 +542,15 @@ hipError_t launch_terrain_rhs(erf_ctx *cx, const void *const S[5], void *const R
     a.Ru = (double *)R[2];
     a.Rv = (double *)R[3];
     a.Rw = (double *)R[4];
-    const dim3 grd((cx->d.nw + kTB - 1) / kTB);
+    const dim3 grd((cx->d.nw + kTB - 1) / kTB), grc((cx->d.n + kTB - 1) / kTB);
     k_ter_prep<<<grd, kTB, 0, cx->stream>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     timing_start(cx, K_TER_RHS);
-    k_ter_rhs<<<grd, kTB, 0, cx->stream>>>(a);
+    k_ter_rhs<0><<<grc, kTB, 0, cx->stream>>>(a);
+    k_ter_rhs<1><<<grc, kTB, 0, cx->stream>>>(a);
+    k_ter_rhs<2><<<grc, kTB, 0, cx->stream>>>(a);
+    k_ter_rhs<3><<<grd, kTB, 0, cx->stream>>>(a);
     timing_stop(cx, K_TER_RHS);
     return hipGetLastError();
 }
