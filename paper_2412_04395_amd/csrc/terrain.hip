@@ -34,9 +34,9 @@
 //               to the known side
 //   k_ter_tri   one thread per column: the tridiagonal W'' rows with the
 //               column's physical heights built on the fly, the forward sweep
-//               (the next level's values loaded while the current one is
-//               eliminated), and the back substitution fused with the
-//               implicit finish of Theta'' and rho''
+//               and the back substitution (each level's loads issued three
+//               levels ahead), the implicit finish of Theta'' and rho'' fused
+//               into the back substitution
 //   k_ter_fin   S_out = S^t + S''
 // All arithmetic is FP64, written in the order of the oracle's expressions so
 // that the two round alike.
@@ -422,64 +422,109 @@ __global__ void __launch_bounds__(kCB) k_ter_tri(StA a)
         return v;
     };
     const double D = dtau * dtau * b2 * b2;
-    TriLv lo = load(0), up = load(1);
+    // Levels k-1 .. k+2 sit in a ring of four (slot = level & 3) while face k
+    // is eliminated, and the slot of level k-1 is refilled with level k+3: the
+    // loads of a level are issued three levels before their use (one
+    // wavefront per SIMD here, so only loads in flight hide the latency).
+    TriLv L[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (u < nz) L[u] = load(u);
     double tfm = 0.0, cpm = 0.0, dpm = 0.0;  // face theta^t below, previous factors
-    for (int k = 1; k <= m; ++k) {
-        TriLv nx{};
-        if (k + 1 < nz) nx = load(k + 1);
-        const int c = col + k * nxy;
-        const double dzf = 0.5 * (lo.H + up.H);
-        const double pif = 0.5 * (lo.pit + up.pit);
-        const double A = kGamma * kRd * (0.5 * (lo.pit + up.pit));
-        const double Cc = gr * 0.5 * (lo.r0 + up.r0) * (kRd / kCv) * (pif / (0.5 * (lo.pi0 + up.pi0))) /
-                          (0.5 * (lo.tt + up.tt));
-        const double idzm = 1.0 / lo.H, idz = 1.0 / up.H;
-        const double tf = 0.5 * (lo.th + up.th), tfp = (k + 1 < nz) ? 0.5 * (up.th + nx.th) : 0.0;
-        const double ta = (k == 1) ? 0.0 : -D * (A * tfm * idzm / dzf + 0.5 * Cc * tfm * idzm - 0.5 * gr * idzm);
-        const double tc = (k == m) ? 0.0 : -D * (A * tfp * idz / dzf - 0.5 * Cc * tfp * idz + 0.5 * gr * idz);
-        const double tb = 1.0 + D * (A * tf * (idz + idzm) / dzf + 0.5 * Cc * tf * (idzm - idz) - 0.5 * gr * (idzm - idz));
-        const double tbk = b1 * up.t2 + b2 * up.hat, tbm = b1 * lo.t2 + b2 * lo.hat;
-        const double rbk = b1 * up.r2 + b2 * up.rh, rbm = b1 * lo.r2 + b2 * lo.rh;
-        const double tr = up.w2 + dtau * (-A * (tbk - tbm) / dzf + 0.5 * Cc * (tbk + tbm) - 0.5 * gr * (rbk + rbm) + up.Rw);
-        double cpk, dpk;
-        if (k == 1) {
-            cpk = tc / tb;
-            dpk = tr / tb;
-        } else {
-            const double den = tb - ta * cpm;
-            cpk = tc / den;
-            dpk = (tr - ta * dpm) / den;
+    for (int k0 = 1; k0 <= m; k0 += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u;  // k0 = 1 mod 4: level k is in slot (u + 1) & 3
+            if (k > m) break;
+            TriLv &lo = L[u & 3];
+            const TriLv &up = L[(u + 1) & 3], &nx = L[(u + 2) & 3];
+            const int c = col + k * nxy;
+            const double dzf = 0.5 * (lo.H + up.H);
+            const double pif = 0.5 * (lo.pit + up.pit);
+            const double A = kGamma * kRd * (0.5 * (lo.pit + up.pit));
+            const double Cc = gr * 0.5 * (lo.r0 + up.r0) * (kRd / kCv) * (pif / (0.5 * (lo.pi0 + up.pi0))) /
+                              (0.5 * (lo.tt + up.tt));
+            const double idzm = 1.0 / lo.H, idz = 1.0 / up.H;
+            const double tf = 0.5 * (lo.th + up.th), tfp = (k + 1 < nz) ? 0.5 * (up.th + nx.th) : 0.0;
+            const double ta = (k == 1) ? 0.0 : -D * (A * tfm * idzm / dzf + 0.5 * Cc * tfm * idzm - 0.5 * gr * idzm);
+            const double tc = (k == m) ? 0.0 : -D * (A * tfp * idz / dzf - 0.5 * Cc * tfp * idz + 0.5 * gr * idz);
+            const double tb =
+                1.0 + D * (A * tf * (idz + idzm) / dzf + 0.5 * Cc * tf * (idzm - idz) - 0.5 * gr * (idzm - idz));
+            const double tbk = b1 * up.t2 + b2 * up.hat, tbm = b1 * lo.t2 + b2 * lo.hat;
+            const double rbk = b1 * up.r2 + b2 * up.rh, rbm = b1 * lo.r2 + b2 * lo.rh;
+            const double tr =
+                up.w2 + dtau * (-A * (tbk - tbm) / dzf + 0.5 * Cc * (tbk + tbm) - 0.5 * gr * (rbk + rbm) + up.Rw);
+            double cpk, dpk;
+            if (k == 1) {
+                cpk = tc / tb;
+                dpk = tr / tb;
+            } else {
+                const double den = tb - ta * cpm;
+                cpk = tc / den;
+                dpk = (tr - ta * dpm) / den;
+            }
+            cp[c] = cpk;
+            dp[c] = dpk;
+            cpm = cpk, dpm = dpk;
+            tfm = tf;
+            if (k + 3 < nz) lo = load(k + 3);
         }
-        cp[c] = cpk;
-        dp[c] = dpk;
-        cpm = cpk, dpm = dpk;
-        tfm = tf;
-        lo = up;
-        up = nx;
     }
     // back substitution (faces m .. 1) with the implicit finish of the cell
-    // above each face; the lids carry W'' = 0
+    // above each face; the lids carry W'' = 0.  The values of level k (the
+    // factors of face k, theta^t below it and the cell's explicit Theta'',
+    // rho'' and height) come from a ring of four filled three levels ahead.
     w2[col] = 0.0;
     w2[col + nz * nxy] = 0.0;
-    const auto finish = [&](int k, double Wt, double Wb, double tz1, double tz0) {
-        const int c = col + k * nxy;
-        const double H = Hc[c];
-        hat[c] = hat[c] - dtau * b2 * (Wt * tz1 - Wb * tz0) / H;
-        r2[c] = rh[c] - dtau * b2 * (Wt - Wb) / H;
+    struct BkLv {
+        double cp, dp, thl, hat, rh, H;
     };
-    double xup = 0.0, thu = tht[col + m * nxy], tzu = 0.0;  // W'' above, theta^t of cell k, face theta above
-    for (int k = m; k >= 1; --k) {
+    const auto bload = [&](int k) {
         const int c = col + k * nxy;
-        const double x = (k == m) ? dp[c] : dp[c] - cp[c] * xup;
-        w2[c] = x;
-        const double thl = tht[c - nxy];
-        const double tz = 0.5 * (thl + thu);
-        finish(k, xup, x, tzu, tz);
-        xup = x;
-        tzu = tz;
-        thu = thl;
+        BkLv v;
+        v.cp = k >= 1 ? cp[c] : 0.0;
+        v.dp = k >= 1 ? dp[c] : 0.0;
+        v.thl = k >= 1 ? tht[c - nxy] : 0.0;
+        v.hat = hat[c], v.rh = rh[c], v.H = Hc[c];
+        return v;
+    };
+    const auto finish = [&](int k, const BkLv &v, double Wt, double Wb, double tz1, double tz0) {
+        const int c = col + k * nxy;
+        hat[c] = v.hat - dtau * b2 * (Wt * tz1 - Wb * tz0) / v.H;
+        r2[c] = v.rh - dtau * b2 * (Wt - Wb) / v.H;
+    };
+    BkLv B[4];  // slot = (m - k) & 3
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (m - u >= 0) B[u] = bload(m - u);
+    double xup = 0.0, thu = tht[col + m * nxy], tzu = 0.0;  // W'' above, theta^t of cell k, face theta above
+    for (int k0 = m; k0 >= 1; k0 -= 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 - u;  // slot (m - k) & 3 = u, since k0 = m mod 4
+            if (k < 1) break;
+            BkLv &v = B[u];
+            const int c = col + k * nxy;
+            const double x = (k == m) ? v.dp : v.dp - v.cp * xup;
+            w2[c] = x;
+            const double tz = 0.5 * (v.thl + thu);
+            finish(k, v, xup, x, tzu, tz);
+            xup = x;
+            tzu = tz;
+            thu = v.thl;
+            if (k - 4 >= 0) v = bload(k - 4);
+        }
     }
-    finish(0, xup, 0.0, tzu, 0.0);
+    // cell 0: its values are in slot m & 3 (chosen by constant indices, so
+    // the ring stays in registers)
+    BkLv v0;
+    switch (m & 3) {
+    case 0: v0 = B[0]; break;
+    case 1: v0 = B[1]; break;
+    case 2: v0 = B[2]; break;
+    default: v0 = B[3]; break;
+    }
+    finish(0, v0, xup, 0.0, tzu, 0.0);
 }
 
 __global__ void __launch_bounds__(kTB) k_ter_fin(StA a)
