@@ -45,7 +45,7 @@
 namespace erfk {
 namespace {
 
-constexpr int kTB = 256;  // threads per block of the per-cell kernels
+constexpr int kTB = 256;  // threads per block of the per-cell kernels (64 x 4 tiles for the stencil kernels)
 constexpr int kCB = 64;   // columns per block of the column kernel
 
 struct Geo {
@@ -111,6 +111,22 @@ __device__ __forceinline__ void split(const Dims &d, int q, int &i, int &j, int 
     i = r - j * d.nx;
 }
 
+// The stencil kernels' blocks are tiles of 64 x 4 cells of one level
+// (blockIdx.x over the tiles of a level, blockIdx.y the level), so that the
+// rows a y-stencil reaches are shared within a block.  False for the threads
+// of a ragged tile that lie outside the domain.
+__device__ __forceinline__ bool tile_cell(const Dims &d, int &i, int &j, int &k, int &q)
+{
+    const int ntx = (d.nx + 63) >> 6;
+    const int ty = blockIdx.x / ntx, tx = blockIdx.x - ty * ntx;
+    i = (tx << 6) + (threadIdx.x & 63);
+    j = (ty << 2) + (threadIdx.x >> 6);
+    k = blockIdx.y;
+    q = (k * d.ny + j) * d.nx + i;
+    return i < d.nx && j < d.ny;
+}
+inline dim3 tile_grid(const Dims &d, int levels) { return dim3(((d.nx + 63) / 64) * ((d.ny + 3) / 4), levels); }
+
 // ---------------------------------------------------------------------------
 // slow right-hand side
 // ---------------------------------------------------------------------------
@@ -128,10 +144,8 @@ __global__ void __launch_bounds__(kTB) k_ter_prep(RhsA a)
 {
     const Geo &G = a.G;
     const Dims &d = G.d;
-    const int q = blockIdx.x * kTB + threadIdx.x;
-    if (q >= d.nw) return;
-    int i, j, k;
-    split(d, q, i, j, k);
+    int i, j, k, q;
+    if (!tile_cell(d, i, j, k, q)) return;
     if (k < d.nz) {
         const double r = a.rho[q];
         a.th[q] = a.rt[q] / r;
@@ -183,10 +197,8 @@ __global__ void __launch_bounds__(kTB) k_ter_rhs(RhsA a)
 {
     const Geo &G = a.G;
     const Dims &d = G.d;
-    const int q = blockIdx.x * kTB + threadIdx.x;
-    if (q >= d.nw) return;
-    int i, j, k;
-    split(d, q, i, j, k);
+    int i, j, k, q;
+    if (!tile_cell(d, i, j, k, q)) return;
     const int nz = d.nz, oh = a.oh, ov = a.ov;
     const double dx = G.dx, dy = G.dy;
     const double *ru = a.ru, *rv = a.rv, *om = a.om, *pp = a.pp;
@@ -324,10 +336,8 @@ __global__ void __launch_bounds__(kTB) k_ter_uv(StA a)
 {
     const Geo &G = a.G;
     const Dims &d = G.d;
-    const int q = blockIdx.x * kTB + threadIdx.x;
-    if (q >= d.n) return;
-    int i, j, k;
-    split(d, q, i, j, k);
+    int i, j, k, q;
+    if (!tile_cell(d, i, j, k, q)) return;
     const double bd = a.bd;
     // Theta'' predicted forward by beta_d (divergence damping)
     const auto tt = [&](int cc) { return a.t2[cc] + bd * (a.t2[cc] - a.t2p[cc]); };
@@ -346,10 +356,8 @@ __global__ void __launch_bounds__(kTB) k_ter_uv(StA a)
 __global__ void __launch_bounds__(kTB) k_ter_m(StA a, const double *ru, const double *rv, double *out)
 {
     const Geo &G = a.G;
-    const int q = blockIdx.x * kTB + threadIdx.x;
-    if (q >= G.d.nw) return;
-    int i, j, k;
-    split(G.d, q, i, j, k);
+    int i, j, k, q;
+    if (!tile_cell(G.d, i, j, k, q)) return;
     out[q] = G.M(ru, rv, i, j, k);
 }
 
@@ -357,10 +365,8 @@ __global__ void __launch_bounds__(kTB) k_ter_hat(StA a)
 {
     const Geo &G = a.G;
     const Dims &d = G.d;
-    const int c = blockIdx.x * kTB + threadIdx.x;
-    if (c >= d.n) return;
-    int i, j, k;
-    split(d, c, i, j, k);
+    int i, j, k, c;
+    if (!tile_cell(d, i, j, k, c)) return;
     const int nz = d.nz, nxy = d.nxy;
     const double dtau = a.dtau, b1 = a.b1, b2 = a.b2;
     const double *tht = a.tht;
@@ -587,15 +593,15 @@ hipError_t launch_terrain_rhs(erf_ctx *cx, const void *const S[5], void *const R
     a.Ru = (double *)R[2];
     a.Rv = (double *)R[3];
     a.Rw = (double *)R[4];
-    const dim3 grd((cx->d.nw + kTB - 1) / kTB), grc((cx->d.n + kTB - 1) / kTB);
-    k_ter_prep<<<grd, kTB, 0, cx->stream>>>(a);
+    const dim3 grc = tile_grid(cx->d, cx->d.nz), grw = tile_grid(cx->d, cx->d.nz + 1);
+    k_ter_prep<<<grw, kTB, 0, cx->stream>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     timing_start(cx, K_TER_RHS);
     k_ter_rhs<0><<<grc, kTB, 0, cx->stream>>>(a);
     k_ter_rhs<1><<<grc, kTB, 0, cx->stream>>>(a);
     k_ter_rhs<2><<<grc, kTB, 0, cx->stream>>>(a);
-    k_ter_rhs<3><<<grd, kTB, 0, cx->stream>>>(a);
+    k_ter_rhs<3><<<grw, kTB, 0, cx->stream>>>(a);
     timing_stop(cx, K_TER_RHS);
     return hipGetLastError();
 }
@@ -636,19 +642,20 @@ hipError_t launch_terrain_stage(erf_ctx *cx, const void *const Sn[5], const void
     a.mn = cx->ter.mn;
     double *const *so = (double *const *)Sout;
     a.o_r = so[0], a.o_t = so[1], a.o_u = so[2], a.o_v = so[3], a.o_w = so[4];
-    const dim3 gw((cx->d.nw + kTB - 1) / kTB), gc((cx->d.n + kTB - 1) / kTB), gcol((cx->d.nxy + kCB - 1) / kCB);
+    const dim3 gw((cx->d.nw + kTB - 1) / kTB), gcol((cx->d.nxy + kCB - 1) / kCB);
+    const dim3 tc = tile_grid(cx->d, cx->d.nz), tw = tile_grid(cx->d, cx->d.nz + 1);
     k_ter_init<<<gw, kTB, 0, cx->stream>>>(a);
-    k_ter_m<<<gw, kTB, 0, cx->stream>>>(a, a.u2, a.v2, a.mo);
+    k_ter_m<<<tw, kTB, 0, cx->stream>>>(a, a.u2, a.v2, a.mo);
     hipError_t e = hipGetLastError();
     for (int s = 0; s < n_sub && e == hipSuccess; ++s) {
         timing_start(cx, K_TER_UV);
-        k_ter_uv<<<gc, kTB, 0, cx->stream>>>(a);
+        k_ter_uv<<<tc, kTB, 0, cx->stream>>>(a);
         timing_stop(cx, K_TER_UV);
         timing_start(cx, K_TER_M);
-        k_ter_m<<<gw, kTB, 0, cx->stream>>>(a, a.un, a.vn, a.mn);
+        k_ter_m<<<tw, kTB, 0, cx->stream>>>(a, a.un, a.vn, a.mn);
         timing_stop(cx, K_TER_M);
         timing_start(cx, K_TER_HAT);
-        k_ter_hat<<<gc, kTB, 0, cx->stream>>>(a);
+        k_ter_hat<<<tc, kTB, 0, cx->stream>>>(a);
         timing_stop(cx, K_TER_HAT);
         timing_start(cx, K_TER_COL);
         k_ter_tri<<<gcol, kCB, 0, cx->stream>>>(a);
