@@ -356,7 +356,7 @@ erf_status erf_set_terrain(erf_ctx *c, const double *h, double beta)
     }
     Terrain &t = c->ter;
     if (!t.mem) {
-        const size_t doubles = (size_t)(nz + 1) + nxy + 9 * n + 5 * nw;
+        const size_t doubles = (size_t)(nz + 1) + nxy + 13 * n + 7 * nw;
         hipError_t e = hipMalloc(&t.mem, doubles * sizeof(double));
         if (e != hipSuccess) {
             t.mem = nullptr;
@@ -378,15 +378,45 @@ erf_status erf_set_terrain(erf_ctx *c, const double *h, double beta)
         t.dp = m, m += nw;
         t.J = m, m += n;
         t.mo = m, m += nw;
-        t.mn = m;
+        t.mn = m, m += nw;
+        t.JU = m, m += n;
+        t.JV = m, m += n;
+        t.hxU = m, m += n;
+        t.heV = m, m += n;
+        t.hxW = m, m += nw;
+        t.heW = m;
     }
     std::vector<double> Jc(n);
     for (int k = 0; k < nz; ++k)
         for (int q = 0; q < nxy; ++q) Jc[(size_t)k * nxy + q] = Hc[(size_t)k * nxy + q] / c->dz_host[k];
+    // face metrics, in the expressions and order the kernels used to evaluate
+    // them (App. B): h_zeta on x-/y-faces as two-cell means, h_xi on x-faces
+    // from the centre heights, h_xi on z-faces by the fourth-order difference
+    std::vector<double> JU(n), JV(n), hxU(n), heV(n), hxW(nw), heW(nw);
+    const double dx = c->grid.dx, dy = c->grid.dy;
+    const auto H = [&](int i, int j) { return hb[(size_t)((j % ny + ny) % ny) * nx + (i % nx + nx) % nx]; };
+    for (int k = 0; k <= nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const size_t q = ((size_t)k * ny + j) * nx + i;
+                hxW[q] = sl[k] * ((H(i - 2, j) - H(i + 2, j)) + 8.0 * (H(i + 1, j) - H(i - 1, j))) / (12.0 * dx);
+                heW[q] = sl[k] * ((H(i, j - 2) - H(i, j + 2)) + 8.0 * (H(i, j + 1) - H(i, j - 1))) / (12.0 * dy);
+                if (k == nz) continue;
+                const size_t kq = (size_t)k * nxy;
+                const double Jw = Jc[kq + (size_t)j * nx + (i + nx - 1) % nx], Js = Jc[kq + (size_t)((j + ny - 1) % ny) * nx + i];
+                JU[q] = 0.5 * (Jw + Jc[q]);
+                JV[q] = 0.5 * (Js + Jc[q]);
+                hxU[q] = 0.5 * (sl[k] + sl[k + 1]) * (H(i, j) - H(i - 1, j)) / dx;
+                heV[q] = 0.5 * (sl[k] + sl[k + 1]) * (H(i, j) - H(i, j - 1)) / dy;
+            }
     hipError_t e = hipMemcpyAsync(t.s, sl.data(), (nz + 1) * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(t.hb, hb.data(), nxy * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(t.Hc, Hc.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(t.J, Jc.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    const double *tabs[6] = {JU.data(), JV.data(), hxU.data(), heV.data(), hxW.data(), heW.data()};
+    double *devs[6] = {t.JU, t.JV, t.hxU, t.heV, t.hxW, t.heW};
+    for (int a = 0; a < 6 && e == hipSuccess; ++a)
+        e = hipMemcpyAsync(devs[a], tabs[a], (a < 4 ? n : nw) * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "uploading the terrain geometry");
     t.Hc_host = std::move(Hc);

@@ -380,6 +380,9 @@ struct Terrain {
     // h_zeta = Hc / dz_k per cell [n]; the metric part M of Omega'' of the old
     // and new horizontal momenta on z-faces [nw]
     double *J = nullptr, *mo = nullptr, *mn = nullptr;
+    // face metrics: h_zeta on x- and y-faces, h_xi on x-faces, h_eta on
+    // y-faces [n each]; h_xi and h_eta on z-faces [nw each]
+    double *JU = nullptr, *JV = nullptr, *hxU = nullptr, *heV = nullptr, *hxW = nullptr, *heW = nullptr;
     void *mem = nullptr;
     std::vector<double> Hc_host, zc_host;  // for erf_terrain_heights
 };

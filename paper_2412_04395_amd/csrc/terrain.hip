@@ -52,6 +52,10 @@ struct Geo {
     Dims d;
     double dx, dy;
     const double *dz, *s, *hb, *Hc, *Jc;
+    // face metrics tabulated at set-up (the expressions below, evaluated in
+    // the same order on the host): h_zeta on x- and y-faces, h_xi on x-faces,
+    // h_eta on y-faces [n]; h_xi, h_eta on z-faces [nw]
+    const double *JUt, *JVt, *hxUt, *heVt, *hxWt, *heWt;
 
     __device__ __forceinline__ int c(int i, int j, int k) const
     {
@@ -64,24 +68,15 @@ struct Geo {
     __device__ __forceinline__ double H(int i, int j, int k) const { return Hc[c(i, j, k)]; }
     // h_zeta = Hc / dz_k, tabulated at set-up
     __device__ __forceinline__ double J(int i, int j, int k) const { return Jc[c(i, j, k)]; }
-    __device__ __forceinline__ double JU(int i, int j, int k) const { return 0.5 * (J(i - 1, j, k) + J(i, j, k)); }
-    __device__ __forceinline__ double JV(int i, int j, int k) const { return 0.5 * (J(i, j - 1, k) + J(i, j, k)); }
-    __device__ __forceinline__ double hxU(int i, int j, int k) const
-    {
-        return 0.5 * (s[k] + s[k + 1]) * (hbar(i, j) - hbar(i - 1, j)) / dx;
-    }
-    __device__ __forceinline__ double heV(int i, int j, int k) const
-    {
-        return 0.5 * (s[k] + s[k + 1]) * (hbar(i, j) - hbar(i, j - 1)) / dy;
-    }
-    __device__ __forceinline__ double hxW(int i, int j, int k) const
-    {
-        return s[k] * ((hbar(i - 2, j) - hbar(i + 2, j)) + 8.0 * (hbar(i + 1, j) - hbar(i - 1, j))) / (12.0 * dx);
-    }
-    __device__ __forceinline__ double heW(int i, int j, int k) const
-    {
-        return s[k] * ((hbar(i, j - 2) - hbar(i, j + 2)) + 8.0 * (hbar(i, j + 1) - hbar(i, j - 1))) / (12.0 * dy);
-    }
+    // h_zeta on the x-face i: 0.5 (J_{i-1} + J_i); on the y-face j likewise
+    __device__ __forceinline__ double JU(int i, int j, int k) const { return JUt[c(i, j, k)]; }
+    __device__ __forceinline__ double JV(int i, int j, int k) const { return JVt[c(i, j, k)]; }
+    // h_xi on the x-face i: 0.5 (s_k + s_{k+1}) (hb_i - hb_{i-1}) / dx; h_eta alike
+    __device__ __forceinline__ double hxU(int i, int j, int k) const { return hxUt[c(i, j, k)]; }
+    __device__ __forceinline__ double heV(int i, int j, int k) const { return heVt[c(i, j, k)]; }
+    // h_xi on the z-face k: s_k ((hb_{i-2} - hb_{i+2}) + 8 (hb_{i+1} - hb_{i-1})) / (12 dx); h_eta alike
+    __device__ __forceinline__ double hxW(int i, int j, int k) const { return hxWt[c(i, j, k)]; }
+    __device__ __forceinline__ double heW(int i, int j, int k) const { return heWt[c(i, j, k)]; }
     // the metric part M of rho Omega (or of Omega'') on the z-face k; zero on the lids
     __device__ __forceinline__ double M(const double *ru, const double *rv, int i, int j, int k) const
     {
@@ -558,6 +553,12 @@ Geo geo_of(const erf_ctx *cx)
     G.hb = cx->ter.hb;
     G.Hc = cx->ter.Hc;
     G.Jc = cx->ter.J;
+    G.JUt = cx->ter.JU;
+    G.JVt = cx->ter.JV;
+    G.hxUt = cx->ter.hxU;
+    G.heVt = cx->ter.heV;
+    G.hxWt = cx->ter.hxW;
+    G.heWt = cx->ter.heW;
     return G;
 }
 
