@@ -201,3 +201,44 @@ def test_benchmark_size_rest_and_conservation():
     assert abs(d1["mass"] / d0["mass"] - 1.0) < 1e-13
     assert abs(d1["theta_mass"] / d0["theta_mass"] - 1.0) < 1e-13
     assert 0.0 < d1["max_w"] < 20.0
+
+
+def test_witch_of_agnesi_mountain_wave_300_steps():
+    # the 2-D ridge case of the oracle's linear-theory pin (Sec. 4.3), 6000 s:
+    # the GPU's w equals the oracle's to roundoff after 300 RK3 steps, and
+    # meets the same bounds against the linear hydrostatic solution
+    from paper_2412_04395_amd import erf
+    cfg = _cfg(nx=128, ny=1, nz=60, dx=2000.0, dy=2000.0, dz=W.uniform_dz(60, 500.0), dt=20.0, n_substeps=6,
+               f_cor=0.0, Ug=0.0, Vg=0.0, steps=300)
+    a, hm, U = 10000.0, 10.0, 10.0
+    h = W.agnesi_nodes(cfg, hm, a, ridge=True)
+    o, s, b, Hc = _sides(cfg, h, 1.0)
+    shp = b["rho0"].shape
+    S = {"rho": b["rho0"].copy(), "rt": b["rho0"] * b["theta0"], "ru": b["rho0"] * U, "rv": np.zeros(shp),
+         "rw": np.zeros((shp[0] + 1,) + shp[1:]), "rq": np.zeros((0,) + shp)}
+    S = {k: np.ascontiguousarray(v) for k, v in S.items()}
+    Sg = s.to_device(S)
+    for _ in range(cfg.steps):
+        o.rk3_step(S)
+        s.rk3_step(Sg)
+    got = s.to_numpy(Sg)
+    e = _errs(got, S, b, ("rho", "rt", "ru", "rw"))
+    _say("agnesi 300 steps gpu vs oracle:", {k: f"{v:.2e}" for k, v in e.items()})
+    for k, v in e.items():
+        assert v <= 1e-10, (k, v)
+    rho = got["rho"][:, 0, :]
+    wf = got["rw"][1:-1, 0, :] / (0.5 * (rho[1:] + rho[:-1]))
+    w = np.zeros_like(rho)
+    w[1:-1] = 0.5 * (wf[:-1] + wf[1:])
+    _, zc = s.terrain_heights()
+    z = zc[:, 0, :]
+    x = (np.arange(cfg.nx) + 0.5) * cfg.dx - 0.5 * cfg.nx * cfg.dx
+    X = np.broadcast_to(x, z.shape)
+    l = N_BV / U
+    den = X * X + a * a
+    deta = hm * a * (-np.sin(l * z) * den - 2.0 * X * (a * np.cos(l * z) - X * np.sin(l * z))) / den ** 2
+    wlin = U * deta * np.sqrt(b["rho0"][0, 0, :] / b["rho0"][:, 0, :])
+    m = (z[:, 0] > 300.0) & (z[:, 0] < 2000.0)
+    corr = float(np.sum(w[m] * wlin[m]) / np.sqrt(np.sum(w[m] ** 2) * np.sum(wlin[m] ** 2)))
+    _say("agnesi lowest 2 km: correlation with the linear solution", corr)
+    assert corr > 0.97
