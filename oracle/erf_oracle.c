@@ -747,7 +747,7 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
 {
     if (P->anelastic && (P->moist || P->sgs == 2 || P->sgs == 3 || !P->p_anel)) return -1;
     if (g->terrain && (P->moist || P->anelastic || P->sgs != 0 || P->nu_m != 0.0 || P->alpha_m != 0.0 ||
-                       P->most_z0 > 0.0 || P->surf_heat_flux != 0.0 || P->n_scalars > 0))
+                       P->most_z0 > 0.0 || P->surf_heat_flux != 0.0))
         return -1;
     /* the Deardorff closure carries rho e as scalar 0 and nothing else */
     if (P->sgs == 3 && (P->n_scalars != 1 || P->moist || !S->rq || !R->rq)) return -1;
@@ -1118,9 +1118,11 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
                     Tn[c] = th_hat[k] - dtau * b2 * (Wt * THZ(k + 1) - Wb * THZ(k)) / Hc[k];
                     Rn[c] = rh_hat[k] - dtau * b2 * (Wt - Wb) / Hc[k];
                 }
+                /* terrain: the vertical flux of the scalars is Omega'', weighted
+                 * as in the Theta'' and rho'' updates (W'' - M, old and new) */
                 for (int k = 0; k <= nz; ++k) {
                     size_t c = CIDX(g, i, j, k);
-                    sW[c] += b1 * W2[c] + b2 * Wn[c];
+                    sW[c] += b1 * (W2[c] - Mo[k]) + b2 * (Wn[c] - Mn[k]);
                 }
 #undef THZ
             }
@@ -1148,7 +1150,12 @@ int orc_acoustic_substeps(const orc_grid *g, const orc_params *P, const orc_base
     }
     for (size_t c = 0; c < nw; ++c) {
         Sout->rw[c] = St->rw[c] + W2[c];
-        if (Fw) Fw[c] = St->rw[c] + sW[c] / n_sub;
+        if (Fw) {
+            /* terrain: the stage-averaged rho Omega, Omega of S^t plus the
+             * average of the substeps' Omega'' */
+            int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+            Fw[c] = t_rOm(g, &T, St->ru, St->rv, St->rw, i, j, k) + sW[c] / n_sub;
+        }
     }
 
     free(tht); free(pit); free(pim); free(rdm); free(U2); free(V2); free(W2); free(T2); free(R2); free(T2p);
@@ -1171,6 +1178,8 @@ int orc_scalar_advance(const orc_grid *g, const orc_params *P, const orc_state *
     if (P->sgs == 3 && (nq != 1 || !src)) return -5;
     size_t n = (size_t)nx * ny * nz;
     int oh = P->adv_order_h, ov = P->adv_order_v;
+    if (g->terrain && (P->moist || P->sgs != 0)) return -5;
+    ter_t T = ter_build(g);
     double *q = dalloc(n);
     for (int s = 0; s < nq; ++s) {
         const double *rqn = Sn->rq + (size_t)s * n, *rqt = St->rq + (size_t)s * n;
@@ -1201,7 +1210,16 @@ int orc_scalar_advance(const orc_grid *g, const orc_params *P, const orc_state *
                             f[4 + side] = fa * (P->scalar_scheme == 1 ? orc_weno5(qq, sgn(fa), WENO_EPS) : orc_interp(ov, qq, sgn(fa)));
                         }
                     }
-                    double div = (f[1] - f[0]) / g->dx + (f[3] - f[2]) / g->dy + (f[5] - f[4]) / g->dz[k];
+                    /* terrain: the horizontal fluxes carry h_zeta of their face,
+                     * Fw is rho Omega, and the divergence is divided by the
+                     * cell's h_zeta (App. A) */
+                    double div;
+                    if (T.on)
+                        div = ((t_JU(g, &T, i + 1, j, k) * f[1] - t_JU(g, &T, i, j, k) * f[0]) / g->dx +
+                               (t_JV(g, &T, i, j + 1, k) * f[3] - t_JV(g, &T, i, j, k) * f[2]) / g->dy +
+                               (f[5] - f[4]) / g->dz[k]) / t_J(g, &T, i, j, k);
+                    else
+                        div = (f[1] - f[0]) / g->dx + (f[3] - f[2]) / g->dy + (f[5] - f[4]) / g->dz[k];
                     out[c] = rqn[c] - dts * div;
                     if (P->sgs == 3 && s == 0) {
                         /* rho e: its source at S^t; negative values are cut to zero */
@@ -1211,6 +1229,7 @@ int orc_scalar_advance(const orc_grid *g, const orc_params *P, const orc_state *
                 }
     }
     free(q);
+    ter_free(&T);
     return 0;
 }
 

@@ -305,3 +305,44 @@ def test_witch_of_agnesi_mountain_wave_matches_linear_theory():
         err = float(np.linalg.norm(ws - wl) / np.linalg.norm(wl))
         assert corr > cmin and err < emax, (zlo, zhi, corr, err)
         assert abs(np.abs(ws).max() / np.abs(wl).max() - 1.0) < 0.2, (zlo, zhi)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_scalars_over_a_hill_keep_a_uniform_mixing_ratio_and_their_mass(scheme):
+    # the scalars' stage-averaged fluxes are the substeps' own (rho Omega with
+    # the beta weights vertically, h_zeta-weighted horizontally), so a uniform
+    # mixing ratio stays uniform as the density changes, and sum rho q dV is
+    # conserved (interpolant of the run's order, and WENO5)
+    cfg = _cfg(n_scalars=2, scalar_scheme=scheme)
+    o, b, Hc, zc = _terrain_oracle(cfg, _hill(cfg), 3.0)
+    S = _flow(cfg, b, 41)
+    S["rq"] = np.ascontiguousarray(np.stack([0.01 * S["rho"], S["rho"] * (1.0 + W.uniform_noise(43, S["rho"].shape, 0.5))]))
+    vol = cfg.dx * cfg.dy * Hc
+    m0 = float(np.sum(S["rq"][1] * vol))
+    for _ in range(3):
+        o.rk3_step(S)
+    q = S["rq"][0] / S["rho"]
+    assert np.max(np.abs(q / 0.01 - 1.0)) < 1e-13
+    assert abs(float(np.sum(S["rq"][1] * vol)) / m0 - 1.0) < 1e-14
+    d = o.diagnostics(S)
+    assert d["scalar_mass"][1] == pytest.approx(float(np.sum(S["rq"][1] * vol)), rel=1e-14)
+
+
+def test_scalars_on_flat_terrain_reproduce_the_flat_path():
+    cfg = _cfg(n_scalars=1, scalar_scheme=1)
+    flat = oracle.Oracle(cfg)
+    zc1 = cfg.z_centres()
+    th1 = W.stratified_theta(zc1, TH_S, N_BV, cfg.grav)
+    bf = flat.init_base_state(th1, P_SEA)
+    ter = oracle.Oracle(cfg)
+    ter.set_terrain(np.zeros((cfg.ny, cfg.nx)), 1.0)
+    shp = (cfg.nz, cfg.ny, cfg.nx)
+    bt = ter.init_base_state_columns(np.broadcast_to(th1[:, None, None], shp), np.full(shp[1:], P_SEA))
+    S = _flow(cfg, bt, 51)
+    S["rq"] = np.ascontiguousarray((S["rho"] * (1.0 + W.uniform_noise(53, shp, 0.5)))[None])
+    A, B = {k: v.copy() for k, v in S.items()}, {k: v.copy() for k, v in S.items()}
+    for _ in range(2):
+        flat.rk3_step(A)
+        ter.rk3_step(B)
+    for f in ("rho", "rt", "ru", "rv", "rw", "rq"):
+        assert np.array_equal(A[f], B[f]), f
