@@ -321,10 +321,10 @@ erf_status erf_set_terrain(erf_ctx *c, const double *h, double beta)
     if (!h) return fail(c, ERF_E_ARG, "terrain heights are NULL");
     const erf_params &p = c->prm;
     if (p.precision != ERF_FP64 || p.moist || p.anelastic || p.sgs != ERF_SGS_NONE || p.nu_m != 0.0 ||
-        p.alpha_m != 0.0 || p.most_z0 > 0.0 || p.surf_heat_flux != 0.0 || p.n_scalars != 0 || c->member)
+        p.alpha_m != 0.0 || p.most_z0 > 0.0 || p.surf_heat_flux != 0.0 || c->member)
         return fail(c, ERF_E_UNSUPPORTED,
-                    "terrain needs a dry, inviscid ERF_FP64 compressible context without scalars, surface layer "
-                    "or surface flux");
+                    "terrain needs a dry, inviscid ERF_FP64 compressible context without surface layer or "
+                    "surface flux");
     if (!(beta >= 1.0 && beta <= 8.0)) return fail(c, ERF_E_ARG, "beta must lie in [1, 8]");
     const int nx = c->d.nx, ny = c->d.ny, nz = c->d.nz, nxy = c->d.nxy;
     const size_t n = (size_t)c->d.n, nw = (size_t)c->d.nw;
@@ -520,9 +520,9 @@ erf_status erf_acoustic_substeps(erf_ctx *c, const erf_state *Sn, const erf_stat
     const void *rt[5] = {Rt->rho, Rt->rhotheta, Rt->rhou, Rt->rhov, Rt->rhow};
     void *so[5] = {Sout->rho, Sout->rhotheta, Sout->rhou, Sout->rhov, Sout->rhow};
     if (c->ter.on) {
-        // a terrain context has no scalars, so no stage-averaged fluxes are kept
-        if (flux) return fail(c, ERF_E_UNSUPPORTED, "a terrain context keeps no stage-averaged fluxes");
-        hipError_t e = launch_terrain_stage(c, sn, st, rt, n_sub, dtau, so);
+        if (flux && (!flux->rhou || !flux->rhov || !flux->rhow)) return fail(c, ERF_E_ARG, "null flux pointer");
+        hipError_t e = launch_terrain_stage(c, sn, st, rt, n_sub, dtau, so, flux ? flux->rhou : nullptr,
+                                            flux ? flux->rhov : nullptr, flux ? flux->rhow : nullptr);
         return e == hipSuccess ? ERF_OK : hip_fail(c, e, "terrain acoustic substeps launch");
     }
     hipError_t e = launch_acoustic_stage(c, sn, st, c->prm.moist ? St->rhoq : nullptr, rt, n_sub, dtau, so,

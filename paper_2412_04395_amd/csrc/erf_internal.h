@@ -561,8 +561,10 @@ int anel_ffty_cols(int nx, int ny);
 // terrain.hip (FP64 contexts with terrain): the slow right-hand side and one
 // RK stage of acoustic substeps with the metric terms
 hipError_t launch_terrain_rhs(erf_ctx *c, const void *const S[5], void *const R[5]);
+// (Fu, Fv, Fw: the stage-averaged fluxes for scalars, rho Omega vertically; null: none)
 hipError_t launch_terrain_stage(erf_ctx *c, const void *const Sn[5], const void *const St[5],
-                                const void *const Rt[5], int n_sub, double dtau, void *const Sout[5]);
+                                const void *const Rt[5], int n_sub, double dtau, void *const Sout[5],
+                                void *Fu, void *Fv, void *Fw);
 // diag.hip
 size_t diag_slots_needed();
 hipError_t launch_diagnostics(erf_ctx *c, const void *const S[6], double *host_out);

@@ -297,6 +297,62 @@ __global__ __launch_bounds__(1024) void k_scalar_batch(const ScalArgs<T> *args, 
 }  // namespace
 
 namespace {
+// Terrain (FP64 contexts, Sec. 3.4 and App. A): one thread per cell and
+// scalar; the horizontal fluxes carry h_zeta of their face, Fw is the
+// stage-averaged rho Omega, and the divergence is divided by the cell's h_zeta
+struct TerScalArgs {
+    Dims d;
+    int nq, oh, ov, weno;
+    double dx, dy, dts;
+    const double *dz, *J, *JU, *JV;
+    const double *rqn, *Fu, *Fv, *Fw, *q;
+    double *out;
+};
+
+__device__ __forceinline__ double ter_face(const TerScalArgs &a, double F, double qm3, double qm2, double qm1,
+                                           double q0, double qp1, double qp2, int order)
+{
+    const double sg = sign_of(F);
+    if (a.weno) {
+        const bool pos = F > 0.0;
+        return F * weno5_face<double>(pos ? qm3 : qp2, pos ? qm2 : qp1, pos ? qm1 : q0, pos ? q0 : qm1,
+                                      pos ? qp1 : qm2);
+    }
+    return F * face_interp<double>(order, qm3, qm2, qm1, q0, qp1, qp2, sg);
+}
+
+__global__ __launch_bounds__(256) void k_ter_scalar(TerScalArgs a)
+{
+    const Dims &d = a.d;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= d.n) return;
+    const int k = c / d.nxy, r = c - k * d.nxy, j = r / d.nx, i = r - j * d.nx;
+    const int s = blockIdx.y;
+    const double *q = a.q + (size_t)s * d.n;
+    const auto at = [&](int ii, int jj, int kk) {
+        return q[(refl_centre(kk, d.nz) * d.ny + wrap_idx(jj, d.ny)) * d.nx + wrap_idx(ii, d.nx)];
+    };
+    const auto cc = [&](int ii, int jj) { return (k * d.ny + wrap_idx(jj, d.ny)) * d.nx + wrap_idx(ii, d.nx); };
+    double f[6];
+    for (int side = 0; side < 2; ++side) {
+        const int ci = cc(i + side, j), cj = cc(i, j + side);
+        f[side] = ter_face(a, a.Fu[ci], at(i + side - 3, j, k), at(i + side - 2, j, k), at(i + side - 1, j, k),
+                           at(i + side, j, k), at(i + side + 1, j, k), at(i + side + 2, j, k), a.oh);
+        f[2 + side] = ter_face(a, a.Fv[cj], at(i, j + side - 3, k), at(i, j + side - 2, k), at(i, j + side - 1, k),
+                               at(i, j + side, k), at(i, j + side + 1, k), at(i, j + side + 2, k), a.oh);
+        const int kf = k + side;
+        f[4 + side] = (kf == 0 || kf == d.nz)
+                          ? 0.0
+                          : ter_face(a, a.Fw[c + side * d.nxy], at(i, j, kf - 3), at(i, j, kf - 2), at(i, j, kf - 1),
+                                     at(i, j, kf), at(i, j, kf + 1), at(i, j, kf + 2), a.ov);
+    }
+    const double div = ((a.JU[cc(i + 1, j)] * f[1] - a.JU[c] * f[0]) / a.dx +
+                        (a.JV[cc(i, j + 1)] * f[3] - a.JV[c] * f[2]) / a.dy + (f[5] - f[4]) / a.dz[k]) /
+                       a.J[c];
+    const size_t o = (size_t)s * d.n + c;
+    a.out[o] = a.rqn[o] - a.dts * div;
+}
+
 template <typename T>
 hipError_t scalar_t(erf_ctx *cx, const void *rqn, const void *rho_t, const void *rq_t, const void *Fu,
                     const void *Fv, const void *Fw, double dts, void *rq_out)
@@ -326,6 +382,20 @@ hipError_t scalar_t(erf_ctx *cx, const void *rqn, const void *rho_t, const void 
     timing_start(cx, K_MIXRATIO);
     run<ScalArgs<T>, k_mixing_ratio<T>, k_mixing_ratio_batch<T>>(cx, dim3((d.n + 255) / 256), dim3(256), 0, a);
     timing_stop(cx, K_MIXRATIO);
+    if constexpr (std::is_same<T, double>::value) {
+        if (cx->ter.on) {
+            TerScalArgs t{};
+            t.d = d;
+            t.nq = a.nq, t.oh = a.oh, t.ov = a.ov, t.weno = a.weno;
+            t.dx = cx->grid.dx, t.dy = cx->grid.dy, t.dts = dts;
+            t.dz = cx->base.dz, t.J = cx->ter.J, t.JU = cx->ter.JU, t.JV = cx->ter.JV;
+            t.rqn = a.rqn, t.Fu = a.Fu, t.Fv = a.Fv, t.Fw = a.Fw, t.q = a.q, t.out = a.out;
+            timing_start(cx, K_SCALAR);
+            k_ter_scalar<<<dim3((d.n + 255) / 256, a.nq), 256, 0, cx->stream>>>(t);
+            timing_stop(cx, K_SCALAR);
+            return hipGetLastError();
+        }
+    }
     const int nchunk = (d.nz + kLev - 1) / kLev;
     dim3 blk(kSX, kSY + 1, 1), grd((d.nx + kSX - 1) / kSX, (d.ny + kSY - 1) / kSY, nchunk * a.nq);
     const bool near = d.nx >= 3 && d.ny >= 3 && d.nz >= 3;

@@ -305,6 +305,12 @@ struct StA {
     double *tht, *pit;
     double *t2, *t2p, *u2, *v2, *un, *vn, *r2, *w2, *rh, *cp, *dp;
     double *mo, *mn;  // M of the old and of the new horizontal momenta on z-faces
+    // scalars: running sums of U'', V'' and of the beta-weighted Omega'' (null:
+    // no sums kept), the substep count and the stage-averaged fluxes written
+    // by k_ter_fin (rho Omega vertically)
+    double *su, *sv, *sw;
+    int nsub;
+    double *o_fu, *o_fv, *o_fw;
     double *o_r, *o_t, *o_u, *o_v, *o_w;
 };
 
@@ -323,8 +329,13 @@ __global__ void __launch_bounds__(kTB) k_ter_init(StA a)
         a.t2[q] = T2;
         a.t2p[q] = T2;
         a.r2[q] = a.n_r[q] - a.t_r[q];
+        if (a.su) {
+            a.su[q] = 0.0;
+            a.sv[q] = 0.0;
+        }
     }
     a.w2[q] = a.n_w[q] - a.t_w[q];
+    if (a.su) a.sw[q] = 0.0;
 }
 
 __global__ void __launch_bounds__(kTB) k_ter_uv(StA a)
@@ -343,8 +354,14 @@ __global__ void __launch_bounds__(kTB) k_ter_uv(StA a)
     const double fzc = G.fz(tt, i, j, k);
     const double cx = 0.5 * G.hxU(i, j, k) * (fzc + G.fz(tt, i - 1, j, k));
     const double cy = 0.5 * G.heV(i, j, k) * (fzc + G.fz(tt, i, j - 1, k));
-    a.un[q] = a.u2[q] + a.dtau * (-kGamma * kRd * pfx * (tt_c - tt_w) / G.dx + kGamma * kRd * pfx * cx + a.R_u[q]);
-    a.vn[q] = a.v2[q] + a.dtau * (-kGamma * kRd * pfy * (tt_c - tt_s) / G.dy + kGamma * kRd * pfy * cy + a.R_v[q]);
+    const double un = a.u2[q] + a.dtau * (-kGamma * kRd * pfx * (tt_c - tt_w) / G.dx + kGamma * kRd * pfx * cx + a.R_u[q]);
+    const double vn = a.v2[q] + a.dtau * (-kGamma * kRd * pfy * (tt_c - tt_s) / G.dy + kGamma * kRd * pfy * cy + a.R_v[q]);
+    a.un[q] = un;
+    a.vn[q] = vn;
+    if (a.su) {
+        a.su[q] += un;
+        a.sv[q] += vn;
+    }
 }
 
 // M(ru, rv) on every z-face (zero on the lids)
@@ -507,6 +524,8 @@ __global__ void __launch_bounds__(kCB) k_ter_tri(StA a)
             BkLv &v = B[u];
             const int c = col + k * nxy;
             const double x = (k == m) ? v.dp : v.dp - v.cp * xup;
+            // scalars: Omega'' of this substep with the beta weights
+            if (a.sw) a.sw[c] += b1 * (w2[c] - a.mo[c]) + b2 * (x - a.mn[c]);
             w2[c] = x;
             const double tz = 0.5 * (v.thl + thu);
             finish(k, v, xup, x, tzu, tz);
@@ -533,6 +552,18 @@ __global__ void __launch_bounds__(kTB) k_ter_fin(StA a)
     const Dims &d = a.G.d;
     const int q = blockIdx.x * kTB + threadIdx.x;
     if (q >= d.nw) return;
+    // the stage-averaged fluxes first: o_* may alias S^n, never S^t
+    if (a.su) {
+        int i, j, k;
+        split(d, q, i, j, k);
+        const bool lid = k == 0 || k == d.nz;
+        const double Om = lid ? a.t_w[q] : a.t_w[q] - a.G.M(a.t_u, a.t_v, i, j, k);
+        a.o_fw[q] = Om + a.sw[q] / a.nsub;
+        if (q < d.n) {
+            a.o_fu[q] = a.t_u[q] + a.su[q] / a.nsub;
+            a.o_fv[q] = a.t_v[q] + a.sv[q] / a.nsub;
+        }
+    }
     if (q < d.n) {
         a.o_r[q] = a.t_r[q] + a.r2[q];
         a.o_t[q] = a.t_t[q] + a.t2[q];
@@ -608,7 +639,8 @@ hipError_t launch_terrain_rhs(erf_ctx *cx, const void *const S[5], void *const R
 }
 
 hipError_t launch_terrain_stage(erf_ctx *cx, const void *const Sn[5], const void *const St[5],
-                                const void *const Rt[5], int n_sub, double dtau, void *const Sout[5])
+                                const void *const Rt[5], int n_sub, double dtau, void *const Sout[5],
+                                void *Fu, void *Fv, void *Fw)
 {
     const Workspace &w = cx->ws;
     StA a;
@@ -643,6 +675,12 @@ hipError_t launch_terrain_stage(erf_ctx *cx, const void *const Sn[5], const void
     a.mn = cx->ter.mn;
     double *const *so = (double *const *)Sout;
     a.o_r = so[0], a.o_t = so[1], a.o_u = so[2], a.o_v = so[3], a.o_w = so[4];
+    const bool sums = Fu && Fv && Fw;
+    a.su = sums ? (double *)w.su : nullptr;
+    a.sv = sums ? (double *)w.sv : nullptr;
+    a.sw = sums ? (double *)w.sw : nullptr;
+    a.nsub = n_sub;
+    a.o_fu = (double *)Fu, a.o_fv = (double *)Fv, a.o_fw = (double *)Fw;
     const dim3 gw((cx->d.nw + kTB - 1) / kTB), gcol((cx->d.nxy + kCB - 1) / kCB);
     const dim3 tc = tile_grid(cx->d, cx->d.nz), tw = tile_grid(cx->d, cx->d.nz + 1);
     k_ter_init<<<gw, kTB, 0, cx->stream>>>(a);

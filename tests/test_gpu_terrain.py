@@ -159,7 +159,7 @@ def test_refusals():
     from paper_2412_04395_amd import erf
     cfg = _cfg()
     h = W.agnesi_nodes(cfg, 400.0, 1000.0)
-    for kw in (dict(sgs=1), dict(n_scalars=1), dict(prec="fp32"), dict(nu_m=1.0)):
+    for kw in (dict(sgs=1), dict(moist=1, n_scalars=3), dict(prec="fp32"), dict(nu_m=1.0)):
         s = erf.Solver(cfg.replace(**kw))
         with pytest.raises(RuntimeError):
             s.set_terrain(h, 1.0)
@@ -242,3 +242,46 @@ def test_witch_of_agnesi_mountain_wave_300_steps():
     corr = float(np.sum(w[m] * wlin[m]) / np.sqrt(np.sum(w[m] ** 2) * np.sum(wlin[m] ** 2)))
     _say("agnesi lowest 2 km: correlation with the linear solution", corr)
     assert corr > 0.97
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_scalars_over_terrain_match_oracle(scheme):
+    # stage-averaged fluxes (rho Omega vertically) and one scalar update per
+    # call; three RK3 steps with two scalars; a uniform mixing ratio stays
+    # uniform on the GPU (interpolant of the run's order, and WENO5)
+    cfg = _cfg(n_scalars=2, scalar_scheme=scheme, adv_order_h=5, adv_order_v=3)
+    h = W.agnesi_nodes(cfg, 400.0, 1000.0)
+    o, s, b, Hc = _sides(cfg, h, 3.0)
+    S = _flow(b, 500)
+    shp = b["rho0"].shape
+    S["rq"] = np.ascontiguousarray(np.stack([0.01 * S["rho"], S["rho"] * (1.0 + W.uniform_noise(501, shp, 0.5))]))
+    R = o.slow_rhs(S)
+    Sn = _flow(b, 600)
+    Sn["rq"] = S["rq"].copy()
+    dtau = cfg.dt / cfg.n_substeps
+    out, F = o.acoustic_substeps(Sn, S, R, 3, dtau)
+    Sg, Sng = s.to_device(S), s.to_device(Sn)
+    outg, Fg = s.acoustic_substeps(Sng, Sg, s.to_device(R), 3, dtau)
+    Fg = s.to_numpy(Fg)
+    for name, ref, got in (("Fu", F[0], Fg["ru"]), ("Fv", F[1], Fg["rv"]), ("Fw", F[2], Fg["rw"])):
+        e = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        _say(f"terrain flux {name} scheme {scheme}: {e:.2e}")
+        assert e <= CALL_TOL, (name, e)
+    dts = cfg.dt / 2.0
+    ref_q = o.scalar_advance(Sn, S, F, dts)
+    import torch
+    flux = {f: torch.from_numpy(np.ascontiguousarray(x)).to(s.device, s.dtype) for f, x in zip(("ru", "rv", "rw"), F)}
+    got_q = s.scalar_advance(Sng, Sg, flux, dts).cpu().numpy()
+    e = float(np.max(np.abs(got_q - ref_q)) / np.max(np.abs(ref_q)))
+    _say(f"terrain scalar advance scheme {scheme}: {e:.2e}")
+    assert e <= CALL_TOL
+    Sg = s.to_device(S)
+    for _ in range(3):
+        o.rk3_step(S)
+        s.rk3_step(Sg)
+    got = s.to_numpy(Sg)
+    e = _errs(got, S, b, ("rho", "rt", "ru", "rv", "rw", "rq"))
+    _say(f"terrain rk3 x3 with scalars scheme {scheme}:", {k: f"{v:.2e}" for k, v in e.items()})
+    for k, v in e.items():
+        assert v <= STEPS_TOL, (k, v)
+    assert np.max(np.abs(got["rq"][0] / got["rho"] / 0.01 - 1.0)) < 1e-13
