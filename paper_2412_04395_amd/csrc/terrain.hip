@@ -1,23 +1,27 @@
 // terrain.hip -- terrain-following coordinates on the FP64 path (Sec. 3.4,
 // App. A, App. B, App. C): the slow right-hand side and one RK stage of
-// acoustic substeps with the metric terms, for dry, inviscid, compressible
-// contexts.
+// acoustic substeps with the metric terms (and the stage-averaged fluxes of
+// the scalars, whose update is k_ter_scalar in scalars.hip), for dry,
+// inviscid, compressible contexts.
 //
-// Geometry (erf_set_terrain): node heights z = zeta + s(zeta) h(x, y) with
-// s = (1 - zeta/z_t)^beta; per column hb, the mean of the cell's four corner
-// heights; per level s_k; per cell the physical height Hc = dz_k + (s_{k+1} -
-// s_k) hb and the Jacobian h_zeta = Hc / dz_k.  Face metrics are recomputed
-// where they are used: h_xi on the x-face i is the difference of the two
-// cells' centre heights over dx, (s_k + s_{k+1})/2 (hb_i - hb_{i-1}) / dx; on
-// the z-face k it is s_k times the fourth-order centred difference of hb
-// (App. B); h_eta alike.  The base state is stored per cell.
+// Geometry (erf_set_terrain, on the host): node heights z = zeta + s(zeta)
+// h(x, y) with s = (1 - zeta/z_t)^beta; per column hb, the mean of the cell's
+// four corner heights; per level s_k; per cell the physical height Hc = dz_k +
+// (s_{k+1} - s_k) hb and the Jacobian h_zeta = Hc / dz_k.  The face metrics
+// are tables: h_zeta on x- and y-faces (two-cell means), h_xi on the x-face i
+// the difference of the two cells' centre heights over dx, (s_k + s_{k+1})/2
+// (hb_i - hb_{i-1}) / dx, and on the z-face k s_k times the fourth-order
+// centred difference of hb (App. B); h_eta alike.  The base state is stored
+// per cell.  The stencil kernels run on tiles of 64 x 4 cells of one level, so
+// that the rows a y-stencil reaches are shared within a block.
 //
 // Kernels:
 //   k_ter_prep  theta, u, v, w, p' and rho Omega = rho w - M on the z-faces,
 //               M = h_xi <rho u> + h_eta <rho v> with the horizontal momenta
 //               averaged from the four faces around the z-face; the lid
 //               faces keep rho w (zero)
-//   k_ter_rhs   slow tendencies: horizontal mass fluxes weighted by the face's
+//   k_ter_rhs   slow tendencies (four kernels: continuity and theta, x-, y- and
+//               z-momentum): horizontal mass fluxes weighted by the face's
 //               h_zeta, rho Omega through the z-faces, each divergence divided
 //               by its control volume's h_zeta; the pressure gradient
 //               p_x = p_xi - h_xi (p_zeta / h_zeta), the last factor the mean
@@ -37,7 +41,9 @@
 //               and the back substitution (each level's loads issued three
 //               levels ahead), the implicit finish of Theta'' and rho'' fused
 //               into the back substitution
-//   k_ter_fin   S_out = S^t + S''
+//   k_ter_fin   S_out = S^t + S''; with scalars, the stage-averaged fluxes
+//               S^t + the substeps' mean, rho Omega vertically (the
+//               beta-weighted Omega'' summed in k_ter_tri)
 // All arithmetic is FP64, written in the order of the oracle's expressions so
 // that the two round alike.
 #include "erf_internal.h"
@@ -51,7 +57,7 @@ constexpr int kCB = 64;   // columns per block of the column kernel
 struct Geo {
     Dims d;
     double dx, dy;
-    const double *dz, *s, *hb, *Hc, *Jc;
+    const double *dz, *Hc, *Jc;
     // face metrics tabulated at set-up (the expressions below, evaluated in
     // the same order on the host): h_zeta on x- and y-faces, h_xi on x-faces,
     // h_eta on y-faces [n]; h_xi, h_eta on z-faces [nw]
@@ -60,10 +66,6 @@ struct Geo {
     __device__ __forceinline__ int c(int i, int j, int k) const
     {
         return (k * d.ny + wrap_idx(j, d.ny)) * d.nx + wrap_idx(i, d.nx);
-    }
-    __device__ __forceinline__ double hbar(int i, int j) const
-    {
-        return hb[wrap_idx(j, d.ny) * d.nx + wrap_idx(i, d.nx)];
     }
     __device__ __forceinline__ double H(int i, int j, int k) const { return Hc[c(i, j, k)]; }
     // h_zeta = Hc / dz_k, tabulated at set-up
@@ -580,8 +582,6 @@ Geo geo_of(const erf_ctx *cx)
     G.dx = cx->grid.dx;
     G.dy = cx->grid.dy;
     G.dz = cx->base.dz;
-    G.s = cx->ter.s;
-    G.hb = cx->ter.hb;
     G.Hc = cx->ter.Hc;
     G.Jc = cx->ter.J;
     G.JUt = cx->ter.JU;
