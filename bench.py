@@ -611,7 +611,39 @@ def run_anelastic(steps: int, warmup: int) -> dict:
 TERRAIN_VALUES = {"ter_rhs": 16, "ter_uv": 10, "ter_m": 3, "ter_hat": 14, "ter_tri": 15}
 
 
-def run_terrain(steps: int, warmup: int) -> dict:
+def terrain_cpu_oracle(target_s: float = 8.0) -> dict:
+    """FP64 oracle on a bounded sample of the terrain workload: a 64 x 64 column
+    block of the same grid over the same hill (scaled to the block), timed for
+    whole RK3 steps on all the host's OpenMP threads."""
+    import oracle
+
+    cfg = W.terrain_hill()
+    sample = cfg.replace(nx=64, ny=64)
+    h = W.agnesi_nodes(sample, 400.0, 2000.0 * 64 / cfg.nx)
+    o = oracle.Oracle(sample)
+    o.set_terrain(h, 1.0)
+    Hc, zc = o.terrain_heights()
+    th0 = W.stratified_theta(zc, 300.0, 0.01, sample.grav)
+    ps = W.stratified_ground_pressure(W.cell_mean_nodes(h), 300.0, 0.01, sample.p_surface, sample.grav)
+    b = o.init_base_state_columns(th0, ps)
+    shp = b["rho0"].shape
+    S = {"rho": b["rho0"].copy(), "rt": b["rho0"] * b["theta0"], "ru": b["rho0"] * 10.0, "rv": np.zeros(shp),
+         "rw": np.zeros((shp[0] + 1,) + shp[1:]), "rq": np.zeros((0,) + shp)}
+    S = {k: np.ascontiguousarray(v) for k, v in S.items()}
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.rk3_step(S)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > target_s or steps >= 40:
+            break
+    cores = _omp_threads() or int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": sample.cells * steps / el, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{sample.nx}x{sample.ny}x{sample.nz} block of the terrain grid over a hill of the same "
+                      f"height and shape, {steps} RK3 steps, {el:.1f} s"}
+
+
+def run_terrain(steps: int, warmup: int, cpu: bool = True) -> dict:
     """Flow over a Witch of Agnesi hill in terrain-following coordinates (Sec.
     3.4, 4.3): 256 x 256 x 128, FP64, basic terrain following, 10 m/s across a
     400 m hill of 2 km half-width, constant N = 0.01 1/s, 6 substeps."""
@@ -652,7 +684,8 @@ def run_terrain(steps: int, warmup: int) -> dict:
             "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": byts,
                          "avg_launch_ms": round(avg_ms, 4), "launches_timed": kn},
-            "final_diag": {"max_w": d["max_w"], "nonfinite": d["nonfinite"]}}
+            "final_diag": {"max_w": d["max_w"], "nonfinite": d["nonfinite"]},
+            **({"cpu_oracle": terrain_cpu_oracle()} if cpu else {})}
 
 
 def _substep_value_adjust(cfg) -> float:
@@ -735,7 +768,7 @@ def main(argv=None):
         print(json.dumps(run_tke(a.steps, a.warmup)), flush=True)
         return 0
     if a.workload == "terrain":
-        print(json.dumps(run_terrain(a.steps, a.warmup)), flush=True)
+        print(json.dumps(run_terrain(a.steps, a.warmup, cpu=not a.no_cpu_baseline)), flush=True)
         return 0
     if a.workload == "closure_training":
         print(json.dumps(run_training(a.steps)), flush=True)
@@ -787,7 +820,7 @@ def main(argv=None):
     if a.workload == "cbl" and not a.no_anelastic:
         out["anelastic"] = run_anelastic(a.steps, a.warmup)
     if a.workload == "cbl" and not a.no_terrain:
-        out["terrain"] = run_terrain(a.steps, a.warmup)
+        out["terrain"] = run_terrain(a.steps, a.warmup, cpu=rank == 0 and not a.no_cpu_baseline)
     if a.workload == "cbl" and not a.no_ensemble:
         out["ensemble"] = run_ensemble(min(a.steps, 5), min(a.warmup, 1))
     if rank == 0 and not a.no_cpu_baseline:
