@@ -356,7 +356,7 @@ erf_status erf_set_terrain(erf_ctx *c, const double *h, double beta)
     }
     Terrain &t = c->ter;
     if (!t.mem) {
-        const size_t doubles = (size_t)(nz + 1) + nxy + 13 * n + 7 * nw;
+        const size_t doubles = (size_t)(nz + 1) + nxy + 14 * n + 7 * nw;
         hipError_t e = hipMalloc(&t.mem, doubles * sizeof(double));
         if (e != hipSuccess) {
             t.mem = nullptr;
@@ -384,7 +384,8 @@ erf_status erf_set_terrain(erf_ctx *c, const double *h, double beta)
         t.hxU = m, m += n;
         t.heV = m, m += n;
         t.hxW = m, m += nw;
-        t.heW = m;
+        t.heW = m, m += nw;
+        t.dzc = m;
     }
     std::vector<double> Jc(n);
     for (int k = 0; k < nz; ++k)
@@ -392,7 +393,17 @@ erf_status erf_set_terrain(erf_ctx *c, const double *h, double beta)
     // face metrics, in the expressions and order the kernels used to evaluate
     // them (App. B): h_zeta on x-/y-faces as two-cell means, h_xi on x-faces
     // from the centre heights, h_xi on z-faces by the fourth-order difference
-    std::vector<double> JU(n), JV(n), hxU(n), heV(n), hxW(nw), heW(nw);
+    std::vector<double> JU(n), JV(n), hxU(n), heV(n), hxW(nw), heW(nw), dzc(n);
+    // the distance of the centres above and below each cell, summed as the
+    // kernels summed it (half the outer cells, then the cell between)
+    for (int k = 0; k < nz; ++k) {
+        const int kl = k > 0 ? k - 1 : 0, ku = k < nz - 1 ? k + 1 : nz - 1;
+        for (int q = 0; q < nxy; ++q) {
+            double v = 0.5 * Hc[(size_t)kl * nxy + q] + 0.5 * Hc[(size_t)ku * nxy + q];
+            for (int mm = kl + 1; mm < ku; ++mm) v += Hc[(size_t)mm * nxy + q];
+            dzc[(size_t)k * nxy + q] = v;
+        }
+    }
     const double dx = c->grid.dx, dy = c->grid.dy;
     const auto H = [&](int i, int j) { return hb[(size_t)((j % ny + ny) % ny) * nx + (i % nx + nx) % nx]; };
     for (int k = 0; k <= nz; ++k)
@@ -413,10 +424,10 @@ erf_status erf_set_terrain(erf_ctx *c, const double *h, double beta)
     if (e == hipSuccess) e = hipMemcpyAsync(t.hb, hb.data(), nxy * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(t.Hc, Hc.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(t.J, Jc.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream);
-    const double *tabs[6] = {JU.data(), JV.data(), hxU.data(), heV.data(), hxW.data(), heW.data()};
-    double *devs[6] = {t.JU, t.JV, t.hxU, t.heV, t.hxW, t.heW};
-    for (int a = 0; a < 6 && e == hipSuccess; ++a)
-        e = hipMemcpyAsync(devs[a], tabs[a], (a < 4 ? n : nw) * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    const double *tabs[7] = {JU.data(), JV.data(), hxU.data(), heV.data(), dzc.data(), hxW.data(), heW.data()};
+    double *devs[7] = {t.JU, t.JV, t.hxU, t.heV, t.dzc, t.hxW, t.heW};
+    for (int a = 0; a < 7 && e == hipSuccess; ++a)
+        e = hipMemcpyAsync(devs[a], tabs[a], (a < 5 ? n : nw) * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "uploading the terrain geometry");
     t.Hc_host = std::move(Hc);

@@ -383,6 +383,8 @@ struct Terrain {
     // face metrics: h_zeta on x- and y-faces, h_xi on x-faces, h_eta on
     // y-faces [n each]; h_xi and h_eta on z-faces [nw each]
     double *JU = nullptr, *JV = nullptr, *hxU = nullptr, *heV = nullptr, *hxW = nullptr, *heW = nullptr;
+    // physical distance of the centres above and below each cell [n]
+    double *dzc = nullptr;
     void *mem = nullptr;
     std::vector<double> Hc_host, zc_host;  // for erf_terrain_heights
 };

@@ -62,6 +62,9 @@ struct Geo {
     // the same order on the host): h_zeta on x- and y-faces, h_xi on x-faces,
     // h_eta on y-faces [n]; h_xi, h_eta on z-faces [nw]
     const double *JUt, *JVt, *hxUt, *heVt, *hxWt, *heWt;
+    // the physical distance of the centres above and below each cell (one
+    // level each way, one-sided in the lowest and highest cells) [n]
+    const double *dzcT;
 
     __device__ __forceinline__ int c(int i, int j, int k) const
     {
@@ -94,9 +97,7 @@ struct Geo {
         const int nz = d.nz;
         if (nz < 2) return 0.0;
         const int kl = k > 0 ? k - 1 : 0, ku = k < nz - 1 ? k + 1 : nz - 1;
-        double dzc = 0.5 * H(i, j, kl) + 0.5 * H(i, j, ku);
-        for (int m = kl + 1; m < ku; ++m) dzc += H(i, j, m);
-        return (f(c(i, j, ku)) - f(c(i, j, kl))) / dzc;
+        return (f(c(i, j, ku)) - f(c(i, j, kl))) / dzcT[c(i, j, k)];
     }
 };
 
@@ -590,6 +591,7 @@ Geo geo_of(const erf_ctx *cx)
     G.heVt = cx->ter.heV;
     G.hxWt = cx->ter.hxW;
     G.heWt = cx->ter.heW;
+    G.dzcT = cx->ter.dzc;
     return G;
 }
 
