@@ -233,7 +233,8 @@ erf_status erf_init_base_state(erf_ctx *ctx, const double *theta0, const double 
  * beta-weighted Omega''), with h_zeta-weighted horizontal fluxes.
  * Needs a dry, inviscid (sgs none, nu_m = alpha_m = 0) ERF_FP64 compressible
  * context without surface layer or surface flux, not an ensemble member
- * (ERF_E_UNSUPPORTED otherwise); ERF_E_ARG for non-finite heights or a
+ * (ERF_E_UNSUPPORTED otherwise; erf_mlp_features and erf_box_filter then
+ * refuse the context too); ERF_E_ARG for non-finite heights or a
  * terrain so high that a cell would have no positive height.  Invalidates the
  * base state: erf_init_base_state_columns must follow (erf_init_base_state is
  * refused).  Synchronous; allocates the terrain arrays on the first call. */

@@ -206,6 +206,8 @@ erf_status erf_mlp_features(erf_ctx *c, const erf_state *S, double *feat)
     CHECK_CTX(c);
     if (!c->have_base) return fail(c, ERF_E_STATE, "erf_init_base_state must come first");
     if (!state5(S) || !feat) return fail(c, ERF_E_ARG, "null pointer");
+    // the inputs are gradients along the flat grid's axes
+    if (c->ter.on) return fail(c, ERF_E_UNSUPPORTED, "closure inputs are not provided over terrain");
     const void *s5[5] = {S->rho, S->rhotheta, S->rhou, S->rhov, S->rhow};
     hipError_t e = launch_prep(c, s5);
     if (e == hipSuccess) e = launch_features(c, feat);
@@ -218,6 +220,7 @@ erf_status erf_box_filter(erf_ctx *c, const erf_state *S, int32_t r, double Cs, 
     CHECK_CTX(c);
     if (!c->have_base) return fail(c, ERF_E_STATE, "erf_init_base_state must come first");
     if (!state5(S) || !state5(coarse) || !targets) return fail(c, ERF_E_ARG, "null pointer");
+    if (c->ter.on) return fail(c, ERF_E_UNSUPPORTED, "the box filter is not provided over terrain");
     if (r < 1 || c->d.nx % r || c->d.ny % r || c->d.nz % r)
         return fail(c, ERF_E_SHAPE, "nx, ny and nz must be multiples of r");
     if (Cs < 0.0 || (Cs > 0.0 && !(Pr_t > 0.0))) return fail(c, ERF_E_ARG, "Cs >= 0 and Pr_t > 0 required");
