@@ -169,6 +169,15 @@ def test_refusals():
     s.set_terrain(h, 1.0)
     with pytest.raises(RuntimeError):
         s.init_base_state(np.full(cfg.nz, 300.0))
+    # the closure's inputs and the box filter follow the flat grid's axes
+    Hc, zc = s.terrain_heights()
+    th0, ps = _inputs(cfg, h, Hc, zc)
+    b = s.init_base_state_columns(th0, ps)
+    Sg = s.to_device(_flow(b, 700))
+    with pytest.raises(RuntimeError):
+        s.mlp_features(Sg)
+    with pytest.raises(RuntimeError):
+        s.box_filter(Sg, 1)
 
 
 def test_benchmark_size_rest_and_conservation():
