@@ -228,11 +228,13 @@ erf_status erf_init_base_state(erf_ctx *ctx, const double *theta0, const double 
  * App. B), divergences divided by h_zeta, and the horizontal pressure gradient
  * p_xi - h_xi (p_zeta / h_zeta) (App. B; one-sided vertical differences in the
  * lowest and highest cells); the substeps likewise with Omega'' (App. C).
+ * A surface heat flux (surf_heat_flux, per unit horizontal area) enters the
+ * lowest cell over its physical height.
  * Passive scalars move with the stage-averaged fluxes, whose vertical part
  * erf_acoustic_substeps returns as rho Omega (the mean of the substeps'
  * beta-weighted Omega''), with h_zeta-weighted horizontal fluxes.
  * Needs a dry, inviscid (sgs none, nu_m = alpha_m = 0) ERF_FP64 compressible
- * context without surface layer or surface flux, not an ensemble member
+ * context without surface layer, not an ensemble member
  * (ERF_E_UNSUPPORTED otherwise; erf_mlp_features and erf_box_filter then
  * refuse the context too); ERF_E_ARG for non-finite heights or a
  * terrain so high that a cell would have no positive height.  Invalidates the

@@ -747,7 +747,7 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
 {
     if (P->anelastic && (P->moist || P->sgs == 2 || P->sgs == 3 || !P->p_anel)) return -1;
     if (g->terrain && (P->moist || P->anelastic || P->sgs != 0 || P->nu_m != 0.0 || P->alpha_m != 0.0 ||
-                       P->most_z0 > 0.0 || P->surf_heat_flux != 0.0))
+                       P->most_z0 > 0.0))
         return -1;
     /* the Deardorff closure carries rho e as scalar 0 and nothing else */
     if (P->sgs == 3 && (P->n_scalars != 1 || P->moist || !S->rq || !R->rq)) return -1;
@@ -946,7 +946,9 @@ int orc_slow_rhs(const orc_grid *g, const orc_params *P, const orc_base *B,
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t c = CIDX(g, i, j, 0);
-                R->rt[c] += S->rho[c] * P->surf_heat_flux / dz[0];
+                /* terrain: the flux per unit horizontal area over the lowest
+                 * cell's physical height (reading) */
+                R->rt[c] += S->rho[c] * P->surf_heat_flux / t_Hc(g, &T, i, j, 0);
             }
 
     free(th); free(u); free(v); free(w); free(pp); free(qf); free(bm);

@@ -34,9 +34,10 @@ typedef struct {
      * of cell (i, j) (periodic); node heights z = zeta + (1 - zeta/z_t)^beta h
      * with zeta the flat grid's level and z_t its top.  With terrain the base
      * state (orc_base) holds one value per cell, and the slow right-hand side,
-     * the substeps and the diagnostics take the metric terms; dry, inviscid
-     * (sgs 0, no constant viscosity, no surface layer or surface flux), no
-     * scalars, compressible only. */
+     * the substeps, the scalars and the diagnostics take the metric terms;
+     * dry, inviscid (sgs 0, no constant viscosity, no surface layer),
+     * compressible only; a surface heat flux enters the lowest cell per unit
+     * horizontal area. */
     const double *terrain;
     double terrain_beta; /* 1: basic terrain following; 3: Sullivan */
 } orc_grid;

@@ -321,10 +321,9 @@ erf_status erf_set_terrain(erf_ctx *c, const double *h, double beta)
     if (!h) return fail(c, ERF_E_ARG, "terrain heights are NULL");
     const erf_params &p = c->prm;
     if (p.precision != ERF_FP64 || p.moist || p.anelastic || p.sgs != ERF_SGS_NONE || p.nu_m != 0.0 ||
-        p.alpha_m != 0.0 || p.most_z0 > 0.0 || p.surf_heat_flux != 0.0 || c->member)
+        p.alpha_m != 0.0 || p.most_z0 > 0.0 || c->member)
         return fail(c, ERF_E_UNSUPPORTED,
-                    "terrain needs a dry, inviscid ERF_FP64 compressible context without surface layer or "
-                    "surface flux");
+                    "terrain needs a dry, inviscid ERF_FP64 compressible context without surface layer");
     if (!(beta >= 1.0 && beta <= 8.0)) return fail(c, ERF_E_ARG, "beta must lie in [1, 8]");
     const int nx = c->d.nx, ny = c->d.ny, nz = c->d.nz, nxy = c->d.nxy;
     const size_t n = (size_t)c->d.n, nw = (size_t)c->d.nw;

@@ -27,7 +27,8 @@
 //               p_x = p_xi - h_xi (p_zeta / h_zeta), the last factor the mean
 //               of the two cells' centred vertical differences over the
 //               physical distance (one-sided in the lowest and highest
-//               cells); buoyancy about the per-cell base state; Coriolis
+//               cells); buoyancy about the per-cell base state; Coriolis; a
+//               surface heat flux into the lowest cell over its physical height
 //   k_ter_init  S'' = S^n - S^t, theta^t and pi^t
 //   k_ter_uv    U'', V'' with the metric correction of the gradient of the
 //               predicted Theta''
@@ -131,6 +132,7 @@ inline dim3 tile_grid(const Dims &d, int levels) { return dim3(((d.nx + 63) / 64
 struct RhsA {
     Geo G;
     double g, f_cor, Ug, Vg;
+    double qs;  // prescribed kinematic surface heat flux (per unit horizontal area)
     int oh, ov;
     const double *rho0, *Theta0, *p0;
     const double *rho, *rt, *ru, *rv, *rw;
@@ -216,7 +218,10 @@ __global__ void __launch_bounds__(kTB) k_ter_rhs(RhsA a)
             const double fy1 = V1 * iy(G, a.th, i, j + 1, k, oh, sign_of(V1));
             const double fz0 = (k == 0) ? 0.0 : W0 * izc(G, a.th, i, j, k, ov, sign_of(W0));
             const double fz1 = (k == nz - 1) ? 0.0 : W1 * izc(G, a.th, i, j, k + 1, ov, sign_of(W1));
-            a.Rt[c] = -((fx1 - fx0) / dx + (fy1 - fy0) / dy + (fz1 - fz0) / G.dz[k]) / Jc;
+            double rt = -((fx1 - fx0) / dx + (fy1 - fy0) / dy + (fz1 - fz0) / G.dz[k]) / Jc;
+            // the surface heat flux enters the lowest cell over its physical height
+            if (k == 0 && a.qs != 0.0) rt += a.rho[c] * a.qs / G.Hc[c];
+            a.Rt[c] = rt;
         }
         const auto pf = [&](int cc) { return pp[cc]; };
         // x-momentum on the x-face i
@@ -606,6 +611,7 @@ hipError_t launch_terrain_rhs(erf_ctx *cx, const void *const S[5], void *const R
     a.f_cor = cx->prm.f_cor;
     a.Ug = cx->prm.Ug;
     a.Vg = cx->prm.Vg;
+    a.qs = cx->prm.surf_heat_flux;
     a.oh = cx->prm.adv_order_h;
     a.ov = cx->prm.adv_order_v;
     a.rho0 = cx->ter.rho0;

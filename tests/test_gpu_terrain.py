@@ -92,6 +92,7 @@ CASES = {
     "btf_o6_ragged": dict(beta=1.0, kw=dict(nx=70, ny=9, nz=20, dz=W.stretched_dz(20, 30.0, 400.0, 4000.0),
                                             adv_order_h=6, adv_order_v=4)),
     "ridge_o2": dict(beta=3.0, kw=dict(adv_order_h=2, adv_order_v=2), ridge=True),
+    "heated_o3": dict(beta=1.0, kw=dict(surf_heat_flux=0.2)),
 }
 
 

@@ -346,3 +346,20 @@ def test_scalars_on_flat_terrain_reproduce_the_flat_path():
         ter.rk3_step(B)
     for f in ("rho", "rt", "ru", "rv", "rw", "rq"):
         assert np.array_equal(A[f], B[f]), f
+
+
+def test_surface_heat_flux_over_terrain_heats_the_ground_cells_by_the_flux_times_the_area():
+    # a resting atmosphere over a hill with a prescribed kinematic surface heat
+    # flux (per unit horizontal area): only the lowest cells gain rho theta,
+    # each by rho Q_s dx dy per unit time in total (its tendency times its
+    # physical volume), whatever the slope under it
+    Qs = 0.2
+    cfg = _cfg(surf_heat_flux=Qs)
+    o, b, Hc, zc = _terrain_oracle(cfg, _hill(cfg, 500.0, 600.0), 3.0)
+    S = _rest(b)
+    R = o.slow_rhs(S)
+    vol = cfg.dx * cfg.dy * Hc
+    assert np.all(R["rt"][1:] == 0.0)
+    assert np.allclose(R["rt"][0] * vol[0], S["rho"][0] * Qs * cfg.dx * cfg.dy, rtol=1e-14, atol=0)
+    for f in ("rho", "ru", "rv", "rw"):
+        assert np.all(R[f] == 0.0), f
