@@ -673,6 +673,26 @@ def run_terrain(steps: int, warmup: int, cpu: bool = True) -> dict:
     el, (kms, kn) = _time_steps(s, S, steps, torch, dom)
     d = s.diagnostics(S, allow_nonfinite=True)
     s.close()
+    del S
+    # the same flow carrying three tracers by WENO5 (the scalar update over
+    # terrain and the substeps' flux sums)
+    cq = cfg.replace(n_scalars=3, scalar_scheme=1)
+    sq = erf.Solver(cq)
+    sq.set_terrain(h, 1.0)
+    Hq, zq = sq.terrain_heights()
+    bq = sq.init_base_state_columns(W.stratified_theta(zq, 300.0, 0.01, cq.grav), ps)
+    rq = np.stack([bq["rho0"] * (1e-3 * (m + 1)) * (1.0 + W.uniform_noise(cq.seed + m, shp, 0.5)) for m in range(3)])
+    Sq = sq.to_device({"rho": bq["rho0"], "rt": bq["rho0"] * bq["theta0"], "ru": bq["rho0"] * 10.0,
+                       "rv": np.zeros(shp), "rw": np.zeros((shp[0] + 1,) + shp[1:]), "rq": rq})
+    del Hq, zq, rq
+    for _ in range(warmup):
+        sq.rk3_step(Sq)
+    qshares = {}
+    for k in ("mixing_ratio", "scalar"):
+        _, (ms, n) = _time_steps(sq, Sq, 1, torch, k)
+        qshares[k] = round(ms, 4)
+    elq, _ = _time_steps(sq, Sq, steps, torch)
+    sq.close()
     avg_ms = kms / max(kn, 1)
     byts = TERRAIN_VALUES[dom] * 8.0 * cfg.cells
     gbs = byts / (avg_ms * 1e-3) / 1e9
@@ -685,6 +705,8 @@ def run_terrain(steps: int, warmup: int, cpu: bool = True) -> dict:
                          "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": byts,
                          "avg_launch_ms": round(avg_ms, 4), "launches_timed": kn},
             "final_diag": {"max_w": d["max_w"], "nonfinite": d["nonfinite"]},
+            "with_scalars": {"n_scalars": 3, "scheme": "WENO5", "value": cq.cells * steps / elq,
+                             "ms_per_step": 1e3 * elq / steps, "kernel_ms_per_step": qshares},
             **({"cpu_oracle": terrain_cpu_oracle()} if cpu else {})}
 
 

@@ -321,13 +321,18 @@ __device__ __forceinline__ double ter_face(const TerScalArgs &a, double F, doubl
     return F * face_interp<double>(order, qm3, qm2, qm1, q0, qp1, qp2, sg);
 }
 
+// blocks are tiles of 64 x 4 cells of one level (blockIdx.x over the tiles of
+// a level, blockIdx.y the level, blockIdx.z the scalar), so that the rows a
+// y-stencil reaches are shared within a block
 __global__ __launch_bounds__(256) void k_ter_scalar(TerScalArgs a)
 {
     const Dims &d = a.d;
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= d.n) return;
-    const int k = c / d.nxy, r = c - k * d.nxy, j = r / d.nx, i = r - j * d.nx;
-    const int s = blockIdx.y;
+    const int ntx = (d.nx + 63) >> 6;
+    const int ty = blockIdx.x / ntx, tx = blockIdx.x - ty * ntx;
+    const int i = (tx << 6) + (threadIdx.x & 63), j = (ty << 2) + (threadIdx.x >> 6), k = blockIdx.y;
+    if (i >= d.nx || j >= d.ny) return;
+    const int c = (k * d.ny + j) * d.nx + i;
+    const int s = blockIdx.z;
     const double *q = a.q + (size_t)s * d.n;
     const auto at = [&](int ii, int jj, int kk) {
         return q[(refl_centre(kk, d.nz) * d.ny + wrap_idx(jj, d.ny)) * d.nx + wrap_idx(ii, d.nx)];
@@ -391,7 +396,7 @@ hipError_t scalar_t(erf_ctx *cx, const void *rqn, const void *rho_t, const void 
             t.dz = cx->base.dz, t.J = cx->ter.J, t.JU = cx->ter.JU, t.JV = cx->ter.JV;
             t.rqn = a.rqn, t.Fu = a.Fu, t.Fv = a.Fv, t.Fw = a.Fw, t.q = a.q, t.out = a.out;
             timing_start(cx, K_SCALAR);
-            k_ter_scalar<<<dim3((d.n + 255) / 256, a.nq), 256, 0, cx->stream>>>(t);
+            k_ter_scalar<<<dim3(((d.nx + 63) / 64) * ((d.ny + 3) / 4), d.nz, a.nq), 256, 0, cx->stream>>>(t);
             timing_stop(cx, K_SCALAR);
             return hipGetLastError();
         }
